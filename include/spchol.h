@@ -1,0 +1,176 @@
+/*
+ * spchol -- supernodal sparse Cholesky factorization and solve on one AMD
+ * Instinct MI355X (gfx950), C ABI.
+ *
+ * Problem (arXiv:1608.00044, Section II-A, equation (1)): A is an n x n
+ * symmetric positive definite matrix; after a fill-reducing symmetric
+ * permutation P (Section V, nested dissection), factor P A P^T = L L^T with L
+ * lower triangular and only L stored, then solve A x = b with the two
+ * triangular solves L y = P b, L^T z = y, x = P^T z (Section II-A).
+ *
+ * The work is split in three calls:
+ *   spc_analyze  -- host-only symbolic analysis: elimination tree and column
+ *                   counts (Section II-B), supernodes (Section II-B) capped at
+ *                   opt.sn_cap columns (Section III-B, 150 by default),
+ *                   optional relaxed amalgamation, storage layout, relative
+ *                   indices for the update scatter, task schedule;
+ *   spc_factor   -- device numeric factorization: per supernode the diagonal
+ *                   factorization and panel solve (task F of Section III-A),
+ *                   the update blocks to every later supernode it touches
+ *                   (task U) and their scatter-add into the target through
+ *                   relative indices (task A), run in a dependency order of
+ *                   the supernodal elimination tree (Section IV);
+ *   spc_solve    -- device forward and backward supernodal triangular solves.
+ *
+ * Conventions used by every entry point:
+ *   - Matrices are the LOWER triangle of A in compressed sparse column form,
+ *     0-based: colptr[n+1] (int64), rowind[nnz] (int32).  Every column holds
+ *     its row indices in strictly increasing order, every row index i of
+ *     column j satisfies j <= i < n.  Upper-triangle entries, duplicates and
+ *     unsorted rows are rejected with SPC_ERR_PATTERN.  A missing diagonal is
+ *     a structural zero: the factorization then reports that column.
+ *   - perm[new] = old: (P A P^T)[i][j] = A[perm[i]][perm[j]].  NULL means the
+ *     identity.  The library uses exactly this permutation (no internal
+ *     reordering), so its L is comparable with any other factor of P A P^T.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are memory on
+ *     the current HIP device (for example torch tensor data_ptr()); "stream"
+ *     is a hipStream_t passed as void* (NULL = the default stream).
+ *   - Values are IEEE binary64.  values[k] belongs to the input entry
+ *     (rowind[k], column of k) of the pattern given to spc_analyze.
+ *   - Status: 0 success; > 0 the 1-based column of P A P^T whose pivot was not
+ *     positive (or not a number), the smallest such column; < 0 an error code
+ *     below.  Invalid arguments are rejected before any device work.
+ *   - Handles are not thread-safe; distinct handles may be used concurrently
+ *     from different threads.
+ */
+#ifndef SPCHOL_H
+#define SPCHOL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t spc_status;
+
+enum {
+    SPC_OK = 0,
+    SPC_ERR_ARG = -1,           /* bad argument (NULL, size, options)               */
+    SPC_ERR_PATTERN = -2,       /* malformed lower CSC pattern                      */
+    SPC_ERR_OOM = -3,           /* host or device allocation failed / over budget   */
+    SPC_ERR_HIP = -4,           /* a HIP runtime call failed                        */
+    SPC_ERR_NOT_FACTORED = -5,  /* solve on a factor that did not complete          */
+    SPC_ERR_NOT_CONVERGED = -6, /* reserved for iterative refinement                */
+    SPC_ERR_TIMEOUT = -7,       /* a device wait exceeded its bounded spin          */
+    SPC_ERR_BUSY = -8           /* symbolic handle still referenced by a factor     */
+};
+
+typedef struct spc_options {
+    int32_t sn_cap;           /* maximum supernode width (columns); default 150     */
+    int32_t sched;            /* 0 = level-by-level launches, 1 = device task queue */
+    double amalg_ratio;       /* relaxed amalgamation zero ratio; 0 = off (default) */
+    int64_t mem_budget_bytes; /* device bytes a factor may hold; 0 = no limit       */
+} spc_options;
+
+typedef struct spc_symbolic spc_symbolic;
+typedef struct spc_numeric spc_numeric;
+
+typedef struct spc_symbolic_info {
+    int64_t n;             /* order of A                                            */
+    int64_t nnz_a;         /* stored entries of the lower triangle of A            */
+    int64_t nnz_l;         /* entries of the exact structure of L                   */
+    int64_t nnz_stored;    /* entries the supernodal storage holds (>= nnz_l)       */
+    int64_t nsup;          /* supernodes after cap split and amalgamation           */
+    int64_t nlevels;       /* levels of the supernodal elimination tree             */
+    int64_t npairs;        /* (source, target) update pairs                         */
+    int64_t nrel;          /* relative indices stored for the scatter              */
+    int64_t factor_bytes;  /* device bytes one numeric factor holds                */
+    int64_t plan_bytes;    /* device bytes of the shared symbolic plan             */
+    double flops;          /* sum_j colcount(j)^2 over the exact structure          */
+    double flops_stored;   /* the same sum over the stored (amalgamated) structure  */
+    int32_t max_width;     /* widest supernode                                      */
+    int32_t max_below;     /* most rows below a diagonal block                      */
+} spc_symbolic_info;
+
+/* Fills *opt with the defaults (sn_cap 150, sched 0, no amalgamation, no budget). */
+void spc_default_options(spc_options* opt);
+
+/* Symbolic analysis on the host (no device work).  colptr/rowind/perm are
+ * host arrays borrowed for the call; the pattern is copied into the handle.
+ * opt may be NULL (defaults).  On success *out owns the analysis; release it
+ * with spc_symbolic_free.  Errors: SPC_ERR_ARG, SPC_ERR_PATTERN, SPC_ERR_OOM. */
+spc_status spc_analyze(int64_t n, const int64_t* colptr, const int32_t* rowind,
+                       const int32_t* perm, const spc_options* opt, spc_symbolic** out);
+
+spc_status spc_symbolic_info_get(const spc_symbolic* sym, spc_symbolic_info* info);
+
+/* Host copies of the analysis, for checking.  Each output may be NULL.
+ *   parent[n]    elimination tree of P A P^T (-1 = root), Section II-B;
+ *   colcount[n]  column counts of L including the diagonal;
+ *   sn_ptr[nsup+1] first column of each supernode, then n;
+ *   sn_parent[nsup] supernodal elimination tree (-1 = root). */
+spc_status spc_symbolic_export(const spc_symbolic* sym, int32_t* parent, int32_t* colcount,
+                               int32_t* sn_ptr, int32_t* sn_parent);
+
+/* Supernode row lists: rowptr[nsup+1] (int64) and rows[rowptr[nsup]] (int32):
+ * the supernode's own columns, then the sorted rows below its diagonal block.
+ * Supernode s stores a column-major (rowptr[s+1]-rowptr[s]) x width block. */
+spc_status spc_symbolic_export_rows(const spc_symbolic* sym, int64_t* rowptr, int32_t* rows);
+
+/* Update pairs and relative indices.  For pair p (npairs of them, grouped by
+ * source): src[p], tgt[p], seg[2p..2p+1] = [begin, end) of the source's
+ * below-diagonal rows that fall in the target's columns, rel_off[p] = offset of
+ * the pair's relative indices in rel[nrel]; for every below-diagonal row i of
+ * the source with i >= begin, rel[rel_off[p] + i - begin] is that row's
+ * position in the target's row list.  Any output may be NULL. */
+spc_status spc_symbolic_export_pairs(const spc_symbolic* sym, int32_t* src, int32_t* tgt,
+                                     int32_t* seg, int64_t* rel_off, int32_t* rel);
+
+/* Releases the handle.  Returns SPC_ERR_BUSY (and frees nothing) while a
+ * numeric factor created from it is alive.  NULL is accepted. */
+spc_status spc_symbolic_free(spc_symbolic* sym);
+
+/* Numeric factorization on the current HIP device, ordered on stream.
+ * values_dev: device array of nnz_a doubles aligned with the analyzed pattern.
+ * The call returns once the work is enqueued; the factor status becomes known
+ * through spc_numeric_status (which synchronizes) or the next spc_solve.  On
+ * success *out owns the factor's device memory; it references sym, so free it
+ * first.  Errors: SPC_ERR_ARG, SPC_ERR_OOM (allocation or mem_budget_bytes),
+ * SPC_ERR_HIP. */
+spc_status spc_factor(const spc_symbolic* sym, const double* values_dev, void* stream,
+                      spc_numeric** out);
+
+/* Factor again with fresh values on the same pattern, reusing num's memory. */
+spc_status spc_refactor(spc_numeric* num, const double* values_dev, void* stream);
+
+/* Synchronizes the factor's stream and returns its status: 0, the 1-based
+ * failing pivot column (> 0), SPC_ERR_TIMEOUT or SPC_ERR_HIP. */
+spc_status spc_numeric_status(spc_numeric* num);
+
+/* x = A^{-1} b for nrhs right-hand sides: b_dev and x_dev are column-major
+ * device arrays (leading dimensions ldb, ldx >= n) of doubles; x_dev may equal
+ * b_dev when ldx == ldb.  Synchronizes on the factor status first: a failed
+ * factor returns its status (> 0) and leaves x_dev untouched.  Enqueued on
+ * stream, otherwise asynchronous. */
+spc_status spc_solve(spc_numeric* num, int32_t nrhs, const double* b_dev, int64_t ldb,
+                     double* x_dev, int64_t ldx, void* stream);
+
+/* Host copy of the factor in the stored (supernodal) column structure:
+ * Sp[n+1] (int64) and Si (int32) give, for column j of supernode s, the rows
+ * j..last(s) then the rows below the supernode's diagonal block; Sx holds the
+ * values.  Entries outside the exact structure of L are explicit zeros.
+ * Synchronizes.  Any output may be NULL; sizes are n+1 and nnz_stored. */
+spc_status spc_factor_export(spc_numeric* num, int64_t* Sp, int32_t* Si, double* Sx);
+
+/* Releases the factor's device memory (synchronizing its stream). NULL is accepted. */
+void spc_numeric_free(spc_numeric* num);
+
+/* Static English text for a status code. */
+const char* spc_status_string(spc_status st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPCHOL_H */

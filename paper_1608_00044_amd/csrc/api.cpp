@@ -1,0 +1,282 @@
+// C ABI of the supernodal Cholesky library (declared in include/spchol.h).
+#include <hip/hip_runtime_api.h>
+
+#include <climits>
+#include <cstring>
+#include <new>
+
+#include "../../include/spchol.h"
+#include "runtime.hpp"
+
+namespace spc {
+int32_t configure_kernels();
+}
+
+using namespace spc;
+
+extern "C" {
+
+void spc_default_options(spc_options* opt) {
+    if (!opt) return;
+    opt->sn_cap = 150;
+    opt->sched = 0;
+    opt->amalg_ratio = 0.0;
+    opt->mem_budget_bytes = 0;
+}
+
+const char* spc_status_string(spc_status st) {
+    if (st > 0) return "factorization stopped: a pivot was not positive";
+    switch (st) {
+        case SPC_OK: return "success";
+        case SPC_ERR_ARG: return "invalid argument";
+        case SPC_ERR_PATTERN: return "malformed lower-triangular CSC pattern";
+        case SPC_ERR_OOM: return "out of memory or over the memory budget";
+        case SPC_ERR_HIP: return "HIP runtime error";
+        case SPC_ERR_NOT_FACTORED: return "no completed factorization";
+        case SPC_ERR_NOT_CONVERGED: return "iterative refinement did not converge";
+        case SPC_ERR_TIMEOUT: return "device wait exceeded its bound";
+        case SPC_ERR_BUSY: return "symbolic handle is still referenced";
+        default: return "unknown status";
+    }
+}
+
+spc_status spc_analyze(int64_t n, const int64_t* colptr, const int32_t* rowind,
+                       const int32_t* perm, const spc_options* opt, spc_symbolic** out) {
+    if (!out) return SPC_ERR_ARG;
+    *out = nullptr;
+    spc_options o;
+    spc_default_options(&o);
+    if (opt) o = *opt;
+    if (o.sn_cap < 1 || o.sn_cap > kMaxWidth) return SPC_ERR_ARG;
+    if (o.sched != 0) return SPC_ERR_ARG;
+    if (!(o.amalg_ratio >= 0.0 && o.amalg_ratio <= 1.0)) return SPC_ERR_ARG;
+    if (o.mem_budget_bytes < 0) return SPC_ERR_ARG;
+    spc_symbolic* h = new (std::nothrow) spc_symbolic();
+    if (!h) return SPC_ERR_OOM;
+    Options so;
+    so.sn_cap = o.sn_cap;
+    so.amalg_ratio = o.amalg_ratio;
+    so.sched = o.sched;
+    int32_t st;
+    try {
+        st = analyze(n, colptr, rowind, perm, so, &h->S);
+        if (st == OK) h->plan_bytes_estimate = plan_bytes(h->S);
+    } catch (const std::bad_alloc&) {
+        st = SPC_ERR_OOM;
+    }
+    if (st != OK) {
+        delete h;
+        return st;
+    }
+    h->budget = o.mem_budget_bytes;
+    *out = h;
+    return SPC_OK;
+}
+
+spc_status spc_symbolic_info_get(const spc_symbolic* sym, spc_symbolic_info* info) {
+    if (!sym || !info) return SPC_ERR_ARG;
+    const Symbolic& S = sym->S;
+    std::memset(info, 0, sizeof(*info));
+    info->n = S.n;
+    info->nnz_a = S.nnz_a;
+    info->nnz_l = S.nnz_l;
+    info->nnz_stored = S.nnz_stored;
+    info->nsup = S.nsup;
+    info->nlevels = (int64_t)S.level_ptr.size() - 1;
+    info->npairs = (int64_t)S.pairs.size();
+    info->nrel = (int64_t)S.rel.size();
+    info->factor_bytes = (int64_t)(S.arena * sizeof(double)) + 256;
+    info->plan_bytes = (int64_t)sym->plan_bytes_estimate;
+    info->flops = S.flops;
+    info->flops_stored = S.flops_stored;
+    info->max_width = S.max_w;
+    info->max_below = S.max_r;
+    return SPC_OK;
+}
+
+spc_status spc_symbolic_export(const spc_symbolic* sym, int32_t* parent, int32_t* colcount,
+                               int32_t* sn_ptr, int32_t* sn_parent) {
+    if (!sym) return SPC_ERR_ARG;
+    const Symbolic& S = sym->S;
+    if (parent && S.n) std::memcpy(parent, S.parent.data(), sizeof(int32_t) * S.n);
+    if (colcount && S.n) std::memcpy(colcount, S.colcount.data(), sizeof(int32_t) * S.n);
+    if (sn_ptr) std::memcpy(sn_ptr, S.sn_ptr.data(), sizeof(int32_t) * (S.nsup + 1));
+    if (sn_parent && S.nsup) std::memcpy(sn_parent, S.sn_parent.data(), sizeof(int32_t) * S.nsup);
+    return SPC_OK;
+}
+
+spc_status spc_symbolic_export_rows(const spc_symbolic* sym, int64_t* rowptr, int32_t* rows) {
+    if (!sym) return SPC_ERR_ARG;
+    const Symbolic& S = sym->S;
+    if (rowptr) std::memcpy(rowptr, S.rowptr.data(), sizeof(int64_t) * (S.nsup + 1));
+    if (rows && !S.rows.empty()) std::memcpy(rows, S.rows.data(), sizeof(int32_t) * S.rows.size());
+    return SPC_OK;
+}
+
+spc_status spc_symbolic_export_pairs(const spc_symbolic* sym, int32_t* src, int32_t* tgt,
+                                     int32_t* seg, int64_t* rel_off, int32_t* rel) {
+    if (!sym) return SPC_ERR_ARG;
+    const Symbolic& S = sym->S;
+    for (size_t p = 0; p < S.pairs.size(); ++p) {
+        if (src) src[p] = S.pairs[p].src;
+        if (tgt) tgt[p] = S.pairs[p].tgt;
+        if (seg) { seg[2 * p] = S.pairs[p].seg_begin; seg[2 * p + 1] = S.pairs[p].seg_end; }
+        if (rel_off) rel_off[p] = S.pairs[p].rel_off;
+    }
+    if (rel && !S.rel.empty()) std::memcpy(rel, S.rel.data(), sizeof(int32_t) * S.rel.size());
+    return SPC_OK;
+}
+
+spc_status spc_symbolic_free(spc_symbolic* sym) {
+    if (!sym) return SPC_OK;
+    {
+        std::lock_guard<std::mutex> lock(sym->mu);
+        if (sym->refs > 0) return SPC_ERR_BUSY;
+    }
+    for (DevicePlan* p : sym->plans) free_plan(p);
+    delete sym;
+    return SPC_OK;
+}
+
+static spc_status alloc_numeric(spc_symbolic* sym, spc_numeric** out) {
+    int32_t st = configure_kernels();
+    if (st != OK) return st;
+    const Symbolic& S = sym->S;
+    const int64_t need = (int64_t)(S.arena * sizeof(double)) + 256;
+    if (sym->budget > 0 && need + (int64_t)sym->plan_bytes_estimate > sym->budget)
+        return SPC_ERR_OOM;
+    DevicePlan* plan = nullptr;
+    st = get_plan(sym, &plan);
+    if (st != OK) return st;
+    spc_numeric* num = new (std::nothrow) spc_numeric();
+    if (!num) return SPC_ERR_OOM;
+    num->sym = sym;
+    num->plan = plan;
+    num->device = plan->device;
+    if (hipMalloc(&num->arena, sizeof(double) * (size_t)(S.arena > 0 ? S.arena : 1)) !=
+        hipSuccess) {
+        delete num;
+        return SPC_ERR_OOM;
+    }
+    if (hipMalloc(&num->status_dev, 256) != hipSuccess) {
+        (void)hipFree(num->arena);
+        delete num;
+        return SPC_ERR_OOM;
+    }
+    {
+        std::lock_guard<std::mutex> lock(sym->mu);
+        sym->refs++;
+    }
+    *out = num;
+    return SPC_OK;
+}
+
+spc_status spc_factor(const spc_symbolic* csym, const double* values_dev, void* stream,
+                      spc_numeric** out) {
+    if (!csym || !out) return SPC_ERR_ARG;
+    *out = nullptr;
+    spc_symbolic* sym = const_cast<spc_symbolic*>(csym);
+    if (sym->S.nnz_a > 0 && !values_dev) return SPC_ERR_ARG;
+    spc_numeric* num = nullptr;
+    spc_status st = alloc_numeric(sym, &num);
+    if (st != SPC_OK) return st;
+    st = run_factor(num, values_dev, (hipStream_t)stream);
+    if (st != SPC_OK) {
+        spc_numeric_free(num);
+        return st;
+    }
+    *out = num;
+    return SPC_OK;
+}
+
+spc_status spc_refactor(spc_numeric* num, const double* values_dev, void* stream) {
+    if (!num) return SPC_ERR_ARG;
+    if (num->sym->S.nnz_a > 0 && !values_dev) return SPC_ERR_ARG;
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return SPC_ERR_HIP;
+    if (cur != num->device) return SPC_ERR_ARG;
+    num->host_status = 0;
+    return run_factor(num, values_dev, (hipStream_t)stream);
+}
+
+spc_status spc_numeric_status(spc_numeric* num) {
+    if (!num) return SPC_ERR_ARG;
+    if (!num->factored) return SPC_ERR_NOT_FACTORED;
+    if (hipStreamSynchronize(num->stream) != hipSuccess) return SPC_ERR_HIP;
+    int32_t v = 0;
+    if (hipMemcpy(&v, num->status_dev, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+        return SPC_ERR_HIP;
+    num->host_status = (v == INT32_MAX) ? 0 : v;
+    return num->host_status;
+}
+
+spc_status spc_solve(spc_numeric* num, int32_t nrhs, const double* b_dev, int64_t ldb,
+                     double* x_dev, int64_t ldx, void* stream) {
+    if (!num || nrhs < 0) return SPC_ERR_ARG;
+    const int64_t n = num->sym->S.n;
+    if (nrhs > 0 && n > 0 && (!b_dev || !x_dev || ldb < n || ldx < n)) return SPC_ERR_ARG;
+    if (b_dev == x_dev && ldb != ldx) return SPC_ERR_ARG;
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return SPC_ERR_HIP;
+    if (cur != num->device) return SPC_ERR_ARG;
+    spc_status st = spc_numeric_status(num);
+    if (st != SPC_OK) return st;
+    return run_solve(num, nrhs, b_dev, ldb, x_dev, ldx, (hipStream_t)stream);
+}
+
+spc_status spc_factor_export(spc_numeric* num, int64_t* Sp, int32_t* Si, double* Sx) {
+    if (!num) return SPC_ERR_ARG;
+    const Symbolic& S = num->sym->S;
+    if (Sp || Si) {
+        int64_t q = 0;
+        if (Sp) Sp[0] = 0;
+        for (int64_t s = 0; s < S.nsup; ++s) {
+            const int32_t w = S.width(s), m = S.nrows(s);
+            const int32_t* R = S.rows.data() + S.rowptr[s];
+            for (int32_t c = 0; c < w; ++c) {
+                for (int32_t i = c; i < m; ++i) {
+                    if (Si) Si[q] = R[i];
+                    ++q;
+                }
+                if (Sp) Sp[S.sn_ptr[s] + c + 1] = q;
+            }
+        }
+    }
+    if (Sx) {
+        if (!num->factored) return SPC_ERR_NOT_FACTORED;
+        if (hipStreamSynchronize(num->stream) != hipSuccess) return SPC_ERR_HIP;
+        std::vector<double> h((size_t)(S.arena > 0 ? S.arena : 1));
+        if (S.arena > 0 &&
+            hipMemcpy(h.data(), num->arena, sizeof(double) * S.arena, hipMemcpyDeviceToHost) !=
+                hipSuccess)
+            return SPC_ERR_HIP;
+        int64_t q = 0;
+        for (int64_t s = 0; s < S.nsup; ++s) {
+            const int32_t w = S.width(s), m = S.nrows(s), ld = S.ld[s];
+            const double* B = h.data() + S.off[s];
+            for (int32_t c = 0; c < w; ++c)
+                for (int32_t i = c; i < m; ++i) Sx[q++] = B[i + (int64_t)c * ld];
+        }
+    }
+    return SPC_OK;
+}
+
+void spc_numeric_free(spc_numeric* num) {
+    if (!num) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(num->device);
+    if (num->stream) (void)hipStreamSynchronize(num->stream);
+    else (void)hipDeviceSynchronize();
+    (void)hipFree(num->arena);
+    (void)hipFree(num->status_dev);
+    if (num->work) (void)hipFree(num->work);
+    (void)hipSetDevice(cur);
+    {
+        std::lock_guard<std::mutex> lock(num->sym->mu);
+        num->sym->refs--;
+    }
+    delete num;
+}
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+// Device side of the supernodal Cholesky: the plan uploaded to HBM, the
+// numeric factor object, and the factor / solve drivers.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+#include <mutex>
+#include <vector>
+
+#include "symbolic.hpp"
+
+namespace spc {
+
+// Tile edge of the update and panel kernels (rows of the below-diagonal panel).
+constexpr int kTile = 64;
+// Widest supernode the diagonal-block kernel holds in LDS (packed lower triangle).
+constexpr int kMaxWidth = 160;
+
+// One update tile: rows [bi*64, bi*64+64) x columns [bj*64, bj*64+64) of the
+// lower triangle of P P^T, P = the below-diagonal panel of source supernode s.
+struct UpdTile { int32_t s; int16_t bi, bj; };
+// One panel row block of source supernode s.
+struct RowBlock { int32_t s; int32_t rb; };
+
+// Device copy of the symbolic analysis, shared by every factor of it on one device.
+struct DevicePlan {
+    int device = -1;
+    void* block = nullptr;  // single allocation holding everything below
+    size_t bytes = 0;
+    int32_t* sn_first = nullptr;
+    int32_t* sn_w = nullptr;
+    int32_t* sn_ld = nullptr;
+    int64_t* sn_off = nullptr;
+    int64_t* rowptr = nullptr;
+    int32_t* rows = nullptr;
+    int32_t* rowpair = nullptr;  // per entry of rows: pair index of the source row, -1 on own columns
+    int64_t* slot = nullptr;
+    int32_t* perm = nullptr;     // perm[new] = old
+    int32_t* pair_tgt = nullptr;
+    int32_t* pair_seg = nullptr;  // seg_begin
+    int64_t* pair_rel = nullptr;  // rel_off
+    int32_t* rel = nullptr;
+    int32_t* level_sn = nullptr;
+    RowBlock* rowblk = nullptr;
+    UpdTile* tiles = nullptr;
+    // host-side launch bookkeeping per level
+    std::vector<int64_t> rowblk_ptr, tile_ptr;
+    std::vector<int32_t> level_maxw;
+};
+
+// Pointer bundle passed by value to kernels.
+struct KArgs {
+    const int32_t* sn_first;
+    const int32_t* sn_w;
+    const int32_t* sn_ld;
+    const int64_t* sn_off;
+    const int64_t* rowptr;
+    const int32_t* rows;
+    const int32_t* rowpair;
+    const int32_t* pair_tgt;
+    const int32_t* pair_seg;
+    const int64_t* pair_rel;
+    const int32_t* rel;
+};
+
+}  // namespace spc
+
+struct spc_symbolic {
+    spc::Symbolic S;
+    int refs = 0;  // live numeric factors
+    std::mutex mu;
+    std::vector<spc::DevicePlan*> plans;  // one per device that used it
+    size_t plan_bytes_estimate = 0;
+    int64_t budget = 0;  // mem_budget_bytes of the options (0 = none)
+};
+
+struct spc_numeric {
+    spc_symbolic* sym = nullptr;
+    spc::DevicePlan* plan = nullptr;
+    int device = -1;
+    double* arena = nullptr;
+    int32_t* status_dev = nullptr;  // INT32_MAX = no failure
+    double* work = nullptr;         // solve vector, n x work_cols
+    int64_t work_cols = 0;
+    hipStream_t stream = nullptr;
+    int32_t host_status = 0;
+    bool factored = false;
+};
+
+namespace spc {
+
+size_t plan_bytes(const Symbolic& S);
+int32_t get_plan(spc_symbolic* sym, DevicePlan** out);
+void free_plan(DevicePlan* p);
+int32_t run_factor(spc_numeric* num, const double* values, hipStream_t stream);
+int32_t run_solve(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb, double* x,
+                  int64_t ldx, hipStream_t stream);
+
+}  // namespace spc

@@ -1,0 +1,328 @@
+"""Python binding of the spchol C ABI (include/spchol.h).
+
+Argument marshalling only: every step of the factorization and solve runs in
+the HIP library ``libspchol.so`` built in-tree by ``paper_1608_00044_amd.build``.
+There is no fallback: if the library is missing, ``lib()`` raises.
+
+Host arrays are numpy; device arrays are torch tensors on the current HIP
+device (float64), passed by ``data_ptr()``; the stream is torch's current
+stream unless one is given.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspchol.so")
+_lib = None
+
+SPC_OK = 0
+SPC_ERR_ARG = -1
+SPC_ERR_PATTERN = -2
+SPC_ERR_OOM = -3
+SPC_ERR_HIP = -4
+SPC_ERR_NOT_FACTORED = -5
+SPC_ERR_NOT_CONVERGED = -6
+SPC_ERR_TIMEOUT = -7
+SPC_ERR_BUSY = -8
+
+# Every symbol include/spchol.h declares.
+EXPORTS = ("spc_default_options", "spc_analyze", "spc_symbolic_info_get", "spc_symbolic_export",
+           "spc_symbolic_export_rows", "spc_symbolic_export_pairs", "spc_symbolic_free",
+           "spc_factor", "spc_refactor", "spc_numeric_status", "spc_solve", "spc_factor_export",
+           "spc_numeric_free", "spc_status_string")
+
+
+class spc_options(C.Structure):
+    _fields_ = [("sn_cap", C.c_int32), ("sched", C.c_int32), ("amalg_ratio", C.c_double),
+                ("mem_budget_bytes", C.c_int64)]
+
+
+class spc_symbolic_info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz_a", C.c_int64), ("nnz_l", C.c_int64),
+                ("nnz_stored", C.c_int64), ("nsup", C.c_int64), ("nlevels", C.c_int64),
+                ("npairs", C.c_int64), ("nrel", C.c_int64), ("factor_bytes", C.c_int64),
+                ("plan_bytes", C.c_int64), ("flops", C.c_double), ("flops_stored", C.c_double),
+                ("max_width", C.c_int32), ("max_below", C.c_int32)]
+
+
+class SpcError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = int(status)
+        super().__init__("%s: %s (%d)" % (where, status_string(status), status))
+
+
+def lib():
+    """Load libspchol.so from the package directory (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libspchol.so is not built; run paper_1608_00044_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.spc_default_options.argtypes = [C.POINTER(spc_options)]
+        L.spc_default_options.restype = None
+        L.spc_analyze.argtypes = [C.c_int64, vp, vp, vp, C.POINTER(spc_options), C.POINTER(vp)]
+        L.spc_analyze.restype = C.c_int32
+        L.spc_symbolic_info_get.argtypes = [vp, C.POINTER(spc_symbolic_info)]
+        L.spc_symbolic_info_get.restype = C.c_int32
+        L.spc_symbolic_export.argtypes = [vp, vp, vp, vp, vp]
+        L.spc_symbolic_export.restype = C.c_int32
+        L.spc_symbolic_export_rows.argtypes = [vp, vp, vp]
+        L.spc_symbolic_export_rows.restype = C.c_int32
+        L.spc_symbolic_export_pairs.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.spc_symbolic_export_pairs.restype = C.c_int32
+        L.spc_symbolic_free.argtypes = [vp]
+        L.spc_symbolic_free.restype = C.c_int32
+        L.spc_factor.argtypes = [vp, vp, vp, C.POINTER(vp)]
+        L.spc_factor.restype = C.c_int32
+        L.spc_refactor.argtypes = [vp, vp, vp]
+        L.spc_refactor.restype = C.c_int32
+        L.spc_numeric_status.argtypes = [vp]
+        L.spc_numeric_status.restype = C.c_int32
+        L.spc_solve.argtypes = [vp, C.c_int32, vp, C.c_int64, vp, C.c_int64, vp]
+        L.spc_solve.restype = C.c_int32
+        L.spc_factor_export.argtypes = [vp, vp, vp, vp]
+        L.spc_factor_export.restype = C.c_int32
+        L.spc_numeric_free.argtypes = [vp]
+        L.spc_numeric_free.restype = None
+        L.spc_status_string.argtypes = [C.c_int32]
+        L.spc_status_string.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def status_string(st: int) -> str:
+    return lib().spc_status_string(int(st)).decode()
+
+
+def _np(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def _ptr(a):
+    return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+def _stream_ptr(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(int(stream.cuda_stream))
+
+
+# ---------------------------------------------------------------------------
+# symbolic
+# ---------------------------------------------------------------------------
+
+class Symbolic:
+    """spc_analyze: host symbolic analysis of the lower CSC pattern."""
+
+    def __init__(self, n, colptr, rowind, perm=None, sn_cap=150, amalg_ratio=0.0, sched=0,
+                 mem_budget_bytes=0):
+        self.n = int(n)
+        cp = _np(colptr, np.int64)
+        ri = _np(rowind, np.int32)
+        pm = None if perm is None else _np(perm, np.int32)
+        opt = spc_options()
+        lib().spc_default_options(C.byref(opt))
+        opt.sn_cap = int(sn_cap)
+        opt.sched = int(sched)
+        opt.amalg_ratio = float(amalg_ratio)
+        opt.mem_budget_bytes = int(mem_budget_bytes)
+        h = C.c_void_p()
+        if ri.size == 0:
+            ri = np.zeros(1, dtype=np.int32)
+        st = lib().spc_analyze(self.n, _ptr(cp), _ptr(ri), _ptr(pm), C.byref(opt), C.byref(h))
+        if st != SPC_OK:
+            raise SpcError(st, "spc_analyze")
+        self.handle = h
+        self.perm = np.arange(self.n, dtype=np.int32) if pm is None else pm.copy()
+
+    def info(self) -> dict:
+        inf = spc_symbolic_info()
+        st = lib().spc_symbolic_info_get(self.handle, C.byref(inf))
+        if st != SPC_OK:
+            raise SpcError(st, "spc_symbolic_info_get")
+        return {f: getattr(inf, f) for f, _ in spc_symbolic_info._fields_}
+
+    def export(self):
+        inf = self.info()
+        n, ns = inf["n"], inf["nsup"]
+        parent = np.zeros(max(n, 1), dtype=np.int32)
+        cc = np.zeros(max(n, 1), dtype=np.int32)
+        sp = np.zeros(ns + 1, dtype=np.int32)
+        spar = np.zeros(max(ns, 1), dtype=np.int32)
+        st = lib().spc_symbolic_export(self.handle, _ptr(parent), _ptr(cc), _ptr(sp), _ptr(spar))
+        if st != SPC_OK:
+            raise SpcError(st, "spc_symbolic_export")
+        return parent[:n], cc[:n], sp, spar[:ns]
+
+    def rows(self):
+        ns = self.info()["nsup"]
+        rp = np.zeros(ns + 1, dtype=np.int64)
+        lib().spc_symbolic_export_rows(self.handle, _ptr(rp), None)
+        rows = np.zeros(max(int(rp[-1]), 1), dtype=np.int32)
+        lib().spc_symbolic_export_rows(self.handle, None, _ptr(rows))
+        return rp, rows[: int(rp[-1])]
+
+    def pairs(self):
+        inf = self.info()
+        npairs, nrel = inf["npairs"], inf["nrel"]
+        src = np.zeros(max(npairs, 1), dtype=np.int32)
+        tgt = np.zeros(max(npairs, 1), dtype=np.int32)
+        seg = np.zeros(max(2 * npairs, 2), dtype=np.int32)
+        ro = np.zeros(max(npairs, 1), dtype=np.int64)
+        rel = np.zeros(max(nrel, 1), dtype=np.int32)
+        st = lib().spc_symbolic_export_pairs(self.handle, _ptr(src), _ptr(tgt), _ptr(seg), _ptr(ro),
+                                             _ptr(rel))
+        if st != SPC_OK:
+            raise SpcError(st, "spc_symbolic_export_pairs")
+        return dict(src=src[:npairs], tgt=tgt[:npairs], seg=seg[: 2 * npairs].reshape(-1, 2),
+                    rel_off=ro[:npairs], rel=rel[:nrel])
+
+    def free(self):
+        if getattr(self, "handle", None):
+            st = lib().spc_symbolic_free(self.handle)
+            if st != SPC_OK:
+                raise SpcError(st, "spc_symbolic_free")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                lib().spc_symbolic_free(self.handle)
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# numeric
+# ---------------------------------------------------------------------------
+
+def _dev_f64(t, name):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError("%s must be a float64 tensor on the GPU" % name)
+    return t
+
+
+class Numeric:
+    """spc_factor: device numeric factorization; owns the factor's device memory."""
+
+    def __init__(self, sym: Symbolic, values, stream=None):
+        values = _dev_f64(values, "values").contiguous()
+        self.sym = sym
+        self._values = values  # keep alive until the stream has consumed it
+        h = C.c_void_p()
+        st = lib().spc_factor(sym.handle, C.c_void_p(values.data_ptr()), _stream_ptr(stream),
+                              C.byref(h))
+        if st != SPC_OK:
+            raise SpcError(st, "spc_factor")
+        self.handle = h
+
+    def refactor(self, values, stream=None):
+        values = _dev_f64(values, "values").contiguous()
+        self._values = values
+        st = lib().spc_refactor(self.handle, C.c_void_p(values.data_ptr()), _stream_ptr(stream))
+        if st != SPC_OK:
+            raise SpcError(st, "spc_refactor")
+
+    def status(self) -> int:
+        return int(lib().spc_numeric_status(self.handle))
+
+    def solve(self, b, x=None, stream=None):
+        """x = A^{-1} b; b is (n,) or (n, k); returns x with b's shape."""
+        import torch
+
+        b = _dev_f64(b, "b")
+        n = self.sym.n
+        one = b.dim() == 1
+        B = b.reshape(n, 1) if one else b
+        if B.shape[0] != n:
+            raise ValueError("b has %d rows, expected %d" % (B.shape[0], n))
+        k = B.shape[1]
+        if B.stride(0) != 1 or (k > 1 and B.stride(1) < n):
+            B = B.t().contiguous().t()  # column-major copy
+        ldb = max(B.stride(1) if k > 1 else n, n)
+        if x is None:
+            X = torch.empty((k, n), dtype=torch.float64, device=b.device).t()
+        else:
+            X = _dev_f64(x, "x").reshape(n, k)
+            if X.stride(0) != 1 or (k > 1 and X.stride(1) < n):
+                raise ValueError("x must be column-major (n, k)")
+        ldx = max(X.stride(1) if k > 1 else n, n)
+        st = lib().spc_solve(self.handle, k, C.c_void_p(B.data_ptr()), ldb,
+                             C.c_void_p(X.data_ptr()), ldx, _stream_ptr(stream))
+        if st != SPC_OK:
+            raise SpcError(st, "spc_solve")
+        return X.reshape(n) if one else X
+
+    def export(self):
+        """Host copy (Sp, Si, Sx) of L in the stored supernodal column structure."""
+        nnz = self.sym.info()["nnz_stored"]
+        n = self.sym.n
+        Sp = np.zeros(n + 1, dtype=np.int64)
+        Si = np.zeros(max(nnz, 1), dtype=np.int32)
+        Sx = np.zeros(max(nnz, 1), dtype=np.float64)
+        st = lib().spc_factor_export(self.handle, _ptr(Sp), _ptr(Si), _ptr(Sx))
+        if st != SPC_OK:
+            raise SpcError(st, "spc_factor_export")
+        return Sp, Si[:nnz], Sx[:nnz]
+
+    def free(self):
+        if getattr(self, "handle", None):
+            lib().spc_numeric_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+# C-ABI-named entry points
+def analyze(n, colptr, rowind, perm=None, **opts) -> Symbolic:
+    return Symbolic(n, colptr, rowind, perm, **opts)
+
+
+def factor(sym: Symbolic, values, stream=None) -> Numeric:
+    return Numeric(sym, values, stream)
+
+
+def refactor(num: Numeric, values, stream=None) -> None:
+    num.refactor(values, stream)
+
+
+def numeric_status(num: Numeric) -> int:
+    return num.status()
+
+
+def solve(num: Numeric, b, x=None, stream=None):
+    return num.solve(b, x, stream)
+
+
+def factor_export(num: Numeric):
+    return num.export()
+
+
+def symbolic_free(sym: Symbolic) -> None:
+    sym.free()
+
+
+def numeric_free(num: Numeric) -> None:
+    num.free()
+
+
+@dataclass
+class StoredFactor:
+    Sp: np.ndarray
+    Si: np.ndarray
+    Sx: np.ndarray

@@ -1,0 +1,190 @@
+"""GPU parity of the HIP factorization and solve with the CPU oracle, through
+the C ABI, on seeded inputs that span several tiles, ragged tails, chains
+split by the cap, amalgamated supernodes and the degenerate cases.
+
+Bars: integer structure bit-exact (checked on the CPU); every entry of the
+FP64 factor within |dL_ij| <= 1e-10 |L_ij| + 1e-13 sqrt(c_ii c_jj) / L_jj of
+the oracle's (c = diagonal of P A P^T); explicit zeros of amalgamated storage
+exactly zero; ||L L^T - P A P^T||_F / ||A||_F <= 1e-12; solutions within
+1e-10 relative of the oracle's and normwise backward error <= 1e-14."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_00044_amd import inputs, spchol
+from tests.gpu_util import compare_factor, gpu_factor, say, torch_dev
+from tests.helpers import load_fig1, spd_values_for_pattern
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(name):
+    if name.startswith("dense"):
+        n = int(name[5:])
+        return inputs.dense_spd(n, seed=n, nrhs=2), 150, 0.0
+    if name.startswith("tridiag"):
+        p = inputs.tridiag(int(name[7:]))
+        p.rhs = np.asfortranarray(np.random.default_rng(1).standard_normal((p.n, 1)))
+        return p, 150, 0.0
+    if name == "fig1":
+        fig = load_fig1()
+        p = spd_values_for_pattern(fig["n"], fig["orig"], seed=2)
+        p.rhs = np.asfortranarray(np.random.default_rng(2).standard_normal((p.n, 3)))
+        return p, 150, 0.0
+    if name.startswith("random"):
+        seed = int(name[6:])
+        rng = np.random.default_rng(seed)
+        n = int(rng.integers(20, 400))
+        return inputs.random_spd_pattern(n, float(rng.uniform(0.005, 0.05)), seed, nrhs=2), \
+            int(rng.choice([4, 16, 150])), float(rng.choice([0.0, 0.2]))
+    if name == "lap2d_64":
+        return inputs.make_workload("lap2d_5pt_64"), 150, 0.0
+    if name == "lap3d_12_amalg":
+        return inputs.make_grid_problem("lap", (12, 12, 12), 5, sigma=1.0, shift=1e-6), 150, 0.1
+    if name == "lap3d_20_cap32":
+        return inputs.make_grid_problem("lap", (20, 20, 20), 6, sigma=1.0, shift=1e-6,
+                                        nrhs=2), 32, 0.1
+    if name == "lap3d_24":
+        return inputs.make_grid_problem("lap", (24, 24, 24), 8, sigma=1.0, shift=1e-6), 150, 0.1
+    if name == "lap2d_40_cap8":
+        return inputs.make_grid_problem("lap", (40, 40), 9, sigma=0.5, shift=1e-3), 8, 0.3
+    if name == "elast27_6":
+        return inputs.make_grid_problem("27pt3", (6, 6, 6), 10, shift=1e-3, nrhs=2), 150, 0.1
+    raise KeyError(name)
+
+
+CASES = ["dense1", "dense2", "dense5", "dense63", "dense64", "dense65", "dense150", "dense151",
+         "dense300", "tridiag1000", "fig1", "random1", "random2", "random3", "random4",
+         "lap2d_64", "lap3d_12_amalg", "lap3d_20_cap32", "lap3d_24", "lap2d_40_cap8",
+         "elast27_6"]
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_factor_and_solve_parity(name):
+    torch = torch_dev()
+    p, cap, ratio = _case(name)
+    say("case", name, "n", p.n, "nnz", p.nnz, "cap", cap, "ratio", ratio)
+    sym, num, _ = gpu_factor(p, cap, ratio)
+    assert num.status() == 0
+    worst, rho, (osym, Lx, got) = compare_factor(p, num, cap, ratio, name)
+    say("  worst/tol", worst, "residual", rho)
+    assert worst <= 1.0
+    assert rho <= 1e-12
+    if p.rhs is not None:
+        b = torch.from_numpy(np.ascontiguousarray(p.rhs)).to("cuda:0")
+        x = num.solve(b if b.shape[1] > 1 else b[:, 0]).cpu().numpy().reshape(p.n, -1)
+        xo = oracle.solve(p.n, osym, Lx, p.perm, p.rhs).reshape(p.n, -1)
+        np.testing.assert_allclose(x, xo, rtol=1e-10, atol=1e-10 * np.abs(xo).max())
+        eta = oracle.backward_error(p.n, p.colptr, p.rowind, p.values, p.rhs, x)
+        say("  backward error", eta.max())
+        assert eta.max() <= 1e-14
+    num.free()
+    sym.free()
+
+
+def test_tridiag_closed_form_on_gpu():
+    n = 777
+    p = inputs.tridiag(n)
+    sym, num, _ = gpu_factor(p)
+    Sp, Si, Sx = num.export()
+    i = np.arange(1, n + 1, dtype=np.float64)
+    diag = Sx[Sp[:-1]]
+    np.testing.assert_allclose(diag, np.sqrt((i + 1) / i), rtol=1e-14)
+    # sub-diagonal: second stored entry of every column but the last
+    sub = Sx[Sp[:-2] + 1]
+    assert np.array_equal(Si[Sp[:-2] + 1], np.arange(1, n))
+    np.testing.assert_allclose(sub, -np.sqrt(i[:-1] / (i[:-1] + 1)), rtol=1e-14)
+
+
+@pytest.mark.parametrize("k", [1, 2, 30, 400])
+def test_non_spd_reports_first_failing_column(k):
+    torch = torch_dev()
+    n = 400
+    p = inputs.tridiag(n)
+    vals = p.values.copy()
+    vals[p.colptr[k - 1]] = (k - 1) / k - 0.5
+    q = inputs.Problem(n, p.colptr, p.rowind, vals, None)
+    sym, num, _ = gpu_factor(q)
+    assert num.status() == k
+    b = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(spchol.SpcError) as e:
+        num.solve(b)
+    assert e.value.status == k
+
+
+def test_non_spd_in_3d_parallel_schedule():
+    """Two independent failures: the smallest failing permuted column is reported."""
+    p = inputs.make_grid_problem("lap", (10, 10, 10), 3, sigma=1.0, shift=1e-3, nrhs=0)
+    Cp, Ci, Cx, mp = oracle.permute(p.n, p.colptr, p.rowind, p.values, p.perm)
+    vals = p.values.copy()
+    # make two diagonal entries negative; find their permuted columns
+    inv = np.argsort(mp)  # C position -> input entry
+    cols = []
+    for j in (137, 611):
+        q = Cp[j]  # diagonal is the first entry of column j of C
+        vals[inv[q]] = -1.0
+        cols.append(j)
+    q2 = inputs.Problem(p.n, p.colptr, p.rowind, vals, p.perm)
+    Cp2, Ci2, Cx2, _ = oracle.permute(p.n, q2.colptr, q2.rowind, q2.values, q2.perm)
+    osym = oracle.symbolic(p.n, Cp2, Ci2)
+    ost, _ = oracle.factor(p.n, Cp2, Ci2, Cx2, osym)
+    sym, num, _ = gpu_factor(q2, 150, 0.1)
+    assert num.status() == ost == min(cols) + 1
+
+
+def test_nan_value_reports_status():
+    n = 50
+    p = inputs.tridiag(n)
+    vals = p.values.copy()
+    vals[p.colptr[9]] = np.nan
+    sym, num, _ = gpu_factor(inputs.Problem(n, p.colptr, p.rowind, vals, None))
+    assert num.status() == 10
+
+
+def test_refactor_and_multi_rhs():
+    torch = torch_dev()
+    p = inputs.make_grid_problem("lap", (16, 16, 16), 21, sigma=1.0, shift=1e-3, nrhs=4)
+    sym, num, _ = gpu_factor(p, 150, 0.1)
+    assert num.status() == 0
+    p2 = inputs.make_grid_problem("lap", (16, 16, 16), 22, sigma=1.0, shift=1e-3, nrhs=4)
+    assert np.array_equal(p2.colptr, p.colptr) and np.array_equal(p2.rowind, p.rowind)
+    num.refactor(torch.from_numpy(p2.values).to("cuda:0"))
+    assert num.status() == 0
+    worst, rho, (osym, Lx, _) = compare_factor(p2, num, 150, 0.1, "refactor")
+    assert worst <= 1.0 and rho <= 1e-12
+    b = torch.from_numpy(np.ascontiguousarray(p2.rhs)).to("cuda:0")
+    x = num.solve(b).cpu().numpy()
+    xo = oracle.solve(p2.n, osym, Lx, p2.perm, p2.rhs)
+    np.testing.assert_allclose(x, xo, rtol=1e-10, atol=1e-10 * np.abs(xo).max())
+    # in-place solve (x aliases b)
+    bb = b.t().contiguous().t()
+    num.solve(bb, x=bb)
+    np.testing.assert_allclose(bb.cpu().numpy(), xo, rtol=1e-10, atol=1e-10 * np.abs(xo).max())
+
+
+def test_empty_matrix():
+    torch = torch_dev()
+    sym = spchol.analyze(0, [0], [])
+    num = spchol.factor(sym, torch.zeros(1, dtype=torch.float64, device="cuda:0"))
+    assert num.status() == 0
+    num.free()
+    sym.free()
+
+
+def test_symbolic_free_refuses_while_factor_alive():
+    p = inputs.tridiag(10)
+    sym, num, _ = gpu_factor(p)
+    with pytest.raises(spchol.SpcError) as e:
+        sym.free()
+    assert e.value.status == spchol.SPC_ERR_BUSY
+    num.free()
+    sym.free()
+
+
+def test_memory_budget_rejects_large_factor():
+    torch = torch_dev()
+    p = inputs.make_grid_problem("lap", (16, 16, 16), 1, sigma=1.0, shift=1e-3, nrhs=0)
+    sym = spchol.analyze(p.n, p.colptr, p.rowind, p.perm, mem_budget_bytes=1 << 20)
+    with pytest.raises(spchol.SpcError) as e:
+        spchol.factor(sym, torch.from_numpy(p.values).to("cuda:0"))
+    assert e.value.status == spchol.SPC_ERR_OOM

@@ -1,0 +1,155 @@
+"""Host logic of the HIP library, on the CPU: the C ABI loads and exports every
+declared symbol, argument checks, and the symbolic analysis matches the
+oracle's bit for bit."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_00044_amd import inputs, spchol
+from tests.helpers import load_fig1, spd_values_for_pattern
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "spchol.h")).read()
+    declared = set(re.findall(r"\b(spc_[a-z_]+)\s*\(", hdr))
+    assert declared == set(spchol.EXPORTS)
+    L = spchol.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_status_strings():
+    assert spchol.status_string(0) == "success"
+    assert "pivot" in spchol.status_string(7)
+    assert spchol.status_string(spchol.SPC_ERR_PATTERN).startswith("malformed")
+
+
+@pytest.mark.parametrize("rows,code", [([1, 0, 1, 2, 3], spchol.SPC_ERR_PATTERN),
+                                       ([0, 0, 1, 2, 3], spchol.SPC_ERR_PATTERN),
+                                       ([0, 1, 0, 2, 3], spchol.SPC_ERR_PATTERN),
+                                       ([0, 1, 1, 2, 4], spchol.SPC_ERR_PATTERN)])
+def test_analyze_rejects_bad_patterns(rows, code):
+    with pytest.raises(spchol.SpcError) as e:
+        spchol.analyze(4, [0, 2, 3, 4, 5], rows)
+    assert e.value.status == code
+
+
+def test_analyze_rejects_bad_arguments():
+    cp, ri = [0, 1, 2], [0, 1]
+    with pytest.raises(spchol.SpcError) as e:
+        spchol.analyze(2, cp, ri, perm=[0, 0])
+    assert e.value.status == spchol.SPC_ERR_ARG
+    for kw in (dict(sn_cap=0), dict(sn_cap=161), dict(amalg_ratio=-0.1), dict(sched=7),
+               dict(mem_budget_bytes=-1)):
+        with pytest.raises(spchol.SpcError) as e:
+            spchol.analyze(2, cp, ri, **kw)
+        assert e.value.status == spchol.SPC_ERR_ARG
+
+
+def _compare_with_oracle(p, cap=150, ratio=0.0):
+    sym = spchol.analyze(p.n, p.colptr, p.rowind, p.perm, sn_cap=cap, amalg_ratio=ratio)
+    parent, cc, sn, snp = sym.export()
+    Cp, Ci, Cx, _ = oracle.permute(p.n, p.colptr, p.rowind, p.values, p.perm)
+    osym = oracle.symbolic(p.n, Cp, Ci)
+    assert np.array_equal(parent, osym.parent)
+    assert np.array_equal(cc, osym.colcount)
+    osn = oracle.supernode_partition(p.n, osym.parent, osym.colcount, cap, ratio)
+    assert np.array_equal(sn, osn)
+    assert np.array_equal(snp, oracle.supernodal_parent(osym.parent, osn))
+    inf = sym.info()
+    assert inf["nnz_l"] == osym.nnz
+    assert inf["flops"] == float(osym.flops)
+    # stored rows below each supernode = exact structure of its last column
+    rp, rows = sym.rowptr_rows = sym.rows()
+    for s in range(len(sn) - 1):
+        a, b = sn[s], sn[s + 1] - 1
+        got = rows[rp[s]:rp[s + 1]]
+        assert got[: b - a + 1].tolist() == list(range(a, b + 1))
+        assert np.array_equal(got[b - a + 1:], osym.Li[osym.Lp[b] + 1:osym.Lp[b + 1]])
+    return sym, osym, sn
+
+
+def _check_relative_indices(sym, sn):
+    rp, rows = sym.rows()
+    pr = sym.pairs()
+    ns = len(sn) - 1
+    owner = np.repeat(np.arange(ns), np.diff(sn))
+    cover = {}
+    for p in range(len(pr["src"])):
+        s, t = int(pr["src"][p]), int(pr["tgt"][p])
+        b, e = pr["seg"][p]
+        w = sn[s + 1] - sn[s]
+        below = rows[rp[s] + w:rp[s + 1]]
+        assert t > s
+        # the segment holds exactly the source rows inside t's columns
+        assert (owner[below[b:e]] == t).all()
+        assert b == 0 or owner[below[b - 1]] < t
+        assert e == len(below) or owner[below[e]] > t
+        # relative index invariant: rows_t[rel[i]] == rows_s[i] for every i >= b
+        rt = rows[rp[t]:rp[t + 1]]
+        rel = pr["rel"][pr["rel_off"][p]:pr["rel_off"][p] + len(below) - b]
+        assert np.array_equal(rt[rel], below[b:])
+        cover.setdefault(s, []).append((b, e))
+    for s in range(ns):
+        w = sn[s + 1] - sn[s]
+        r = rp[s + 1] - rp[s] - w
+        segs = sorted(cover.get(s, []))
+        pos = 0
+        for b, e in segs:
+            assert b == pos
+            pos = e
+        assert pos == r
+
+
+def test_fig1_bit_exact():
+    fig = load_fig1()
+    p = spd_values_for_pattern(fig["n"], fig["orig"], seed=1)
+    sym, osym, sn = _compare_with_oracle(p)
+    assert len(sn) - 1 == 10
+    _check_relative_indices(sym, sn)
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_random_bit_exact(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 60))
+    p = inputs.random_spd_pattern(n, float(rng.uniform(0.02, 0.3)), seed=seed)
+    cap = int(rng.choice([1, 2, 3, 8, 150]))
+    ratio = float(rng.choice([0.0, 0.1, 0.5]))
+    sym, _, sn = _compare_with_oracle(p, cap, ratio)
+    _check_relative_indices(sym, sn)
+
+
+@pytest.mark.parametrize("dims,cap,ratio", [((64, 64), 150, 0.0), ((12, 12, 12), 150, 0.1),
+                                            ((20, 20, 20), 32, 0.1), ((40, 40), 150, 0.3)])
+def test_grid_bit_exact(dims, cap, ratio):
+    p = inputs.make_grid_problem("lap", dims, seed=7, sigma=1.0, shift=1e-6, nrhs=0)
+    sym, _, sn = _compare_with_oracle(p, cap, ratio)
+    if p.n <= 5000:
+        _check_relative_indices(sym, sn)
+
+
+def test_cfg2_symbolic_bit_exact():
+    """Full-size 64^3 7-point workload with amalgamation 0.1 (integer parity)."""
+    p = inputs.make_workload("lap3d_7pt_64", nrhs=0)
+    _compare_with_oracle(p, 150, 0.1)
+
+
+def test_empty_and_single():
+    sym = spchol.analyze(0, [0], [])
+    assert sym.info()["nsup"] == 0
+    sym = spchol.analyze(1, [0, 1], [0])
+    parent, cc, sn, snp = sym.export()
+    assert parent.tolist() == [-1] and cc.tolist() == [1] and sn.tolist() == [0, 1]
+
+
+def test_missing_diagonal_is_structural():
+    # column 1 has no diagonal entry: still analyzable (its pivot will be zero)
+    sym = spchol.analyze(3, [0, 2, 2, 3], [0, 1, 2])
+    parent, cc, _, _ = sym.export()
+    assert parent.tolist() == [1, -1, -1]
