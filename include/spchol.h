@@ -163,6 +163,21 @@ spc_status spc_solve(spc_numeric* num, int32_t nrhs, const double* b_dev, int64_
  * Synchronizes.  Any output may be NULL; sizes are n+1 and nnz_stored. */
 spc_status spc_factor_export(spc_numeric* num, int64_t* Sp, int32_t* Si, double* Sx);
 
+/* Per-kernel-class device times of the most recent factorization, measured
+ * with HIP events recorded on the factor's stream around every launch while
+ * timing is enabled (spc_numeric_set_timing).  Classes: 0 value load (fill +
+ * load), 1 diagonal factorization, 2 panel solve, 3 update + scatter.
+ * ms[c] is the summed duration of class c, launches[c] its launch count.
+ * Synchronizes the stream.  SPC_ERR_ARG if timing was never enabled. */
+typedef struct spc_kernel_times {
+    double ms[4];
+    int64_t launches[4];
+    double total_ms; /* from the first to the last recorded event */
+} spc_kernel_times;
+
+spc_status spc_numeric_set_timing(spc_numeric* num, int32_t enable);
+spc_status spc_numeric_get_timing(spc_numeric* num, spc_kernel_times* out);
+
 /* Releases the factor's device memory (synchronizing its stream). NULL is accepted. */
 void spc_numeric_free(spc_numeric* num);
 

@@ -261,6 +261,34 @@ spc_status spc_factor_export(spc_numeric* num, int64_t* Sp, int32_t* Si, double*
     return SPC_OK;
 }
 
+spc_status spc_numeric_set_timing(spc_numeric* num, int32_t enable) {
+    if (!num) return SPC_ERR_ARG;
+    num->timing = enable != 0;
+    return SPC_OK;
+}
+
+spc_status spc_numeric_get_timing(spc_numeric* num, spc_kernel_times* out) {
+    if (!num || !out) return SPC_ERR_ARG;
+    std::memset(out, 0, sizeof(*out));
+    if (num->marks.empty()) return num->timing ? SPC_OK : SPC_ERR_ARG;
+    if (hipStreamSynchronize(num->stream) != hipSuccess) return SPC_ERR_HIP;
+    for (const auto& m : num->marks) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, num->events[m.a], num->events[m.b]) != hipSuccess)
+            return SPC_ERR_HIP;
+        if (m.cls >= 0 && m.cls < 4) {
+            out->ms[m.cls] += ms;
+            out->launches[m.cls] += 1;
+        }
+    }
+    float tot = 0.f;
+    if (hipEventElapsedTime(&tot, num->events[num->marks.front().a],
+                            num->events[num->marks.back().b]) != hipSuccess)
+        return SPC_ERR_HIP;
+    out->total_ms = tot;
+    return SPC_OK;
+}
+
 void spc_numeric_free(spc_numeric* num) {
     if (!num) return;
     int cur = 0;
@@ -271,6 +299,7 @@ void spc_numeric_free(spc_numeric* num) {
     (void)hipFree(num->arena);
     (void)hipFree(num->status_dev);
     if (num->work) (void)hipFree(num->work);
+    for (hipEvent_t e : num->events) (void)hipEventDestroy(e);
     (void)hipSetDevice(cur);
     {
         std::lock_guard<std::mutex> lock(num->sym->mu);

@@ -110,6 +110,7 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
     for (DevicePlan* p : sym->plans)
         if (p->device == dev) { *out = p; return OK; }
     const Symbolic& S = sym->S;
+    if (S.max_r >= 32767 * kTile) return ERR_ARG;  // tile coordinates are 16-bit
     DevicePlan* P = new DevicePlan();
     P->device = dev;
     count_work(S, P->rowblk_ptr, P->tile_ptr);
@@ -163,7 +164,7 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
             for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
                 const int32_t s = S.level_sn[q];
                 P->level_maxw[l] = std::max(P->level_maxw[l], S.width(s));
-                const int32_t nb = (S.nbelow(s) + kTile - 1) / kTile;
+                const int32_t nb = (S.nbelow(s) + kTile - 1) / kTile;  // < 32768 (checked)
                 for (int32_t i = 0; i < nb; ++i) rb[a++] = RowBlock{s, i};
                 for (int32_t i = 0; i < nb; ++i)
                     for (int32_t j = 0; j <= i; ++j) tl[b++] = UpdTile{s, (int16_t)i, (int16_t)j};
@@ -430,12 +431,43 @@ static int grid_for(int64_t n, int block) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, 65536));
 }
 
+namespace {
+
+int take_event(spc_numeric* num) {
+    if (num->next_event == num->events.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return -1;
+        num->events.push_back(e);
+    }
+    return (int)num->next_event++;
+}
+
+// Records an event before a launch group when timing is on; returns its index or -1.
+int mark_begin(spc_numeric* num, hipStream_t st) {
+    if (!num->timing) return -1;
+    int e = take_event(num);
+    if (e >= 0 && hipEventRecord(num->events[e], st) != hipSuccess) return -1;
+    return e;
+}
+
+void mark_end(spc_numeric* num, hipStream_t st, int cls, int a) {
+    if (a < 0) return;
+    int b = take_event(num);
+    if (b < 0 || hipEventRecord(num->events[b], st) != hipSuccess) return;
+    num->marks.push_back(spc_numeric::Mark{cls, a, b});
+}
+
+}  // namespace
+
 int32_t run_factor(spc_numeric* num, const double* values, hipStream_t st) {
     const Symbolic& S = num->sym->S;
     const DevicePlan* P = num->plan;
     const KArgs a = kargs(P);
     num->stream = st;
     num->factored = false;
+    num->marks.clear();
+    num->next_event = 0;
+    int ev = mark_begin(num, st);
     if (S.arena > 0)
         hipLaunchKernelGGL(k_fill, dim3(grid_for(S.arena, 256)), dim3(256), 0, st, num->arena,
                            S.arena, 0.0);
@@ -444,22 +476,31 @@ int32_t run_factor(spc_numeric* num, const double* values, hipStream_t st) {
     if (S.nnz_a > 0)
         hipLaunchKernelGGL(k_load, dim3(grid_for(S.nnz_a, 256)), dim3(256), 0, st, values,
                            P->slot, num->arena, S.nnz_a);
+    mark_end(num, st, 0, ev);
     const int32_t nl = (int32_t)S.level_ptr.size() - 1;
     for (int32_t l = 0; l < nl; ++l) {
         const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1];
         const int wmax = P->level_maxw[l];
         const size_t lds_tri = (size_t)wmax * (wmax + 1) / 2 * sizeof(double);
+        ev = mark_begin(num, st);
         hipLaunchKernelGGL(k_potrf, dim3(n1 - n0), dim3(256), lds_tri, st, P->level_sn + n0, a,
                            num->arena, num->status_dev);
+        mark_end(num, st, 1, ev);
         const int64_t rb0 = P->rowblk_ptr[l], rb1 = P->rowblk_ptr[l + 1];
-        if (rb1 > rb0)
+        if (rb1 > rb0) {
+            ev = mark_begin(num, st);
             hipLaunchKernelGGL(k_trsm, dim3((unsigned)(rb1 - rb0)), dim3(kTile),
                                (size_t)wmax * kTile * sizeof(double), st, P->rowblk + rb0, a,
                                num->arena);
+            mark_end(num, st, 2, ev);
+        }
         const int64_t t0 = P->tile_ptr[l], t1 = P->tile_ptr[l + 1];
-        if (t1 > t0)
+        if (t1 > t0) {
+            ev = mark_begin(num, st);
             hipLaunchKernelGGL(k_update, dim3((unsigned)(t1 - t0)), dim3(256), 0, st,
                                P->tiles + t0, a, num->arena);
+            mark_end(num, st, 3, ev);
+        }
     }
     HIP_TRY(hipGetLastError());
     num->factored = true;

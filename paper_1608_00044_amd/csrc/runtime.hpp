@@ -86,6 +86,12 @@ struct spc_numeric {
     hipStream_t stream = nullptr;
     int32_t host_status = 0;
     bool factored = false;
+    // optional per-launch event timing (class, start, stop)
+    bool timing = false;
+    std::vector<hipEvent_t> events;
+    struct Mark { int cls; int a, b; };
+    std::vector<Mark> marks;
+    size_t next_event = 0;
 };
 
 namespace spc {

@@ -12,7 +12,6 @@ from __future__ import annotations
 
 import ctypes as C
 import os
-from dataclasses import dataclass
 
 import numpy as np
 
@@ -34,7 +33,8 @@ SPC_ERR_BUSY = -8
 EXPORTS = ("spc_default_options", "spc_analyze", "spc_symbolic_info_get", "spc_symbolic_export",
            "spc_symbolic_export_rows", "spc_symbolic_export_pairs", "spc_symbolic_free",
            "spc_factor", "spc_refactor", "spc_numeric_status", "spc_solve", "spc_factor_export",
-           "spc_numeric_free", "spc_status_string")
+           "spc_numeric_free", "spc_status_string", "spc_numeric_set_timing",
+           "spc_numeric_get_timing")
 
 
 class spc_options(C.Structure):
@@ -48,6 +48,13 @@ class spc_symbolic_info(C.Structure):
                 ("npairs", C.c_int64), ("nrel", C.c_int64), ("factor_bytes", C.c_int64),
                 ("plan_bytes", C.c_int64), ("flops", C.c_double), ("flops_stored", C.c_double),
                 ("max_width", C.c_int32), ("max_below", C.c_int32)]
+
+
+class spc_kernel_times(C.Structure):
+    _fields_ = [("ms", C.c_double * 4), ("launches", C.c_int64 * 4), ("total_ms", C.c_double)]
+
+
+KERNEL_CLASSES = ("load", "potrf", "trsm", "update")
 
 
 class SpcError(RuntimeError):
@@ -90,6 +97,10 @@ def lib():
         L.spc_factor_export.restype = C.c_int32
         L.spc_numeric_free.argtypes = [vp]
         L.spc_numeric_free.restype = None
+        L.spc_numeric_set_timing.argtypes = [vp, C.c_int32]
+        L.spc_numeric_set_timing.restype = C.c_int32
+        L.spc_numeric_get_timing.argtypes = [vp, C.POINTER(spc_kernel_times)]
+        L.spc_numeric_get_timing.restype = C.c_int32
         L.spc_status_string.argtypes = [C.c_int32]
         L.spc_status_string.restype = C.c_char_p
         _lib = L
@@ -264,6 +275,21 @@ class Numeric:
             raise SpcError(st, "spc_solve")
         return X.reshape(n) if one else X
 
+    def set_timing(self, enable=True):
+        st = lib().spc_numeric_set_timing(self.handle, int(bool(enable)))
+        if st != SPC_OK:
+            raise SpcError(st, "spc_numeric_set_timing")
+
+    def timing(self) -> dict:
+        """Per-kernel-class device ms and launch counts of the last factorization."""
+        t = spc_kernel_times()
+        st = lib().spc_numeric_get_timing(self.handle, C.byref(t))
+        if st != SPC_OK:
+            raise SpcError(st, "spc_numeric_get_timing")
+        out = {c: dict(ms=t.ms[i], launches=t.launches[i]) for i, c in enumerate(KERNEL_CLASSES)}
+        out["total_ms"] = t.total_ms
+        return out
+
     def export(self):
         """Host copy (Sp, Si, Sx) of L in the stored supernodal column structure."""
         nnz = self.sym.info()["nnz_stored"]
@@ -320,9 +346,3 @@ def symbolic_free(sym: Symbolic) -> None:
 def numeric_free(num: Numeric) -> None:
     num.free()
 
-
-@dataclass
-class StoredFactor:
-    Sp: np.ndarray
-    Si: np.ndarray
-    Sx: np.ndarray
