@@ -85,7 +85,7 @@ spc_status spc_symbolic_info_get(const spc_symbolic* sym, spc_symbolic_info* inf
     info->nlevels = (int64_t)S.level_ptr.size() - 1;
     info->npairs = (int64_t)S.pairs.size();
     info->nrel = (int64_t)S.rel.size();
-    info->factor_bytes = (int64_t)(S.arena * sizeof(double)) + 256;
+    info->factor_bytes = (int64_t)((S.arena + inverse_blocks_elems(S)) * sizeof(double)) + 256;
     info->plan_bytes = (int64_t)sym->plan_bytes_estimate;
     info->flops = S.flops;
     info->flops_stored = S.flops_stored;
@@ -142,7 +142,7 @@ static spc_status alloc_numeric(spc_symbolic* sym, spc_numeric** out) {
     int32_t st = configure_kernels();
     if (st != OK) return st;
     const Symbolic& S = sym->S;
-    const int64_t need = (int64_t)(S.arena * sizeof(double)) + 256;
+    const int64_t need = (int64_t)((S.arena + inverse_blocks_elems(S)) * sizeof(double)) + 256;
     if (sym->budget > 0 && need + (int64_t)sym->plan_bytes_estimate > sym->budget)
         return SPC_ERR_OOM;
     DevicePlan* plan = nullptr;
@@ -160,6 +160,13 @@ static spc_status alloc_numeric(spc_symbolic* sym, spc_numeric** out) {
     }
     if (hipMalloc(&num->status_dev, 256) != hipSuccess) {
         (void)hipFree(num->arena);
+        delete num;
+        return SPC_ERR_OOM;
+    }
+    if (hipMalloc(&num->dinv, sizeof(double) * (size_t)(plan->inv_elems > 0 ? plan->inv_elems : 1)) !=
+        hipSuccess) {
+        (void)hipFree(num->arena);
+        (void)hipFree(num->status_dev);
         delete num;
         return SPC_ERR_OOM;
     }
@@ -207,6 +214,7 @@ spc_status spc_numeric_status(spc_numeric* num) {
     if (hipMemcpy(&v, num->status_dev, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
         return SPC_ERR_HIP;
     num->host_status = (v == INT32_MAX) ? 0 : v;
+    num->status_known = true;
     return num->host_status;
 }
 
@@ -219,7 +227,7 @@ spc_status spc_solve(spc_numeric* num, int32_t nrhs, const double* b_dev, int64_
     int cur = 0;
     if (hipGetDevice(&cur) != hipSuccess) return SPC_ERR_HIP;
     if (cur != num->device) return SPC_ERR_ARG;
-    spc_status st = spc_numeric_status(num);
+    spc_status st = num->status_known ? num->host_status : spc_numeric_status(num);
     if (st != SPC_OK) return st;
     return run_solve(num, nrhs, b_dev, ldb, x_dev, ldx, (hipStream_t)stream);
 }
@@ -298,6 +306,7 @@ void spc_numeric_free(spc_numeric* num) {
     else (void)hipDeviceSynchronize();
     (void)hipFree(num->arena);
     (void)hipFree(num->status_dev);
+    (void)hipFree(num->dinv);
     if (num->work) (void)hipFree(num->work);
     for (hipEvent_t e : num->events) (void)hipEventDestroy(e);
     (void)hipSetDevice(cur);

@@ -3,14 +3,15 @@
 //
 // Tasks (Section III-A of arXiv:1608.00044), per supernode s of width w with
 // r rows below its diagonal block, stored as a column-major (w + r) x w block:
-//   F  (k_potrf, k_trsm):  L11 = chol(A11) in LDS, then L21 = A21 L11^{-T}
-//                          row by row;
+//   F  (k_potrf, k_trsm):  L11 = chol(A11), blocked by 16-column panels in
+//                          LDS, then L21 = A21 L11^{-T} on matrix cores using
+//                          the inverses of the 16 x 16 diagonal blocks;
 //   U  (k_update):         the lower triangle of L21 L21^T in 64 x 64 tiles on
 //                          FP64 matrix cores (v_mfma_f64_16x16x4);
 //   A  (k_update epilogue): each tile entry is subtracted from the target
 //                          supernode that owns its column, at the row given by
-//                          the precomputed relative index (an atomic add, since
-//                          sibling supernodes of one level may hit the same target).
+//                          the precomputed relative index (an atomic add when
+//                          sibling supernodes of one level share the target).
 // Dependencies (Section II-C) are met by running the supernodal elimination
 // tree level by level: every supernode of level l only receives updates from
 // descendants, which all sit on lower levels.
@@ -18,6 +19,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cmath>
 #include <cstring>
 
 #include "runtime.hpp"
@@ -30,207 +32,6 @@ typedef double v4d __attribute__((ext_vector_type(4)));
     do {                                         \
         if ((x) != hipSuccess) return ERR_HIP;   \
     } while (0)
-
-// ---------------------------------------------------------------------------
-// plan upload
-// ---------------------------------------------------------------------------
-
-namespace {
-
-struct Layout {
-    size_t total = 0;
-    template <class T>
-    size_t add(size_t count) {
-        size_t at = (total + 255) & ~size_t(255);
-        total = at + count * sizeof(T);
-        return at;
-    }
-};
-
-struct PlanOffsets {
-    size_t sn_first, sn_w, sn_ld, sn_off, rowptr, rows, rowpair, slot, perm, pair_tgt, pair_seg,
-        pair_rel, rel, level_sn, rowblk, tiles;
-    size_t total;
-};
-
-void count_work(const Symbolic& S, std::vector<int64_t>& rb_ptr, std::vector<int64_t>& tl_ptr) {
-    const int32_t nl = (int32_t)S.level_ptr.size() - 1;
-    rb_ptr.assign((size_t)nl + 1, 0);
-    tl_ptr.assign((size_t)nl + 1, 0);
-    for (int32_t l = 0; l < nl; ++l) {
-        int64_t rb = 0, tl = 0;
-        for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
-            const int64_t r = S.nbelow(S.level_sn[q]);
-            const int64_t nb = (r + kTile - 1) / kTile;
-            rb += nb;
-            tl += nb * (nb + 1) / 2;
-        }
-        rb_ptr[l + 1] = rb_ptr[l] + rb;
-        tl_ptr[l + 1] = tl_ptr[l] + tl;
-    }
-}
-
-PlanOffsets plan_layout(const Symbolic& S, const std::vector<int64_t>& rb_ptr,
-                        const std::vector<int64_t>& tl_ptr) {
-    Layout L;
-    PlanOffsets o;
-    const size_t ns = (size_t)S.nsup;
-    o.sn_first = L.add<int32_t>(ns);
-    o.sn_w = L.add<int32_t>(ns);
-    o.sn_ld = L.add<int32_t>(ns);
-    o.sn_off = L.add<int64_t>(ns);
-    o.rowptr = L.add<int64_t>(ns + 1);
-    o.rows = L.add<int32_t>(S.rows.size());
-    o.rowpair = L.add<int32_t>(S.rows.size());
-    o.slot = L.add<int64_t>(S.slot.size());
-    o.perm = L.add<int32_t>(S.perm.size());
-    o.pair_tgt = L.add<int32_t>(S.pairs.size());
-    o.pair_seg = L.add<int32_t>(S.pairs.size());
-    o.pair_rel = L.add<int64_t>(S.pairs.size());
-    o.rel = L.add<int32_t>(S.rel.size());
-    o.level_sn = L.add<int32_t>(S.level_sn.size());
-    o.rowblk = L.add<RowBlock>((size_t)rb_ptr.back());
-    o.tiles = L.add<UpdTile>((size_t)tl_ptr.back());
-    o.total = L.total;
-    return o;
-}
-
-}  // namespace
-
-size_t plan_bytes(const Symbolic& S) {
-    std::vector<int64_t> a, b;
-    count_work(S, a, b);
-    return plan_layout(S, a, b).total;
-}
-
-int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
-    int dev = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    std::lock_guard<std::mutex> lock(sym->mu);
-    for (DevicePlan* p : sym->plans)
-        if (p->device == dev) { *out = p; return OK; }
-    const Symbolic& S = sym->S;
-    if (S.max_r >= 32767 * kTile) return ERR_ARG;  // tile coordinates are 16-bit
-    DevicePlan* P = new DevicePlan();
-    P->device = dev;
-    count_work(S, P->rowblk_ptr, P->tile_ptr);
-    PlanOffsets o = plan_layout(S, P->rowblk_ptr, P->tile_ptr);
-    std::vector<char> h(o.total ? o.total : 1, 0);
-    auto put = [&](size_t at, const void* src, size_t bytes) {
-        if (bytes) std::memcpy(h.data() + at, src, bytes);
-    };
-    const size_t ns = (size_t)S.nsup;
-    std::vector<int32_t> w(ns), first(ns);
-    for (size_t s = 0; s < ns; ++s) { first[s] = S.sn_ptr[s]; w[s] = S.width((int64_t)s); }
-    put(o.sn_first, first.data(), ns * 4);
-    put(o.sn_w, w.data(), ns * 4);
-    put(o.sn_ld, S.ld.data(), ns * 4);
-    put(o.sn_off, S.off.data(), ns * 8);
-    put(o.rowptr, S.rowptr.data(), (ns + 1) * 8);
-    put(o.rows, S.rows.data(), S.rows.size() * 4);
-    {
-        std::vector<int32_t> rp(S.rows.size(), -1);
-        for (size_t p = 0; p < S.pairs.size(); ++p) {
-            const Pair& pr = S.pairs[p];
-            const int64_t base = S.rowptr[pr.src] + S.width(pr.src);
-            for (int32_t i = pr.seg_begin; i < pr.seg_end; ++i) rp[base + i] = (int32_t)p;
-        }
-        put(o.rowpair, rp.data(), rp.size() * 4);
-    }
-    put(o.slot, S.slot.data(), S.slot.size() * 8);
-    put(o.perm, S.perm.data(), S.perm.size() * 4);
-    {
-        const size_t np = S.pairs.size();
-        std::vector<int32_t> tg(np), sg(np);
-        std::vector<int64_t> ro(np);
-        for (size_t p = 0; p < np; ++p) {
-            tg[p] = S.pairs[p].tgt;
-            sg[p] = S.pairs[p].seg_begin;
-            ro[p] = S.pairs[p].rel_off;
-        }
-        put(o.pair_tgt, tg.data(), np * 4);
-        put(o.pair_seg, sg.data(), np * 4);
-        put(o.pair_rel, ro.data(), np * 8);
-    }
-    put(o.rel, S.rel.data(), S.rel.size() * 4);
-    put(o.level_sn, S.level_sn.data(), S.level_sn.size() * 4);
-    {
-        const int32_t nl = (int32_t)S.level_ptr.size() - 1;
-        std::vector<RowBlock> rb((size_t)P->rowblk_ptr.back());
-        std::vector<UpdTile> tl((size_t)P->tile_ptr.back());
-        P->level_maxw.assign((size_t)nl, 0);
-        size_t a = 0, b = 0;
-        for (int32_t l = 0; l < nl; ++l) {
-            for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
-                const int32_t s = S.level_sn[q];
-                P->level_maxw[l] = std::max(P->level_maxw[l], S.width(s));
-                const int32_t nb = (S.nbelow(s) + kTile - 1) / kTile;  // < 32768 (checked)
-                for (int32_t i = 0; i < nb; ++i) rb[a++] = RowBlock{s, i};
-                for (int32_t i = 0; i < nb; ++i)
-                    for (int32_t j = 0; j <= i; ++j) tl[b++] = UpdTile{s, (int16_t)i, (int16_t)j};
-            }
-        }
-        put(o.rowblk, rb.data(), rb.size() * sizeof(RowBlock));
-        put(o.tiles, tl.data(), tl.size() * sizeof(UpdTile));
-    }
-    void* d = nullptr;
-    if (hipMalloc(&d, o.total ? o.total : 256) != hipSuccess) { delete P; return ERR_OOM; }
-    if (hipMemcpy(d, h.data(), o.total, hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(d);
-        delete P;
-        return ERR_HIP;
-    }
-    char* base = (char*)d;
-    P->block = d;
-    P->bytes = o.total;
-    P->sn_first = (int32_t*)(base + o.sn_first);
-    P->sn_w = (int32_t*)(base + o.sn_w);
-    P->sn_ld = (int32_t*)(base + o.sn_ld);
-    P->sn_off = (int64_t*)(base + o.sn_off);
-    P->rowptr = (int64_t*)(base + o.rowptr);
-    P->rows = (int32_t*)(base + o.rows);
-    P->rowpair = (int32_t*)(base + o.rowpair);
-    P->slot = (int64_t*)(base + o.slot);
-    P->perm = (int32_t*)(base + o.perm);
-    P->pair_tgt = (int32_t*)(base + o.pair_tgt);
-    P->pair_seg = (int32_t*)(base + o.pair_seg);
-    P->pair_rel = (int64_t*)(base + o.pair_rel);
-    P->rel = (int32_t*)(base + o.rel);
-    P->level_sn = (int32_t*)(base + o.level_sn);
-    P->rowblk = (RowBlock*)(base + o.rowblk);
-    P->tiles = (UpdTile*)(base + o.tiles);
-    sym->plans.push_back(P);
-    *out = P;
-    return OK;
-}
-
-void free_plan(DevicePlan* p) {
-    if (!p) return;
-    if (p->block) {
-        int cur = 0;
-        (void)hipGetDevice(&cur);
-        (void)hipSetDevice(p->device);
-        (void)hipFree(p->block);
-        (void)hipSetDevice(cur);
-    }
-    delete p;
-}
-
-static KArgs kargs(const DevicePlan* P) {
-    KArgs a;
-    a.sn_first = P->sn_first;
-    a.sn_w = P->sn_w;
-    a.sn_ld = P->sn_ld;
-    a.sn_off = P->sn_off;
-    a.rowptr = P->rowptr;
-    a.rows = P->rows;
-    a.rowpair = P->rowpair;
-    a.pair_tgt = P->pair_tgt;
-    a.pair_seg = P->pair_seg;
-    a.pair_rel = P->pair_rel;
-    a.rel = P->rel;
-    return a;
-}
 
 // ---------------------------------------------------------------------------
 // value load
@@ -258,108 +59,393 @@ __global__ void k_load(const double* __restrict__ values, const int64_t* __restr
 }
 
 // ---------------------------------------------------------------------------
-// F: diagonal block factorization (POTRF)
+// F: diagonal block factorization (blocked POTRF)
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ int tri_idx(int i, int j, int w) {
-    // packed lower triangle, column major: column j starts after sum_{c<j} (w - c)
-    return j * w - (j * (j - 1)) / 2 + (i - j);
+// Value of a double held by one lane of the wave (the lane index must be
+// wave-uniform): two v_readlane_b32, no LDS round trip.
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// One workgroup per supernode of the level.  The w x w diagonal block is held
-// as a packed lower triangle in LDS and factored right-looking: pivot, scale
-// the column, rank-1 update of the trailing triangle (Algorithm 1 on the
-// block).  A pivot that is not positive records its global column with
-// atomicMin on *status (the smallest failing column wins).
-__global__ __launch_bounds__(256) void k_potrf(const int32_t* __restrict__ level_sn, KArgs a,
-                                               double* __restrict__ arena,
-                                               int32_t* __restrict__ status) {
+constexpr int kPotrfThreads = 256;
+constexpr int kDs = kPanel + 1;  // padded row stride of the dense 16 x 16 panel block
+
+// 1/sqrt(d) from the hardware estimate refined by two Newton steps, and sqrt(d)
+// as d/sqrt(d); within a few units in the last place of the rounded values.
+__device__ __forceinline__ void rsqrt_sqrt(double d, double& rs, double& sq) {
+    double y = __builtin_amdgcn_rsq(d);
+    y = y * (1.5 - 0.5 * d * y * y);
+    y = y * (1.5 - 0.5 * d * y * y);
+    rs = y;
+    sq = d * y;
+}
+
+// Wave-level factorization of the 16 x 16 diagonal block of panel q (columns
+// j0 .. j0 + jb - 1): copy it from the packed triangle T into the dense tile
+// Dt (identity past its edge), factor it in registers (lane i holds row i;
+// the pivot comes by v_readlane, each finished column goes back to the tile
+// and is read by every lane), form inv(D) by forward substitution (one column
+// per lane), and write L back to T and inv(D) to Dinv and dinv.
+template <class Cst>
+__device__ __forceinline__ void panel_factor(double* __restrict__ T, double* __restrict__ Dt,
+                                             double* __restrict__ Dinv,
+                                             double* __restrict__ inv_g, Cst cst, int dummy,
+                                             int j0, int jb, int q, int lane, int first,
+                                             int32_t* __restrict__ status) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int idx = lane + 64 * m, i = idx >> 4, j = idx & 15;
+        const bool in = i < jb && j <= i;
+        const double v = T[in ? cst(j0 + j) + j0 + i : dummy];
+        Dt[i * kDs + j] = in ? v : (i == j ? 1.0 : 0.0);
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int i = lane & 15;  // lanes 16..63 mirror lanes 0..15
+    double d[kPanel], rd[kPanel];
+#pragma unroll
+    for (int j = 0; j < kPanel; ++j) d[j] = Dt[i * kDs + j];
+#pragma unroll
+    for (int k = 0; k < kPanel; ++k) {
+        const double dkk = lane_value(d[k], k);
+        if (k < jb && !(dkk > 0.0) && lane == 0) atomicMin(status, first + j0 + k + 1);
+        double rinv, lkk;
+        rsqrt_sqrt(dkk, rinv, lkk);
+        rd[k] = rinv;
+        d[k] = (i == k) ? lkk : d[k] * rinv;
+        Dt[i * kDs + k] = d[k];  // column k of L, read back by every lane
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int j = k + 1; j < kPanel; ++j) {
+            const double ljk = Dt[j * kDs + k];
+            d[j] -= ((i >= j) ? d[k] : 0.0) * ljk;
+        }
+    }
+    double x[kPanel];
+#pragma unroll
+    for (int rr = 0; rr < kPanel; ++rr) {
+        double acc = (rr == i) ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = 0; k < rr; ++k) acc -= Dt[rr * kDs + k] * x[k];
+        x[rr] = acc * rd[rr];
+    }
+    if (lane < kPanel) {
+#pragma unroll
+        for (int rr = 0; rr < kPanel; ++rr) {
+            const double v = (i < jb && rr < jb) ? x[rr] : 0.0;
+            Dinv[rr * kPanel + i] = v;
+            inv_g[q * kPanel * kPanel + rr * kPanel + i] = v;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int idx = lane + 64 * m, ii = idx >> 4, j = idx & 15;
+        const bool in = ii < jb && j <= ii;
+        T[in ? cst(j0 + j) + j0 + ii : dummy] = Dt[ii * kDs + j];
+    }
+}
+
+// Trailing-update block b of panel p (blocks numbered row by row over the
+// lower triangle of the trailing part, 16 x 16 each, K = 16 on the matrix
+// cores), in place in the packed triangle.
+template <class Cst>
+__device__ __forceinline__ void trailing_block(double* __restrict__ T, Cst cst, int dummy, int w,
+                                               int j0, int t0, int b, int lr, int lk) {
+    int bi = (int)((sqrtf(8.0f * b + 1.0f) - 1.0f) * 0.5f);
+    bi -= (bi * (bi + 1) / 2 > b);
+    bi += ((bi + 1) * (bi + 2) / 2 <= b);
+    const int bj = b - bi * (bi + 1) / 2;
+    const int row0 = t0 + bi * kPanel, col0 = t0 + bj * kPanel;
+    const int ra = row0 + lr, rb = col0 + lr;
+    const bool oka = ra < w, okb = rb < w;
+    double cv[4], av[4], bv[4];
+    int ci[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int rr = row0 + 4 * q + lk, cc = col0 + lr;
+        const bool ok = rr < w && cc < w && rr >= cc;
+        ci[q] = ok ? cst(cc) + rr : dummy;
+        cv[q] = T[ci[q]];
+    }
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+        const int k = j0 + 4 * kk + lk;
+        const double ta = T[oka ? cst(k) + ra : dummy];
+        const double tb = T[okb ? cst(k) + rb : dummy];
+        av[kk] = oka ? -ta : 0.0;
+        bv[kk] = okb ? tb : 0.0;
+    }
+    v4d acc = v4d{cv[0], cv[1], cv[2], cv[3]};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kk], bv[kk], acc, 0, 0, 0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) T[ci[q]] = acc[q];
+}
+
+// One workgroup (4 waves) per supernode of the level.  The w x w diagonal
+// block lives in LDS as a packed lower triangle, column major: entry (i, j)
+// at cst(j) + i, plus one dummy slot that absorbs masked accesses so the
+// inner loops stay branch free.  Right-looking by 16-column panels with a
+// one-panel lookahead:
+//   1. wave 0 factors the panel's 16 x 16 diagonal block and inverts it
+//      (panel_factor); the inverse also goes to dinv for the panel and
+//      triangular solves;
+//   2. the rows below the panel inside the diagonal block are multiplied by
+//      inv(D)^T on v_mfma_f64_16x16x4, one 16-row block per wave;
+//   3. the trailing lower triangle is updated in 16 x 16 blocks; wave 0
+//      updates the next panel's diagonal block first and factors it while
+//      waves 1-3 update the rest.
+// Global loads and stores of the block are issued many per thread at a time.
+// A pivot that is not positive records its global column with atomicMin on
+// *status; the smallest failing column wins.
+__global__ __launch_bounds__(kPotrfThreads) void k_potrf(const int32_t* __restrict__ level_sn,
+                                                         KArgs a, double* __restrict__ arena,
+                                                         double* __restrict__ dinv,
+                                                         int32_t* __restrict__ status) {
     extern __shared__ double T[];
-    __shared__ double piv;
+    __shared__ double Dinv[kPanel * kPanel];  // row major: Dinv[r * 16 + c] = inv(D)[r][c]
+    __shared__ double Dt[kPanel * kDs];       // dense panel block, row major
     const int s = level_sn[blockIdx.x];
     const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
     double* __restrict__ base = arena + a.sn_off[s];
-    const int tid = threadIdx.x;
-    for (int e = tid; e < w * w; e += blockDim.x) {
-        const int i = e % w, j = e / w;
-        if (i >= j) T[tri_idx(i, j, w)] = base[i + (int64_t)j * ld];
+    double* __restrict__ inv_g = dinv + a.inv_off[s];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    constexpr int nwave = kPotrfThreads / 64;
+    // packed column start: entry (i, j) of the lower triangle sits at cst(j) + i
+    auto cst = [w](int j) { return (j * (2 * w - j - 1)) >> 1; };
+    const int dummy = w * (w + 1) / 2;  // masked accesses land here
+    const int ww = w * w;
+    for (int e0 = tid; e0 < ww; e0 += 16 * kPotrfThreads) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = e0 + u * kPotrfThreads, i = e % w, j = e / w;
+            const bool ok = e < ww && i >= j;
+            v[u] = base[ok ? i + (int64_t)j * ld : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = e0 + u * kPotrfThreads, i = e % w, j = e / w;
+            const bool ok = e < ww && i >= j;
+            T[ok ? cst(j) + i : dummy] = v[u];
+        }
     }
     __syncthreads();
-    for (int k = 0; k < w; ++k) {
-        if (tid == 0) {
-            double d = T[tri_idx(k, k, w)];
-            if (!(d > 0.0)) atomicMin(status, first + k + 1);
-            double p = sqrt(d);
-            T[tri_idx(k, k, w)] = p;
-            piv = p;
-        }
-        __syncthreads();
-        const double inv = 1.0 / piv;
-        for (int i = k + 1 + tid; i < w; i += blockDim.x) T[tri_idx(i, k, w)] *= inv;
-        __syncthreads();
-        const int m = w - k - 1;
-        for (int e = tid; e < m * m; e += blockDim.x) {
-            const int ii = e % m, jj = e / m;
-            if (ii >= jj) {
-                const int i = k + 1 + ii, j = k + 1 + jj;
-                T[tri_idx(i, j, w)] -= T[tri_idx(i, k, w)] * T[tri_idx(j, k, w)];
+    const int npanel = (w + kPanel - 1) / kPanel;
+    if (wave == 0) panel_factor(T, Dt, Dinv, inv_g, cst, dummy, 0, min(kPanel, w), 0, lane, first, status);
+    __syncthreads();
+    for (int p = 0; p < npanel; ++p) {
+        const int j0 = p * kPanel;
+        const int jb = min(kPanel, w - j0);
+        // rows below the panel inside the diagonal block: X = A inv(D)^T
+        const int t0 = j0 + kPanel;
+        const int nrow = w - j0 - jb;  // > 0 only when the panel is full
+        const int nrb = (nrow + kPanel - 1) / kPanel;
+        for (int rb = wave; rb < nrb; rb += nwave) {
+            const int row0 = t0 + rb * kPanel;
+            const bool okr = row0 + lr < w;
+            double av[4], bv[4];
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const double t = T[okr ? cst(j0 + 4 * kk + lk) + row0 + lr : dummy];
+                av[kk] = okr ? t : 0.0;
+                bv[kk] = Dinv[lr * kPanel + 4 * kk + lk];
+            }
+            v4d out = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+                out = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kk], bv[kk], out, 0, 0, 0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int rr = row0 + 4 * q + lk;
+                T[rr < w ? cst(j0 + lr) + rr : dummy] = out[q];
             }
         }
         __syncthreads();
+        if (nrow <= 0) break;
+        // trailing update with lookahead on the next panel's diagonal block
+        const int nbr = (w - t0 + kPanel - 1) / kPanel;
+        const int nblk = nbr * (nbr + 1) / 2;
+        if (wave == 0) {
+            trailing_block(T, cst, dummy, w, j0, t0, 0, lr, lk);
+            __builtin_amdgcn_wave_barrier();
+            panel_factor(T, Dt, Dinv, inv_g, cst, dummy, t0, min(kPanel, w - t0), p + 1, lane,
+                         first, status);
+        } else {
+            for (int b = wave; b < nblk; b += nwave - 1)
+                trailing_block(T, cst, dummy, w, j0, t0, b, lr, lk);
+        }
+        __syncthreads();
     }
-    for (int e = tid; e < w * w; e += blockDim.x) {
-        const int i = e % w, j = e / w;
-        if (i >= j) base[i + (int64_t)j * ld] = T[tri_idx(i, j, w)];
+    for (int e0 = tid; e0 < ww; e0 += 8 * kPotrfThreads) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * kPotrfThreads, i = e % w, j = e / w;
+            if (e < ww && i >= j) base[i + (int64_t)j * ld] = T[cst(j) + i];
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
-// F: panel solve (TRSM) L21 = A21 L11^{-T}
+// F: panel solve L21 = A21 L11^{-T}
 // ---------------------------------------------------------------------------
 
-// One 64-thread workgroup per 64-row block of a panel; each lane solves one
-// row x L11^T = a by forward substitution, with its row staged in LDS.
-__global__ __launch_bounds__(64) void k_trsm(const RowBlock* __restrict__ work, KArgs a,
-                                             double* __restrict__ arena) {
-    extern __shared__ double X[];  // [w][64]
+// One workgroup of 2 waves per 64-row block of a panel.  The whole diagonal
+// block L11 (packed lower triangle) and its 16 x 16 diagonal-block inverses
+// are staged in LDS once; then each wave takes 16 rows at a time (two passes
+// cover the 64 rows), staged as X[k * 16 + row], and runs the blocked forward
+// substitution by 16-column panels on v_mfma_f64_16x16x4 with no workgroup
+// barrier:
+//   B  = X[:, p] - X[:, <p] L[p, <p]^T      (K = 16 p)
+//   X[:, p] = B inv(D_p)^T                  (K = 16, inverse from k_potrf)
+constexpr int kTrsmThreads = 128;
+
+__global__ __launch_bounds__(kTrsmThreads) void k_trsm(const RowBlock* __restrict__ work, KArgs a,
+                                                       double* __restrict__ arena,
+                                                       const double* __restrict__ dinv) {
+    extern __shared__ double sm[];
     const RowBlock wb = work[blockIdx.x];
     const int s = wb.s;
     const int w = a.sn_w[s], ld = a.sn_ld[s];
     const int r = (int)(a.rowptr[s + 1] - a.rowptr[s]) - w;
     const double* __restrict__ L = arena + a.sn_off[s];
     double* __restrict__ P = arena + a.sn_off[s] + w;
-    const int t = threadIdx.x;
-    const int row = wb.rb * kTile + t;
-    const bool ok = row < r;
-    for (int k = 0; k < w; ++k) X[k * kTile + t] = ok ? P[row + (int64_t)k * ld] : 0.0;
-    for (int j = 0; j < w; ++j) {
-        double acc = X[j * kTile + t];
-        const double* __restrict__ Lj = L + j;
-        for (int k = 0; k < j; ++k) acc -= X[k * kTile + t] * Lj[(int64_t)k * ld];
-        X[j * kTile + t] = acc / Lj[(int64_t)j * ld];
+    const double* __restrict__ inv = dinv + a.inv_off[s];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int npanel = (w + kPanel - 1) / kPanel;
+    const int w16 = npanel * kPanel;
+    auto cst = [w](int j) { return (j * (2 * w - j - 1)) >> 1; };
+    double* __restrict__ T = sm;                                  // L11, packed
+    double* __restrict__ I = T + w * (w + 1) / 2;                 // inverses
+    double* __restrict__ X = I + npanel * kPanel * kPanel + (size_t)wave * 16 * w16;
+    {
+        const int ww = w * w;
+        for (int e0 = tid; e0 < ww; e0 += 16 * kTrsmThreads) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int e = e0 + u * kTrsmThreads, i = e % w, j = e / w;
+                const bool ok = e < ww && i >= j;
+                v[u] = L[ok ? i + (int64_t)j * ld : 0];
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int e = e0 + u * kTrsmThreads, i = e % w, j = e / w;
+                if (e < ww && i >= j) T[cst(j) + i] = v[u];
+            }
+        }
+        const int ni = npanel * kPanel * kPanel;
+        for (int e0 = tid; e0 < ni; e0 += 8 * kTrsmThreads) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = inv[min(e0 + u * kTrsmThreads, ni - 1)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (e0 + u * kTrsmThreads < ni) I[e0 + u * kTrsmThreads] = v[u];
+        }
     }
-    if (ok)
-        for (int k = 0; k < w; ++k) P[row + (int64_t)k * ld] = X[k * kTile + t];
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+        const int row0 = wb.rb * kTile + pass * 32 + wave * 16;
+        if (row0 >= r) break;
+        for (int e0 = lane; e0 < 16 * w16; e0 += 16 * 64) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int e = e0 + 64 * u, rr = e & 15, k = e >> 4;
+                const bool ok = e < 16 * w16 && k < w && row0 + rr < r;
+                v[u] = P[ok ? row0 + rr + (int64_t)k * ld : 0];
+                v[u] = ok ? v[u] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                if (e0 + 64 * u < 16 * w16) X[e0 + 64 * u] = v[u];
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int p = 0; p < npanel; ++p) {
+            const int j0 = p * kPanel;
+            const int col = j0 + lr;
+            const bool okc = col < w;
+            v4d acc;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = X[col * 16 + 4 * q + lk];
+            for (int k0 = 0; k0 < j0; k0 += 4) {
+                const double av = -X[(k0 + lk) * 16 + lr];
+                const double t = T[okc ? cst(k0 + lk) + col : 0];
+                const double bv = okc ? t : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) X[col * 16 + 4 * q + lk] = acc[q];
+            __builtin_amdgcn_wave_barrier();
+            double av[4], bv[4];
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                av[kk] = X[(j0 + 4 * kk + lk) * 16 + lr];
+                bv[kk] = I[p * kPanel * kPanel + lr * kPanel + 4 * kk + lk];
+            }
+            v4d out = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+                out = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kk], bv[kk], out, 0, 0, 0);
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int q = 0; q < 4; ++q) X[col * 16 + 4 * q + lk] = out[q];
+            __builtin_amdgcn_wave_barrier();
+        }
+        for (int e = lane; e < 16 * w16; e += 64) {
+            const int rr = e & 15, k = e >> 4;
+            if (k < w && row0 + rr < r) P[row0 + rr + (int64_t)k * ld] = X[e];
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
 }
 
 // ---------------------------------------------------------------------------
 // U + A: update tiles on FP64 MFMA with relative-index scatter
 // ---------------------------------------------------------------------------
 
+constexpr int kChunk = 16;             // K columns staged per step
+constexpr int kLdsStride = kTile + 2;  // padded row count of a staged K column
 constexpr int kCtPad = kTile + 1;
 
+// XCD-aware tile order: consecutive dispatches go round-robin over the 8
+// XCDs, so block b runs on XCD b % 8.  Give each XCD a contiguous range of
+// tiles (the tiles of one source share its panel in that XCD's L2).
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
+    const int64_t q = nb >> 3, rem = nb & 7;
+    const int64_t x = b & 7, j = b >> 3;
+    return x * q + (x < rem ? x : rem) + j;
+}
+
 // 256 threads = 4 waves in a 2 x 2 grid, each wave a 32 x 32 quarter of the
-// 64 x 64 tile as 2 x 2 blocks of v_mfma_f64_16x16x4.  Operand lanes: lane l
-// holds element (row l % 16, k l / 16) of each 16 x 4 slice; the A and B
-// operands are both rows of the same column-major panel.  The result goes to
-// LDS, then every entry (i, c), i >= c, is subtracted from the target that
-// owns the column's row: target block + rel[i] + (row(c) - first(t)) * ld(t).
-__global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tiles, KArgs a,
+// 64 x 64 tile as 2 x 2 blocks of v_mfma_f64_16x16x4.  The K dimension (the
+// source width w) goes through LDS in chunks of 16 columns, double buffered:
+// the next chunk is loaded into registers while the current one feeds the
+// matrix cores.  Operand lanes: lane l holds element (row l % 16, k l / 16) of
+// each 16 x 4 slice; A and B are both rows of the same column-major panel
+// (a diagonal tile stages them once).  The result goes to LDS, then every
+// entry (i, c), i >= c, is subtracted from the target that owns the column's
+// row: target block + rel[i] + (row(c) - first(t)) * ld(t), with a plain
+// read-modify-write when the pair's target has no other source in this
+// level and an atomic add otherwise.
+__global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tiles, int64_t ntiles,
+                                                KArgs a, const uint8_t* __restrict__ pair_excl,
                                                 double* __restrict__ arena) {
-    __shared__ double Ct[kTile * kCtPad];  // column-major: Ct[c * kCtPad + i]
+    __shared__ double lds[2 * 2 * kChunk * kLdsStride > kTile * kCtPad
+                              ? 2 * 2 * kChunk * kLdsStride
+                              : kTile * kCtPad];
     __shared__ int64_t colbase[kTile];
     __shared__ int64_t relbase[kTile];
-    const UpdTile tile = tiles[blockIdx.x];
+    __shared__ int colexcl[kTile];
+    const UpdTile tile = tiles[xcd_tile(blockIdx.x, ntiles)];
     const int s = tile.s;
     const int w = a.sn_w[s], ld = a.sn_ld[s];
     const int64_t rp = a.rowptr[s];
@@ -371,29 +457,73 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
     const int lr = lane & 15, lk = lane >> 4;
     const bool diag = tile.bi == tile.bj;
     const bool skip = diag && wr < wc;  // strictly upper quarter of a diagonal tile
-
+    // staging: thread -> row (tid & 63), columns kq*4 .. kq*4+3 of the chunk
+    const int srow = tid & 63, kq = tid >> 6;
+    const bool va = i0 + srow < r, vb = c0 + srow < r;
+    double* As = lds;                               // [buf][k][row]
+    double* Bs = lds + 2 * kChunk * kLdsStride;     // [buf][k][row]
+    const int nchunk = (w + kChunk - 1) / kChunk;
+    double ra[4], rb[4];
+    auto fetch = [&](int chunk) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = chunk * kChunk + kq * 4 + u;
+            const bool vk = k < w;
+            const double* __restrict__ col = P + (int64_t)k * ld;
+            ra[u] = (vk && va) ? col[i0 + srow] : 0.0;
+            rb[u] = (!diag && vk && vb) ? col[c0 + srow] : 0.0;
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            As[(buf * kChunk + kq * 4 + u) * kLdsStride + srow] = ra[u];
+            if (!diag) Bs[(buf * kChunk + kq * 4 + u) * kLdsStride + srow] = rb[u];
+        }
+    };
+    // column -> target lookups first, so their latency hides under the K loop
+    int64_t my_colbase = 0, my_relbase = 0;
+    int my_excl = 0;
+    if (tid < kTile) {
+        const int gc = c0 + tid;
+        if (gc < r) {
+            const int64_t at = rp + w + gc;
+            const int p = a.rowpair[at];
+            const int t = a.pair_tgt[p];
+            my_colbase = a.sn_off[t] + (int64_t)(a.rows[at] - a.sn_first[t]) * a.sn_ld[t];
+            my_relbase = a.pair_rel[p] - a.pair_seg[p];
+            my_excl = pair_excl[p];
+        }
+    }
     v4d acc[2][2];
     for (int m = 0; m < 2; ++m)
         for (int n = 0; n < 2; ++n) acc[m][n] = v4d{0.0, 0.0, 0.0, 0.0};
-    if (!skip) {
-        const int ra0 = i0 + wr * 32 + lr, ra1 = ra0 + 16;
-        const int rb0 = c0 + wc * 32 + lr, rb1 = rb0 + 16;
-        const bool va0 = ra0 < r, va1 = ra1 < r, vb0 = rb0 < r, vb1 = rb1 < r;
-        for (int k0 = 0; k0 < w; k0 += 4) {
-            const int k = k0 + lk;
-            const bool vk = k < w;
-            const double* __restrict__ col = P + (int64_t)k * ld;
-            const double a0 = (vk && va0) ? col[ra0] : 0.0;
-            const double a1 = (vk && va1) ? col[ra1] : 0.0;
-            const double b0 = (vk && vb0) ? col[rb0] : 0.0;
-            const double b1 = (vk && vb1) ? col[rb1] : 0.0;
-            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    const double* Bsrc = diag ? As : Bs;
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < nchunk) fetch(ch + 1);
+        if (!skip) {
+#pragma unroll
+            for (int kk = 0; kk < kChunk / 4; ++kk) {
+                const int krow = (buf * kChunk + kk * 4 + lk) * kLdsStride;
+                const double a0 = As[krow + wr * 32 + lr];
+                const double a1 = As[krow + wr * 32 + 16 + lr];
+                const double b0 = Bsrc[krow + wc * 32 + lr];
+                const double b1 = Bsrc[krow + wc * 32 + 16 + lr];
+                acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+            }
         }
+        if (ch + 1 < nchunk) stash(buf ^ 1);
+        __syncthreads();
     }
     // accumulator layout (v_mfma_f64_16x16x4): register q of lane l holds D[4q + l/16][l%16]
+    double* Ct = lds;  // the staging buffers are free now
     for (int m = 0; m < 2; ++m)
         for (int n = 0; n < 2; ++n)
             for (int q = 0; q < 4; ++q) {
@@ -402,29 +532,48 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
                 Ct[c * kCtPad + i] = acc[m][n][q];
             }
     if (tid < kTile) {
-        const int gc = c0 + tid;
-        if (gc < r) {
-            const int64_t at = rp + w + gc;
-            const int p = a.rowpair[at];
-            const int t = a.pair_tgt[p];
-            colbase[tid] = a.sn_off[t] + (int64_t)(a.rows[at] - a.sn_first[t]) * a.sn_ld[t];
-            relbase[tid] = a.pair_rel[p] - a.pair_seg[p];
-        }
+        colbase[tid] = my_colbase;
+        relbase[tid] = my_relbase;
+        colexcl[tid] = my_excl;
     }
     __syncthreads();
-    for (int e = tid; e < kTile * kTile; e += blockDim.x) {
-        const int i = e & (kTile - 1), c = e >> 6;
-        const int gi = i0 + i, gc = c0 + c;
-        if (gi < r && gc < r && gi >= gc) {
-            const int64_t dst = colbase[c] + a.rel[relbase[c] + gi];
-            unsafeAtomicAdd(arena + dst, -Ct[c * kCtPad + i]);
-        }
+    // thread -> row i = tid & 63 of the tile, columns c = tid / 64 + 4u (u < 16);
+    // every relative index is loaded before the first update is issued
+    constexpr int kPer = kTile * kTile / 256;
+    const int i = tid & (kTile - 1), gi = i0 + i;
+    int64_t dst[kPer];
+    bool ok[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int c = (tid >> 6) + 4 * u, gc = c0 + c;
+        ok[u] = gi < r && gc < r && gi >= gc;
+        dst[u] = ok[u] ? colbase[c] + a.rel[relbase[c] + gi] : 0;
+    }
+    double old[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int c = (tid >> 6) + 4 * u;
+        old[u] = (ok[u] && colexcl[c]) ? arena[dst[u]] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        if (!ok[u]) continue;
+        const int c = (tid >> 6) + 4 * u;
+        const double v = Ct[c * kCtPad + i];
+        if (colexcl[c]) arena[dst[u]] = old[u] - v;
+        else unsafeAtomicAdd(arena + dst[u], -v);
     }
 }
 
 // ---------------------------------------------------------------------------
 // driver
 // ---------------------------------------------------------------------------
+
+static size_t trsm_lds(int wmax) {
+    const size_t np = (wmax + kPanel - 1) / kPanel;
+    return ((size_t)wmax * (wmax + 1) / 2 + np * kPanel * kPanel +
+            (size_t)(kTrsmThreads / 64) * 16 * np * kPanel) * sizeof(double);
+}
 
 static int grid_for(int64_t n, int block) {
     int64_t g = (n + block - 1) / block;
@@ -465,6 +614,7 @@ int32_t run_factor(spc_numeric* num, const double* values, hipStream_t st) {
     const KArgs a = kargs(P);
     num->stream = st;
     num->factored = false;
+    num->status_known = false;
     num->marks.clear();
     num->next_event = 0;
     int ev = mark_begin(num, st);
@@ -481,24 +631,25 @@ int32_t run_factor(spc_numeric* num, const double* values, hipStream_t st) {
     for (int32_t l = 0; l < nl; ++l) {
         const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1];
         const int wmax = P->level_maxw[l];
-        const size_t lds_tri = (size_t)wmax * (wmax + 1) / 2 * sizeof(double);
+        const size_t lds_tri = ((size_t)wmax * (wmax + 1) / 2 + 1) * sizeof(double);
         ev = mark_begin(num, st);
-        hipLaunchKernelGGL(k_potrf, dim3(n1 - n0), dim3(256), lds_tri, st, P->level_sn + n0, a,
-                           num->arena, num->status_dev);
+        hipLaunchKernelGGL(k_potrf, dim3(n1 - n0), dim3(kPotrfThreads), lds_tri, st, P->level_sn + n0, a,
+                           num->arena, num->dinv, num->status_dev);
         mark_end(num, st, 1, ev);
         const int64_t rb0 = P->rowblk_ptr[l], rb1 = P->rowblk_ptr[l + 1];
         if (rb1 > rb0) {
             ev = mark_begin(num, st);
-            hipLaunchKernelGGL(k_trsm, dim3((unsigned)(rb1 - rb0)), dim3(kTile),
-                               (size_t)wmax * kTile * sizeof(double), st, P->rowblk + rb0, a,
-                               num->arena);
+            hipLaunchKernelGGL(k_trsm, dim3((unsigned)(rb1 - rb0)), dim3(kTrsmThreads),
+                               trsm_lds(wmax), st, P->rowblk + rb0, a, num->arena,
+                               (const double*)num->dinv);
             mark_end(num, st, 2, ev);
         }
         const int64_t t0 = P->tile_ptr[l], t1 = P->tile_ptr[l + 1];
         if (t1 > t0) {
             ev = mark_begin(num, st);
             hipLaunchKernelGGL(k_update, dim3((unsigned)(t1 - t0)), dim3(256), 0, st,
-                               P->tiles + t0, a, num->arena);
+                               P->tiles + t0, t1 - t0, a, (const uint8_t*)P->pair_excl,
+                               num->arena);
             mark_end(num, st, 3, ev);
         }
     }
@@ -507,17 +658,20 @@ int32_t run_factor(spc_numeric* num, const double* values, hipStream_t st) {
     return OK;
 }
 
+int32_t configure_solve_kernels();
+
 int32_t configure_kernels() {
     static int done = 0;
     static int32_t result = OK;
     if (done) return result;
     done = 1;
-    const int lds_max = (int)(((size_t)kMaxWidth * (kMaxWidth + 1) / 2) * sizeof(double));
+    result = configure_solve_kernels();
+    const int lds_max = (int)(((size_t)kMaxWidth * (kMaxWidth + 1) / 2 + 1) * sizeof(double));
     if (hipFuncSetAttribute((const void*)k_potrf, hipFuncAttributeMaxDynamicSharedMemorySize,
                             lds_max) != hipSuccess)
         result = ERR_HIP;
     if (hipFuncSetAttribute((const void*)k_trsm, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            kMaxWidth * kTile * (int)sizeof(double)) != hipSuccess)
+                            (int)trsm_lds(kMaxWidth)) != hipSuccess)
         result = ERR_HIP;
     return result;
 }

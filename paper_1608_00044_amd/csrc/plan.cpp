@@ -1,0 +1,250 @@
+// Upload of the symbolic analysis to HBM: one allocation holding the
+// supernode table, row lists, slot map, update pairs, relative indices and
+// the per-level work lists the kernels walk.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "runtime.hpp"
+
+namespace spc {
+
+namespace {
+
+struct Layout {
+    size_t total = 0;
+    template <class T>
+    size_t add(size_t count) {
+        size_t at = (total + 255) & ~size_t(255);
+        total = at + count * sizeof(T);
+        return at;
+    }
+};
+
+struct PlanOffsets {
+    size_t sn_first, sn_w, sn_ld, sn_off, inv_off, rowptr, rows, rowpair, slot, perm, pair_tgt,
+        pair_seg, pair_rel, pair_excl, rel, level_sn, rowblk, tiles;
+    size_t total;
+};
+
+void count_work(const Symbolic& S, std::vector<int64_t>& rb_ptr, std::vector<int64_t>& tl_ptr) {
+    const int32_t nl = (int32_t)S.level_ptr.size() - 1;
+    rb_ptr.assign((size_t)nl + 1, 0);
+    tl_ptr.assign((size_t)nl + 1, 0);
+    for (int32_t l = 0; l < nl; ++l) {
+        int64_t rb = 0, tl = 0;
+        for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
+            const int64_t r = S.nbelow(S.level_sn[q]);
+            const int64_t nb = (r + kTile - 1) / kTile;
+            rb += nb;
+            tl += nb * (nb + 1) / 2;
+        }
+        rb_ptr[l + 1] = rb_ptr[l] + rb;
+        tl_ptr[l + 1] = tl_ptr[l] + tl;
+    }
+}
+
+PlanOffsets plan_layout(const Symbolic& S, const std::vector<int64_t>& rb_ptr,
+                        const std::vector<int64_t>& tl_ptr) {
+    Layout L;
+    PlanOffsets o;
+    const size_t ns = (size_t)S.nsup;
+    o.sn_first = L.add<int32_t>(ns);
+    o.sn_w = L.add<int32_t>(ns);
+    o.sn_ld = L.add<int32_t>(ns);
+    o.sn_off = L.add<int64_t>(ns);
+    o.inv_off = L.add<int64_t>(ns);
+    o.rowptr = L.add<int64_t>(ns + 1);
+    o.rows = L.add<int32_t>(S.rows.size());
+    o.rowpair = L.add<int32_t>(S.rows.size());
+    o.slot = L.add<int64_t>(S.slot.size());
+    o.perm = L.add<int32_t>(S.perm.size());
+    o.pair_tgt = L.add<int32_t>(S.pairs.size());
+    o.pair_seg = L.add<int32_t>(S.pairs.size());
+    o.pair_rel = L.add<int64_t>(S.pairs.size());
+    o.pair_excl = L.add<uint8_t>(S.pairs.size());
+    o.rel = L.add<int32_t>(S.rel.size());
+    o.level_sn = L.add<int32_t>(S.level_sn.size());
+    o.rowblk = L.add<RowBlock>((size_t)rb_ptr.back());
+    o.tiles = L.add<UpdTile>((size_t)tl_ptr.back());
+    o.total = L.total;
+    return o;
+}
+
+}  // namespace
+
+int64_t inverse_blocks_elems(const Symbolic& S) {
+    int64_t t = 0;
+    for (int64_t s = 0; s < S.nsup; ++s) t += (int64_t)((S.width(s) + kPanel - 1) / kPanel) * kPanel * kPanel;
+    return t;
+}
+
+size_t plan_bytes(const Symbolic& S) {
+    std::vector<int64_t> a, b;
+    count_work(S, a, b);
+    return plan_layout(S, a, b).total;
+}
+
+int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return ERR_HIP;
+    std::lock_guard<std::mutex> lock(sym->mu);
+    for (DevicePlan* p : sym->plans)
+        if (p->device == dev) { *out = p; return OK; }
+    const Symbolic& S = sym->S;
+    if (S.max_r >= 32767 * kTile) return ERR_ARG;  // tile coordinates are 16-bit
+    DevicePlan* P = new DevicePlan();
+    P->device = dev;
+    count_work(S, P->rowblk_ptr, P->tile_ptr);
+    PlanOffsets o = plan_layout(S, P->rowblk_ptr, P->tile_ptr);
+    std::vector<char> h(o.total ? o.total : 1, 0);
+    auto put = [&](size_t at, const void* src, size_t bytes) {
+        if (bytes) std::memcpy(h.data() + at, src, bytes);
+    };
+    const size_t ns = (size_t)S.nsup;
+    std::vector<int32_t> w(ns), first(ns);
+    std::vector<int64_t> inv(ns);
+    int64_t io = 0;
+    for (size_t s = 0; s < ns; ++s) {
+        first[s] = S.sn_ptr[s];
+        w[s] = S.width((int64_t)s);
+        inv[s] = io;
+        io += (int64_t)((w[s] + kPanel - 1) / kPanel) * kPanel * kPanel;
+    }
+    P->inv_elems = io;
+    put(o.sn_first, first.data(), ns * 4);
+    put(o.sn_w, w.data(), ns * 4);
+    put(o.sn_ld, S.ld.data(), ns * 4);
+    put(o.sn_off, S.off.data(), ns * 8);
+    put(o.inv_off, inv.data(), ns * 8);
+    put(o.rowptr, S.rowptr.data(), (ns + 1) * 8);
+    put(o.rows, S.rows.data(), S.rows.size() * 4);
+    {
+        std::vector<int32_t> rp(S.rows.size(), -1);
+        for (size_t p = 0; p < S.pairs.size(); ++p) {
+            const Pair& pr = S.pairs[p];
+            const int64_t base = S.rowptr[pr.src] + S.width(pr.src);
+            for (int32_t i = pr.seg_begin; i < pr.seg_end; ++i) rp[base + i] = (int32_t)p;
+        }
+        put(o.rowpair, rp.data(), rp.size() * 4);
+    }
+    put(o.slot, S.slot.data(), S.slot.size() * 8);
+    put(o.perm, S.perm.data(), S.perm.size() * 4);
+    {
+        const size_t np = S.pairs.size();
+        std::vector<int32_t> tg(np), sg(np);
+        std::vector<int64_t> ro(np);
+        for (size_t p = 0; p < np; ++p) {
+            tg[p] = S.pairs[p].tgt;
+            sg[p] = S.pairs[p].seg_begin;
+            ro[p] = S.pairs[p].rel_off;
+        }
+        put(o.pair_tgt, tg.data(), np * 4);
+        put(o.pair_seg, sg.data(), np * 4);
+        put(o.pair_rel, ro.data(), np * 8);
+        // a pair is exclusive when no other source of its level updates its target
+        std::vector<uint8_t> ex(np, 0);
+        std::vector<int32_t> cnt((size_t)S.nsup, 0), stamp((size_t)S.nsup, -1);
+        const int32_t nl = (int32_t)S.level_ptr.size() - 1;
+        for (int32_t l = 0; l < nl; ++l) {
+            for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
+                const int32_t s = S.level_sn[q];
+                for (int64_t p = S.pair_ptr[s]; p < S.pair_ptr[s + 1]; ++p) {
+                    const int32_t t = S.pairs[p].tgt;
+                    if (stamp[t] != l) { stamp[t] = l; cnt[t] = 0; }
+                    cnt[t]++;
+                }
+            }
+            for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
+                const int32_t s = S.level_sn[q];
+                for (int64_t p = S.pair_ptr[s]; p < S.pair_ptr[s + 1]; ++p)
+                    ex[p] = cnt[S.pairs[p].tgt] == 1;
+            }
+        }
+        put(o.pair_excl, ex.data(), np);
+    }
+    put(o.rel, S.rel.data(), S.rel.size() * 4);
+    put(o.level_sn, S.level_sn.data(), S.level_sn.size() * 4);
+    {
+        const int32_t nl = (int32_t)S.level_ptr.size() - 1;
+        std::vector<RowBlock> rb((size_t)P->rowblk_ptr.back());
+        std::vector<UpdTile> tl((size_t)P->tile_ptr.back());
+        P->level_maxw.assign((size_t)nl, 0);
+        size_t a = 0, b = 0;
+        for (int32_t l = 0; l < nl; ++l) {
+            for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
+                const int32_t s = S.level_sn[q];
+                P->level_maxw[l] = std::max(P->level_maxw[l], S.width(s));
+                const int32_t nb = (S.nbelow(s) + kTile - 1) / kTile;
+                for (int32_t i = 0; i < nb; ++i) rb[a++] = RowBlock{s, i};
+                for (int32_t i = 0; i < nb; ++i)
+                    for (int32_t j = 0; j <= i; ++j) tl[b++] = UpdTile{s, (int16_t)i, (int16_t)j};
+            }
+        }
+        put(o.rowblk, rb.data(), rb.size() * sizeof(RowBlock));
+        put(o.tiles, tl.data(), tl.size() * sizeof(UpdTile));
+    }
+    void* d = nullptr;
+    if (hipMalloc(&d, o.total ? o.total : 256) != hipSuccess) { delete P; return ERR_OOM; }
+    if (hipMemcpy(d, h.data(), o.total, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        delete P;
+        return ERR_HIP;
+    }
+    char* base = (char*)d;
+    P->block = d;
+    P->bytes = o.total;
+    P->sn_first = (int32_t*)(base + o.sn_first);
+    P->sn_w = (int32_t*)(base + o.sn_w);
+    P->sn_ld = (int32_t*)(base + o.sn_ld);
+    P->sn_off = (int64_t*)(base + o.sn_off);
+    P->inv_off = (int64_t*)(base + o.inv_off);
+    P->rowptr = (int64_t*)(base + o.rowptr);
+    P->rows = (int32_t*)(base + o.rows);
+    P->rowpair = (int32_t*)(base + o.rowpair);
+    P->slot = (int64_t*)(base + o.slot);
+    P->perm = (int32_t*)(base + o.perm);
+    P->pair_tgt = (int32_t*)(base + o.pair_tgt);
+    P->pair_seg = (int32_t*)(base + o.pair_seg);
+    P->pair_rel = (int64_t*)(base + o.pair_rel);
+    P->pair_excl = (uint8_t*)(base + o.pair_excl);
+    P->rel = (int32_t*)(base + o.rel);
+    P->level_sn = (int32_t*)(base + o.level_sn);
+    P->rowblk = (RowBlock*)(base + o.rowblk);
+    P->tiles = (UpdTile*)(base + o.tiles);
+    sym->plans.push_back(P);
+    *out = P;
+    return OK;
+}
+
+void free_plan(DevicePlan* p) {
+    if (!p) return;
+    if (p->block) {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(p->device);
+        (void)hipFree(p->block);
+        (void)hipSetDevice(cur);
+    }
+    delete p;
+}
+
+KArgs kargs(const DevicePlan* P) {
+    KArgs a;
+    a.sn_first = P->sn_first;
+    a.sn_w = P->sn_w;
+    a.sn_ld = P->sn_ld;
+    a.sn_off = P->sn_off;
+    a.inv_off = P->inv_off;
+    a.rowptr = P->rowptr;
+    a.rows = P->rows;
+    a.rowpair = P->rowpair;
+    a.pair_tgt = P->pair_tgt;
+    a.pair_seg = P->pair_seg;
+    a.pair_rel = P->pair_rel;
+    a.rel = P->rel;
+    return a;
+}
+
+}  // namespace spc

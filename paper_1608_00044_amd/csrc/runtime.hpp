@@ -14,8 +14,12 @@ namespace spc {
 
 // Tile edge of the update and panel kernels (rows of the below-diagonal panel).
 constexpr int kTile = 64;
-// Widest supernode the diagonal-block kernel holds in LDS (packed lower triangle).
-constexpr int kMaxWidth = 160;
+// Widest supernode the diagonal-block kernels hold in LDS (packed lower
+// triangle plus inverse blocks and staged rows); the paper's cap is 150.
+constexpr int kMaxWidth = 150;
+// Column panel of the blocked diagonal factorization; the inverse of every
+// kPanel x kPanel diagonal block is kept for the panel and triangular solves.
+constexpr int kPanel = 16;
 
 // One update tile: rows [bi*64, bi*64+64) x columns [bj*64, bj*64+64) of the
 // lower triangle of P P^T, P = the below-diagonal panel of source supernode s.
@@ -32,6 +36,8 @@ struct DevicePlan {
     int32_t* sn_w = nullptr;
     int32_t* sn_ld = nullptr;
     int64_t* sn_off = nullptr;
+    int64_t* inv_off = nullptr;  // offset of the supernode's diagonal-block inverses
+    int64_t inv_elems = 0;
     int64_t* rowptr = nullptr;
     int32_t* rows = nullptr;
     int32_t* rowpair = nullptr;  // per entry of rows: pair index of the source row, -1 on own columns
@@ -40,6 +46,7 @@ struct DevicePlan {
     int32_t* pair_tgt = nullptr;
     int32_t* pair_seg = nullptr;  // seg_begin
     int64_t* pair_rel = nullptr;  // rel_off
+    uint8_t* pair_excl = nullptr; // 1 if no other source of the level shares the target
     int32_t* rel = nullptr;
     int32_t* level_sn = nullptr;
     RowBlock* rowblk = nullptr;
@@ -55,6 +62,7 @@ struct KArgs {
     const int32_t* sn_w;
     const int32_t* sn_ld;
     const int64_t* sn_off;
+    const int64_t* inv_off;
     const int64_t* rowptr;
     const int32_t* rows;
     const int32_t* rowpair;
@@ -80,11 +88,13 @@ struct spc_numeric {
     spc::DevicePlan* plan = nullptr;
     int device = -1;
     double* arena = nullptr;
+    double* dinv = nullptr;         // inverses of the kPanel diagonal blocks
     int32_t* status_dev = nullptr;  // INT32_MAX = no failure
     double* work = nullptr;         // solve vector, n x work_cols
     int64_t work_cols = 0;
     hipStream_t stream = nullptr;
     int32_t host_status = 0;
+    bool status_known = false;  // host_status holds the current factorization's status
     bool factored = false;
     // optional per-launch event timing (class, start, stop)
     bool timing = false;
@@ -97,6 +107,8 @@ struct spc_numeric {
 namespace spc {
 
 size_t plan_bytes(const Symbolic& S);
+int64_t inverse_blocks_elems(const Symbolic& S);
+KArgs kargs(const DevicePlan* P);
 int32_t get_plan(spc_symbolic* sym, DevicePlan** out);
 void free_plan(DevicePlan* p);
 int32_t run_factor(spc_numeric* num, const double* values, hipStream_t stream);

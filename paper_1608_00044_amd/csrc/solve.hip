@@ -2,10 +2,16 @@
 // arXiv:1608.00044): y = L^{-1} P b by a forward sweep over the supernodal
 // elimination tree from the leaves, then z = L^{-T} y from the root back, and
 // x = P^T z.  Both sweeps go level by level; within a level every supernode
-// is independent.  The forward sweep subtracts L21 y_s from the rows below
-// each supernode with atomic adds (sibling supernodes share ancestor rows);
-// the backward sweep only reads ancestor entries, which earlier levels of the
-// reverse sweep have finished.
+// is independent.  Each level is two launches:
+//   forward:  k_fwd_diag  -- y_s = L11^{-1} y_s, one workgroup per supernode, by
+//                            16-column panels using the inverted 16 x 16
+//                            diagonal blocks the factorization kept;
+//             k_fwd_gemv  -- y[rows below] -= L21 y_s for every 64-row block
+//                            of every panel (atomic adds: sibling supernodes
+//                            share ancestor rows);
+//   backward: k_bwd_gemv  -- t_s += L21^T y[rows below], per 64-row block
+//                            with wave reductions;
+//             k_bwd_diag  -- y_s = L11^{-T} (y_s - t_s), panels in reverse.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -18,8 +24,6 @@ namespace spc {
     do {                                         \
         if ((x) != hipSuccess) return ERR_HIP;   \
     } while (0)
-
-constexpr int kChunk = 2048;
 
 __global__ void k_gather(const double* __restrict__ b, int64_t ldb,
                          const int32_t* __restrict__ perm, double* __restrict__ y, int64_t n,
@@ -42,82 +46,219 @@ __global__ void k_scatter(const double* __restrict__ y, const int32_t* __restric
     }
 }
 
-// Forward: y_s = L11^{-1} y_s (column-oriented substitution in LDS), then
-// y[rows below] -= L21 y_s.
-__global__ __launch_bounds__(256) void k_fwd(const int32_t* __restrict__ level_sn, KArgs a,
-                                             const double* __restrict__ arena,
-                                             double* __restrict__ y, int64_t n, int nrhs) {
-    __shared__ double ys[kMaxWidth];
+__global__ void k_zero(double* __restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+// Stages the packed lower triangle of the w x w diagonal block (entry (i, j)
+// at cst(j) + i) and the supernode's 16 x 16 inverse blocks into LDS, eight
+// independent global loads per thread in flight.
+__device__ __forceinline__ void stage_block(double* __restrict__ T, double* __restrict__ I,
+                                            const double* __restrict__ L,
+                                            const double* __restrict__ inv, int w, int ld,
+                                            int npanel, int tid) {
+    const int ww = w * w;
+    for (int e0 = tid; e0 < ww; e0 += 8 * 256) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * 256, i = e % w, j = e / w;
+            v[u] = (e < ww && i >= j) ? L[i + (int64_t)j * ld] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * 256, i = e % w, j = e / w;
+            if (e < ww && i >= j) T[((j * (2 * w - j - 1)) >> 1) + i] = v[u];
+        }
+    }
+    const int ni = npanel * kPanel * kPanel;
+    for (int e0 = tid; e0 < ni; e0 += 8 * 256) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = (e0 + u * 256 < ni) ? inv[e0 + u * 256] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (e0 + u * 256 < ni) I[e0 + u * 256] = v[u];
+    }
+}
+
+// Forward, diagonal block: the block L11 (packed lower triangle) and its
+// 16 x 16 diagonal-block inverses are staged in LDS by the workgroup, then
+// wave 0 runs, for each 16-column panel p,
+//   t = y_p - L[p, <p] y_{<p}   (lanes j + 16 part split the dot products),
+//   y_p = inv(D_p) t.
+__global__ __launch_bounds__(256) void k_fwd_diag(const int32_t* __restrict__ level_sn, KArgs a,
+                                                  const double* __restrict__ arena,
+                                                  const double* __restrict__ dinv,
+                                                  double* __restrict__ y, int64_t n, int nrhs) {
+    extern __shared__ double sm[];
+    __shared__ double ys[kMaxWidth + kPanel];
     const int s = level_sn[blockIdx.x];
     const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
-    const int64_t rp = a.rowptr[s];
-    const int r = (int)(a.rowptr[s + 1] - rp) - w;
     const double* __restrict__ L = arena + a.sn_off[s];
-    const int32_t* __restrict__ below = a.rows + rp + w;
-    const int tid = threadIdx.x;
+    const double* __restrict__ inv = dinv + a.inv_off[s];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, j = lane & 15,
+              part = lane >> 4;
+    const int npanel = (w + kPanel - 1) / kPanel;
+    auto cst = [w](int jj) { return (jj * (2 * w - jj - 1)) >> 1; };
+    double* T = sm;
+    double* I = sm + w * (w + 1) / 2;
+    stage_block(T, I, L, inv, w, ld, npanel, tid);
     for (int c = 0; c < nrhs; ++c) {
         double* __restrict__ yc = y + (int64_t)c * n;
-        for (int k = tid; k < w; k += blockDim.x) ys[k] = yc[first + k];
+        for (int k = tid; k < w; k += 256) ys[k] = yc[first + k];
         __syncthreads();
-        for (int k = 0; k < w; ++k) {
-            if (tid == 0) ys[k] /= L[k + (int64_t)k * ld];
-            __syncthreads();
-            const double yk = ys[k];
-            for (int j = k + 1 + tid; j < w; j += blockDim.x) ys[j] -= L[j + (int64_t)k * ld] * yk;
-            __syncthreads();
+        if (wave == 0) {
+            for (int p = 0; p < npanel; ++p) {
+                const int j0 = p * kPanel, jb = min(kPanel, w - j0);
+                double acc = 0.0;
+                if (j < jb)
+                    for (int k = part; k < j0; k += 4) acc += T[cst(k) + j0 + j] * ys[k];
+                acc += __shfl_xor(acc, 16);
+                acc += __shfl_xor(acc, 32);
+                const double t = (j < jb) ? ys[j0 + j] - acc : 0.0;
+                double out = 0.0;
+#pragma unroll
+                for (int k = 0; k < kPanel; ++k)
+                    out += I[p * kPanel * kPanel + j * kPanel + k] * __shfl(t, k);
+                if (lane < jb) ys[j0 + lane] = out;
+            }
         }
-        for (int k = tid; k < w; k += blockDim.x) yc[first + k] = ys[k];
-        for (int i = tid; i < r; i += blockDim.x) {
-            double acc = 0.0;
-            for (int k = 0; k < w; ++k) acc += L[w + i + (int64_t)k * ld] * ys[k];
-            unsafeAtomicAdd(yc + below[i], -acc);
-        }
+        __syncthreads();
+        for (int k = tid; k < w; k += 256) yc[first + k] = ys[k];
         __syncthreads();
     }
 }
 
-// Backward: y_s -= L21^T y[rows below] (each wave reduces columns k = wave,
-// wave + 4, ...; the gathered entries are staged in LDS by chunks), then
-// y_s = L11^{-T} y_s by back substitution.
-__global__ __launch_bounds__(256) void k_bwd(const int32_t* __restrict__ level_sn, KArgs a,
-                                             const double* __restrict__ arena,
-                                             double* __restrict__ y, int64_t n, int nrhs) {
+// Forward, below the diagonal block: y[rows(i)] -= sum_k L21[i][k] y_s[k];
+// the four waves split the columns and combine through LDS.
+__global__ __launch_bounds__(256) void k_fwd_gemv(const RowBlock* __restrict__ work, KArgs a,
+                                                  const double* __restrict__ arena,
+                                                  double* __restrict__ y, int64_t n, int nrhs) {
     __shared__ double ys[kMaxWidth];
-    __shared__ double xb[kChunk];
-    const int s = level_sn[blockIdx.x];
+    __shared__ double red[256];
+    const RowBlock wb = work[blockIdx.x];
+    const int s = wb.s;
     const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
     const int64_t rp = a.rowptr[s];
     const int r = (int)(a.rowptr[s + 1] - rp) - w;
-    const double* __restrict__ L = arena + a.sn_off[s];
+    const double* __restrict__ P = arena + a.sn_off[s] + w;
     const int32_t* __restrict__ below = a.rows + rp + w;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int i = wb.rb * kTile + lane;
     for (int c = 0; c < nrhs; ++c) {
         double* __restrict__ yc = y + (int64_t)c * n;
-        for (int k = tid; k < w; k += blockDim.x) ys[k] = yc[first + k];
-        for (int i0 = 0; i0 < r; i0 += kChunk) {
-            const int m = min(kChunk, r - i0);
-            __syncthreads();
-            for (int i = tid; i < m; i += blockDim.x) xb[i] = yc[below[i0 + i]];
-            __syncthreads();
-            for (int k = wave; k < w; k += 4) {
-                const double* __restrict__ col = L + w + i0 + (int64_t)k * ld;
-                double part = 0.0;
-                for (int i = lane; i < m; i += 64) part += col[i] * xb[i];
-                for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
-                if (lane == 0) ys[k] -= part;
+        for (int k = tid; k < w; k += 256) ys[k] = yc[first + k];
+        __syncthreads();
+        double acc = 0.0;
+        if (i < r) {
+#pragma unroll 4
+            for (int k = wave; k < w; k += 4) acc += P[i + (int64_t)k * ld] * ys[k];
+        }
+        red[tid] = acc;
+        __syncthreads();
+        if (tid < 64 && i < r)
+            unsafeAtomicAdd(yc + below[i], -(red[lane] + red[64 + lane] + red[128 + lane] +
+                                             red[192 + lane]));
+        __syncthreads();
+    }
+}
+
+// Backward, below the diagonal block: t_s[k] += sum_i L21[i][k] y[rows(i)]
+// over one 64-row block; wave q reduces the columns k = q, q + 4, ...
+__global__ __launch_bounds__(256) void k_bwd_gemv(const RowBlock* __restrict__ work, KArgs a,
+                                                  const double* __restrict__ arena,
+                                                  const double* __restrict__ y,
+                                                  double* __restrict__ tacc, int64_t n,
+                                                  int nrhs) {
+    const RowBlock wb = work[blockIdx.x];
+    const int s = wb.s;
+    const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
+    const int64_t rp = a.rowptr[s];
+    const int r = (int)(a.rowptr[s + 1] - rp) - w;
+    const double* __restrict__ P = arena + a.sn_off[s] + w;
+    const int32_t* __restrict__ below = a.rows + rp + w;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = wb.rb * kTile + lane;
+    for (int c = 0; c < nrhs; ++c) {
+        const double* __restrict__ yc = y + (int64_t)c * n;
+        const double xr = (i < r) ? yc[below[i]] : 0.0;
+#pragma unroll 2
+        for (int k = wave; k < w; k += 4) {
+            double v = (i < r) ? P[i + (int64_t)k * ld] * xr : 0.0;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if (lane == 0) unsafeAtomicAdd(tacc + (int64_t)c * n + first + k, v);
+        }
+    }
+}
+
+// Backward, diagonal block: y_s = L11^{-T} (y_s - t_s), panels from the last:
+//   u = v_p - L[>p, p]^T y_{>p},   y_p = inv(D_p)^T u,
+// with L11 and the inverses staged in LDS as in k_fwd_diag.
+__global__ __launch_bounds__(256) void k_bwd_diag(const int32_t* __restrict__ level_sn, KArgs a,
+                                                  const double* __restrict__ arena,
+                                                  const double* __restrict__ dinv,
+                                                  double* __restrict__ y,
+                                                  const double* __restrict__ tacc, int64_t n,
+                                                  int nrhs) {
+    extern __shared__ double sm[];
+    __shared__ double ys[kMaxWidth + kPanel];
+    const int s = level_sn[blockIdx.x];
+    const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
+    const double* __restrict__ L = arena + a.sn_off[s];
+    const double* __restrict__ inv = dinv + a.inv_off[s];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, j = lane & 15,
+              part = lane >> 4;
+    const int npanel = (w + kPanel - 1) / kPanel;
+    auto cst = [w](int jj) { return (jj * (2 * w - jj - 1)) >> 1; };
+    double* T = sm;
+    double* I = sm + w * (w + 1) / 2;
+    stage_block(T, I, L, inv, w, ld, npanel, tid);
+    for (int c = 0; c < nrhs; ++c) {
+        double* __restrict__ yc = y + (int64_t)c * n;
+        const double* __restrict__ tc = tacc + (int64_t)c * n;
+        for (int k = tid; k < w; k += 256) ys[k] = yc[first + k] - tc[first + k];
+        __syncthreads();
+        if (wave == 0) {
+            for (int p = npanel - 1; p >= 0; --p) {
+                const int j0 = p * kPanel, jb = min(kPanel, w - j0);
+                double acc = 0.0;
+                if (j < jb)
+                    for (int k = j0 + kPanel + part; k < w; k += 4)
+                        acc += T[cst(j0 + j) + k] * ys[k];
+                acc += __shfl_xor(acc, 16);
+                acc += __shfl_xor(acc, 32);
+                const double u = (j < jb) ? ys[j0 + j] - acc : 0.0;
+                double out = 0.0;
+#pragma unroll
+                for (int k = 0; k < kPanel; ++k)
+                    out += I[p * kPanel * kPanel + k * kPanel + j] * __shfl(u, k);
+                if (lane < jb) ys[j0 + lane] = out;
             }
         }
         __syncthreads();
-        for (int k = w - 1; k >= 0; --k) {
-            if (tid == 0) ys[k] /= L[k + (int64_t)k * ld];
-            __syncthreads();
-            const double yk = ys[k];
-            for (int j = tid; j < k; j += blockDim.x) ys[j] -= L[k + (int64_t)j * ld] * yk;
-            __syncthreads();
-        }
-        for (int k = tid; k < w; k += blockDim.x) yc[first + k] = ys[k];
+        for (int k = tid; k < w; k += 256) yc[first + k] = ys[k];
         __syncthreads();
     }
+}
+
+static size_t diag_lds(int wmax) {
+    const int np = (wmax + kPanel - 1) / kPanel;
+    return ((size_t)wmax * (wmax + 1) / 2 + (size_t)np * kPanel * kPanel) * sizeof(double);
+}
+
+int32_t configure_solve_kernels() {
+    const int mx = (int)diag_lds(kMaxWidth);
+    if (hipFuncSetAttribute((const void*)k_fwd_diag, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            mx) != hipSuccess)
+        return ERR_HIP;
+    if (hipFuncSetAttribute((const void*)k_bwd_diag, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            mx) != hipSuccess)
+        return ERR_HIP;
+    return OK;
 }
 
 int32_t run_solve(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb, double* x,
@@ -128,41 +269,46 @@ int32_t run_solve(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb, 
     if (n == 0 || nrhs == 0) return OK;
     if (num->work_cols < nrhs) {
         if (num->work) {
-            HIP_TRY(hipStreamSynchronize(num->stream));
+            HIP_TRY(hipDeviceSynchronize());
             HIP_TRY(hipFree(num->work));
             num->work = nullptr;
             num->work_cols = 0;
         }
-        if (hipMalloc(&num->work, sizeof(double) * (size_t)n * nrhs) != hipSuccess) return ERR_OOM;
+        if (hipMalloc(&num->work, 2 * sizeof(double) * (size_t)n * nrhs) != hipSuccess)
+            return ERR_OOM;
         num->work_cols = nrhs;
     }
-    KArgs a;
-    a.sn_first = P->sn_first;
-    a.sn_w = P->sn_w;
-    a.sn_ld = P->sn_ld;
-    a.sn_off = P->sn_off;
-    a.rowptr = P->rowptr;
-    a.rows = P->rows;
-    a.rowpair = P->rowpair;
-    a.pair_tgt = P->pair_tgt;
-    a.pair_seg = P->pair_seg;
-    a.pair_rel = P->pair_rel;
-    a.rel = P->rel;
+    double* y = num->work;
+    double* tacc = num->work + (size_t)n * nrhs;
+    const KArgs a = kargs(P);
     const int64_t total = n * nrhs;
-    const int g = (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 65536));
-    hipLaunchKernelGGL(k_gather, dim3(g), dim3(256), 0, st, b, ldb, P->perm, num->work, n, nrhs);
+    const int g = (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_zero, dim3(g), dim3(256), 0, st, tacc, total);
+    hipLaunchKernelGGL(k_gather, dim3(g), dim3(256), 0, st, b, ldb, P->perm, y, n, nrhs);
     const int32_t nl = (int32_t)S.level_ptr.size() - 1;
     for (int32_t l = 0; l < nl; ++l) {
         const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1];
-        hipLaunchKernelGGL(k_fwd, dim3(n1 - n0), dim3(256), 0, st, P->level_sn + n0, a,
-                           num->arena, num->work, n, nrhs);
+        const size_t lds = diag_lds(P->level_maxw[l]);
+        hipLaunchKernelGGL(k_fwd_diag, dim3(n1 - n0), dim3(256), lds, st, P->level_sn + n0, a,
+                           (const double*)num->arena, (const double*)num->dinv, y, n, nrhs);
+        const int64_t rb0 = P->rowblk_ptr[l], rb1 = P->rowblk_ptr[l + 1];
+        if (rb1 > rb0)
+            hipLaunchKernelGGL(k_fwd_gemv, dim3((unsigned)(rb1 - rb0)), dim3(256), 0, st,
+                               P->rowblk + rb0, a, (const double*)num->arena, y, n, nrhs);
     }
     for (int32_t l = nl - 1; l >= 0; --l) {
         const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1];
-        hipLaunchKernelGGL(k_bwd, dim3(n1 - n0), dim3(256), 0, st, P->level_sn + n0, a,
-                           num->arena, num->work, n, nrhs);
+        const int64_t rb0 = P->rowblk_ptr[l], rb1 = P->rowblk_ptr[l + 1];
+        if (rb1 > rb0)
+            hipLaunchKernelGGL(k_bwd_gemv, dim3((unsigned)(rb1 - rb0)), dim3(256), 0, st,
+                               P->rowblk + rb0, a, (const double*)num->arena,
+                               (const double*)y, tacc, n, nrhs);
+        hipLaunchKernelGGL(k_bwd_diag, dim3(n1 - n0), dim3(256), diag_lds(P->level_maxw[l]), st,
+                           P->level_sn + n0, a,
+                           (const double*)num->arena, (const double*)num->dinv, y,
+                           (const double*)tacc, n, nrhs);
     }
-    hipLaunchKernelGGL(k_scatter, dim3(g), dim3(256), 0, st, num->work, P->perm, x, ldx, n, nrhs);
+    hipLaunchKernelGGL(k_scatter, dim3(g), dim3(256), 0, st, y, P->perm, x, ldx, n, nrhs);
     HIP_TRY(hipGetLastError());
     return OK;
 }
