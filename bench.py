@@ -96,6 +96,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="lap3d_7pt_64")
     ap.add_argument("--solves", type=int, default=200)
+    ap.add_argument("--sched", type=int, default=1, help="0 level sets, 1 with lookahead")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", default=None,
                     help="grid of the bounded oracle sample (default: 40^3 for 3D workloads, "
@@ -119,7 +120,8 @@ def main():
     log("workload", name, "n", p.n, "nnz", p.nnz)
 
     t0 = time.perf_counter()
-    sym = spchol.analyze(p.n, p.colptr, p.rowind, p.perm, sn_cap=150, amalg_ratio=amalg)
+    sym = spchol.analyze(p.n, p.colptr, p.rowind, p.perm, sn_cap=150, amalg_ratio=amalg,
+                         sched=args.sched)
     analyze_ms = (time.perf_counter() - t0) * 1e3
     info = sym.info()
     F = info["flops"]
@@ -208,6 +210,7 @@ def main():
                    "nnz_lower": p.nnz, "nnz_L": info["nnz_l"], "flops_F": F,
                    "flops_stored": info["flops_stored"], "sn_cap": 150, "amalg_ratio": amalg,
                    "nsup": info["nsup"], "levels": info["nlevels"], "nrhs": 1,
+                   "schedule": ["level sets", "level sets + lookahead"][args.sched],
                    "precision": "fp64"},
         "factor_ms": factor_ms, "factor_ms_min": float(min(f_ms)),
         "solve_ms_in_step": float(np.mean(s_ms)),

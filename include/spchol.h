@@ -68,7 +68,8 @@ enum {
 
 typedef struct spc_options {
     int32_t sn_cap;           /* maximum supernode width, 1..150 columns; default 150 */
-    int32_t sched;            /* 0 = level-by-level launches, 1 = device task queue */
+    int32_t sched;            /* 0 = level by level; 1 = level by level with a
+                                 one-level lookahead on two streams         */
     double amalg_ratio;       /* relaxed amalgamation zero ratio; 0 = off (default) */
     int64_t mem_budget_bytes; /* device bytes a factor may hold; 0 = no limit       */
 } spc_options;

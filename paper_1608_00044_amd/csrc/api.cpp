@@ -48,7 +48,7 @@ spc_status spc_analyze(int64_t n, const int64_t* colptr, const int32_t* rowind,
     spc_default_options(&o);
     if (opt) o = *opt;
     if (o.sn_cap < 1 || o.sn_cap > kMaxWidth) return SPC_ERR_ARG;
-    if (o.sched != 0) return SPC_ERR_ARG;
+    if (o.sched != 0 && o.sched != 1) return SPC_ERR_ARG;
     if (!(o.amalg_ratio >= 0.0 && o.amalg_ratio <= 1.0)) return SPC_ERR_ARG;
     if (o.mem_budget_bytes < 0) return SPC_ERR_ARG;
     spc_symbolic* h = new (std::nothrow) spc_symbolic();
@@ -170,6 +170,15 @@ static spc_status alloc_numeric(spc_symbolic* sym, spc_numeric** out) {
         delete num;
         return SPC_ERR_OOM;
     }
+    num->sched = S.opt.sched;
+    if (num->sched == 1 &&
+        hipStreamCreateWithFlags(&num->bulk, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipFree(num->arena);
+        (void)hipFree(num->status_dev);
+        (void)hipFree(num->dinv);
+        delete num;
+        return SPC_ERR_HIP;
+    }
     {
         std::lock_guard<std::mutex> lock(sym->mu);
         sym->refs++;
@@ -290,9 +299,13 @@ spc_status spc_numeric_get_timing(spc_numeric* num, spc_kernel_times* out) {
         }
     }
     float tot = 0.f;
-    if (hipEventElapsedTime(&tot, num->events[num->marks.front().a],
-                            num->events[num->marks.back().b]) != hipSuccess)
-        return SPC_ERR_HIP;
+    for (const auto& m : num->marks) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, num->events[num->marks.front().a], num->events[m.b]) !=
+            hipSuccess)
+            return SPC_ERR_HIP;
+        tot = t > tot ? t : tot;
+    }
     out->total_ms = tot;
     return SPC_OK;
 }
@@ -307,8 +320,15 @@ void spc_numeric_free(spc_numeric* num) {
     (void)hipFree(num->arena);
     (void)hipFree(num->status_dev);
     (void)hipFree(num->dinv);
+    drop_solve_graphs(num);
+    if (num->capture) (void)hipStreamDestroy(num->capture);
     if (num->work) (void)hipFree(num->work);
     for (hipEvent_t e : num->events) (void)hipEventDestroy(e);
+    for (hipEvent_t e : num->sync_ev) (void)hipEventDestroy(e);
+    if (num->bulk) {
+        (void)hipStreamSynchronize(num->bulk);
+        (void)hipStreamDestroy(num->bulk);
+    }
     (void)hipSetDevice(cur);
     {
         std::lock_guard<std::mutex> lock(num->sym->mu);

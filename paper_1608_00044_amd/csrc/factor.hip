@@ -296,20 +296,103 @@ __global__ __launch_bounds__(kPotrfThreads) void k_potrf(const int32_t* __restri
 // F: panel solve L21 = A21 L11^{-T}
 // ---------------------------------------------------------------------------
 
-// One workgroup of 2 waves per 64-row block of a panel.  The whole diagonal
-// block L11 (packed lower triangle) and its 16 x 16 diagonal-block inverses
-// are staged in LDS once; then each wave takes 16 rows at a time (two passes
-// cover the 64 rows), staged as X[k * 16 + row], and runs the blocked forward
-// substitution by 16-column panels on v_mfma_f64_16x16x4 with no workgroup
-// barrier:
-//   B  = X[:, p] - X[:, <p] L[p, <p]^T      (K = 16 p)
-//   X[:, p] = B inv(D_p)^T                  (K = 16, inverse from k_potrf)
-constexpr int kTrsmThreads = 128;
+// Panel solve for the 16 rows [row0, row0 + 16) of a panel, one wave, with
+// NP 16-column panels (w <= 16 NP).  Everything stays in registers:
+//   xo[p][q]  = X[4q + lk][16p + lr]     (matrix-core output layout)
+//   xa[p][kk] = X[lr][16p + 4kk + lk]    (matrix-core A-operand layout)
+// Panel p: B = X[:, p] - sum_{p' < p} X[:, p'] L[p, p']^T on
+// v_mfma_f64_16x16x4 with L read straight from the supernode block (the next
+// panel's operands are prefetched into registers while the current panel
+// runs), then X[:, p] = B inv(D_p)^T; a 16 x 16 LDS tile converts between the
+// layouts.
+template <int NP>
+__device__ __forceinline__ void trsm_rows(const double* __restrict__ L, int ld,
+                                          const double* __restrict__ inv,
+                                          double* __restrict__ P, int w, int r, int row0,
+                                          double* __restrict__ tr, int lane) {
+    const int lr = lane & 15, lk = lane >> 4;
+    double xo[NP][4], xa[NP][4];
+    // operands of panel p: L[16p + lr][16pp + 4kk + lk] for pp < p, and inv(D_p);
+    // the next panel's are loaded while the current one runs (two register sets)
+    double lv0[4 * NP], lv1[4 * NP], iv0[4], iv1[4];
+    auto fetch = [&](int p, double* lv, double* iv) {
+        const int col = 16 * p + lr;
+        const bool okc = col < w;
+#pragma unroll
+        for (int pp = 0; pp < NP; ++pp) {
+            if (pp < p) {
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int k = 16 * pp + 4 * kk + lk;
+                    const double v = L[okc ? col + (int64_t)k * ld : 0];
+                    lv[4 * pp + kk] = okc ? v : 0.0;
+                }
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) iv[kk] = inv[p * kPanel * kPanel + lr * kPanel + 4 * kk + lk];
+    };
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int row = row0 + 4 * q + lk, col = 16 * p + lr;
+            const bool ok = row < r && col < w;
+            const double v = P[ok ? row + (int64_t)col * ld : 0];
+            xo[p][q] = ok ? v : 0.0;
+        }
+    fetch(0, lv0, iv0);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        double* lv = (p & 1) ? lv1 : lv0;
+        double* iv = (p & 1) ? iv1 : iv0;
+        if (p + 1 < NP) fetch(p + 1, (p & 1) ? lv0 : lv1, (p & 1) ? iv0 : iv1);
+        v4d acc = v4d{xo[p][0], xo[p][1], xo[p][2], xo[p][3]};
+#pragma unroll
+        for (int pp = 0; pp < p; ++pp)
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-xa[pp][kk], lv[4 * pp + kk], acc, 0, 0,
+                                                           0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) tr[(4 * q + lk) * 17 + lr] = acc[q];
+        __builtin_amdgcn_wave_barrier();
+        double bA[4];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) bA[kk] = tr[lr * 17 + 4 * kk + lk];
+        __builtin_amdgcn_wave_barrier();
+        v4d out = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+            out = __builtin_amdgcn_mfma_f64_16x16x4f64(bA[kk], iv[kk], out, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            xo[p][q] = out[q];
+            tr[(4 * q + lk) * 17 + lr] = out[q];
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) xa[p][kk] = tr[lr * 17 + 4 * kk + lk];
+        __builtin_amdgcn_wave_barrier();
+    }
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int row = row0 + 4 * q + lk, col = 16 * p + lr;
+            if (row < r && col < w) P[row + (int64_t)col * ld] = xo[p][q];
+        }
+}
+
+// One workgroup of 4 waves per 64-row block of a panel, 16 rows per wave, no
+// workgroup barrier: L21 = A21 L11^{-T} by blocked forward substitution over
+// 16-column panels with the inverses of the diagonal blocks from k_potrf.
+constexpr int kTrsmThreads = 256;
 
 __global__ __launch_bounds__(kTrsmThreads) void k_trsm(const RowBlock* __restrict__ work, KArgs a,
                                                        double* __restrict__ arena,
                                                        const double* __restrict__ dinv) {
-    extern __shared__ double sm[];
+    __shared__ double trs[kTrsmThreads / 64][16 * 17];
     const RowBlock wb = work[blockIdx.x];
     const int s = wb.s;
     const int w = a.sn_w[s], ld = a.sn_ld[s];
@@ -317,96 +400,25 @@ __global__ __launch_bounds__(kTrsmThreads) void k_trsm(const RowBlock* __restric
     const double* __restrict__ L = arena + a.sn_off[s];
     double* __restrict__ P = arena + a.sn_off[s] + w;
     const double* __restrict__ inv = dinv + a.inv_off[s];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int lr = lane & 15, lk = lane >> 4;
-    const int npanel = (w + kPanel - 1) / kPanel;
-    const int w16 = npanel * kPanel;
-    auto cst = [w](int j) { return (j * (2 * w - j - 1)) >> 1; };
-    double* __restrict__ T = sm;                                  // L11, packed
-    double* __restrict__ I = T + w * (w + 1) / 2;                 // inverses
-    double* __restrict__ X = I + npanel * kPanel * kPanel + (size_t)wave * 16 * w16;
-    {
-        const int ww = w * w;
-        for (int e0 = tid; e0 < ww; e0 += 16 * kTrsmThreads) {
-            double v[16];
-#pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int e = e0 + u * kTrsmThreads, i = e % w, j = e / w;
-                const bool ok = e < ww && i >= j;
-                v[u] = L[ok ? i + (int64_t)j * ld : 0];
-            }
-#pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int e = e0 + u * kTrsmThreads, i = e % w, j = e / w;
-                if (e < ww && i >= j) T[cst(j) + i] = v[u];
-            }
-        }
-        const int ni = npanel * kPanel * kPanel;
-        for (int e0 = tid; e0 < ni; e0 += 8 * kTrsmThreads) {
-            double v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = inv[min(e0 + u * kTrsmThreads, ni - 1)];
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (e0 + u * kTrsmThreads < ni) I[e0 + u * kTrsmThreads] = v[u];
-        }
-    }
-    __syncthreads();
-    for (int pass = 0; pass < 2; ++pass) {
-        const int row0 = wb.rb * kTile + pass * 32 + wave * 16;
-        if (row0 >= r) break;
-        for (int e0 = lane; e0 < 16 * w16; e0 += 16 * 64) {
-            double v[16];
-#pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int e = e0 + 64 * u, rr = e & 15, k = e >> 4;
-                const bool ok = e < 16 * w16 && k < w && row0 + rr < r;
-                v[u] = P[ok ? row0 + rr + (int64_t)k * ld : 0];
-                v[u] = ok ? v[u] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < 16; ++u)
-                if (e0 + 64 * u < 16 * w16) X[e0 + 64 * u] = v[u];
-        }
-        __builtin_amdgcn_wave_barrier();
-        for (int p = 0; p < npanel; ++p) {
-            const int j0 = p * kPanel;
-            const int col = j0 + lr;
-            const bool okc = col < w;
-            v4d acc;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] = X[col * 16 + 4 * q + lk];
-            for (int k0 = 0; k0 < j0; k0 += 4) {
-                const double av = -X[(k0 + lk) * 16 + lr];
-                const double t = T[okc ? cst(k0 + lk) + col : 0];
-                const double bv = okc ? t : 0.0;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) X[col * 16 + 4 * q + lk] = acc[q];
-            __builtin_amdgcn_wave_barrier();
-            double av[4], bv[4];
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                av[kk] = X[(j0 + 4 * kk + lk) * 16 + lr];
-                bv[kk] = I[p * kPanel * kPanel + lr * kPanel + 4 * kk + lk];
-            }
-            v4d out = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk)
-                out = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kk], bv[kk], out, 0, 0, 0);
-            __builtin_amdgcn_wave_barrier();
-#pragma unroll
-            for (int q = 0; q < 4; ++q) X[col * 16 + 4 * q + lk] = out[q];
-            __builtin_amdgcn_wave_barrier();
-        }
-        for (int e = lane; e < 16 * w16; e += 64) {
-            const int rr = e & 15, k = e >> 4;
-            if (k < w && row0 + rr < r) P[row0 + rr + (int64_t)k * ld] = X[e];
-        }
-        __builtin_amdgcn_wave_barrier();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row0 = wb.rb * kTile + wave * 16;
+    if (row0 >= r) return;  // no barrier follows
+    double* tr = trs[wave];
+    switch ((w + kPanel - 1) / kPanel) {
+        case 1: trsm_rows<1>(L, ld, inv, P, w, r, row0, tr, lane); break;
+        case 2: trsm_rows<2>(L, ld, inv, P, w, r, row0, tr, lane); break;
+        case 3: trsm_rows<3>(L, ld, inv, P, w, r, row0, tr, lane); break;
+        case 4: trsm_rows<4>(L, ld, inv, P, w, r, row0, tr, lane); break;
+        case 5: trsm_rows<5>(L, ld, inv, P, w, r, row0, tr, lane); break;
+        case 6: trsm_rows<6>(L, ld, inv, P, w, r, row0, tr, lane); break;
+        case 7: trsm_rows<7>(L, ld, inv, P, w, r, row0, tr, lane); break;
+        case 8: trsm_rows<8>(L, ld, inv, P, w, r, row0, tr, lane); break;
+        case 9: trsm_rows<9>(L, ld, inv, P, w, r, row0, tr, lane); break;
+        default: trsm_rows<10>(L, ld, inv, P, w, r, row0, tr, lane); break;
     }
 }
+
+static_assert(kMaxWidth <= 10 * kPanel, "k_trsm instantiates at most 10 panels");
 
 // ---------------------------------------------------------------------------
 // U + A: update tiles on FP64 MFMA with relative-index scatter
@@ -492,7 +504,7 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
             const int t = a.pair_tgt[p];
             my_colbase = a.sn_off[t] + (int64_t)(a.rows[at] - a.sn_first[t]) * a.sn_ld[t];
             my_relbase = a.pair_rel[p] - a.pair_seg[p];
-            my_excl = pair_excl[p];
+            my_excl = pair_excl ? pair_excl[p] : 0;
         }
     }
     v4d acc[2][2];
@@ -569,11 +581,6 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
 // driver
 // ---------------------------------------------------------------------------
 
-static size_t trsm_lds(int wmax) {
-    const size_t np = (wmax + kPanel - 1) / kPanel;
-    return ((size_t)wmax * (wmax + 1) / 2 + np * kPanel * kPanel +
-            (size_t)(kTrsmThreads / 64) * 16 * np * kPanel) * sizeof(double);
-}
 
 static int grid_for(int64_t n, int block) {
     int64_t g = (n + block - 1) / block;
@@ -608,6 +615,47 @@ void mark_end(spc_numeric* num, hipStream_t st, int cls, int a) {
 
 }  // namespace
 
+// Launches of one level: diagonal factorizations and panel solves on stream
+// fs, then the update tiles [u0, u1) of the level's list on stream us.
+namespace {
+
+void launch_ft(spc_numeric* num, const DevicePlan* P, const Symbolic& S, const KArgs& a,
+               int32_t l, hipStream_t st) {
+    const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1];
+    const int wmax = P->level_maxw[l];
+    const size_t lds_tri = ((size_t)wmax * (wmax + 1) / 2 + 1) * sizeof(double);
+    int ev = mark_begin(num, st);
+    hipLaunchKernelGGL(k_potrf, dim3(n1 - n0), dim3(kPotrfThreads), lds_tri, st, P->level_sn + n0,
+                       a, num->arena, num->dinv, num->status_dev);
+    mark_end(num, st, 1, ev);
+    const int64_t rb0 = P->rowblk_ptr[l], rb1 = P->rowblk_ptr[l + 1];
+    if (rb1 > rb0) {
+        ev = mark_begin(num, st);
+        hipLaunchKernelGGL(k_trsm, dim3((unsigned)(rb1 - rb0)), dim3(kTrsmThreads), 0, st,
+                           P->rowblk + rb0, a, num->arena, (const double*)num->dinv);
+        mark_end(num, st, 2, ev);
+    }
+}
+
+void launch_update(spc_numeric* num, const DevicePlan* P, const KArgs& a, int64_t u0, int64_t u1,
+                   bool exclusive_ok, hipStream_t st) {
+    if (u1 <= u0) return;
+    const int ev = mark_begin(num, st);
+    hipLaunchKernelGGL(k_update, dim3((unsigned)(u1 - u0)), dim3(256), 0, st, P->tiles + u0, u1 - u0,
+                       a, exclusive_ok ? (const uint8_t*)P->pair_excl : nullptr, num->arena);
+    mark_end(num, st, 3, ev);
+}
+
+}  // namespace
+
+// Factorization driver.  sched 0: one stream, level by level (every
+// dependency points to a lower level of the supernodal elimination tree).
+// sched 1: the same order with a one-level lookahead on two streams: the
+// diagonal factorizations, panel solves and the update tiles that feed the
+// next level run on the caller's stream; the other ("bulk") update tiles of
+// level l run on a second stream concurrently with level l + 1, and level l
+// waits only for the bulk tiles of levels <= l - 2.  Concurrent tiles may hit
+// one target, so the lookahead uses atomic adds throughout.
 int32_t run_factor(spc_numeric* num, const double* values, hipStream_t st) {
     const Symbolic& S = num->sym->S;
     const DevicePlan* P = num->plan;
@@ -628,30 +676,34 @@ int32_t run_factor(spc_numeric* num, const double* values, hipStream_t st) {
                            P->slot, num->arena, S.nnz_a);
     mark_end(num, st, 0, ev);
     const int32_t nl = (int32_t)S.level_ptr.size() - 1;
-    for (int32_t l = 0; l < nl; ++l) {
-        const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1];
-        const int wmax = P->level_maxw[l];
-        const size_t lds_tri = ((size_t)wmax * (wmax + 1) / 2 + 1) * sizeof(double);
-        ev = mark_begin(num, st);
-        hipLaunchKernelGGL(k_potrf, dim3(n1 - n0), dim3(kPotrfThreads), lds_tri, st, P->level_sn + n0, a,
-                           num->arena, num->dinv, num->status_dev);
-        mark_end(num, st, 1, ev);
-        const int64_t rb0 = P->rowblk_ptr[l], rb1 = P->rowblk_ptr[l + 1];
-        if (rb1 > rb0) {
-            ev = mark_begin(num, st);
-            hipLaunchKernelGGL(k_trsm, dim3((unsigned)(rb1 - rb0)), dim3(kTrsmThreads),
-                               trsm_lds(wmax), st, P->rowblk + rb0, a, num->arena,
-                               (const double*)num->dinv);
-            mark_end(num, st, 2, ev);
+    if (num->sched == 0 || nl < 2) {
+        for (int32_t l = 0; l < nl; ++l) {
+            launch_ft(num, P, S, a, l, st);
+            launch_update(num, P, a, P->tile_ptr[l], P->tile_ptr[l + 1], true, st);
         }
-        const int64_t t0 = P->tile_ptr[l], t1 = P->tile_ptr[l + 1];
-        if (t1 > t0) {
-            ev = mark_begin(num, st);
-            hipLaunchKernelGGL(k_update, dim3((unsigned)(t1 - t0)), dim3(256), 0, st,
-                               P->tiles + t0, t1 - t0, a, (const uint8_t*)P->pair_excl,
-                               num->arena);
-            mark_end(num, st, 3, ev);
+    } else {
+        hipStream_t sb = num->bulk;
+        // events: [0] start, [1 + 2l] panel solves of level l done, [2 + 2l] bulk of level l done
+        if (num->sync_ev.size() < (size_t)(2 * nl + 1)) {
+            const size_t old = num->sync_ev.size();
+            num->sync_ev.resize((size_t)(2 * nl + 1));
+            for (size_t i = old; i < num->sync_ev.size(); ++i)
+                HIP_TRY(hipEventCreateWithFlags(&num->sync_ev[i], hipEventDisableTiming));
         }
+        hipEvent_t* E = num->sync_ev.data();
+        HIP_TRY(hipEventRecord(E[0], st));
+        HIP_TRY(hipStreamWaitEvent(sb, E[0], 0));
+        for (int32_t l = 0; l < nl; ++l) {
+            if (l >= 2) HIP_TRY(hipStreamWaitEvent(st, E[2 + 2 * (l - 2)], 0));
+            launch_ft(num, P, S, a, l, st);
+            HIP_TRY(hipEventRecord(E[1 + 2 * l], st));
+            const int64_t u0 = P->tile_ptr[l], uc = u0 + P->tile_crit[l], u1 = P->tile_ptr[l + 1];
+            launch_update(num, P, a, u0, uc, false, st);
+            HIP_TRY(hipStreamWaitEvent(sb, E[1 + 2 * l], 0));
+            launch_update(num, P, a, uc, u1, false, sb);
+            HIP_TRY(hipEventRecord(E[2 + 2 * l], sb));
+        }
+        HIP_TRY(hipStreamWaitEvent(st, E[2 + 2 * (nl - 1)], 0));
     }
     HIP_TRY(hipGetLastError());
     num->factored = true;
@@ -669,9 +721,6 @@ int32_t configure_kernels() {
     const int lds_max = (int)(((size_t)kMaxWidth * (kMaxWidth + 1) / 2 + 1) * sizeof(double));
     if (hipFuncSetAttribute((const void*)k_potrf, hipFuncAttributeMaxDynamicSharedMemorySize,
                             lds_max) != hipSuccess)
-        result = ERR_HIP;
-    if (hipFuncSetAttribute((const void*)k_trsm, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)trsm_lds(kMaxWidth)) != hipSuccess)
         result = ERR_HIP;
     return result;
 }

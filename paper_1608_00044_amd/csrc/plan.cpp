@@ -171,16 +171,35 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
         std::vector<RowBlock> rb((size_t)P->rowblk_ptr.back());
         std::vector<UpdTile> tl((size_t)P->tile_ptr.back());
         P->level_maxw.assign((size_t)nl, 0);
+        P->tile_crit.assign((size_t)nl, 0);
         size_t a = 0, b = 0;
+        std::vector<UpdTile> bulk;
+        std::vector<uint8_t> colcrit;
         for (int32_t l = 0; l < nl; ++l) {
+            // tiles of this level whose columns reach a supernode of level l + 1
+            // (needed before that level can be factored) come first, the
+            // rest ("bulk") after them
+            bulk.clear();
             for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
                 const int32_t s = S.level_sn[q];
                 P->level_maxw[l] = std::max(P->level_maxw[l], S.width(s));
-                const int32_t nb = (S.nbelow(s) + kTile - 1) / kTile;
+                const int32_t r = S.nbelow(s);
+                const int32_t nb = (r + kTile - 1) / kTile;
                 for (int32_t i = 0; i < nb; ++i) rb[a++] = RowBlock{s, i};
+                colcrit.assign((size_t)nb, 0);
+                for (int64_t pp = S.pair_ptr[s]; pp < S.pair_ptr[s + 1]; ++pp)
+                    if (S.level[S.pairs[pp].tgt] == l + 1)
+                        for (int32_t c = S.pairs[pp].seg_begin; c < S.pairs[pp].seg_end; ++c)
+                            colcrit[c / kTile] = 1;
                 for (int32_t i = 0; i < nb; ++i)
-                    for (int32_t j = 0; j <= i; ++j) tl[b++] = UpdTile{s, (int16_t)i, (int16_t)j};
+                    for (int32_t j = 0; j <= i; ++j) {
+                        const UpdTile t{s, (int16_t)i, (int16_t)j};
+                        if (colcrit[j]) tl[b++] = t;
+                        else bulk.push_back(t);
+                    }
             }
+            P->tile_crit[l] = (int64_t)b - P->tile_ptr[l];
+            for (const UpdTile& t : bulk) tl[b++] = t;
         }
         put(o.rowblk, rb.data(), rb.size() * sizeof(RowBlock));
         put(o.tiles, tl.data(), tl.size() * sizeof(UpdTile));

@@ -53,6 +53,7 @@ struct DevicePlan {
     UpdTile* tiles = nullptr;
     // host-side launch bookkeeping per level
     std::vector<int64_t> rowblk_ptr, tile_ptr;
+    std::vector<int64_t> tile_crit;   // per level: leading tiles that feed level l + 1
     std::vector<int32_t> level_maxw;
 };
 
@@ -91,6 +92,12 @@ struct spc_numeric {
     double* dinv = nullptr;         // inverses of the kPanel diagonal blocks
     int32_t* status_dev = nullptr;  // INT32_MAX = no failure
     double* work = nullptr;         // solve vector, n x work_cols
+    int32_t sched = 0;              // 0 level sets, 1 level sets with lookahead
+    hipStream_t bulk = nullptr;     // second stream for the lookahead schedule
+    std::vector<hipEvent_t> sync_ev; // per-level ordering events between the two streams
+    hipStream_t capture = nullptr;  // stream the solve sweeps are captured on
+    struct SolveGraph { int32_t nrhs; hipGraph_t graph; hipGraphExec_t exec; };
+    std::vector<SolveGraph> solve_graphs;
     int64_t work_cols = 0;
     hipStream_t stream = nullptr;
     int32_t host_status = 0;
@@ -114,5 +121,6 @@ void free_plan(DevicePlan* p);
 int32_t run_factor(spc_numeric* num, const double* values, hipStream_t stream);
 int32_t run_solve(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb, double* x,
                   int64_t ldx, hipStream_t stream);
+void drop_solve_graphs(spc_numeric* num);
 
 }  // namespace spc

@@ -9,9 +9,11 @@
 //             k_fwd_gemv  -- y[rows below] -= L21 y_s for every 64-row block
 //                            of every panel (atomic adds: sibling supernodes
 //                            share ancestor rows);
-//   backward: k_bwd_gemv  -- t_s += L21^T y[rows below], per 64-row block
-//                            with wave reductions;
+//   backward: k_bwd_gemv  -- t_s += L21^T y[rows below], per 64-row block,
+//                            one thread per column;
 //             k_bwd_diag  -- y_s = L11^{-T} (y_s - t_s), panels in reverse.
+// The level sweeps are captured once per right-hand-side count into a HIP
+// graph and replayed, so a solve costs three launches on the host.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -60,15 +62,16 @@ __device__ __forceinline__ void stage_block(double* __restrict__ T, double* __re
                                             const double* __restrict__ inv, int w, int ld,
                                             int npanel, int tid) {
     const int ww = w * w;
-    for (int e0 = tid; e0 < ww; e0 += 8 * 256) {
-        double v[8];
+    for (int e0 = tid; e0 < ww; e0 += 24 * 256) {
+        double v[24];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < 24; ++u) {
             const int e = e0 + u * 256, i = e % w, j = e / w;
-            v[u] = (e < ww && i >= j) ? L[i + (int64_t)j * ld] : 0.0;
+            const bool ok = e < ww && i >= j;
+            v[u] = L[ok ? i + (int64_t)j * ld : 0];
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < 24; ++u) {
             const int e = e0 + u * 256, i = e % w, j = e / w;
             if (e < ww && i >= j) T[((j * (2 * w - j - 1)) >> 1) + i] = v[u];
         }
@@ -85,22 +88,23 @@ __device__ __forceinline__ void stage_block(double* __restrict__ T, double* __re
 }
 
 // Forward, diagonal block: the block L11 (packed lower triangle) and its
-// 16 x 16 diagonal-block inverses are staged in LDS by the workgroup, then
-// wave 0 runs, for each 16-column panel p,
-//   t = y_p - L[p, <p] y_{<p}   (lanes j + 16 part split the dot products),
-//   y_p = inv(D_p) t.
+// 16 x 16 diagonal-block inverses are staged in LDS by the workgroup; then for
+// each 16-column panel p
+//   t = y_p - L[p, <p] y_{<p}   (thread (j, part) sums every 16th column k,
+//                                the 16 parts meet in LDS),
+//   y_p = inv(D_p) t            (16 lanes of wave 0).
 __global__ __launch_bounds__(256) void k_fwd_diag(const int32_t* __restrict__ level_sn, KArgs a,
                                                   const double* __restrict__ arena,
                                                   const double* __restrict__ dinv,
                                                   double* __restrict__ y, int64_t n, int nrhs) {
     extern __shared__ double sm[];
     __shared__ double ys[kMaxWidth + kPanel];
+    __shared__ double red[16][17];
     const int s = level_sn[blockIdx.x];
     const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
     const double* __restrict__ L = arena + a.sn_off[s];
     const double* __restrict__ inv = dinv + a.inv_off[s];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, j = lane & 15,
-              part = lane >> 4;
+    const int tid = threadIdx.x, j = tid & 15, part = tid >> 4;
     const int npanel = (w + kPanel - 1) / kPanel;
     auto cst = [w](int jj) { return (jj * (2 * w - jj - 1)) >> 1; };
     double* T = sm;
@@ -110,23 +114,27 @@ __global__ __launch_bounds__(256) void k_fwd_diag(const int32_t* __restrict__ le
         double* __restrict__ yc = y + (int64_t)c * n;
         for (int k = tid; k < w; k += 256) ys[k] = yc[first + k];
         __syncthreads();
-        if (wave == 0) {
-            for (int p = 0; p < npanel; ++p) {
-                const int j0 = p * kPanel, jb = min(kPanel, w - j0);
-                double acc = 0.0;
-                if (j < jb)
-                    for (int k = part; k < j0; k += 4) acc += T[cst(k) + j0 + j] * ys[k];
-                acc += __shfl_xor(acc, 16);
-                acc += __shfl_xor(acc, 32);
-                const double t = (j < jb) ? ys[j0 + j] - acc : 0.0;
+        for (int p = 0; p < npanel; ++p) {
+            const int j0 = p * kPanel, jb = min(kPanel, w - j0);
+            double acc = 0.0;
+            if (j < jb)
+                for (int k = part; k < j0; k += 16) acc += T[cst(k) + j0 + j] * ys[k];
+            red[part][j] = acc;
+            __syncthreads();
+            if (tid < kPanel) {
+                double tot = 0.0;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) tot += red[q][tid];
+                const double t = (tid < jb) ? ys[j0 + tid] - tot : 0.0;
+                red[0][tid] = t;  // wave 0 only: read back below in order
                 double out = 0.0;
 #pragma unroll
                 for (int k = 0; k < kPanel; ++k)
-                    out += I[p * kPanel * kPanel + j * kPanel + k] * __shfl(t, k);
-                if (lane < jb) ys[j0 + lane] = out;
+                    out += I[p * kPanel * kPanel + tid * kPanel + k] * red[0][k];
+                if (tid < jb) ys[j0 + tid] = out;
             }
+            __syncthreads();
         }
-        __syncthreads();
         for (int k = tid; k < w; k += 256) yc[first + k] = ys[k];
         __syncthreads();
     }
@@ -167,12 +175,15 @@ __global__ __launch_bounds__(256) void k_fwd_gemv(const RowBlock* __restrict__ w
 }
 
 // Backward, below the diagonal block: t_s[k] += sum_i L21[i][k] y[rows(i)]
-// over one 64-row block; wave q reduces the columns k = q, q + 4, ...
+// over one 64-row block: the gathered entries go to LDS, then thread k walks
+// column k of the block (its own contiguous 64 entries) and adds one partial
+// sum per column.
 __global__ __launch_bounds__(256) void k_bwd_gemv(const RowBlock* __restrict__ work, KArgs a,
                                                   const double* __restrict__ arena,
                                                   const double* __restrict__ y,
                                                   double* __restrict__ tacc, int64_t n,
                                                   int nrhs) {
+    __shared__ double xr[kTile];
     const RowBlock wb = work[blockIdx.x];
     const int s = wb.s;
     const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
@@ -180,24 +191,33 @@ __global__ __launch_bounds__(256) void k_bwd_gemv(const RowBlock* __restrict__ w
     const int r = (int)(a.rowptr[s + 1] - rp) - w;
     const double* __restrict__ P = arena + a.sn_off[s] + w;
     const int32_t* __restrict__ below = a.rows + rp + w;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int i = wb.rb * kTile + lane;
+    const int tid = threadIdx.x;
+    const int i0 = wb.rb * kTile, m = min(kTile, r - i0);
     for (int c = 0; c < nrhs; ++c) {
         const double* __restrict__ yc = y + (int64_t)c * n;
-        const double xr = (i < r) ? yc[below[i]] : 0.0;
-#pragma unroll 2
-        for (int k = wave; k < w; k += 4) {
-            double v = (i < r) ? P[i + (int64_t)k * ld] * xr : 0.0;
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-            if (lane == 0) unsafeAtomicAdd(tacc + (int64_t)c * n + first + k, v);
+        if (tid < kTile) xr[tid] = (tid < m) ? yc[below[i0 + tid]] : 0.0;
+        __syncthreads();
+        for (int k = tid; k < w; k += 256) {
+            const double* __restrict__ col = P + i0 + (int64_t)k * ld;
+            double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+            int i = 0;
+            for (; i + 4 <= m; i += 4) {
+                acc0 += col[i] * xr[i];
+                acc1 += col[i + 1] * xr[i + 1];
+                acc2 += col[i + 2] * xr[i + 2];
+                acc3 += col[i + 3] * xr[i + 3];
+            }
+            for (; i < m; ++i) acc0 += col[i] * xr[i];
+            unsafeAtomicAdd(tacc + (int64_t)c * n + first + k, (acc0 + acc1) + (acc2 + acc3));
         }
+        __syncthreads();
     }
 }
 
 // Backward, diagonal block: y_s = L11^{-T} (y_s - t_s), panels from the last:
 //   u = v_p - L[>p, p]^T y_{>p},   y_p = inv(D_p)^T u,
-// with L11 and the inverses staged in LDS as in k_fwd_diag.
+// with L11 and the inverses staged in LDS and the dot products split over
+// the workgroup as in k_fwd_diag.
 __global__ __launch_bounds__(256) void k_bwd_diag(const int32_t* __restrict__ level_sn, KArgs a,
                                                   const double* __restrict__ arena,
                                                   const double* __restrict__ dinv,
@@ -206,12 +226,12 @@ __global__ __launch_bounds__(256) void k_bwd_diag(const int32_t* __restrict__ le
                                                   int nrhs) {
     extern __shared__ double sm[];
     __shared__ double ys[kMaxWidth + kPanel];
+    __shared__ double red[16][17];
     const int s = level_sn[blockIdx.x];
     const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
     const double* __restrict__ L = arena + a.sn_off[s];
     const double* __restrict__ inv = dinv + a.inv_off[s];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, j = lane & 15,
-              part = lane >> 4;
+    const int tid = threadIdx.x, j = tid & 15, part = tid >> 4;
     const int npanel = (w + kPanel - 1) / kPanel;
     auto cst = [w](int jj) { return (jj * (2 * w - jj - 1)) >> 1; };
     double* T = sm;
@@ -222,24 +242,27 @@ __global__ __launch_bounds__(256) void k_bwd_diag(const int32_t* __restrict__ le
         const double* __restrict__ tc = tacc + (int64_t)c * n;
         for (int k = tid; k < w; k += 256) ys[k] = yc[first + k] - tc[first + k];
         __syncthreads();
-        if (wave == 0) {
-            for (int p = npanel - 1; p >= 0; --p) {
-                const int j0 = p * kPanel, jb = min(kPanel, w - j0);
-                double acc = 0.0;
-                if (j < jb)
-                    for (int k = j0 + kPanel + part; k < w; k += 4)
-                        acc += T[cst(j0 + j) + k] * ys[k];
-                acc += __shfl_xor(acc, 16);
-                acc += __shfl_xor(acc, 32);
-                const double u = (j < jb) ? ys[j0 + j] - acc : 0.0;
+        for (int p = npanel - 1; p >= 0; --p) {
+            const int j0 = p * kPanel, jb = min(kPanel, w - j0);
+            double acc = 0.0;
+            if (j < jb)
+                for (int k = j0 + kPanel + part; k < w; k += 16) acc += T[cst(j0 + j) + k] * ys[k];
+            red[part][j] = acc;
+            __syncthreads();
+            if (tid < kPanel) {
+                double tot = 0.0;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) tot += red[q][tid];
+                const double u = (tid < jb) ? ys[j0 + tid] - tot : 0.0;
+                red[0][tid] = u;
                 double out = 0.0;
 #pragma unroll
                 for (int k = 0; k < kPanel; ++k)
-                    out += I[p * kPanel * kPanel + k * kPanel + j] * __shfl(u, k);
-                if (lane < jb) ys[j0 + lane] = out;
+                    out += I[p * kPanel * kPanel + k * kPanel + tid] * red[0][k];
+                if (tid < jb) ys[j0 + tid] = out;
             }
+            __syncthreads();
         }
-        __syncthreads();
         for (int k = tid; k < w; k += 256) yc[first + k] = ys[k];
         __syncthreads();
     }
@@ -261,30 +284,19 @@ int32_t configure_solve_kernels() {
     return OK;
 }
 
-int32_t run_solve(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb, double* x,
-                  int64_t ldx, hipStream_t st) {
+namespace {
+
+// The level sweeps of one solve on the internal work vectors (y, t), as
+// enqueued on stream st.  Gather and scatter stay outside: they touch the
+// caller's b and x, which change from call to call.
+void enqueue_sweeps(spc_numeric* num, int32_t nrhs, double* y, double* tacc, hipStream_t st) {
     const Symbolic& S = num->sym->S;
     const DevicePlan* P = num->plan;
     const int64_t n = S.n;
-    if (n == 0 || nrhs == 0) return OK;
-    if (num->work_cols < nrhs) {
-        if (num->work) {
-            HIP_TRY(hipDeviceSynchronize());
-            HIP_TRY(hipFree(num->work));
-            num->work = nullptr;
-            num->work_cols = 0;
-        }
-        if (hipMalloc(&num->work, 2 * sizeof(double) * (size_t)n * nrhs) != hipSuccess)
-            return ERR_OOM;
-        num->work_cols = nrhs;
-    }
-    double* y = num->work;
-    double* tacc = num->work + (size_t)n * nrhs;
     const KArgs a = kargs(P);
     const int64_t total = n * nrhs;
     const int g = (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 4096));
     hipLaunchKernelGGL(k_zero, dim3(g), dim3(256), 0, st, tacc, total);
-    hipLaunchKernelGGL(k_gather, dim3(g), dim3(256), 0, st, b, ldb, P->perm, y, n, nrhs);
     const int32_t nl = (int32_t)S.level_ptr.size() - 1;
     for (int32_t l = 0; l < nl; ++l) {
         const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1];
@@ -304,10 +316,64 @@ int32_t run_solve(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb, 
                                P->rowblk + rb0, a, (const double*)num->arena,
                                (const double*)y, tacc, n, nrhs);
         hipLaunchKernelGGL(k_bwd_diag, dim3(n1 - n0), dim3(256), diag_lds(P->level_maxw[l]), st,
-                           P->level_sn + n0, a,
-                           (const double*)num->arena, (const double*)num->dinv, y,
-                           (const double*)tacc, n, nrhs);
+                           P->level_sn + n0, a, (const double*)num->arena,
+                           (const double*)num->dinv, y, (const double*)tacc, n, nrhs);
     }
+}
+
+}  // namespace
+
+void drop_solve_graphs(spc_numeric* num) {
+    for (auto& g : num->solve_graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    num->solve_graphs.clear();
+}
+
+int32_t run_solve(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb, double* x,
+                  int64_t ldx, hipStream_t st) {
+    const Symbolic& S = num->sym->S;
+    const DevicePlan* P = num->plan;
+    const int64_t n = S.n;
+    if (n == 0 || nrhs == 0) return OK;
+    if (num->work_cols < nrhs) {
+        if (num->work) {
+            HIP_TRY(hipDeviceSynchronize());
+            drop_solve_graphs(num);
+            HIP_TRY(hipFree(num->work));
+            num->work = nullptr;
+            num->work_cols = 0;
+        }
+        if (hipMalloc(&num->work, 2 * sizeof(double) * (size_t)n * nrhs) != hipSuccess)
+            return ERR_OOM;
+        num->work_cols = nrhs;
+    }
+    double* y = num->work;
+    double* tacc = num->work + (size_t)n * nrhs;
+    const int64_t total = n * nrhs;
+    const int g = (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_gather, dim3(g), dim3(256), 0, st, b, ldb, P->perm, y, n, nrhs);
+    // the sweeps replay from a graph captured once per right-hand-side count
+    spc_numeric::SolveGraph* sg = nullptr;
+    for (auto& e : num->solve_graphs)
+        if (e.nrhs == nrhs) sg = &e;
+    if (!sg) {
+        if (!num->capture) HIP_TRY(hipStreamCreateWithFlags(&num->capture, hipStreamNonBlocking));
+        spc_numeric::SolveGraph e;
+        e.nrhs = nrhs;
+        HIP_TRY(hipStreamBeginCapture(num->capture, hipStreamCaptureModeThreadLocal));
+        enqueue_sweeps(num, nrhs, y, tacc, num->capture);
+        const hipError_t ce = hipStreamEndCapture(num->capture, &e.graph);
+        if (ce != hipSuccess || !e.graph) return ERR_HIP;
+        if (hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(e.graph);
+            return ERR_HIP;
+        }
+        num->solve_graphs.push_back(e);
+        sg = &num->solve_graphs.back();
+    }
+    HIP_TRY(hipGraphLaunch(sg->exec, st));
     hipLaunchKernelGGL(k_scatter, dim3(g), dim3(256), 0, st, y, P->perm, x, ldx, n, nrhs);
     HIP_TRY(hipGetLastError());
     return OK;

@@ -23,10 +23,11 @@ def torch_dev():
     return torch
 
 
-def gpu_factor(p, cap=150, ratio=0.0):
+def gpu_factor(p, cap=150, ratio=0.0, sched=0):
     """Analyze + factor on cuda:0; returns (sym, num, values_tensor)."""
     torch = torch_dev()
-    sym = spchol.analyze(p.n, p.colptr, p.rowind, p.perm, sn_cap=cap, amalg_ratio=ratio)
+    sym = spchol.analyze(p.n, p.colptr, p.rowind, p.perm, sn_cap=cap, amalg_ratio=ratio,
+                         sched=sched)
     vals = torch.from_numpy(np.ascontiguousarray(p.values)).to("cuda:0")
     num = spchol.factor(sym, vals)
     return sym, num, vals

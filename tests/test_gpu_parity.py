@@ -76,12 +76,17 @@ CASES = ["dense1", "dense2", "dense5", "dense63", "dense64", "dense65", "dense15
          "elast27_6"]
 
 
-@pytest.mark.parametrize("name", CASES)
-def test_factor_and_solve_parity(name):
+SCHED_CASES = [(c, 0) for c in CASES] + [(c, 1) for c in ("dense300", "fig1", "random3",
+                                                          "lap2d_64", "lap3d_20_cap32",
+                                                          "lap3d_24", "elast27_6")]
+
+
+@pytest.mark.parametrize("name,sched", SCHED_CASES)
+def test_factor_and_solve_parity(name, sched):
     torch = torch_dev()
     p, cap, ratio = _case(name)
-    say("case", name, "n", p.n, "nnz", p.nnz, "cap", cap, "ratio", ratio)
-    sym, num, _ = gpu_factor(p, cap, ratio)
+    say("case", name, "sched", sched, "n", p.n, "nnz", p.nnz, "cap", cap, "ratio", ratio)
+    sym, num, _ = gpu_factor(p, cap, ratio, sched)
     assert num.status() == 0
     worst, rho, (osym, Lx, got) = compare_factor(p, num, cap, ratio, name)
     say("  worst/tol", worst, "residual", rho)
@@ -214,3 +219,28 @@ def test_memory_budget_rejects_large_factor():
     with pytest.raises(spchol.SpcError) as e:
         spchol.factor(sym, torch.from_numpy(p.values).to("cuda:0"))
     assert e.value.status == spchol.SPC_ERR_OOM
+
+
+def test_solve_graph_replays_match():
+    """The solve sweeps replay from a captured graph: repeated solves, with
+    other right-hand sides and a refactorization between them, all give the
+    oracle's answer (to rounding: atomic accumulation order may vary)."""
+    torch = torch_dev()
+    p = inputs.make_grid_problem("lap", (14, 14, 14), 31, sigma=1.0, shift=1e-3, nrhs=3)
+    sym, num, vals = gpu_factor(p, 150, 0.1)
+    out = oracle.run(p, cap=150, ratio=0.1)
+    xo = out["x"]
+    b = torch.from_numpy(np.ascontiguousarray(p.rhs)).to("cuda:0")
+    scale = np.abs(xo).max()
+    other = torch.randn(p.n, dtype=torch.float64, device="cuda:0")
+    for rep in range(5):
+        x = num.solve(b).cpu().numpy()
+        np.testing.assert_allclose(x, xo, rtol=0, atol=1e-9 * scale)
+        num.solve(other)                       # a different graph (nrhs = 1)
+        x1 = num.solve(b[:, 1]).cpu().numpy()  # and a one-column replay
+        np.testing.assert_allclose(x1, xo[:, 1], rtol=0, atol=1e-9 * scale)
+        if rep == 2:
+            num.refactor(vals)                 # same values: same factor
+            assert num.status() == 0
+    num.free()
+    sym.free()

@@ -44,7 +44,7 @@ def test_analyze_rejects_bad_arguments():
     with pytest.raises(spchol.SpcError) as e:
         spchol.analyze(2, cp, ri, perm=[0, 0])
     assert e.value.status == spchol.SPC_ERR_ARG
-    for kw in (dict(sn_cap=0), dict(sn_cap=151), dict(amalg_ratio=-0.1), dict(sched=7),
+    for kw in (dict(sn_cap=0), dict(sn_cap=151), dict(amalg_ratio=-0.1), dict(sched=7), dict(sched=-1),
                dict(mem_budget_bytes=-1)):
         with pytest.raises(spchol.SpcError) as e:
             spchol.analyze(2, cp, ri, **kw)
