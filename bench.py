@@ -96,7 +96,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="lap3d_7pt_64")
     ap.add_argument("--solves", type=int, default=200)
-    ap.add_argument("--sched", type=int, default=1, help="0 level sets, 1 with lookahead")
+    ap.add_argument("--sched", type=int, default=1, choices=(0, 1, 2),
+                    help="0 level sets, 1 with lookahead, 2 device task queue")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", default=None,
                     help="grid of the bounded oracle sample (default: 40^3 for 3D workloads, "
@@ -192,14 +193,21 @@ def main():
     log("solve p50 %.3f ms p99 %.3f ms, backward error %.2e" %
         (np.percentile(lat, 50), np.percentile(lat, 99), eta))
 
-    upd_ms = kern["update"] / args.steps
-    upd_launch = launches["update"] / args.steps
-    achieved = uflops / (upd_ms * 1e-3) / 1e12 if upd_ms > 0 else 0.0
-    roofline = {"kernel": "k_update (FP64 MFMA SYRK tile + relative-index scatter)",
+    if args.sched == 2:
+        # one persistent launch runs every F, T and U task of the factorization
+        kname, kcls, kflops = ("k_sched (persistent task queue: POTRF, TRSM, FP64 MFMA update "
+                               "tiles + scatter)", "tasks", F)
+    else:
+        kname, kcls, kflops = ("k_update (FP64 MFMA SYRK tile + relative-index scatter)",
+                               "update", uflops)
+    k_ms = kern[kcls] / args.steps
+    k_launch = launches[kcls] / args.steps
+    achieved = kflops / (k_ms * 1e-3) / 1e12 if k_ms > 0 else 0.0
+    roofline = {"kernel": kname,
                 "bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": None,
-                "algorithmic_flops_per_launch": uflops / max(upd_launch, 1),
-                "avg_launch_ms": upd_ms / max(upd_launch, 1), "launches_per_factor": upd_launch}
+                "algorithmic_flops_per_launch": kflops / max(k_launch, 1),
+                "avg_launch_ms": k_ms / max(k_launch, 1), "launches_per_factor": k_launch}
 
     out = {
         "metric": METRIC, "value": gflops, "unit": "GFLOP/s", "n_gpus": 1,
@@ -210,7 +218,8 @@ def main():
                    "nnz_lower": p.nnz, "nnz_L": info["nnz_l"], "flops_F": F,
                    "flops_stored": info["flops_stored"], "sn_cap": 150, "amalg_ratio": amalg,
                    "nsup": info["nsup"], "levels": info["nlevels"], "nrhs": 1,
-                   "schedule": ["level sets", "level sets + lookahead"][args.sched],
+                   "schedule": ["level sets", "level sets + lookahead",
+                                "device task queue"][args.sched],
                    "precision": "fp64"},
         "factor_ms": factor_ms, "factor_ms_min": float(min(f_ms)),
         "solve_ms_in_step": float(np.mean(s_ms)),

@@ -69,9 +69,16 @@ enum {
 typedef struct spc_options {
     int32_t sn_cap;           /* maximum supernode width, 1..150 columns; default 150 */
     int32_t sched;            /* 0 = level by level; 1 = level by level with a
-                                 one-level lookahead on two streams         */
+                                 one-level lookahead on two streams; 2 = device task
+                                 queue (dependency counters, Section IV)        */
     double amalg_ratio;       /* relaxed amalgamation zero ratio; 0 = off (default) */
     int64_t mem_budget_bytes; /* device bytes a factor may hold; 0 = no limit       */
+    int64_t spin_limit;       /* sched 2: bound on every device wait, in microseconds;
+                                 past it the factorization stops and its status
+                                 reads SPC_ERR_TIMEOUT; 0 = default (ten seconds) */
+    int32_t debug_flags;      /* bit 0: withhold one dependency count so that the
+                                 bounded wait fires (testing only); default 0    */
+    int32_t reserved;
 } spc_options;
 
 typedef struct spc_symbolic spc_symbolic;
@@ -94,7 +101,8 @@ typedef struct spc_symbolic_info {
     int32_t max_below;     /* most rows below a diagonal block                      */
 } spc_symbolic_info;
 
-/* Fills *opt with the defaults (sn_cap 150, sched 0, no amalgamation, no budget). */
+/* Fills *opt with the defaults (sn_cap 150, sched 0, no amalgamation, no budget,
+ * default spin limit, no debug flags). */
 void spc_default_options(spc_options* opt);
 
 /* Symbolic analysis on the host (no device work).  colptr/rowind/perm are
@@ -127,6 +135,20 @@ spc_status spc_symbolic_export_rows(const spc_symbolic* sym, int64_t* rowptr, in
  * position in the target's row list.  Any output may be NULL. */
 spc_status spc_symbolic_export_pairs(const spc_symbolic* sym, int32_t* src, int32_t* tgt,
                                      int32_t* seg, int64_t* rel_off, int32_t* rel);
+
+/* Task order of the device task-queue schedule (sched 2), computed on the
+ * host for `workers` device workers (> 0).  The tasks follow the paper's
+ * factorization, update and aggregation tasks (Section III-A) at tile
+ * granularity: kind 0 = F(s) diagonal factorization of supernode s, kind 1 =
+ * T(s, a) panel solve of 64-row block a of s, kind 2 = U(s, a, b) the 64 x 64
+ * update tile (row block a, column block b, a >= b) of s scatter-added into
+ * its targets.  cnt0[t] is the initial dependency counter of F(t)
+ * (Section IV): the number of (update tile, distinct target t) pairs.
+ * *ntasks receives the task count; tasks (4 int32 per task: kind, s, a, b, in
+ * start order) and cnt0 (nsup entries) may be NULL to query the size first.
+ * Host only; needs no device. */
+spc_status spc_symbolic_export_tasks(const spc_symbolic* sym, int32_t workers, int64_t* ntasks,
+                                     int32_t* tasks, int32_t* cnt0);
 
 /* Releases the handle.  Returns SPC_ERR_BUSY (and frees nothing) while a
  * numeric factor created from it is alive.  NULL is accepted. */
@@ -167,12 +189,13 @@ spc_status spc_factor_export(spc_numeric* num, int64_t* Sp, int32_t* Si, double*
 /* Per-kernel-class device times of the most recent factorization, measured
  * with HIP events recorded on the factor's stream around every launch while
  * timing is enabled (spc_numeric_set_timing).  Classes: 0 value load (fill +
- * load), 1 diagonal factorization, 2 panel solve, 3 update + scatter.
+ * load), 1 diagonal factorization, 2 panel solve, 3 update + scatter, 4 the
+ * persistent task-queue kernel (schedule 2: all of 1-3 in one launch).
  * ms[c] is the summed duration of class c, launches[c] its launch count.
  * Synchronizes the stream.  SPC_ERR_ARG if timing was never enabled. */
 typedef struct spc_kernel_times {
-    double ms[4];
-    int64_t launches[4];
+    double ms[5];
+    int64_t launches[5];
     double total_ms; /* from the first to the last recorded event */
 } spc_kernel_times;
 

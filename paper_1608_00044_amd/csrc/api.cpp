@@ -22,6 +22,9 @@ void spc_default_options(spc_options* opt) {
     opt->sched = 0;
     opt->amalg_ratio = 0.0;
     opt->mem_budget_bytes = 0;
+    opt->spin_limit = 0;
+    opt->debug_flags = 0;
+    opt->reserved = 0;
 }
 
 const char* spc_status_string(spc_status st) {
@@ -48,7 +51,8 @@ spc_status spc_analyze(int64_t n, const int64_t* colptr, const int32_t* rowind,
     spc_default_options(&o);
     if (opt) o = *opt;
     if (o.sn_cap < 1 || o.sn_cap > kMaxWidth) return SPC_ERR_ARG;
-    if (o.sched != 0 && o.sched != 1) return SPC_ERR_ARG;
+    if (o.sched < 0 || o.sched > 2) return SPC_ERR_ARG;
+    if (o.spin_limit < 0) return SPC_ERR_ARG;
     if (!(o.amalg_ratio >= 0.0 && o.amalg_ratio <= 1.0)) return SPC_ERR_ARG;
     if (o.mem_budget_bytes < 0) return SPC_ERR_ARG;
     spc_symbolic* h = new (std::nothrow) spc_symbolic();
@@ -57,6 +61,8 @@ spc_status spc_analyze(int64_t n, const int64_t* colptr, const int32_t* rowind,
     so.sn_cap = o.sn_cap;
     so.amalg_ratio = o.amalg_ratio;
     so.sched = o.sched;
+    so.spin_limit = o.spin_limit;
+    so.debug_flags = o.debug_flags;
     int32_t st;
     try {
         st = analyze(n, colptr, rowind, perm, so, &h->S);
@@ -127,6 +133,25 @@ spc_status spc_symbolic_export_pairs(const spc_symbolic* sym, int32_t* src, int3
     return SPC_OK;
 }
 
+spc_status spc_symbolic_export_tasks(const spc_symbolic* sym, int32_t workers, int64_t* ntasks,
+                                     int32_t* tasks, int32_t* cnt0) {
+    if (!sym || !ntasks || workers <= 0) return SPC_ERR_ARG;
+    std::vector<Task> order;
+    std::vector<int32_t> c0, rb_base;
+    const int32_t st = build_task_order(sym->S, workers, order, c0, rb_base);
+    if (st != OK) return st;
+    *ntasks = (int64_t)order.size();
+    if (tasks)
+        for (size_t i = 0; i < order.size(); ++i) {
+            tasks[4 * i] = order[i].kind;
+            tasks[4 * i + 1] = order[i].s;
+            tasks[4 * i + 2] = order[i].a;
+            tasks[4 * i + 3] = order[i].b;
+        }
+    if (cnt0 && !c0.empty()) std::memcpy(cnt0, c0.data(), sizeof(int32_t) * c0.size());
+    return SPC_OK;
+}
+
 spc_status spc_symbolic_free(spc_symbolic* sym) {
     if (!sym) return SPC_OK;
     {
@@ -171,6 +196,17 @@ static spc_status alloc_numeric(spc_symbolic* sym, spc_numeric** out) {
         return SPC_ERR_OOM;
     }
     num->sched = S.opt.sched;
+    if (num->sched == 2) {
+        const size_t ints = 2 * (size_t)S.nsup + (size_t)plan->nrowblk + 4;
+        if (hipMalloc(&num->sched_state, ints * sizeof(int32_t)) != hipSuccess) {
+            (void)hipFree(num->arena);
+            (void)hipFree(num->status_dev);
+            (void)hipFree(num->dinv);
+            delete num;
+            return SPC_ERR_OOM;
+        }
+        num->spin_limit = S.opt.spin_limit > 0 ? S.opt.spin_limit : (int64_t)10000000;
+    }
     if (num->sched == 1 &&
         hipStreamCreateWithFlags(&num->bulk, hipStreamNonBlocking) != hipSuccess) {
         (void)hipFree(num->arena);
@@ -223,6 +259,15 @@ spc_status spc_numeric_status(spc_numeric* num) {
     if (hipMemcpy(&v, num->status_dev, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
         return SPC_ERR_HIP;
     num->host_status = (v == INT32_MAX) ? 0 : v;
+    if (num->sched_state) {
+        const Symbolic& S = num->sym->S;
+        int32_t err = 0;
+        const size_t at = 2 * (size_t)S.nsup + (size_t)num->plan->nrowblk + 2;
+        if (hipMemcpy(&err, num->sched_state + at, sizeof(int32_t), hipMemcpyDeviceToHost) !=
+            hipSuccess)
+            return SPC_ERR_HIP;
+        if (err) num->host_status = SPC_ERR_TIMEOUT;
+    }
     num->status_known = true;
     return num->host_status;
 }
@@ -293,7 +338,7 @@ spc_status spc_numeric_get_timing(spc_numeric* num, spc_kernel_times* out) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, num->events[m.a], num->events[m.b]) != hipSuccess)
             return SPC_ERR_HIP;
-        if (m.cls >= 0 && m.cls < 4) {
+        if (m.cls >= 0 && m.cls < 5) {
             out->ms[m.cls] += ms;
             out->launches[m.cls] += 1;
         }
@@ -320,6 +365,7 @@ void spc_numeric_free(spc_numeric* num) {
     (void)hipFree(num->arena);
     (void)hipFree(num->status_dev);
     (void)hipFree(num->dinv);
+    if (num->sched_state) (void)hipFree(num->sched_state);
     drop_solve_graphs(num);
     if (num->capture) (void)hipStreamDestroy(num->capture);
     if (num->work) (void)hipFree(num->work);

@@ -187,8 +187,8 @@ __device__ __forceinline__ void trailing_block(double* __restrict__ T, Cst cst, 
     for (int q = 0; q < 4; ++q) T[ci[q]] = acc[q];
 }
 
-// One workgroup (4 waves) per supernode of the level.  The w x w diagonal
-// block lives in LDS as a packed lower triangle, column major: entry (i, j)
+// Diagonal factorization of supernode s by one workgroup of 4 waves.  The
+// w x w diagonal block lives in LDS (T) as a packed lower triangle, column major: entry (i, j)
 // at cst(j) + i, plus one dummy slot that absorbs masked accesses so the
 // inner loops stay branch free.  Right-looking by 16-column panels with a
 // one-panel lookahead:
@@ -203,14 +203,12 @@ __device__ __forceinline__ void trailing_block(double* __restrict__ T, Cst cst, 
 // Global loads and stores of the block are issued many per thread at a time.
 // A pivot that is not positive records its global column with atomicMin on
 // *status; the smallest failing column wins.
-__global__ __launch_bounds__(kPotrfThreads) void k_potrf(const int32_t* __restrict__ level_sn,
-                                                         KArgs a, double* __restrict__ arena,
-                                                         double* __restrict__ dinv,
-                                                         int32_t* __restrict__ status) {
-    extern __shared__ double T[];
+__device__ __forceinline__ void potrf_task(int s, const KArgs& a, double* __restrict__ arena,
+                                           double* __restrict__ dinv,
+                                           int32_t* __restrict__ status,
+                                           double* __restrict__ T) {
     __shared__ double Dinv[kPanel * kPanel];  // row major: Dinv[r * 16 + c] = inv(D)[r][c]
     __shared__ double Dt[kPanel * kDs];       // dense panel block, row major
-    const int s = level_sn[blockIdx.x];
     const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
     double* __restrict__ base = arena + a.sn_off[s];
     double* __restrict__ inv_g = dinv + a.inv_off[s];
@@ -290,6 +288,15 @@ __global__ __launch_bounds__(kPotrfThreads) void k_potrf(const int32_t* __restri
             if (e < ww && i >= j) base[i + (int64_t)j * ld] = T[cst(j) + i];
         }
     }
+}
+
+// Level-set form: one workgroup per supernode of the level.
+__global__ __launch_bounds__(kPotrfThreads) void k_potrf(const int32_t* __restrict__ level_sn,
+                                                         KArgs a, double* __restrict__ arena,
+                                                         double* __restrict__ dinv,
+                                                         int32_t* __restrict__ status) {
+    extern __shared__ double T[];
+    potrf_task(level_sn[blockIdx.x], a, arena, dinv, status, T);
 }
 
 // ---------------------------------------------------------------------------
@@ -389,11 +396,9 @@ __device__ __forceinline__ void trsm_rows(const double* __restrict__ L, int ld,
 // 16-column panels with the inverses of the diagonal blocks from k_potrf.
 constexpr int kTrsmThreads = 256;
 
-__global__ __launch_bounds__(kTrsmThreads) void k_trsm(const RowBlock* __restrict__ work, KArgs a,
-                                                       double* __restrict__ arena,
-                                                       const double* __restrict__ dinv) {
+__device__ __forceinline__ void trsm_task(RowBlock wb, const KArgs& a, double* __restrict__ arena,
+                                          const double* __restrict__ dinv) {
     __shared__ double trs[kTrsmThreads / 64][16 * 17];
-    const RowBlock wb = work[blockIdx.x];
     const int s = wb.s;
     const int w = a.sn_w[s], ld = a.sn_ld[s];
     const int r = (int)(a.rowptr[s + 1] - a.rowptr[s]) - w;
@@ -416,6 +421,12 @@ __global__ __launch_bounds__(kTrsmThreads) void k_trsm(const RowBlock* __restric
         case 9: trsm_rows<9>(L, ld, inv, P, w, r, row0, tr, lane); break;
         default: trsm_rows<10>(L, ld, inv, P, w, r, row0, tr, lane); break;
     }
+}
+
+__global__ __launch_bounds__(kTrsmThreads) void k_trsm(const RowBlock* __restrict__ work, KArgs a,
+                                                       double* __restrict__ arena,
+                                                       const double* __restrict__ dinv) {
+    trsm_task(work[blockIdx.x], a, arena, dinv);
 }
 
 static_assert(kMaxWidth <= 10 * kPanel, "k_trsm instantiates at most 10 panels");
@@ -448,16 +459,18 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
 // row: target block + rel[i] + (row(c) - first(t)) * ld(t), with a plain
 // read-modify-write when the pair's target has no other source in this
 // level and an atomic add otherwise.
-__global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tiles, int64_t ntiles,
-                                                KArgs a, const uint8_t* __restrict__ pair_excl,
-                                                double* __restrict__ arena) {
+// Update tile by one workgroup of 4 waves.  If coltgt is given (an LDS array
+// of kTile entries), it receives each column's target supernode (-1 past the
+// panel), in non-decreasing order.
+__device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
+                                            const uint8_t* __restrict__ pair_excl,
+                                            double* __restrict__ arena, int* coltgt) {
     __shared__ double lds[2 * 2 * kChunk * kLdsStride > kTile * kCtPad
                               ? 2 * 2 * kChunk * kLdsStride
                               : kTile * kCtPad];
     __shared__ int64_t colbase[kTile];
     __shared__ int64_t relbase[kTile];
     __shared__ int colexcl[kTile];
-    const UpdTile tile = tiles[xcd_tile(blockIdx.x, ntiles)];
     const int s = tile.s;
     const int w = a.sn_w[s], ld = a.sn_ld[s];
     const int64_t rp = a.rowptr[s];
@@ -498,10 +511,12 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
     int my_excl = 0;
     if (tid < kTile) {
         const int gc = c0 + tid;
+        if (coltgt) coltgt[tid] = -1;
         if (gc < r) {
             const int64_t at = rp + w + gc;
             const int p = a.rowpair[at];
             const int t = a.pair_tgt[p];
+            if (coltgt) coltgt[tid] = t;
             my_colbase = a.sn_off[t] + (int64_t)(a.rows[at] - a.sn_first[t]) * a.sn_ld[t];
             my_relbase = a.pair_rel[p] - a.pair_seg[p];
             my_excl = pair_excl ? pair_excl[p] : 0;
@@ -574,6 +589,124 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
         const double v = Ct[c * kCtPad + i];
         if (colexcl[c]) arena[dst[u]] = old[u] - v;
         else unsafeAtomicAdd(arena + dst[u], -v);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tiles, int64_t ntiles,
+                                                KArgs a, const uint8_t* __restrict__ pair_excl,
+                                                double* __restrict__ arena) {
+    update_task(tiles[xcd_tile(blockIdx.x, ntiles)], a, pair_excl, arena, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// Task-queue schedule: one persistent kernel, dependency counters in HBM
+// ---------------------------------------------------------------------------
+//
+// The paper's dynamic scheduling (Section IV) on one GPU: every workgroup is
+// a worker that takes the next task of a fixed topological order with an
+// atomic ticket, waits until the task's inputs are done, runs it and
+// signals its successors:
+//   F(s)       waits until cntF[s] == 0 (all updates into s have landed);
+//              runs the diagonal factorization; sets doneF[s];
+//   T(s, b)    waits for doneF[s]; solves row block b; sets doneT;
+//   U(s, i, j) waits for doneT of row blocks i and j; computes the tile and
+//              scatter-adds it (atomic adds); decrements cntF[t] once for
+//              every distinct target t of its columns.
+// The lowest unfinished ticket always has its inputs done, so the queue
+// cannot deadlock whatever the number of resident workers.  Every wait is
+// bounded: past the deadline the worker raises the abort flag and records
+// the error, and every worker exits at its next poll.
+//
+// State layout (int32): cntF[nsup], doneF[nsup], doneT[nrowblk], ctrl[4]
+// with ctrl = {ticket, abort, error, unused}.
+
+__global__ void k_sched_reset(const int32_t* __restrict__ cnt0, int32_t* __restrict__ state,
+                              int64_t nsup, int64_t total) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x)
+        state[i] = i < nsup ? cnt0[i] : 0;
+}
+
+__device__ __forceinline__ int32_t load_acquire(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bounded wait of one thread until *p == want.  Returns false on abort.
+__device__ bool wait_eq(const int32_t* p, int32_t want, int32_t* ctrl, uint64_t deadline) {
+    for (;;) {
+        if (load_acquire(p) == want) return true;
+        if (__hip_atomic_load(ctrl + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+        if (wall_clock64() > deadline) {
+            __hip_atomic_store(ctrl + 2, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(ctrl + 1, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(4);
+    }
+}
+
+constexpr int kSchedThreads = 256;
+static_assert(kSchedThreads == kPotrfThreads && kSchedThreads == kTrsmThreads,
+              "one workgroup shape runs every task kind");
+
+__global__ __launch_bounds__(kSchedThreads) void k_sched(
+    const Task* __restrict__ tasks, int64_t ntasks, const int32_t* __restrict__ rb_base, KArgs a,
+    double* __restrict__ arena, double* __restrict__ dinv, int32_t* __restrict__ status,
+    int32_t* __restrict__ state, int64_t nsup, int64_t nrowblk, uint64_t wait_ticks) {
+    extern __shared__ double T[];
+    __shared__ int32_t sh_ticket;
+    __shared__ int coltgt[kTile];
+    int32_t* cntF = state;
+    int32_t* doneF = state + nsup;
+    int32_t* doneT = doneF + nsup;
+    int32_t* ctrl = doneT + nrowblk;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) {
+            int32_t t = atomicAdd(ctrl, 1);
+            if (t < ntasks) {
+                const Task tk = tasks[t];
+                const uint64_t deadline = wall_clock64() + wait_ticks;
+                bool ok;
+                if (tk.kind == kTaskF) {
+                    ok = wait_eq(cntF + tk.s, 0, ctrl, deadline);
+                } else if (tk.kind == kTaskT) {
+                    ok = wait_eq(doneF + tk.s, 1, ctrl, deadline);
+                } else {
+                    const int32_t rb = rb_base[tk.s];
+                    ok = wait_eq(doneT + rb + tk.a, 1, ctrl, deadline) &&
+                         (tk.a == tk.b || wait_eq(doneT + rb + tk.b, 1, ctrl, deadline));
+                }
+                if (!ok) t = -1;
+            }
+            sh_ticket = t;
+        }
+        __syncthreads();
+        const int32_t t = sh_ticket;
+        if (t < 0 || t >= ntasks) break;
+        __threadfence();  // acquire for every wave: inputs written by other workers
+        const Task tk = tasks[t];
+        if (tk.kind == kTaskF) {
+            potrf_task(tk.s, a, arena, dinv, status, T);
+        } else if (tk.kind == kTaskT) {
+            trsm_task(RowBlock{tk.s, tk.a}, a, arena, dinv);
+        } else {
+            update_task(UpdTile{tk.s, tk.a, tk.b}, a, nullptr, arena, coltgt);
+        }
+        __threadfence();  // release: this task's results before its signal
+        __syncthreads();
+        if (tk.kind == kTaskF) {
+            if (tid == 0) __hip_atomic_store(doneF + tk.s, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (tk.kind == kTaskT) {
+            if (tid == 0)
+                __hip_atomic_store(doneT + rb_base[tk.s] + tk.a, 1, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        } else if (tid < kTile) {
+            const int tg = coltgt[tid];
+            if (tg >= 0 && (tid == 0 || coltgt[tid - 1] != tg))
+                __hip_atomic_fetch_add(cntF + tg, -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
     }
 }
 
@@ -676,7 +809,29 @@ int32_t run_factor(spc_numeric* num, const double* values, hipStream_t st) {
                            P->slot, num->arena, S.nnz_a);
     mark_end(num, st, 0, ev);
     const int32_t nl = (int32_t)S.level_ptr.size() - 1;
-    if (num->sched == 0 || nl < 2) {
+    if (num->sched == 2) {
+        const int64_t total = 2 * S.nsup + P->nrowblk + 4;
+        hipLaunchKernelGGL(k_sched_reset, dim3(grid_for(total, 256)), dim3(256), 0, st, P->cnt0,
+                           num->sched_state, S.nsup, total);
+        if (P->ntasks > 0) {
+            const size_t lds_tri = ((size_t)P->max_w * (P->max_w + 1) / 2 + 1) * sizeof(double);
+            int per_cu = 0, ncu = 0, dev = 0, clock_khz = 0;
+            HIP_TRY(hipGetDevice(&dev));
+            HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+            HIP_TRY(hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev));
+            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sched, kSchedThreads,
+                                                                lds_tri));
+            const int64_t workers =
+                std::min<int64_t>(P->ntasks, (int64_t)std::max(1, ncu) * std::max(1, per_cu));
+            const uint64_t ticks = (uint64_t)num->spin_limit * (uint64_t)std::max(1, clock_khz) / 1000;
+            ev = mark_begin(num, st);
+            hipLaunchKernelGGL(k_sched, dim3((unsigned)workers), dim3(kSchedThreads), lds_tri, st,
+                               (const Task*)P->tasks, P->ntasks, (const int32_t*)P->rb_base, a,
+                               num->arena, num->dinv, num->status_dev, num->sched_state, S.nsup,
+                               P->nrowblk, ticks);
+            mark_end(num, st, 4, ev);
+        }
+    } else if (num->sched == 0 || nl < 2) {
         for (int32_t l = 0; l < nl; ++l) {
             launch_ft(num, P, S, a, l, st);
             launch_update(num, P, a, P->tile_ptr[l], P->tile_ptr[l + 1], true, st);
@@ -720,6 +875,9 @@ int32_t configure_kernels() {
     result = configure_solve_kernels();
     const int lds_max = (int)(((size_t)kMaxWidth * (kMaxWidth + 1) / 2 + 1) * sizeof(double));
     if (hipFuncSetAttribute((const void*)k_potrf, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds_max) != hipSuccess)
+        result = ERR_HIP;
+    if (hipFuncSetAttribute((const void*)k_sched, hipFuncAttributeMaxDynamicSharedMemorySize,
                             lds_max) != hipSuccess)
         result = ERR_HIP;
     return result;

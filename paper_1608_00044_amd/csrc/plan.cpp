@@ -24,7 +24,7 @@ struct Layout {
 
 struct PlanOffsets {
     size_t sn_first, sn_w, sn_ld, sn_off, inv_off, rowptr, rows, rowpair, slot, perm, pair_tgt,
-        pair_seg, pair_rel, pair_excl, rel, level_sn, rowblk, tiles;
+        pair_seg, pair_rel, pair_excl, rel, level_sn, rowblk, tiles, tasks, cnt0, rb_base;
     size_t total;
 };
 
@@ -68,6 +68,7 @@ PlanOffsets plan_layout(const Symbolic& S, const std::vector<int64_t>& rb_ptr,
     o.level_sn = L.add<int32_t>(S.level_sn.size());
     o.rowblk = L.add<RowBlock>((size_t)rb_ptr.back());
     o.tiles = L.add<UpdTile>((size_t)tl_ptr.back());
+    o.tasks = o.cnt0 = o.rb_base = 0;
     o.total = L.total;
     return o;
 }
@@ -98,6 +99,25 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
     P->device = dev;
     count_work(S, P->rowblk_ptr, P->tile_ptr);
     PlanOffsets o = plan_layout(S, P->rowblk_ptr, P->tile_ptr);
+    // task-queue schedule: task order, dependency counts, row-block bases
+    std::vector<Task> tasks;
+    std::vector<int32_t> cnt0, rb_base;
+    if (S.opt.sched == 2) {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            ncu = 256;
+        int32_t st = build_task_order(S, ncu, tasks, cnt0, rb_base);
+        if (st != OK) { delete P; return st; }
+        if ((S.opt.debug_flags & 1) && S.nsup > 0) cnt0[S.nsup - 1] += 1;
+        Layout L2;
+        L2.total = o.total;
+        o.tasks = L2.add<Task>(tasks.size());
+        o.cnt0 = L2.add<int32_t>(cnt0.size());
+        o.rb_base = L2.add<int32_t>(rb_base.size());
+        o.total = L2.total;
+        P->ntasks = (int64_t)tasks.size();
+        P->nrowblk = rb_base.empty() ? 0 : rb_base.back();
+    }
     std::vector<char> h(o.total ? o.total : 1, 0);
     auto put = [&](size_t at, const void* src, size_t bytes) {
         if (bytes) std::memcpy(h.data() + at, src, bytes);
@@ -204,6 +224,10 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
         put(o.rowblk, rb.data(), rb.size() * sizeof(RowBlock));
         put(o.tiles, tl.data(), tl.size() * sizeof(UpdTile));
     }
+    if (!tasks.empty()) put(o.tasks, tasks.data(), tasks.size() * sizeof(Task));
+    if (!cnt0.empty()) put(o.cnt0, cnt0.data(), cnt0.size() * 4);
+    if (!rb_base.empty()) put(o.rb_base, rb_base.data(), rb_base.size() * 4);
+    P->max_w = S.max_w;
     void* d = nullptr;
     if (hipMalloc(&d, o.total ? o.total : 256) != hipSuccess) { delete P; return ERR_OOM; }
     if (hipMemcpy(d, h.data(), o.total, hipMemcpyHostToDevice) != hipSuccess) {
@@ -232,6 +256,11 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
     P->level_sn = (int32_t*)(base + o.level_sn);
     P->rowblk = (RowBlock*)(base + o.rowblk);
     P->tiles = (UpdTile*)(base + o.tiles);
+    if (S.opt.sched == 2) {
+        P->tasks = (Task*)(base + o.tasks);
+        P->cnt0 = (int32_t*)(base + o.cnt0);
+        P->rb_base = (int32_t*)(base + o.rb_base);
+    }
     sym->plans.push_back(P);
     *out = P;
     return OK;

@@ -21,6 +21,10 @@ constexpr int kMaxWidth = 150;
 // kPanel x kPanel diagonal block is kept for the panel and triangular solves.
 constexpr int kPanel = 16;
 
+// Device task-queue schedule: task kinds and the task record.
+enum : int32_t { kTaskF = 0, kTaskT = 1, kTaskU = 2 };
+struct Task { int32_t s; int16_t a, b; int32_t kind; };
+
 // One update tile: rows [bi*64, bi*64+64) x columns [bj*64, bj*64+64) of the
 // lower triangle of P P^T, P = the below-diagonal panel of source supernode s.
 struct UpdTile { int32_t s; int16_t bi, bj; };
@@ -51,6 +55,13 @@ struct DevicePlan {
     int32_t* level_sn = nullptr;
     RowBlock* rowblk = nullptr;
     UpdTile* tiles = nullptr;
+    // device task-queue schedule (only when analyzed with sched 2)
+    Task* tasks = nullptr;
+    int64_t ntasks = 0;
+    int32_t* cnt0 = nullptr;     // per supernode: update tiles that scatter into it
+    int32_t* rb_base = nullptr;  // per supernode: index of its first panel row block
+    int64_t nrowblk = 0;
+    int32_t max_w = 0;
     // host-side launch bookkeeping per level
     std::vector<int64_t> rowblk_ptr, tile_ptr;
     std::vector<int64_t> tile_crit;   // per level: leading tiles that feed level l + 1
@@ -96,6 +107,8 @@ struct spc_numeric {
     hipStream_t bulk = nullptr;     // second stream for the lookahead schedule
     std::vector<hipEvent_t> sync_ev; // per-level ordering events between the two streams
     hipStream_t capture = nullptr;  // stream the solve sweeps are captured on
+    int32_t* sched_state = nullptr; // task-queue counters: cntF, doneF, doneT, ticket/abort/err
+    int64_t spin_limit = 0;
     struct SolveGraph { int32_t nrhs; hipGraph_t graph; hipGraphExec_t exec; };
     std::vector<SolveGraph> solve_graphs;
     int64_t work_cols = 0;
@@ -114,6 +127,8 @@ struct spc_numeric {
 namespace spc {
 
 size_t plan_bytes(const Symbolic& S);
+int32_t build_task_order(const Symbolic& S, int workers, std::vector<Task>& order,
+                         std::vector<int32_t>& cnt0, std::vector<int32_t>& rb_base);
 int64_t inverse_blocks_elems(const Symbolic& S);
 KArgs kargs(const DevicePlan* P);
 int32_t get_plan(spc_symbolic* sym, DevicePlan** out);

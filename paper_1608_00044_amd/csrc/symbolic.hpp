@@ -19,6 +19,8 @@ struct Options {
     int32_t sn_cap = 150;
     double amalg_ratio = 0.0;
     int32_t sched = 0;
+    int32_t debug_flags = 0;  // bit 0: withhold one dependency (exercises the watchdog)
+    int64_t spin_limit = 0;   // bounded waits of the task-queue schedule; 0 = default
 };
 
 // One (source, target) update pair: source supernode s sends its update block

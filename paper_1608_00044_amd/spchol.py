@@ -31,7 +31,8 @@ SPC_ERR_BUSY = -8
 
 # Every symbol include/spchol.h declares.
 EXPORTS = ("spc_default_options", "spc_analyze", "spc_symbolic_info_get", "spc_symbolic_export",
-           "spc_symbolic_export_rows", "spc_symbolic_export_pairs", "spc_symbolic_free",
+           "spc_symbolic_export_rows", "spc_symbolic_export_pairs", "spc_symbolic_export_tasks",
+           "spc_symbolic_free",
            "spc_factor", "spc_refactor", "spc_numeric_status", "spc_solve", "spc_factor_export",
            "spc_numeric_free", "spc_status_string", "spc_numeric_set_timing",
            "spc_numeric_get_timing")
@@ -39,7 +40,8 @@ EXPORTS = ("spc_default_options", "spc_analyze", "spc_symbolic_info_get", "spc_s
 
 class spc_options(C.Structure):
     _fields_ = [("sn_cap", C.c_int32), ("sched", C.c_int32), ("amalg_ratio", C.c_double),
-                ("mem_budget_bytes", C.c_int64)]
+                ("mem_budget_bytes", C.c_int64), ("spin_limit", C.c_int64),
+                ("debug_flags", C.c_int32), ("reserved", C.c_int32)]
 
 
 class spc_symbolic_info(C.Structure):
@@ -51,10 +53,10 @@ class spc_symbolic_info(C.Structure):
 
 
 class spc_kernel_times(C.Structure):
-    _fields_ = [("ms", C.c_double * 4), ("launches", C.c_int64 * 4), ("total_ms", C.c_double)]
+    _fields_ = [("ms", C.c_double * 5), ("launches", C.c_int64 * 5), ("total_ms", C.c_double)]
 
 
-KERNEL_CLASSES = ("load", "potrf", "trsm", "update")
+KERNEL_CLASSES = ("load", "potrf", "trsm", "update", "tasks")
 
 
 class SpcError(RuntimeError):
@@ -83,6 +85,8 @@ def lib():
         L.spc_symbolic_export_rows.restype = C.c_int32
         L.spc_symbolic_export_pairs.argtypes = [vp, vp, vp, vp, vp, vp]
         L.spc_symbolic_export_pairs.restype = C.c_int32
+        L.spc_symbolic_export_tasks.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), vp, vp]
+        L.spc_symbolic_export_tasks.restype = C.c_int32
         L.spc_symbolic_free.argtypes = [vp]
         L.spc_symbolic_free.restype = C.c_int32
         L.spc_factor.argtypes = [vp, vp, vp, C.POINTER(vp)]
@@ -135,7 +139,7 @@ class Symbolic:
     """spc_analyze: host symbolic analysis of the lower CSC pattern."""
 
     def __init__(self, n, colptr, rowind, perm=None, sn_cap=150, amalg_ratio=0.0, sched=0,
-                 mem_budget_bytes=0):
+                 mem_budget_bytes=0, spin_limit=0, debug_flags=0):
         self.n = int(n)
         cp = _np(colptr, np.int64)
         ri = _np(rowind, np.int32)
@@ -146,6 +150,8 @@ class Symbolic:
         opt.sched = int(sched)
         opt.amalg_ratio = float(amalg_ratio)
         opt.mem_budget_bytes = int(mem_budget_bytes)
+        opt.spin_limit = int(spin_limit)
+        opt.debug_flags = int(debug_flags)
         h = C.c_void_p()
         if ri.size == 0:
             ri = np.zeros(1, dtype=np.int32)
@@ -196,6 +202,21 @@ class Symbolic:
             raise SpcError(st, "spc_symbolic_export_pairs")
         return dict(src=src[:npairs], tgt=tgt[:npairs], seg=seg[: 2 * npairs].reshape(-1, 2),
                     rel_off=ro[:npairs], rel=rel[:nrel])
+
+    def tasks(self, workers=256):
+        """Task order of the task-queue schedule: (tasks[ntasks, 4] as
+        (kind, s, a, b), cnt0[nsup])."""
+        nt = C.c_int64(0)
+        st = lib().spc_symbolic_export_tasks(self.handle, int(workers), C.byref(nt), None, None)
+        if st != SPC_OK:
+            raise SpcError(st, "spc_symbolic_export_tasks")
+        tk = np.zeros(max(4 * nt.value, 4), dtype=np.int32)
+        cnt0 = np.zeros(max(self.info()["nsup"], 1), dtype=np.int32)
+        st = lib().spc_symbolic_export_tasks(self.handle, int(workers), C.byref(nt), _ptr(tk),
+                                             _ptr(cnt0))
+        if st != SPC_OK:
+            raise SpcError(st, "spc_symbolic_export_tasks")
+        return tk[: 4 * nt.value].reshape(-1, 4), cnt0[: self.info()["nsup"]]
 
     def free(self):
         if getattr(self, "handle", None):

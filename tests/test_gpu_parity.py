@@ -76,9 +76,10 @@ CASES = ["dense1", "dense2", "dense5", "dense63", "dense64", "dense65", "dense15
          "elast27_6"]
 
 
-SCHED_CASES = [(c, 0) for c in CASES] + [(c, 1) for c in ("dense300", "fig1", "random3",
-                                                          "lap2d_64", "lap3d_20_cap32",
-                                                          "lap3d_24", "elast27_6")]
+SCHED_CASES = ([(c, 0) for c in CASES] + [(c, 1) for c in ("dense300", "fig1", "random3",
+                                                           "lap2d_64", "lap3d_20_cap32",
+                                                           "lap3d_24", "elast27_6")]
+               + [(c, 2) for c in CASES])
 
 
 @pytest.mark.parametrize("name,sched", SCHED_CASES)
@@ -158,6 +159,52 @@ def test_non_spd_in_3d_parallel_schedule():
     ost, _ = oracle.factor(p.n, Cp2, Ci2, Cx2, osym)
     sym, num, _ = gpu_factor(q2, 150, 0.1)
     assert num.status() == ost == min(cols) + 1
+
+
+@pytest.mark.parametrize("sched", [1, 2])
+def test_non_spd_status_other_schedules(sched):
+    """The failing column is reported the same way by every schedule."""
+    n = 400
+    p = inputs.tridiag(n)
+    vals = p.values.copy()
+    vals[p.colptr[29]] = 29 / 30 - 0.5
+    sym, num, _ = gpu_factor(inputs.Problem(n, p.colptr, p.rowind, vals, None), sched=sched)
+    assert num.status() == 30
+
+
+def test_task_queue_refactor_resets_counters():
+    """Two factorizations in a row through one task-queue plan: the dependency
+    counters start over each time."""
+    torch = torch_dev()
+    p = inputs.make_grid_problem("lap", (14, 14, 14), 31, sigma=1.0, shift=1e-3, nrhs=0)
+    sym, num, _ = gpu_factor(p, 150, 0.1, sched=2)
+    assert num.status() == 0
+    p2 = inputs.make_grid_problem("lap", (14, 14, 14), 32, sigma=1.0, shift=1e-3, nrhs=0)
+    for _ in range(2):
+        num.refactor(torch.from_numpy(p2.values).to("cuda:0"))
+        assert num.status() == 0
+        worst, rho, _ = compare_factor(p2, num, 150, 0.1, "refactor-sched2")
+        assert worst <= 1.0 and rho <= 1e-12
+
+
+def test_task_queue_bounded_wait_reports_timeout():
+    """A dependency the host withholds (debug flag) never arrives: the bounded
+    device wait ends the factorization with SPC_ERR_TIMEOUT, every worker
+    exits, and the device stays usable."""
+    torch = torch_dev()
+    p = inputs.make_grid_problem("lap", (8, 8, 8), 5, sigma=1.0, shift=1e-3, nrhs=0)
+    sym = spchol.analyze(p.n, p.colptr, p.rowind, p.perm, sched=2, spin_limit=200000,
+                         debug_flags=1)
+    vals = torch.from_numpy(p.values).to("cuda:0")
+    num = spchol.factor(sym, vals)
+    assert num.status() == spchol.SPC_ERR_TIMEOUT
+    with pytest.raises(spchol.SpcError) as e:
+        num.solve(torch.ones(p.n, dtype=torch.float64, device="cuda:0"))
+    assert e.value.status == spchol.SPC_ERR_TIMEOUT
+    num.free()
+    sym.free()
+    sym2, num2, _ = gpu_factor(p, sched=2)
+    assert num2.status() == 0
 
 
 def test_nan_value_reports_status():

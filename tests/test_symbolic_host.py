@@ -44,8 +44,8 @@ def test_analyze_rejects_bad_arguments():
     with pytest.raises(spchol.SpcError) as e:
         spchol.analyze(2, cp, ri, perm=[0, 0])
     assert e.value.status == spchol.SPC_ERR_ARG
-    for kw in (dict(sn_cap=0), dict(sn_cap=151), dict(amalg_ratio=-0.1), dict(sched=7), dict(sched=-1),
-               dict(mem_budget_bytes=-1)):
+    for kw in (dict(sn_cap=0), dict(sn_cap=151), dict(amalg_ratio=-0.1), dict(sched=3), dict(sched=-1),
+               dict(mem_budget_bytes=-1), dict(spin_limit=-1)):
         with pytest.raises(spchol.SpcError) as e:
             spchol.analyze(2, cp, ri, **kw)
         assert e.value.status == spchol.SPC_ERR_ARG
@@ -153,3 +153,67 @@ def test_missing_diagonal_is_structural():
     sym = spchol.analyze(3, [0, 2, 2, 3], [0, 1, 2])
     parent, cc, _, _ = sym.export()
     assert parent.tolist() == [1, -1, -1]
+
+
+def _check_task_order(sym, sn, workers):
+    """The task-queue order is a topological order of the F/T/U task graph and
+    the F counters count (tile, distinct target) pairs; derived here from the
+    supernode row lists alone."""
+    tk, cnt0 = sym.tasks(workers)
+    rp, rows = sym.rows()
+    ns = len(sn) - 1
+    owner = np.repeat(np.arange(ns), np.diff(sn))
+    pos = {}
+    for q, (kind, s, a, b) in enumerate(tk.tolist()):
+        key = (kind, s, a, b) if kind == 2 else ((kind, s, a) if kind == 1 else (kind, s))
+        assert key not in pos
+        pos[key] = q
+    expect_cnt = np.zeros(ns, dtype=np.int64)
+    want = 0
+    for s in range(ns):
+        w = sn[s + 1] - sn[s]
+        below = rows[rp[s] + w:rp[s + 1]]
+        nb = (len(below) + 63) // 64
+        want += 1 + nb + nb * (nb + 1) // 2
+        for b in range(nb):
+            assert pos[(0, s)] < pos[(1, s, b)]
+        for j in range(nb):
+            tg = np.unique(owner[below[64 * j:64 * j + 64]])
+            for i in range(j, nb):
+                u = pos[(2, s, i, j)]
+                assert pos[(1, s, i)] < u and pos[(1, s, j)] < u
+                for t in tg:
+                    assert u < pos[(0, int(t))]
+                    expect_cnt[t] += 1
+    assert len(tk) == want
+    assert np.array_equal(cnt0, expect_cnt)
+
+
+@pytest.mark.parametrize("case", ["fig1", "rand0", "rand1", "grid12", "grid2d"])
+@pytest.mark.parametrize("workers", [1, 7, 256])
+def test_task_order_is_topological(case, workers):
+    if case == "fig1":
+        fig = load_fig1()
+        p = spd_values_for_pattern(fig["n"], fig["orig"], seed=1)
+        cap, ratio = 150, 0.0
+    elif case.startswith("rand"):
+        p = inputs.random_spd_pattern(150, 0.1, seed=int(case[-1]))
+        cap, ratio = 8, 0.1
+    elif case == "grid12":
+        p = inputs.make_grid_problem("lap", (12, 12, 12), seed=3, sigma=1.0, shift=1e-3, nrhs=0)
+        cap, ratio = 150, 0.1
+    else:
+        p = inputs.make_grid_problem("lap", (90, 90), seed=3, sigma=1.0, shift=1e-3, nrhs=0)
+        cap, ratio = 32, 0.0
+    sym = spchol.analyze(p.n, p.colptr, p.rowind, p.perm, sn_cap=cap, amalg_ratio=ratio, sched=2)
+    _, _, sn, _ = sym.export()
+    _check_task_order(sym, sn, workers)
+
+
+def test_task_order_arguments():
+    sym = spchol.analyze(1, [0, 1], [0], sched=2)
+    with pytest.raises(spchol.SpcError) as e:
+        sym.tasks(0)
+    assert e.value.status == spchol.SPC_ERR_ARG
+    tk, cnt0 = sym.tasks(4)
+    assert tk.tolist() == [[0, 0, 0, 0]] and cnt0.tolist() == [0]
