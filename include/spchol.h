@@ -78,7 +78,9 @@ typedef struct spc_options {
                                  reads SPC_ERR_TIMEOUT; 0 = default (ten seconds) */
     int32_t debug_flags;      /* bit 0: withhold one dependency count so that the
                                  bounded wait fires (testing only); default 0    */
-    int32_t reserved;
+    int32_t precision;        /* 0 = FP64 factor (default); 1 = FP32 factor on FP32
+                                 matrix cores with FP32 accumulation, for use with
+                                 spc_solve_refine (FP64 iterative refinement)     */
 } spc_options;
 
 typedef struct spc_symbolic spc_symbolic;
@@ -185,6 +187,35 @@ spc_status spc_solve(spc_numeric* num, int32_t nrhs, const double* b_dev, int64_
  * values.  Entries outside the exact structure of L are explicit zeros.
  * Synchronizes.  Any output may be NULL; sizes are n+1 and nnz_stored. */
 spc_status spc_factor_export(spc_numeric* num, int64_t* Sp, int32_t* Si, double* Sx);
+
+/* Mixed-precision solve: iterative refinement in FP64 around the factor
+ * (an extension of the solves of Section II-A; the paper works in one
+ * precision).  x_0 = 0; each step forms r = b - A x in FP64 from a copy of A
+ * taken at factorization time, the normwise backward error
+ * eta_c = ||r_c||_inf / (||A||_inf ||x_c||_inf + ||b_c||_inf) of every column,
+ * and, while some eta_c > tol, solves L L^T d = r / ||r|| in the factor's
+ * precision and adds ||r|| d to x in FP64.  b_dev, x_dev: column-major device
+ * arrays (ldb, ldx >= n) of doubles that must not overlap.  Returns SPC_OK
+ * once every column meets tol, SPC_ERR_NOT_CONVERGED after max_iter
+ * corrections (x holds the last iterate), or the factor's status.  *iters
+ * (may be NULL) receives the number of corrections; berr (host, nrhs entries,
+ * may be NULL) the final eta.  Synchronizes stream once per step. */
+spc_status spc_solve_refine(spc_numeric* num, int32_t nrhs, const double* b_dev, int64_t ldb,
+                            double* x_dev, int64_t ldx, double tol, int32_t max_iter,
+                            void* stream, int32_t* iters, double* berr);
+
+/* Facts about a numeric factor.  fp64_blocks: for an FP32 factor, the number
+ * of diagonal blocks whose FP32 factorization met a pivot at most 1e-3 times
+ * its starting diagonal entry and that were factored again in FP64 (the
+ * result is stored in FP32).  Synchronizes the factor's stream. */
+typedef struct spc_numeric_info {
+    int32_t precision;     /* 0 FP64, 1 FP32 */
+    int32_t sched;
+    int64_t factor_bytes;  /* device bytes held by the factor (estimate) */
+    int64_t fp64_blocks;
+} spc_numeric_info;
+
+spc_status spc_numeric_info_get(spc_numeric* num, spc_numeric_info* out);
 
 /* Per-kernel-class device times of the most recent factorization, measured
  * with HIP events recorded on the factor's stream around every launch while

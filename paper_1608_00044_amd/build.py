@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libspchol.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["symbolic.cpp", "plan.cpp", "schedule.cpp", "api.cpp", "factor.hip", "solve.hip"]
+SOURCES = ["symbolic.cpp", "plan.cpp", "schedule.cpp", "api.cpp", "factor.hip", "solve.hip", "refine.hip"]
 ARCH = os.environ.get("SPCHOL_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

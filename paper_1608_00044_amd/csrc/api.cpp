@@ -14,6 +14,42 @@ int32_t configure_kernels();
 
 using namespace spc;
 
+namespace {
+
+size_t real_size(const Symbolic& S) { return S.opt.precision == 1 ? sizeof(float) : sizeof(double); }
+
+// Device bytes of one numeric factor: supernode blocks and diagonal-block
+// inverses in the factor's type, the FP64 copy of A kept for refinement
+// (full CSR: 8-byte value, 4-byte column and 8-byte source index per entry,
+// plus row pointers), task-queue counters, status words.
+int64_t factor_bytes(const Symbolic& S) {
+    const int64_t nnzf = 2 * S.nnz_a;  // bound: diagonal entries appear once
+    int64_t b = (int64_t)((S.arena + inverse_blocks_elems(S)) * real_size(S));
+    b += nnzf * 20 + (S.n + 1) * 8;
+    if (S.opt.sched == 2) b += 4 * (3 * S.nsup + 4);
+    return b + 512;
+}
+
+// Frees whatever the numeric object holds (any member may still be null).
+void release_numeric(spc_numeric* num) {
+    (void)hipFree(num->arena);
+    (void)hipFree(num->status_dev);
+    (void)hipFree(num->dinv);
+    (void)hipFree(num->sched_state);
+    drop_solve_graphs(num);
+    if (num->capture) (void)hipStreamDestroy(num->capture);
+    (void)hipFree(num->work);
+    free_refine(num);
+    for (hipEvent_t e : num->events) (void)hipEventDestroy(e);
+    for (hipEvent_t e : num->sync_ev) (void)hipEventDestroy(e);
+    if (num->bulk) {
+        (void)hipStreamSynchronize(num->bulk);
+        (void)hipStreamDestroy(num->bulk);
+    }
+}
+
+}  // namespace
+
 extern "C" {
 
 void spc_default_options(spc_options* opt) {
@@ -24,7 +60,7 @@ void spc_default_options(spc_options* opt) {
     opt->mem_budget_bytes = 0;
     opt->spin_limit = 0;
     opt->debug_flags = 0;
-    opt->reserved = 0;
+    opt->precision = 0;
 }
 
 const char* spc_status_string(spc_status st) {
@@ -55,6 +91,7 @@ spc_status spc_analyze(int64_t n, const int64_t* colptr, const int32_t* rowind,
     if (o.spin_limit < 0) return SPC_ERR_ARG;
     if (!(o.amalg_ratio >= 0.0 && o.amalg_ratio <= 1.0)) return SPC_ERR_ARG;
     if (o.mem_budget_bytes < 0) return SPC_ERR_ARG;
+    if (o.precision != 0 && o.precision != 1) return SPC_ERR_ARG;
     spc_symbolic* h = new (std::nothrow) spc_symbolic();
     if (!h) return SPC_ERR_OOM;
     Options so;
@@ -63,6 +100,7 @@ spc_status spc_analyze(int64_t n, const int64_t* colptr, const int32_t* rowind,
     so.sched = o.sched;
     so.spin_limit = o.spin_limit;
     so.debug_flags = o.debug_flags;
+    so.precision = o.precision;
     int32_t st;
     try {
         st = analyze(n, colptr, rowind, perm, so, &h->S);
@@ -91,7 +129,7 @@ spc_status spc_symbolic_info_get(const spc_symbolic* sym, spc_symbolic_info* inf
     info->nlevels = (int64_t)S.level_ptr.size() - 1;
     info->npairs = (int64_t)S.pairs.size();
     info->nrel = (int64_t)S.rel.size();
-    info->factor_bytes = (int64_t)((S.arena + inverse_blocks_elems(S)) * sizeof(double)) + 256;
+    info->factor_bytes = factor_bytes(S);
     info->plan_bytes = (int64_t)sym->plan_bytes_estimate;
     info->flops = S.flops;
     info->flops_stored = S.flops_stored;
@@ -167,8 +205,7 @@ static spc_status alloc_numeric(spc_symbolic* sym, spc_numeric** out) {
     int32_t st = configure_kernels();
     if (st != OK) return st;
     const Symbolic& S = sym->S;
-    const int64_t need = (int64_t)((S.arena + inverse_blocks_elems(S)) * sizeof(double)) + 256;
-    if (sym->budget > 0 && need + (int64_t)sym->plan_bytes_estimate > sym->budget)
+    if (sym->budget > 0 && factor_bytes(S) + (int64_t)sym->plan_bytes_estimate > sym->budget)
         return SPC_ERR_OOM;
     DevicePlan* plan = nullptr;
     st = get_plan(sym, &plan);
@@ -178,40 +215,26 @@ static spc_status alloc_numeric(spc_symbolic* sym, spc_numeric** out) {
     num->sym = sym;
     num->plan = plan;
     num->device = plan->device;
-    if (hipMalloc(&num->arena, sizeof(double) * (size_t)(S.arena > 0 ? S.arena : 1)) !=
-        hipSuccess) {
-        delete num;
-        return SPC_ERR_OOM;
-    }
-    if (hipMalloc(&num->status_dev, 256) != hipSuccess) {
-        (void)hipFree(num->arena);
-        delete num;
-        return SPC_ERR_OOM;
-    }
-    if (hipMalloc(&num->dinv, sizeof(double) * (size_t)(plan->inv_elems > 0 ? plan->inv_elems : 1)) !=
-        hipSuccess) {
-        (void)hipFree(num->arena);
-        (void)hipFree(num->status_dev);
-        delete num;
-        return SPC_ERR_OOM;
-    }
+    num->prec = S.opt.precision;
     num->sched = S.opt.sched;
-    if (num->sched == 2) {
+    const size_t rs = real_size(S);
+    bool ok = hipMalloc(&num->arena, rs * (size_t)(S.arena > 0 ? S.arena : 1)) == hipSuccess &&
+              hipMalloc(&num->status_dev, 256) == hipSuccess &&
+              hipMalloc(&num->dinv, rs * (size_t)(plan->inv_elems > 0 ? plan->inv_elems : 1)) ==
+                  hipSuccess;
+    if (ok && num->sched == 2) {
         const size_t ints = 2 * (size_t)S.nsup + (size_t)plan->nrowblk + 4;
-        if (hipMalloc(&num->sched_state, ints * sizeof(int32_t)) != hipSuccess) {
-            (void)hipFree(num->arena);
-            (void)hipFree(num->status_dev);
-            (void)hipFree(num->dinv);
-            delete num;
-            return SPC_ERR_OOM;
-        }
+        ok = hipMalloc(&num->sched_state, ints * sizeof(int32_t)) == hipSuccess;
         num->spin_limit = S.opt.spin_limit > 0 ? S.opt.spin_limit : (int64_t)10000000;
+    }
+    if (!ok) {
+        release_numeric(num);
+        delete num;
+        return SPC_ERR_OOM;
     }
     if (num->sched == 1 &&
         hipStreamCreateWithFlags(&num->bulk, hipStreamNonBlocking) != hipSuccess) {
-        (void)hipFree(num->arena);
-        (void)hipFree(num->status_dev);
-        (void)hipFree(num->dinv);
+        release_numeric(num);
         delete num;
         return SPC_ERR_HIP;
     }
@@ -223,6 +246,13 @@ static spc_status alloc_numeric(spc_symbolic* sym, spc_numeric** out) {
     return SPC_OK;
 }
 
+// Factorization plus the FP64 copy of A that refinement reads.
+static spc_status factor_and_keep(spc_numeric* num, const double* values_dev, hipStream_t st) {
+    spc_status r = run_factor(num, values_dev, st);
+    if (r != SPC_OK) return r;
+    return load_refine_matrix(num, values_dev, st);
+}
+
 spc_status spc_factor(const spc_symbolic* csym, const double* values_dev, void* stream,
                       spc_numeric** out) {
     if (!csym || !out) return SPC_ERR_ARG;
@@ -232,7 +262,7 @@ spc_status spc_factor(const spc_symbolic* csym, const double* values_dev, void* 
     spc_numeric* num = nullptr;
     spc_status st = alloc_numeric(sym, &num);
     if (st != SPC_OK) return st;
-    st = run_factor(num, values_dev, (hipStream_t)stream);
+    st = factor_and_keep(num, values_dev, (hipStream_t)stream);
     if (st != SPC_OK) {
         spc_numeric_free(num);
         return st;
@@ -248,7 +278,7 @@ spc_status spc_refactor(spc_numeric* num, const double* values_dev, void* stream
     if (hipGetDevice(&cur) != hipSuccess) return SPC_ERR_HIP;
     if (cur != num->device) return SPC_ERR_ARG;
     num->host_status = 0;
-    return run_factor(num, values_dev, (hipStream_t)stream);
+    return factor_and_keep(num, values_dev, (hipStream_t)stream);
 }
 
 spc_status spc_numeric_status(spc_numeric* num) {
@@ -286,6 +316,38 @@ spc_status spc_solve(spc_numeric* num, int32_t nrhs, const double* b_dev, int64_
     return run_solve(num, nrhs, b_dev, ldb, x_dev, ldx, (hipStream_t)stream);
 }
 
+spc_status spc_solve_refine(spc_numeric* num, int32_t nrhs, const double* b_dev, int64_t ldb,
+                            double* x_dev, int64_t ldx, double tol, int32_t max_iter,
+                            void* stream, int32_t* iters, double* berr) {
+    if (!num || nrhs < 0 || max_iter < 0 || !(tol >= 0.0)) return SPC_ERR_ARG;
+    const int64_t n = num->sym->S.n;
+    if (nrhs > 0 && n > 0 && (!b_dev || !x_dev || ldb < n || ldx < n || b_dev == x_dev))
+        return SPC_ERR_ARG;
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return SPC_ERR_HIP;
+    if (cur != num->device) return SPC_ERR_ARG;
+    spc_status st = num->status_known ? num->host_status : spc_numeric_status(num);
+    if (st != SPC_OK) return st;
+    return run_refine(num, nrhs, b_dev, ldb, x_dev, ldx, tol, max_iter, (hipStream_t)stream,
+                      iters, berr);
+}
+
+spc_status spc_numeric_info_get(spc_numeric* num, spc_numeric_info* out) {
+    if (!num || !out) return SPC_ERR_ARG;
+    std::memset(out, 0, sizeof(*out));
+    out->precision = num->prec;
+    out->sched = num->sched;
+    out->factor_bytes = factor_bytes(num->sym->S);
+    if (num->factored) {
+        if (hipStreamSynchronize(num->stream) != hipSuccess) return SPC_ERR_HIP;
+        int32_t v[2] = {0, 0};
+        if (hipMemcpy(v, num->status_dev, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess)
+            return SPC_ERR_HIP;
+        out->fp64_blocks = v[1];
+    }
+    return SPC_OK;
+}
+
 spc_status spc_factor_export(spc_numeric* num, int64_t* Sp, int32_t* Si, double* Sx) {
     if (!num) return SPC_ERR_ARG;
     const Symbolic& S = num->sym->S;
@@ -308,10 +370,17 @@ spc_status spc_factor_export(spc_numeric* num, int64_t* Sp, int32_t* Si, double*
         if (!num->factored) return SPC_ERR_NOT_FACTORED;
         if (hipStreamSynchronize(num->stream) != hipSuccess) return SPC_ERR_HIP;
         std::vector<double> h((size_t)(S.arena > 0 ? S.arena : 1));
-        if (S.arena > 0 &&
-            hipMemcpy(h.data(), num->arena, sizeof(double) * S.arena, hipMemcpyDeviceToHost) !=
-                hipSuccess)
+        if (S.arena > 0 && num->prec == 1) {
+            std::vector<float> hf((size_t)S.arena);
+            if (hipMemcpy(hf.data(), num->arena, sizeof(float) * S.arena,
+                          hipMemcpyDeviceToHost) != hipSuccess)
+                return SPC_ERR_HIP;
+            for (int64_t k = 0; k < S.arena; ++k) h[(size_t)k] = (double)hf[(size_t)k];
+        } else if (S.arena > 0 &&
+                   hipMemcpy(h.data(), num->arena, sizeof(double) * S.arena,
+                             hipMemcpyDeviceToHost) != hipSuccess) {
             return SPC_ERR_HIP;
+        }
         int64_t q = 0;
         for (int64_t s = 0; s < S.nsup; ++s) {
             const int32_t w = S.width(s), m = S.nrows(s), ld = S.ld[s];
@@ -362,19 +431,7 @@ void spc_numeric_free(spc_numeric* num) {
     (void)hipSetDevice(num->device);
     if (num->stream) (void)hipStreamSynchronize(num->stream);
     else (void)hipDeviceSynchronize();
-    (void)hipFree(num->arena);
-    (void)hipFree(num->status_dev);
-    (void)hipFree(num->dinv);
-    if (num->sched_state) (void)hipFree(num->sched_state);
-    drop_solve_graphs(num);
-    if (num->capture) (void)hipStreamDestroy(num->capture);
-    if (num->work) (void)hipFree(num->work);
-    for (hipEvent_t e : num->events) (void)hipEventDestroy(e);
-    for (hipEvent_t e : num->sync_ev) (void)hipEventDestroy(e);
-    if (num->bulk) {
-        (void)hipStreamSynchronize(num->bulk);
-        (void)hipStreamDestroy(num->bulk);
-    }
+    release_numeric(num);
     (void)hipSetDevice(cur);
     {
         std::lock_guard<std::mutex> lock(num->sym->mu);

@@ -1,5 +1,6 @@
-// Numeric supernodal Cholesky on gfx950: plan upload, value load, and the
-// per-level task kernels.
+// Numeric supernodal Cholesky on gfx950: value load and the task kernels, in
+// FP64 (v_mfma_f64_16x16x4) or FP32 (v_mfma_f32_16x16x4_f32, FP32
+// accumulation) arithmetic; every kernel is a template on the real type R.
 //
 // Tasks (Section III-A of arXiv:1608.00044), per supernode s of width w with
 // r rows below its diagonal block, stored as a column-major (w + r) x w block:
@@ -27,6 +28,27 @@
 namespace spc {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Matrix-core tile 16 x 16 x 4 in FP64 or FP32.  Operands: lane l holds
+// A[l % 16][l / 16] and B[l / 16][l % 16].  The accumulator layouts differ:
+// register q of lane l holds D[row(q, l / 16)][l % 16] with row = 4q + l/16 for
+// v_mfma_f64_16x16x4_f64 and row = 4 (l/16) + q for v_mfma_f32_16x16x4_f32.
+template <class R> struct Mx;
+template <> struct Mx<double> {
+    typedef v4d acc;
+    static __device__ __forceinline__ acc mfma(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int q, int lk) { return 4 * q + lk; }
+};
+template <> struct Mx<float> {
+    typedef v4f acc;
+    static __device__ __forceinline__ acc mfma(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int q, int lk) { return 4 * lk + q; }
+};
 
 #define HIP_TRY(x)                               \
     do {                                         \
@@ -37,7 +59,8 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // value load
 // ---------------------------------------------------------------------------
 
-__global__ void k_fill(double* __restrict__ p, int64_t n, double v) {
+template <class R>
+__global__ void k_fill(R* __restrict__ p, int64_t n, R v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -51,11 +74,12 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
 
 // arena[slot[k]] = values[k]: every input entry of A goes to its place in the
 // supernodal storage of P A P^T.
+template <class R>
 __global__ void k_load(const double* __restrict__ values, const int64_t* __restrict__ slot,
-                       double* __restrict__ arena, int64_t nnz) {
+                       R* __restrict__ arena, int64_t nnz) {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz;
          k += (int64_t)gridDim.x * blockDim.x)
-        arena[slot[k]] = values[k];
+        arena[slot[k]] = (R)values[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -70,9 +94,16 @@ __device__ __forceinline__ double lane_value(double v, int lane) {
     const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
+__device__ __forceinline__ float lane_value(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
 
 constexpr int kPotrfThreads = 256;
 constexpr int kDs = kPanel + 1;  // padded row stride of the dense 16 x 16 panel block
+// FP32 diagonal factorization: a pivot at most this fraction of the diagonal
+// entry it started from (before the block's own elimination) marks the block
+// for FP64 (the block lost about log10(1/kPivotTau) digits to cancellation).
+constexpr float kPivotTau = 1e-3f;
 
 // 1/sqrt(d) from the hardware estimate refined by two Newton steps, and sqrt(d)
 // as d/sqrt(d); within a few units in the last place of the rounded values.
@@ -83,6 +114,13 @@ __device__ __forceinline__ void rsqrt_sqrt(double d, double& rs, double& sq) {
     rs = y;
     sq = d * y;
 }
+// FP32: the estimate of v_rsq_f32 refined by one Newton step.
+__device__ __forceinline__ void rsqrt_sqrt(float d, float& rs, float& sq) {
+    float y = __builtin_amdgcn_rsqf(d);
+    y = y * (1.5f - 0.5f * d * y * y);
+    rs = y;
+    sq = d * y;
+}
 
 // Wave-level factorization of the 16 x 16 diagonal block of panel q (columns
 // j0 .. j0 + jb - 1): copy it from the packed triangle T into the dense tile
@@ -90,29 +128,36 @@ __device__ __forceinline__ void rsqrt_sqrt(double d, double& rs, double& sq) {
 // the pivot comes by v_readlane, each finished column goes back to the tile
 // and is read by every lane), form inv(D) by forward substitution (one column
 // per lane), and write L back to T and inv(D) to Dinv and dinv.
-template <class Cst>
-__device__ __forceinline__ void panel_factor(double* __restrict__ T, double* __restrict__ Dt,
-                                             double* __restrict__ Dinv,
-                                             double* __restrict__ inv_g, Cst cst, int dummy,
-                                             int j0, int jb, int q, int lane, int first,
-                                             int32_t* __restrict__ status) {
+// kCheck (the FP32 pass): instead of recording failed pivots in *status, flag
+// the block as unstable when a pivot is not above tau times the diagonal
+// entry it started from (d0, the block's diagonal before the factorization).
+template <class C, class S, bool kCheck, class Cst>
+__device__ __forceinline__ void panel_factor(C* __restrict__ T, C* __restrict__ Dt,
+                                             C* __restrict__ Dinv, S* __restrict__ inv_g,
+                                             Cst cst, int dummy, int j0, int jb, int q, int lane,
+                                             int first, int32_t* __restrict__ status,
+                                             const C* __restrict__ d0, int* unstable) {
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         const int idx = lane + 64 * m, i = idx >> 4, j = idx & 15;
         const bool in = i < jb && j <= i;
-        const double v = T[in ? cst(j0 + j) + j0 + i : dummy];
-        Dt[i * kDs + j] = in ? v : (i == j ? 1.0 : 0.0);
+        const C v = T[in ? cst(j0 + j) + j0 + i : dummy];
+        Dt[i * kDs + j] = in ? v : (i == j ? C(1) : C(0));
     }
     __builtin_amdgcn_wave_barrier();
     const int i = lane & 15;  // lanes 16..63 mirror lanes 0..15
-    double d[kPanel], rd[kPanel];
+    C d[kPanel], rd[kPanel];
 #pragma unroll
     for (int j = 0; j < kPanel; ++j) d[j] = Dt[i * kDs + j];
 #pragma unroll
     for (int k = 0; k < kPanel; ++k) {
-        const double dkk = lane_value(d[k], k);
-        if (k < jb && !(dkk > 0.0) && lane == 0) atomicMin(status, first + j0 + k + 1);
-        double rinv, lkk;
+        const C dkk = lane_value(d[k], k);
+        if (kCheck) {
+            if (k < jb && !(dkk > kPivotTau * d0[j0 + k]) && lane == 0) *unstable = 1;
+        } else {
+            if (k < jb && !(dkk > C(0)) && lane == 0) atomicMin(status, first + j0 + k + 1);
+        }
+        C rinv, lkk;
         rsqrt_sqrt(dkk, rinv, lkk);
         rd[k] = rinv;
         d[k] = (i == k) ? lkk : d[k] * rinv;
@@ -120,14 +165,14 @@ __device__ __forceinline__ void panel_factor(double* __restrict__ T, double* __r
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int j = k + 1; j < kPanel; ++j) {
-            const double ljk = Dt[j * kDs + k];
-            d[j] -= ((i >= j) ? d[k] : 0.0) * ljk;
+            const C ljk = Dt[j * kDs + k];
+            d[j] -= ((i >= j) ? d[k] : C(0)) * ljk;
         }
     }
-    double x[kPanel];
+    C x[kPanel];
 #pragma unroll
     for (int rr = 0; rr < kPanel; ++rr) {
-        double acc = (rr == i) ? 1.0 : 0.0;
+        C acc = (rr == i) ? C(1) : C(0);
 #pragma unroll
         for (int k = 0; k < rr; ++k) acc -= Dt[rr * kDs + k] * x[k];
         x[rr] = acc * rd[rr];
@@ -135,9 +180,9 @@ __device__ __forceinline__ void panel_factor(double* __restrict__ T, double* __r
     if (lane < kPanel) {
 #pragma unroll
         for (int rr = 0; rr < kPanel; ++rr) {
-            const double v = (i < jb && rr < jb) ? x[rr] : 0.0;
+            const C v = (i < jb && rr < jb) ? x[rr] : C(0);
             Dinv[rr * kPanel + i] = v;
-            inv_g[q * kPanel * kPanel + rr * kPanel + i] = v;
+            inv_g[q * kPanel * kPanel + rr * kPanel + i] = (S)v;
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -152,8 +197,8 @@ __device__ __forceinline__ void panel_factor(double* __restrict__ T, double* __r
 // Trailing-update block b of panel p (blocks numbered row by row over the
 // lower triangle of the trailing part, 16 x 16 each, K = 16 on the matrix
 // cores), in place in the packed triangle.
-template <class Cst>
-__device__ __forceinline__ void trailing_block(double* __restrict__ T, Cst cst, int dummy, int w,
+template <class C, class Cst>
+__device__ __forceinline__ void trailing_block(C* __restrict__ T, Cst cst, int dummy, int w,
                                                int j0, int t0, int b, int lr, int lk) {
     int bi = (int)((sqrtf(8.0f * b + 1.0f) - 1.0f) * 0.5f);
     bi -= (bi * (bi + 1) / 2 > b);
@@ -162,11 +207,11 @@ __device__ __forceinline__ void trailing_block(double* __restrict__ T, Cst cst, 
     const int row0 = t0 + bi * kPanel, col0 = t0 + bj * kPanel;
     const int ra = row0 + lr, rb = col0 + lr;
     const bool oka = ra < w, okb = rb < w;
-    double cv[4], av[4], bv[4];
+    C cv[4], av[4], bv[4];
     int ci[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int rr = row0 + 4 * q + lk, cc = col0 + lr;
+        const int rr = row0 + Mx<C>::row(q, lk), cc = col0 + lr;
         const bool ok = rr < w && cc < w && rr >= cc;
         ci[q] = ok ? cst(cc) + rr : dummy;
         cv[q] = T[ci[q]];
@@ -174,15 +219,14 @@ __device__ __forceinline__ void trailing_block(double* __restrict__ T, Cst cst, 
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
         const int k = j0 + 4 * kk + lk;
-        const double ta = T[oka ? cst(k) + ra : dummy];
-        const double tb = T[okb ? cst(k) + rb : dummy];
-        av[kk] = oka ? -ta : 0.0;
-        bv[kk] = okb ? tb : 0.0;
+        const C ta = T[oka ? cst(k) + ra : dummy];
+        const C tb = T[okb ? cst(k) + rb : dummy];
+        av[kk] = oka ? -ta : C(0);
+        bv[kk] = okb ? tb : C(0);
     }
-    v4d acc = v4d{cv[0], cv[1], cv[2], cv[3]};
+    typename Mx<C>::acc acc = {cv[0], cv[1], cv[2], cv[3]};
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kk], bv[kk], acc, 0, 0, 0);
+    for (int kk = 0; kk < 4; ++kk) acc = Mx<C>::mfma(av[kk], bv[kk], acc);
 #pragma unroll
     for (int q = 0; q < 4; ++q) T[ci[q]] = acc[q];
 }
@@ -196,22 +240,28 @@ __device__ __forceinline__ void trailing_block(double* __restrict__ T, Cst cst, 
 //      (panel_factor); the inverse also goes to dinv for the panel and
 //      triangular solves;
 //   2. the rows below the panel inside the diagonal block are multiplied by
-//      inv(D)^T on v_mfma_f64_16x16x4, one 16-row block per wave;
+//      inv(D)^T on the matrix cores, one 16-row block per wave;
 //   3. the trailing lower triangle is updated in 16 x 16 blocks; wave 0
 //      updates the next panel's diagonal block first and factors it while
 //      waves 1-3 update the rest.
 // Global loads and stores of the block are issued many per thread at a time.
-// A pivot that is not positive records its global column with atomicMin on
-// *status; the smallest failing column wins.
-__device__ __forceinline__ void potrf_task(int s, const KArgs& a, double* __restrict__ arena,
-                                           double* __restrict__ dinv,
-                                           int32_t* __restrict__ status,
-                                           double* __restrict__ T) {
-    __shared__ double Dinv[kPanel * kPanel];  // row major: Dinv[r * 16 + c] = inv(D)[r][c]
-    __shared__ double Dt[kPanel * kDs];       // dense panel block, row major
+// Storage type S (the arena), compute type C (LDS and registers).  Without
+// kCheck a pivot that is not positive records its global column with
+// atomicMin on *status (the smallest failing column wins).  With kCheck (FP32
+// pass) nothing is recorded: if any pivot is not above kPivotTau times its
+// starting diagonal entry the block is left unwritten in global memory and
+// the function returns true, so that the caller can factor it again in FP64.
+template <class S, class C, bool kCheck>
+__device__ __forceinline__ bool potrf_task(int s, const KArgs& a, S* __restrict__ arena,
+                                           S* __restrict__ dinv, int32_t* __restrict__ status,
+                                           C* __restrict__ T) {
+    __shared__ C Dinv[kPanel * kPanel];  // row major: Dinv[r * 16 + c] = inv(D)[r][c]
+    __shared__ C Dt[kPanel * kDs];       // dense panel block, row major
+    __shared__ C d0[kCheck ? kMaxWidth : 1];
+    __shared__ int unstable;
     const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
-    double* __restrict__ base = arena + a.sn_off[s];
-    double* __restrict__ inv_g = dinv + a.inv_off[s];
+    S* __restrict__ base = arena + a.sn_off[s];
+    S* __restrict__ inv_g = dinv + a.inv_off[s];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lk = lane >> 4;
     constexpr int nwave = kPotrfThreads / 64;
@@ -219,24 +269,28 @@ __device__ __forceinline__ void potrf_task(int s, const KArgs& a, double* __rest
     auto cst = [w](int j) { return (j * (2 * w - j - 1)) >> 1; };
     const int dummy = w * (w + 1) / 2;  // masked accesses land here
     const int ww = w * w;
+    if (kCheck && tid == 0) unstable = 0;
     for (int e0 = tid; e0 < ww; e0 += 16 * kPotrfThreads) {
-        double v[16];
+        C v[16];
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
             const int e = e0 + u * kPotrfThreads, i = e % w, j = e / w;
             const bool ok = e < ww && i >= j;
-            v[u] = base[ok ? i + (int64_t)j * ld : 0];
+            v[u] = (C)base[ok ? i + (int64_t)j * ld : 0];
         }
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
             const int e = e0 + u * kPotrfThreads, i = e % w, j = e / w;
             const bool ok = e < ww && i >= j;
             T[ok ? cst(j) + i : dummy] = v[u];
+            if (kCheck && ok && i == j) d0[i] = v[u];
         }
     }
     __syncthreads();
     const int npanel = (w + kPanel - 1) / kPanel;
-    if (wave == 0) panel_factor(T, Dt, Dinv, inv_g, cst, dummy, 0, min(kPanel, w), 0, lane, first, status);
+    if (wave == 0)
+        panel_factor<C, S, kCheck>(T, Dt, Dinv, inv_g, cst, dummy, 0, min(kPanel, w), 0, lane,
+                                   first, status, d0, &unstable);
     __syncthreads();
     for (int p = 0; p < npanel; ++p) {
         const int j0 = p * kPanel;
@@ -248,20 +302,19 @@ __device__ __forceinline__ void potrf_task(int s, const KArgs& a, double* __rest
         for (int rb = wave; rb < nrb; rb += nwave) {
             const int row0 = t0 + rb * kPanel;
             const bool okr = row0 + lr < w;
-            double av[4], bv[4];
+            C av[4], bv[4];
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {
-                const double t = T[okr ? cst(j0 + 4 * kk + lk) + row0 + lr : dummy];
-                av[kk] = okr ? t : 0.0;
+                const C t = T[okr ? cst(j0 + 4 * kk + lk) + row0 + lr : dummy];
+                av[kk] = okr ? t : C(0);
                 bv[kk] = Dinv[lr * kPanel + 4 * kk + lk];
             }
-            v4d out = v4d{0.0, 0.0, 0.0, 0.0};
+            typename Mx<C>::acc out = {C(0), C(0), C(0), C(0)};
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk)
-                out = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kk], bv[kk], out, 0, 0, 0);
+            for (int kk = 0; kk < 4; ++kk) out = Mx<C>::mfma(av[kk], bv[kk], out);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int rr = row0 + 4 * q + lk;
+                const int rr = row0 + Mx<C>::row(q, lk);
                 T[rr < w ? cst(j0 + lr) + rr : dummy] = out[q];
             }
         }
@@ -271,32 +324,53 @@ __device__ __forceinline__ void potrf_task(int s, const KArgs& a, double* __rest
         const int nbr = (w - t0 + kPanel - 1) / kPanel;
         const int nblk = nbr * (nbr + 1) / 2;
         if (wave == 0) {
-            trailing_block(T, cst, dummy, w, j0, t0, 0, lr, lk);
+            trailing_block<C>(T, cst, dummy, w, j0, t0, 0, lr, lk);
             __builtin_amdgcn_wave_barrier();
-            panel_factor(T, Dt, Dinv, inv_g, cst, dummy, t0, min(kPanel, w - t0), p + 1, lane,
-                         first, status);
+            panel_factor<C, S, kCheck>(T, Dt, Dinv, inv_g, cst, dummy, t0, min(kPanel, w - t0),
+                                       p + 1, lane, first, status, d0, &unstable);
         } else {
             for (int b = wave; b < nblk; b += nwave - 1)
-                trailing_block(T, cst, dummy, w, j0, t0, b, lr, lk);
+                trailing_block<C>(T, cst, dummy, w, j0, t0, b, lr, lk);
         }
         __syncthreads();
     }
+    if (kCheck && unstable) return true;  // uniform: read after the last barrier
     for (int e0 = tid; e0 < ww; e0 += 8 * kPotrfThreads) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int e = e0 + u * kPotrfThreads, i = e % w, j = e / w;
-            if (e < ww && i >= j) base[i + (int64_t)j * ld] = T[cst(j) + i];
+            if (e < ww && i >= j) base[i + (int64_t)j * ld] = (S)T[cst(j) + i];
         }
+    }
+    return false;
+}
+
+// Diagonal factorization in the factor's precision.  FP64 factors: one FP64
+// pass.  FP32 factors: an FP32 pass; a block it flags as unstable (a pivot
+// ratio below kPivotTau) is factored again from its unchanged FP32 input in
+// FP64 arithmetic and rounded to FP32, and counted in *fallbacks.  T must
+// hold the packed triangle in the compute type of either pass.
+__device__ __forceinline__ void diag_factor(int s, const KArgs& a, double* arena, double* dinv,
+                                            int32_t* status, int32_t* fallbacks, void* T) {
+    potrf_task<double, double, false>(s, a, arena, dinv, status, (double*)T);
+}
+__device__ __forceinline__ void diag_factor(int s, const KArgs& a, float* arena, float* dinv,
+                                            int32_t* status, int32_t* fallbacks, void* T) {
+    if (potrf_task<float, float, true>(s, a, arena, dinv, status, (float*)T)) {
+        __syncthreads();
+        potrf_task<float, double, false>(s, a, arena, dinv, status, (double*)T);
+        if (threadIdx.x == 0) atomicAdd(fallbacks, 1);
     }
 }
 
 // Level-set form: one workgroup per supernode of the level.
+template <class R>
 __global__ __launch_bounds__(kPotrfThreads) void k_potrf(const int32_t* __restrict__ level_sn,
-                                                         KArgs a, double* __restrict__ arena,
-                                                         double* __restrict__ dinv,
+                                                         KArgs a, R* __restrict__ arena,
+                                                         R* __restrict__ dinv,
                                                          int32_t* __restrict__ status) {
     extern __shared__ double T[];
-    potrf_task(level_sn[blockIdx.x], a, arena, dinv, status, T);
+    diag_factor(level_sn[blockIdx.x], a, arena, dinv, status, status + 1, T);
 }
 
 // ---------------------------------------------------------------------------
@@ -305,24 +379,24 @@ __global__ __launch_bounds__(kPotrfThreads) void k_potrf(const int32_t* __restri
 
 // Panel solve for the 16 rows [row0, row0 + 16) of a panel, one wave, with
 // NP 16-column panels (w <= 16 NP).  Everything stays in registers:
-//   xo[p][q]  = X[4q + lk][16p + lr]     (matrix-core output layout)
+//   xo[p][q]  = X[row(q, lk)][16p + lr]  (matrix-core output layout)
 //   xa[p][kk] = X[lr][16p + 4kk + lk]    (matrix-core A-operand layout)
 // Panel p: B = X[:, p] - sum_{p' < p} X[:, p'] L[p, p']^T on
-// v_mfma_f64_16x16x4 with L read straight from the supernode block (the next
+// the matrix cores with L read straight from the supernode block (the next
 // panel's operands are prefetched into registers while the current panel
 // runs), then X[:, p] = B inv(D_p)^T; a 16 x 16 LDS tile converts between the
 // layouts.
-template <int NP>
-__device__ __forceinline__ void trsm_rows(const double* __restrict__ L, int ld,
-                                          const double* __restrict__ inv,
-                                          double* __restrict__ P, int w, int r, int row0,
-                                          double* __restrict__ tr, int lane) {
+template <class R, int NP>
+__device__ __forceinline__ void trsm_rows(const R* __restrict__ L, int ld,
+                                          const R* __restrict__ inv, R* __restrict__ P, int w,
+                                          int r, int row0, R* __restrict__ tr, int lane) {
+    typedef typename Mx<R>::acc Acc;
     const int lr = lane & 15, lk = lane >> 4;
-    double xo[NP][4], xa[NP][4];
+    R xo[NP][4], xa[NP][4];
     // operands of panel p: L[16p + lr][16pp + 4kk + lk] for pp < p, and inv(D_p);
     // the next panel's are loaded while the current one runs (two register sets)
-    double lv0[4 * NP], lv1[4 * NP], iv0[4], iv1[4];
-    auto fetch = [&](int p, double* lv, double* iv) {
+    R lv0[4 * NP], lv1[4 * NP], iv0[4], iv1[4];
+    auto fetch = [&](int p, R* lv, R* iv) {
         const int col = 16 * p + lr;
         const bool okc = col < w;
 #pragma unroll
@@ -331,8 +405,8 @@ __device__ __forceinline__ void trsm_rows(const double* __restrict__ L, int ld,
 #pragma unroll
                 for (int kk = 0; kk < 4; ++kk) {
                     const int k = 16 * pp + 4 * kk + lk;
-                    const double v = L[okc ? col + (int64_t)k * ld : 0];
-                    lv[4 * pp + kk] = okc ? v : 0.0;
+                    const R v = L[okc ? col + (int64_t)k * ld : 0];
+                    lv[4 * pp + kk] = okc ? v : R(0);
                 }
             }
         }
@@ -343,39 +417,36 @@ __device__ __forceinline__ void trsm_rows(const double* __restrict__ L, int ld,
     for (int p = 0; p < NP; ++p)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int row = row0 + 4 * q + lk, col = 16 * p + lr;
+            const int row = row0 + Mx<R>::row(q, lk), col = 16 * p + lr;
             const bool ok = row < r && col < w;
-            const double v = P[ok ? row + (int64_t)col * ld : 0];
-            xo[p][q] = ok ? v : 0.0;
+            const R v = P[ok ? row + (int64_t)col * ld : 0];
+            xo[p][q] = ok ? v : R(0);
         }
     fetch(0, lv0, iv0);
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-        double* lv = (p & 1) ? lv1 : lv0;
-        double* iv = (p & 1) ? iv1 : iv0;
+        R* lv = (p & 1) ? lv1 : lv0;
+        R* iv = (p & 1) ? iv1 : iv0;
         if (p + 1 < NP) fetch(p + 1, (p & 1) ? lv0 : lv1, (p & 1) ? iv0 : iv1);
-        v4d acc = v4d{xo[p][0], xo[p][1], xo[p][2], xo[p][3]};
+        Acc acc = {xo[p][0], xo[p][1], xo[p][2], xo[p][3]};
 #pragma unroll
         for (int pp = 0; pp < p; ++pp)
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk)
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-xa[pp][kk], lv[4 * pp + kk], acc, 0, 0,
-                                                           0);
+            for (int kk = 0; kk < 4; ++kk) acc = Mx<R>::mfma(-xa[pp][kk], lv[4 * pp + kk], acc);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) tr[(4 * q + lk) * 17 + lr] = acc[q];
+        for (int q = 0; q < 4; ++q) tr[Mx<R>::row(q, lk) * 17 + lr] = acc[q];
         __builtin_amdgcn_wave_barrier();
-        double bA[4];
+        R bA[4];
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) bA[kk] = tr[lr * 17 + 4 * kk + lk];
         __builtin_amdgcn_wave_barrier();
-        v4d out = v4d{0.0, 0.0, 0.0, 0.0};
+        Acc out = {R(0), R(0), R(0), R(0)};
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk)
-            out = __builtin_amdgcn_mfma_f64_16x16x4f64(bA[kk], iv[kk], out, 0, 0, 0);
+        for (int kk = 0; kk < 4; ++kk) out = Mx<R>::mfma(bA[kk], iv[kk], out);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             xo[p][q] = out[q];
-            tr[(4 * q + lk) * 17 + lr] = out[q];
+            tr[Mx<R>::row(q, lk) * 17 + lr] = out[q];
         }
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -386,7 +457,7 @@ __device__ __forceinline__ void trsm_rows(const double* __restrict__ L, int ld,
     for (int p = 0; p < NP; ++p)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int row = row0 + 4 * q + lk, col = 16 * p + lr;
+            const int row = row0 + Mx<R>::row(q, lk), col = 16 * p + lr;
             if (row < r && col < w) P[row + (int64_t)col * ld] = xo[p][q];
         }
 }
@@ -396,36 +467,38 @@ __device__ __forceinline__ void trsm_rows(const double* __restrict__ L, int ld,
 // 16-column panels with the inverses of the diagonal blocks from k_potrf.
 constexpr int kTrsmThreads = 256;
 
-__device__ __forceinline__ void trsm_task(RowBlock wb, const KArgs& a, double* __restrict__ arena,
-                                          const double* __restrict__ dinv) {
-    __shared__ double trs[kTrsmThreads / 64][16 * 17];
+template <class R>
+__device__ __forceinline__ void trsm_task(RowBlock wb, const KArgs& a, R* __restrict__ arena,
+                                          const R* __restrict__ dinv) {
+    __shared__ R trs[kTrsmThreads / 64][16 * 17];
     const int s = wb.s;
     const int w = a.sn_w[s], ld = a.sn_ld[s];
     const int r = (int)(a.rowptr[s + 1] - a.rowptr[s]) - w;
-    const double* __restrict__ L = arena + a.sn_off[s];
-    double* __restrict__ P = arena + a.sn_off[s] + w;
-    const double* __restrict__ inv = dinv + a.inv_off[s];
+    const R* __restrict__ L = arena + a.sn_off[s];
+    R* __restrict__ P = arena + a.sn_off[s] + w;
+    const R* __restrict__ inv = dinv + a.inv_off[s];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int row0 = wb.rb * kTile + wave * 16;
     if (row0 >= r) return;  // no barrier follows
-    double* tr = trs[wave];
+    R* tr = trs[wave];
     switch ((w + kPanel - 1) / kPanel) {
-        case 1: trsm_rows<1>(L, ld, inv, P, w, r, row0, tr, lane); break;
-        case 2: trsm_rows<2>(L, ld, inv, P, w, r, row0, tr, lane); break;
-        case 3: trsm_rows<3>(L, ld, inv, P, w, r, row0, tr, lane); break;
-        case 4: trsm_rows<4>(L, ld, inv, P, w, r, row0, tr, lane); break;
-        case 5: trsm_rows<5>(L, ld, inv, P, w, r, row0, tr, lane); break;
-        case 6: trsm_rows<6>(L, ld, inv, P, w, r, row0, tr, lane); break;
-        case 7: trsm_rows<7>(L, ld, inv, P, w, r, row0, tr, lane); break;
-        case 8: trsm_rows<8>(L, ld, inv, P, w, r, row0, tr, lane); break;
-        case 9: trsm_rows<9>(L, ld, inv, P, w, r, row0, tr, lane); break;
-        default: trsm_rows<10>(L, ld, inv, P, w, r, row0, tr, lane); break;
+        case 1: trsm_rows<R, 1>(L, ld, inv, P, w, r, row0, tr, lane); break;
+        case 2: trsm_rows<R, 2>(L, ld, inv, P, w, r, row0, tr, lane); break;
+        case 3: trsm_rows<R, 3>(L, ld, inv, P, w, r, row0, tr, lane); break;
+        case 4: trsm_rows<R, 4>(L, ld, inv, P, w, r, row0, tr, lane); break;
+        case 5: trsm_rows<R, 5>(L, ld, inv, P, w, r, row0, tr, lane); break;
+        case 6: trsm_rows<R, 6>(L, ld, inv, P, w, r, row0, tr, lane); break;
+        case 7: trsm_rows<R, 7>(L, ld, inv, P, w, r, row0, tr, lane); break;
+        case 8: trsm_rows<R, 8>(L, ld, inv, P, w, r, row0, tr, lane); break;
+        case 9: trsm_rows<R, 9>(L, ld, inv, P, w, r, row0, tr, lane); break;
+        default: trsm_rows<R, 10>(L, ld, inv, P, w, r, row0, tr, lane); break;
     }
 }
 
+template <class R>
 __global__ __launch_bounds__(kTrsmThreads) void k_trsm(const RowBlock* __restrict__ work, KArgs a,
-                                                       double* __restrict__ arena,
-                                                       const double* __restrict__ dinv) {
+                                                       R* __restrict__ arena,
+                                                       const R* __restrict__ dinv) {
     trsm_task(work[blockIdx.x], a, arena, dinv);
 }
 
@@ -449,7 +522,7 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
 }
 
 // 256 threads = 4 waves in a 2 x 2 grid, each wave a 32 x 32 quarter of the
-// 64 x 64 tile as 2 x 2 blocks of v_mfma_f64_16x16x4.  The K dimension (the
+// 64 x 64 tile as 2 x 2 blocks of 16 x 16 x 4 matrix-core products.  The K dimension (the
 // source width w) goes through LDS in chunks of 16 columns, double buffered:
 // the next chunk is loaded into registers while the current one feeds the
 // matrix cores.  Operand lanes: lane l holds element (row l % 16, k l / 16) of
@@ -462,10 +535,12 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
 // Update tile by one workgroup of 4 waves.  If coltgt is given (an LDS array
 // of kTile entries), it receives each column's target supernode (-1 past the
 // panel), in non-decreasing order.
+template <class R>
 __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
                                             const uint8_t* __restrict__ pair_excl,
-                                            double* __restrict__ arena, int* coltgt) {
-    __shared__ double lds[2 * 2 * kChunk * kLdsStride > kTile * kCtPad
+                                            R* __restrict__ arena, int* coltgt) {
+    typedef typename Mx<R>::acc Acc;
+    __shared__ R lds[2 * 2 * kChunk * kLdsStride > kTile * kCtPad
                               ? 2 * 2 * kChunk * kLdsStride
                               : kTile * kCtPad];
     __shared__ int64_t colbase[kTile];
@@ -475,7 +550,7 @@ __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
     const int w = a.sn_w[s], ld = a.sn_ld[s];
     const int64_t rp = a.rowptr[s];
     const int r = (int)(a.rowptr[s + 1] - rp) - w;
-    const double* __restrict__ P = arena + a.sn_off[s] + w;
+    const R* __restrict__ P = arena + a.sn_off[s] + w;
     const int i0 = tile.bi * kTile, c0 = tile.bj * kTile;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int wr = wave >> 1, wc = wave & 1;
@@ -485,18 +560,18 @@ __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
     // staging: thread -> row (tid & 63), columns kq*4 .. kq*4+3 of the chunk
     const int srow = tid & 63, kq = tid >> 6;
     const bool va = i0 + srow < r, vb = c0 + srow < r;
-    double* As = lds;                               // [buf][k][row]
-    double* Bs = lds + 2 * kChunk * kLdsStride;     // [buf][k][row]
+    R* As = lds;                               // [buf][k][row]
+    R* Bs = lds + 2 * kChunk * kLdsStride;     // [buf][k][row]
     const int nchunk = (w + kChunk - 1) / kChunk;
-    double ra[4], rb[4];
+    R ra[4], rb[4];
     auto fetch = [&](int chunk) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int k = chunk * kChunk + kq * 4 + u;
             const bool vk = k < w;
-            const double* __restrict__ col = P + (int64_t)k * ld;
-            ra[u] = (vk && va) ? col[i0 + srow] : 0.0;
-            rb[u] = (!diag && vk && vb) ? col[c0 + srow] : 0.0;
+            const R* __restrict__ col = P + (int64_t)k * ld;
+            ra[u] = (vk && va) ? col[i0 + srow] : R(0);
+            rb[u] = (!diag && vk && vb) ? col[c0 + srow] : R(0);
         }
     };
     auto stash = [&](int buf) {
@@ -522,13 +597,13 @@ __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
             my_excl = pair_excl ? pair_excl[p] : 0;
         }
     }
-    v4d acc[2][2];
+    Acc acc[2][2];
     for (int m = 0; m < 2; ++m)
-        for (int n = 0; n < 2; ++n) acc[m][n] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int n = 0; n < 2; ++n) acc[m][n] = Acc{R(0), R(0), R(0), R(0)};
     fetch(0);
     stash(0);
     __syncthreads();
-    const double* Bsrc = diag ? As : Bs;
+    const R* Bsrc = diag ? As : Bs;
     for (int ch = 0; ch < nchunk; ++ch) {
         const int buf = ch & 1;
         if (ch + 1 < nchunk) fetch(ch + 1);
@@ -536,25 +611,24 @@ __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
 #pragma unroll
             for (int kk = 0; kk < kChunk / 4; ++kk) {
                 const int krow = (buf * kChunk + kk * 4 + lk) * kLdsStride;
-                const double a0 = As[krow + wr * 32 + lr];
-                const double a1 = As[krow + wr * 32 + 16 + lr];
-                const double b0 = Bsrc[krow + wc * 32 + lr];
-                const double b1 = Bsrc[krow + wc * 32 + 16 + lr];
-                acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-                acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-                acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-                acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+                const R a0 = As[krow + wr * 32 + lr];
+                const R a1 = As[krow + wr * 32 + 16 + lr];
+                const R b0 = Bsrc[krow + wc * 32 + lr];
+                const R b1 = Bsrc[krow + wc * 32 + 16 + lr];
+                acc[0][0] = Mx<R>::mfma(a0, b0, acc[0][0]);
+                acc[0][1] = Mx<R>::mfma(a0, b1, acc[0][1]);
+                acc[1][0] = Mx<R>::mfma(a1, b0, acc[1][0]);
+                acc[1][1] = Mx<R>::mfma(a1, b1, acc[1][1]);
             }
         }
         if (ch + 1 < nchunk) stash(buf ^ 1);
         __syncthreads();
     }
-    // accumulator layout (v_mfma_f64_16x16x4): register q of lane l holds D[4q + l/16][l%16]
-    double* Ct = lds;  // the staging buffers are free now
+    R* Ct = lds;  // the staging buffers are free now
     for (int m = 0; m < 2; ++m)
         for (int n = 0; n < 2; ++n)
             for (int q = 0; q < 4; ++q) {
-                const int i = wr * 32 + m * 16 + 4 * q + lk;
+                const int i = wr * 32 + m * 16 + Mx<R>::row(q, lk);
                 const int c = wc * 32 + n * 16 + lr;
                 Ct[c * kCtPad + i] = acc[m][n][q];
             }
@@ -576,26 +650,27 @@ __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
         ok[u] = gi < r && gc < r && gi >= gc;
         dst[u] = ok[u] ? colbase[c] + a.rel[relbase[c] + gi] : 0;
     }
-    double old[kPer];
+    R old[kPer];
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const int c = (tid >> 6) + 4 * u;
-        old[u] = (ok[u] && colexcl[c]) ? arena[dst[u]] : 0.0;
+        old[u] = (ok[u] && colexcl[c]) ? arena[dst[u]] : R(0);
     }
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         if (!ok[u]) continue;
         const int c = (tid >> 6) + 4 * u;
-        const double v = Ct[c * kCtPad + i];
+        const R v = Ct[c * kCtPad + i];
         if (colexcl[c]) arena[dst[u]] = old[u] - v;
         else unsafeAtomicAdd(arena + dst[u], -v);
     }
 }
 
+template <class R>
 __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tiles, int64_t ntiles,
                                                 KArgs a, const uint8_t* __restrict__ pair_excl,
-                                                double* __restrict__ arena) {
-    update_task(tiles[xcd_tile(blockIdx.x, ntiles)], a, pair_excl, arena, nullptr);
+                                                R* __restrict__ arena) {
+    update_task<R>(tiles[xcd_tile(blockIdx.x, ntiles)], a, pair_excl, arena, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -649,9 +724,10 @@ constexpr int kSchedThreads = 256;
 static_assert(kSchedThreads == kPotrfThreads && kSchedThreads == kTrsmThreads,
               "one workgroup shape runs every task kind");
 
+template <class R>
 __global__ __launch_bounds__(kSchedThreads) void k_sched(
     const Task* __restrict__ tasks, int64_t ntasks, const int32_t* __restrict__ rb_base, KArgs a,
-    double* __restrict__ arena, double* __restrict__ dinv, int32_t* __restrict__ status,
+    R* __restrict__ arena, R* __restrict__ dinv, int32_t* __restrict__ status,
     int32_t* __restrict__ state, int64_t nsup, int64_t nrowblk, uint64_t wait_ticks) {
     extern __shared__ double T[];
     __shared__ int32_t sh_ticket;
@@ -687,11 +763,11 @@ __global__ __launch_bounds__(kSchedThreads) void k_sched(
         __threadfence();  // acquire for every wave: inputs written by other workers
         const Task tk = tasks[t];
         if (tk.kind == kTaskF) {
-            potrf_task(tk.s, a, arena, dinv, status, T);
+            diag_factor(tk.s, a, arena, dinv, status, status + 1, T);
         } else if (tk.kind == kTaskT) {
-            trsm_task(RowBlock{tk.s, tk.a}, a, arena, dinv);
+            trsm_task<R>(RowBlock{tk.s, tk.a}, a, arena, dinv);
         } else {
-            update_task(UpdTile{tk.s, tk.a, tk.b}, a, nullptr, arena, coltgt);
+            update_task<R>(UpdTile{tk.s, tk.a, tk.b}, a, nullptr, arena, coltgt);
         }
         __threadfence();  // release: this task's results before its signal
         __syncthreads();
@@ -748,38 +824,40 @@ void mark_end(spc_numeric* num, hipStream_t st, int cls, int a) {
 
 }  // namespace
 
-// Launches of one level: diagonal factorizations and panel solves on stream
-// fs, then the update tiles [u0, u1) of the level's list on stream us.
+// Launches of one level: diagonal factorizations and panel solves, then the
+// update tiles [u0, u1) of the level's list.
 namespace {
 
+template <class R>
 void launch_ft(spc_numeric* num, const DevicePlan* P, const Symbolic& S, const KArgs& a,
                int32_t l, hipStream_t st) {
     const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1];
     const int wmax = P->level_maxw[l];
+    // room for the packed triangle in FP64 (also the FP32 kernel's fallback pass)
     const size_t lds_tri = ((size_t)wmax * (wmax + 1) / 2 + 1) * sizeof(double);
     int ev = mark_begin(num, st);
-    hipLaunchKernelGGL(k_potrf, dim3(n1 - n0), dim3(kPotrfThreads), lds_tri, st, P->level_sn + n0,
-                       a, num->arena, num->dinv, num->status_dev);
+    hipLaunchKernelGGL(k_potrf<R>, dim3(n1 - n0), dim3(kPotrfThreads), lds_tri, st,
+                       P->level_sn + n0, a, (R*)num->arena, (R*)num->dinv, num->status_dev);
     mark_end(num, st, 1, ev);
     const int64_t rb0 = P->rowblk_ptr[l], rb1 = P->rowblk_ptr[l + 1];
     if (rb1 > rb0) {
         ev = mark_begin(num, st);
-        hipLaunchKernelGGL(k_trsm, dim3((unsigned)(rb1 - rb0)), dim3(kTrsmThreads), 0, st,
-                           P->rowblk + rb0, a, num->arena, (const double*)num->dinv);
+        hipLaunchKernelGGL(k_trsm<R>, dim3((unsigned)(rb1 - rb0)), dim3(kTrsmThreads), 0, st,
+                           P->rowblk + rb0, a, (R*)num->arena, (const R*)num->dinv);
         mark_end(num, st, 2, ev);
     }
 }
 
+template <class R>
 void launch_update(spc_numeric* num, const DevicePlan* P, const KArgs& a, int64_t u0, int64_t u1,
                    bool exclusive_ok, hipStream_t st) {
     if (u1 <= u0) return;
     const int ev = mark_begin(num, st);
-    hipLaunchKernelGGL(k_update, dim3((unsigned)(u1 - u0)), dim3(256), 0, st, P->tiles + u0, u1 - u0,
-                       a, exclusive_ok ? (const uint8_t*)P->pair_excl : nullptr, num->arena);
+    hipLaunchKernelGGL(k_update<R>, dim3((unsigned)(u1 - u0)), dim3(256), 0, st, P->tiles + u0,
+                       u1 - u0, a, exclusive_ok ? (const uint8_t*)P->pair_excl : nullptr,
+                       (R*)num->arena);
     mark_end(num, st, 3, ev);
 }
-
-}  // namespace
 
 // Factorization driver.  sched 0: one stream, level by level (every
 // dependency points to a lower level of the supernodal elimination tree).
@@ -788,25 +866,26 @@ void launch_update(spc_numeric* num, const DevicePlan* P, const KArgs& a, int64_
 // next level run on the caller's stream; the other ("bulk") update tiles of
 // level l run on a second stream concurrently with level l + 1, and level l
 // waits only for the bulk tiles of levels <= l - 2.  Concurrent tiles may hit
-// one target, so the lookahead uses atomic adds throughout.
-int32_t run_factor(spc_numeric* num, const double* values, hipStream_t st) {
+// one target, so the lookahead uses atomic adds throughout.  sched 2: one
+// persistent launch of the task queue.
+template <class R>
+int32_t run_factor_t(spc_numeric* num, const double* values, hipStream_t st) {
     const Symbolic& S = num->sym->S;
     const DevicePlan* P = num->plan;
     const KArgs a = kargs(P);
-    num->stream = st;
-    num->factored = false;
-    num->status_known = false;
-    num->marks.clear();
-    num->next_event = 0;
+    R* arena = (R*)num->arena;
     int ev = mark_begin(num, st);
     if (S.arena > 0)
-        hipLaunchKernelGGL(k_fill, dim3(grid_for(S.arena, 256)), dim3(256), 0, st, num->arena,
-                           S.arena, 0.0);
+        hipLaunchKernelGGL(k_fill<R>, dim3(grid_for(S.arena, 256)), dim3(256), 0, st, arena,
+                           S.arena, R(0));
+    // status[0]: smallest failing column (INT32_MAX = none); status[1]: FP64 fallbacks
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, num->status_dev, (int64_t)1,
                        (int32_t)INT32_MAX);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, num->status_dev + 1, (int64_t)1,
+                       (int32_t)0);
     if (S.nnz_a > 0)
-        hipLaunchKernelGGL(k_load, dim3(grid_for(S.nnz_a, 256)), dim3(256), 0, st, values,
-                           P->slot, num->arena, S.nnz_a);
+        hipLaunchKernelGGL(k_load<R>, dim3(grid_for(S.nnz_a, 256)), dim3(256), 0, st, values,
+                           P->slot, arena, S.nnz_a);
     mark_end(num, st, 0, ev);
     const int32_t nl = (int32_t)S.level_ptr.size() - 1;
     if (num->sched == 2) {
@@ -819,22 +898,23 @@ int32_t run_factor(spc_numeric* num, const double* values, hipStream_t st) {
             HIP_TRY(hipGetDevice(&dev));
             HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
             HIP_TRY(hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev));
-            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sched, kSchedThreads,
-                                                                lds_tri));
+            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sched<R>,
+                                                                kSchedThreads, lds_tri));
             const int64_t workers =
                 std::min<int64_t>(P->ntasks, (int64_t)std::max(1, ncu) * std::max(1, per_cu));
-            const uint64_t ticks = (uint64_t)num->spin_limit * (uint64_t)std::max(1, clock_khz) / 1000;
+            const uint64_t ticks =
+                (uint64_t)num->spin_limit * (uint64_t)std::max(1, clock_khz) / 1000;
             ev = mark_begin(num, st);
-            hipLaunchKernelGGL(k_sched, dim3((unsigned)workers), dim3(kSchedThreads), lds_tri, st,
-                               (const Task*)P->tasks, P->ntasks, (const int32_t*)P->rb_base, a,
-                               num->arena, num->dinv, num->status_dev, num->sched_state, S.nsup,
-                               P->nrowblk, ticks);
+            hipLaunchKernelGGL(k_sched<R>, dim3((unsigned)workers), dim3(kSchedThreads), lds_tri,
+                               st, (const Task*)P->tasks, P->ntasks, (const int32_t*)P->rb_base,
+                               a, arena, (R*)num->dinv, num->status_dev, num->sched_state,
+                               S.nsup, P->nrowblk, ticks);
             mark_end(num, st, 4, ev);
         }
     } else if (num->sched == 0 || nl < 2) {
         for (int32_t l = 0; l < nl; ++l) {
-            launch_ft(num, P, S, a, l, st);
-            launch_update(num, P, a, P->tile_ptr[l], P->tile_ptr[l + 1], true, st);
+            launch_ft<R>(num, P, S, a, l, st);
+            launch_update<R>(num, P, a, P->tile_ptr[l], P->tile_ptr[l + 1], true, st);
         }
     } else {
         hipStream_t sb = num->bulk;
@@ -850,16 +930,30 @@ int32_t run_factor(spc_numeric* num, const double* values, hipStream_t st) {
         HIP_TRY(hipStreamWaitEvent(sb, E[0], 0));
         for (int32_t l = 0; l < nl; ++l) {
             if (l >= 2) HIP_TRY(hipStreamWaitEvent(st, E[2 + 2 * (l - 2)], 0));
-            launch_ft(num, P, S, a, l, st);
+            launch_ft<R>(num, P, S, a, l, st);
             HIP_TRY(hipEventRecord(E[1 + 2 * l], st));
             const int64_t u0 = P->tile_ptr[l], uc = u0 + P->tile_crit[l], u1 = P->tile_ptr[l + 1];
-            launch_update(num, P, a, u0, uc, false, st);
+            launch_update<R>(num, P, a, u0, uc, false, st);
             HIP_TRY(hipStreamWaitEvent(sb, E[1 + 2 * l], 0));
-            launch_update(num, P, a, uc, u1, false, sb);
+            launch_update<R>(num, P, a, uc, u1, false, sb);
             HIP_TRY(hipEventRecord(E[2 + 2 * l], sb));
         }
         HIP_TRY(hipStreamWaitEvent(st, E[2 + 2 * (nl - 1)], 0));
     }
+    return OK;
+}
+
+}  // namespace
+
+int32_t run_factor(spc_numeric* num, const double* values, hipStream_t st) {
+    num->stream = st;
+    num->factored = false;
+    num->status_known = false;
+    num->marks.clear();
+    num->next_event = 0;
+    const int32_t r = num->prec == 1 ? run_factor_t<float>(num, values, st)
+                                     : run_factor_t<double>(num, values, st);
+    if (r != OK) return r;
     HIP_TRY(hipGetLastError());
     num->factored = true;
     return OK;
@@ -874,12 +968,12 @@ int32_t configure_kernels() {
     done = 1;
     result = configure_solve_kernels();
     const int lds_max = (int)(((size_t)kMaxWidth * (kMaxWidth + 1) / 2 + 1) * sizeof(double));
-    if (hipFuncSetAttribute((const void*)k_potrf, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            lds_max) != hipSuccess)
-        result = ERR_HIP;
-    if (hipFuncSetAttribute((const void*)k_sched, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            lds_max) != hipSuccess)
-        result = ERR_HIP;
+    const void* big[] = {(const void*)k_potrf<double>, (const void*)k_potrf<float>,
+                         (const void*)k_sched<double>, (const void*)k_sched<float>};
+    for (const void* f : big)
+        if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max) !=
+            hipSuccess)
+            result = ERR_HIP;
     return result;
 }
 

@@ -1,0 +1,333 @@
+// Iterative refinement in FP64 around the supernodal factor: the mixed-
+// precision form of the solve.  The factor (FP32 or FP64) gives corrections;
+// the residual r = b - A x, its norms and the update x += d stay in FP64:
+//
+//   x = 0
+//   repeat:  r = b - A x                        (FP64, full CSR of A)
+//            eta_c = ||r_c|| / (||A|| ||x_c|| + ||b_c||)   (inf-norms, per column)
+//            stop when every eta_c <= tol
+//            d = (L L^T)^{-1} P (r / ||r||)    (gather, scaled, in the factor's type;
+//                                              level sweeps of the solve)
+//            x += ||r|| P^T d                  (FP64)
+//
+// Scaling r by its norm before the rounding to FP32 keeps every correction
+// solve in the normal range of FP32.  eta is the normwise backward error of
+// Rigal and Gaches in the infinity norm.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "runtime.hpp"
+
+namespace spc {
+
+#define HIP_TRY(x)                               \
+    do {                                         \
+        if ((x) != hipSuccess) return ERR_HIP;   \
+    } while (0)
+
+namespace {
+
+int grid_of(int64_t n) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192));
+}
+
+// Non-negative doubles order like their bit patterns as unsigned integers.
+__device__ __forceinline__ void atomic_max_nonneg(double* p, double v) {
+    atomicMax((unsigned long long*)p, (unsigned long long)__double_as_longlong(v));
+}
+
+// Maximum over a workgroup of 256 threads, then one atomic per workgroup.
+__device__ __forceinline__ void block_max_to(double* out, double v) {
+    __shared__ double part[4];
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) atomic_max_nonneg(out, fmax(fmax(part[0], part[1]), fmax(part[2], part[3])));
+    __syncthreads();
+}
+
+__global__ void k_fill_f64(double* __restrict__ p, int64_t n, double v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// x[:, c] = 0 for the caller's column-major x with leading dimension ldx.
+__global__ void k_zero_cols(double* __restrict__ x, int64_t ldx, int64_t n, int nrhs) {
+    const int64_t total = n * nrhs;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = e / n, i = e - c * n;
+        x[i + c * ldx] = 0.0;
+    }
+}
+
+// a_val[q] = values[a_src[q]]: the caller's lower-CSC values into the full CSR.
+__global__ void k_gather_vals(const double* __restrict__ values, const int64_t* __restrict__ src,
+                              double* __restrict__ aval, int64_t nnz) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nnz;
+         q += (int64_t)gridDim.x * blockDim.x)
+        aval[q] = values[src[q]];
+}
+
+// ||A||_inf = max over rows of the absolute row sum.  Grid-stride loops keep
+// every thread of a workgroup alive to the block reduction.
+__global__ __launch_bounds__(256) void k_anorm(const int64_t* __restrict__ ptr,
+                                               const double* __restrict__ val, int64_t n,
+                                               double* __restrict__ out) {
+    double m = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int64_t q = ptr[i]; q < ptr[i + 1]; ++q) s += fabs(val[q]);
+        m = fmax(m, s);
+    }
+    block_max_to(out, m);
+}
+
+// ||v_c||_inf for the nrhs columns of v (leading dimension ld); blockIdx.y = c.
+__global__ __launch_bounds__(256) void k_colmax(const double* __restrict__ v, int64_t ld, int64_t n,
+                                                double* __restrict__ out) {
+    const int c = blockIdx.y;
+    double m = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        m = fmax(m, fabs(v[i + c * ld]));
+    block_max_to(out + c, m);
+}
+
+// r_c = b_c - A x_c and ||r_c||_inf, one thread per row; blockIdx.y = c.
+__global__ __launch_bounds__(256) void k_resid(const int64_t* __restrict__ ptr,
+                                               const int32_t* __restrict__ col,
+                                               const double* __restrict__ val,
+                                               const double* __restrict__ b, int64_t ldb,
+                                               const double* __restrict__ x, int64_t ldx,
+                                               double* __restrict__ r, int64_t n,
+                                               double* __restrict__ rnorm) {
+    const int c = blockIdx.y;
+    const double* __restrict__ xc = x + c * ldx;
+    double m = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double s0 = 0.0, s1 = 0.0;
+        int64_t q = ptr[i];
+        const int64_t q1 = ptr[i + 1];
+        for (; q + 1 < q1; q += 2) {
+            s0 += val[q] * xc[col[q]];
+            s1 += val[q + 1] * xc[col[q + 1]];
+        }
+        if (q < q1) s0 += val[q] * xc[col[q]];
+        const double ri = b[i + c * ldb] - (s0 + s1);
+        r[i + c * n] = ri;
+        m = fmax(m, fabs(ri));
+    }
+    block_max_to(rnorm + c, m);
+}
+
+// eta_c and the scale 1 / ||r_c|| of the next correction (0 when r_c = 0).
+__global__ void k_eta(const double* __restrict__ rn, const double* __restrict__ xn,
+                      const double* __restrict__ bn, const double* __restrict__ anorm,
+                      double* __restrict__ eta, double* __restrict__ scale, int nrhs) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nrhs) return;
+    const double den = anorm[0] * xn[c] + bn[c];
+    eta[c] = den > 0.0 ? rn[c] / den : (rn[c] > 0.0 ? 1.0 : 0.0);
+    scale[c] = rn[c] > 0.0 ? 1.0 / rn[c] : 0.0;
+}
+
+// y = P (r / ||r||) rounded to the factor's type.
+template <class R>
+__global__ void k_gather_scaled(const double* __restrict__ r, const int32_t* __restrict__ perm,
+                                const double* __restrict__ scale, R* __restrict__ y, int64_t n,
+                                int nrhs) {
+    const int64_t total = n * nrhs;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = e / n, i = e - c * n;
+        y[e] = (R)(r[perm[i] + c * n] * scale[c]);
+    }
+}
+
+// x += ||r|| P^T y in FP64.
+template <class R>
+__global__ void k_scatter_add(const R* __restrict__ y, const int32_t* __restrict__ perm,
+                              const double* __restrict__ rn, double* __restrict__ x, int64_t ldx,
+                              int64_t n, int nrhs) {
+    const int64_t total = n * nrhs;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = e / n, i = e - c * n;
+        x[perm[i] + c * ldx] += (double)y[e] * rn[c];
+    }
+}
+
+template <class R>
+void correction(spc_numeric* num, int32_t nrhs, const double* r, const double* scale,
+                const double* rn, double* x, int64_t ldx, hipStream_t st, int32_t* rc) {
+    const int64_t n = num->sym->S.n;
+    const int32_t* perm = num->plan->perm;
+    const int g = grid_of(n * nrhs);
+    hipLaunchKernelGGL(k_gather_scaled<R>, dim3(g), dim3(256), 0, st, r, perm, scale,
+                       (R*)num->work, n, nrhs);
+    *rc = run_sweeps(num, nrhs, st);
+    if (*rc != OK) return;
+    hipLaunchKernelGGL(k_scatter_add<R>, dim3(g), dim3(256), 0, st, (const R*)num->work, perm, rn,
+                       x, ldx, n, nrhs);
+}
+
+}  // namespace
+
+// Full symmetric CSR of the input matrix A (original numbering), built on
+// the host from the permuted lower pattern: entry q of C = lower(P A P^T) in
+// row i, column j is A(perm[i], perm[j]); each stored entry appears in row
+// perm[i] and, off the diagonal, in row perm[j].  a_src maps every CSR entry
+// to the caller's value index.
+static int32_t build_refine_matrix(spc_numeric* num) {
+    const Symbolic& S = num->sym->S;
+    const int64_t n = S.n, nnz = S.nnz_a;
+    std::vector<int64_t> inv_amap((size_t)nnz);
+    for (int64_t k = 0; k < nnz; ++k) inv_amap[(size_t)S.amap[k]] = k;
+    std::vector<int64_t> ptr((size_t)n + 1, 0);
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t q = S.Cp[j]; q < S.Cp[j + 1]; ++q) {
+            const int64_t i = S.Ci[q];
+            ptr[(size_t)S.perm[i] + 1]++;
+            if (i != j) ptr[(size_t)S.perm[j] + 1]++;
+        }
+    for (int64_t i = 0; i < n; ++i) ptr[i + 1] += ptr[i];
+    const int64_t nnzf = ptr[n];
+    num->a_nnz = nnzf;
+    std::vector<int32_t> col((size_t)std::max<int64_t>(nnzf, 1));
+    std::vector<int64_t> src((size_t)std::max<int64_t>(nnzf, 1));
+    std::vector<int64_t> next(ptr.begin(), ptr.end() - 1);
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t q = S.Cp[j]; q < S.Cp[j + 1]; ++q) {
+            const int64_t i = S.Ci[q];
+            const int32_t oi = S.perm[i], oj = S.perm[j];
+            int64_t at = next[oi]++;
+            col[at] = oj;
+            src[at] = inv_amap[q];
+            if (i != j) {
+                at = next[oj]++;
+                col[at] = oi;
+                src[at] = inv_amap[q];
+            }
+        }
+    const size_t b_ptr = sizeof(int64_t) * (size_t)(n + 1);
+    const size_t b_nz = (size_t)std::max<int64_t>(nnzf, 1);
+    if (hipMalloc(&num->a_ptr, b_ptr) != hipSuccess) return ERR_OOM;
+    if (hipMalloc(&num->a_col, sizeof(int32_t) * b_nz) != hipSuccess) return ERR_OOM;
+    if (hipMalloc(&num->a_src, sizeof(int64_t) * b_nz) != hipSuccess) return ERR_OOM;
+    if (hipMalloc(&num->a_val, sizeof(double) * b_nz) != hipSuccess) return ERR_OOM;
+    if (hipMalloc(&num->a_norm, 256) != hipSuccess) return ERR_OOM;
+    HIP_TRY(hipMemcpy(num->a_ptr, ptr.data(), b_ptr, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(num->a_col, col.data(), sizeof(int32_t) * b_nz, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(num->a_src, src.data(), sizeof(int64_t) * b_nz, hipMemcpyHostToDevice));
+    return OK;
+}
+
+int32_t load_refine_matrix(spc_numeric* num, const double* values, hipStream_t st) {
+    const Symbolic& S = num->sym->S;
+    if (!num->a_ptr) {
+        const int32_t r = build_refine_matrix(num);
+        if (r != OK) return r;
+    }
+    const int64_t nnzf = num->a_nnz;
+    if (nnzf > 0)
+        hipLaunchKernelGGL(k_gather_vals, dim3(grid_of(nnzf)), dim3(256), 0, st, values,
+                           (const int64_t*)num->a_src, num->a_val, nnzf);
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, st, num->a_norm, (int64_t)1, 0.0);
+    if (S.n > 0)
+        hipLaunchKernelGGL(k_anorm, dim3(grid_of(S.n)), dim3(256), 0, st,
+                           (const int64_t*)num->a_ptr, (const double*)num->a_val, S.n,
+                           num->a_norm);
+    HIP_TRY(hipGetLastError());
+    return OK;
+}
+
+void free_refine(spc_numeric* num) {
+    (void)hipFree(num->a_ptr);
+    (void)hipFree(num->a_col);
+    (void)hipFree(num->a_src);
+    (void)hipFree(num->a_val);
+    (void)hipFree(num->a_norm);
+    (void)hipFree(num->ir_work);
+    if (num->ir_host) (void)hipHostFree(num->ir_host);
+    num->a_ptr = nullptr;
+    num->a_col = nullptr;
+    num->a_src = nullptr;
+    num->a_val = nullptr;
+    num->a_norm = nullptr;
+    num->ir_work = nullptr;
+    num->ir_host = nullptr;
+    num->ir_cols = 0;
+}
+
+int32_t run_refine(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb, double* x,
+                   int64_t ldx, double tol, int32_t max_iter, hipStream_t st, int32_t* iters,
+                   double* berr) {
+    const int64_t n = num->sym->S.n;
+    if (iters) *iters = 0;
+    if (n == 0 || nrhs == 0) {
+        for (int32_t c = 0; berr && c < nrhs; ++c) berr[c] = 0.0;
+        return OK;
+    }
+    int32_t rc = ensure_solve_work(num, nrhs);
+    if (rc != OK) return rc;
+    if (num->ir_cols < nrhs) {
+        (void)hipFree(num->ir_work);
+        if (num->ir_host) (void)hipHostFree(num->ir_host);
+        num->ir_work = nullptr;
+        num->ir_host = nullptr;
+        num->ir_cols = 0;
+        if (hipMalloc(&num->ir_work, sizeof(double) * ((size_t)n + 5) * nrhs) != hipSuccess)
+            return ERR_OOM;
+        if (hipHostMalloc(&num->ir_host, sizeof(double) * nrhs, hipHostMallocDefault) !=
+            hipSuccess)
+            return ERR_OOM;
+        num->ir_cols = nrhs;
+    }
+    double* r = num->ir_work;
+    double* bn = r + (size_t)n * nrhs;
+    double* xn = bn + nrhs;
+    double* rn = xn + nrhs;
+    double* eta = rn + nrhs;
+    double* scale = eta + nrhs;
+    const int gy = std::min<int64_t>(grid_of(n), 1024);
+    hipLaunchKernelGGL(k_zero_cols, dim3(grid_of(n * nrhs)), dim3(256), 0, st, x, ldx, n, nrhs);
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, st, bn, (int64_t)nrhs, 0.0);
+    hipLaunchKernelGGL(k_colmax, dim3(gy, nrhs), dim3(256), 0, st, b, ldb, n, bn);
+    for (int32_t it = 0;; ++it) {
+        hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, st, xn, (int64_t)(2 * nrhs), 0.0);
+        hipLaunchKernelGGL(k_resid, dim3(gy, nrhs), dim3(256), 0, st, (const int64_t*)num->a_ptr,
+                           (const int32_t*)num->a_col, (const double*)num->a_val, b, ldb,
+                           (const double*)x, ldx, r, n, rn);
+        hipLaunchKernelGGL(k_colmax, dim3(gy, nrhs), dim3(256), 0, st, (const double*)x, ldx, n,
+                           xn);
+        hipLaunchKernelGGL(k_eta, dim3((nrhs + 63) / 64), dim3(64), 0, st, (const double*)rn,
+                           (const double*)xn, (const double*)bn, (const double*)num->a_norm, eta,
+                           scale, nrhs);
+        HIP_TRY(hipMemcpyAsync(num->ir_host, eta, sizeof(double) * nrhs, hipMemcpyDeviceToHost,
+                               st));
+        HIP_TRY(hipStreamSynchronize(st));
+        bool done = true;
+        for (int32_t c = 0; c < nrhs; ++c) {
+            const double e = num->ir_host[c];
+            if (berr) berr[c] = e;
+            if (!(e <= tol)) done = false;
+        }
+        if (iters) *iters = it;
+        if (done) return OK;
+        if (it >= max_iter) return ERR_NOT_CONVERGED;
+        if (num->prec == 1)
+            correction<float>(num, nrhs, r, scale, rn, x, ldx, st, &rc);
+        else
+            correction<double>(num, nrhs, r, scale, rn, x, ldx, st, &rc);
+        if (rc != OK) return rc;
+        HIP_TRY(hipGetLastError());
+    }
+}
+
+}  // namespace spc

@@ -99,10 +99,11 @@ struct spc_numeric {
     spc_symbolic* sym = nullptr;
     spc::DevicePlan* plan = nullptr;
     int device = -1;
-    double* arena = nullptr;
-    double* dinv = nullptr;         // inverses of the kPanel diagonal blocks
-    int32_t* status_dev = nullptr;  // INT32_MAX = no failure
-    double* work = nullptr;         // solve vector, n x work_cols
+    int32_t prec = 0;               // 0: FP64 factor; 1: FP32 factor (FP64 refinement)
+    void* arena = nullptr;          // supernode blocks, double or float by prec
+    void* dinv = nullptr;           // inverses of the kPanel diagonal blocks, same type
+    int32_t* status_dev = nullptr;  // [0] failing column (INT32_MAX = none), [1] FP64 fallbacks
+    void* work = nullptr;           // solve vectors y and t, n x work_cols each, factor type
     int32_t sched = 0;              // 0 level sets, 1 level sets with lookahead
     hipStream_t bulk = nullptr;     // second stream for the lookahead schedule
     std::vector<hipEvent_t> sync_ev; // per-level ordering events between the two streams
@@ -116,6 +117,17 @@ struct spc_numeric {
     int32_t host_status = 0;
     bool status_known = false;  // host_status holds the current factorization's status
     bool factored = false;
+    // iterative refinement (FP64): symmetric matrix in full CSR form, values
+    // gathered from the caller's array at every factorization
+    int64_t a_nnz = 0;              // entries of the full CSR
+    int64_t* a_ptr = nullptr;       // n + 1
+    int32_t* a_col = nullptr;       // nnz_full
+    int64_t* a_src = nullptr;       // nnz_full: input entry of each CSR entry
+    double* a_val = nullptr;        // nnz_full
+    double* a_norm = nullptr;       // ||A||_inf (device scalar)
+    double* ir_work = nullptr;      // residuals n x ir_cols, then 4 x ir_cols norms/scales
+    int64_t ir_cols = 0;
+    double* ir_host = nullptr;      // pinned: backward errors of the current iterate
     // optional per-launch event timing (class, start, stop)
     bool timing = false;
     std::vector<hipEvent_t> events;
@@ -136,6 +148,15 @@ void free_plan(DevicePlan* p);
 int32_t run_factor(spc_numeric* num, const double* values, hipStream_t stream);
 int32_t run_solve(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb, double* x,
                   int64_t ldx, hipStream_t stream);
+// Solve sweeps on the internal vectors after they hold the permuted right-hand sides.
+int32_t run_sweeps(spc_numeric* num, int32_t nrhs, hipStream_t stream);
+int32_t ensure_solve_work(spc_numeric* num, int32_t nrhs);
+int32_t run_refine(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb, double* x,
+                   int64_t ldx, double tol, int32_t max_iter, hipStream_t stream,
+                   int32_t* iters, double* berr);
+// Gathers the caller's values into the refinement copy of A (FP64).
+int32_t load_refine_matrix(spc_numeric* num, const double* values, hipStream_t stream);
+void free_refine(spc_numeric* num);
 void drop_solve_graphs(spc_numeric* num);
 
 }  // namespace spc

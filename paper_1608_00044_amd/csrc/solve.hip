@@ -13,7 +13,9 @@
 //                            one thread per column;
 //             k_bwd_diag  -- y_s = L11^{-T} (y_s - t_s), panels in reverse.
 // The level sweeps are captured once per right-hand-side count into a HIP
-// graph and replayed, so a solve costs three launches on the host.
+// graph and replayed, so a solve costs three launches on the host.  The
+// kernels are templates on the factor's real type R: an FP32 factor is
+// solved in FP32 arithmetic with FP32 work vectors.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,43 +29,46 @@ namespace spc {
         if ((x) != hipSuccess) return ERR_HIP;   \
     } while (0)
 
+template <class R>
 __global__ void k_gather(const double* __restrict__ b, int64_t ldb,
-                         const int32_t* __restrict__ perm, double* __restrict__ y, int64_t n,
+                         const int32_t* __restrict__ perm, R* __restrict__ y, int64_t n,
                          int nrhs) {
     const int64_t total = n * nrhs;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t c = e / n, i = e - c * n;
-        y[e] = b[perm[i] + c * ldb];
+        y[e] = (R)b[perm[i] + c * ldb];
     }
 }
 
-__global__ void k_scatter(const double* __restrict__ y, const int32_t* __restrict__ perm,
+template <class R>
+__global__ void k_scatter(const R* __restrict__ y, const int32_t* __restrict__ perm,
                           double* __restrict__ x, int64_t ldx, int64_t n, int nrhs) {
     const int64_t total = n * nrhs;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t c = e / n, i = e - c * n;
-        x[perm[i] + c * ldx] = y[e];
+        x[perm[i] + c * ldx] = (double)y[e];
     }
 }
 
-__global__ void k_zero(double* __restrict__ p, int64_t n) {
+template <class R>
+__global__ void k_zero(R* __restrict__ p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = 0.0;
+        p[i] = R(0);
 }
 
 // Stages the packed lower triangle of the w x w diagonal block (entry (i, j)
 // at cst(j) + i) and the supernode's 16 x 16 inverse blocks into LDS, eight
 // independent global loads per thread in flight.
-__device__ __forceinline__ void stage_block(double* __restrict__ T, double* __restrict__ I,
-                                            const double* __restrict__ L,
-                                            const double* __restrict__ inv, int w, int ld,
-                                            int npanel, int tid) {
+template <class R>
+__device__ __forceinline__ void stage_block(R* __restrict__ T, R* __restrict__ I,
+                                            const R* __restrict__ L, const R* __restrict__ inv,
+                                            int w, int ld, int npanel, int tid) {
     const int ww = w * w;
     for (int e0 = tid; e0 < ww; e0 += 24 * 256) {
-        double v[24];
+        R v[24];
 #pragma unroll
         for (int u = 0; u < 24; ++u) {
             const int e = e0 + u * 256, i = e % w, j = e / w;
@@ -78,9 +83,9 @@ __device__ __forceinline__ void stage_block(double* __restrict__ T, double* __re
     }
     const int ni = npanel * kPanel * kPanel;
     for (int e0 = tid; e0 < ni; e0 += 8 * 256) {
-        double v[8];
+        R v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = (e0 + u * 256 < ni) ? inv[e0 + u * 256] : 0.0;
+        for (int u = 0; u < 8; ++u) v[u] = (e0 + u * 256 < ni) ? inv[e0 + u * 256] : R(0);
 #pragma unroll
         for (int u = 0; u < 8; ++u)
             if (e0 + u * 256 < ni) I[e0 + u * 256] = v[u];
@@ -93,41 +98,43 @@ __device__ __forceinline__ void stage_block(double* __restrict__ T, double* __re
 //   t = y_p - L[p, <p] y_{<p}   (thread (j, part) sums every 16th column k,
 //                                the 16 parts meet in LDS),
 //   y_p = inv(D_p) t            (16 lanes of wave 0).
+template <class R>
 __global__ __launch_bounds__(256) void k_fwd_diag(const int32_t* __restrict__ level_sn, KArgs a,
-                                                  const double* __restrict__ arena,
-                                                  const double* __restrict__ dinv,
-                                                  double* __restrict__ y, int64_t n, int nrhs) {
-    extern __shared__ double sm[];
-    __shared__ double ys[kMaxWidth + kPanel];
-    __shared__ double red[16][17];
+                                                  const R* __restrict__ arena,
+                                                  const R* __restrict__ dinv, R* __restrict__ y,
+                                                  int64_t n, int nrhs) {
+    extern __shared__ double sm_raw[];
+    R* sm = (R*)sm_raw;
+    __shared__ R ys[kMaxWidth + kPanel];
+    __shared__ R red[16][17];
     const int s = level_sn[blockIdx.x];
     const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
-    const double* __restrict__ L = arena + a.sn_off[s];
-    const double* __restrict__ inv = dinv + a.inv_off[s];
+    const R* __restrict__ L = arena + a.sn_off[s];
+    const R* __restrict__ inv = dinv + a.inv_off[s];
     const int tid = threadIdx.x, j = tid & 15, part = tid >> 4;
     const int npanel = (w + kPanel - 1) / kPanel;
     auto cst = [w](int jj) { return (jj * (2 * w - jj - 1)) >> 1; };
-    double* T = sm;
-    double* I = sm + w * (w + 1) / 2;
-    stage_block(T, I, L, inv, w, ld, npanel, tid);
+    R* T = sm;
+    R* I = sm + w * (w + 1) / 2;
+    stage_block<R>(T, I, L, inv, w, ld, npanel, tid);
     for (int c = 0; c < nrhs; ++c) {
-        double* __restrict__ yc = y + (int64_t)c * n;
+        R* __restrict__ yc = y + (int64_t)c * n;
         for (int k = tid; k < w; k += 256) ys[k] = yc[first + k];
         __syncthreads();
         for (int p = 0; p < npanel; ++p) {
             const int j0 = p * kPanel, jb = min(kPanel, w - j0);
-            double acc = 0.0;
+            R acc = R(0);
             if (j < jb)
                 for (int k = part; k < j0; k += 16) acc += T[cst(k) + j0 + j] * ys[k];
             red[part][j] = acc;
             __syncthreads();
             if (tid < kPanel) {
-                double tot = 0.0;
+                R tot = R(0);
 #pragma unroll
                 for (int q = 0; q < 16; ++q) tot += red[q][tid];
-                const double t = (tid < jb) ? ys[j0 + tid] - tot : 0.0;
+                const R t = (tid < jb) ? ys[j0 + tid] - tot : R(0);
                 red[0][tid] = t;  // wave 0 only: read back below in order
-                double out = 0.0;
+                R out = R(0);
 #pragma unroll
                 for (int k = 0; k < kPanel; ++k)
                     out += I[p * kPanel * kPanel + tid * kPanel + k] * red[0][k];
@@ -142,25 +149,26 @@ __global__ __launch_bounds__(256) void k_fwd_diag(const int32_t* __restrict__ le
 
 // Forward, below the diagonal block: y[rows(i)] -= sum_k L21[i][k] y_s[k];
 // the four waves split the columns and combine through LDS.
+template <class R>
 __global__ __launch_bounds__(256) void k_fwd_gemv(const RowBlock* __restrict__ work, KArgs a,
-                                                  const double* __restrict__ arena,
-                                                  double* __restrict__ y, int64_t n, int nrhs) {
-    __shared__ double ys[kMaxWidth];
-    __shared__ double red[256];
+                                                  const R* __restrict__ arena, R* __restrict__ y,
+                                                  int64_t n, int nrhs) {
+    __shared__ R ys[kMaxWidth];
+    __shared__ R red[256];
     const RowBlock wb = work[blockIdx.x];
     const int s = wb.s;
     const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
     const int64_t rp = a.rowptr[s];
     const int r = (int)(a.rowptr[s + 1] - rp) - w;
-    const double* __restrict__ P = arena + a.sn_off[s] + w;
+    const R* __restrict__ P = arena + a.sn_off[s] + w;
     const int32_t* __restrict__ below = a.rows + rp + w;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int i = wb.rb * kTile + lane;
     for (int c = 0; c < nrhs; ++c) {
-        double* __restrict__ yc = y + (int64_t)c * n;
+        R* __restrict__ yc = y + (int64_t)c * n;
         for (int k = tid; k < w; k += 256) ys[k] = yc[first + k];
         __syncthreads();
-        double acc = 0.0;
+        R acc = R(0);
         if (i < r) {
 #pragma unroll 4
             for (int k = wave; k < w; k += 4) acc += P[i + (int64_t)k * ld] * ys[k];
@@ -178,28 +186,28 @@ __global__ __launch_bounds__(256) void k_fwd_gemv(const RowBlock* __restrict__ w
 // over one 64-row block: the gathered entries go to LDS, then thread k walks
 // column k of the block (its own contiguous 64 entries) and adds one partial
 // sum per column.
+template <class R>
 __global__ __launch_bounds__(256) void k_bwd_gemv(const RowBlock* __restrict__ work, KArgs a,
-                                                  const double* __restrict__ arena,
-                                                  const double* __restrict__ y,
-                                                  double* __restrict__ tacc, int64_t n,
-                                                  int nrhs) {
-    __shared__ double xr[kTile];
+                                                  const R* __restrict__ arena,
+                                                  const R* __restrict__ y, R* __restrict__ tacc,
+                                                  int64_t n, int nrhs) {
+    __shared__ R xr[kTile];
     const RowBlock wb = work[blockIdx.x];
     const int s = wb.s;
     const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
     const int64_t rp = a.rowptr[s];
     const int r = (int)(a.rowptr[s + 1] - rp) - w;
-    const double* __restrict__ P = arena + a.sn_off[s] + w;
+    const R* __restrict__ P = arena + a.sn_off[s] + w;
     const int32_t* __restrict__ below = a.rows + rp + w;
     const int tid = threadIdx.x;
     const int i0 = wb.rb * kTile, m = min(kTile, r - i0);
     for (int c = 0; c < nrhs; ++c) {
-        const double* __restrict__ yc = y + (int64_t)c * n;
-        if (tid < kTile) xr[tid] = (tid < m) ? yc[below[i0 + tid]] : 0.0;
+        const R* __restrict__ yc = y + (int64_t)c * n;
+        if (tid < kTile) xr[tid] = (tid < m) ? yc[below[i0 + tid]] : R(0);
         __syncthreads();
         for (int k = tid; k < w; k += 256) {
-            const double* __restrict__ col = P + i0 + (int64_t)k * ld;
-            double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+            const R* __restrict__ col = P + i0 + (int64_t)k * ld;
+            R acc0 = R(0), acc1 = R(0), acc2 = R(0), acc3 = R(0);
             int i = 0;
             for (; i + 4 <= m; i += 4) {
                 acc0 += col[i] * xr[i];
@@ -218,44 +226,45 @@ __global__ __launch_bounds__(256) void k_bwd_gemv(const RowBlock* __restrict__ w
 //   u = v_p - L[>p, p]^T y_{>p},   y_p = inv(D_p)^T u,
 // with L11 and the inverses staged in LDS and the dot products split over
 // the workgroup as in k_fwd_diag.
+template <class R>
 __global__ __launch_bounds__(256) void k_bwd_diag(const int32_t* __restrict__ level_sn, KArgs a,
-                                                  const double* __restrict__ arena,
-                                                  const double* __restrict__ dinv,
-                                                  double* __restrict__ y,
-                                                  const double* __restrict__ tacc, int64_t n,
+                                                  const R* __restrict__ arena,
+                                                  const R* __restrict__ dinv, R* __restrict__ y,
+                                                  const R* __restrict__ tacc, int64_t n,
                                                   int nrhs) {
-    extern __shared__ double sm[];
-    __shared__ double ys[kMaxWidth + kPanel];
-    __shared__ double red[16][17];
+    extern __shared__ double sm_raw[];
+    R* sm = (R*)sm_raw;
+    __shared__ R ys[kMaxWidth + kPanel];
+    __shared__ R red[16][17];
     const int s = level_sn[blockIdx.x];
     const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
-    const double* __restrict__ L = arena + a.sn_off[s];
-    const double* __restrict__ inv = dinv + a.inv_off[s];
+    const R* __restrict__ L = arena + a.sn_off[s];
+    const R* __restrict__ inv = dinv + a.inv_off[s];
     const int tid = threadIdx.x, j = tid & 15, part = tid >> 4;
     const int npanel = (w + kPanel - 1) / kPanel;
     auto cst = [w](int jj) { return (jj * (2 * w - jj - 1)) >> 1; };
-    double* T = sm;
-    double* I = sm + w * (w + 1) / 2;
-    stage_block(T, I, L, inv, w, ld, npanel, tid);
+    R* T = sm;
+    R* I = sm + w * (w + 1) / 2;
+    stage_block<R>(T, I, L, inv, w, ld, npanel, tid);
     for (int c = 0; c < nrhs; ++c) {
-        double* __restrict__ yc = y + (int64_t)c * n;
-        const double* __restrict__ tc = tacc + (int64_t)c * n;
+        R* __restrict__ yc = y + (int64_t)c * n;
+        const R* __restrict__ tc = tacc + (int64_t)c * n;
         for (int k = tid; k < w; k += 256) ys[k] = yc[first + k] - tc[first + k];
         __syncthreads();
         for (int p = npanel - 1; p >= 0; --p) {
             const int j0 = p * kPanel, jb = min(kPanel, w - j0);
-            double acc = 0.0;
+            R acc = R(0);
             if (j < jb)
                 for (int k = j0 + kPanel + part; k < w; k += 16) acc += T[cst(j0 + j) + k] * ys[k];
             red[part][j] = acc;
             __syncthreads();
             if (tid < kPanel) {
-                double tot = 0.0;
+                R tot = R(0);
 #pragma unroll
                 for (int q = 0; q < 16; ++q) tot += red[q][tid];
-                const double u = (tid < jb) ? ys[j0 + tid] - tot : 0.0;
+                const R u = (tid < jb) ? ys[j0 + tid] - tot : R(0);
                 red[0][tid] = u;
-                double out = 0.0;
+                R out = R(0);
 #pragma unroll
                 for (int k = 0; k < kPanel; ++k)
                     out += I[p * kPanel * kPanel + k * kPanel + tid] * red[0][k];
@@ -268,19 +277,19 @@ __global__ __launch_bounds__(256) void k_bwd_diag(const int32_t* __restrict__ le
     }
 }
 
-static size_t diag_lds(int wmax) {
+// Dynamic LDS of the diagonal-block kernels: packed triangle + inverse blocks.
+static size_t diag_lds(int wmax, size_t elem) {
     const int np = (wmax + kPanel - 1) / kPanel;
-    return ((size_t)wmax * (wmax + 1) / 2 + (size_t)np * kPanel * kPanel) * sizeof(double);
+    return ((size_t)wmax * (wmax + 1) / 2 + (size_t)np * kPanel * kPanel) * elem;
 }
 
 int32_t configure_solve_kernels() {
-    const int mx = (int)diag_lds(kMaxWidth);
-    if (hipFuncSetAttribute((const void*)k_fwd_diag, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            mx) != hipSuccess)
-        return ERR_HIP;
-    if (hipFuncSetAttribute((const void*)k_bwd_diag, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            mx) != hipSuccess)
-        return ERR_HIP;
+    const int mx = (int)diag_lds(kMaxWidth, sizeof(double));
+    const void* fns[] = {(const void*)k_fwd_diag<double>, (const void*)k_bwd_diag<double>,
+                         (const void*)k_fwd_diag<float>, (const void*)k_bwd_diag<float>};
+    for (const void* f : fns)
+        if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, mx) != hipSuccess)
+            return ERR_HIP;
     return OK;
 }
 
@@ -289,37 +298,41 @@ namespace {
 // The level sweeps of one solve on the internal work vectors (y, t), as
 // enqueued on stream st.  Gather and scatter stay outside: they touch the
 // caller's b and x, which change from call to call.
-void enqueue_sweeps(spc_numeric* num, int32_t nrhs, double* y, double* tacc, hipStream_t st) {
+template <class R>
+void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* y, R* tacc, hipStream_t st) {
     const Symbolic& S = num->sym->S;
     const DevicePlan* P = num->plan;
     const int64_t n = S.n;
     const KArgs a = kargs(P);
+    const R* arena = (const R*)num->arena;
+    const R* dinv = (const R*)num->dinv;
     const int64_t total = n * nrhs;
     const int g = (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 4096));
-    hipLaunchKernelGGL(k_zero, dim3(g), dim3(256), 0, st, tacc, total);
+    hipLaunchKernelGGL(k_zero<R>, dim3(g), dim3(256), 0, st, tacc, total);
     const int32_t nl = (int32_t)S.level_ptr.size() - 1;
     for (int32_t l = 0; l < nl; ++l) {
         const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1];
-        const size_t lds = diag_lds(P->level_maxw[l]);
-        hipLaunchKernelGGL(k_fwd_diag, dim3(n1 - n0), dim3(256), lds, st, P->level_sn + n0, a,
-                           (const double*)num->arena, (const double*)num->dinv, y, n, nrhs);
+        const size_t lds = diag_lds(P->level_maxw[l], sizeof(R));
+        hipLaunchKernelGGL(k_fwd_diag<R>, dim3(n1 - n0), dim3(256), lds, st, P->level_sn + n0, a,
+                           arena, dinv, y, n, nrhs);
         const int64_t rb0 = P->rowblk_ptr[l], rb1 = P->rowblk_ptr[l + 1];
         if (rb1 > rb0)
-            hipLaunchKernelGGL(k_fwd_gemv, dim3((unsigned)(rb1 - rb0)), dim3(256), 0, st,
-                               P->rowblk + rb0, a, (const double*)num->arena, y, n, nrhs);
+            hipLaunchKernelGGL(k_fwd_gemv<R>, dim3((unsigned)(rb1 - rb0)), dim3(256), 0, st,
+                               P->rowblk + rb0, a, arena, y, n, nrhs);
     }
     for (int32_t l = nl - 1; l >= 0; --l) {
         const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1];
         const int64_t rb0 = P->rowblk_ptr[l], rb1 = P->rowblk_ptr[l + 1];
         if (rb1 > rb0)
-            hipLaunchKernelGGL(k_bwd_gemv, dim3((unsigned)(rb1 - rb0)), dim3(256), 0, st,
-                               P->rowblk + rb0, a, (const double*)num->arena,
-                               (const double*)y, tacc, n, nrhs);
-        hipLaunchKernelGGL(k_bwd_diag, dim3(n1 - n0), dim3(256), diag_lds(P->level_maxw[l]), st,
-                           P->level_sn + n0, a, (const double*)num->arena,
-                           (const double*)num->dinv, y, (const double*)tacc, n, nrhs);
+            hipLaunchKernelGGL(k_bwd_gemv<R>, dim3((unsigned)(rb1 - rb0)), dim3(256), 0, st,
+                               P->rowblk + rb0, a, arena, (const R*)y, tacc, n, nrhs);
+        hipLaunchKernelGGL(k_bwd_diag<R>, dim3(n1 - n0), dim3(256),
+                           diag_lds(P->level_maxw[l], sizeof(R)), st, P->level_sn + n0, a, arena,
+                           dinv, y, (const R*)tacc, n, nrhs);
     }
 }
+
+size_t elem_size(const spc_numeric* num) { return num->prec == 1 ? sizeof(float) : sizeof(double); }
 
 }  // namespace
 
@@ -331,30 +344,26 @@ void drop_solve_graphs(spc_numeric* num) {
     num->solve_graphs.clear();
 }
 
-int32_t run_solve(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb, double* x,
-                  int64_t ldx, hipStream_t st) {
-    const Symbolic& S = num->sym->S;
-    const DevicePlan* P = num->plan;
-    const int64_t n = S.n;
-    if (n == 0 || nrhs == 0) return OK;
-    if (num->work_cols < nrhs) {
-        if (num->work) {
-            HIP_TRY(hipDeviceSynchronize());
-            drop_solve_graphs(num);
-            HIP_TRY(hipFree(num->work));
-            num->work = nullptr;
-            num->work_cols = 0;
-        }
-        if (hipMalloc(&num->work, 2 * sizeof(double) * (size_t)n * nrhs) != hipSuccess)
-            return ERR_OOM;
-        num->work_cols = nrhs;
+// Work vectors y and t (n x nrhs each, factor type) for nrhs right-hand sides.
+int32_t ensure_solve_work(spc_numeric* num, int32_t nrhs) {
+    const int64_t n = num->sym->S.n;
+    if (num->work_cols >= nrhs) return OK;
+    if (num->work) {
+        HIP_TRY(hipDeviceSynchronize());
+        drop_solve_graphs(num);
+        HIP_TRY(hipFree(num->work));
+        num->work = nullptr;
+        num->work_cols = 0;
     }
-    double* y = num->work;
-    double* tacc = num->work + (size_t)n * nrhs;
-    const int64_t total = n * nrhs;
-    const int g = (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 4096));
-    hipLaunchKernelGGL(k_gather, dim3(g), dim3(256), 0, st, b, ldb, P->perm, y, n, nrhs);
-    // the sweeps replay from a graph captured once per right-hand-side count
+    if (hipMalloc(&num->work, 2 * elem_size(num) * (size_t)n * nrhs) != hipSuccess)
+        return ERR_OOM;
+    num->work_cols = nrhs;
+    return OK;
+}
+
+// Replays (capturing on first use) the sweeps for nrhs columns on stream st.
+int32_t run_sweeps(spc_numeric* num, int32_t nrhs, hipStream_t st) {
+    const int64_t n = num->sym->S.n;
     spc_numeric::SolveGraph* sg = nullptr;
     for (auto& e : num->solve_graphs)
         if (e.nrhs == nrhs) sg = &e;
@@ -363,7 +372,13 @@ int32_t run_solve(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb, 
         spc_numeric::SolveGraph e;
         e.nrhs = nrhs;
         HIP_TRY(hipStreamBeginCapture(num->capture, hipStreamCaptureModeThreadLocal));
-        enqueue_sweeps(num, nrhs, y, tacc, num->capture);
+        if (num->prec == 1) {
+            float* y = (float*)num->work;
+            enqueue_sweeps<float>(num, nrhs, y, y + (size_t)n * nrhs, num->capture);
+        } else {
+            double* y = (double*)num->work;
+            enqueue_sweeps<double>(num, nrhs, y, y + (size_t)n * nrhs, num->capture);
+        }
         const hipError_t ce = hipStreamEndCapture(num->capture, &e.graph);
         if (ce != hipSuccess || !e.graph) return ERR_HIP;
         if (hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0) != hipSuccess) {
@@ -374,7 +389,34 @@ int32_t run_solve(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb, 
         sg = &num->solve_graphs.back();
     }
     HIP_TRY(hipGraphLaunch(sg->exec, st));
-    hipLaunchKernelGGL(k_scatter, dim3(g), dim3(256), 0, st, y, P->perm, x, ldx, n, nrhs);
+    return OK;
+}
+
+int32_t run_solve(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb, double* x,
+                  int64_t ldx, hipStream_t st) {
+    const Symbolic& S = num->sym->S;
+    const DevicePlan* P = num->plan;
+    const int64_t n = S.n;
+    if (n == 0 || nrhs == 0) return OK;
+    int32_t r = ensure_solve_work(num, nrhs);
+    if (r != OK) return r;
+    const int64_t total = n * nrhs;
+    const int g = (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 4096));
+    if (num->prec == 1)
+        hipLaunchKernelGGL(k_gather<float>, dim3(g), dim3(256), 0, st, b, ldb, P->perm,
+                           (float*)num->work, n, nrhs);
+    else
+        hipLaunchKernelGGL(k_gather<double>, dim3(g), dim3(256), 0, st, b, ldb, P->perm,
+                           (double*)num->work, n, nrhs);
+    // the sweeps replay from a graph captured once per right-hand-side count
+    r = run_sweeps(num, nrhs, st);
+    if (r != OK) return r;
+    if (num->prec == 1)
+        hipLaunchKernelGGL(k_scatter<float>, dim3(g), dim3(256), 0, st, (const float*)num->work,
+                           P->perm, x, ldx, n, nrhs);
+    else
+        hipLaunchKernelGGL(k_scatter<double>, dim3(g), dim3(256), 0, st, (const double*)num->work,
+                           P->perm, x, ldx, n, nrhs);
     HIP_TRY(hipGetLastError());
     return OK;
 }

@@ -21,6 +21,7 @@ struct Options {
     int32_t sched = 0;
     int32_t debug_flags = 0;  // bit 0: withhold one dependency (exercises the watchdog)
     int64_t spin_limit = 0;   // bounded waits of the task-queue schedule; 0 = default
+    int32_t precision = 0;    // 0: FP64 factor; 1: FP32 factor with FP64 refinement
 };
 
 // One (source, target) update pair: source supernode s sends its update block

@@ -35,13 +35,13 @@ EXPORTS = ("spc_default_options", "spc_analyze", "spc_symbolic_info_get", "spc_s
            "spc_symbolic_free",
            "spc_factor", "spc_refactor", "spc_numeric_status", "spc_solve", "spc_factor_export",
            "spc_numeric_free", "spc_status_string", "spc_numeric_set_timing",
-           "spc_numeric_get_timing")
+           "spc_numeric_get_timing", "spc_solve_refine", "spc_numeric_info_get")
 
 
 class spc_options(C.Structure):
     _fields_ = [("sn_cap", C.c_int32), ("sched", C.c_int32), ("amalg_ratio", C.c_double),
                 ("mem_budget_bytes", C.c_int64), ("spin_limit", C.c_int64),
-                ("debug_flags", C.c_int32), ("reserved", C.c_int32)]
+                ("debug_flags", C.c_int32), ("precision", C.c_int32)]
 
 
 class spc_symbolic_info(C.Structure):
@@ -50,6 +50,11 @@ class spc_symbolic_info(C.Structure):
                 ("npairs", C.c_int64), ("nrel", C.c_int64), ("factor_bytes", C.c_int64),
                 ("plan_bytes", C.c_int64), ("flops", C.c_double), ("flops_stored", C.c_double),
                 ("max_width", C.c_int32), ("max_below", C.c_int32)]
+
+
+class spc_numeric_info(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("sched", C.c_int32), ("factor_bytes", C.c_int64),
+                ("fp64_blocks", C.c_int64)]
 
 
 class spc_kernel_times(C.Structure):
@@ -105,6 +110,11 @@ def lib():
         L.spc_numeric_set_timing.restype = C.c_int32
         L.spc_numeric_get_timing.argtypes = [vp, C.POINTER(spc_kernel_times)]
         L.spc_numeric_get_timing.restype = C.c_int32
+        L.spc_solve_refine.argtypes = [vp, C.c_int32, vp, C.c_int64, vp, C.c_int64, C.c_double,
+                                       C.c_int32, vp, C.POINTER(C.c_int32), vp]
+        L.spc_solve_refine.restype = C.c_int32
+        L.spc_numeric_info_get.argtypes = [vp, C.POINTER(spc_numeric_info)]
+        L.spc_numeric_info_get.restype = C.c_int32
         L.spc_status_string.argtypes = [C.c_int32]
         L.spc_status_string.restype = C.c_char_p
         _lib = L
@@ -139,7 +149,7 @@ class Symbolic:
     """spc_analyze: host symbolic analysis of the lower CSC pattern."""
 
     def __init__(self, n, colptr, rowind, perm=None, sn_cap=150, amalg_ratio=0.0, sched=0,
-                 mem_budget_bytes=0, spin_limit=0, debug_flags=0):
+                 mem_budget_bytes=0, spin_limit=0, debug_flags=0, precision=0):
         self.n = int(n)
         cp = _np(colptr, np.int64)
         ri = _np(rowind, np.int32)
@@ -152,6 +162,7 @@ class Symbolic:
         opt.mem_budget_bytes = int(mem_budget_bytes)
         opt.spin_limit = int(spin_limit)
         opt.debug_flags = int(debug_flags)
+        opt.precision = int(precision)
         h = C.c_void_p()
         if ri.size == 0:
             ri = np.zeros(1, dtype=np.int32)
@@ -269,8 +280,8 @@ class Numeric:
     def status(self) -> int:
         return int(lib().spc_numeric_status(self.handle))
 
-    def solve(self, b, x=None, stream=None):
-        """x = A^{-1} b; b is (n,) or (n, k); returns x with b's shape."""
+    def _operands(self, b, x):
+        """Column-major (n, k) views of b and x (x allocated when None)."""
         import torch
 
         b = _dev_f64(b, "b")
@@ -290,11 +301,37 @@ class Numeric:
             if X.stride(0) != 1 or (k > 1 and X.stride(1) < n):
                 raise ValueError("x must be column-major (n, k)")
         ldx = max(X.stride(1) if k > 1 else n, n)
+        return one, B, ldb, X, ldx, k
+
+    def solve(self, b, x=None, stream=None):
+        """x = A^{-1} b; b is (n,) or (n, k); returns x with b's shape."""
+        one, B, ldb, X, ldx, k = self._operands(b, x)
         st = lib().spc_solve(self.handle, k, C.c_void_p(B.data_ptr()), ldb,
                              C.c_void_p(X.data_ptr()), ldx, _stream_ptr(stream))
         if st != SPC_OK:
             raise SpcError(st, "spc_solve")
-        return X.reshape(n) if one else X
+        return X.reshape(self.sym.n) if one else X
+
+    def solve_refine(self, b, x=None, tol=1e-10, max_iter=10, stream=None, check=True):
+        """Iterative refinement in FP64 (spc_solve_refine).  Returns (x, iters,
+        berr); raises SpcError unless converged when check is set."""
+        one, B, ldb, X, ldx, k = self._operands(b, x)
+        it = C.c_int32(0)
+        berr = np.zeros(max(k, 1), dtype=np.float64)
+        st = lib().spc_solve_refine(self.handle, k, C.c_void_p(B.data_ptr()), ldb,
+                                    C.c_void_p(X.data_ptr()), ldx, float(tol), int(max_iter),
+                                    _stream_ptr(stream), C.byref(it), _ptr(berr))
+        self.last_refine_status = int(st)
+        if st != SPC_OK and (check or st != SPC_ERR_NOT_CONVERGED):
+            raise SpcError(st, "spc_solve_refine")
+        return (X.reshape(self.sym.n) if one else X), int(it.value), berr[:k]
+
+    def info(self) -> dict:
+        t = spc_numeric_info()
+        st = lib().spc_numeric_info_get(self.handle, C.byref(t))
+        if st != SPC_OK:
+            raise SpcError(st, "spc_numeric_info_get")
+        return {f: getattr(t, f) for f, _ in t._fields_}
 
     def set_timing(self, enable=True):
         st = lib().spc_numeric_set_timing(self.handle, int(bool(enable)))
@@ -354,6 +391,14 @@ def numeric_status(num: Numeric) -> int:
 
 def solve(num: Numeric, b, x=None, stream=None):
     return num.solve(b, x, stream)
+
+
+def solve_refine(num: Numeric, b, x=None, tol=1e-10, max_iter=10, stream=None):
+    return num.solve_refine(b, x, tol, max_iter, stream)
+
+
+def numeric_info_get(num: Numeric) -> dict:
+    return num.info()
 
 
 def factor_export(num: Numeric):

@@ -45,7 +45,8 @@ def test_analyze_rejects_bad_arguments():
         spchol.analyze(2, cp, ri, perm=[0, 0])
     assert e.value.status == spchol.SPC_ERR_ARG
     for kw in (dict(sn_cap=0), dict(sn_cap=151), dict(amalg_ratio=-0.1), dict(sched=3), dict(sched=-1),
-               dict(mem_budget_bytes=-1), dict(spin_limit=-1)):
+               dict(mem_budget_bytes=-1), dict(spin_limit=-1), dict(precision=2),
+               dict(precision=-1)):
         with pytest.raises(spchol.SpcError) as e:
             spchol.analyze(2, cp, ri, **kw)
         assert e.value.status == spchol.SPC_ERR_ARG
