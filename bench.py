@@ -38,6 +38,9 @@ WORKLOAD_TEXT = {
                     "1 RHS N(0,1)",
     "lap2d_5pt_64": "2D 5-point Laplacian 64x64 (n=4096), unit weights + 1e-3 shift, "
                     "geometric nested dissection, 1 RHS N(0,1)",
+    "elast27_48": "3D 27-point stencil, 3 unknowns per node, 48^3 grid (n=331776): random "
+                  "3x3 SPD (Wishart) edge blocks, diagonal blocks dominant + 1e-3 shift, "
+                  "geometric nested dissection, amalgamation 0.1, 8 RHS N(0,1)",
 }
 
 
@@ -89,6 +92,71 @@ def cpu_baseline(name, sample_dims, repeat=0):
                       "%.1f s" % ("x".join(map(str, sample_dims)), p.n, sym.flops, dt)}
 
 
+def mixed_precision(name, steps, warmup, tol=1e-10):
+    """FP64 factor + solve against FP32 factor + FP64 refinement to a normwise
+    backward error <= tol, on the same resident workload and right-hand sides."""
+    import torch
+
+    from paper_1608_00044_amd import inputs, spchol
+
+    p = inputs.make_workload(name)
+    k = p.rhs.shape[1]
+    dev = torch.device("cuda:0")
+    vals = torch.from_numpy(p.values).to(dev)
+    b = torch.from_numpy(np.ascontiguousarray(p.rhs)).to(dev)
+    stream = torch.cuda.current_stream()
+    out = {"workload": name, "description": WORKLOAD_TEXT.get(name, name), "n": p.n,
+           "nrhs": k, "tol": tol}
+    for prec in (0, 1):
+        sym = spchol.analyze(p.n, p.colptr, p.rowind, p.perm, sn_cap=150,
+                             amalg_ratio=p.meta["amalg"], precision=prec)
+        F = sym.info()["flops"]
+        num = spchol.factor(sym, vals)
+        if num.status() != 0:
+            raise RuntimeError("factor status %d (precision %d)" % (num.status(), prec))
+        x = None
+        for _ in range(max(1, warmup)):
+            num.refactor(vals)
+            if prec == 0:
+                x = num.solve(b, x=x)
+            else:
+                x, _, _ = num.solve_refine(b, x=x, tol=tol, max_iter=20)
+        torch.cuda.synchronize()
+        f_ms, s_ms, iters, berr = [], [], [], None
+        for _ in range(steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            num.refactor(vals)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if prec == 0:
+                x = num.solve(b, x=x)
+                torch.cuda.synchronize()
+            else:
+                x, it, berr = num.solve_refine(b, x=x, tol=tol, max_iter=20)
+                iters.append(it)
+            s_ms.append((time.perf_counter() - t0) * 1e3)
+            f_ms.append(e0.elapsed_time(e1))
+        xs = x.cpu().numpy()
+        eta = max(backward_error(p, xs[:, c], p.rhs[:, c]) for c in range(k))
+        fm, sm = float(np.mean(f_ms)), float(np.mean(s_ms))
+        key = "fp64" if prec == 0 else "fp32_ir"
+        out[key] = {"factor_ms": fm, "factor_gflops": F / (fm * 1e-3) / 1e9,
+                    "solve_ms": sm, "total_ms": fm + sm, "backward_error": eta}
+        if prec == 1:
+            out[key]["refine_iters"] = float(np.mean(iters))
+            out[key]["fp64_blocks"] = num.info()["fp64_blocks"]
+            out[key]["solve_ms_note"] = "iterative refinement: residuals in FP64, corrections " \
+                                        "with the FP32 factor, until every column meets tol"
+        log("mixed %s: factor %.2f ms (%.1f GFLOP/s), solve %.2f ms, eta %.2e" %
+            (key, fm, F / (fm * 1e-3) / 1e9, sm, eta))
+        num.free()
+        sym.free()
+    out["speedup_fp32_ir_vs_fp64"] = out["fp64"]["total_ms"] / out["fp32_ir"]["total_ms"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +167,9 @@ def main():
     ap.add_argument("--sched", type=int, default=1, choices=(0, 1, 2),
                     help="0 level sets, 1 with lookahead, 2 device task queue")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mixed-workload", default="elast27_48",
+                    help="workload of the FP64 vs FP32+refinement comparison ('' to skip)")
+    ap.add_argument("--mixed-steps", type=int, default=3)
     ap.add_argument("--cpu-sample", default=None,
                     help="grid of the bounded oracle sample (default: 40^3 for 3D workloads, "
                          "the full grid for 2D ones)")
@@ -231,6 +302,10 @@ def main():
         "kernel_launches_per_factor": {c: launches[c] / args.steps for c in launches},
         "roofline": roofline,
     }
+    num.free()
+    sym.free()
+    if args.mixed_workload:
+        out["mixed_precision"] = mixed_precision(args.mixed_workload, args.mixed_steps, 1)
     if not args.no_cpu_baseline:
         if args.cpu_sample:
             dims = tuple(int(v) for v in args.cpu_sample.split(","))
@@ -241,8 +316,6 @@ def main():
         out["cpu_baseline"] = cpu_baseline(name, dims)
     else:
         out["cpu_baseline"] = None
-    num.free()
-    sym.free()
     print(json.dumps(out), flush=True)
 
 

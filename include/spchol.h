@@ -101,6 +101,7 @@ typedef struct spc_symbolic_info {
     double flops_stored;   /* the same sum over the stored (amalgamated) structure  */
     int32_t max_width;     /* widest supernode                                      */
     int32_t max_below;     /* most rows below a diagonal block                      */
+    int64_t nbatch;        /* independent matrices (1 unless spc_analyze_batch)     */
 } spc_symbolic_info;
 
 /* Fills *opt with the defaults (sn_cap 150, sched 0, no amalgamation, no budget,
@@ -115,6 +116,21 @@ spc_status spc_analyze(int64_t n, const int64_t* colptr, const int32_t* rowind,
                        const int32_t* perm, const spc_options* opt, spc_symbolic** out);
 
 spc_status spc_symbolic_info_get(const spc_symbolic* sym, spc_symbolic_info* info);
+
+/* Batched analysis of `count` independent SPD matrices (matrix k: order n[k],
+ * lower CSC colptr[k] / rowind[k], optional ordering perm[k] or NULL): one
+ * symbolic handle for their block-diagonal direct sum, matrix k taking rows
+ * and columns [o_k, o_k + n[k]) with o_k = n[0] + ... + n[k-1].  Its
+ * elimination forest is the union of theirs (Section II-B), so supernodes,
+ * levels and update pairs never cross two matrices, and one factorization
+ * or solve launch covers every matrix.  Values for spc_factor are the
+ * matrices' value arrays one after the other; right-hand sides and solutions
+ * are the matrices' blocks stacked by rows.  spc_solve_refine measures and
+ * meets tol for every matrix separately (berr: count values per column).
+ * Every matrix is validated as by spc_analyze. */
+spc_status spc_analyze_batch(int32_t count, const int64_t* n, const int64_t* const* colptr,
+                             const int32_t* const* rowind, const int32_t* const* perm,
+                             const spc_options* opt, spc_symbolic** out);
 
 /* Host copies of the analysis, for checking.  Each output may be NULL.
  *   parent[n]    elimination tree of P A P^T (-1 = root), Section II-B;
@@ -198,8 +214,10 @@ spc_status spc_factor_export(spc_numeric* num, int64_t* Sp, int32_t* Si, double*
  * arrays (ldb, ldx >= n) of doubles that must not overlap.  Returns SPC_OK
  * once every column meets tol, SPC_ERR_NOT_CONVERGED after max_iter
  * corrections (x holds the last iterate), or the factor's status.  *iters
- * (may be NULL) receives the number of corrections; berr (host, nrhs entries,
- * may be NULL) the final eta.  Synchronizes stream once per step. */
+ * (may be NULL) receives the number of corrections; berr (host, may be NULL)
+ * the final eta: nrhs entries, or for a batch analysis nrhs x nbatch entries
+ * (berr[c * nbatch + k]: matrix k, column c), each matrix's norms taken over
+ * its own rows.  Synchronizes stream once per step. */
 spc_status spc_solve_refine(spc_numeric* num, int32_t nrhs, const double* b_dev, int64_t ldb,
                             double* x_dev, int64_t ldx, double tol, int32_t max_iter,
                             void* stream, int32_t* iters, double* berr);

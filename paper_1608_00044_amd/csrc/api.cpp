@@ -1,9 +1,11 @@
 // C ABI of the supernodal Cholesky library (declared in include/spchol.h).
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <climits>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "../../include/spchol.h"
 #include "runtime.hpp"
@@ -79,8 +81,9 @@ const char* spc_status_string(spc_status st) {
     }
 }
 
-spc_status spc_analyze(int64_t n, const int64_t* colptr, const int32_t* rowind,
-                       const int32_t* perm, const spc_options* opt, spc_symbolic** out) {
+static spc_status analyze_checked(int64_t n, const int64_t* colptr, const int32_t* rowind,
+                                  const int32_t* perm, const spc_options* opt,
+                                  const std::vector<int64_t>* batch, spc_symbolic** out) {
     if (!out) return SPC_ERR_ARG;
     *out = nullptr;
     spc_options o;
@@ -104,7 +107,10 @@ spc_status spc_analyze(int64_t n, const int64_t* colptr, const int32_t* rowind,
     int32_t st;
     try {
         st = analyze(n, colptr, rowind, perm, so, &h->S);
-        if (st == OK) h->plan_bytes_estimate = plan_bytes(h->S);
+        if (st == OK) {
+            if (batch) h->S.batch_ptr = *batch;
+            h->plan_bytes_estimate = plan_bytes(h->S);
+        }
     } catch (const std::bad_alloc&) {
         st = SPC_ERR_OOM;
     }
@@ -115,6 +121,45 @@ spc_status spc_analyze(int64_t n, const int64_t* colptr, const int32_t* rowind,
     h->budget = o.mem_budget_bytes;
     *out = h;
     return SPC_OK;
+}
+
+spc_status spc_analyze(int64_t n, const int64_t* colptr, const int32_t* rowind,
+                       const int32_t* perm, const spc_options* opt, spc_symbolic** out) {
+    return analyze_checked(n, colptr, rowind, perm, opt, nullptr, out);
+}
+
+spc_status spc_analyze_batch(int32_t count, const int64_t* n, const int64_t* const* colptr,
+                             const int32_t* const* rowind, const int32_t* const* perm,
+                             const spc_options* opt, spc_symbolic** out) {
+    if (!out) return SPC_ERR_ARG;
+    *out = nullptr;
+    if (count < 0 || (count > 0 && (!n || !colptr || !rowind))) return SPC_ERR_ARG;
+    std::vector<int64_t> rows(1, 0), ents(1, 0);
+    for (int32_t k = 0; k < count; ++k) {
+        const int32_t st = validate_input(n[k], colptr[k], rowind[k], perm ? perm[k] : nullptr);
+        if (st != OK) return st;
+        rows.push_back(rows.back() + n[k]);
+        ents.push_back(ents.back() + (n[k] ? colptr[k][n[k]] : 0));
+        if (rows.back() > INT32_MAX - 1) return SPC_ERR_ARG;
+    }
+    const int64_t N = rows.back();
+    std::vector<int64_t> cp((size_t)N + 1, 0);
+    std::vector<int32_t> ri((size_t)std::max<int64_t>(ents.back(), 1));
+    std::vector<int32_t> pm((size_t)std::max<int64_t>(N, 1));
+    try {
+        for (int32_t k = 0; k < count; ++k) {
+            const int64_t o = rows[k], e = ents[k];
+            for (int64_t j = 0; j < n[k]; ++j) {
+                cp[o + j + 1] = e + colptr[k][j + 1];
+                for (int64_t q = colptr[k][j]; q < colptr[k][j + 1]; ++q)
+                    ri[e + q] = (int32_t)(rowind[k][q] + o);
+                pm[o + j] = (int32_t)(o + (perm && perm[k] ? perm[k][j] : j));
+            }
+        }
+    } catch (const std::bad_alloc&) {
+        return SPC_ERR_OOM;
+    }
+    return analyze_checked(N, cp.data(), ri.data(), pm.data(), opt, &rows, out);
 }
 
 spc_status spc_symbolic_info_get(const spc_symbolic* sym, spc_symbolic_info* info) {
@@ -135,6 +180,7 @@ spc_status spc_symbolic_info_get(const spc_symbolic* sym, spc_symbolic_info* inf
     info->flops_stored = S.flops_stored;
     info->max_width = S.max_w;
     info->max_below = S.max_r;
+    info->nbatch = (int64_t)S.batch_ptr.size() - 1;
     return SPC_OK;
 }
 

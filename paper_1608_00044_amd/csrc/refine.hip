@@ -33,19 +33,29 @@ int grid_of(int64_t n) {
     return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192));
 }
 
+// One thread per element (the row kernels reduce per wave, so every row needs its own lane).
+unsigned blocks_of(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + 255) / 256); }
+
 // Non-negative doubles order like their bit patterns as unsigned integers.
 __device__ __forceinline__ void atomic_max_nonneg(double* p, double v) {
     atomicMax((unsigned long long*)p, (unsigned long long)__double_as_longlong(v));
 }
 
-// Maximum over a workgroup of 256 threads, then one atomic per workgroup.
-__device__ __forceinline__ void block_max_to(double* out, double v) {
-    __shared__ double part[4];
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) atomic_max_nonneg(out, fmax(fmax(part[0], part[1]), fmax(part[2], part[3])));
-    __syncthreads();
+// out[seg] = max(out[seg], v) for the row of this lane (seg < 0: no row).  A
+// wave whose rows all lie in one matrix of the batch reduces first and
+// issues one atomic; otherwise every lane issues its own.
+__device__ __forceinline__ void seg_max(double* out, int seg, double v) {
+    const int s0 = __shfl(seg, 0, 64);
+    if (__all(seg == s0 || seg < 0) && s0 >= 0) {
+        for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+        if ((threadIdx.x & 63) == 0) atomic_max_nonneg(out + s0, v);
+    } else if (seg >= 0) {
+        atomic_max_nonneg(out + seg, v);
+    }
+}
+
+__device__ __forceinline__ int seg_of(const int32_t* seg, int64_t i, int64_t n) {
+    return i < n ? (seg ? seg[i] : 0) : -1;
 }
 
 __global__ void k_fill_f64(double* __restrict__ p, int64_t n, double v) {
@@ -72,45 +82,42 @@ __global__ void k_gather_vals(const double* __restrict__ values, const int64_t* 
         aval[q] = values[src[q]];
 }
 
-// ||A||_inf = max over rows of the absolute row sum.  Grid-stride loops keep
-// every thread of a workgroup alive to the block reduction.
+// ||A_k||_inf = max over the rows of matrix k of the absolute row sum; one
+// thread per row.
 __global__ __launch_bounds__(256) void k_anorm(const int64_t* __restrict__ ptr,
-                                               const double* __restrict__ val, int64_t n,
+                                               const double* __restrict__ val,
+                                               const int32_t* __restrict__ seg, int64_t n,
                                                double* __restrict__ out) {
-    double m = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        double s = 0.0;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    if (i < n)
         for (int64_t q = ptr[i]; q < ptr[i + 1]; ++q) s += fabs(val[q]);
-        m = fmax(m, s);
-    }
-    block_max_to(out, m);
+    seg_max(out, seg_of(seg, i, n), s);
 }
 
-// ||v_c||_inf for the nrhs columns of v (leading dimension ld); blockIdx.y = c.
+// ||v_{k,c}||_inf per matrix k and column c (blockIdx.y); out[c * nseg + k].
 __global__ __launch_bounds__(256) void k_colmax(const double* __restrict__ v, int64_t ld, int64_t n,
+                                                const int32_t* __restrict__ seg, int64_t nseg,
                                                 double* __restrict__ out) {
     const int c = blockIdx.y;
-    double m = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        m = fmax(m, fabs(v[i + c * ld]));
-    block_max_to(out + c, m);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    seg_max(out + c * nseg, seg_of(seg, i, n), i < n ? fabs(v[i + c * ld]) : 0.0);
 }
 
-// r_c = b_c - A x_c and ||r_c||_inf, one thread per row; blockIdx.y = c.
+// r_c = b_c - A x_c and ||r_{k,c}||_inf, one thread per row; blockIdx.y = c.
 __global__ __launch_bounds__(256) void k_resid(const int64_t* __restrict__ ptr,
                                                const int32_t* __restrict__ col,
                                                const double* __restrict__ val,
                                                const double* __restrict__ b, int64_t ldb,
                                                const double* __restrict__ x, int64_t ldx,
                                                double* __restrict__ r, int64_t n,
+                                               const int32_t* __restrict__ seg, int64_t nseg,
                                                double* __restrict__ rnorm) {
     const int c = blockIdx.y;
     const double* __restrict__ xc = x + c * ldx;
-    double m = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double ri = 0.0;
+    if (i < n) {
         double s0 = 0.0, s1 = 0.0;
         int64_t q = ptr[i];
         const int64_t q1 = ptr[i + 1];
@@ -119,47 +126,52 @@ __global__ __launch_bounds__(256) void k_resid(const int64_t* __restrict__ ptr,
             s1 += val[q + 1] * xc[col[q + 1]];
         }
         if (q < q1) s0 += val[q] * xc[col[q]];
-        const double ri = b[i + c * ldb] - (s0 + s1);
+        ri = b[i + c * ldb] - (s0 + s1);
         r[i + c * n] = ri;
-        m = fmax(m, fabs(ri));
     }
-    block_max_to(rnorm + c, m);
+    seg_max(rnorm + c * nseg, seg_of(seg, i, n), fabs(ri));
 }
 
-// eta_c and the scale 1 / ||r_c|| of the next correction (0 when r_c = 0).
+// eta and the scale 1 / ||r|| of the next correction (0 when r = 0), per
+// (column, matrix) entry e = c * nseg + k.
 __global__ void k_eta(const double* __restrict__ rn, const double* __restrict__ xn,
                       const double* __restrict__ bn, const double* __restrict__ anorm,
-                      double* __restrict__ eta, double* __restrict__ scale, int nrhs) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nrhs) return;
-    const double den = anorm[0] * xn[c] + bn[c];
-    eta[c] = den > 0.0 ? rn[c] / den : (rn[c] > 0.0 ? 1.0 : 0.0);
-    scale[c] = rn[c] > 0.0 ? 1.0 / rn[c] : 0.0;
+                      int64_t nseg, double* __restrict__ eta, double* __restrict__ scale,
+                      int64_t total) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const double den = anorm[e % nseg] * xn[e] + bn[e];
+    eta[e] = den > 0.0 ? rn[e] / den : (rn[e] > 0.0 ? 1.0 : 0.0);
+    scale[e] = rn[e] > 0.0 ? 1.0 / rn[e] : 0.0;
 }
 
-// y = P (r / ||r||) rounded to the factor's type.
+// y = P (r / ||r||) rounded to the factor's type (each matrix scaled by its own norm).
 template <class R>
 __global__ void k_gather_scaled(const double* __restrict__ r, const int32_t* __restrict__ perm,
+                                const int32_t* __restrict__ seg, int64_t nseg,
                                 const double* __restrict__ scale, R* __restrict__ y, int64_t n,
                                 int nrhs) {
     const int64_t total = n * nrhs;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t c = e / n, i = e - c * n;
-        y[e] = (R)(r[perm[i] + c * n] * scale[c]);
+        const int32_t o = perm[i];
+        y[e] = (R)(r[o + c * n] * scale[c * nseg + (seg ? seg[o] : 0)]);
     }
 }
 
 // x += ||r|| P^T y in FP64.
 template <class R>
 __global__ void k_scatter_add(const R* __restrict__ y, const int32_t* __restrict__ perm,
+                              const int32_t* __restrict__ seg, int64_t nseg,
                               const double* __restrict__ rn, double* __restrict__ x, int64_t ldx,
                               int64_t n, int nrhs) {
     const int64_t total = n * nrhs;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t c = e / n, i = e - c * n;
-        x[perm[i] + c * ldx] += (double)y[e] * rn[c];
+        const int32_t o = perm[i];
+        x[o + c * ldx] += (double)y[e] * rn[c * nseg + (seg ? seg[o] : 0)];
     }
 }
 
@@ -169,12 +181,12 @@ void correction(spc_numeric* num, int32_t nrhs, const double* r, const double* s
     const int64_t n = num->sym->S.n;
     const int32_t* perm = num->plan->perm;
     const int g = grid_of(n * nrhs);
-    hipLaunchKernelGGL(k_gather_scaled<R>, dim3(g), dim3(256), 0, st, r, perm, scale,
-                       (R*)num->work, n, nrhs);
+    hipLaunchKernelGGL(k_gather_scaled<R>, dim3(g), dim3(256), 0, st, r, perm,
+                       (const int32_t*)num->a_seg, num->nseg, scale, (R*)num->work, n, nrhs);
     *rc = run_sweeps(num, nrhs, st);
     if (*rc != OK) return;
-    hipLaunchKernelGGL(k_scatter_add<R>, dim3(g), dim3(256), 0, st, (const R*)num->work, perm, rn,
-                       x, ldx, n, nrhs);
+    hipLaunchKernelGGL(k_scatter_add<R>, dim3(g), dim3(256), 0, st, (const R*)num->work, perm,
+                       (const int32_t*)num->a_seg, num->nseg, rn, x, ldx, n, nrhs);
 }
 
 }  // namespace
@@ -221,7 +233,15 @@ static int32_t build_refine_matrix(spc_numeric* num) {
     if (hipMalloc(&num->a_col, sizeof(int32_t) * b_nz) != hipSuccess) return ERR_OOM;
     if (hipMalloc(&num->a_src, sizeof(int64_t) * b_nz) != hipSuccess) return ERR_OOM;
     if (hipMalloc(&num->a_val, sizeof(double) * b_nz) != hipSuccess) return ERR_OOM;
-    if (hipMalloc(&num->a_norm, 256) != hipSuccess) return ERR_OOM;
+    num->nseg = std::max<int64_t>(1, (int64_t)S.batch_ptr.size() - 1);
+    if (hipMalloc(&num->a_norm, sizeof(double) * (size_t)num->nseg) != hipSuccess) return ERR_OOM;
+    if (num->nseg > 1) {
+        std::vector<int32_t> seg((size_t)n);
+        for (int64_t k = 0; k + 1 < (int64_t)S.batch_ptr.size(); ++k)
+            for (int64_t i = S.batch_ptr[k]; i < S.batch_ptr[k + 1]; ++i) seg[i] = (int32_t)k;
+        if (hipMalloc(&num->a_seg, sizeof(int32_t) * (size_t)n) != hipSuccess) return ERR_OOM;
+        HIP_TRY(hipMemcpy(num->a_seg, seg.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
+    }
     HIP_TRY(hipMemcpy(num->a_ptr, ptr.data(), b_ptr, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(num->a_col, col.data(), sizeof(int32_t) * b_nz, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(num->a_src, src.data(), sizeof(int64_t) * b_nz, hipMemcpyHostToDevice));
@@ -238,11 +258,12 @@ int32_t load_refine_matrix(spc_numeric* num, const double* values, hipStream_t s
     if (nnzf > 0)
         hipLaunchKernelGGL(k_gather_vals, dim3(grid_of(nnzf)), dim3(256), 0, st, values,
                            (const int64_t*)num->a_src, num->a_val, nnzf);
-    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, st, num->a_norm, (int64_t)1, 0.0);
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_of(num->nseg)), dim3(256), 0, st, num->a_norm,
+                       num->nseg, 0.0);
     if (S.n > 0)
-        hipLaunchKernelGGL(k_anorm, dim3(grid_of(S.n)), dim3(256), 0, st,
-                           (const int64_t*)num->a_ptr, (const double*)num->a_val, S.n,
-                           num->a_norm);
+        hipLaunchKernelGGL(k_anorm, dim3(blocks_of(S.n)), dim3(256), 0, st,
+                           (const int64_t*)num->a_ptr, (const double*)num->a_val,
+                           (const int32_t*)num->a_seg, S.n, num->a_norm);
     HIP_TRY(hipGetLastError());
     return OK;
 }
@@ -253,6 +274,7 @@ void free_refine(spc_numeric* num) {
     (void)hipFree(num->a_src);
     (void)hipFree(num->a_val);
     (void)hipFree(num->a_norm);
+    (void)hipFree(num->a_seg);
     (void)hipFree(num->ir_work);
     if (num->ir_host) (void)hipHostFree(num->ir_host);
     num->a_ptr = nullptr;
@@ -260,6 +282,7 @@ void free_refine(spc_numeric* num) {
     num->a_src = nullptr;
     num->a_val = nullptr;
     num->a_norm = nullptr;
+    num->a_seg = nullptr;
     num->ir_work = nullptr;
     num->ir_host = nullptr;
     num->ir_cols = 0;
@@ -269,9 +292,11 @@ int32_t run_refine(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb,
                    int64_t ldx, double tol, int32_t max_iter, hipStream_t st, int32_t* iters,
                    double* berr) {
     const int64_t n = num->sym->S.n;
+    const int64_t ns = num->nseg;
+    const int64_t ne = ns * nrhs;  // (column, matrix) entries
     if (iters) *iters = 0;
     if (n == 0 || nrhs == 0) {
-        for (int32_t c = 0; berr && c < nrhs; ++c) berr[c] = 0.0;
+        for (int64_t e = 0; berr && e < ne; ++e) berr[e] = 0.0;
         return OK;
     }
     int32_t rc = ensure_solve_work(num, nrhs);
@@ -282,41 +307,43 @@ int32_t run_refine(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb,
         num->ir_work = nullptr;
         num->ir_host = nullptr;
         num->ir_cols = 0;
-        if (hipMalloc(&num->ir_work, sizeof(double) * ((size_t)n + 5) * nrhs) != hipSuccess)
-            return ERR_OOM;
-        if (hipHostMalloc(&num->ir_host, sizeof(double) * nrhs, hipHostMallocDefault) !=
+        if (hipMalloc(&num->ir_work, sizeof(double) * ((size_t)n + 5 * (size_t)ns) * nrhs) !=
             hipSuccess)
+            return ERR_OOM;
+        if (hipHostMalloc(&num->ir_host, sizeof(double) * (size_t)ns * nrhs,
+                          hipHostMallocDefault) != hipSuccess)
             return ERR_OOM;
         num->ir_cols = nrhs;
     }
     double* r = num->ir_work;
     double* bn = r + (size_t)n * nrhs;
-    double* xn = bn + nrhs;
-    double* rn = xn + nrhs;
-    double* eta = rn + nrhs;
-    double* scale = eta + nrhs;
-    const int gy = std::min<int64_t>(grid_of(n), 1024);
+    double* xn = bn + ne;
+    double* rn = xn + ne;
+    double* eta = rn + ne;
+    double* scale = eta + ne;
+    const int32_t* seg = num->a_seg;
+    const dim3 grid_rows(blocks_of(n), nrhs);
     hipLaunchKernelGGL(k_zero_cols, dim3(grid_of(n * nrhs)), dim3(256), 0, st, x, ldx, n, nrhs);
-    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, st, bn, (int64_t)nrhs, 0.0);
-    hipLaunchKernelGGL(k_colmax, dim3(gy, nrhs), dim3(256), 0, st, b, ldb, n, bn);
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_of(ne)), dim3(256), 0, st, bn, ne, 0.0);
+    hipLaunchKernelGGL(k_colmax, grid_rows, dim3(256), 0, st, b, ldb, n, seg, ns, bn);
     for (int32_t it = 0;; ++it) {
-        hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, st, xn, (int64_t)(2 * nrhs), 0.0);
-        hipLaunchKernelGGL(k_resid, dim3(gy, nrhs), dim3(256), 0, st, (const int64_t*)num->a_ptr,
+        hipLaunchKernelGGL(k_fill_f64, dim3(grid_of(2 * ne)), dim3(256), 0, st, xn, 2 * ne, 0.0);
+        hipLaunchKernelGGL(k_resid, grid_rows, dim3(256), 0, st, (const int64_t*)num->a_ptr,
                            (const int32_t*)num->a_col, (const double*)num->a_val, b, ldb,
-                           (const double*)x, ldx, r, n, rn);
-        hipLaunchKernelGGL(k_colmax, dim3(gy, nrhs), dim3(256), 0, st, (const double*)x, ldx, n,
-                           xn);
-        hipLaunchKernelGGL(k_eta, dim3((nrhs + 63) / 64), dim3(64), 0, st, (const double*)rn,
-                           (const double*)xn, (const double*)bn, (const double*)num->a_norm, eta,
-                           scale, nrhs);
-        HIP_TRY(hipMemcpyAsync(num->ir_host, eta, sizeof(double) * nrhs, hipMemcpyDeviceToHost,
+                           (const double*)x, ldx, r, n, seg, ns, rn);
+        hipLaunchKernelGGL(k_colmax, grid_rows, dim3(256), 0, st, (const double*)x, ldx, n, seg,
+                           ns, xn);
+        hipLaunchKernelGGL(k_eta, dim3(blocks_of(ne)), dim3(256), 0, st, (const double*)rn,
+                           (const double*)xn, (const double*)bn, (const double*)num->a_norm, ns,
+                           eta, scale, ne);
+        HIP_TRY(hipMemcpyAsync(num->ir_host, eta, sizeof(double) * ne, hipMemcpyDeviceToHost,
                                st));
         HIP_TRY(hipStreamSynchronize(st));
         bool done = true;
-        for (int32_t c = 0; c < nrhs; ++c) {
-            const double e = num->ir_host[c];
-            if (berr) berr[c] = e;
-            if (!(e <= tol)) done = false;
+        for (int64_t e = 0; e < ne; ++e) {
+            const double v = num->ir_host[e];
+            if (berr) berr[e] = v;
+            if (!(v <= tol)) done = false;
         }
         if (iters) *iters = it;
         if (done) return OK;

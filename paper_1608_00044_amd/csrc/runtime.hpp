@@ -124,7 +124,9 @@ struct spc_numeric {
     int32_t* a_col = nullptr;       // nnz_full
     int64_t* a_src = nullptr;       // nnz_full: input entry of each CSR entry
     double* a_val = nullptr;        // nnz_full
-    double* a_norm = nullptr;       // ||A||_inf (device scalar)
+    double* a_norm = nullptr;       // ||A_k||_inf per matrix of the batch
+    int32_t* a_seg = nullptr;       // batch matrix of every row (null for one matrix)
+    int64_t nseg = 1;
     double* ir_work = nullptr;      // residuals n x ir_cols, then 4 x ir_cols norms/scales
     int64_t ir_cols = 0;
     double* ir_host = nullptr;      // pinned: backward errors of the current iterate

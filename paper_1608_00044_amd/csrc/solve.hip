@@ -11,6 +11,8 @@
 //                            share ancestor rows);
 //   backward: k_bwd_gemv  -- t_s += L21^T y[rows below], per 64-row block,
 //                            one thread per column;
+// Several right-hand sides go through every kernel in groups of eight, so the
+// factor is read once per group.
 //             k_bwd_diag  -- y_s = L11^{-T} (y_s - t_s), panels in reverse.
 // The level sweeps are captured once per right-hand-side count into a HIP
 // graph and replayed, so a solve costs three launches on the host.  The
@@ -92,69 +94,92 @@ __device__ __forceinline__ void stage_block(R* __restrict__ T, R* __restrict__ I
     }
 }
 
+// Right-hand sides are processed NR at a time (NR = 1, or kRhs for several):
+// every kernel reads its part of L once per group of NR columns and keeps NR
+// partial sums per thread.
+constexpr int kRhs = 8;
+
 // Forward, diagonal block: the block L11 (packed lower triangle) and its
 // 16 x 16 diagonal-block inverses are staged in LDS by the workgroup; then for
-// each 16-column panel p
+// each 16-column panel p and each of the NR right-hand sides
 //   t = y_p - L[p, <p] y_{<p}   (thread (j, part) sums every 16th column k,
 //                                the 16 parts meet in LDS),
-//   y_p = inv(D_p) t            (16 lanes of wave 0).
-template <class R>
+//   y_p = inv(D_p) t            (16 threads per right-hand side).
+template <class R, int NR>
 __global__ __launch_bounds__(256) void k_fwd_diag(const int32_t* __restrict__ level_sn, KArgs a,
                                                   const R* __restrict__ arena,
                                                   const R* __restrict__ dinv, R* __restrict__ y,
                                                   int64_t n, int nrhs) {
     extern __shared__ double sm_raw[];
     R* sm = (R*)sm_raw;
-    __shared__ R ys[kMaxWidth + kPanel];
-    __shared__ R red[16][17];
+    __shared__ R ys[NR][kMaxWidth + kPanel];
+    __shared__ R red[NR][16][17];
+    __shared__ R tt[NR][16];
     const int s = level_sn[blockIdx.x];
     const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
     const R* __restrict__ L = arena + a.sn_off[s];
     const R* __restrict__ inv = dinv + a.inv_off[s];
     const int tid = threadIdx.x, j = tid & 15, part = tid >> 4;
+    const int jj = tid & 15, cc = tid >> 4;  // reduction stage: column cc, entry jj
     const int npanel = (w + kPanel - 1) / kPanel;
-    auto cst = [w](int jj) { return (jj * (2 * w - jj - 1)) >> 1; };
+    auto cst = [w](int q) { return (q * (2 * w - q - 1)) >> 1; };
     R* T = sm;
     R* I = sm + w * (w + 1) / 2;
     stage_block<R>(T, I, L, inv, w, ld, npanel, tid);
-    for (int c = 0; c < nrhs; ++c) {
-        R* __restrict__ yc = y + (int64_t)c * n;
-        for (int k = tid; k < w; k += 256) ys[k] = yc[first + k];
+    for (int c0 = 0; c0 < nrhs; c0 += NR) {
+        const int nc = min(NR, nrhs - c0);
+        for (int e = tid; e < NR * w; e += 256) {
+            const int c = e / w, k = e - c * w;
+            ys[c][k] = c < nc ? y[(int64_t)(c0 + c) * n + first + k] : R(0);
+        }
         __syncthreads();
         for (int p = 0; p < npanel; ++p) {
             const int j0 = p * kPanel, jb = min(kPanel, w - j0);
-            R acc = R(0);
+            R acc[NR];
+#pragma unroll
+            for (int c = 0; c < NR; ++c) acc[c] = R(0);
             if (j < jb)
-                for (int k = part; k < j0; k += 16) acc += T[cst(k) + j0 + j] * ys[k];
-            red[part][j] = acc;
+                for (int k = part; k < j0; k += 16) {
+                    const R l = T[cst(k) + j0 + j];
+#pragma unroll
+                    for (int c = 0; c < NR; ++c) acc[c] += l * ys[c][k];
+                }
+#pragma unroll
+            for (int c = 0; c < NR; ++c) red[c][part][j] = acc[c];
             __syncthreads();
-            if (tid < kPanel) {
+            if (cc < NR) {
                 R tot = R(0);
 #pragma unroll
-                for (int q = 0; q < 16; ++q) tot += red[q][tid];
-                const R t = (tid < jb) ? ys[j0 + tid] - tot : R(0);
-                red[0][tid] = t;  // wave 0 only: read back below in order
+                for (int q = 0; q < 16; ++q) tot += red[cc][q][jj];
+                tt[cc][jj] = (jj < jb) ? ys[cc][j0 + jj] - tot : R(0);
+            }
+            __syncthreads();
+            if (cc < NR) {
                 R out = R(0);
 #pragma unroll
                 for (int k = 0; k < kPanel; ++k)
-                    out += I[p * kPanel * kPanel + tid * kPanel + k] * red[0][k];
-                if (tid < jb) ys[j0 + tid] = out;
+                    out += I[p * kPanel * kPanel + jj * kPanel + k] * tt[cc][k];
+                if (jj < jb) ys[cc][j0 + jj] = out;
             }
             __syncthreads();
         }
-        for (int k = tid; k < w; k += 256) yc[first + k] = ys[k];
+        for (int e = tid; e < nc * w; e += 256) {
+            const int c = e / w, k = e - c * w;
+            y[(int64_t)(c0 + c) * n + first + k] = ys[c][k];
+        }
         __syncthreads();
     }
 }
 
 // Forward, below the diagonal block: y[rows(i)] -= sum_k L21[i][k] y_s[k];
-// the four waves split the columns and combine through LDS.
-template <class R>
+// thread (row, wave) walks every 4th column; the four waves combine through
+// LDS.  The block of L21 is read once per NR right-hand sides.
+template <class R, int NR>
 __global__ __launch_bounds__(256) void k_fwd_gemv(const RowBlock* __restrict__ work, KArgs a,
                                                   const R* __restrict__ arena, R* __restrict__ y,
                                                   int64_t n, int nrhs) {
-    __shared__ R ys[kMaxWidth];
-    __shared__ R red[256];
+    __shared__ R ys[kMaxWidth][NR];
+    __shared__ R red[4][NR][64];
     const RowBlock wb = work[blockIdx.x];
     const int s = wb.s;
     const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
@@ -164,34 +189,48 @@ __global__ __launch_bounds__(256) void k_fwd_gemv(const RowBlock* __restrict__ w
     const int32_t* __restrict__ below = a.rows + rp + w;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int i = wb.rb * kTile + lane;
-    for (int c = 0; c < nrhs; ++c) {
-        R* __restrict__ yc = y + (int64_t)c * n;
-        for (int k = tid; k < w; k += 256) ys[k] = yc[first + k];
+    for (int c0 = 0; c0 < nrhs; c0 += NR) {
+        const int nc = min(NR, nrhs - c0);
+        for (int e = tid; e < NR * w; e += 256) {
+            const int c = e / w, k = e - c * w;
+            ys[k][c] = c < nc ? y[(int64_t)(c0 + c) * n + first + k] : R(0);
+        }
         __syncthreads();
-        R acc = R(0);
+        R acc[NR];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) acc[c] = R(0);
         if (i < r) {
 #pragma unroll 4
-            for (int k = wave; k < w; k += 4) acc += P[i + (int64_t)k * ld] * ys[k];
+            for (int k = wave; k < w; k += 4) {
+                const R pv = P[i + (int64_t)k * ld];
+#pragma unroll
+                for (int c = 0; c < NR; ++c) acc[c] += pv * ys[k][c];
+            }
         }
-        red[tid] = acc;
+#pragma unroll
+        for (int c = 0; c < NR; ++c) red[wave][c][lane] = acc[c];
         __syncthreads();
-        if (tid < 64 && i < r)
-            unsafeAtomicAdd(yc + below[i], -(red[lane] + red[64 + lane] + red[128 + lane] +
-                                             red[192 + lane]));
+        if (tid < 64 && i < r) {
+            const int32_t row = below[i];
+            for (int c = 0; c < nc; ++c)
+                unsafeAtomicAdd(y + (int64_t)(c0 + c) * n + row,
+                                -((red[0][c][lane] + red[1][c][lane]) +
+                                  (red[2][c][lane] + red[3][c][lane])));
+        }
         __syncthreads();
     }
 }
 
 // Backward, below the diagonal block: t_s[k] += sum_i L21[i][k] y[rows(i)]
 // over one 64-row block: the gathered entries go to LDS, then thread k walks
-// column k of the block (its own contiguous 64 entries) and adds one partial
-// sum per column.
-template <class R>
+// column k of the block (its own contiguous 64 entries) once per NR
+// right-hand sides and adds one partial sum per column and right-hand side.
+template <class R, int NR>
 __global__ __launch_bounds__(256) void k_bwd_gemv(const RowBlock* __restrict__ work, KArgs a,
                                                   const R* __restrict__ arena,
                                                   const R* __restrict__ y, R* __restrict__ tacc,
                                                   int64_t n, int nrhs) {
-    __shared__ R xr[kTile];
+    __shared__ R xr[kTile][NR];
     const RowBlock wb = work[blockIdx.x];
     const int s = wb.s;
     const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
@@ -201,22 +240,38 @@ __global__ __launch_bounds__(256) void k_bwd_gemv(const RowBlock* __restrict__ w
     const int32_t* __restrict__ below = a.rows + rp + w;
     const int tid = threadIdx.x;
     const int i0 = wb.rb * kTile, m = min(kTile, r - i0);
-    for (int c = 0; c < nrhs; ++c) {
-        const R* __restrict__ yc = y + (int64_t)c * n;
-        if (tid < kTile) xr[tid] = (tid < m) ? yc[below[i0 + tid]] : R(0);
+    for (int c0 = 0; c0 < nrhs; c0 += NR) {
+        const int nc = min(NR, nrhs - c0);
+        for (int e = tid; e < NR * kTile; e += 256) {
+            const int c = e / kTile, ii = e - c * kTile;
+            xr[ii][c] = (c < nc && ii < m) ? y[(int64_t)(c0 + c) * n + below[i0 + ii]] : R(0);
+        }
         __syncthreads();
         for (int k = tid; k < w; k += 256) {
             const R* __restrict__ col = P + i0 + (int64_t)k * ld;
-            R acc0 = R(0), acc1 = R(0), acc2 = R(0), acc3 = R(0);
-            int i = 0;
-            for (; i + 4 <= m; i += 4) {
-                acc0 += col[i] * xr[i];
-                acc1 += col[i + 1] * xr[i + 1];
-                acc2 += col[i + 2] * xr[i + 2];
-                acc3 += col[i + 3] * xr[i + 3];
+            if (NR == 1) {
+                R acc0 = R(0), acc1 = R(0), acc2 = R(0), acc3 = R(0);
+                int i = 0;
+                for (; i + 4 <= m; i += 4) {
+                    acc0 += col[i] * xr[i][0];
+                    acc1 += col[i + 1] * xr[i + 1][0];
+                    acc2 += col[i + 2] * xr[i + 2][0];
+                    acc3 += col[i + 3] * xr[i + 3][0];
+                }
+                for (; i < m; ++i) acc0 += col[i] * xr[i][0];
+                unsafeAtomicAdd(tacc + (int64_t)c0 * n + first + k, (acc0 + acc1) + (acc2 + acc3));
+            } else {
+                R acc[NR];
+#pragma unroll
+                for (int c = 0; c < NR; ++c) acc[c] = R(0);
+                for (int i = 0; i < m; ++i) {
+                    const R pv = col[i];
+#pragma unroll
+                    for (int c = 0; c < NR; ++c) acc[c] += pv * xr[i][c];
+                }
+                for (int c = 0; c < nc; ++c)
+                    unsafeAtomicAdd(tacc + (int64_t)(c0 + c) * n + first + k, acc[c]);
             }
-            for (; i < m; ++i) acc0 += col[i] * xr[i];
-            unsafeAtomicAdd(tacc + (int64_t)c * n + first + k, (acc0 + acc1) + (acc2 + acc3));
         }
         __syncthreads();
     }
@@ -225,8 +280,8 @@ __global__ __launch_bounds__(256) void k_bwd_gemv(const RowBlock* __restrict__ w
 // Backward, diagonal block: y_s = L11^{-T} (y_s - t_s), panels from the last:
 //   u = v_p - L[>p, p]^T y_{>p},   y_p = inv(D_p)^T u,
 // with L11 and the inverses staged in LDS and the dot products split over
-// the workgroup as in k_fwd_diag.
-template <class R>
+// the workgroup as in k_fwd_diag, NR right-hand sides at a time.
+template <class R, int NR>
 __global__ __launch_bounds__(256) void k_bwd_diag(const int32_t* __restrict__ level_sn, KArgs a,
                                                   const R* __restrict__ arena,
                                                   const R* __restrict__ dinv, R* __restrict__ y,
@@ -234,45 +289,62 @@ __global__ __launch_bounds__(256) void k_bwd_diag(const int32_t* __restrict__ le
                                                   int nrhs) {
     extern __shared__ double sm_raw[];
     R* sm = (R*)sm_raw;
-    __shared__ R ys[kMaxWidth + kPanel];
-    __shared__ R red[16][17];
+    __shared__ R ys[NR][kMaxWidth + kPanel];
+    __shared__ R red[NR][16][17];
+    __shared__ R tt[NR][16];
     const int s = level_sn[blockIdx.x];
     const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
     const R* __restrict__ L = arena + a.sn_off[s];
     const R* __restrict__ inv = dinv + a.inv_off[s];
     const int tid = threadIdx.x, j = tid & 15, part = tid >> 4;
+    const int jj = tid & 15, cc = tid >> 4;
     const int npanel = (w + kPanel - 1) / kPanel;
-    auto cst = [w](int jj) { return (jj * (2 * w - jj - 1)) >> 1; };
+    auto cst = [w](int q) { return (q * (2 * w - q - 1)) >> 1; };
     R* T = sm;
     R* I = sm + w * (w + 1) / 2;
     stage_block<R>(T, I, L, inv, w, ld, npanel, tid);
-    for (int c = 0; c < nrhs; ++c) {
-        R* __restrict__ yc = y + (int64_t)c * n;
-        const R* __restrict__ tc = tacc + (int64_t)c * n;
-        for (int k = tid; k < w; k += 256) ys[k] = yc[first + k] - tc[first + k];
+    for (int c0 = 0; c0 < nrhs; c0 += NR) {
+        const int nc = min(NR, nrhs - c0);
+        for (int e = tid; e < NR * w; e += 256) {
+            const int c = e / w, k = e - c * w;
+            const int64_t at = (int64_t)(c0 + c) * n + first + k;
+            ys[c][k] = c < nc ? y[at] - tacc[at] : R(0);
+        }
         __syncthreads();
         for (int p = npanel - 1; p >= 0; --p) {
             const int j0 = p * kPanel, jb = min(kPanel, w - j0);
-            R acc = R(0);
+            R acc[NR];
+#pragma unroll
+            for (int c = 0; c < NR; ++c) acc[c] = R(0);
             if (j < jb)
-                for (int k = j0 + kPanel + part; k < w; k += 16) acc += T[cst(j0 + j) + k] * ys[k];
-            red[part][j] = acc;
+                for (int k = j0 + kPanel + part; k < w; k += 16) {
+                    const R l = T[cst(j0 + j) + k];
+#pragma unroll
+                    for (int c = 0; c < NR; ++c) acc[c] += l * ys[c][k];
+                }
+#pragma unroll
+            for (int c = 0; c < NR; ++c) red[c][part][j] = acc[c];
             __syncthreads();
-            if (tid < kPanel) {
+            if (cc < NR) {
                 R tot = R(0);
 #pragma unroll
-                for (int q = 0; q < 16; ++q) tot += red[q][tid];
-                const R u = (tid < jb) ? ys[j0 + tid] - tot : R(0);
-                red[0][tid] = u;
+                for (int q = 0; q < 16; ++q) tot += red[cc][q][jj];
+                tt[cc][jj] = (jj < jb) ? ys[cc][j0 + jj] - tot : R(0);
+            }
+            __syncthreads();
+            if (cc < NR) {
                 R out = R(0);
 #pragma unroll
                 for (int k = 0; k < kPanel; ++k)
-                    out += I[p * kPanel * kPanel + k * kPanel + tid] * red[0][k];
-                if (tid < jb) ys[j0 + tid] = out;
+                    out += I[p * kPanel * kPanel + k * kPanel + jj] * tt[cc][k];
+                if (jj < jb) ys[cc][j0 + jj] = out;
             }
             __syncthreads();
         }
-        for (int k = tid; k < w; k += 256) yc[first + k] = ys[k];
+        for (int e = tid; e < nc * w; e += 256) {
+            const int c = e / w, k = e - c * w;
+            y[(int64_t)(c0 + c) * n + first + k] = ys[c][k];
+        }
         __syncthreads();
     }
 }
@@ -285,8 +357,12 @@ static size_t diag_lds(int wmax, size_t elem) {
 
 int32_t configure_solve_kernels() {
     const int mx = (int)diag_lds(kMaxWidth, sizeof(double));
-    const void* fns[] = {(const void*)k_fwd_diag<double>, (const void*)k_bwd_diag<double>,
-                         (const void*)k_fwd_diag<float>, (const void*)k_bwd_diag<float>};
+    const void* fns[] = {(const void*)k_fwd_diag<double, 1>, (const void*)k_bwd_diag<double, 1>,
+                         (const void*)k_fwd_diag<float, 1>, (const void*)k_bwd_diag<float, 1>,
+                         (const void*)k_fwd_diag<double, kRhs>,
+                         (const void*)k_bwd_diag<double, kRhs>,
+                         (const void*)k_fwd_diag<float, kRhs>,
+                         (const void*)k_bwd_diag<float, kRhs>};
     for (const void* f : fns)
         if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, mx) != hipSuccess)
             return ERR_HIP;
@@ -298,7 +374,7 @@ namespace {
 // The level sweeps of one solve on the internal work vectors (y, t), as
 // enqueued on stream st.  Gather and scatter stay outside: they touch the
 // caller's b and x, which change from call to call.
-template <class R>
+template <class R, int NR>
 void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* y, R* tacc, hipStream_t st) {
     const Symbolic& S = num->sym->S;
     const DevicePlan* P = num->plan;
@@ -313,20 +389,20 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* y, R* tacc, hipStream_t s
     for (int32_t l = 0; l < nl; ++l) {
         const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1];
         const size_t lds = diag_lds(P->level_maxw[l], sizeof(R));
-        hipLaunchKernelGGL(k_fwd_diag<R>, dim3(n1 - n0), dim3(256), lds, st, P->level_sn + n0, a,
+        hipLaunchKernelGGL((k_fwd_diag<R, NR>), dim3(n1 - n0), dim3(256), lds, st, P->level_sn + n0, a,
                            arena, dinv, y, n, nrhs);
         const int64_t rb0 = P->rowblk_ptr[l], rb1 = P->rowblk_ptr[l + 1];
         if (rb1 > rb0)
-            hipLaunchKernelGGL(k_fwd_gemv<R>, dim3((unsigned)(rb1 - rb0)), dim3(256), 0, st,
+            hipLaunchKernelGGL((k_fwd_gemv<R, NR>), dim3((unsigned)(rb1 - rb0)), dim3(256), 0, st,
                                P->rowblk + rb0, a, arena, y, n, nrhs);
     }
     for (int32_t l = nl - 1; l >= 0; --l) {
         const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1];
         const int64_t rb0 = P->rowblk_ptr[l], rb1 = P->rowblk_ptr[l + 1];
         if (rb1 > rb0)
-            hipLaunchKernelGGL(k_bwd_gemv<R>, dim3((unsigned)(rb1 - rb0)), dim3(256), 0, st,
+            hipLaunchKernelGGL((k_bwd_gemv<R, NR>), dim3((unsigned)(rb1 - rb0)), dim3(256), 0, st,
                                P->rowblk + rb0, a, arena, (const R*)y, tacc, n, nrhs);
-        hipLaunchKernelGGL(k_bwd_diag<R>, dim3(n1 - n0), dim3(256),
+        hipLaunchKernelGGL((k_bwd_diag<R, NR>), dim3(n1 - n0), dim3(256),
                            diag_lds(P->level_maxw[l], sizeof(R)), st, P->level_sn + n0, a, arena,
                            dinv, y, (const R*)tacc, n, nrhs);
     }
@@ -372,12 +448,15 @@ int32_t run_sweeps(spc_numeric* num, int32_t nrhs, hipStream_t st) {
         spc_numeric::SolveGraph e;
         e.nrhs = nrhs;
         HIP_TRY(hipStreamBeginCapture(num->capture, hipStreamCaptureModeThreadLocal));
+        const size_t half = (size_t)n * nrhs;
         if (num->prec == 1) {
             float* y = (float*)num->work;
-            enqueue_sweeps<float>(num, nrhs, y, y + (size_t)n * nrhs, num->capture);
+            if (nrhs == 1) enqueue_sweeps<float, 1>(num, nrhs, y, y + half, num->capture);
+            else enqueue_sweeps<float, kRhs>(num, nrhs, y, y + half, num->capture);
         } else {
             double* y = (double*)num->work;
-            enqueue_sweeps<double>(num, nrhs, y, y + (size_t)n * nrhs, num->capture);
+            if (nrhs == 1) enqueue_sweeps<double, 1>(num, nrhs, y, y + half, num->capture);
+            else enqueue_sweeps<double, kRhs>(num, nrhs, y, y + half, num->capture);
         }
         const hipError_t ce = hipStreamEndCapture(num->capture, &e.graph);
         if (ce != hipSuccess || !e.graph) return ERR_HIP;

@@ -427,6 +427,7 @@ int32_t analyze(int64_t n, const int64_t* colptr, const int32_t* rowind, const i
     S = Symbolic();
     S.n = n;
     S.opt = opt;
+    S.batch_ptr = {0, n};
     S.nnz_a = n ? colptr[n] : 0;
     S.perm.resize((size_t)n);
     for (int64_t k = 0; k < n; ++k) S.perm[k] = perm ? perm[k] : (int32_t)k;

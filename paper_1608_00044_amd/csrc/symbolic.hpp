@@ -71,6 +71,9 @@ struct Symbolic {
     std::vector<int32_t> level_ptr; // nlevels+1 into level_sn
     std::vector<int32_t> level_sn;  // supernodes grouped by level, increasing index inside
     int32_t max_w = 0, max_r = 0;
+    // independent matrices of a batch: matrix k holds rows and columns
+    // [batch_ptr[k], batch_ptr[k + 1]) of the block-diagonal whole ({0, n} for one)
+    std::vector<int64_t> batch_ptr;
 
     int32_t width(int64_t s) const { return sn_ptr[s + 1] - sn_ptr[s]; }
     int32_t nrows(int64_t s) const { return (int32_t)(rowptr[s + 1] - rowptr[s]); }

@@ -320,6 +320,54 @@ def make_workload(name, repeat=0, nrhs=None, dims=None):
     return p
 
 
+# Batch of independent 2D 5-point Laplacians: grid side uniform in
+# [side_lo, side_hi], lognormal(0, 0.5) edge weights, diagonal = incident
+# weight sum + shift, geometric nested dissection, one N(0, 1) right-hand side.
+BATCH_RECIPE = dict(count=2000, side_lo=16, side_hi=128, sigma=0.5, shift=1e-3, nrhs=1, cfg=4)
+
+
+def make_batch(count=None, seed=4000, side_lo=None, side_hi=None, nrhs=None):
+    """List of Problems following BATCH_RECIPE (overrides shrink it for tests)."""
+    r = BATCH_RECIPE
+    count = r["count"] if count is None else count
+    lo = r["side_lo"] if side_lo is None else side_lo
+    hi = r["side_hi"] if side_hi is None else side_hi
+    nrhs = r["nrhs"] if nrhs is None else nrhs
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sides = rng.integers(lo, hi + 1, size=count)
+    return [make_grid_problem("lap", (int(sd), int(sd)), seed + 1 + k, sigma=r["sigma"],
+                              shift=r["shift"], nrhs=nrhs) for k, sd in enumerate(sides)]
+
+
+def stack_batch(probs):
+    """Concatenated values and right-hand sides of a batch (matrix k's rows
+    after matrix k-1's), as the batched C ABI takes them."""
+    vals = np.concatenate([p.values for p in probs]) if probs else np.zeros(0)
+    rhs = None
+    if probs and probs[0].rhs is not None:
+        rhs = np.asfortranarray(np.concatenate([p.rhs for p in probs], axis=0))
+    return vals, rhs
+
+
+def block_diagonal(probs):
+    """The direct sum of a batch as one Problem (the matrix a batched analysis
+    factors), with the members' orderings and right-hand sides stacked."""
+    n = sum(p.n for p in probs)
+    cps, ris, pms = [np.zeros(1, dtype=np.int64)], [], []
+    off, ent = 0, 0
+    for p in probs:
+        cps.append(np.asarray(p.colptr[1:], dtype=np.int64) + ent)
+        ris.append(np.asarray(p.rowind, dtype=np.int64) + off)
+        pm = np.arange(p.n) if p.perm is None else np.asarray(p.perm)
+        pms.append(pm + off)
+        off += p.n
+        ent += int(p.colptr[-1])
+    vals, rhs = stack_batch(probs)
+    ri = np.concatenate(ris).astype(np.int32) if ris else np.zeros(0, dtype=np.int32)
+    pm = np.concatenate(pms).astype(np.int32) if pms else np.zeros(0, dtype=np.int32)
+    return Problem(n, np.concatenate(cps), ri, vals, pm, rhs)
+
+
 # ---------------------------------------------------------------------------
 # tiny cases
 # ---------------------------------------------------------------------------

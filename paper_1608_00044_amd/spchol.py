@@ -35,7 +35,8 @@ EXPORTS = ("spc_default_options", "spc_analyze", "spc_symbolic_info_get", "spc_s
            "spc_symbolic_free",
            "spc_factor", "spc_refactor", "spc_numeric_status", "spc_solve", "spc_factor_export",
            "spc_numeric_free", "spc_status_string", "spc_numeric_set_timing",
-           "spc_numeric_get_timing", "spc_solve_refine", "spc_numeric_info_get")
+           "spc_numeric_get_timing", "spc_solve_refine", "spc_numeric_info_get",
+           "spc_analyze_batch")
 
 
 class spc_options(C.Structure):
@@ -49,7 +50,7 @@ class spc_symbolic_info(C.Structure):
                 ("nnz_stored", C.c_int64), ("nsup", C.c_int64), ("nlevels", C.c_int64),
                 ("npairs", C.c_int64), ("nrel", C.c_int64), ("factor_bytes", C.c_int64),
                 ("plan_bytes", C.c_int64), ("flops", C.c_double), ("flops_stored", C.c_double),
-                ("max_width", C.c_int32), ("max_below", C.c_int32)]
+                ("max_width", C.c_int32), ("max_below", C.c_int32), ("nbatch", C.c_int64)]
 
 
 class spc_numeric_info(C.Structure):
@@ -82,6 +83,9 @@ def lib():
         L.spc_default_options.restype = None
         L.spc_analyze.argtypes = [C.c_int64, vp, vp, vp, C.POINTER(spc_options), C.POINTER(vp)]
         L.spc_analyze.restype = C.c_int32
+        L.spc_analyze_batch.argtypes = [C.c_int32, vp, vp, vp, vp, C.POINTER(spc_options),
+                                        C.POINTER(vp)]
+        L.spc_analyze_batch.restype = C.c_int32
         L.spc_symbolic_info_get.argtypes = [vp, C.POINTER(spc_symbolic_info)]
         L.spc_symbolic_info_get.restype = C.c_int32
         L.spc_symbolic_export.argtypes = [vp, vp, vp, vp, vp]
@@ -145,24 +149,29 @@ def _stream_ptr(stream):
 # symbolic
 # ---------------------------------------------------------------------------
 
+def _options(sn_cap=150, amalg_ratio=0.0, sched=0, mem_budget_bytes=0, spin_limit=0,
+             debug_flags=0, precision=0):
+    opt = spc_options()
+    lib().spc_default_options(C.byref(opt))
+    opt.sn_cap = int(sn_cap)
+    opt.sched = int(sched)
+    opt.amalg_ratio = float(amalg_ratio)
+    opt.mem_budget_bytes = int(mem_budget_bytes)
+    opt.spin_limit = int(spin_limit)
+    opt.debug_flags = int(debug_flags)
+    opt.precision = int(precision)
+    return opt
+
+
 class Symbolic:
     """spc_analyze: host symbolic analysis of the lower CSC pattern."""
 
-    def __init__(self, n, colptr, rowind, perm=None, sn_cap=150, amalg_ratio=0.0, sched=0,
-                 mem_budget_bytes=0, spin_limit=0, debug_flags=0, precision=0):
+    def __init__(self, n, colptr, rowind, perm=None, **opts):
         self.n = int(n)
         cp = _np(colptr, np.int64)
         ri = _np(rowind, np.int32)
         pm = None if perm is None else _np(perm, np.int32)
-        opt = spc_options()
-        lib().spc_default_options(C.byref(opt))
-        opt.sn_cap = int(sn_cap)
-        opt.sched = int(sched)
-        opt.amalg_ratio = float(amalg_ratio)
-        opt.mem_budget_bytes = int(mem_budget_bytes)
-        opt.spin_limit = int(spin_limit)
-        opt.debug_flags = int(debug_flags)
-        opt.precision = int(precision)
+        opt = _options(**opts)
         h = C.c_void_p()
         if ri.size == 0:
             ri = np.zeros(1, dtype=np.int32)
@@ -171,6 +180,41 @@ class Symbolic:
             raise SpcError(st, "spc_analyze")
         self.handle = h
         self.perm = np.arange(self.n, dtype=np.int32) if pm is None else pm.copy()
+        self.batch_ptr = np.array([0, self.n], dtype=np.int64)
+
+    @classmethod
+    def batch(cls, mats, **opts):
+        """spc_analyze_batch over mats = [(n, colptr, rowind, perm or None), ...]."""
+        self = cls.__new__(cls)
+        count = len(mats)
+        ns = np.array([int(m[0]) for m in mats], dtype=np.int64)
+        keep = []
+        cps = (C.c_void_p * max(count, 1))()
+        ris = (C.c_void_p * max(count, 1))()
+        pms = (C.c_void_p * max(count, 1))()
+        any_perm = False
+        for k, m in enumerate(mats):
+            cp = _np(m[1], np.int64)
+            ri = _np(m[2], np.int32)
+            if ri.size == 0:
+                ri = np.zeros(1, dtype=np.int32)
+            pm = None if len(m) < 4 or m[3] is None else _np(m[3], np.int32)
+            keep += [cp, ri, pm]
+            cps[k] = cp.ctypes.data
+            ris[k] = ri.ctypes.data
+            pms[k] = None if pm is None else pm.ctypes.data
+            any_perm |= pm is not None
+        opt = _options(**opts)
+        h = C.c_void_p()
+        st = lib().spc_analyze_batch(count, _ptr(ns) if count else None, cps, ris,
+                                     pms if any_perm else None, C.byref(opt), C.byref(h))
+        if st != SPC_OK:
+            raise SpcError(st, "spc_analyze_batch")
+        self.handle = h
+        self.n = int(ns.sum())
+        self.batch_ptr = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+        self.perm = None
+        return self
 
     def info(self) -> dict:
         inf = spc_symbolic_info()
@@ -317,14 +361,19 @@ class Numeric:
         berr); raises SpcError unless converged when check is set."""
         one, B, ldb, X, ldx, k = self._operands(b, x)
         it = C.c_int32(0)
-        berr = np.zeros(max(k, 1), dtype=np.float64)
+        berr = np.zeros(max(k * max(len(self.sym.batch_ptr) - 1, 1), 1), dtype=np.float64)
         st = lib().spc_solve_refine(self.handle, k, C.c_void_p(B.data_ptr()), ldb,
                                     C.c_void_p(X.data_ptr()), ldx, float(tol), int(max_iter),
                                     _stream_ptr(stream), C.byref(it), _ptr(berr))
         self.last_refine_status = int(st)
         if st != SPC_OK and (check or st != SPC_ERR_NOT_CONVERGED):
             raise SpcError(st, "spc_solve_refine")
-        return (X.reshape(self.sym.n) if one else X), int(it.value), berr[:k]
+        nb = len(self.sym.batch_ptr) - 1
+        if nb > 1:  # (matrix, column) backward errors of a batch
+            berr = berr[: k * nb].reshape(k, nb).T
+        else:
+            berr = berr[:k]
+        return (X.reshape(self.sym.n) if one else X), int(it.value), berr
 
     def info(self) -> dict:
         t = spc_numeric_info()
@@ -375,6 +424,10 @@ class Numeric:
 # C-ABI-named entry points
 def analyze(n, colptr, rowind, perm=None, **opts) -> Symbolic:
     return Symbolic(n, colptr, rowind, perm, **opts)
+
+
+def analyze_batch(mats, **opts) -> Symbolic:
+    return Symbolic.batch(mats, **opts)
 
 
 def factor(sym: Symbolic, values, stream=None) -> Numeric:

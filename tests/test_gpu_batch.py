@@ -1,0 +1,90 @@
+"""GPU checks of batched factorization: many independent SPD matrices of
+uneven size through one analysis, one set of factorization launches (level
+sets, or the one persistent task-queue launch) and one solve.
+
+The oracle factors the direct sum of the batch (the matrix the batched
+analysis defines); bars as for single matrices: FP64 factor entries within
+|dL_ij| <= 1e-10 |L_ij| + 1e-13 sqrt(c_ii c_jj) / L_jj, residual <= 1e-12,
+every matrix's own backward error <= 1e-14 (FP64 solve) or <= 1e-10 (FP32
+factor + FP64 refinement, measured per matrix by the library and by the
+oracle); a matrix factored and solved inside the batch matches the same
+matrix factored and solved alone to rounding level."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_00044_amd import inputs, spchol
+from tests.gpu_util import compare_factor, say, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch(count, seed, lo=6, hi=40):
+    probs = inputs.make_batch(count=count, seed=seed, side_lo=lo, side_hi=hi)
+    probs.append(inputs.random_spd_pattern(90, 0.05, seed=seed, nrhs=1))
+    probs.append(inputs.dense_spd(70, seed=seed, nrhs=1))
+    return probs
+
+
+def _factor_batch(probs, sched=0, precision=0, cap=150, ratio=0.1):
+    torch = torch_dev()
+    sym = spchol.analyze_batch([(p.n, p.colptr, p.rowind, p.perm) for p in probs], sn_cap=cap,
+                               amalg_ratio=ratio, sched=sched, precision=precision)
+    vals, rhs = inputs.stack_batch(probs)
+    num = spchol.factor(sym, torch.from_numpy(vals).to("cuda:0"))
+    return sym, num, rhs
+
+
+@pytest.mark.parametrize("sched", [0, 1, 2])
+def test_batch_fp64_factor_and_solve(sched):
+    torch = torch_dev()
+    probs = _batch(12, 77 + sched)
+    sym, num, rhs = _factor_batch(probs, sched=sched)
+    assert num.status() == 0
+    big = inputs.block_diagonal(probs)
+    worst, rho, _ = compare_factor(big, num, 150, 0.1, "batch")
+    say("batch sched", sched, "n", big.n, "worst/tol", worst, "residual", rho)
+    assert worst <= 1.0 and rho <= 1e-12
+    x = num.solve(torch.from_numpy(rhs).to("cuda:0")).cpu().numpy().reshape(-1, 1)
+    off = 0
+    for p in probs:
+        xk = x[off:off + p.n]
+        eta = oracle.backward_error(p.n, p.colptr, p.rowind, p.values, p.rhs, xk)
+        assert eta.max() <= 1e-14
+        off += p.n
+
+
+def test_batch_member_matches_single_factorization():
+    torch = torch_dev()
+    probs = _batch(9, 5)
+    sym, num, rhs = _factor_batch(probs)
+    x = num.solve(torch.from_numpy(rhs).to("cuda:0")).cpu().numpy().ravel()
+    off = 0
+    for k, p in enumerate(probs):
+        if k % 3 == 0:
+            s1 = spchol.analyze(p.n, p.colptr, p.rowind, p.perm, sn_cap=150, amalg_ratio=0.1)
+            n1 = spchol.factor(s1, torch.from_numpy(p.values).to("cuda:0"))
+            x1 = n1.solve(torch.from_numpy(np.ascontiguousarray(p.rhs[:, 0])).to("cuda:0"))
+            x1 = x1.cpu().numpy()
+            np.testing.assert_allclose(x[off:off + p.n], x1, rtol=0,
+                                       atol=1e-12 * np.abs(x1).max())
+        off += p.n
+
+
+@pytest.mark.parametrize("sched", [0, 2])
+def test_batch_fp32_refined_per_matrix(sched):
+    torch = torch_dev()
+    probs = _batch(10, 31 + sched)
+    sym, num, rhs = _factor_batch(probs, sched=sched, precision=1)
+    assert num.status() == 0
+    x, iters, berr = num.solve_refine(torch.from_numpy(rhs).to("cuda:0"), tol=1e-10,
+                                      max_iter=10)
+    assert berr.shape == (len(probs), 1)
+    xs = x.cpu().numpy().reshape(-1, 1)
+    off = 0
+    for k, p in enumerate(probs):
+        eta = oracle.backward_error(p.n, p.colptr, p.rowind, p.values, p.rhs, xs[off:off + p.n])
+        assert eta.max() <= 1e-10
+        np.testing.assert_allclose(berr[k, 0], eta[0], rtol=0.05, atol=1e-14)
+        off += p.n
+    say("batch fp32 refine iters", iters, "max eta", berr.max())

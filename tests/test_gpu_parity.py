@@ -291,3 +291,21 @@ def test_solve_graph_replays_match():
             assert num.status() == 0
     num.free()
     sym.free()
+
+
+@pytest.mark.parametrize("k", [1, 7, 8, 9, 20])
+def test_solve_right_hand_side_groups(k):
+    """Right-hand sides go through the solve kernels in groups of eight: every
+    column of a ragged last group matches the one-column solve of the same
+    right-hand side, and all are backward stable."""
+    torch = torch_dev()
+    p = inputs.make_grid_problem("lap", (14, 14, 14), 51, sigma=1.0, shift=1e-3, nrhs=0)
+    sym, num, _ = gpu_factor(p, 150, 0.1)
+    assert num.status() == 0
+    B = np.asfortranarray(np.random.default_rng(k).standard_normal((p.n, k)))
+    x = num.solve(torch.from_numpy(B).to("cuda:0")).cpu().numpy().reshape(p.n, k)
+    eta = oracle.backward_error(p.n, p.colptr, p.rowind, p.values, B, x)
+    assert eta.max() <= 1e-14
+    for c in (0, k - 1):
+        xc = num.solve(torch.from_numpy(np.ascontiguousarray(B[:, c])).to("cuda:0")).cpu().numpy()
+        np.testing.assert_allclose(x[:, c], xc, rtol=0, atol=1e-12 * np.abs(xc).max())

@@ -218,3 +218,44 @@ def test_task_order_arguments():
     assert e.value.status == spchol.SPC_ERR_ARG
     tk, cnt0 = sym.tasks(4)
     assert tk.tolist() == [[0, 0, 0, 0]] and cnt0.tolist() == [0]
+
+
+def test_batch_analysis_is_the_union_of_single_analyses():
+    """The batched analysis of independent matrices equals their single
+    analyses side by side: etree, column counts, supernodes (never across two
+    matrices) and row lists, shifted by each matrix's offset."""
+    probs = inputs.make_batch(count=6, side_lo=5, side_hi=17)
+    probs.append(inputs.random_spd_pattern(40, 0.1, seed=3))
+    probs.append(inputs.tridiag(1))
+    mats = [(p.n, p.colptr, p.rowind, p.perm) for p in probs]
+    bs = spchol.analyze_batch(mats, sn_cap=16, amalg_ratio=0.1)
+    inf = bs.info()
+    assert inf["nbatch"] == len(probs) and inf["n"] == sum(p.n for p in probs)
+    parent, cc, sn, _ = bs.export()
+    rp, rows = bs.rows()
+    off, s_at = 0, 0
+    flops = 0.0
+    for p in probs:
+        one = spchol.analyze(p.n, p.colptr, p.rowind, p.perm, sn_cap=16, amalg_ratio=0.1)
+        par1, cc1, sn1, _ = one.export()
+        rp1, rows1 = one.rows()
+        assert np.array_equal(parent[off:off + p.n], np.where(par1 < 0, -1, par1 + off))
+        assert np.array_equal(cc[off:off + p.n], cc1)
+        ns1 = len(sn1) - 1
+        assert np.array_equal(sn[s_at:s_at + ns1 + 1], sn1 + off)
+        got = rows[rp[s_at]:rp[s_at + ns1]]
+        assert np.array_equal(got, rows1 + off)
+        flops += one.info()["flops"]
+        off += p.n
+        s_at += ns1
+    assert s_at == inf["nsup"] and inf["flops"] == flops
+
+
+def test_batch_rejects_bad_member():
+    good = inputs.tridiag(5)
+    with pytest.raises(spchol.SpcError) as e:
+        spchol.analyze_batch([(5, good.colptr, good.rowind, None),
+                              (4, [0, 2, 3, 4, 5], [1, 0, 2, 3, 3], None)])
+    assert e.value.status == spchol.SPC_ERR_PATTERN
+    empty = spchol.analyze_batch([])
+    assert empty.info()["n"] == 0 and empty.info()["nbatch"] == 0
