@@ -257,6 +257,74 @@ void spc_numeric_free(spc_numeric* num);
 /* Static English text for a status code. */
 const char* spc_status_string(spc_status st);
 
+/* ------------------------------------------------------------------------
+ * Request server (continuous batching over resident patterns)
+ *
+ * Serves factor+solve and solve-only requests on the current device.  Each
+ * added pattern keeps numeric factors resident in HBM; a factor+solve
+ * request refactors an idle one of its pattern with fresh values (a new one
+ * is created when the predicted bytes, spc_symbolic_info.factor_bytes plus
+ * work vectors for max_nrhs columns, fit the budget after evicting idle
+ * factors least recently used first) and solves; a completed, successful
+ * factorization becomes the pattern's current factor, which solve-only
+ * requests use.  Up to max_inflight requests run at once on separate
+ * streams, so their kernels overlap on the device; requests that arrive
+ * meanwhile are admitted in arrival order as slots and memory free up.  A
+ * worker thread schedules; submit and wait are thread safe.  The caller's
+ * device buffers (values, b, x) must stay valid until the request's wait
+ * returns.  This extends the paper's factor/solve split (Section II-A) to a
+ * stream of requests; the paper itself serves none.
+ * ------------------------------------------------------------------------ */
+typedef struct spc_server spc_server;
+
+typedef struct spc_server_options {
+    int32_t max_inflight;      /* requests on the device at once, 1..64 (default 8)  */
+    int32_t max_nrhs;          /* most right-hand sides of one request (default 64) */
+    int64_t mem_budget_bytes;  /* bytes for resident factors and their work vectors;
+                                  0 = 80% of the device's free memory at creation   */
+} spc_server_options;
+
+typedef struct spc_request {
+    int32_t pattern;        /* from spc_server_add_pattern                           */
+    int32_t kind;           /* 0: factor `values` then solve; 1: solve with the
+                               pattern's current factor                              */
+    int32_t nrhs;           /* 0..max_nrhs                                           */
+    int32_t reserved;
+    const double* values;   /* device, nnz_a values of the pattern (kind 0)          */
+    const double* b;        /* device, column-major n x nrhs, leading dimension ldb  */
+    int64_t ldb;
+    double* x;              /* device, column-major n x nrhs, leading dimension ldx  */
+    int64_t ldx;
+} spc_request;
+
+typedef struct spc_request_result {
+    int32_t status;         /* 0; a failed pivot column (> 0, kind 0); SPC_ERR_OOM (the
+                               pattern cannot fit the budget); SPC_ERR_NOT_FACTORED
+                               (kind 1 with no current factor); SPC_ERR_HIP         */
+    int32_t reserved;
+    double queue_ms;        /* submit to admission                                   */
+    double latency_ms;      /* submit to completion of its device work               */
+} spc_request_result;
+
+typedef struct spc_server_stats {
+    int64_t submitted, completed, rejected, evictions;
+    int64_t bytes_in_use, peak_bytes, budget_bytes;
+    int32_t peak_inflight, resident_factors;
+} spc_server_stats;
+
+void spc_server_default_options(spc_server_options* opt);
+spc_status spc_server_create(const spc_server_options* opt, spc_server** out);
+/* Registers a symbolic handle (kept referenced until spc_server_destroy). */
+spc_status spc_server_add_pattern(spc_server* srv, spc_symbolic* sym, int32_t* pattern);
+/* Queues a request; *ticket identifies it.  SPC_ERR_ARG on bad sizes. */
+spc_status spc_server_submit(spc_server* srv, const spc_request* req, int64_t* ticket);
+/* Blocks until the request has completed; fills *out (may be NULL) and
+ * forgets the ticket. */
+spc_status spc_server_wait(spc_server* srv, int64_t ticket, spc_request_result* out);
+spc_status spc_server_stats_get(spc_server* srv, spc_server_stats* out);
+/* Completes every queued request, then frees the resident factors. */
+spc_status spc_server_destroy(spc_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,7 +11,8 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libspchol.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["symbolic.cpp", "plan.cpp", "schedule.cpp", "api.cpp", "factor.hip", "solve.hip", "refine.hip"]
+SOURCES = ["symbolic.cpp", "plan.cpp", "schedule.cpp", "api.cpp", "server.cpp", "factor.hip",
+           "solve.hip", "refine.hip"]
 ARCH = os.environ.get("SPCHOL_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -47,7 +48,8 @@ def build(verbose: bool = False) -> str:
     if failed:
         raise RuntimeError("HIP build failed for: " + ", ".join(failed))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "-shared", "--offload-arch=" + ARCH, "-o", tmp] + objs
+    # -z defs: an unresolved symbol is a build error, not a load-time one
+    cmd = [HIPCC, "-shared", "--offload-arch=" + ARCH, "-Wl,-z,defs", "-pthread", "-o", tmp] + objs
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB

@@ -487,3 +487,9 @@ void spc_numeric_free(spc_numeric* num) {
 }
 
 }  // extern "C"
+
+namespace spc {
+// Numeric object of sym without a factorization (the request server's pool).
+int32_t numeric_create(spc_symbolic* sym, spc_numeric** out) { return alloc_numeric(sym, out); }
+int64_t numeric_bytes(const Symbolic& S) { return factor_bytes(S); }
+}  // namespace spc

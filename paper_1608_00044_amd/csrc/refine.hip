@@ -29,29 +29,60 @@ namespace spc {
 
 namespace {
 
+// Groups of 64 rows walked by one wave of the row kernels.
+constexpr int kRowsPerWave = 16;
+
 int grid_of(int64_t n) {
     return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192));
 }
 
-// One thread per element (the row kernels reduce per wave, so every row needs its own lane).
+// One thread per element.
 unsigned blocks_of(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + 255) / 256); }
+// Row kernels: each wave covers kRowsPerWave x 64 consecutive rows.
+unsigned row_blocks(int64_t n) {
+    const int64_t per_block = 4 * 64 * (int64_t)kRowsPerWave;
+    return (unsigned)std::max<int64_t>(1, (n + per_block - 1) / per_block);
+}
 
 // Non-negative doubles order like their bit patterns as unsigned integers.
 __device__ __forceinline__ void atomic_max_nonneg(double* p, double v) {
     atomicMax((unsigned long long*)p, (unsigned long long)__double_as_longlong(v));
 }
 
-// out[seg] = max(out[seg], v) for the row of this lane (seg < 0: no row).  A
-// wave whose rows all lie in one matrix of the batch reduces first and
-// issues one atomic; otherwise every lane issues its own.
-__device__ __forceinline__ void seg_max(double* out, int seg, double v) {
-    const int s0 = __shfl(seg, 0, 64);
-    if (__all(seg == s0 || seg < 0) && s0 >= 0) {
-        for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-        if ((threadIdx.x & 63) == 0) atomic_max_nonneg(out + s0, v);
-    } else if (seg >= 0) {
-        atomic_max_nonneg(out + seg, v);
+// Per-matrix maxima over rows.  Every wave walks kRowsPerWave consecutive
+// groups of 64 rows and carries a wave-uniform (matrix, max) pair: a group
+// whose rows all lie in one matrix is reduced across the wave and merged
+// into the pair (flushed with one atomic when the matrix changes); a group
+// that straddles matrices issues one atomic per lane.  One matrix costs one
+// atomic per wave, not per row.
+
+struct SegMax {
+    int seg = -1;
+    double m = 0.0;
+    __device__ __forceinline__ void add(double* out, int segi, double v) {
+        const int s0 = __shfl(segi, 0, 64);
+        if (__all(segi == s0 || segi < 0) && s0 >= 0) {
+            for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+            if (s0 != seg) {
+                flush(out);
+                seg = s0;
+                m = v;
+            } else {
+                m = fmax(m, v);
+            }
+        } else if (segi >= 0) {
+            atomic_max_nonneg(out + segi, v);
+        }
     }
+    __device__ __forceinline__ void flush(double* out) {
+        if (seg >= 0 && (threadIdx.x & 63) == 0) atomic_max_nonneg(out + seg, m);
+    }
+};
+
+// Row handled by this lane in step u of its wave's range.
+__device__ __forceinline__ int64_t row_of(int u) {
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    return (wave * kRowsPerWave + u) * 64 + (threadIdx.x & 63);
 }
 
 __device__ __forceinline__ int seg_of(const int32_t* seg, int64_t i, int64_t n) {
@@ -82,17 +113,20 @@ __global__ void k_gather_vals(const double* __restrict__ values, const int64_t* 
         aval[q] = values[src[q]];
 }
 
-// ||A_k||_inf = max over the rows of matrix k of the absolute row sum; one
-// thread per row.
+// ||A_k||_inf = max over the rows of matrix k of the absolute row sum.
 __global__ __launch_bounds__(256) void k_anorm(const int64_t* __restrict__ ptr,
                                                const double* __restrict__ val,
                                                const int32_t* __restrict__ seg, int64_t n,
                                                double* __restrict__ out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double s = 0.0;
-    if (i < n)
-        for (int64_t q = ptr[i]; q < ptr[i + 1]; ++q) s += fabs(val[q]);
-    seg_max(out, seg_of(seg, i, n), s);
+    SegMax sm;
+    for (int u = 0; u < kRowsPerWave; ++u) {
+        const int64_t i = row_of(u);
+        double s = 0.0;
+        if (i < n)
+            for (int64_t q = ptr[i]; q < ptr[i + 1]; ++q) s += fabs(val[q]);
+        sm.add(out, seg_of(seg, i, n), s);
+    }
+    sm.flush(out);
 }
 
 // ||v_{k,c}||_inf per matrix k and column c (blockIdx.y); out[c * nseg + k].
@@ -100,8 +134,12 @@ __global__ __launch_bounds__(256) void k_colmax(const double* __restrict__ v, in
                                                 const int32_t* __restrict__ seg, int64_t nseg,
                                                 double* __restrict__ out) {
     const int c = blockIdx.y;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    seg_max(out + c * nseg, seg_of(seg, i, n), i < n ? fabs(v[i + c * ld]) : 0.0);
+    SegMax sm;
+    for (int u = 0; u < kRowsPerWave; ++u) {
+        const int64_t i = row_of(u);
+        sm.add(out + c * nseg, seg_of(seg, i, n), i < n ? fabs(v[i + c * ld]) : 0.0);
+    }
+    sm.flush(out + c * nseg);
 }
 
 // r_c = b_c - A x_c and ||r_{k,c}||_inf, one thread per row; blockIdx.y = c.
@@ -115,21 +153,25 @@ __global__ __launch_bounds__(256) void k_resid(const int64_t* __restrict__ ptr,
                                                double* __restrict__ rnorm) {
     const int c = blockIdx.y;
     const double* __restrict__ xc = x + c * ldx;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double ri = 0.0;
-    if (i < n) {
-        double s0 = 0.0, s1 = 0.0;
-        int64_t q = ptr[i];
-        const int64_t q1 = ptr[i + 1];
-        for (; q + 1 < q1; q += 2) {
-            s0 += val[q] * xc[col[q]];
-            s1 += val[q + 1] * xc[col[q + 1]];
+    SegMax sm;
+    for (int u = 0; u < kRowsPerWave; ++u) {
+        const int64_t i = row_of(u);
+        double ri = 0.0;
+        if (i < n) {
+            double s0 = 0.0, s1 = 0.0;
+            int64_t q = ptr[i];
+            const int64_t q1 = ptr[i + 1];
+            for (; q + 1 < q1; q += 2) {
+                s0 += val[q] * xc[col[q]];
+                s1 += val[q + 1] * xc[col[q + 1]];
+            }
+            if (q < q1) s0 += val[q] * xc[col[q]];
+            ri = b[i + c * ldb] - (s0 + s1);
+            r[i + c * n] = ri;
         }
-        if (q < q1) s0 += val[q] * xc[col[q]];
-        ri = b[i + c * ldb] - (s0 + s1);
-        r[i + c * n] = ri;
+        sm.add(rnorm + c * nseg, seg_of(seg, i, n), fabs(ri));
     }
-    seg_max(rnorm + c * nseg, seg_of(seg, i, n), fabs(ri));
+    sm.flush(rnorm + c * nseg);
 }
 
 // eta and the scale 1 / ||r|| of the next correction (0 when r = 0), per
@@ -261,7 +303,7 @@ int32_t load_refine_matrix(spc_numeric* num, const double* values, hipStream_t s
     hipLaunchKernelGGL(k_fill_f64, dim3(grid_of(num->nseg)), dim3(256), 0, st, num->a_norm,
                        num->nseg, 0.0);
     if (S.n > 0)
-        hipLaunchKernelGGL(k_anorm, dim3(blocks_of(S.n)), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_anorm, dim3(row_blocks(S.n)), dim3(256), 0, st,
                            (const int64_t*)num->a_ptr, (const double*)num->a_val,
                            (const int32_t*)num->a_seg, S.n, num->a_norm);
     HIP_TRY(hipGetLastError());
@@ -322,7 +364,7 @@ int32_t run_refine(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb,
     double* eta = rn + ne;
     double* scale = eta + ne;
     const int32_t* seg = num->a_seg;
-    const dim3 grid_rows(blocks_of(n), nrhs);
+    const dim3 grid_rows(row_blocks(n), nrhs);
     hipLaunchKernelGGL(k_zero_cols, dim3(grid_of(n * nrhs)), dim3(256), 0, st, x, ldx, n, nrhs);
     hipLaunchKernelGGL(k_fill_f64, dim3(grid_of(ne)), dim3(256), 0, st, bn, ne, 0.0);
     hipLaunchKernelGGL(k_colmax, grid_rows, dim3(256), 0, st, b, ldb, n, seg, ns, bn);

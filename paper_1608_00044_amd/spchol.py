@@ -36,7 +36,9 @@ EXPORTS = ("spc_default_options", "spc_analyze", "spc_symbolic_info_get", "spc_s
            "spc_factor", "spc_refactor", "spc_numeric_status", "spc_solve", "spc_factor_export",
            "spc_numeric_free", "spc_status_string", "spc_numeric_set_timing",
            "spc_numeric_get_timing", "spc_solve_refine", "spc_numeric_info_get",
-           "spc_analyze_batch")
+           "spc_analyze_batch", "spc_server_default_options", "spc_server_create",
+           "spc_server_add_pattern", "spc_server_submit", "spc_server_wait",
+           "spc_server_stats_get", "spc_server_destroy")
 
 
 class spc_options(C.Structure):
@@ -58,6 +60,29 @@ class spc_numeric_info(C.Structure):
                 ("fp64_blocks", C.c_int64)]
 
 
+class spc_server_options(C.Structure):
+    _fields_ = [("max_inflight", C.c_int32), ("max_nrhs", C.c_int32),
+                ("mem_budget_bytes", C.c_int64)]
+
+
+class spc_request(C.Structure):
+    _fields_ = [("pattern", C.c_int32), ("kind", C.c_int32), ("nrhs", C.c_int32),
+                ("reserved", C.c_int32), ("values", C.c_void_p), ("b", C.c_void_p),
+                ("ldb", C.c_int64), ("x", C.c_void_p), ("ldx", C.c_int64)]
+
+
+class spc_request_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("reserved", C.c_int32), ("queue_ms", C.c_double),
+                ("latency_ms", C.c_double)]
+
+
+class spc_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("rejected", C.c_int64),
+                ("evictions", C.c_int64), ("bytes_in_use", C.c_int64), ("peak_bytes", C.c_int64),
+                ("budget_bytes", C.c_int64), ("peak_inflight", C.c_int32),
+                ("resident_factors", C.c_int32)]
+
+
 class spc_kernel_times(C.Structure):
     _fields_ = [("ms", C.c_double * 5), ("launches", C.c_int64 * 5), ("total_ms", C.c_double)]
 
@@ -77,6 +102,12 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError("libspchol.so is not built; run paper_1608_00044_amd.build.build()")
+        # torch ships its own HIP runtime: load it first so that the library
+        # binds to that same runtime (one runtime per process, shared streams)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         vp = C.c_void_p
         L.spc_default_options.argtypes = [C.POINTER(spc_options)]
@@ -119,6 +150,20 @@ def lib():
         L.spc_solve_refine.restype = C.c_int32
         L.spc_numeric_info_get.argtypes = [vp, C.POINTER(spc_numeric_info)]
         L.spc_numeric_info_get.restype = C.c_int32
+        L.spc_server_default_options.argtypes = [C.POINTER(spc_server_options)]
+        L.spc_server_default_options.restype = None
+        L.spc_server_create.argtypes = [C.POINTER(spc_server_options), C.POINTER(vp)]
+        L.spc_server_create.restype = C.c_int32
+        L.spc_server_add_pattern.argtypes = [vp, vp, C.POINTER(C.c_int32)]
+        L.spc_server_add_pattern.restype = C.c_int32
+        L.spc_server_submit.argtypes = [vp, C.POINTER(spc_request), C.POINTER(C.c_int64)]
+        L.spc_server_submit.restype = C.c_int32
+        L.spc_server_wait.argtypes = [vp, C.c_int64, C.POINTER(spc_request_result)]
+        L.spc_server_wait.restype = C.c_int32
+        L.spc_server_stats_get.argtypes = [vp, C.POINTER(spc_server_stats)]
+        L.spc_server_stats_get.restype = C.c_int32
+        L.spc_server_destroy.argtypes = [vp]
+        L.spc_server_destroy.restype = C.c_int32
         L.spc_status_string.argtypes = [C.c_int32]
         L.spc_status_string.restype = C.c_char_p
         _lib = L
@@ -417,6 +462,87 @@ class Numeric:
     def __del__(self):
         try:
             self.free()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# request server
+# ---------------------------------------------------------------------------
+
+class Server:
+    """spc_server_*: continuous batching of factor+solve / solve-only requests."""
+
+    def __init__(self, max_inflight=8, max_nrhs=64, mem_budget_bytes=0):
+        opt = spc_server_options()
+        lib().spc_server_default_options(C.byref(opt))
+        opt.max_inflight = int(max_inflight)
+        opt.max_nrhs = int(max_nrhs)
+        opt.mem_budget_bytes = int(mem_budget_bytes)
+        h = C.c_void_p()
+        st = lib().spc_server_create(C.byref(opt), C.byref(h))
+        if st != SPC_OK:
+            raise SpcError(st, "spc_server_create")
+        self.handle = h
+        self._patterns = []
+        self._keep = {}
+
+    def add_pattern(self, sym: Symbolic) -> int:
+        pid = C.c_int32(0)
+        st = lib().spc_server_add_pattern(self.handle, sym.handle, C.byref(pid))
+        if st != SPC_OK:
+            raise SpcError(st, "spc_server_add_pattern")
+        self._patterns.append(sym)
+        return int(pid.value)
+
+    def submit(self, pattern, b, x, values=None, kind=None) -> int:
+        """b, x: column-major (n, k) float64 device tensors (x written);
+        values given: factor then solve (kind 0), else solve only (kind 1)."""
+        r = spc_request()
+        r.pattern = int(pattern)
+        r.kind = int((0 if values is not None else 1) if kind is None else kind)
+        n = self._patterns[pattern].n
+        B = b.reshape(n, -1)
+        X = x.reshape(n, -1)
+        k = B.shape[1]
+        for t, nm in ((B, "b"), (X, "x")):
+            if t.stride(0) != 1 or (k > 1 and t.stride(1) < n):
+                raise ValueError("%s must be column-major (n, k)" % nm)
+        r.nrhs = k
+        r.values = None if values is None else values.data_ptr()
+        r.b, r.ldb = B.data_ptr(), max(B.stride(1) if k > 1 else n, n)
+        r.x, r.ldx = X.data_ptr(), max(X.stride(1) if k > 1 else n, n)
+        t = C.c_int64(0)
+        st = lib().spc_server_submit(self.handle, C.byref(r), C.byref(t))
+        if st != SPC_OK:
+            raise SpcError(st, "spc_server_submit")
+        self._keep[int(t.value)] = (values, b, x)
+        return int(t.value)
+
+    def wait(self, ticket) -> dict:
+        res = spc_request_result()
+        st = lib().spc_server_wait(self.handle, int(ticket), C.byref(res))
+        if st != SPC_OK:
+            raise SpcError(st, "spc_server_wait")
+        self._keep.pop(int(ticket), None)
+        return {"status": res.status, "queue_ms": res.queue_ms, "latency_ms": res.latency_ms}
+
+    def stats(self) -> dict:
+        t = spc_server_stats()
+        st = lib().spc_server_stats_get(self.handle, C.byref(t))
+        if st != SPC_OK:
+            raise SpcError(st, "spc_server_stats_get")
+        return {f: getattr(t, f) for f, _ in t._fields_}
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            lib().spc_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.destroy()
         except Exception:
             pass
 
