@@ -157,6 +157,150 @@ def mixed_precision(name, steps, warmup, tol=1e-10):
     return out
 
 
+def batched(count, steps, precision, tol=1e-10):
+    """Batch of independent 2D Laplacians (BATCH_RECIPE): one batched analysis,
+    then timed steps of factorization + one-RHS solve (FP64) or factorization
+    + refinement to tol (FP32)."""
+    import torch
+
+    from paper_1608_00044_amd import inputs, spchol
+
+    t0 = time.perf_counter()
+    probs = inputs.make_batch(count=count)
+    gen_s = time.perf_counter() - t0
+    vals_h, rhs_h = inputs.stack_batch(probs)
+    t0 = time.perf_counter()
+    sym = spchol.analyze_batch([(p.n, p.colptr, p.rowind, p.perm) for p in probs], sn_cap=150,
+                               amalg_ratio=0.0, precision=precision)
+    an_ms = (time.perf_counter() - t0) * 1e3
+    inf = sym.info()
+    vals = torch.from_numpy(vals_h).to("cuda:0")
+    b = torch.from_numpy(np.ascontiguousarray(rhs_h)).to("cuda:0")
+    num = spchol.factor(sym, vals)
+    if num.status() != 0:
+        raise RuntimeError("batched factor status %d" % num.status())
+    x = None
+    stream = torch.cuda.current_stream()
+    f_ms, s_ms, iters = [], [], []
+    for k in range(steps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        num.refactor(vals)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if precision == 0:
+            x = num.solve(b, x=x)
+            torch.cuda.synchronize()
+        else:
+            x, it, berr = num.solve_refine(b, x=x, tol=tol, max_iter=20)
+            iters.append(it)
+        if k > 0:  # the first step captures the solve graphs
+            s_ms.append((time.perf_counter() - t0) * 1e3)
+            f_ms.append(e0.elapsed_time(e1))
+    xs = x.cpu().numpy().ravel()
+    worst, off = 0.0, 0
+    for p in probs[:: max(1, len(probs) // 50)] if False else probs[:50]:
+        worst = max(worst, backward_error(p, xs[off:off + p.n], p.rhs[:, 0]))
+        off += p.n
+    fm, sm = float(np.mean(f_ms)), float(np.mean(s_ms))
+    out = {"count": count, "n_total": inf["n"], "nnz_L": inf["nnz_l"], "flops_F": inf["flops"],
+           "nsup": inf["nsup"], "levels": inf["nlevels"], "precision": ["fp64", "fp32_ir"][precision],
+           "generate_s": gen_s, "analyze_ms": an_ms, "factor_ms": fm,
+           "factor_gflops": inf["flops"] / (fm * 1e-3) / 1e9, "solve_ms": sm,
+           "matrices_per_s": count / ((fm + sm) * 1e-3),
+           "backward_error_first50": worst,
+           "launches": "level-set launches over all matrices at once"}
+    if precision == 1:
+        out["refine_iters"] = float(np.mean(iters))
+    log("batch %s: factor %.2f ms (%.1f GFLOP/s), solve %.2f ms, %.0f matrices/s" %
+        (out["precision"], fm, out["factor_gflops"], sm, out["matrices_per_s"]))
+    num.free()
+    sym.free()
+    return out
+
+
+SERVE_RECIPE = dict(rate=200.0, patterns_2d=16, patterns_3d=16, side2d=(32, 256),
+                    side3d=(16, 48), sigma=1.0, solve_only=0.3, nrhs=(1, 4, 16, 64),
+                    value_sets=2)
+
+
+def serving(requests, seed=5000):
+    """Poisson request stream over 32 resident patterns through the request
+    server; reports latency percentiles and throughput."""
+    import torch
+
+    from paper_1608_00044_amd import inputs, spchol
+
+    r = SERVE_RECIPE
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sides2 = np.linspace(r["side2d"][0], r["side2d"][1], r["patterns_2d"]).round().astype(int)
+    sides3 = np.linspace(r["side3d"][0], r["side3d"][1], r["patterns_3d"]).round().astype(int)
+    dims = [(int(s), int(s)) for s in sides2] + [(int(s),) * 3 for s in sides3]
+    probs, vals = [], []
+    for k, d in enumerate(dims):
+        sets = [inputs.make_grid_problem("lap", d, seed + 100 * k + v, sigma=r["sigma"],
+                                         shift=1e-3, nrhs=0) for v in range(r["value_sets"])]
+        probs.append(sets[0])
+        vals.append([torch.from_numpy(p.values).to("cuda:0") for p in sets])
+    torch.zeros(1, device="cuda:0")
+    srv = spchol.Server(max_inflight=16, max_nrhs=max(r["nrhs"]))
+    syms = [spchol.analyze(p.n, p.colptr, p.rowind, p.perm, sn_cap=150, amalg_ratio=0.1)
+            for p in probs]
+    pids = [srv.add_pattern(s) for s in syms]
+    # requests: pattern, kind, nrhs, arrival time
+    gaps = rng.exponential(1.0 / r["rate"], size=requests)
+    arrive = np.cumsum(gaps)
+    pat = rng.integers(len(probs), size=requests)
+    kind = (rng.random(requests) < r["solve_only"]).astype(int)
+    nrhs = rng.choice(r["nrhs"], size=requests)
+    # every pattern's first request factors
+    seen = set()
+    for i in range(requests):
+        if pat[i] not in seen:
+            kind[i] = 0
+            seen.add(pat[i])
+    bufs = {}
+    for k in range(len(probs)):
+        n = probs[k].n
+        bufs[k] = (torch.randn((max(r["nrhs"]), n), dtype=torch.float64, device="cuda:0").t(),)
+    xs = [torch.empty((int(nrhs[i]), probs[pat[i]].n), dtype=torch.float64,
+                      device="cuda:0").t() for i in range(requests)]
+    torch.cuda.synchronize()
+    tickets = []
+    t0 = time.perf_counter()
+    for i in range(requests):
+        wait = t0 + arrive[i] - time.perf_counter()
+        if wait > 0:
+            time.sleep(wait)
+        k = int(pat[i])
+        b = bufs[k][0][:, : int(nrhs[i])]
+        v = vals[k][i % r["value_sets"]] if kind[i] == 0 else None
+        tickets.append(srv.submit(pids[k], b, xs[i], values=v))
+    res = [srv.wait(t) for t in tickets]
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.destroy()
+    lat = np.array([q["latency_ms"] for q in res])
+    ok = sum(1 for q in res if q["status"] == 0)
+    cols = int(sum(int(nrhs[i]) for i in range(requests) if res[i]["status"] == 0))
+    out = {"requests": requests, "rate_per_s": r["rate"], "patterns": len(probs),
+           "ok": ok, "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "mean_ms": float(lat.mean()), "requests_per_s": requests / wall,
+           "solves_per_s": cols / wall, "peak_inflight": st["peak_inflight"],
+           "peak_bytes": st["peak_bytes"], "evictions": st["evictions"],
+           "recipe": "Poisson arrivals at %g/s over %d 2D (side %d..%d) and %d 3D 7-point "
+                     "(side %d..%d) patterns, lognormal(0,%g) weights, %d%% solve-only on the "
+                     "current factor, nrhs uniform in %s" % (
+                         r["rate"], r["patterns_2d"], r["side2d"][0], r["side2d"][1],
+                         r["patterns_3d"], r["side3d"][0], r["side3d"][1], r["sigma"],
+                         int(100 * r["solve_only"]), list(r["nrhs"]))}
+    log("serve: p50 %.2f ms p99 %.2f ms, %.1f req/s, %.0f solves/s, peak inflight %d" %
+        (out["p50_ms"], out["p99_ms"], out["requests_per_s"], out["solves_per_s"],
+         out["peak_inflight"]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +314,10 @@ def main():
     ap.add_argument("--mixed-workload", default="elast27_48",
                     help="workload of the FP64 vs FP32+refinement comparison ('' to skip)")
     ap.add_argument("--mixed-steps", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=2000,
+                    help="matrices of the batched workload (0 to skip)")
+    ap.add_argument("--serve-requests", type=int, default=1000,
+                    help="requests of the serving stream (0 to skip)")
     ap.add_argument("--cpu-sample", default=None,
                     help="grid of the bounded oracle sample (default: 40^3 for 3D workloads, "
                          "the full grid for 2D ones)")
@@ -306,6 +454,10 @@ def main():
     sym.free()
     if args.mixed_workload:
         out["mixed_precision"] = mixed_precision(args.mixed_workload, args.mixed_steps, 1)
+    if args.batch:
+        out["batched"] = [batched(args.batch, 3, 0), batched(args.batch, 3, 1)]
+    if args.serve_requests:
+        out["serving"] = serving(args.serve_requests)
     if not args.no_cpu_baseline:
         if args.cpu_sample:
             dims = tuple(int(v) for v in args.cpu_sample.split(","))

@@ -182,7 +182,8 @@ __device__ __forceinline__ void panel_factor(C* __restrict__ T, C* __restrict__ 
         for (int rr = 0; rr < kPanel; ++rr) {
             const C v = (i < jb && rr < jb) ? x[rr] : C(0);
             Dinv[rr * kPanel + i] = v;
-            inv_g[q * kPanel * kPanel + rr * kPanel + i] = (S)v;
+            // compact global copy: the panel's jb x jb inverse, row major
+            if (i < jb && rr < jb) inv_g[q * kPanel * kPanel + rr * jb + i] = (S)v;
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -410,8 +411,14 @@ __device__ __forceinline__ void trsm_rows(const R* __restrict__ L, int ld,
                 }
             }
         }
+        const int jbp = min(kPanel, w - kPanel * p);  // the inverse is jbp x jbp
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) iv[kk] = inv[p * kPanel * kPanel + lr * kPanel + 4 * kk + lk];
+        for (int kk = 0; kk < 4; ++kk) {
+            const int c = 4 * kk + lk;
+            const bool in = lr < jbp && c < jbp;
+            const R v = inv[in ? p * kPanel * kPanel + lr * jbp + c : 0];
+            iv[kk] = in ? v : R(0);
+        }
     };
 #pragma unroll
     for (int p = 0; p < NP; ++p)

@@ -83,11 +83,19 @@ __device__ __forceinline__ void stage_block(R* __restrict__ T, R* __restrict__ I
             if (e < ww && i >= j) T[((j * (2 * w - j - 1)) >> 1) + i] = v[u];
         }
     }
+    // the inverses are stored compactly (the last panel as jb x jb); LDS
+    // holds every panel as a zero-padded 16 x 16 block
     const int ni = npanel * kPanel * kPanel;
     for (int e0 = tid; e0 < ni; e0 += 8 * 256) {
         R v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = (e0 + u * 256 < ni) ? inv[e0 + u * 256] : R(0);
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * 256, p = e >> 8, r = (e >> 4) & 15, c = e & 15;
+            const int jbp = min(kPanel, w - kPanel * p);
+            const bool in = e < ni && r < jbp && c < jbp;
+            const R t = inv[in ? p * kPanel * kPanel + r * jbp + c : 0];
+            v[u] = in ? t : R(0);
+        }
 #pragma unroll
         for (int u = 0; u < 8; ++u)
             if (e0 + u * 256 < ni) I[e0 + u * 256] = v[u];

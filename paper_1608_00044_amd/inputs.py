@@ -107,20 +107,20 @@ def dense_from_lower_csc(n, colptr, rowind, values, perm=None):
 
 def _box_ids(lo, hi, dims):
     """Node ids of the box [lo, hi) in natural order (x fastest)."""
-    axes = [np.arange(lo[d], hi[d], dtype=np.int64) for d in range(len(dims))]
-    if any(ax.size == 0 for ax in axes):
+    ndim = len(dims)
+    if any(hi[d] <= lo[d] for d in range(ndim)):
         return np.zeros(0, dtype=np.int64)
-    grids = np.meshgrid(*axes, indexing="ij")  # grids[d][ix, iy, iz]
-    ids = np.zeros(grids[0].shape, dtype=np.int64)
+    ids = np.zeros([1] * ndim, dtype=np.int64)
     stride = 1
-    for d in range(len(dims)):
-        ids += grids[d] * stride
+    for d in range(ndim):
+        shape = [1] * ndim
+        shape[ndim - 1 - d] = hi[d] - lo[d]  # slowest axis first
+        ids = ids + (np.arange(lo[d], hi[d], dtype=np.int64) * stride).reshape(shape)
         stride *= dims[d]
-    # natural order = increasing id
-    return np.sort(ids.ravel())
+    return ids.ravel()
 
 
-@functools.lru_cache(maxsize=64)
+@functools.lru_cache(maxsize=256)
 def nested_dissection(dims: tuple) -> np.ndarray:
     """Geometric nested-dissection elimination order of a regular grid.
 
@@ -130,15 +130,27 @@ def nested_dissection(dims: tuple) -> np.ndarray:
     node is numbered as is.  Returns ``order`` with order[new] = old node id.
     """
     dims = tuple(int(d) for d in dims)
-    out: list[np.ndarray] = []
+    ndim = len(dims)
+    strides = [int(np.prod(dims[:d])) for d in range(ndim)]
+    order = np.empty(int(np.prod(dims)), dtype=np.int64)
+    pos = [0]
+
+    def emit(lo, hi):
+        if all(hi[d] - lo[d] == 1 for d in range(ndim)):
+            order[pos[0]] = sum(lo[d] * strides[d] for d in range(ndim))
+            pos[0] += 1
+        else:
+            ids = _box_ids(lo, hi, dims)
+            order[pos[0]:pos[0] + ids.size] = ids
+            pos[0] += ids.size
 
     def rec(lo, hi):
-        ext = [hi[d] - lo[d] for d in range(len(dims))]
+        ext = [hi[d] - lo[d] for d in range(ndim)]
         if min(ext) <= 0:
             return
         big = max(ext)
         if big == 1:
-            out.append(_box_ids(lo, hi, dims))
+            emit(lo, hi)
             return
         ax = ext.index(big)
         mid = lo[ax] + big // 2
@@ -150,10 +162,10 @@ def nested_dissection(dims: tuple) -> np.ndarray:
         lo_s[ax], hi_s[ax] = mid, mid + 1
         rec(lo_l, hi_l)
         rec(lo_r, hi_r)
-        out.append(_box_ids(lo_s, hi_s, dims))
+        emit(lo_s, hi_s)
 
-    rec([0] * len(dims), list(dims))
-    order = np.concatenate(out) if out else np.zeros(0, dtype=np.int64)
+    rec([0] * ndim, list(dims))
+    assert pos[0] == order.size
     order.setflags(write=False)
     return order
 
@@ -222,25 +234,38 @@ def _grid_edges(dims, full):
     return u[order], v[order]
 
 
+@functools.lru_cache(maxsize=256)
+def _laplacian_pattern(dims):
+    """Edges and lower CSC pattern of the grid Laplacian, with the position
+    in the CSC of every COO entry [(v, u) per edge, then the diagonal]."""
+    n = int(np.prod(dims))
+    u, v = _grid_edges(dims, full=False)
+    rows = np.concatenate([v, np.arange(n)])
+    cols = np.concatenate([u, np.arange(n)])
+    order = np.argsort(cols * n + rows, kind="stable")  # the entries are distinct
+    colptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(colptr, cols + 1, 1)
+    colptr = np.cumsum(colptr)
+    for a in (u, v, order, colptr):
+        a.setflags(write=False)
+    return n, u, v, colptr, rows[order].astype(np.int32), order
+
+
 def grid_laplacian(dims, rng, sigma=None, shift=0.0):
     """Graph Laplacian of the 2D 5-point / 3D 7-point grid plus shift*I.
 
     Edge weights are 1 (sigma None) or lognormal(0, sigma) drawn in edge order;
     off-diagonal entries are -w and diag = sum of incident w + shift."""
     dims = tuple(int(d) for d in dims)
-    n = int(np.prod(dims))
-    u, v = _grid_edges(dims, full=False)
+    n, u, v, colptr, rowind, order = _laplacian_pattern(dims)
     if sigma is None:
         w = np.ones(u.size)
     else:
         w = rng.lognormal(mean=0.0, sigma=sigma, size=u.size)
-    deg = np.zeros(n)
-    np.add.at(deg, u, w)
-    np.add.at(deg, v, w)
-    rows = np.concatenate([v, np.arange(n)])
-    cols = np.concatenate([u, np.arange(n)])
-    vals = np.concatenate([-w, deg + shift])
-    return (n,) + lower_csc_from_coo(n, rows, cols, vals)
+    # incident weights summed in edge order, first as u then as v
+    deg = np.bincount(np.concatenate([u, v]), weights=np.concatenate([w, w]), minlength=n)
+    vals = np.concatenate([-w, deg + shift])[order]
+    return n, colptr.copy(), rowind.copy(), vals
 
 
 def grid27_3dof(dims, rng, shift=1e-3):
