@@ -239,12 +239,14 @@ spc_status spc_numeric_info_get(spc_numeric* num, spc_numeric_info* out);
  * with HIP events recorded on the factor's stream around every launch while
  * timing is enabled (spc_numeric_set_timing).  Classes: 0 value load (fill +
  * load), 1 diagonal factorization, 2 panel solve, 3 update + scatter, 4 the
- * persistent task-queue kernel (schedule 2: all of 1-3 in one launch).
+ * persistent task-queue kernel (schedule 2: all of 1-3 in one launch), 5 the
+ * small-supernode kernel (1-3 for supernodes of at most 16 columns and 64 rows
+ * below the diagonal block, one wavefront each).
  * ms[c] is the summed duration of class c, launches[c] its launch count.
  * Synchronizes the stream.  SPC_ERR_ARG if timing was never enabled. */
 typedef struct spc_kernel_times {
-    double ms[5];
-    int64_t launches[5];
+    double ms[6];
+    int64_t launches[6];
     double total_ms; /* from the first to the last recorded event */
 } spc_kernel_times;
 

@@ -453,7 +453,7 @@ spc_status spc_numeric_get_timing(spc_numeric* num, spc_kernel_times* out) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, num->events[m.a], num->events[m.b]) != hipSuccess)
             return SPC_ERR_HIP;
-        if (m.cls >= 0 && m.cls < 5) {
+        if (m.cls >= 0 && m.cls < 6) {
             out->ms[m.cls] += ms;
             out->launches[m.cls] += 1;
         }

@@ -838,14 +838,22 @@ namespace {
 template <class R>
 void launch_ft(spc_numeric* num, const DevicePlan* P, const Symbolic& S, const KArgs& a,
                int32_t l, hipStream_t st) {
-    const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1];
+    const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1], nbig = P->level_nbig[l];
     const int wmax = P->level_maxw[l];
     // room for the packed triangle in FP64 (also the FP32 kernel's fallback pass)
     const size_t lds_tri = ((size_t)wmax * (wmax + 1) / 2 + 1) * sizeof(double);
-    int ev = mark_begin(num, st);
-    hipLaunchKernelGGL(k_potrf<R>, dim3(n1 - n0), dim3(kPotrfThreads), lds_tri, st,
-                       P->level_sn + n0, a, (R*)num->arena, (R*)num->dinv, num->status_dev);
-    mark_end(num, st, 1, ev);
+    int ev;
+    if (nbig > 0) {
+        ev = mark_begin(num, st);
+        hipLaunchKernelGGL(k_potrf<R>, dim3(nbig), dim3(kPotrfThreads), lds_tri, st,
+                           P->level_sn + n0, a, (R*)num->arena, (R*)num->dinv, num->status_dev);
+        mark_end(num, st, 1, ev);
+    }
+    if (n1 - n0 > nbig) {  // small supernodes: factor, update and scatter, one wave each
+        ev = mark_begin(num, st);
+        launch_small_factor(num, a, P->level_sn + n0 + nbig, n1 - n0 - nbig, st);
+        mark_end(num, st, 5, ev);
+    }
     const int64_t rb0 = P->rowblk_ptr[l], rb1 = P->rowblk_ptr[l + 1];
     if (rb1 > rb0) {
         ev = mark_begin(num, st);

@@ -35,6 +35,7 @@ void count_work(const Symbolic& S, std::vector<int64_t>& rb_ptr, std::vector<int
     for (int32_t l = 0; l < nl; ++l) {
         int64_t rb = 0, tl = 0;
         for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
+            if (is_small(S, S.level_sn[q])) continue;  // one wave does all of its work
             const int64_t r = S.nbelow(S.level_sn[q]);
             const int64_t nb = (r + kTile - 1) / kTile;
             rb += nb;
@@ -193,7 +194,21 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
         put(o.pair_excl, ex.data(), np);
     }
     put(o.rel, S.rel.data(), S.rel.size() * 4);
-    put(o.level_sn, S.level_sn.data(), S.level_sn.size() * 4);
+    {
+        // per level: the large supernodes first (in the analysis' order), then the small
+        const int32_t nl = (int32_t)S.level_ptr.size() - 1;
+        std::vector<int32_t> ls;
+        ls.reserve(S.level_sn.size());
+        P->level_nbig.assign((size_t)nl, 0);
+        for (int32_t l = 0; l < nl; ++l) {
+            for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q)
+                if (!is_small(S, S.level_sn[q])) ls.push_back(S.level_sn[q]);
+            P->level_nbig[l] = (int32_t)(ls.size() - S.level_ptr[l]);
+            for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q)
+                if (is_small(S, S.level_sn[q])) ls.push_back(S.level_sn[q]);
+        }
+        put(o.level_sn, ls.data(), ls.size() * 4);
+    }
     {
         const int32_t nl = (int32_t)S.level_ptr.size() - 1;
         std::vector<RowBlock> rb((size_t)P->rowblk_ptr.back());
@@ -210,6 +225,7 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
             bulk.clear();
             for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
                 const int32_t s = S.level_sn[q];
+                if (is_small(S, s)) continue;
                 P->level_maxw[l] = std::max(P->level_maxw[l], S.width(s));
                 const int32_t r = S.nbelow(s);
                 const int32_t nb = (r + kTile - 1) / kTile;

@@ -20,6 +20,13 @@ constexpr int kMaxWidth = 150;
 // Column panel of the blocked diagonal factorization; the inverse of every
 // kPanel x kPanel diagonal block is kept for the panel and triangular solves.
 constexpr int kPanel = 16;
+// Small supernodes (at most kSmallW columns and kSmallR rows below the
+// diagonal block) are factored and solved by one wavefront each.
+constexpr int kSmallW = 16;
+constexpr int kSmallR = 64;
+inline bool is_small(const Symbolic& S, int64_t s) {
+    return S.width(s) <= kSmallW && S.nbelow(s) <= kSmallR;
+}
 
 // Device task-queue schedule: task kinds and the task record.
 enum : int32_t { kTaskF = 0, kTaskT = 1, kTaskU = 2 };
@@ -62,10 +69,12 @@ struct DevicePlan {
     int32_t* rb_base = nullptr;  // per supernode: index of its first panel row block
     int64_t nrowblk = 0;
     int32_t max_w = 0;
-    // host-side launch bookkeeping per level
+    // host-side launch bookkeeping per level; inside each level of level_sn
+    // the large supernodes come first, then the small ones
+    std::vector<int32_t> level_nbig;
     std::vector<int64_t> rowblk_ptr, tile_ptr;
     std::vector<int64_t> tile_crit;   // per level: leading tiles that feed level l + 1
-    std::vector<int32_t> level_maxw;
+    std::vector<int32_t> level_maxw;  // widest large supernode of the level
 };
 
 // Pointer bundle passed by value to kernels.
@@ -160,5 +169,10 @@ int32_t run_refine(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb,
 int32_t load_refine_matrix(spc_numeric* num, const double* values, hipStream_t stream);
 void free_refine(spc_numeric* num);
 void drop_solve_graphs(spc_numeric* num);
+// Small-supernode kernels (one wave per supernode of list[0 .. count)).
+void launch_small_factor(spc_numeric* num, const KArgs& a, const int32_t* list, int count,
+                         hipStream_t stream);
+void launch_small_solve(spc_numeric* num, const KArgs& a, const int32_t* list, int count,
+                        void* y, int64_t n, int nrhs, bool forward, hipStream_t stream);
 
 }  // namespace spc

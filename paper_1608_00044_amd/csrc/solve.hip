@@ -395,24 +395,29 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* y, R* tacc, hipStream_t s
     hipLaunchKernelGGL(k_zero<R>, dim3(g), dim3(256), 0, st, tacc, total);
     const int32_t nl = (int32_t)S.level_ptr.size() - 1;
     for (int32_t l = 0; l < nl; ++l) {
-        const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1];
+        const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1], nbig = P->level_nbig[l];
         const size_t lds = diag_lds(P->level_maxw[l], sizeof(R));
-        hipLaunchKernelGGL((k_fwd_diag<R, NR>), dim3(n1 - n0), dim3(256), lds, st, P->level_sn + n0, a,
-                           arena, dinv, y, n, nrhs);
+        if (nbig > 0)
+            hipLaunchKernelGGL((k_fwd_diag<R, NR>), dim3(nbig), dim3(256), lds, st,
+                               P->level_sn + n0, a, arena, dinv, y, n, nrhs);
+        launch_small_solve(num, a, P->level_sn + n0 + nbig, n1 - n0 - nbig, y, n, nrhs, true, st);
         const int64_t rb0 = P->rowblk_ptr[l], rb1 = P->rowblk_ptr[l + 1];
         if (rb1 > rb0)
             hipLaunchKernelGGL((k_fwd_gemv<R, NR>), dim3((unsigned)(rb1 - rb0)), dim3(256), 0, st,
                                P->rowblk + rb0, a, arena, y, n, nrhs);
     }
     for (int32_t l = nl - 1; l >= 0; --l) {
-        const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1];
+        const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1], nbig = P->level_nbig[l];
         const int64_t rb0 = P->rowblk_ptr[l], rb1 = P->rowblk_ptr[l + 1];
         if (rb1 > rb0)
             hipLaunchKernelGGL((k_bwd_gemv<R, NR>), dim3((unsigned)(rb1 - rb0)), dim3(256), 0, st,
                                P->rowblk + rb0, a, arena, (const R*)y, tacc, n, nrhs);
-        hipLaunchKernelGGL((k_bwd_diag<R, NR>), dim3(n1 - n0), dim3(256),
-                           diag_lds(P->level_maxw[l], sizeof(R)), st, P->level_sn + n0, a, arena,
-                           dinv, y, (const R*)tacc, n, nrhs);
+        if (nbig > 0)
+            hipLaunchKernelGGL((k_bwd_diag<R, NR>), dim3(nbig), dim3(256),
+                               diag_lds(P->level_maxw[l], sizeof(R)), st, P->level_sn + n0, a,
+                               arena, dinv, y, (const R*)tacc, n, nrhs);
+        launch_small_solve(num, a, P->level_sn + n0 + nbig, n1 - n0 - nbig, y, n, nrhs, false,
+                           st);
     }
 }
 

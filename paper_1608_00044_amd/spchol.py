@@ -84,10 +84,10 @@ class spc_server_stats(C.Structure):
 
 
 class spc_kernel_times(C.Structure):
-    _fields_ = [("ms", C.c_double * 5), ("launches", C.c_int64 * 5), ("total_ms", C.c_double)]
+    _fields_ = [("ms", C.c_double * 6), ("launches", C.c_int64 * 6), ("total_ms", C.c_double)]
 
 
-KERNEL_CLASSES = ("load", "potrf", "trsm", "update", "tasks")
+KERNEL_CLASSES = ("load", "potrf", "trsm", "update", "tasks", "small")
 
 
 class SpcError(RuntimeError):
