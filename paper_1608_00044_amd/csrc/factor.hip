@@ -343,6 +343,9 @@ __device__ __forceinline__ bool potrf_task(int s, const KArgs& a, S* __restrict_
             if (e < ww && i >= j) base[i + (int64_t)j * ld] = (S)T[cst(j) + i];
         }
     }
+    // packed copy of L11 for the solves, after the inverses
+    S* __restrict__ pk = inv_g + inverse_elems(w);
+    for (int e = tid; e < dummy; e += kPotrfThreads) pk[e] = (S)T[e];
     return false;
 }
 

@@ -76,17 +76,9 @@ PlanOffsets plan_layout(const Symbolic& S, const std::vector<int64_t>& rb_ptr,
 
 }  // namespace
 
-// Inverses of the kPanel-column diagonal blocks of a w-column supernode,
-// stored compactly: every full panel as kPanel x kPanel, the last partial one
-// (jb < kPanel columns) as jb x jb, each row major.
-int64_t inverse_elems(int32_t w) {
-    const int64_t full = w / kPanel, rem = w % kPanel;
-    return full * kPanel * kPanel + rem * rem;
-}
-
 int64_t inverse_blocks_elems(const Symbolic& S) {
     int64_t t = 0;
-    for (int64_t s = 0; s < S.nsup; ++s) t += inverse_elems(S.width(s));
+    for (int64_t s = 0; s < S.nsup; ++s) t += diag_region_elems(S.width(s));
     return t;
 }
 
@@ -139,7 +131,7 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
         first[s] = S.sn_ptr[s];
         w[s] = S.width((int64_t)s);
         inv[s] = io;
-        io += inverse_elems(w[s]);
+        io += diag_region_elems(w[s]);
     }
     P->inv_elems = io;
     put(o.sn_first, first.data(), ns * 4);

@@ -27,6 +27,19 @@ constexpr int kSmallR = 64;
 inline bool is_small(const Symbolic& S, int64_t s) {
     return S.width(s) <= kSmallW && S.nbelow(s) <= kSmallR;
 }
+// Per-supernode region of the factor's side array (dinv), for w columns:
+//   the inverses of the kPanel-column diagonal blocks, compact: every full
+//   panel as kPanel x kPanel, the last partial one (jb < kPanel columns) as
+//   jb x jb, each row major;
+//   then a packed copy of L11 (lower triangle, column major: entry (i, j) at
+//   j (2w - j - 1) / 2 + i), which the solves load in one contiguous sweep.
+__host__ __device__ inline int64_t inverse_elems(int32_t w) {
+    const int64_t full = w / kPanel, rem = w % kPanel;
+    return full * kPanel * kPanel + rem * rem;
+}
+__host__ __device__ inline int64_t diag_region_elems(int32_t w) {
+    return inverse_elems(w) + (int64_t)w * (w + 1) / 2;
+}
 
 // Device task-queue schedule: task kinds and the task record.
 enum : int32_t { kTaskF = 0, kTaskT = 1, kTaskU = 2 };
@@ -47,7 +60,7 @@ struct DevicePlan {
     int32_t* sn_w = nullptr;
     int32_t* sn_ld = nullptr;
     int64_t* sn_off = nullptr;
-    int64_t* inv_off = nullptr;  // offset of the supernode's diagonal-block inverses
+    int64_t* inv_off = nullptr;  // offset of the supernode's region of dinv (inverses, packed L11)
     int64_t inv_elems = 0;
     int64_t* rowptr = nullptr;
     int32_t* rows = nullptr;

@@ -61,131 +61,147 @@ __global__ void k_zero(R* __restrict__ p, int64_t n) {
         p[i] = R(0);
 }
 
-// Stages the packed lower triangle of the w x w diagonal block (entry (i, j)
-// at cst(j) + i) and the supernode's 16 x 16 inverse blocks into LDS, eight
-// independent global loads per thread in flight.
+// Threads of the diagonal-block solve kernels: eight waves, each solving its
+// own right-hand sides after the workgroup has staged the block.
+constexpr int kDiagThreads = 512;
+constexpr int kDiagRegionMax = (kMaxWidth / kPanel) * kPanel * kPanel +
+                               (kMaxWidth % kPanel) * (kMaxWidth % kPanel) +
+                               kMaxWidth * (kMaxWidth + 1) / 2;
+
+// Stages the supernode's region of dinv (compact diagonal-block inverses,
+// then the packed L11) into LDS in one sweep with every load in flight: T gets
+// the packed lower triangle (entry (i, j) at cst(j) + i), I every panel's
+// inverse as a zero-padded 16 x 16 row-major block.
 template <class R>
 __device__ __forceinline__ void stage_block(R* __restrict__ T, R* __restrict__ I,
-                                            const R* __restrict__ L, const R* __restrict__ inv,
-                                            int w, int ld, int npanel, int tid) {
-    const int ww = w * w;
-    for (int e0 = tid; e0 < ww; e0 += 24 * 256) {
-        R v[24];
+                                            const R* __restrict__ region, int w, int tid) {
+    constexpr int kPer = (kDiagRegionMax + kDiagThreads - 1) / kDiagThreads;
+    const int ninv = (int)inverse_elems(w);
+    const int total = ninv + w * (w + 1) / 2;
+    const int plast = w / kPanel, jbl = w % kPanel;  // trailing partial panel, if any
+    R v[kPer];
 #pragma unroll
-        for (int u = 0; u < 24; ++u) {
-            const int e = e0 + u * 256, i = e % w, j = e / w;
-            const bool ok = e < ww && i >= j;
-            v[u] = L[ok ? i + (int64_t)j * ld : 0];
-        }
+    for (int u = 0; u < kPer; ++u) {
+        const int e = tid + u * kDiagThreads;
+        v[u] = e < total ? region[e] : R(0);
+    }
 #pragma unroll
-        for (int u = 0; u < 24; ++u) {
-            const int e = e0 + u * 256, i = e % w, j = e / w;
-            if (e < ww && i >= j) T[((j * (2 * w - j - 1)) >> 1) + i] = v[u];
+    for (int u = 0; u < kPer; ++u) {
+        const int e = tid + u * kDiagThreads;
+        if (e >= total) continue;
+        if (e >= ninv) {
+            T[e - ninv] = v[u];
+        } else {
+            const int p = e >> 8, q = e & 255;
+            const int jbp = p < plast ? kPanel : jbl;
+            I[p * kPanel * kPanel + (q / jbp) * kPanel + q % jbp] = v[u];
         }
     }
-    // the inverses are stored compactly (the last panel as jb x jb); LDS
-    // holds every panel as a zero-padded 16 x 16 block
-    const int ni = npanel * kPanel * kPanel;
-    for (int e0 = tid; e0 < ni; e0 += 8 * 256) {
-        R v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int e = e0 + u * 256, p = e >> 8, r = (e >> 4) & 15, c = e & 15;
-            const int jbp = min(kPanel, w - kPanel * p);
-            const bool in = e < ni && r < jbp && c < jbp;
-            const R t = inv[in ? p * kPanel * kPanel + r * jbp + c : 0];
-            v[u] = in ? t : R(0);
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (e0 + u * 256 < ni) I[e0 + u * 256] = v[u];
+    if (jbl) {  // zero padding of the partial panel
+        for (int e = tid; e < kPanel * kPanel; e += kDiagThreads)
+            if ((e >> 4) >= jbl || (e & 15) >= jbl) I[plast * kPanel * kPanel + e] = R(0);
     }
 }
 
-// Right-hand sides are processed NR at a time (NR = 1, or kRhs for several):
-// every kernel reads its part of L once per group of NR columns and keeps NR
-// partial sums per thread.
+// Right-hand sides go through the row-block kernels NR at a time (NR = 1,
+// or kRhs for several): the block of L21 is read once per group and every
+// thread keeps NR partial sums.
 constexpr int kRhs = 8;
+constexpr int kPs = kTile + 1;  // padded LDS column stride of a staged 64-row block of L21
 
-// Forward, diagonal block: the block L11 (packed lower triangle) and its
-// 16 x 16 diagonal-block inverses are staged in LDS by the workgroup; then for
-// each 16-column panel p and each of the NR right-hand sides
-//   t = y_p - L[p, <p] y_{<p}   (thread (j, part) sums every 16th column k,
-//                                the 16 parts meet in LDS),
-//   y_p = inv(D_p) t            (16 threads per right-hand side).
-template <class R, int NR>
-__global__ __launch_bounds__(256) void k_fwd_diag(const int32_t* __restrict__ level_sn, KArgs a,
+// Stages rows [i0, i0 + 64) of the w columns of a panel block into LDS,
+// column by column (Pl[k * kPs + i]), zero past the m valid rows; sixteen
+// independent loads per thread in flight.
+template <class R>
+__device__ __forceinline__ void stage_rows(R* __restrict__ Pl, const R* __restrict__ P, int ld,
+                                           int i0, int m, int w, int tid) {
+    constexpr int kPer = (kTile * kMaxWidth + 255) / 256;
+    const int total = kTile * w;
+    R v[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int e = tid + u * 256, k = e >> 6, i = e & 63;
+        v[u] = (e < total && i < m) ? P[i0 + i + (int64_t)k * ld] : R(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int e = tid + u * 256;
+        if (e < total) Pl[(e >> 6) * kPs + (e & 63)] = v[u];
+    }
+}
+
+// Diagonal block, forward: y_s = L11^{-1} y_s.  The workgroup stages L11
+// (packed lower triangle) and the 16 x 16 diagonal-block inverses in LDS;
+// then each wave solves its own right-hand sides with no workgroup barrier,
+// panel by panel:
+//   t = y_p - L[p, <p] y_{<p}   (lane (j, part) sums every 4th column, the
+//                                four parts meet by cross-lane adds),
+//   y_p = inv(D_p) t            (cross-lane broadcasts of t).
+template <class R>
+__global__ __launch_bounds__(kDiagThreads) void k_fwd_diag(const int32_t* __restrict__ level_sn,
+                                                           KArgs a,
                                                   const R* __restrict__ arena,
                                                   const R* __restrict__ dinv, R* __restrict__ y,
                                                   int64_t n, int nrhs) {
     extern __shared__ double sm_raw[];
     R* sm = (R*)sm_raw;
-    __shared__ R ys[NR][kMaxWidth + kPanel];
-    __shared__ R red[NR][16][17];
-    __shared__ R tt[NR][16];
+    __shared__ R ys[kDiagThreads / 64][kMaxWidth + kPanel];
     const int s = level_sn[blockIdx.x];
-    const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
-    const R* __restrict__ L = arena + a.sn_off[s];
-    const R* __restrict__ inv = dinv + a.inv_off[s];
-    const int tid = threadIdx.x, j = tid & 15, part = tid >> 4;
-    const int jj = tid & 15, cc = tid >> 4;  // reduction stage: column cc, entry jj
+    const int w = a.sn_w[s], first = a.sn_first[s];
+    const R* __restrict__ inv = dinv + a.inv_off[s];  // inverses, then packed L11
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int j = lane & 15, part = lane >> 4;
     const int npanel = (w + kPanel - 1) / kPanel;
     auto cst = [w](int q) { return (q * (2 * w - q - 1)) >> 1; };
     R* T = sm;
     R* I = sm + w * (w + 1) / 2;
-    stage_block<R>(T, I, L, inv, w, ld, npanel, tid);
-    for (int c0 = 0; c0 < nrhs; c0 += NR) {
-        const int nc = min(NR, nrhs - c0);
-        for (int e = tid; e < NR * w; e += 256) {
-            const int c = e / w, k = e - c * w;
-            ys[c][k] = c < nc ? y[(int64_t)(c0 + c) * n + first + k] : R(0);
-        }
-        __syncthreads();
+    stage_block<R>(T, I, inv, w, tid);
+    __syncthreads();
+    R* yw = ys[wave];
+    for (int c = wave; c < nrhs; c += kDiagThreads / 64) {
+        R* __restrict__ yc = y + (int64_t)c * n;
+        for (int k = lane; k < w; k += 64) yw[k] = yc[first + k];
+        __builtin_amdgcn_wave_barrier();
         for (int p = 0; p < npanel; ++p) {
             const int j0 = p * kPanel, jb = min(kPanel, w - j0);
-            R acc[NR];
-#pragma unroll
-            for (int c = 0; c < NR; ++c) acc[c] = R(0);
-            if (j < jb)
-                for (int k = part; k < j0; k += 16) {
-                    const R l = T[cst(k) + j0 + j];
-#pragma unroll
-                    for (int c = 0; c < NR; ++c) acc[c] += l * ys[c][k];
+            R acc0 = R(0), acc1 = R(0);
+            if (j < jb) {
+                int k = part;
+                for (; k + 4 < j0; k += 8) {
+                    acc0 += T[cst(k) + j0 + j] * yw[k];
+                    acc1 += T[cst(k + 4) + j0 + j] * yw[k + 4];
                 }
-#pragma unroll
-            for (int c = 0; c < NR; ++c) red[c][part][j] = acc[c];
-            __syncthreads();
-            if (cc < NR) {
-                R tot = R(0);
-#pragma unroll
-                for (int q = 0; q < 16; ++q) tot += red[cc][q][jj];
-                tt[cc][jj] = (jj < jb) ? ys[cc][j0 + jj] - tot : R(0);
+                if (k < j0) acc0 += T[cst(k) + j0 + j] * yw[k];
             }
-            __syncthreads();
-            if (cc < NR) {
-                R out = R(0);
+            R acc = acc0 + acc1;
+            acc += __shfl_xor(acc, 16, 64);
+            acc += __shfl_xor(acc, 32, 64);
+            const R t = (j < jb) ? yw[j0 + j] - acc : R(0);
+            R o = R(0);
 #pragma unroll
-                for (int k = 0; k < kPanel; ++k)
-                    out += I[p * kPanel * kPanel + jj * kPanel + k] * tt[cc][k];
-                if (jj < jb) ys[cc][j0 + jj] = out;
+            for (int q = 0; q < 4; ++q) {
+                const int k = 4 * part + q;
+                o += I[p * kPanel * kPanel + j * kPanel + k] * __shfl(t, k, 64);
             }
-            __syncthreads();
+            o += __shfl_xor(o, 16, 64);
+            o += __shfl_xor(o, 32, 64);
+            if (part == 0 && j < jb) yw[j0 + j] = o;
+            __builtin_amdgcn_wave_barrier();
         }
-        for (int e = tid; e < nc * w; e += 256) {
-            const int c = e / w, k = e - c * w;
-            y[(int64_t)(c0 + c) * n + first + k] = ys[c][k];
-        }
-        __syncthreads();
+        for (int k = lane; k < w; k += 64) yc[first + k] = yw[k];
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
-// Forward, below the diagonal block: y[rows(i)] -= sum_k L21[i][k] y_s[k];
-// thread (row, wave) walks every 4th column; the four waves combine through
-// LDS.  The block of L21 is read once per NR right-hand sides.
+// Below the diagonal block, forward: y[rows(i)] -= sum_k L21[i][k] y_s[k] for
+// one 64-row block: the block is staged in LDS, thread (row, wave) sums every
+// 4th column, the four waves meet in LDS, one atomic per row and column.
 template <class R, int NR>
 __global__ __launch_bounds__(256) void k_fwd_gemv(const RowBlock* __restrict__ work, KArgs a,
                                                   const R* __restrict__ arena, R* __restrict__ y,
                                                   int64_t n, int nrhs) {
+    extern __shared__ double sm_raw[];
+    R* Pl = (R*)sm_raw;
     __shared__ R ys[kMaxWidth][NR];
     __shared__ R red[4][NR][64];
     const RowBlock wb = work[blockIdx.x];
@@ -196,7 +212,8 @@ __global__ __launch_bounds__(256) void k_fwd_gemv(const RowBlock* __restrict__ w
     const R* __restrict__ P = arena + a.sn_off[s] + w;
     const int32_t* __restrict__ below = a.rows + rp + w;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int i = wb.rb * kTile + lane;
+    const int i0 = wb.rb * kTile, m = min(kTile, r - i0);
+    stage_rows<R>(Pl, P, ld, i0, m, w, tid);
     for (int c0 = 0; c0 < nrhs; c0 += NR) {
         const int nc = min(NR, nrhs - c0);
         for (int e = tid; e < NR * w; e += 256) {
@@ -207,37 +224,37 @@ __global__ __launch_bounds__(256) void k_fwd_gemv(const RowBlock* __restrict__ w
         R acc[NR];
 #pragma unroll
         for (int c = 0; c < NR; ++c) acc[c] = R(0);
-        if (i < r) {
 #pragma unroll 4
-            for (int k = wave; k < w; k += 4) {
-                const R pv = P[i + (int64_t)k * ld];
+        for (int k = wave; k < w; k += 4) {
+            const R pv = Pl[k * kPs + lane];
 #pragma unroll
-                for (int c = 0; c < NR; ++c) acc[c] += pv * ys[k][c];
-            }
+            for (int c = 0; c < NR; ++c) acc[c] += pv * ys[k][c];
         }
 #pragma unroll
         for (int c = 0; c < NR; ++c) red[wave][c][lane] = acc[c];
         __syncthreads();
-        if (tid < 64 && i < r) {
-            const int32_t row = below[i];
+        if (tid < m) {
+            const int32_t row = below[i0 + tid];
             for (int c = 0; c < nc; ++c)
                 unsafeAtomicAdd(y + (int64_t)(c0 + c) * n + row,
-                                -((red[0][c][lane] + red[1][c][lane]) +
-                                  (red[2][c][lane] + red[3][c][lane])));
+                                -((red[0][c][tid] + red[1][c][tid]) +
+                                  (red[2][c][tid] + red[3][c][tid])));
         }
         __syncthreads();
     }
 }
 
-// Backward, below the diagonal block: t_s[k] += sum_i L21[i][k] y[rows(i)]
-// over one 64-row block: the gathered entries go to LDS, then thread k walks
-// column k of the block (its own contiguous 64 entries) once per NR
-// right-hand sides and adds one partial sum per column and right-hand side.
+// Below the diagonal block, backward: t_s[k] += sum_i L21[i][k] y[rows(i)]
+// over one 64-row block staged in LDS: thread k walks column k (its own
+// padded LDS column) for NR right-hand sides at a time and adds one partial
+// sum per column and right-hand side.
 template <class R, int NR>
 __global__ __launch_bounds__(256) void k_bwd_gemv(const RowBlock* __restrict__ work, KArgs a,
                                                   const R* __restrict__ arena,
                                                   const R* __restrict__ y, R* __restrict__ tacc,
                                                   int64_t n, int nrhs) {
+    extern __shared__ double sm_raw[];
+    R* Pl = (R*)sm_raw;
     __shared__ R xr[kTile][NR];
     const RowBlock wb = work[blockIdx.x];
     const int s = wb.s;
@@ -248,6 +265,7 @@ __global__ __launch_bounds__(256) void k_bwd_gemv(const RowBlock* __restrict__ w
     const int32_t* __restrict__ below = a.rows + rp + w;
     const int tid = threadIdx.x;
     const int i0 = wb.rb * kTile, m = min(kTile, r - i0);
+    stage_rows<R>(Pl, P, ld, i0, m, w, tid);
     for (int c0 = 0; c0 < nrhs; c0 += NR) {
         const int nc = min(NR, nrhs - c0);
         for (int e = tid; e < NR * kTile; e += 256) {
@@ -256,104 +274,84 @@ __global__ __launch_bounds__(256) void k_bwd_gemv(const RowBlock* __restrict__ w
         }
         __syncthreads();
         for (int k = tid; k < w; k += 256) {
-            const R* __restrict__ col = P + i0 + (int64_t)k * ld;
-            if (NR == 1) {
-                R acc0 = R(0), acc1 = R(0), acc2 = R(0), acc3 = R(0);
-                int i = 0;
-                for (; i + 4 <= m; i += 4) {
-                    acc0 += col[i] * xr[i][0];
-                    acc1 += col[i + 1] * xr[i + 1][0];
-                    acc2 += col[i + 2] * xr[i + 2][0];
-                    acc3 += col[i + 3] * xr[i + 3][0];
-                }
-                for (; i < m; ++i) acc0 += col[i] * xr[i][0];
-                unsafeAtomicAdd(tacc + (int64_t)c0 * n + first + k, (acc0 + acc1) + (acc2 + acc3));
-            } else {
-                R acc[NR];
+            const R* __restrict__ col = Pl + k * kPs;
+            R acc[NR][2];
 #pragma unroll
-                for (int c = 0; c < NR; ++c) acc[c] = R(0);
-                for (int i = 0; i < m; ++i) {
-                    const R pv = col[i];
+            for (int c = 0; c < NR; ++c) acc[c][0] = acc[c][1] = R(0);
+            for (int i = 0; i < m; i += 2) {  // rows past m are zero in LDS
+                const R p0 = col[i], p1 = col[i + 1];
 #pragma unroll
-                    for (int c = 0; c < NR; ++c) acc[c] += pv * xr[i][c];
+                for (int c = 0; c < NR; ++c) {
+                    acc[c][0] += p0 * xr[i][c];
+                    acc[c][1] += p1 * xr[i + 1][c];
                 }
-                for (int c = 0; c < nc; ++c)
-                    unsafeAtomicAdd(tacc + (int64_t)(c0 + c) * n + first + k, acc[c]);
             }
+            for (int c = 0; c < nc; ++c)
+                unsafeAtomicAdd(tacc + (int64_t)(c0 + c) * n + first + k, acc[c][0] + acc[c][1]);
         }
         __syncthreads();
     }
 }
 
-// Backward, diagonal block: y_s = L11^{-T} (y_s - t_s), panels from the last:
+// Diagonal block, backward: y_s = L11^{-T} (y_s - t_s), panels from the last:
 //   u = v_p - L[>p, p]^T y_{>p},   y_p = inv(D_p)^T u,
-// with L11 and the inverses staged in LDS and the dot products split over
-// the workgroup as in k_fwd_diag, NR right-hand sides at a time.
-template <class R, int NR>
-__global__ __launch_bounds__(256) void k_bwd_diag(const int32_t* __restrict__ level_sn, KArgs a,
+// one wave per right-hand side as in k_fwd_diag.
+template <class R>
+__global__ __launch_bounds__(kDiagThreads) void k_bwd_diag(const int32_t* __restrict__ level_sn,
+                                                           KArgs a,
                                                   const R* __restrict__ arena,
                                                   const R* __restrict__ dinv, R* __restrict__ y,
                                                   const R* __restrict__ tacc, int64_t n,
                                                   int nrhs) {
     extern __shared__ double sm_raw[];
     R* sm = (R*)sm_raw;
-    __shared__ R ys[NR][kMaxWidth + kPanel];
-    __shared__ R red[NR][16][17];
-    __shared__ R tt[NR][16];
+    __shared__ R ys[kDiagThreads / 64][kMaxWidth + kPanel];
     const int s = level_sn[blockIdx.x];
-    const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
-    const R* __restrict__ L = arena + a.sn_off[s];
-    const R* __restrict__ inv = dinv + a.inv_off[s];
-    const int tid = threadIdx.x, j = tid & 15, part = tid >> 4;
-    const int jj = tid & 15, cc = tid >> 4;
+    const int w = a.sn_w[s], first = a.sn_first[s];
+    const R* __restrict__ inv = dinv + a.inv_off[s];  // inverses, then packed L11
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int j = lane & 15, part = lane >> 4;
     const int npanel = (w + kPanel - 1) / kPanel;
     auto cst = [w](int q) { return (q * (2 * w - q - 1)) >> 1; };
     R* T = sm;
     R* I = sm + w * (w + 1) / 2;
-    stage_block<R>(T, I, L, inv, w, ld, npanel, tid);
-    for (int c0 = 0; c0 < nrhs; c0 += NR) {
-        const int nc = min(NR, nrhs - c0);
-        for (int e = tid; e < NR * w; e += 256) {
-            const int c = e / w, k = e - c * w;
-            const int64_t at = (int64_t)(c0 + c) * n + first + k;
-            ys[c][k] = c < nc ? y[at] - tacc[at] : R(0);
-        }
-        __syncthreads();
+    stage_block<R>(T, I, inv, w, tid);
+    __syncthreads();
+    R* yw = ys[wave];
+    for (int c = wave; c < nrhs; c += kDiagThreads / 64) {
+        R* __restrict__ yc = y + (int64_t)c * n;
+        const R* __restrict__ tc = tacc + (int64_t)c * n;
+        for (int k = lane; k < w; k += 64) yw[k] = yc[first + k] - tc[first + k];
+        __builtin_amdgcn_wave_barrier();
         for (int p = npanel - 1; p >= 0; --p) {
             const int j0 = p * kPanel, jb = min(kPanel, w - j0);
-            R acc[NR];
-#pragma unroll
-            for (int c = 0; c < NR; ++c) acc[c] = R(0);
-            if (j < jb)
-                for (int k = j0 + kPanel + part; k < w; k += 16) {
-                    const R l = T[cst(j0 + j) + k];
-#pragma unroll
-                    for (int c = 0; c < NR; ++c) acc[c] += l * ys[c][k];
+            R acc0 = R(0), acc1 = R(0);
+            if (j < jb) {
+                const int cj = cst(j0 + j);
+                int k = j0 + kPanel + part;
+                for (; k + 4 < w; k += 8) {
+                    acc0 += T[cj + k] * yw[k];
+                    acc1 += T[cj + k + 4] * yw[k + 4];
                 }
-#pragma unroll
-            for (int c = 0; c < NR; ++c) red[c][part][j] = acc[c];
-            __syncthreads();
-            if (cc < NR) {
-                R tot = R(0);
-#pragma unroll
-                for (int q = 0; q < 16; ++q) tot += red[cc][q][jj];
-                tt[cc][jj] = (jj < jb) ? ys[cc][j0 + jj] - tot : R(0);
+                if (k < w) acc0 += T[cj + k] * yw[k];
             }
-            __syncthreads();
-            if (cc < NR) {
-                R out = R(0);
+            R acc = acc0 + acc1;
+            acc += __shfl_xor(acc, 16, 64);
+            acc += __shfl_xor(acc, 32, 64);
+            const R u = (j < jb) ? yw[j0 + j] - acc : R(0);
+            R o = R(0);
 #pragma unroll
-                for (int k = 0; k < kPanel; ++k)
-                    out += I[p * kPanel * kPanel + k * kPanel + jj] * tt[cc][k];
-                if (jj < jb) ys[cc][j0 + jj] = out;
+            for (int q = 0; q < 4; ++q) {
+                const int k = 4 * part + q;
+                o += I[p * kPanel * kPanel + k * kPanel + j] * __shfl(u, k, 64);
             }
-            __syncthreads();
+            o += __shfl_xor(o, 16, 64);
+            o += __shfl_xor(o, 32, 64);
+            if (part == 0 && j < jb) yw[j0 + j] = o;
+            __builtin_amdgcn_wave_barrier();
         }
-        for (int e = tid; e < nc * w; e += 256) {
-            const int c = e / w, k = e - c * w;
-            y[(int64_t)(c0 + c) * n + first + k] = ys[c][k];
-        }
-        __syncthreads();
+        for (int k = lane; k < w; k += 64) yc[first + k] = yw[k];
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -365,14 +363,20 @@ static size_t diag_lds(int wmax, size_t elem) {
 
 int32_t configure_solve_kernels() {
     const int mx = (int)diag_lds(kMaxWidth, sizeof(double));
-    const void* fns[] = {(const void*)k_fwd_diag<double, 1>, (const void*)k_bwd_diag<double, 1>,
-                         (const void*)k_fwd_diag<float, 1>, (const void*)k_bwd_diag<float, 1>,
-                         (const void*)k_fwd_diag<double, kRhs>,
-                         (const void*)k_bwd_diag<double, kRhs>,
-                         (const void*)k_fwd_diag<float, kRhs>,
-                         (const void*)k_bwd_diag<float, kRhs>};
-    for (const void* f : fns)
+    const void* diag[] = {(const void*)k_fwd_diag<double>, (const void*)k_bwd_diag<double>,
+                          (const void*)k_fwd_diag<float>, (const void*)k_bwd_diag<float>};
+    for (const void* f : diag)
         if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, mx) != hipSuccess)
+            return ERR_HIP;
+    const int mg = (int)(kMaxWidth * kPs * sizeof(double));
+    const void* gemv[] = {(const void*)k_fwd_gemv<double, 1>, (const void*)k_bwd_gemv<double, 1>,
+                          (const void*)k_fwd_gemv<float, 1>, (const void*)k_bwd_gemv<float, 1>,
+                          (const void*)k_fwd_gemv<double, kRhs>,
+                          (const void*)k_bwd_gemv<double, kRhs>,
+                          (const void*)k_fwd_gemv<float, kRhs>,
+                          (const void*)k_bwd_gemv<float, kRhs>};
+    for (const void* f : gemv)
+        if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, mg) != hipSuccess)
             return ERR_HIP;
     return OK;
 }
@@ -397,23 +401,25 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* y, R* tacc, hipStream_t s
     for (int32_t l = 0; l < nl; ++l) {
         const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1], nbig = P->level_nbig[l];
         const size_t lds = diag_lds(P->level_maxw[l], sizeof(R));
+        const size_t lds_rows = (size_t)P->level_maxw[l] * kPs * sizeof(R);
         if (nbig > 0)
-            hipLaunchKernelGGL((k_fwd_diag<R, NR>), dim3(nbig), dim3(256), lds, st,
+            hipLaunchKernelGGL(k_fwd_diag<R>, dim3(nbig), dim3(kDiagThreads), lds, st,
                                P->level_sn + n0, a, arena, dinv, y, n, nrhs);
         launch_small_solve(num, a, P->level_sn + n0 + nbig, n1 - n0 - nbig, y, n, nrhs, true, st);
         const int64_t rb0 = P->rowblk_ptr[l], rb1 = P->rowblk_ptr[l + 1];
         if (rb1 > rb0)
-            hipLaunchKernelGGL((k_fwd_gemv<R, NR>), dim3((unsigned)(rb1 - rb0)), dim3(256), 0, st,
-                               P->rowblk + rb0, a, arena, y, n, nrhs);
+            hipLaunchKernelGGL((k_fwd_gemv<R, NR>), dim3((unsigned)(rb1 - rb0)), dim3(256),
+                               lds_rows, st, P->rowblk + rb0, a, arena, y, n, nrhs);
     }
     for (int32_t l = nl - 1; l >= 0; --l) {
         const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1], nbig = P->level_nbig[l];
         const int64_t rb0 = P->rowblk_ptr[l], rb1 = P->rowblk_ptr[l + 1];
         if (rb1 > rb0)
-            hipLaunchKernelGGL((k_bwd_gemv<R, NR>), dim3((unsigned)(rb1 - rb0)), dim3(256), 0, st,
-                               P->rowblk + rb0, a, arena, (const R*)y, tacc, n, nrhs);
+            hipLaunchKernelGGL((k_bwd_gemv<R, NR>), dim3((unsigned)(rb1 - rb0)), dim3(256),
+                               (size_t)P->level_maxw[l] * kPs * sizeof(R), st, P->rowblk + rb0, a,
+                               arena, (const R*)y, tacc, n, nrhs);
         if (nbig > 0)
-            hipLaunchKernelGGL((k_bwd_diag<R, NR>), dim3(nbig), dim3(256),
+            hipLaunchKernelGGL(k_bwd_diag<R>, dim3(nbig), dim3(kDiagThreads),
                                diag_lds(P->level_maxw[l], sizeof(R)), st, P->level_sn + n0, a,
                                arena, dinv, y, (const R*)tacc, n, nrhs);
         launch_small_solve(num, a, P->level_sn + n0 + nbig, n1 - n0 - nbig, y, n, nrhs, false,
