@@ -61,6 +61,17 @@ __global__ void k_zero(R* __restrict__ p, int64_t n) {
         p[i] = R(0);
 }
 
+// Value held by lane `lane` (wave-uniform) of the wave, as v_readlane.
+__device__ __forceinline__ double lane_bcast(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float lane_bcast(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
 // Threads of the diagonal-block solve kernels: eight waves, each solving its
 // own right-hand sides after the workgroup has staged the block.
 constexpr int kDiagThreads = 512;
@@ -93,8 +104,8 @@ __device__ __forceinline__ void stage_block(R* __restrict__ T, R* __restrict__ I
             T[e - ninv] = v[u];
         } else {
             const int p = e >> 8, q = e & 255;
-            const int jbp = p < plast ? kPanel : jbl;
-            I[p * kPanel * kPanel + (q / jbp) * kPanel + q % jbp] = v[u];
+            if (p < plast) I[e] = v[u];  // full panel: already 16 x 16
+            else I[p * kPanel * kPanel + (q / jbl) * kPanel + q % jbl] = v[u];
         }
     }
     if (jbl) {  // zero padding of the partial panel
@@ -133,10 +144,11 @@ __device__ __forceinline__ void stage_rows(R* __restrict__ Pl, const R* __restri
 // Diagonal block, forward: y_s = L11^{-1} y_s.  The workgroup stages L11
 // (packed lower triangle) and the 16 x 16 diagonal-block inverses in LDS;
 // then each wave solves its own right-hand sides with no workgroup barrier,
-// panel by panel:
-//   t = y_p - L[p, <p] y_{<p}   (lane (j, part) sums every 4th column, the
-//                                four parts meet by cross-lane adds),
-//   y_p = inv(D_p) t            (cross-lane broadcasts of t).
+// right-looking by panels:
+//   y_p = inv(D_p) y_p                      (lane (j, part): four products,
+//                                             the parts meet by cross-lane adds)
+//   y[k] -= L[k, p] y_p for every k below   (one row per lane, the sixteen
+//                                             y_p values broadcast in registers)
 template <class R>
 __global__ __launch_bounds__(kDiagThreads) void k_fwd_diag(const int32_t* __restrict__ level_sn,
                                                            KArgs a,
@@ -164,28 +176,32 @@ __global__ __launch_bounds__(kDiagThreads) void k_fwd_diag(const int32_t* __rest
         __builtin_amdgcn_wave_barrier();
         for (int p = 0; p < npanel; ++p) {
             const int j0 = p * kPanel, jb = min(kPanel, w - j0);
-            R acc0 = R(0), acc1 = R(0);
-            if (j < jb) {
-                int k = part;
-                for (; k + 4 < j0; k += 8) {
-                    acc0 += T[cst(k) + j0 + j] * yw[k];
-                    acc1 += T[cst(k + 4) + j0 + j] * yw[k + 4];
-                }
-                if (k < j0) acc0 += T[cst(k) + j0 + j] * yw[k];
-            }
-            R acc = acc0 + acc1;
-            acc += __shfl_xor(acc, 16, 64);
-            acc += __shfl_xor(acc, 32, 64);
-            const R t = (j < jb) ? yw[j0 + j] - acc : R(0);
             R o = R(0);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int k = 4 * part + q;
-                o += I[p * kPanel * kPanel + j * kPanel + k] * __shfl(t, k, 64);
+                o += I[p * kPanel * kPanel + j * kPanel + k] * (k < jb ? yw[j0 + k] : R(0));
             }
             o += __shfl_xor(o, 16, 64);
             o += __shfl_xor(o, 32, 64);
+            R yp[kPanel];
+#pragma unroll
+            for (int q = 0; q < kPanel; ++q) yp[q] = lane_bcast(o, q);
+            __builtin_amdgcn_wave_barrier();
             if (part == 0 && j < jb) yw[j0 + j] = o;
+            for (int k = j0 + kPanel + lane; k < w; k += 64) {
+                // every load of the row first, then two accumulation chains
+                R tv[kPanel];
+#pragma unroll
+                for (int q = 0; q < kPanel; ++q) tv[q] = T[cst(j0 + q) + k];
+                R acc0 = R(0), acc1 = R(0);
+#pragma unroll
+                for (int q = 0; q < kPanel; q += 2) {
+                    acc0 += tv[q] * yp[q];
+                    acc1 += tv[q + 1] * yp[q + 1];
+                }
+                yw[k] -= acc0 + acc1;
+            }
             __builtin_amdgcn_wave_barrier();
         }
         for (int k = lane; k < w; k += 64) yc[first + k] = yw[k];
@@ -293,8 +309,9 @@ __global__ __launch_bounds__(256) void k_bwd_gemv(const RowBlock* __restrict__ w
     }
 }
 
-// Diagonal block, backward: y_s = L11^{-T} (y_s - t_s), panels from the last:
-//   u = v_p - L[>p, p]^T y_{>p},   y_p = inv(D_p)^T u,
+// Diagonal block, backward: y_s = L11^{-T} (y_s - t_s), right-looking from
+// the last panel:
+//   y_p = inv(D_p)^T y_p;   y[k] -= L[p, k]^T y_p for every k left of the panel,
 // one wave per right-hand side as in k_fwd_diag.
 template <class R>
 __global__ __launch_bounds__(kDiagThreads) void k_bwd_diag(const int32_t* __restrict__ level_sn,
@@ -325,29 +342,34 @@ __global__ __launch_bounds__(kDiagThreads) void k_bwd_diag(const int32_t* __rest
         __builtin_amdgcn_wave_barrier();
         for (int p = npanel - 1; p >= 0; --p) {
             const int j0 = p * kPanel, jb = min(kPanel, w - j0);
-            R acc0 = R(0), acc1 = R(0);
-            if (j < jb) {
-                const int cj = cst(j0 + j);
-                int k = j0 + kPanel + part;
-                for (; k + 4 < w; k += 8) {
-                    acc0 += T[cj + k] * yw[k];
-                    acc1 += T[cj + k + 4] * yw[k + 4];
-                }
-                if (k < w) acc0 += T[cj + k] * yw[k];
-            }
-            R acc = acc0 + acc1;
-            acc += __shfl_xor(acc, 16, 64);
-            acc += __shfl_xor(acc, 32, 64);
-            const R u = (j < jb) ? yw[j0 + j] - acc : R(0);
             R o = R(0);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int k = 4 * part + q;
-                o += I[p * kPanel * kPanel + k * kPanel + j] * __shfl(u, k, 64);
+                o += I[p * kPanel * kPanel + k * kPanel + j] * (k < jb ? yw[j0 + k] : R(0));
             }
             o += __shfl_xor(o, 16, 64);
             o += __shfl_xor(o, 32, 64);
+            R yp[kPanel];
+#pragma unroll
+            for (int q = 0; q < kPanel; ++q) yp[q] = lane_bcast(o, q);  // zero past jb
+            __builtin_amdgcn_wave_barrier();
             if (part == 0 && j < jb) yw[j0 + j] = o;
+            for (int k = lane; k < j0; k += 64) {
+                // row j0 + q of column k (past the last row, any entry of the
+                // column: it meets yp[q] = 0)
+                const int ck = cst(k) + j0;
+                R tv[kPanel];
+#pragma unroll
+                for (int q = 0; q < kPanel; ++q) tv[q] = T[q < jb ? ck + q : ck];
+                R acc0 = R(0), acc1 = R(0);
+#pragma unroll
+                for (int q = 0; q < kPanel; q += 2) {
+                    acc0 += tv[q] * yp[q];
+                    acc1 += tv[q + 1] * yp[q + 1];
+                }
+                yw[k] -= acc0 + acc1;
+            }
             __builtin_amdgcn_wave_barrier();
         }
         for (int k = lane; k < w; k += 64) yc[first + k] = yw[k];
