@@ -172,7 +172,17 @@ __global__ __launch_bounds__(kDiagThreads) void k_fwd_diag(const int32_t* __rest
     R* yw = ys[wave];
     for (int c = wave; c < nrhs; c += kDiagThreads / 64) {
         R* __restrict__ yc = y + (int64_t)c * n;
-        for (int k = lane; k < w; k += 64) yw[k] = yc[first + k];
+        {
+            R v[(kMaxWidth + 63) / 64];  // all of the wave's loads in flight at once
+#pragma unroll
+            for (int u = 0; u < (kMaxWidth + 63) / 64; ++u) {
+                const int k = lane + 64 * u;
+                v[u] = k < w ? yc[first + k] : R(0);
+            }
+#pragma unroll
+            for (int u = 0; u < (kMaxWidth + 63) / 64; ++u)
+                if (lane + 64 * u < w) yw[lane + 64 * u] = v[u];
+        }
         __builtin_amdgcn_wave_barrier();
         for (int p = 0; p < npanel; ++p) {
             const int j0 = p * kPanel, jb = min(kPanel, w - j0);
@@ -232,19 +242,38 @@ __global__ __launch_bounds__(256) void k_fwd_gemv(const RowBlock* __restrict__ w
     stage_rows<R>(Pl, P, ld, i0, m, w, tid);
     for (int c0 = 0; c0 < nrhs; c0 += NR) {
         const int nc = min(NR, nrhs - c0);
-        for (int e = tid; e < NR * w; e += 256) {
-            const int c = e / w, k = e - c * w;
-            ys[k][c] = c < nc ? y[(int64_t)(c0 + c) * n + first + k] : R(0);
+        {
+            constexpr int kPer = (NR * kMaxWidth + 255) / 256;
+            R v[kPer];
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                const int e = tid + 256 * u, c = e / w, k = e - c * w;
+                v[u] = (e < NR * w && c < nc) ? y[(int64_t)(c0 + c) * n + first + k] : R(0);
+            }
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                const int e = tid + 256 * u, c = e / w, k = e - c * w;
+                if (e < NR * w) ys[k][c] = v[u];
+            }
         }
         __syncthreads();
         R acc[NR];
 #pragma unroll
         for (int c = 0; c < NR; ++c) acc[c] = R(0);
-#pragma unroll 4
-        for (int k = wave; k < w; k += 4) {
-            const R pv = Pl[k * kPs + lane];
+        for (int k0 = wave; k0 < w; k0 += 32) {  // eight columns per step, loads first
+            R pv[8], yv[8][NR];
 #pragma unroll
-            for (int c = 0; c < NR; ++c) acc[c] += pv * ys[k][c];
+            for (int u = 0; u < 8; ++u) {
+                const int k = min(k0 + 4 * u, w - 1);
+                const bool in = k0 + 4 * u < w;
+                pv[u] = in ? Pl[k * kPs + lane] : R(0);
+#pragma unroll
+                for (int c = 0; c < NR; ++c) yv[u][c] = ys[k][c];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int c = 0; c < NR; ++c) acc[c] += pv[u] * yv[u][c];
         }
 #pragma unroll
         for (int c = 0; c < NR; ++c) red[wave][c][lane] = acc[c];
@@ -294,13 +323,22 @@ __global__ __launch_bounds__(256) void k_bwd_gemv(const RowBlock* __restrict__ w
             R acc[NR][2];
 #pragma unroll
             for (int c = 0; c < NR; ++c) acc[c][0] = acc[c][1] = R(0);
-            for (int i = 0; i < m; i += 2) {  // rows past m are zero in LDS
-                const R p0 = col[i], p1 = col[i + 1];
+            // eight rows per step, every load first (rows past m are zero in LDS)
+            for (int ib = 0; ib < m; ib += 8) {
+                R pv[8], xv[8][NR];
 #pragma unroll
-                for (int c = 0; c < NR; ++c) {
-                    acc[c][0] += p0 * xr[i][c];
-                    acc[c][1] += p1 * xr[i + 1][c];
+                for (int u = 0; u < 8; ++u) {
+                    pv[u] = col[ib + u];
+#pragma unroll
+                    for (int c = 0; c < NR; ++c) xv[u][c] = xr[ib + u][c];
                 }
+#pragma unroll
+                for (int u = 0; u < 8; u += 2)
+#pragma unroll
+                    for (int c = 0; c < NR; ++c) {
+                        acc[c][0] += pv[u] * xv[u][c];
+                        acc[c][1] += pv[u + 1] * xv[u + 1][c];
+                    }
             }
             for (int c = 0; c < nc; ++c)
                 unsafeAtomicAdd(tacc + (int64_t)(c0 + c) * n + first + k, acc[c][0] + acc[c][1]);
@@ -338,7 +376,18 @@ __global__ __launch_bounds__(kDiagThreads) void k_bwd_diag(const int32_t* __rest
     for (int c = wave; c < nrhs; c += kDiagThreads / 64) {
         R* __restrict__ yc = y + (int64_t)c * n;
         const R* __restrict__ tc = tacc + (int64_t)c * n;
-        for (int k = lane; k < w; k += 64) yw[k] = yc[first + k] - tc[first + k];
+        {
+            R v[(kMaxWidth + 63) / 64], t[(kMaxWidth + 63) / 64];
+#pragma unroll
+            for (int u = 0; u < (kMaxWidth + 63) / 64; ++u) {
+                const int k = lane + 64 * u;
+                v[u] = k < w ? yc[first + k] : R(0);
+                t[u] = k < w ? tc[first + k] : R(0);
+            }
+#pragma unroll
+            for (int u = 0; u < (kMaxWidth + 63) / 64; ++u)
+                if (lane + 64 * u < w) yw[lane + 64 * u] = v[u] - t[u];
+        }
         __builtin_amdgcn_wave_barrier();
         for (int p = npanel - 1; p >= 0; --p) {
             const int j0 = p * kPanel, jb = min(kPanel, w - j0);
