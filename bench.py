@@ -92,6 +92,28 @@ def cpu_baseline(name, sample_dims, repeat=0):
                       "%.1f s" % ("x".join(map(str, sample_dims)), p.n, sym.flops, dt)}
 
 
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/), or None when there is none for this workload or the kernel's
+    source has changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "%s_traffic_%s.txt" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(" "):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    src = os.path.join(ROOT, kv.get("source", ""))
+    if "traffic_bytes_per_launch" not in kv or not os.path.isfile(src):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != kv.get("source_sha256"):
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def mixed_precision(name, steps, warmup, tol=1e-10):
     """FP64 factor + solve against FP32 factor + FP64 refinement to a normwise
     backward error <= tol, on the same resident workload and right-hand sides."""
@@ -318,6 +340,9 @@ def main():
                     help="matrices of the batched workload (0 to skip)")
     ap.add_argument("--serve-requests", type=int, default=1000,
                     help="requests of the serving stream (0 to skip)")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first copy a buffer of this many MiB (a dispatch of known traffic "
+                         "for scaling hardware byte counters)")
     ap.add_argument("--cpu-sample", default=None,
                     help="grid of the bounded oracle sample (default: 40^3 for 3D workloads, "
                          "the full grid for 2D ones)")
@@ -334,6 +359,14 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibrate_copy_mib:
+        src = torch.ones(args.calibrate_copy_mib << 17, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d MiB read, %d MiB written" % (args.calibrate_copy_mib,
+                                                                  args.calibrate_copy_mib))
+        del src, dst
     name = args.workload
     p = inputs.make_workload(name)
     amalg = p.meta["amalg"]
@@ -422,9 +455,12 @@ def main():
     k_ms = kern[kcls] / args.steps
     k_launch = launches[kcls] / args.steps
     achieved = kflops / (k_ms * 1e-3) / 1e12 if k_ms > 0 else 0.0
+    traffic = measured_traffic("k_update", name) if kcls == "update" else None
     roofline = {"kernel": kname,
                 "bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": traffic,
+                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                "scaled by a copy kernel; profiles/)",
                 "algorithmic_flops_per_launch": kflops / max(k_launch, 1),
                 "avg_launch_ms": k_ms / max(k_launch, 1), "launches_per_factor": k_launch}
 

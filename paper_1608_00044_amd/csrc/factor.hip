@@ -270,21 +270,24 @@ __device__ __forceinline__ bool potrf_task(int s, const KArgs& a, S* __restrict_
     auto cst = [w](int j) { return (j * (2 * w - j - 1)) >> 1; };
     const int dummy = w * (w + 1) / 2;  // masked accesses land here
     const int ww = w * w;
+    const float invw = 1.0f / (float)w;
     if (kCheck && tid == 0) unstable = 0;
     for (int e0 = tid; e0 < ww; e0 += 16 * kPotrfThreads) {
         C v[16];
+        int at[16], dg[16];
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
-            const int e = e0 + u * kPotrfThreads, i = e % w, j = e / w;
-            const bool ok = e < ww && i >= j;
-            v[u] = (C)base[ok ? i + (int64_t)j * ld : 0];
+            int i, j;
+            divmod_small(e0 + u * kPotrfThreads, w, invw, j, i);
+            const bool ok = e0 + u * kPotrfThreads < ww && i >= j;
+            v[u] = ok ? (C)base[i + (int64_t)j * ld] : C(0);
+            at[u] = ok ? cst(j) + i : dummy;
+            dg[u] = (ok && i == j) ? i : -1;
         }
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
-            const int e = e0 + u * kPotrfThreads, i = e % w, j = e / w;
-            const bool ok = e < ww && i >= j;
-            T[ok ? cst(j) + i : dummy] = v[u];
-            if (kCheck && ok && i == j) d0[i] = v[u];
+            T[at[u]] = v[u];
+            if (kCheck && dg[u] >= 0) d0[dg[u]] = v[u];
         }
     }
     __syncthreads();
@@ -339,8 +342,9 @@ __device__ __forceinline__ bool potrf_task(int s, const KArgs& a, S* __restrict_
     for (int e0 = tid; e0 < ww; e0 += 8 * kPotrfThreads) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int e = e0 + u * kPotrfThreads, i = e % w, j = e / w;
-            if (e < ww && i >= j) base[i + (int64_t)j * ld] = (S)T[cst(j) + i];
+            int i, j;
+            divmod_small(e0 + u * kPotrfThreads, w, invw, j, i);
+            if (e0 + u * kPotrfThreads < ww && i >= j) base[i + (int64_t)j * ld] = (S)T[cst(j) + i];
         }
     }
     // packed copy of L11 for the solves, after the inverses

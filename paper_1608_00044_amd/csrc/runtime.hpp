@@ -40,6 +40,20 @@ __host__ __device__ inline int64_t inverse_elems(int32_t w) {
 __host__ __device__ inline int64_t diag_region_elems(int32_t w) {
     return inverse_elems(w) + (int64_t)w * (w + 1) / 2;
 }
+// q = e / w, r = e % w for 0 <= e < 2^24 and 0 < w, by a float reciprocal
+// (invw = 1.0f / w) and one correction step; integer division by a runtime
+// value costs tens of instructions on the GPU.
+__host__ __device__ inline void divmod_small(int e, int w, float invw, int& q, int& r) {
+    q = (int)((float)e * invw);
+    r = e - q * w;
+    if (r < 0) {
+        --q;
+        r += w;
+    } else if (r >= w) {
+        ++q;
+        r -= w;
+    }
+}
 
 // Device task-queue schedule: task kinds and the task record.
 enum : int32_t { kTaskF = 0, kTaskT = 1, kTaskU = 2 };

@@ -244,17 +244,20 @@ __global__ __launch_bounds__(256) void k_fwd_gemv(const RowBlock* __restrict__ w
         const int nc = min(NR, nrhs - c0);
         {
             constexpr int kPer = (NR * kMaxWidth + 255) / 256;
+            const float invw = 1.0f / (float)w;
             R v[kPer];
+            int kk[kPer];
 #pragma unroll
             for (int u = 0; u < kPer; ++u) {
-                const int e = tid + 256 * u, c = e / w, k = e - c * w;
+                const int e = tid + 256 * u;
+                int c, k;
+                divmod_small(e, w, invw, c, k);
+                kk[u] = (e < NR * w) ? k * NR + c : -1;
                 v[u] = (e < NR * w && c < nc) ? y[(int64_t)(c0 + c) * n + first + k] : R(0);
             }
 #pragma unroll
-            for (int u = 0; u < kPer; ++u) {
-                const int e = tid + 256 * u, c = e / w, k = e - c * w;
-                if (e < NR * w) ys[k][c] = v[u];
-            }
+            for (int u = 0; u < kPer; ++u)
+                if (kk[u] >= 0) (&ys[0][0])[kk[u]] = v[u];
         }
         __syncthreads();
         R acc[NR];
