@@ -39,6 +39,8 @@ void release_numeric(spc_numeric* num) {
     (void)hipFree(num->dinv);
     (void)hipFree(num->sched_state);
     drop_solve_graphs(num);
+    if (num->factor_exec) (void)hipGraphExecDestroy(num->factor_exec);
+    if (num->factor_graph) (void)hipGraphDestroy(num->factor_graph);
     if (num->capture) (void)hipStreamDestroy(num->capture);
     (void)hipFree(num->work);
     free_refine(num);

@@ -934,9 +934,33 @@ int32_t run_factor_t(spc_numeric* num, const double* values, hipStream_t st) {
             mark_end(num, st, 4, ev);
         }
     } else if (num->sched == 0 || nl < 2) {
-        for (int32_t l = 0; l < nl; ++l) {
-            launch_ft<R>(num, P, S, a, l, st);
-            launch_update<R>(num, P, a, P->tile_ptr[l], P->tile_ptr[l + 1], true, st);
+        if (num->timing) {  // per-launch events: launch directly
+            for (int32_t l = 0; l < nl; ++l) {
+                launch_ft<R>(num, P, S, a, l, st);
+                launch_update<R>(num, P, a, P->tile_ptr[l], P->tile_ptr[l + 1], true, st);
+            }
+        } else {
+            // the level launches depend only on the plan and this factor's
+            // buffers: capture them once, replay them on every factorization
+            if (!num->factor_exec) {
+                if (!num->capture)
+                    HIP_TRY(hipStreamCreateWithFlags(&num->capture, hipStreamNonBlocking));
+                HIP_TRY(hipStreamBeginCapture(num->capture, hipStreamCaptureModeThreadLocal));
+                for (int32_t l = 0; l < nl; ++l) {
+                    launch_ft<R>(num, P, S, a, l, num->capture);
+                    launch_update<R>(num, P, a, P->tile_ptr[l], P->tile_ptr[l + 1], true,
+                                     num->capture);
+                }
+                const hipError_t ce = hipStreamEndCapture(num->capture, &num->factor_graph);
+                if (ce != hipSuccess || !num->factor_graph) return ERR_HIP;
+                if (hipGraphInstantiate(&num->factor_exec, num->factor_graph, nullptr, nullptr,
+                                        0) != hipSuccess) {
+                    (void)hipGraphDestroy(num->factor_graph);
+                    num->factor_graph = nullptr;
+                    return ERR_HIP;
+                }
+            }
+            HIP_TRY(hipGraphLaunch(num->factor_exec, st));
         }
     } else {
         hipStream_t sb = num->bulk;

@@ -148,6 +148,9 @@ struct spc_numeric {
     int64_t spin_limit = 0;
     struct SolveGraph { int32_t nrhs; hipGraph_t graph; hipGraphExec_t exec; };
     std::vector<SolveGraph> solve_graphs;
+    // level-set factorization launches (after the value load), captured once
+    hipGraph_t factor_graph = nullptr;
+    hipGraphExec_t factor_exec = nullptr;
     int64_t work_cols = 0;
     hipStream_t stream = nullptr;
     int32_t host_status = 0;

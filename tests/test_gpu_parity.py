@@ -309,3 +309,27 @@ def test_solve_right_hand_side_groups(k):
     for c in (0, k - 1):
         xc = num.solve(torch.from_numpy(np.ascontiguousarray(B[:, c])).to("cuda:0")).cpu().numpy()
         np.testing.assert_allclose(x[:, c], xc, rtol=0, atol=1e-12 * np.abs(xc).max())
+
+
+def test_factor_graph_replays_match_direct_launches():
+    """The level-set factorization is captured into a graph on the first
+    factorization and replayed after; every replay (with eager work between)
+    and a directly launched factorization (per-launch timing on) agree to
+    rounding, and the last replay meets the parity bars."""
+    torch = torch_dev()
+    p = inputs.make_grid_problem("lap", (16, 16, 16), 71, sigma=1.0, shift=1e-3, nrhs=0)
+    sym, num, vals = gpu_factor(p, 150, 0.1)
+    L1 = num.export()[2]
+    scale = np.abs(L1).max()
+    for _ in range(3):
+        torch.ones(1000, device="cuda:0").sum().item()  # eager work between replays
+        num.refactor(vals)
+        np.testing.assert_allclose(num.export()[2], L1, rtol=0, atol=1e-13 * scale)
+    num.set_timing(True)
+    num.refactor(vals)
+    np.testing.assert_allclose(num.export()[2], L1, rtol=0, atol=1e-13 * scale)
+    assert num.timing()["update"]["launches"] > 0
+    num.set_timing(False)
+    num.refactor(vals)
+    worst, rho, _ = compare_factor(p, num, 150, 0.1, "graph replay")
+    assert worst <= 1.0 and rho <= 1e-12
