@@ -122,89 +122,146 @@ __device__ __forceinline__ void rsqrt_sqrt(float d, float& rs, float& sq) {
     sq = d * y;
 }
 
-// Wave-level factorization of the 16 x 16 diagonal block of panel q (columns
-// j0 .. j0 + jb - 1): copy it from the packed triangle T into the dense tile
-// Dt (identity past its edge), factor it in registers (lane i holds row i;
-// the pivot comes by v_readlane, each finished column goes back to the tile
-// and is read by every lane), form inv(D) by forward substitution (one column
-// per lane), and write L back to T and inv(D) to Dinv and dinv.
-// kCheck (the FP32 pass): instead of recording failed pivots in *status, flag
-// the block as unstable when a pivot is not above tau times the diagonal
-// entry it started from (d0, the block's diagonal before the factorization).
-template <class C, class S, bool kCheck, class Cst>
-__device__ __forceinline__ void panel_factor(C* __restrict__ T, C* __restrict__ Dt,
-                                             C* __restrict__ Dinv, S* __restrict__ inv_g,
-                                             Cst cst, int dummy, int j0, int jb, int q, int lane,
-                                             int first, int32_t* __restrict__ status,
-                                             const C* __restrict__ d0, int* unstable) {
+// Column factorization of one panel by one wave, in registers: the jb
+// columns j0 .. j0 + jb - 1 over every row from j0 to w - 1 of the packed
+// lower triangle T (entry (i, j) at cst(j) + i).  Lane l holds rows
+// j0 + l + 64 q (q < NQ, with NQ chunks covering the w - j0 rows).  For each
+// column c the pivot comes from the lane that holds row c (v_readlane), the
+// column is scaled by 1/sqrt(pivot), lanes 0-15 put its diagonal-block part
+// L(j0 .. j0 + 15, c) in the LDS array colbuf, and every lane reads those
+// values back (same address, one broadcast read per pair) to update the
+// panel's later columns.  Entries above the diagonal hold garbage in
+// registers and are never stored or broadcast.  1/L(c, c) goes to rdiag[c].
+// Without kCheck the smallest column with a pivot that is not positive is
+// recorded (global column + 1) with atomicMin on *status; with kCheck (FP32
+// pass) a pivot at most kPivotTau times its starting diagonal entry d0[c]
+// sets *unstable.  kFull: jb == kPanel (every panel but the last).
+template <int NQ, bool kFull, class C, bool kCheck, class Cst>
+__device__ __forceinline__ void panel_columns_q(C* __restrict__ T, C* __restrict__ rdiag,
+                                                C* __restrict__ colbuf, Cst cst, int w, int j0,
+                                                int jb, int lane, int first,
+                                                int32_t* __restrict__ status,
+                                                const C* __restrict__ d0, int* unstable) {
+    C x[NQ][kPanel];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        const int idx = lane + 64 * m, i = idx >> 4, j = idx & 15;
-        const bool in = i < jb && j <= i;
-        const C v = T[in ? cst(j0 + j) + j0 + i : dummy];
-        Dt[i * kDs + j] = in ? v : (i == j ? C(1) : C(0));
-    }
-    __builtin_amdgcn_wave_barrier();
-    const int i = lane & 15;  // lanes 16..63 mirror lanes 0..15
-    C d[kPanel], rd[kPanel];
+    for (int q = 0; q < NQ; ++q)
 #pragma unroll
-    for (int j = 0; j < kPanel; ++j) d[j] = Dt[i * kDs + j];
+        for (int k = 0; k < kPanel; ++k) {
+            const int i = j0 + lane + 64 * q;
+            const bool in = (kFull || k < jb) && i < w && i >= j0 + k;
+            x[q][k] = T[in ? cst(j0 + k) + i : 0];
+            if (!in) x[q][k] = C(0);
+        }
+    const C piv0 = kCheck ? kPivotTau * d0[lane < jb ? j0 + lane : 0] : C(0);
+    C rsv = C(0);   // lane k keeps 1/L(j0 + k, j0 + k)
+    int bad = kPanel;  // first failing column of the panel
 #pragma unroll
     for (int k = 0; k < kPanel; ++k) {
-        const C dkk = lane_value(d[k], k);
-        if (kCheck) {
-            if (k < jb && !(dkk > kPivotTau * d0[j0 + k]) && lane == 0) *unstable = 1;
-        } else {
-            if (k < jb && !(dkk > C(0)) && lane == 0) atomicMin(status, first + j0 + k + 1);
-        }
-        C rinv, lkk;
-        rsqrt_sqrt(dkk, rinv, lkk);
-        rd[k] = rinv;
-        d[k] = (i == k) ? lkk : d[k] * rinv;
-        Dt[i * kDs + k] = d[k];  // column k of L, read back by every lane
-        __builtin_amdgcn_wave_barrier();
+        if (kFull || k < jb) {
+            const C d = lane_value(x[0][k], k);
+            const bool fail = kCheck ? !(d > lane_value(piv0, k)) : !(d > C(0));
+            bad = (fail && bad == kPanel) ? k : bad;
+            C rs, l;
+            rsqrt_sqrt(d, rs, l);
+            rsv = lane == k ? rs : rsv;
+            x[0][k] = lane == k ? l : x[0][k] * rs;
 #pragma unroll
-        for (int j = k + 1; j < kPanel; ++j) {
-            const C ljk = Dt[j * kDs + k];
-            d[j] -= ((i >= j) ? d[k] : C(0)) * ljk;
+            for (int q = 1; q < NQ; ++q) x[q][k] *= rs;
+            if (k + 1 < kPanel && (kFull || k + 1 < jb)) {
+                if (lane < kPanel) colbuf[k * kPanel + lane] = x[0][k];
+                __builtin_amdgcn_wave_barrier();
+                C ljc[kPanel];
+#pragma unroll
+                for (int j = k + 1; j < kPanel; ++j) ljc[j] = colbuf[k * kPanel + j];
+#pragma unroll
+                for (int j = k + 1; j < kPanel; ++j) {
+                    if (kFull || j < jb) {
+#pragma unroll
+                        for (int q = 0; q < NQ; ++q) x[q][j] -= x[q][k] * ljc[j];
+                    }
+                }
+            }
         }
     }
-    C x[kPanel];
-#pragma unroll
-    for (int rr = 0; rr < kPanel; ++rr) {
-        C acc = (rr == i) ? C(1) : C(0);
-#pragma unroll
-        for (int k = 0; k < rr; ++k) acc -= Dt[rr * kDs + k] * x[k];
-        x[rr] = acc * rd[rr];
+    if (lane < jb) rdiag[j0 + lane] = rsv;
+    if (bad < kPanel && lane == 0) {
+        if (kCheck) *unstable = 1;
+        else atomicMin(status, first + j0 + bad + 1);
     }
-    if (lane < kPanel) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int k = 0; k < kPanel; ++k) {
+            const int i = j0 + lane + 64 * q;
+            if ((kFull || k < jb) && i < w && i >= j0 + k) T[cst(j0 + k) + i] = x[q][k];
+        }
+}
+
+// Panel j0 of width jb: the register factorization sized to its rows.
+template <class C, bool kCheck, class Cst>
+__device__ __forceinline__ void panel_columns(C* __restrict__ T, C* __restrict__ rdiag,
+                                              C* __restrict__ colbuf, Cst cst, int w, int j0,
+                                              int jb, int lane, int first,
+                                              int32_t* __restrict__ status,
+                                              const C* __restrict__ d0, int* unstable) {
+    static_assert(kMaxWidth <= 192, "three 64-row chunks per lane");
+    const int rows = w - j0;
+#define SPC_PANEL(NQ, FULL)                                                                   \
+    panel_columns_q<NQ, FULL, C, kCheck>(T, rdiag, colbuf, cst, w, j0, jb, lane, first, status, \
+                                         d0, unstable)
+    if (jb < kPanel)  // the last panel: fewer than 16 rows
+        SPC_PANEL(1, false);
+    else if (rows <= 64)
+        SPC_PANEL(1, true);
+    else if (rows <= 128)
+        SPC_PANEL(2, true);
+    else
+        SPC_PANEL(3, true);
+#undef SPC_PANEL
+}
+
+// Inverses of the diagonal blocks of every panel (lower triangular, jb x jb),
+// all at once: lane 16 g + c of wave v takes column c of panel 4 v + g (and
+// panel 4 v + g + 16 k beyond that) and forms it by forward substitution,
+// row by row, with the row's entries loaded before its products.  Written
+// compactly (row major, stride jb) to inv_g at p * 256.
+template <class C, class S, class Cst>
+__device__ __forceinline__ void panel_inverses(const C* __restrict__ T,
+                                               const C* __restrict__ rdiag, S* __restrict__ inv_g,
+                                               Cst cst, int w, int npanel, int wave, int lane) {
+    const int c = lane & 15;
+    for (int p = 4 * wave + (lane >> 4); p < npanel; p += 16) {
+        const int j0 = p * kPanel, jb = min(kPanel, w - j0);
+        C x[kPanel];
 #pragma unroll
         for (int rr = 0; rr < kPanel; ++rr) {
-            const C v = (i < jb && rr < jb) ? x[rr] : C(0);
-            Dinv[rr * kPanel + i] = v;
-            // compact global copy: the panel's jb x jb inverse, row major
-            if (i < jb && rr < jb) inv_g[q * kPanel * kPanel + rr * jb + i] = (S)v;
-        }
-    }
-    __builtin_amdgcn_wave_barrier();
+            C lrow[kPanel];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        const int idx = lane + 64 * m, ii = idx >> 4, j = idx & 15;
-        const bool in = ii < jb && j <= ii;
-        T[in ? cst(j0 + j) + j0 + ii : dummy] = Dt[ii * kDs + j];
+            for (int k = 0; k < kPanel; ++k) {
+                const bool in = k < rr && rr < jb;
+                lrow[k] = T[in ? cst(j0 + k) + j0 + rr : 0];
+                if (!in) lrow[k] = C(0);
+            }
+            C acc = (rr == c) ? C(1) : C(0);
+#pragma unroll
+            for (int k = 0; k < kPanel; ++k)
+                if (k < rr) acc -= lrow[k] * x[k];
+            x[rr] = rr < jb ? acc * rdiag[rr < jb ? j0 + rr : 0] : C(0);
+        }
+        if (c < jb) {
+#pragma unroll
+            for (int rr = 0; rr < kPanel; ++rr)
+                if (rr < jb) inv_g[p * kPanel * kPanel + rr * jb + c] = (S)x[rr];
+        }
     }
 }
 
-// Trailing-update block b of panel p (blocks numbered row by row over the
-// lower triangle of the trailing part, 16 x 16 each, K = 16 on the matrix
+// Trailing-update block (bi, bj) of panel j0 (16 x 16 blocks of the
+// trailing lower triangle starting at row and column t0; K = 16 on the matrix
 // cores), in place in the packed triangle.
 template <class C, class Cst>
 __device__ __forceinline__ void trailing_block(C* __restrict__ T, Cst cst, int dummy, int w,
-                                               int j0, int t0, int b, int lr, int lk) {
-    int bi = (int)((sqrtf(8.0f * b + 1.0f) - 1.0f) * 0.5f);
-    bi -= (bi * (bi + 1) / 2 > b);
-    bi += ((bi + 1) * (bi + 2) / 2 <= b);
-    const int bj = b - bi * (bi + 1) / 2;
+                                               int j0, int t0, int bi, int bj, int lr, int lk) {
     const int row0 = t0 + bi * kPanel, col0 = t0 + bj * kPanel;
     const int ra = row0 + lr, rb = col0 + lr;
     const bool oka = ra < w, okb = rb < w;
@@ -232,32 +289,32 @@ __device__ __forceinline__ void trailing_block(C* __restrict__ T, Cst cst, int d
     for (int q = 0; q < 4; ++q) T[ci[q]] = acc[q];
 }
 
-// Diagonal factorization of supernode s by one workgroup of 4 waves.  The
-// w x w diagonal block lives in LDS (T) as a packed lower triangle, column major: entry (i, j)
-// at cst(j) + i, plus one dummy slot that absorbs masked accesses so the
-// inner loops stay branch free.  Right-looking by 16-column panels with a
-// one-panel lookahead:
-//   1. wave 0 factors the panel's 16 x 16 diagonal block and inverts it
-//      (panel_factor); the inverse also goes to dinv for the panel and
-//      triangular solves;
-//   2. the rows below the panel inside the diagonal block are multiplied by
-//      inv(D)^T on the matrix cores, one 16-row block per wave;
-//   3. the trailing lower triangle is updated in 16 x 16 blocks; wave 0
-//      updates the next panel's diagonal block first and factors it while
-//      waves 1-3 update the rest.
-// Global loads and stores of the block are issued many per thread at a time.
-// Storage type S (the arena), compute type C (LDS and registers).  Without
-// kCheck a pivot that is not positive records its global column with
-// atomicMin on *status (the smallest failing column wins).  With kCheck (FP32
-// pass) nothing is recorded: if any pivot is not above kPivotTau times its
-// starting diagonal entry the block is left unwritten in global memory and
-// the function returns true, so that the caller can factor it again in FP64.
+// Diagonal factorization of supernode s by one workgroup of 4 waves, on the
+// w x w block held in LDS (T) as a packed lower triangle, column major: entry
+// (i, j) at cst(j) + i, plus one dummy slot that absorbs masked accesses.
+// Right-looking by 16-column panels:
+//   1. the four waves update the next panel's columns with the current
+//      panel (16 x 16 blocks, K = 16 on the matrix cores);
+//   2. wave 0 factors the next panel column by column in registers
+//      (panel_columns: its diagonal block and every row below it at once),
+//      while waves 1-3 update the rest of the trailing triangle;
+// so the chain from panel to panel is one block update and one register
+// column factorization.  The inverses of the 16 x 16 diagonal blocks (for the
+// panel and triangular solves) are formed at the end by all four waves.  The
+// block is loaded and written back by packed index with many accesses per
+// thread in flight; the packed copy goes after the inverses in dinv.
+// Storage type S, compute type C.  Without kCheck a pivot that is not
+// positive records its global column with atomicMin on *status (the smallest
+// failing column wins).  With kCheck (FP32 pass) nothing is recorded: if any
+// pivot is not above kPivotTau times its starting diagonal entry the block is
+// left unwritten in global memory and the function returns true, so that the
+// caller can factor it again in FP64.
 template <class S, class C, bool kCheck>
 __device__ __forceinline__ bool potrf_task(int s, const KArgs& a, S* __restrict__ arena,
                                            S* __restrict__ dinv, int32_t* __restrict__ status,
                                            C* __restrict__ T) {
-    __shared__ C Dinv[kPanel * kPanel];  // row major: Dinv[r * 16 + c] = inv(D)[r][c]
-    __shared__ C Dt[kPanel * kDs];       // dense panel block, row major
+    __shared__ C rdiag[kMaxWidth];
+    __shared__ C colbuf[kPanel * kPanel];  // one column of the panel's diagonal block
     __shared__ C d0[kCheck ? kMaxWidth : 1];
     __shared__ int unstable;
     const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
@@ -266,90 +323,85 @@ __device__ __forceinline__ bool potrf_task(int s, const KArgs& a, S* __restrict_
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lk = lane >> 4;
     constexpr int nwave = kPotrfThreads / 64;
-    // packed column start: entry (i, j) of the lower triangle sits at cst(j) + i
     auto cst = [w](int j) { return (j * (2 * w - j - 1)) >> 1; };
     const int dummy = w * (w + 1) / 2;  // masked accesses land here
-    const int ww = w * w;
-    const float invw = 1.0f / (float)w;
     if (kCheck && tid == 0) unstable = 0;
-    for (int e0 = tid; e0 < ww; e0 += 16 * kPotrfThreads) {
-        C v[16];
-        int at[16], dg[16];
+    // the lower triangle, packed index e straight to T[e], in two rounds of
+    // loads all in flight (w <= kMaxWidth)
+    constexpr int kPerT =
+        (kMaxWidth * (kMaxWidth + 1) / 2 + 2 * kPotrfThreads - 1) / (2 * kPotrfThreads);
+    for (int e0 = tid; e0 < dummy; e0 += kPerT * kPotrfThreads) {
+        C v[kPerT];
+        int dg[kCheck ? kPerT : 1];  // diagonal entries keep their column for d0
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            int i, j;
-            divmod_small(e0 + u * kPotrfThreads, w, invw, j, i);
-            const bool ok = e0 + u * kPotrfThreads < ww && i >= j;
-            v[u] = ok ? (C)base[i + (int64_t)j * ld] : C(0);
-            at[u] = ok ? cst(j) + i : dummy;
-            dg[u] = (ok && i == j) ? i : -1;
+        for (int u = 0; u < kPerT; ++u) {
+            const int e = e0 + u * kPotrfThreads;
+            int i = 0, j = 0;
+            if (e < dummy) tri_entry(e, w, i, j);
+            v[u] = e < dummy ? (C)base[i + (int64_t)j * ld] : C(0);
+            if (kCheck) dg[u] = (e < dummy && i == j) ? j : -1;
         }
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            T[at[u]] = v[u];
-            if (kCheck && dg[u] >= 0) d0[dg[u]] = v[u];
+        for (int u = 0; u < kPerT; ++u) {
+            const int e = e0 + u * kPotrfThreads;
+            if (e < dummy) T[e] = v[u];
+            if (kCheck && dg[kCheck ? u : 0] >= 0) d0[dg[kCheck ? u : 0]] = v[u];
         }
     }
     __syncthreads();
     const int npanel = (w + kPanel - 1) / kPanel;
     if (wave == 0)
-        panel_factor<C, S, kCheck>(T, Dt, Dinv, inv_g, cst, dummy, 0, min(kPanel, w), 0, lane,
-                                   first, status, d0, &unstable);
+        panel_columns<C, kCheck>(T, rdiag, colbuf, cst, w, 0, min(kPanel, w), lane, first,
+                                 status, d0, &unstable);
     __syncthreads();
-    for (int p = 0; p < npanel; ++p) {
-        const int j0 = p * kPanel;
-        const int jb = min(kPanel, w - j0);
-        // rows below the panel inside the diagonal block: X = A inv(D)^T
-        const int t0 = j0 + kPanel;
-        const int nrow = w - j0 - jb;  // > 0 only when the panel is full
-        const int nrb = (nrow + kPanel - 1) / kPanel;
-        for (int rb = wave; rb < nrb; rb += nwave) {
-            const int row0 = t0 + rb * kPanel;
-            const bool okr = row0 + lr < w;
-            C av[4], bv[4];
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const C t = T[okr ? cst(j0 + 4 * kk + lk) + row0 + lr : dummy];
-                av[kk] = okr ? t : C(0);
-                bv[kk] = Dinv[lr * kPanel + 4 * kk + lk];
-            }
-            typename Mx<C>::acc out = {C(0), C(0), C(0), C(0)};
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) out = Mx<C>::mfma(av[kk], bv[kk], out);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int rr = row0 + Mx<C>::row(q, lk);
-                T[rr < w ? cst(j0 + lr) + rr : dummy] = out[q];
-            }
-        }
+    for (int p = 0; p + 1 < npanel; ++p) {
+        const int j0 = p * kPanel, t0 = j0 + kPanel;
+        const int nbr = (w - t0 + kPanel - 1) / kPanel;  // trailing block rows
+        // 1. the next panel's column of blocks
+        for (int bi = wave; bi < nbr; bi += nwave)
+            trailing_block<C>(T, cst, dummy, w, j0, t0, bi, 0, lr, lk);
         __syncthreads();
-        if (nrow <= 0) break;
-        // trailing update with lookahead on the next panel's diagonal block
-        const int nbr = (w - t0 + kPanel - 1) / kPanel;
-        const int nblk = nbr * (nbr + 1) / 2;
+        // 2. wave 0 factors the next panel; waves 1-3 update the other columns
         if (wave == 0) {
-            trailing_block<C>(T, cst, dummy, w, j0, t0, 0, lr, lk);
-            __builtin_amdgcn_wave_barrier();
-            panel_factor<C, S, kCheck>(T, Dt, Dinv, inv_g, cst, dummy, t0, min(kPanel, w - t0),
-                                       p + 1, lane, first, status, d0, &unstable);
+            panel_columns<C, kCheck>(T, rdiag, colbuf, cst, w, t0, min(kPanel, w - t0), lane,
+                                     first, status, d0, &unstable);
         } else {
-            for (int b = wave; b < nblk; b += nwave - 1)
-                trailing_block<C>(T, cst, dummy, w, j0, t0, b, lr, lk);
+            const int nblk = nbr * (nbr - 1) / 2;  // blocks (bi, bj), 1 <= bj <= bi
+            for (int b = wave - 1; b < nblk; b += nwave - 1) {
+                int bi = (int)((sqrtf(8.0f * b + 1.0f) + 1.0f) * 0.5f);
+                bi -= (bi * (bi - 1) / 2 > b);
+                bi += ((bi + 1) * bi / 2 <= b);
+                const int bj = b - bi * (bi - 1) / 2 + 1;
+                trailing_block<C>(T, cst, dummy, w, j0, t0, bi, bj, lr, lk);
+            }
         }
         __syncthreads();
     }
     if (kCheck && unstable) return true;  // uniform: read after the last barrier
-    for (int e0 = tid; e0 < ww; e0 += 8 * kPotrfThreads) {
+    panel_inverses<C, S>(T, rdiag, inv_g, cst, w, npanel, wave, lane);
+    // L11 back to the block, and its packed copy for the solves after the
+    // inverses: packed index e, many stores per thread in flight
+    S* __restrict__ pk = inv_g + inverse_elems(w);
+    for (int e0 = tid; e0 < dummy; e0 += kPerT * kPotrfThreads) {
+        C v[kPerT];
+        int at[kPerT];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            int i, j;
-            divmod_small(e0 + u * kPotrfThreads, w, invw, j, i);
-            if (e0 + u * kPotrfThreads < ww && i >= j) base[i + (int64_t)j * ld] = (S)T[cst(j) + i];
+        for (int u = 0; u < kPerT; ++u) {
+            const int e = e0 + u * kPotrfThreads;
+            int i = 0, j = 0;
+            if (e < dummy) tri_entry(e, w, i, j);
+            at[u] = i + j * ld;
+            v[u] = T[e < dummy ? e : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < kPerT; ++u) {
+            const int e = e0 + u * kPotrfThreads;
+            if (e < dummy) {
+                base[at[u]] = (S)v[u];
+                pk[e] = (S)v[u];
+            }
         }
     }
-    // packed copy of L11 for the solves, after the inverses
-    S* __restrict__ pk = inv_g + inverse_elems(w);
-    for (int e = tid; e < dummy; e += kPotrfThreads) pk[e] = (S)T[e];
     return false;
 }
 
@@ -571,17 +623,18 @@ __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
     const int lr = lane & 15, lk = lane >> 4;
     const bool diag = tile.bi == tile.bj;
     const bool skip = diag && wr < wc;  // strictly upper quarter of a diagonal tile
-    // staging: thread -> row (tid & 63), columns kq*4 .. kq*4+3 of the chunk
+    // staging: thread -> row (tid & 63), columns kq * kPerT .. of the chunk
     const int srow = tid & 63, kq = tid >> 6;
     const bool va = i0 + srow < r, vb = c0 + srow < r;
     R* As = lds;                               // [buf][k][row]
     R* Bs = lds + 2 * kChunk * kLdsStride;     // [buf][k][row]
     const int nchunk = (w + kChunk - 1) / kChunk;
-    R ra[4], rb[4];
+    constexpr int kPerT = kChunk / 4;  // chunk columns staged per thread
+    R ra[kPerT], rb[kPerT];
     auto fetch = [&](int chunk) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int k = chunk * kChunk + kq * 4 + u;
+        for (int u = 0; u < kPerT; ++u) {
+            const int k = chunk * kChunk + kq * kPerT + u;
             const bool vk = k < w;
             const R* __restrict__ col = P + (int64_t)k * ld;
             ra[u] = (vk && va) ? col[i0 + srow] : R(0);
@@ -590,9 +643,9 @@ __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
     };
     auto stash = [&](int buf) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            As[(buf * kChunk + kq * 4 + u) * kLdsStride + srow] = ra[u];
-            if (!diag) Bs[(buf * kChunk + kq * 4 + u) * kLdsStride + srow] = rb[u];
+        for (int u = 0; u < kPerT; ++u) {
+            As[(buf * kChunk + kq * kPerT + u) * kLdsStride + srow] = ra[u];
+            if (!diag) Bs[(buf * kChunk + kq * kPerT + u) * kLdsStride + srow] = rb[u];
         }
     };
     // column -> target lookups first, so their latency hides under the K loop

@@ -40,6 +40,19 @@ __host__ __device__ inline int64_t inverse_elems(int32_t w) {
 __host__ __device__ inline int64_t diag_region_elems(int32_t w) {
     return inverse_elems(w) + (int64_t)w * (w + 1) / 2;
 }
+// Row i and column j of entry e of a packed lower triangle of order w stored
+// by columns (column j starts at j (2w - j - 1) / 2 + j): j from the root of
+// j^2 - (2w + 1) j + 2e = 0 in single precision, then one correction step.
+__host__ __device__ inline void tri_entry(int e, int w, int& i, int& j) {
+    const float b = 2.0f * (float)w + 1.0f;
+    j = (int)((b - sqrtf(b * b - 8.0f * (float)e)) * 0.5f);
+    if (j < 0) j = 0;
+    if (j > w - 1) j = w - 1;
+    auto start = [w](int c) { return (c * (2 * w - c + 1)) >> 1; };  // index of (c, c)
+    if (start(j) > e) --j;
+    else if (j + 1 < w && start(j + 1) <= e) ++j;
+    i = e - start(j) + j;
+}
 // q = e / w, r = e % w for 0 <= e < 2^24 and 0 < w, by a float reciprocal
 // (invw = 1.0f / w) and one correction step; integer division by a runtime
 // value costs tens of instructions on the GPU.
