@@ -326,25 +326,38 @@ __device__ __forceinline__ bool potrf_task(int s, const KArgs& a, S* __restrict_
     auto cst = [w](int j) { return (j * (2 * w - j - 1)) >> 1; };
     const int dummy = w * (w + 1) / 2;  // masked accesses land here
     if (kCheck && tid == 0) unstable = 0;
-    // the lower triangle, packed index e straight to T[e], in two rounds of
-    // loads all in flight (w <= kMaxWidth)
-    constexpr int kPerT =
-        (kMaxWidth * (kMaxWidth + 1) / 2 + 2 * kPotrfThreads - 1) / (2 * kPotrfThreads);
-    for (int e0 = tid; e0 < dummy; e0 += kPerT * kPotrfThreads) {
+    // The lower triangle folded into a (w + 1) x ceil(w / 2) rectangle:
+    // rectangle column p holds column p (rows p .. w - 1) followed by column
+    // w - 1 - p (rows w - 1 - p .. w - 1), so a flat index maps to its entry
+    // with one division; for odd w the middle column is taken once.  Loaded in
+    // two rounds with every load of a round in flight.
+    const int hw = (w + 1) >> 1, w1 = w + 1, nrect = w1 * hw;
+    const float inv_w1 = 1.0f / (float)w1;
+    auto fold = [&](int e, int& i, int& j) {  // false past the end or for a duplicate
+        int pcol, q;
+        divmod_small(e, w1, inv_w1, pcol, q);
+        const bool first = q < w - pcol;
+        j = first ? pcol : w - 1 - pcol;
+        i = first ? pcol + q : j + q - (w - pcol);
+        return e < nrect && (first || j != pcol);
+    };
+    constexpr int kPerT = ((kMaxWidth + 1) * ((kMaxWidth + 1) / 2) + 2 * kPotrfThreads - 1) /
+                          (2 * kPotrfThreads);
+    for (int e0 = tid; e0 < nrect; e0 += kPerT * kPotrfThreads) {
         C v[kPerT];
+        int at[kPerT];
         int dg[kCheck ? kPerT : 1];  // diagonal entries keep their column for d0
 #pragma unroll
         for (int u = 0; u < kPerT; ++u) {
-            const int e = e0 + u * kPotrfThreads;
-            int i = 0, j = 0;
-            if (e < dummy) tri_entry(e, w, i, j);
-            v[u] = e < dummy ? (C)base[i + (int64_t)j * ld] : C(0);
-            if (kCheck) dg[u] = (e < dummy && i == j) ? j : -1;
+            int i, j;
+            const bool ok = fold(e0 + u * kPotrfThreads, i, j);
+            v[u] = ok ? (C)base[i + (int64_t)j * ld] : C(0);
+            at[u] = ok ? cst(j) + i : dummy;
+            if (kCheck) dg[kCheck ? u : 0] = (ok && i == j) ? j : -1;
         }
 #pragma unroll
         for (int u = 0; u < kPerT; ++u) {
-            const int e = e0 + u * kPotrfThreads;
-            if (e < dummy) T[e] = v[u];
+            T[at[u]] = v[u];
             if (kCheck && dg[kCheck ? u : 0] >= 0) d0[dg[kCheck ? u : 0]] = v[u];
         }
     }
@@ -380,25 +393,25 @@ __device__ __forceinline__ bool potrf_task(int s, const KArgs& a, S* __restrict_
     if (kCheck && unstable) return true;  // uniform: read after the last barrier
     panel_inverses<C, S>(T, rdiag, inv_g, cst, w, npanel, wave, lane);
     // L11 back to the block, and its packed copy for the solves after the
-    // inverses: packed index e, many stores per thread in flight
+    // inverses, by the same folded index, many stores per thread in flight
     S* __restrict__ pk = inv_g + inverse_elems(w);
-    for (int e0 = tid; e0 < dummy; e0 += kPerT * kPotrfThreads) {
+    for (int e0 = tid; e0 < nrect; e0 += kPerT * kPotrfThreads) {
         C v[kPerT];
-        int at[kPerT];
+        int at[kPerT], gj[kPerT];
+        bool ok[kPerT];
 #pragma unroll
         for (int u = 0; u < kPerT; ++u) {
-            const int e = e0 + u * kPotrfThreads;
-            int i = 0, j = 0;
-            if (e < dummy) tri_entry(e, w, i, j);
-            at[u] = i + j * ld;
-            v[u] = T[e < dummy ? e : 0];
+            int i, j;
+            ok[u] = fold(e0 + u * kPotrfThreads, i, j);
+            at[u] = ok[u] ? cst(j) + i : dummy;
+            gj[u] = i + j * ld;
+            v[u] = T[at[u]];
         }
 #pragma unroll
         for (int u = 0; u < kPerT; ++u) {
-            const int e = e0 + u * kPotrfThreads;
-            if (e < dummy) {
-                base[at[u]] = (S)v[u];
-                pk[e] = (S)v[u];
+            if (ok[u]) {
+                base[gj[u]] = (S)v[u];
+                pk[at[u]] = (S)v[u];
             }
         }
     }
@@ -648,7 +661,9 @@ __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
             if (!diag) Bs[(buf * kChunk + kq * kPerT + u) * kLdsStride + srow] = rb[u];
         }
     };
-    // column -> target lookups first, so their latency hides under the K loop
+    // the first chunk's loads go out before the column -> target lookups,
+    // whose chain of dependent loads then hides under them
+    fetch(0);
     int64_t my_colbase = 0, my_relbase = 0;
     int my_excl = 0;
     if (tid < kTile) {
@@ -667,7 +682,6 @@ __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
     Acc acc[2][2];
     for (int m = 0; m < 2; ++m)
         for (int n = 0; n < 2; ++n) acc[m][n] = Acc{R(0), R(0), R(0), R(0)};
-    fetch(0);
     stash(0);
     __syncthreads();
     const R* Bsrc = diag ? As : Bs;
@@ -688,6 +702,11 @@ __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
                 acc[1][1] = Mx<R>::mfma(a1, b1, acc[1][1]);
             }
         }
+        if (ch == 0 && tid < kTile) {
+            colbase[tid] = my_colbase;
+            relbase[tid] = my_relbase;
+            colexcl[tid] = my_excl;
+        }
         if (ch + 1 < nchunk) stash(buf ^ 1);
         __syncthreads();
     }
@@ -699,14 +718,11 @@ __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
                 const int c = wc * 32 + n * 16 + lr;
                 Ct[c * kCtPad + i] = acc[m][n][q];
             }
-    if (tid < kTile) {
-        colbase[tid] = my_colbase;
-        relbase[tid] = my_relbase;
-        colexcl[tid] = my_excl;
-    }
     __syncthreads();
-    // thread -> row i = tid & 63 of the tile, columns c = tid / 64 + 4u (u < 16);
-    // every relative index is loaded before the first update is issued
+    // thread -> row i = tid & 63 of the tile, columns c = tid / 64 + 4 u
+    // (u < 16); every relative index is loaded before the first update is
+    // issued (loading them earlier costs registers, and occupancy, that the
+    // K loop needs)
     constexpr int kPer = kTile * kTile / 256;
     const int i = tid & (kTile - 1), gi = i0 + i;
     int64_t dst[kPer];
