@@ -957,8 +957,10 @@ void launch_update(spc_numeric* num, const DevicePlan* P, const KArgs& a, int64_
 // next level run on the caller's stream; the other ("bulk") update tiles of
 // level l run on a second stream concurrently with level l + 1, and level l
 // waits only for the bulk tiles of levels <= l - 2.  Concurrent tiles may hit
-// one target, so the lookahead uses atomic adds throughout.  sched 2: one
-// persistent launch of the task queue.
+// one target, so the lookahead uses atomic adds throughout.  Without
+// per-launch timing, sched 0 and 1 are captured into a graph on the first
+// factorization and replayed after.  sched 2: one persistent launch of the
+// task queue.
 template <class R>
 int32_t run_factor_t(spc_numeric* num, const double* values, hipStream_t st) {
     const Symbolic& S = num->sym->S;
@@ -1002,58 +1004,66 @@ int32_t run_factor_t(spc_numeric* num, const double* values, hipStream_t st) {
                                S.nsup, P->nrowblk, ticks);
             mark_end(num, st, 4, ev);
         }
-    } else if (num->sched == 0 || nl < 2) {
-        if (num->timing) {  // per-launch events: launch directly
-            for (int32_t l = 0; l < nl; ++l) {
-                launch_ft<R>(num, P, S, a, l, st);
-                launch_update<R>(num, P, a, P->tile_ptr[l], P->tile_ptr[l + 1], true, st);
-            }
-        } else {
-            // the level launches depend only on the plan and this factor's
-            // buffers: capture them once, replay them on every factorization
-            if (!num->factor_exec) {
-                if (!num->capture)
-                    HIP_TRY(hipStreamCreateWithFlags(&num->capture, hipStreamNonBlocking));
-                HIP_TRY(hipStreamBeginCapture(num->capture, hipStreamCaptureModeThreadLocal));
-                for (int32_t l = 0; l < nl; ++l) {
-                    launch_ft<R>(num, P, S, a, l, num->capture);
-                    launch_update<R>(num, P, a, P->tile_ptr[l], P->tile_ptr[l + 1], true,
-                                     num->capture);
-                }
-                const hipError_t ce = hipStreamEndCapture(num->capture, &num->factor_graph);
-                if (ce != hipSuccess || !num->factor_graph) return ERR_HIP;
-                if (hipGraphInstantiate(&num->factor_exec, num->factor_graph, nullptr, nullptr,
-                                        0) != hipSuccess) {
-                    (void)hipGraphDestroy(num->factor_graph);
-                    num->factor_graph = nullptr;
-                    return ERR_HIP;
-                }
-            }
-            HIP_TRY(hipGraphLaunch(num->factor_exec, st));
-        }
     } else {
-        hipStream_t sb = num->bulk;
-        // events: [0] start, [1 + 2l] panel solves of level l done, [2 + 2l] bulk of level l done
-        if (num->sync_ev.size() < (size_t)(2 * nl + 1)) {
-            const size_t old = num->sync_ev.size();
-            num->sync_ev.resize((size_t)(2 * nl + 1));
-            for (size_t i = old; i < num->sync_ev.size(); ++i)
-                HIP_TRY(hipEventCreateWithFlags(&num->sync_ev[i], hipEventDisableTiming));
+        // sched 0 (or fewer than two levels): one stream m, level by level.
+        // sched 1: the lookahead on m and the bulk stream.
+        auto enqueue = [&](hipStream_t m) -> int32_t {
+            if (num->sched == 0 || nl < 2) {
+                for (int32_t l = 0; l < nl; ++l) {
+                    launch_ft<R>(num, P, S, a, l, m);
+                    launch_update<R>(num, P, a, P->tile_ptr[l], P->tile_ptr[l + 1], true, m);
+                }
+                return OK;
+            }
+            hipStream_t sb = num->bulk;
+            // events: [0] start, [1 + 2l] panel solves of level l done, [2 + 2l]
+            // bulk of level l done
+            if (num->sync_ev.size() < (size_t)(2 * nl + 1)) {
+                const size_t old = num->sync_ev.size();
+                num->sync_ev.resize((size_t)(2 * nl + 1));
+                for (size_t i = old; i < num->sync_ev.size(); ++i)
+                    HIP_TRY(hipEventCreateWithFlags(&num->sync_ev[i], hipEventDisableTiming));
+            }
+            hipEvent_t* E = num->sync_ev.data();
+            HIP_TRY(hipEventRecord(E[0], m));
+            HIP_TRY(hipStreamWaitEvent(sb, E[0], 0));
+            for (int32_t l = 0; l < nl; ++l) {
+                if (l >= 2) HIP_TRY(hipStreamWaitEvent(m, E[2 + 2 * (l - 2)], 0));
+                launch_ft<R>(num, P, S, a, l, m);
+                HIP_TRY(hipEventRecord(E[1 + 2 * l], m));
+                const int64_t u0 = P->tile_ptr[l], uc = u0 + P->tile_crit[l];
+                const int64_t u1 = P->tile_ptr[l + 1];
+                launch_update<R>(num, P, a, u0, uc, false, m);
+                HIP_TRY(hipStreamWaitEvent(sb, E[1 + 2 * l], 0));
+                launch_update<R>(num, P, a, uc, u1, false, sb);
+                HIP_TRY(hipEventRecord(E[2 + 2 * l], sb));
+            }
+            HIP_TRY(hipStreamWaitEvent(m, E[2 + 2 * (nl - 1)], 0));
+            return OK;
+        };
+        if (num->timing) return enqueue(st);  // per-launch events: launch directly
+        // the level launches depend only on the plan and this factor's
+        // buffers: capture them once (the bulk stream joins the capture
+        // through the events), replay them on every factorization
+        if (!num->factor_exec) {
+            if (!num->capture)
+                HIP_TRY(hipStreamCreateWithFlags(&num->capture, hipStreamNonBlocking));
+            HIP_TRY(hipStreamBeginCapture(num->capture, hipStreamCaptureModeThreadLocal));
+            const int32_t e = enqueue(num->capture);
+            hipGraph_t g = nullptr;
+            const hipError_t ce = hipStreamEndCapture(num->capture, &g);
+            if (e != OK || ce != hipSuccess || !g) {
+                if (g) (void)hipGraphDestroy(g);
+                return e != OK ? e : ERR_HIP;
+            }
+            if (hipGraphInstantiate(&num->factor_exec, g, nullptr, nullptr, 0) != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                num->factor_exec = nullptr;
+                return ERR_HIP;
+            }
+            num->factor_graph = g;
         }
-        hipEvent_t* E = num->sync_ev.data();
-        HIP_TRY(hipEventRecord(E[0], st));
-        HIP_TRY(hipStreamWaitEvent(sb, E[0], 0));
-        for (int32_t l = 0; l < nl; ++l) {
-            if (l >= 2) HIP_TRY(hipStreamWaitEvent(st, E[2 + 2 * (l - 2)], 0));
-            launch_ft<R>(num, P, S, a, l, st);
-            HIP_TRY(hipEventRecord(E[1 + 2 * l], st));
-            const int64_t u0 = P->tile_ptr[l], uc = u0 + P->tile_crit[l], u1 = P->tile_ptr[l + 1];
-            launch_update<R>(num, P, a, u0, uc, false, st);
-            HIP_TRY(hipStreamWaitEvent(sb, E[1 + 2 * l], 0));
-            launch_update<R>(num, P, a, uc, u1, false, sb);
-            HIP_TRY(hipEventRecord(E[2 + 2 * l], sb));
-        }
-        HIP_TRY(hipStreamWaitEvent(st, E[2 + 2 * (nl - 1)], 0));
+        HIP_TRY(hipGraphLaunch(num->factor_exec, st));
     }
     return OK;
 }

@@ -311,14 +311,16 @@ def test_solve_right_hand_side_groups(k):
         np.testing.assert_allclose(x[:, c], xc, rtol=0, atol=1e-12 * np.abs(xc).max())
 
 
-def test_factor_graph_replays_match_direct_launches():
-    """The level-set factorization is captured into a graph on the first
+@pytest.mark.parametrize("sched", [0, 1])
+def test_factor_graph_replays_match_direct_launches(sched):
+    """The level-set factorization (sched 1: with the lookahead's second
+    stream joined into the capture) is captured into a graph on the first
     factorization and replayed after; every replay (with eager work between)
     and a directly launched factorization (per-launch timing on) agree to
     rounding, and the last replay meets the parity bars."""
     torch = torch_dev()
     p = inputs.make_grid_problem("lap", (16, 16, 16), 71, sigma=1.0, shift=1e-3, nrhs=0)
-    sym, num, vals = gpu_factor(p, 150, 0.1)
+    sym, num, vals = gpu_factor(p, 150, 0.1, sched)
     L1 = num.export()[2]
     scale = np.abs(L1).max()
     for _ in range(3):
