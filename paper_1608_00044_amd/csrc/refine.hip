@@ -31,6 +31,8 @@ namespace {
 
 // Groups of 64 rows walked by one wave of the row kernels.
 constexpr int kRowsPerWave = 16;
+// Right-hand sides per pass of the residual kernel.
+constexpr int kResidCols = 8;
 
 int grid_of(int64_t n) {
     return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192));
@@ -113,17 +115,40 @@ __global__ void k_gather_vals(const double* __restrict__ values, const int64_t* 
         aval[q] = values[src[q]];
 }
 
+// Sparse row kernels: a group of kLpr consecutive lanes takes one row (lane j
+// of the group reads entries ptr[i] + j, + kLpr, ... so the group's loads of
+// val and col are contiguous), the partial sums meet by shuffles, and each
+// wave walks kRowGroups groups of 64 / kLpr consecutive rows.
+constexpr int kLpr = 8;
+constexpr int kRowGroups = 16;
+unsigned sparse_blocks(int64_t n) {
+    const int64_t per_block = 4 * (64 / kLpr) * (int64_t)kRowGroups;
+    return (unsigned)std::max<int64_t>(1, (n + per_block - 1) / per_block);
+}
+// Row of this lane's group in step u, and the lane's place in the group.
+__device__ __forceinline__ int64_t sparse_row(int u) {
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    return (wave * kRowGroups + u) * (64 / kLpr) + ((threadIdx.x & 63) / kLpr);
+}
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int o = 1; o < kLpr; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 // ||A_k||_inf = max over the rows of matrix k of the absolute row sum.
 __global__ __launch_bounds__(256) void k_anorm(const int64_t* __restrict__ ptr,
                                                const double* __restrict__ val,
                                                const int32_t* __restrict__ seg, int64_t n,
                                                double* __restrict__ out) {
+    const int j = threadIdx.x % kLpr;
     SegMax sm;
-    for (int u = 0; u < kRowsPerWave; ++u) {
-        const int64_t i = row_of(u);
+    for (int u = 0; u < kRowGroups; ++u) {
+        const int64_t i = sparse_row(u);
         double s = 0.0;
         if (i < n)
-            for (int64_t q = ptr[i]; q < ptr[i + 1]; ++q) s += fabs(val[q]);
+            for (int64_t q = ptr[i] + j; q < ptr[i + 1]; q += kLpr) s += fabs(val[q]);
+        s = group_sum(s);
         sm.add(out, seg_of(seg, i, n), s);
     }
     sm.flush(out);
@@ -142,36 +167,51 @@ __global__ __launch_bounds__(256) void k_colmax(const double* __restrict__ v, in
     sm.flush(out + c * nseg);
 }
 
-// r_c = b_c - A x_c and ||r_{k,c}||_inf, one thread per row; blockIdx.y = c.
+// r_c = b_c - A x_c and ||r_{k,c}||_inf for the columns c0 .. c0 + NR - 1
+// (those below nrhs) in one pass over A: each entry of A is read once and
+// multiplies NR gathered entries of x.
+template <int NR>
 __global__ __launch_bounds__(256) void k_resid(const int64_t* __restrict__ ptr,
                                                const int32_t* __restrict__ col,
                                                const double* __restrict__ val,
                                                const double* __restrict__ b, int64_t ldb,
                                                const double* __restrict__ x, int64_t ldx,
-                                               double* __restrict__ r, int64_t n,
-                                               const int32_t* __restrict__ seg, int64_t nseg,
-                                               double* __restrict__ rnorm) {
-    const int c = blockIdx.y;
-    const double* __restrict__ xc = x + c * ldx;
-    SegMax sm;
-    for (int u = 0; u < kRowsPerWave; ++u) {
-        const int64_t i = row_of(u);
-        double ri = 0.0;
+                                               double* __restrict__ r, int64_t n, int c0,
+                                               int nrhs, const int32_t* __restrict__ seg,
+                                               int64_t nseg, double* __restrict__ rnorm) {
+    const int j = threadIdx.x % kLpr;
+    const int nc = min(NR, nrhs - c0);
+    SegMax sm[NR];
+    for (int u = 0; u < kRowGroups; ++u) {
+        const int64_t i = sparse_row(u);
+        double acc[NR];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) acc[c] = 0.0;
         if (i < n) {
-            double s0 = 0.0, s1 = 0.0;
-            int64_t q = ptr[i];
-            const int64_t q1 = ptr[i + 1];
-            for (; q + 1 < q1; q += 2) {
-                s0 += val[q] * xc[col[q]];
-                s1 += val[q + 1] * xc[col[q + 1]];
+            for (int64_t q = ptr[i] + j; q < ptr[i + 1]; q += kLpr) {
+                const double v = val[q];
+                const int64_t k = col[q];
+#pragma unroll
+                for (int c = 0; c < NR; ++c)
+                    if (c < nc) acc[c] += v * x[k + (int64_t)(c0 + c) * ldx];
             }
-            if (q < q1) s0 += val[q] * xc[col[q]];
-            ri = b[i + c * ldb] - (s0 + s1);
-            r[i + c * n] = ri;
         }
-        sm.add(rnorm + c * nseg, seg_of(seg, i, n), fabs(ri));
+        const int si = seg_of(seg, i, n);
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            if (c >= nc) break;  // uniform
+            const double s = group_sum(acc[c]);
+            double ri = 0.0;
+            if (i < n) {
+                ri = b[i + (int64_t)(c0 + c) * ldb] - s;
+                if (j == 0) r[i + (int64_t)(c0 + c) * n] = ri;
+            }
+            sm[c].add(rnorm + (int64_t)(c0 + c) * nseg, si, fabs(ri));
+        }
     }
-    sm.flush(rnorm + c * nseg);
+#pragma unroll
+    for (int c = 0; c < NR; ++c)
+        if (c < nc) sm[c].flush(rnorm + (int64_t)(c0 + c) * nseg);
 }
 
 // eta and the scale 1 / ||r|| of the next correction (0 when r = 0), per
@@ -303,7 +343,7 @@ int32_t load_refine_matrix(spc_numeric* num, const double* values, hipStream_t s
     hipLaunchKernelGGL(k_fill_f64, dim3(grid_of(num->nseg)), dim3(256), 0, st, num->a_norm,
                        num->nseg, 0.0);
     if (S.n > 0)
-        hipLaunchKernelGGL(k_anorm, dim3(row_blocks(S.n)), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_anorm, dim3(sparse_blocks(S.n)), dim3(256), 0, st,
                            (const int64_t*)num->a_ptr, (const double*)num->a_val,
                            (const int32_t*)num->a_seg, S.n, num->a_norm);
     HIP_TRY(hipGetLastError());
@@ -370,9 +410,13 @@ int32_t run_refine(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb,
     hipLaunchKernelGGL(k_colmax, grid_rows, dim3(256), 0, st, b, ldb, n, seg, ns, bn);
     for (int32_t it = 0;; ++it) {
         hipLaunchKernelGGL(k_fill_f64, dim3(grid_of(2 * ne)), dim3(256), 0, st, xn, 2 * ne, 0.0);
-        hipLaunchKernelGGL(k_resid, grid_rows, dim3(256), 0, st, (const int64_t*)num->a_ptr,
-                           (const int32_t*)num->a_col, (const double*)num->a_val, b, ldb,
-                           (const double*)x, ldx, r, n, seg, ns, rn);
+        for (int32_t c0 = 0; c0 < nrhs; c0 += kResidCols) {
+            auto kr = nrhs - c0 == 1 ? k_resid<1> : k_resid<kResidCols>;
+            hipLaunchKernelGGL(kr, dim3(sparse_blocks(n)), dim3(256), 0, st,
+                               (const int64_t*)num->a_ptr, (const int32_t*)num->a_col,
+                               (const double*)num->a_val, b, ldb, (const double*)x, ldx, r, n,
+                               (int)c0, (int)nrhs, seg, ns, rn);
+        }
         hipLaunchKernelGGL(k_colmax, grid_rows, dim3(256), 0, st, (const double*)x, ldx, n, seg,
                            ns, xn);
         hipLaunchKernelGGL(k_eta, dim3(blocks_of(ne)), dim3(256), 0, st, (const double*)rn,

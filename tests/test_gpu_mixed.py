@@ -177,3 +177,26 @@ def test_fp32_plain_solve_and_refactor():
     assert num.status() == 0
     Cp, Ci, Cx, osym, Lx = _oracle(p2)
     _check_refined(p2, num, osym, Lx, p2.rhs)
+
+
+@pytest.mark.parametrize("k", [1, 8, 11])
+def test_refine_right_hand_side_groups(k):
+    """The residual goes through A eight right-hand sides at a time: one, a
+    full group and a ragged second group all refine to 1e-10, and the last
+    column agrees with its own one-column refinement to within the bound two
+    backward-stable solutions share."""
+    torch = torch_dev()
+    p = inputs.make_grid_problem("27pt3", (6, 6, 6), 43, shift=1e-3, nrhs=0)
+    sym, num = _fp32_factor(p, 150, 0.1)
+    Cp, Ci, Cx, osym, Lx = _oracle(p)
+    B = np.asfortranarray(np.random.default_rng(k).standard_normal((p.n, k)))
+    _check_refined(p, num, osym, Lx, B)
+    b = torch.from_numpy(B).to("cuda:0")
+    x, _, _ = num.solve_refine(b, tol=1e-10)
+    x = x.cpu().numpy().reshape(p.n, k)
+    xl, _, _ = num.solve_refine(torch.from_numpy(np.ascontiguousarray(B[:, k - 1])).to("cuda:0"),
+                                tol=1e-10)
+    xl = xl.cpu().numpy().reshape(p.n)
+    # both meet eta <= 1e-10, so they agree to within cond(A) times twice that
+    bound = max(1e-12, 4 * _cond_bound(p) * 2e-10)
+    assert np.abs(x[:, k - 1] - xl).max() / np.abs(xl).max() <= bound
