@@ -72,6 +72,7 @@ def _mixed_case(name):
 
 
 @pytest.mark.parametrize("name,sched", [(c, 0) for c in MIXED_CASES] +
+                         [(c, 1) for c in ("dense300", "lap3d_20_cap32", "lap3d_12_shift3")] +
                          [(c, 2) for c in ("dense300", "lap3d_20_cap32", "elast27_6")])
 def test_fp32_factor_and_refined_solve(name, sched):
     p, cap, ratio = _mixed_case(name)
