@@ -65,9 +65,25 @@ __device__ bool small_body(int s, const KArgs& a, S* __restrict__ arena, S* __re
     const int64_t rp = a.rowptr[s];
     const int m = (int)(a.rowptr[s + 1] - rp), r = m - w;
     S* __restrict__ base = arena + a.sn_off[s];
-    for (int j = 0; j < w; ++j)
-        for (int i = lane; i < m; i += 64)
-            blk[j * kSmallLd + i] = i >= j ? (C)base[i + (int64_t)j * ld] : C(0);
+    // the block into LDS, eight columns at a time with every load in flight
+    for (int j0 = 0; j0 < w; j0 += 8) {
+        constexpr int kChunks = (kSmallLd + 63) / 64;
+        C v[8][kChunks];
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj)
+#pragma unroll
+            for (int q = 0; q < kChunks; ++q) {
+                const int i = lane + 64 * q, j = j0 + jj;
+                v[jj][q] = (j < w && i < m && i >= j) ? (C)base[i + (int64_t)j * ld] : C(0);
+            }
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj)
+#pragma unroll
+            for (int q = 0; q < kChunks; ++q) {
+                const int i = lane + 64 * q, j = j0 + jj;
+                if (j < w && i < m) blk[j * kSmallLd + i] = v[jj][q];
+            }
+    }
     // targets of the rows below (their columns in the update)
     if (lane < r) {
         const int64_t at = rp + w + lane;
@@ -118,17 +134,32 @@ __device__ bool small_body(int s, const KArgs& a, S* __restrict__ arena, S* __re
     }
     for (int j = 0; j < w; ++j)
         for (int i = j + lane; i < m; i += 64) base[i + (int64_t)j * ld] = (S)blk[j * kSmallLd + i];
-    // update + scatter: lane i takes row i below the block and every column c <= i
+    // update + scatter: lane i takes row i below the block and every column
+    // c <= i, in groups of kGroup columns whose relative indices are all
+    // loaded before the group's products and atomics
     if (lane < r) {
+        constexpr int kGroup = 8;
         C li[kSmallW];
 #pragma unroll
         for (int k = 0; k < kSmallW; ++k) li[k] = k < w ? blk[k * kSmallLd + w + lane] : C(0);
-        for (int c = 0; c <= lane; ++c) {
-            C v = C(0);
+        for (int c0 = 0; c0 <= lane; c0 += kGroup) {
+            int32_t rv[kGroup];
 #pragma unroll
-            for (int k = 0; k < kSmallW; ++k)
-                if (k < w) v += li[k] * blk[k * kSmallLd + w + c];
-            unsafeAtomicAdd(arena + colbase[c] + a.rel[relbase[c] + lane], (S)(-v));
+            for (int u = 0; u < kGroup; ++u) {
+                const int c = c0 + u;
+                rv[u] = c <= lane ? a.rel[relbase[c] + lane] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) {
+                const int c = c0 + u;
+                if (c <= lane) {
+                    C v = C(0);
+#pragma unroll
+                    for (int k = 0; k < kSmallW; ++k)
+                        if (k < w) v += li[k] * blk[k * kSmallLd + w + c];
+                    unsafeAtomicAdd(arena + colbase[c] + rv[u], (S)(-v));
+                }
+            }
         }
     }
     return false;
@@ -150,18 +181,26 @@ __device__ __forceinline__ void small_factor(int s, const KArgs& a, float* arena
 }
 
 // One wave per small supernode of list[0 .. count).  A wave past the end
-// returns at once: the kernel has no workgroup barrier.
+// returns at once: the kernel has no workgroup barrier.  LDS (dynamic) holds
+// per wave the block's first maxw columns (stride kSmallLd, FP64) and maxr
+// column lookups: sized to the widest and tallest small supernode of the
+// level, so that levels of tiny supernodes keep many waves per CU.
 template <class R>
 __global__ __launch_bounds__(256) void k_small(const int32_t* __restrict__ list, int count,
                                                KArgs a, R* __restrict__ arena,
-                                               R* __restrict__ dinv, int32_t* __restrict__ status) {
-    __shared__ double lds[4][kSmallLd * kSmallW];
-    __shared__ int64_t cb[4][kSmallR], rb[4][kSmallR];
+                                               R* __restrict__ dinv, int32_t* __restrict__ status,
+                                               int maxw, int maxr) {
+    extern __shared__ double sm_small[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double* blk = sm_small + (size_t)wave * kSmallLd * maxw;
+    int64_t* cb = (int64_t*)(sm_small + (size_t)4 * kSmallLd * maxw) + (size_t)wave * 2 * maxr;
     const int idx = blockIdx.x * 4 + wave;
     if (idx >= count) return;
-    small_factor(list[idx], a, arena, dinv, status, status + 1, lds[wave], cb[wave], rb[wave],
-                 lane);
+    small_factor(list[idx], a, arena, dinv, status, status + 1, blk, cb, cb + maxr, lane);
+}
+
+size_t small_lds(int maxw, int maxr) {
+    return (size_t)4 * kSmallLd * maxw * sizeof(double) + (size_t)4 * 2 * maxr * sizeof(int64_t);
 }
 
 // Forward solve of one small supernode per wave, every right-hand side:
@@ -247,14 +286,19 @@ unsigned waves_grid(int count) { return (unsigned)std::max(1, (count + 3) / 4); 
 }  // namespace
 
 void launch_small_factor(spc_numeric* num, const KArgs& a, const int32_t* list, int count,
-                         hipStream_t st) {
+                         int maxw, int maxr, hipStream_t st) {
     if (count <= 0) return;
+    maxw = std::max(1, std::min(maxw, kSmallW));
+    maxr = std::max(1, std::min(maxr, kSmallR));
+    const size_t lds = small_lds(maxw, maxr);
     if (num->prec == 1)
-        hipLaunchKernelGGL(k_small<float>, dim3(waves_grid(count)), dim3(256), 0, st, list, count,
-                           a, (float*)num->arena, (float*)num->dinv, num->status_dev);
+        hipLaunchKernelGGL(k_small<float>, dim3(waves_grid(count)), dim3(256), lds, st, list,
+                           count, a, (float*)num->arena, (float*)num->dinv, num->status_dev, maxw,
+                           maxr);
     else
-        hipLaunchKernelGGL(k_small<double>, dim3(waves_grid(count)), dim3(256), 0, st, list,
-                           count, a, (double*)num->arena, (double*)num->dinv, num->status_dev);
+        hipLaunchKernelGGL(k_small<double>, dim3(waves_grid(count)), dim3(256), lds, st, list,
+                           count, a, (double*)num->arena, (double*)num->dinv, num->status_dev,
+                           maxw, maxr);
 }
 
 void launch_small_solve(spc_numeric* num, const KArgs& a, const int32_t* list, int count,
