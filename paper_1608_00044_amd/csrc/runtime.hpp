@@ -217,6 +217,6 @@ void drop_solve_graphs(spc_numeric* num);
 void launch_small_factor(spc_numeric* num, const KArgs& a, const int32_t* list, int count,
                          int maxw, int maxr, hipStream_t st);
 void launch_small_solve(spc_numeric* num, const KArgs& a, const int32_t* list, int count,
-                        void* y, int64_t n, int nrhs, bool forward, hipStream_t stream);
+                        int maxw, void* y, int64_t n, int nrhs, bool forward, hipStream_t st);
 
 }  // namespace spc

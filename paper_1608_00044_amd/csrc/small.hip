@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <type_traits>
 
 #include "runtime.hpp"
 
@@ -203,9 +204,10 @@ size_t small_lds(int maxw, int maxr) {
     return (size_t)4 * kSmallLd * maxw * sizeof(double) + (size_t)4 * 2 * maxr * sizeof(int64_t);
 }
 
-// Forward solve of one small supernode per wave, every right-hand side:
+// Forward solve of one small supernode per wave, every right-hand side
+// (WB: a bound on the level's small widths, so registers follow the level):
 //   y_s = inv(L11) y_s;  y[rows below] -= L21 y_s  (atomic: siblings share ancestors)
-template <class R>
+template <class R, int WB>
 __global__ __launch_bounds__(256) void k_small_fwd(const int32_t* __restrict__ list, int count,
                                                    KArgs a, const R* __restrict__ arena,
                                                    const R* __restrict__ dinv,
@@ -219,9 +221,9 @@ __global__ __launch_bounds__(256) void k_small_fwd(const int32_t* __restrict__ l
     const int r = (int)(a.rowptr[s + 1] - rp) - w;
     const R* __restrict__ L = arena + a.sn_off[s];
     const R* __restrict__ inv = dinv + a.inv_off[s];
-    R li[kSmallW], iv[kSmallW];
+    R li[WB], iv[WB];
 #pragma unroll
-    for (int k = 0; k < kSmallW; ++k) {
+    for (int k = 0; k < WB; ++k) {
         li[k] = (lane < r && k < w) ? L[w + lane + (int64_t)k * ld] : R(0);
         iv[k] = (lane < w && k < w) ? inv[lane * w + k] : R(0);
     }
@@ -231,18 +233,19 @@ __global__ __launch_bounds__(256) void k_small_fwd(const int32_t* __restrict__ l
         const R b = lane < w ? yc[first + lane] : R(0);
         R ys = R(0);
 #pragma unroll
-        for (int k = 0; k < kSmallW; ++k) ys += iv[k] * __shfl(b, k, 64);
+        for (int k = 0; k < WB; ++k) ys += iv[k] * __shfl(b, k, 64);
         if (lane < w) yc[first + lane] = ys;
         R acc = R(0);
 #pragma unroll
-        for (int k = 0; k < kSmallW; ++k) acc += li[k] * __shfl(ys, k, 64);
+        for (int k = 0; k < WB; ++k) acc += li[k] * __shfl(ys, k, 64);
         if (lane < r) unsafeAtomicAdd(yc + row, -acc);
     }
 }
 
-// Backward solve of one small supernode per wave, every right-hand side:
+// Backward solve of one small supernode per wave, every right-hand side
+// (WB as for the forward solve):
 //   t = L21^T y[rows below] (wave sums);  y_s = inv(L11)^T (y_s - t)
-template <class R>
+template <class R, int WB>
 __global__ __launch_bounds__(256) void k_small_bwd(const int32_t* __restrict__ list, int count,
                                                    KArgs a, const R* __restrict__ arena,
                                                    const R* __restrict__ dinv,
@@ -256,9 +259,9 @@ __global__ __launch_bounds__(256) void k_small_bwd(const int32_t* __restrict__ l
     const int r = (int)(a.rowptr[s + 1] - rp) - w;
     const R* __restrict__ L = arena + a.sn_off[s];
     const R* __restrict__ inv = dinv + a.inv_off[s];
-    R li[kSmallW], ivt[kSmallW];
+    R li[WB], ivt[WB];
 #pragma unroll
-    for (int k = 0; k < kSmallW; ++k) {
+    for (int k = 0; k < WB; ++k) {
         li[k] = (lane < r && k < w) ? L[w + lane + (int64_t)k * ld] : R(0);
         ivt[k] = (lane < w && k < w) ? inv[k * w + lane] : R(0);
     }
@@ -268,7 +271,7 @@ __global__ __launch_bounds__(256) void k_small_bwd(const int32_t* __restrict__ l
         const R yb = lane < r ? yc[row] : R(0);
         R u = lane < w ? yc[first + lane] : R(0);
 #pragma unroll
-        for (int k = 0; k < kSmallW; ++k) {
+        for (int k = 0; k < WB; ++k) {
             if (k < w) {
                 const R t = wave_sum(li[k] * yb);
                 if (lane == k) u -= t;
@@ -276,7 +279,7 @@ __global__ __launch_bounds__(256) void k_small_bwd(const int32_t* __restrict__ l
         }
         R out = R(0);
 #pragma unroll
-        for (int k = 0; k < kSmallW; ++k) out += ivt[k] * __shfl(u, k, 64);
+        for (int k = 0; k < WB; ++k) out += ivt[k] * __shfl(u, k, 64);
         if (lane < w) yc[first + lane] = out;
     }
 }
@@ -302,27 +305,28 @@ void launch_small_factor(spc_numeric* num, const KArgs& a, const int32_t* list, 
 }
 
 void launch_small_solve(spc_numeric* num, const KArgs& a, const int32_t* list, int count,
-                        void* y, int64_t n, int nrhs, bool forward, hipStream_t st) {
+                        int maxw, void* y, int64_t n, int nrhs, bool forward, hipStream_t st) {
     if (count <= 0) return;
     const dim3 g(waves_grid(count)), b(256);
+    auto go = [&](auto kf, auto kb, auto* yt) {
+        using T = std::remove_pointer_t<decltype(yt)>;
+        if (forward)
+            hipLaunchKernelGGL(kf, g, b, 0, st, list, count, a, (const T*)num->arena,
+                               (const T*)num->dinv, yt, n, nrhs);
+        else
+            hipLaunchKernelGGL(kb, g, b, 0, st, list, count, a, (const T*)num->arena,
+                               (const T*)num->dinv, yt, n, nrhs);
+    };
     if (num->prec == 1) {
-        if (forward)
-            hipLaunchKernelGGL(k_small_fwd<float>, g, b, 0, st, list, count, a,
-                               (const float*)num->arena, (const float*)num->dinv, (float*)y, n,
-                               nrhs);
-        else
-            hipLaunchKernelGGL(k_small_bwd<float>, g, b, 0, st, list, count, a,
-                               (const float*)num->arena, (const float*)num->dinv, (float*)y, n,
-                               nrhs);
+        float* yf = (float*)y;
+        if (maxw <= 4) go(k_small_fwd<float, 4>, k_small_bwd<float, 4>, yf);
+        else if (maxw <= 8) go(k_small_fwd<float, 8>, k_small_bwd<float, 8>, yf);
+        else go(k_small_fwd<float, kSmallW>, k_small_bwd<float, kSmallW>, yf);
     } else {
-        if (forward)
-            hipLaunchKernelGGL(k_small_fwd<double>, g, b, 0, st, list, count, a,
-                               (const double*)num->arena, (const double*)num->dinv, (double*)y,
-                               n, nrhs);
-        else
-            hipLaunchKernelGGL(k_small_bwd<double>, g, b, 0, st, list, count, a,
-                               (const double*)num->arena, (const double*)num->dinv, (double*)y,
-                               n, nrhs);
+        double* yd = (double*)y;
+        if (maxw <= 4) go(k_small_fwd<double, 4>, k_small_bwd<double, 4>, yd);
+        else if (maxw <= 8) go(k_small_fwd<double, 8>, k_small_bwd<double, 8>, yd);
+        else go(k_small_fwd<double, kSmallW>, k_small_bwd<double, kSmallW>, yd);
     }
 }
 
