@@ -928,7 +928,7 @@ void launch_ft(spc_numeric* num, const DevicePlan* P, const Symbolic& S, const K
     if (n1 - n0 > nbig) {  // small supernodes: factor, update and scatter, one wave each
         ev = mark_begin(num, st);
         launch_small_factor(num, a, P->level_sn + n0 + nbig, n1 - n0 - nbig, P->small_maxw[l],
-                            P->small_maxr[l], st);
+                            P->small_maxr[l], P->small_maxm[l], st);
         mark_end(num, st, 5, ev);
     }
     const int64_t rb0 = P->rowblk_ptr[l], rb1 = P->rowblk_ptr[l + 1];

@@ -194,12 +194,14 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
         P->level_nbig.assign((size_t)nl, 0);
         P->small_maxw.assign((size_t)nl, 0);
         P->small_maxr.assign((size_t)nl, 0);
+        P->small_maxm.assign((size_t)nl, 0);
         for (int32_t l = 0; l < nl; ++l) {
             for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
                 const int32_t s = S.level_sn[q];
                 if (!is_small(S, s)) continue;
                 P->small_maxw[l] = std::max<int32_t>(P->small_maxw[l], S.width(s));
                 P->small_maxr[l] = std::max<int32_t>(P->small_maxr[l], (int32_t)S.nbelow(s));
+                P->small_maxm[l] = std::max<int32_t>(P->small_maxm[l], (int32_t)S.nrows(s));
             }
             for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q)
                 if (!is_small(S, S.level_sn[q])) ls.push_back(S.level_sn[q]);

@@ -115,7 +115,8 @@ struct DevicePlan {
     std::vector<int64_t> rowblk_ptr, tile_ptr;
     std::vector<int64_t> tile_crit;   // per level: leading tiles that feed level l + 1
     std::vector<int32_t> level_maxw;  // widest large supernode of the level
-    std::vector<int32_t> small_maxw, small_maxr;  // widest / tallest small supernode of the level
+    std::vector<int32_t> small_maxw, small_maxr, small_maxm;  // widest / tallest (below, all) small
+                                                              // supernode of the level
 };
 
 // Pointer bundle passed by value to kernels.
@@ -215,8 +216,9 @@ void free_refine(spc_numeric* num);
 void drop_solve_graphs(spc_numeric* num);
 // Small-supernode kernels (one wave per supernode of list[0 .. count)).
 void launch_small_factor(spc_numeric* num, const KArgs& a, const int32_t* list, int count,
-                         int maxw, int maxr, hipStream_t st);
+                         int maxw, int maxr, int maxm, hipStream_t st);
 void launch_small_solve(spc_numeric* num, const KArgs& a, const int32_t* list, int count,
-                        int maxw, void* y, int64_t n, int nrhs, bool forward, hipStream_t st);
+                        int maxw, int maxm, void* y, int64_t n, int nrhs, bool forward,
+                        hipStream_t st);
 
 }  // namespace spc

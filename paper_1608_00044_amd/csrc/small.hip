@@ -52,112 +52,115 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
-// Factorization, inverse and scatter of one small supernode by one wave.
-// Storage type S, compute type C.  kCheck (the FP32 pass): no status is
-// recorded; a pivot at most kSmallTau times its starting diagonal entry
-// makes the function return true before anything is written to global
-// memory, so that the caller can run it again in FP64.
-template <class S, class C, bool kCheck>
+// Factorization, inverse and scatter of one small supernode by G lanes of a
+// wave (gl: the lane's place among them; G = 64 takes any small supernode,
+// G = 16 or 32 only those with at most G rows, several per wave).  The block
+// sits in LDS with column stride LDG rows.  Storage type S, compute type C.
+// kCheck (the FP32 pass): no status is recorded; a pivot at most kSmallTau
+// times its starting diagonal entry makes the function return true before
+// anything is written to global memory, so that the caller can run it again
+// in FP64.
+template <class S, class C, bool kCheck, int G, int LDG>
 __device__ bool small_body(int s, const KArgs& a, S* __restrict__ arena, S* __restrict__ dinv,
                            int32_t* __restrict__ status, C* __restrict__ blk,
                            int64_t* __restrict__ colbase, int64_t* __restrict__ relbase,
-                           int lane) {
+                           int gl) {
     const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
     const int64_t rp = a.rowptr[s];
     const int m = (int)(a.rowptr[s + 1] - rp), r = m - w;
     S* __restrict__ base = arena + a.sn_off[s];
     // the block into LDS, eight columns at a time with every load in flight
     for (int j0 = 0; j0 < w; j0 += 8) {
-        constexpr int kChunks = (kSmallLd + 63) / 64;
+        constexpr int kChunks = (LDG + G - 1) / G;
         C v[8][kChunks];
 #pragma unroll
         for (int jj = 0; jj < 8; ++jj)
 #pragma unroll
             for (int q = 0; q < kChunks; ++q) {
-                const int i = lane + 64 * q, j = j0 + jj;
+                const int i = gl + G * q, j = j0 + jj;
                 v[jj][q] = (j < w && i < m && i >= j) ? (C)base[i + (int64_t)j * ld] : C(0);
             }
 #pragma unroll
         for (int jj = 0; jj < 8; ++jj)
 #pragma unroll
             for (int q = 0; q < kChunks; ++q) {
-                const int i = lane + 64 * q, j = j0 + jj;
-                if (j < w && i < m) blk[j * kSmallLd + i] = v[jj][q];
+                const int i = gl + G * q, j = j0 + jj;
+                if (j < w && i < m) blk[j * LDG + i] = v[jj][q];
             }
     }
     // targets of the rows below (their columns in the update)
-    if (lane < r) {
-        const int64_t at = rp + w + lane;
+    if (gl < r) {
+        const int64_t at = rp + w + gl;
         const int p = a.rowpair[at];
         const int t = a.pair_tgt[p];
-        colbase[lane] = a.sn_off[t] + (int64_t)(a.rows[at] - a.sn_first[t]) * a.sn_ld[t];
-        relbase[lane] = a.pair_rel[p] - a.pair_seg[p];
+        colbase[gl] = a.sn_off[t] + (int64_t)(a.rows[at] - a.sn_first[t]) * a.sn_ld[t];
+        relbase[gl] = a.pair_rel[p] - a.pair_seg[p];
     }
     __builtin_amdgcn_wave_barrier();
     bool bad = false;
     for (int k = 0; k < w; ++k) {
-        const C d = blk[k * kSmallLd + k];
+        const C d = blk[k * LDG + k];
         if (kCheck) {
             bad |= !(d > (C)kSmallTau * (C)base[k + (int64_t)k * ld]);
-        } else if (!(d > C(0)) && lane == 0) {
+        } else if (!(d > C(0)) && gl == 0) {
             atomicMin(status, first + k + 1);
         }
         C rs, l;
         rsqrt_sqrt_s(d, rs, l);
         __builtin_amdgcn_wave_barrier();
-        for (int i = k + 1 + lane; i < m; i += 64) blk[k * kSmallLd + i] *= rs;
-        if (lane == 0) blk[k * kSmallLd + k] = l;
+        for (int i = k + 1 + gl; i < m; i += G) blk[k * LDG + i] *= rs;
+        if (gl == 0) blk[k * LDG + k] = l;
         __builtin_amdgcn_wave_barrier();
-        for (int i = k + 1 + lane; i < m; i += 64) {
-            const C lik = blk[k * kSmallLd + i];
+        for (int i = k + 1 + gl; i < m; i += G) {
+            const C lik = blk[k * LDG + i];
             const int jend = min(w, i + 1);
-            for (int j = k + 1; j < jend; ++j) blk[j * kSmallLd + i] -= lik * blk[k * kSmallLd + j];
+            for (int j = k + 1; j < jend; ++j) blk[j * LDG + i] -= lik * blk[k * LDG + j];
         }
         __builtin_amdgcn_wave_barrier();
     }
     if (kCheck && bad) return true;
     // inverse of L11, column c by lane c, row major into the compact w x w block
-    if (lane < w) {
+    if (gl < w) {
         S* __restrict__ inv = dinv + a.inv_off[s];
         C x[kSmallW];
 #pragma unroll
         for (int q = 0; q < kSmallW; ++q) {
             if (q < w) {
-                C acc = q == lane ? C(1) : C(0);
+                C acc = q == gl ? C(1) : C(0);
 #pragma unroll
-                for (int k = 0; k < q; ++k) acc -= blk[k * kSmallLd + q] * x[k];
-                x[q] = acc / blk[q * kSmallLd + q];
-                inv[q * w + lane] = (S)x[q];
+                for (int k = 0; k < q; ++k) acc -= blk[k * LDG + q] * x[k];
+                x[q] = acc / blk[q * LDG + q];
+                inv[q * w + gl] = (S)x[q];
             } else {
                 x[q] = C(0);
             }
         }
     }
     for (int j = 0; j < w; ++j)
-        for (int i = j + lane; i < m; i += 64) base[i + (int64_t)j * ld] = (S)blk[j * kSmallLd + i];
+        for (int i = j + gl; i < m; i += G) base[i + (int64_t)j * ld] = (S)blk[j * LDG + i];
     // update + scatter: lane i takes row i below the block and every column
     // c <= i, in groups of kGroup columns whose relative indices are all
     // loaded before the group's products and atomics
-    if (lane < r) {
+    if (gl < r) {
         constexpr int kGroup = 8;
         C li[kSmallW];
 #pragma unroll
-        for (int k = 0; k < kSmallW; ++k) li[k] = k < w ? blk[k * kSmallLd + w + lane] : C(0);
-        for (int c0 = 0; c0 <= lane; c0 += kGroup) {
+        for (int k = 0; k < kSmallW; ++k) li[k] = k < w ? blk[k * LDG + w + gl] : C(0);
+        for (int c0 = 0; c0 <= gl; c0 += kGroup) {
             int32_t rv[kGroup];
 #pragma unroll
             for (int u = 0; u < kGroup; ++u) {
                 const int c = c0 + u;
-                rv[u] = c <= lane ? a.rel[relbase[c] + lane] : 0;
+                rv[u] = c <= gl ? a.rel[relbase[c] + gl] : 0;
             }
 #pragma unroll
             for (int u = 0; u < kGroup; ++u) {
                 const int c = c0 + u;
-                if (c <= lane) {
+                if (c <= gl) {
                     C v = C(0);
 #pragma unroll
                     for (int k = 0; k < kSmallW; ++k)
-                        if (k < w) v += li[k] * blk[k * kSmallLd + w + c];
+                        if (k < w) v += li[k] * blk[k * LDG + w + c];
                     unsafeAtomicAdd(arena + colbase[c] + rv[u], (S)(-v));
                 }
             }
@@ -166,54 +169,71 @@ __device__ bool small_body(int s, const KArgs& a, S* __restrict__ arena, S* __re
     return false;
 }
 
+template <int G, int LDG>
 __device__ __forceinline__ void small_factor(int s, const KArgs& a, double* arena, double* dinv,
                                              int32_t* status, int32_t*, double* lds,
-                                             int64_t* cb, int64_t* rb, int lane) {
-    small_body<double, double, false>(s, a, arena, dinv, status, lds, cb, rb, lane);
+                                             int64_t* cb, int64_t* rb, int gl) {
+    small_body<double, double, false, G, LDG>(s, a, arena, dinv, status, lds, cb, rb, gl);
 }
+template <int G, int LDG>
 __device__ __forceinline__ void small_factor(int s, const KArgs& a, float* arena, float* dinv,
                                              int32_t* status, int32_t* fallbacks, double* lds,
-                                             int64_t* cb, int64_t* rb, int lane) {
-    if (small_body<float, float, true>(s, a, arena, dinv, status, (float*)lds, cb, rb, lane)) {
+                                             int64_t* cb, int64_t* rb, int gl) {
+    if (small_body<float, float, true, G, LDG>(s, a, arena, dinv, status, (float*)lds, cb, rb,
+                                               gl)) {
         __builtin_amdgcn_wave_barrier();
-        small_body<float, double, false>(s, a, arena, dinv, status, lds, cb, rb, lane);
-        if (lane == 0) atomicAdd(fallbacks, 1);
+        small_body<float, double, false, G, LDG>(s, a, arena, dinv, status, lds, cb, rb, gl);
+        if (gl == 0) atomicAdd(fallbacks, 1);
     }
 }
 
-// One wave per small supernode of list[0 .. count).  A wave past the end
-// returns at once: the kernel has no workgroup barrier.  LDS (dynamic) holds
-// per wave the block's first maxw columns (stride kSmallLd, FP64) and maxr
-// column lookups: sized to the widest and tallest small supernode of the
-// level, so that levels of tiny supernodes keep many waves per CU.
-template <class R>
+// G lanes per small supernode of list[0 .. count), 64 / G supernodes per
+// wave.  A group past the end returns at once: the kernel has no workgroup
+// barrier.  LDS (dynamic) holds per group the block's first maxw columns
+// (stride LDG rows, FP64) and maxr column lookups, sized to the widest and
+// tallest small supernode of the level, so that levels of tiny supernodes
+// keep many waves per CU.
+template <class R, int G, int LDG>
 __global__ __launch_bounds__(256) void k_small(const int32_t* __restrict__ list, int count,
                                                KArgs a, R* __restrict__ arena,
                                                R* __restrict__ dinv, int32_t* __restrict__ status,
                                                int maxw, int maxr) {
     extern __shared__ double sm_small[];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double* blk = sm_small + (size_t)wave * kSmallLd * maxw;
-    int64_t* cb = (int64_t*)(sm_small + (size_t)4 * kSmallLd * maxw) + (size_t)wave * 2 * maxr;
-    const int idx = blockIdx.x * 4 + wave;
+    constexpr int kGroups = 4 * (64 / G);  // groups per workgroup
+    const int lane = threadIdx.x & 63;
+    const int grp = threadIdx.x / G, gl = lane % G;
+    double* blk = sm_small + (size_t)grp * LDG * maxw;
+    int64_t* cb = (int64_t*)(sm_small + (size_t)kGroups * LDG * maxw) + (size_t)grp * 2 * maxr;
+    const int idx = blockIdx.x * kGroups + grp;
     if (idx >= count) return;
-    small_factor(list[idx], a, arena, dinv, status, status + 1, blk, cb, cb + maxr, lane);
+    small_factor<G, LDG>(list[idx], a, arena, dinv, status, status + 1, blk, cb, cb + maxr, gl);
 }
 
+template <int G, int LDG>
 size_t small_lds(int maxw, int maxr) {
-    return (size_t)4 * kSmallLd * maxw * sizeof(double) + (size_t)4 * 2 * maxr * sizeof(int64_t);
+    constexpr int kGroups = 4 * (64 / G);
+    return (size_t)kGroups * LDG * maxw * sizeof(double) +
+           (size_t)kGroups * 2 * maxr * sizeof(int64_t);
 }
 
-// Forward solve of one small supernode per wave, every right-hand side
+// Sum over the G lanes of a lane group (G a power of two, groups aligned).
+template <int G, class T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Forward solve of one small supernode per G lanes, every right-hand side
 // (WB: a bound on the level's small widths, so registers follow the level):
 //   y_s = inv(L11) y_s;  y[rows below] -= L21 y_s  (atomic: siblings share ancestors)
-template <class R, int WB>
+template <class R, int WB, int G>
 __global__ __launch_bounds__(256) void k_small_fwd(const int32_t* __restrict__ list, int count,
                                                    KArgs a, const R* __restrict__ arena,
                                                    const R* __restrict__ dinv,
                                                    R* __restrict__ y, int64_t n, int nrhs) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int idx = blockIdx.x * 4 + wave;
+    const int lane = threadIdx.x & 63, gl = lane % G;
+    const int idx = blockIdx.x * (256 / G) + (int)threadIdx.x / G;
     if (idx >= count) return;
     const int s = list[idx];
     const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
@@ -224,34 +244,34 @@ __global__ __launch_bounds__(256) void k_small_fwd(const int32_t* __restrict__ l
     R li[WB], iv[WB];
 #pragma unroll
     for (int k = 0; k < WB; ++k) {
-        li[k] = (lane < r && k < w) ? L[w + lane + (int64_t)k * ld] : R(0);
-        iv[k] = (lane < w && k < w) ? inv[lane * w + k] : R(0);
+        li[k] = (gl < r && k < w) ? L[w + gl + (int64_t)k * ld] : R(0);
+        iv[k] = (gl < w && k < w) ? inv[gl * w + k] : R(0);
     }
-    const int32_t row = lane < r ? a.rows[rp + w + lane] : 0;
+    const int32_t row = gl < r ? a.rows[rp + w + gl] : 0;
     for (int c = 0; c < nrhs; ++c) {
         R* __restrict__ yc = y + (int64_t)c * n;
-        const R b = lane < w ? yc[first + lane] : R(0);
+        const R b = gl < w ? yc[first + gl] : R(0);
         R ys = R(0);
 #pragma unroll
-        for (int k = 0; k < WB; ++k) ys += iv[k] * __shfl(b, k, 64);
-        if (lane < w) yc[first + lane] = ys;
+        for (int k = 0; k < WB; ++k) ys += iv[k] * __shfl(b, k, G);
+        if (gl < w) yc[first + gl] = ys;
         R acc = R(0);
 #pragma unroll
-        for (int k = 0; k < WB; ++k) acc += li[k] * __shfl(ys, k, 64);
-        if (lane < r) unsafeAtomicAdd(yc + row, -acc);
+        for (int k = 0; k < WB; ++k) acc += li[k] * __shfl(ys, k, G);
+        if (gl < r) unsafeAtomicAdd(yc + row, -acc);
     }
 }
 
-// Backward solve of one small supernode per wave, every right-hand side
+// Backward solve of one small supernode per G lanes, every right-hand side
 // (WB as for the forward solve):
-//   t = L21^T y[rows below] (wave sums);  y_s = inv(L11)^T (y_s - t)
-template <class R, int WB>
+//   t = L21^T y[rows below] (group sums);  y_s = inv(L11)^T (y_s - t)
+template <class R, int WB, int G>
 __global__ __launch_bounds__(256) void k_small_bwd(const int32_t* __restrict__ list, int count,
                                                    KArgs a, const R* __restrict__ arena,
                                                    const R* __restrict__ dinv,
                                                    R* __restrict__ y, int64_t n, int nrhs) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int idx = blockIdx.x * 4 + wave;
+    const int lane = threadIdx.x & 63, gl = lane % G;
+    const int idx = blockIdx.x * (256 / G) + (int)threadIdx.x / G;
     if (idx >= count) return;
     const int s = list[idx];
     const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
@@ -262,54 +282,62 @@ __global__ __launch_bounds__(256) void k_small_bwd(const int32_t* __restrict__ l
     R li[WB], ivt[WB];
 #pragma unroll
     for (int k = 0; k < WB; ++k) {
-        li[k] = (lane < r && k < w) ? L[w + lane + (int64_t)k * ld] : R(0);
-        ivt[k] = (lane < w && k < w) ? inv[k * w + lane] : R(0);
+        li[k] = (gl < r && k < w) ? L[w + gl + (int64_t)k * ld] : R(0);
+        ivt[k] = (gl < w && k < w) ? inv[k * w + gl] : R(0);
     }
-    const int32_t row = lane < r ? a.rows[rp + w + lane] : 0;
+    const int32_t row = gl < r ? a.rows[rp + w + gl] : 0;
     for (int c = 0; c < nrhs; ++c) {
         R* __restrict__ yc = y + (int64_t)c * n;
-        const R yb = lane < r ? yc[row] : R(0);
-        R u = lane < w ? yc[first + lane] : R(0);
+        const R yb = gl < r ? yc[row] : R(0);
+        R u = gl < w ? yc[first + gl] : R(0);
 #pragma unroll
         for (int k = 0; k < WB; ++k) {
             if (k < w) {
-                const R t = wave_sum(li[k] * yb);
-                if (lane == k) u -= t;
+                const R t = group_sum<G>(li[k] * yb);
+                if (gl == k) u -= t;
             }
         }
         R out = R(0);
 #pragma unroll
-        for (int k = 0; k < WB; ++k) out += ivt[k] * __shfl(u, k, 64);
-        if (lane < w) yc[first + lane] = out;
+        for (int k = 0; k < WB; ++k) out += ivt[k] * __shfl(u, k, G);
+        if (gl < w) yc[first + gl] = out;
     }
 }
-
-unsigned waves_grid(int count) { return (unsigned)std::max(1, (count + 3) / 4); }
 
 }  // namespace
 
 void launch_small_factor(spc_numeric* num, const KArgs& a, const int32_t* list, int count,
-                         int maxw, int maxr, hipStream_t st) {
+                         int maxw, int maxr, int maxm, hipStream_t st) {
     if (count <= 0) return;
     maxw = std::max(1, std::min(maxw, kSmallW));
     maxr = std::max(1, std::min(maxr, kSmallR));
-    const size_t lds = small_lds(maxw, maxr);
-    if (num->prec == 1)
-        hipLaunchKernelGGL(k_small<float>, dim3(waves_grid(count)), dim3(256), lds, st, list,
-                           count, a, (float*)num->arena, (float*)num->dinv, num->status_dev, maxw,
-                           maxr);
-    else
-        hipLaunchKernelGGL(k_small<double>, dim3(waves_grid(count)), dim3(256), lds, st, list,
-                           count, a, (double*)num->arena, (double*)num->dinv, num->status_dev,
-                           maxw, maxr);
+    auto go = [&](auto kern, size_t lds, int per_block, auto* arena) {
+        using T = std::remove_pointer_t<decltype(arena)>;
+        const unsigned g = (unsigned)std::max(1, (count + per_block - 1) / per_block);
+        hipLaunchKernelGGL(kern, dim3(g), dim3(256), lds, st, list, count, a, arena,
+                           (T*)num->dinv, num->status_dev, maxw, maxr);
+    };
+    // several supernodes per wave when every one of the level has few rows
+    if (num->prec == 1) {
+        float* ar = (float*)num->arena;
+        if (maxm <= 16) go(k_small<float, 16, 16>, small_lds<16, 16>(maxw, maxr), 16, ar);
+        else if (maxm <= 32) go(k_small<float, 32, 32>, small_lds<32, 32>(maxw, maxr), 8, ar);
+        else go(k_small<float, 64, kSmallLd>, small_lds<64, kSmallLd>(maxw, maxr), 4, ar);
+    } else {
+        double* ar = (double*)num->arena;
+        if (maxm <= 16) go(k_small<double, 16, 16>, small_lds<16, 16>(maxw, maxr), 16, ar);
+        else if (maxm <= 32) go(k_small<double, 32, 32>, small_lds<32, 32>(maxw, maxr), 8, ar);
+        else go(k_small<double, 64, kSmallLd>, small_lds<64, kSmallLd>(maxw, maxr), 4, ar);
+    }
 }
 
 void launch_small_solve(spc_numeric* num, const KArgs& a, const int32_t* list, int count,
-                        int maxw, void* y, int64_t n, int nrhs, bool forward, hipStream_t st) {
+                        int maxw, int maxm, void* y, int64_t n, int nrhs, bool forward,
+                        hipStream_t st) {
     if (count <= 0) return;
-    const dim3 g(waves_grid(count)), b(256);
-    auto go = [&](auto kf, auto kb, auto* yt) {
+    auto go = [&](auto kf, auto kb, int per_block, auto* yt) {
         using T = std::remove_pointer_t<decltype(yt)>;
+        const dim3 g((unsigned)std::max(1, (count + per_block - 1) / per_block)), b(256);
         if (forward)
             hipLaunchKernelGGL(kf, g, b, 0, st, list, count, a, (const T*)num->arena,
                                (const T*)num->dinv, yt, n, nrhs);
@@ -317,17 +345,26 @@ void launch_small_solve(spc_numeric* num, const KArgs& a, const int32_t* list, i
             hipLaunchKernelGGL(kb, g, b, 0, st, list, count, a, (const T*)num->arena,
                                (const T*)num->dinv, yt, n, nrhs);
     };
-    if (num->prec == 1) {
-        float* yf = (float*)y;
-        if (maxw <= 4) go(k_small_fwd<float, 4>, k_small_bwd<float, 4>, yf);
-        else if (maxw <= 8) go(k_small_fwd<float, 8>, k_small_bwd<float, 8>, yf);
-        else go(k_small_fwd<float, kSmallW>, k_small_bwd<float, kSmallW>, yf);
-    } else {
-        double* yd = (double*)y;
-        if (maxw <= 4) go(k_small_fwd<double, 4>, k_small_bwd<double, 4>, yd);
-        else if (maxw <= 8) go(k_small_fwd<double, 8>, k_small_bwd<double, 8>, yd);
-        else go(k_small_fwd<double, kSmallW>, k_small_bwd<double, kSmallW>, yd);
-    }
+    // the width bound sizes the registers; lanes per supernode follow the
+    // level's tallest small supernode
+    auto pick = [&](auto* yt) {
+        using T = std::remove_pointer_t<decltype(yt)>;
+        if (maxm <= 16) {
+            if (maxw <= 4) go(k_small_fwd<T, 4, 16>, k_small_bwd<T, 4, 16>, 16, yt);
+            else if (maxw <= 8) go(k_small_fwd<T, 8, 16>, k_small_bwd<T, 8, 16>, 16, yt);
+            else go(k_small_fwd<T, kSmallW, 16>, k_small_bwd<T, kSmallW, 16>, 16, yt);
+        } else if (maxm <= 32) {
+            if (maxw <= 4) go(k_small_fwd<T, 4, 32>, k_small_bwd<T, 4, 32>, 8, yt);
+            else if (maxw <= 8) go(k_small_fwd<T, 8, 32>, k_small_bwd<T, 8, 32>, 8, yt);
+            else go(k_small_fwd<T, kSmallW, 32>, k_small_bwd<T, kSmallW, 32>, 8, yt);
+        } else {
+            if (maxw <= 4) go(k_small_fwd<T, 4, 64>, k_small_bwd<T, 4, 64>, 4, yt);
+            else if (maxw <= 8) go(k_small_fwd<T, 8, 64>, k_small_bwd<T, 8, 64>, 4, yt);
+            else go(k_small_fwd<T, kSmallW, 64>, k_small_bwd<T, kSmallW, 64>, 4, yt);
+        }
+    };
+    if (num->prec == 1) pick((float*)y);
+    else pick((double*)y);
 }
 
 }  // namespace spc

@@ -479,8 +479,8 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* y, R* tacc, hipStream_t s
         if (nbig > 0)
             hipLaunchKernelGGL(k_fwd_diag<R>, dim3(nbig), dim3(kDiagThreads), lds, st,
                                P->level_sn + n0, a, arena, dinv, y, n, nrhs);
-        launch_small_solve(num, a, P->level_sn + n0 + nbig, n1 - n0 - nbig, P->small_maxw[l], y, n,
-                           nrhs, true, st);
+        launch_small_solve(num, a, P->level_sn + n0 + nbig, n1 - n0 - nbig, P->small_maxw[l],
+                           P->small_maxm[l], y, n, nrhs, true, st);
         const int64_t rb0 = P->rowblk_ptr[l], rb1 = P->rowblk_ptr[l + 1];
         if (rb1 > rb0)
             hipLaunchKernelGGL((k_fwd_gemv<R, NR>), dim3((unsigned)(rb1 - rb0)), dim3(256),
@@ -497,8 +497,8 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* y, R* tacc, hipStream_t s
             hipLaunchKernelGGL(k_bwd_diag<R>, dim3(nbig), dim3(kDiagThreads),
                                diag_lds(P->level_maxw[l], sizeof(R)), st, P->level_sn + n0, a,
                                arena, dinv, y, (const R*)tacc, n, nrhs);
-        launch_small_solve(num, a, P->level_sn + n0 + nbig, n1 - n0 - nbig, P->small_maxw[l], y, n,
-                           nrhs, false, st);
+        launch_small_solve(num, a, P->level_sn + n0 + nbig, n1 - n0 - nbig, P->small_maxw[l],
+                           P->small_maxm[l], y, n, nrhs, false, st);
     }
 }
 
