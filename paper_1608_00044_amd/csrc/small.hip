@@ -1,5 +1,7 @@
-// Small supernodes (width <= 16, at most 64 rows below the diagonal block)
-// one wavefront each, with no workgroup barrier: the F task (diagonal
+// Small supernodes (width <= 16, at most 64 rows below the diagonal block),
+// one group of 16, 32 or 64 lanes each (several per wavefront when every
+// small supernode of the level has at most 16 or 32 rows), with no workgroup
+// barrier: the F task (diagonal
 // factorization and panel solve) and the U + A tasks (update and
 // relative-index scatter) of Section III-A fused in one pass over the
 // supernode, and both solves of Section II-A fused per supernode.  Nested
