@@ -71,13 +71,22 @@ def backward_error(p, x, b):
 def cpu_baseline(name, sample_dims, repeat=0):
     """The oracle (plain left-looking column Cholesky, one core) timed on a
     bounded sample: the same workload recipe on a smaller grid."""
+    saved = os.sched_getaffinity(0) if hasattr(os, "sched_getaffinity") else None
+    try:
+        os.sched_setaffinity(0, {sorted(saved)[0]})
+    except (AttributeError, OSError, TypeError):
+        pass
+    try:
+        return _cpu_baseline_pinned(name, sample_dims, repeat)
+    finally:
+        if saved is not None:
+            os.sched_setaffinity(0, saved)
+
+
+def _cpu_baseline_pinned(name, sample_dims, repeat):
     import oracle
     from paper_1608_00044_amd import inputs
 
-    try:
-        os.sched_setaffinity(0, {sorted(os.sched_getaffinity(0))[0]})
-    except (AttributeError, OSError):
-        pass
     p = inputs.make_workload(name, repeat=repeat, nrhs=0, dims=sample_dims)
     Cp, Ci, Cx, _ = oracle.permute(p.n, p.colptr, p.rowind, p.values, p.perm)
     sym = oracle.symbolic(p.n, Cp, Ci)
@@ -90,6 +99,54 @@ def cpu_baseline(name, sample_dims, repeat=0):
     return {"value": sym.flops / dt / 1e9, "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
             "sample": "same recipe on a %s grid (n=%d, F=%.3e), numeric factorization only, "
                       "%.1f s" % ("x".join(map(str, sample_dims)), p.n, sym.flops, dt)}
+
+
+def _oracle_batch_share(job):
+    """Pool worker: the oracle's whole pipeline (permute, symbolic, factor,
+    one-RHS solve) on members `ks` of the batch, each timed alone."""
+    count, ks = job
+    import oracle
+    from paper_1608_00044_amd import inputs
+
+    out = []
+    for p in inputs.make_batch(count=count, members=ks):
+        t0 = time.perf_counter()
+        Cp, Ci, Cx, _ = oracle.permute(p.n, p.colptr, p.rowind, p.values, p.perm)
+        sym = oracle.symbolic(p.n, Cp, Ci)
+        st, Lx = oracle.factor(p.n, Cp, Ci, Cx, sym)
+        if st == 0:
+            oracle.solve(p.n, sym, Lx, p.perm, p.rhs[:, 0])
+        out.append((time.perf_counter() - t0, float(sym.flops), int(st)))
+    return out
+
+
+def cpu_batch_baseline(count, sample, max_workers=16):
+    """The oracle on the first `sample` matrices of the batched workload,
+    spread over the host's cores by a process pool (members dealt round
+    robin): the one-core sum and the pool's makespan (the slowest worker's
+    summed compute time), scaled to matrices/s."""
+    import multiprocessing
+
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else 1
+    workers = max(1, min(cores, max_workers, sample))
+    jobs = [(count, list(range(w, sample, workers))) for w in range(workers)]
+    t0 = time.perf_counter()
+    with multiprocessing.get_context("spawn").Pool(workers) as pool:
+        res = pool.map(_oracle_batch_share, jobs)
+    wall = time.perf_counter() - t0
+    if any(st != 0 for r in res for _, _, st in r):
+        raise RuntimeError("oracle failed on a batch member")
+    per_worker = [sum(t for t, _, _ in r) for r in res]
+    one_core = sum(per_worker)
+    makespan = max(per_worker)
+    flops = sum(f for r in res for _, f, _ in r)
+    return {"value": sample / makespan, "unit": "matrices/s", "cores": workers, "kind": "oracle",
+            "sample": "first %d of the %d matrices: permute + symbolic + factor + one-RHS "
+                      "solve each; %d worker processes, members dealt round robin"
+                      % (sample, count, workers),
+            "one_core_sum_s": one_core, "makespan_s": makespan, "pool_wall_s": wall,
+            "one_core_matrices_per_s": sample / one_core,
+            "factor_flops_F": flops}
 
 
 def measured_traffic(kernel, workload):
@@ -222,7 +279,7 @@ def batched(count, steps, precision, tol=1e-10):
             f_ms.append(e0.elapsed_time(e1))
     xs = x.cpu().numpy().ravel()
     worst, off = 0.0, 0
-    for p in probs[:: max(1, len(probs) // 50)] if False else probs[:50]:
+    for p in probs[:50]:
         worst = max(worst, backward_error(p, xs[off:off + p.n], p.rhs[:, 0]))
         off += p.n
     fm, sm = float(np.mean(f_ms)), float(np.mean(s_ms))
@@ -343,6 +400,9 @@ def main():
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB (a dispatch of known traffic "
                          "for scaling hardware byte counters)")
+    ap.add_argument("--cpu-batch-sample", type=int, default=1000,
+                    help="matrices of the batched workload the oracle runs on a process "
+                         "pool (0 to skip)")
     ap.add_argument("--cpu-sample", default=None,
                     help="grid of the bounded oracle sample (default: 40^3 for 3D workloads, "
                          "the full grid for 2D ones)")
@@ -508,6 +568,10 @@ def main():
             dims = (40, 40, 40) if len(full) == 3 else full
         log("cpu baseline on", dims)
         out["cpu_baseline"] = cpu_baseline(name, dims)
+        if args.batch and args.cpu_batch_sample:
+            log("cpu baseline of the batch, %d matrices" % min(args.batch, args.cpu_batch_sample))
+            out["batched_cpu_baseline"] = cpu_batch_baseline(
+                args.batch, min(args.batch, args.cpu_batch_sample))
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

@@ -351,8 +351,10 @@ def make_workload(name, repeat=0, nrhs=None, dims=None):
 BATCH_RECIPE = dict(count=2000, side_lo=16, side_hi=128, sigma=0.5, shift=1e-3, nrhs=1, cfg=4)
 
 
-def make_batch(count=None, seed=4000, side_lo=None, side_hi=None, nrhs=None):
-    """List of Problems following BATCH_RECIPE (overrides shrink it for tests)."""
+def make_batch(count=None, seed=4000, side_lo=None, side_hi=None, nrhs=None, members=None):
+    """List of Problems following BATCH_RECIPE (overrides shrink it for tests).
+    `members` (indices into the batch) builds only those matrices, each the
+    same as in the whole batch."""
     r = BATCH_RECIPE
     count = r["count"] if count is None else count
     lo = r["side_lo"] if side_lo is None else side_lo
@@ -360,8 +362,9 @@ def make_batch(count=None, seed=4000, side_lo=None, side_hi=None, nrhs=None):
     nrhs = r["nrhs"] if nrhs is None else nrhs
     rng = np.random.Generator(np.random.PCG64(seed))
     sides = rng.integers(lo, hi + 1, size=count)
-    return [make_grid_problem("lap", (int(sd), int(sd)), seed + 1 + k, sigma=r["sigma"],
-                              shift=r["shift"], nrhs=nrhs) for k, sd in enumerate(sides)]
+    ks = range(count) if members is None else members
+    return [make_grid_problem("lap", (int(sides[k]), int(sides[k])), seed + 1 + k,
+                              sigma=r["sigma"], shift=r["shift"], nrhs=nrhs) for k in ks]
 
 
 def stack_batch(probs):

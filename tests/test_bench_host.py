@@ -1,0 +1,59 @@
+"""Host-side parts of bench.py: the one-GPU guard, the oracle baselines and
+the committed counter summary lookup. No GPU is used."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+import bench
+from paper_1608_00044_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_batch_members_match_the_whole_batch():
+    whole = inputs.make_batch(count=7, side_lo=5, side_hi=12)
+    part = inputs.make_batch(count=7, side_lo=5, side_hi=12, members=[5, 2])
+    for k, q in zip([5, 2], part):
+        p = whole[k]
+        assert p.n == q.n
+        np.testing.assert_array_equal(p.colptr, q.colptr)
+        np.testing.assert_array_equal(p.rowind, q.rowind)
+        np.testing.assert_array_equal(p.perm, q.perm)
+        np.testing.assert_array_equal(p.values, q.values)
+        np.testing.assert_array_equal(p.rhs, q.rhs)
+
+
+def test_cpu_batch_baseline_small_sample():
+    r = bench.cpu_batch_baseline(2000, 6, max_workers=3)
+    assert r["kind"] == "oracle" and r["unit"] == "matrices/s"
+    assert r["cores"] == 3
+    assert r["makespan_s"] <= r["one_core_sum_s"]
+    assert r["value"] >= r["one_core_matrices_per_s"]
+    assert r["factor_flops_F"] > 0
+
+
+def test_cpu_baseline_restores_affinity():
+    if not hasattr(os, "sched_getaffinity"):
+        return
+    before = os.sched_getaffinity(0)
+    r = bench.cpu_baseline("lap2d_5pt_64", (16, 16))
+    assert os.sched_getaffinity(0) == before
+    assert r["cores"] == 1 and r["value"] > 0
+
+
+def test_measured_traffic_follows_the_source():
+    assert bench.measured_traffic("k_update", "no_such_workload") is None
+    path = os.path.join(ROOT, "profiles", "k_update_traffic_lap3d_7pt_64.txt")
+    if os.path.exists(path):
+        t = bench.measured_traffic("k_update", "lap3d_7pt_64")
+        # present only while the summary's source hash matches the kernel file
+        assert t is None or t > 0
