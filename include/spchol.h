@@ -81,6 +81,9 @@ typedef struct spc_options {
     int32_t precision;        /* 0 = FP64 factor (default); 1 = FP32 factor on FP32
                                  matrix cores with FP32 accumulation, for use with
                                  spc_solve_refine (FP64 iterative refinement)     */
+    int32_t threads;          /* host threads of spc_analyze_batch (matrices are
+                                 analysed side by side); 0 = default: the host's
+                                 hardware threads, at most 16                     */
 } spc_options;
 
 typedef struct spc_symbolic spc_symbolic;
@@ -127,7 +130,10 @@ spc_status spc_symbolic_info_get(const spc_symbolic* sym, spc_symbolic_info* inf
  * matrices' value arrays one after the other; right-hand sides and solutions
  * are the matrices' blocks stacked by rows.  spc_solve_refine measures and
  * meets tol for every matrix separately (berr: count values per column).
- * Every matrix is validated as by spc_analyze. */
+ * Every matrix is validated as by spc_analyze; the first failing one (in
+ * order) gives the status.  The matrices are analysed on up to opt->threads
+ * host threads and the results joined; the handle is the same, field by
+ * field, as spc_analyze of the block-diagonal matrix, whatever the count. */
 spc_status spc_analyze_batch(int32_t count, const int64_t* n, const int64_t* const* colptr,
                              const int32_t* const* rowind, const int32_t* const* perm,
                              const spc_options* opt, spc_symbolic** out);

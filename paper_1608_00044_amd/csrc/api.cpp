@@ -5,6 +5,7 @@
 #include <climits>
 #include <cstring>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "../../include/spchol.h"
@@ -52,6 +53,45 @@ void release_numeric(spc_numeric* num) {
     }
 }
 
+template <class Run>
+spc_status analyze_checked(const spc_options* opt, spc_symbolic** out, Run run) {
+    if (!out) return SPC_ERR_ARG;
+    *out = nullptr;
+    spc_options o;
+    spc_default_options(&o);
+    if (opt) o = *opt;
+    if (o.sn_cap < 1 || o.sn_cap > kMaxWidth) return SPC_ERR_ARG;
+    if (o.sched < 0 || o.sched > 2) return SPC_ERR_ARG;
+    if (o.spin_limit < 0) return SPC_ERR_ARG;
+    if (!(o.amalg_ratio >= 0.0 && o.amalg_ratio <= 1.0)) return SPC_ERR_ARG;
+    if (o.mem_budget_bytes < 0) return SPC_ERR_ARG;
+    if (o.precision != 0 && o.precision != 1) return SPC_ERR_ARG;
+    if (o.threads < 0) return SPC_ERR_ARG;
+    spc_symbolic* h = new (std::nothrow) spc_symbolic();
+    if (!h) return SPC_ERR_OOM;
+    Options so;
+    so.sn_cap = o.sn_cap;
+    so.amalg_ratio = o.amalg_ratio;
+    so.sched = o.sched;
+    so.spin_limit = o.spin_limit;
+    so.debug_flags = o.debug_flags;
+    so.precision = o.precision;
+    int32_t st;
+    try {
+        st = run(so, o.threads, &h->S);
+        if (st == OK) h->plan_bytes_estimate = plan_bytes(h->S);
+    } catch (const std::bad_alloc&) {
+        st = SPC_ERR_OOM;
+    }
+    if (st != OK) {
+        delete h;
+        return st;
+    }
+    h->budget = o.mem_budget_bytes;
+    *out = h;
+    return SPC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -65,6 +105,7 @@ void spc_default_options(spc_options* opt) {
     opt->spin_limit = 0;
     opt->debug_flags = 0;
     opt->precision = 0;
+    opt->threads = 0;
 }
 
 const char* spc_status_string(spc_status st) {
@@ -83,51 +124,11 @@ const char* spc_status_string(spc_status st) {
     }
 }
 
-static spc_status analyze_checked(int64_t n, const int64_t* colptr, const int32_t* rowind,
-                                  const int32_t* perm, const spc_options* opt,
-                                  const std::vector<int64_t>* batch, spc_symbolic** out) {
-    if (!out) return SPC_ERR_ARG;
-    *out = nullptr;
-    spc_options o;
-    spc_default_options(&o);
-    if (opt) o = *opt;
-    if (o.sn_cap < 1 || o.sn_cap > kMaxWidth) return SPC_ERR_ARG;
-    if (o.sched < 0 || o.sched > 2) return SPC_ERR_ARG;
-    if (o.spin_limit < 0) return SPC_ERR_ARG;
-    if (!(o.amalg_ratio >= 0.0 && o.amalg_ratio <= 1.0)) return SPC_ERR_ARG;
-    if (o.mem_budget_bytes < 0) return SPC_ERR_ARG;
-    if (o.precision != 0 && o.precision != 1) return SPC_ERR_ARG;
-    spc_symbolic* h = new (std::nothrow) spc_symbolic();
-    if (!h) return SPC_ERR_OOM;
-    Options so;
-    so.sn_cap = o.sn_cap;
-    so.amalg_ratio = o.amalg_ratio;
-    so.sched = o.sched;
-    so.spin_limit = o.spin_limit;
-    so.debug_flags = o.debug_flags;
-    so.precision = o.precision;
-    int32_t st;
-    try {
-        st = analyze(n, colptr, rowind, perm, so, &h->S);
-        if (st == OK) {
-            if (batch) h->S.batch_ptr = *batch;
-            h->plan_bytes_estimate = plan_bytes(h->S);
-        }
-    } catch (const std::bad_alloc&) {
-        st = SPC_ERR_OOM;
-    }
-    if (st != OK) {
-        delete h;
-        return st;
-    }
-    h->budget = o.mem_budget_bytes;
-    *out = h;
-    return SPC_OK;
-}
-
 spc_status spc_analyze(int64_t n, const int64_t* colptr, const int32_t* rowind,
                        const int32_t* perm, const spc_options* opt, spc_symbolic** out) {
-    return analyze_checked(n, colptr, rowind, perm, opt, nullptr, out);
+    return analyze_checked(opt, out, [&](const Options& so, int, Symbolic* S) {
+        return analyze(n, colptr, rowind, perm, so, S);
+    });
 }
 
 spc_status spc_analyze_batch(int32_t count, const int64_t* n, const int64_t* const* colptr,
@@ -136,32 +137,16 @@ spc_status spc_analyze_batch(int32_t count, const int64_t* n, const int64_t* con
     if (!out) return SPC_ERR_ARG;
     *out = nullptr;
     if (count < 0 || (count > 0 && (!n || !colptr || !rowind))) return SPC_ERR_ARG;
-    std::vector<int64_t> rows(1, 0), ents(1, 0);
+    int64_t rows = 0;
     for (int32_t k = 0; k < count; ++k) {
-        const int32_t st = validate_input(n[k], colptr[k], rowind[k], perm ? perm[k] : nullptr);
-        if (st != OK) return st;
-        rows.push_back(rows.back() + n[k]);
-        ents.push_back(ents.back() + (n[k] ? colptr[k][n[k]] : 0));
-        if (rows.back() > INT32_MAX - 1) return SPC_ERR_ARG;
+        if (n[k] < 0 || n[k] > INT32_MAX - 1 - rows) return SPC_ERR_ARG;
+        rows += n[k];
     }
-    const int64_t N = rows.back();
-    std::vector<int64_t> cp((size_t)N + 1, 0);
-    std::vector<int32_t> ri((size_t)std::max<int64_t>(ents.back(), 1));
-    std::vector<int32_t> pm((size_t)std::max<int64_t>(N, 1));
-    try {
-        for (int32_t k = 0; k < count; ++k) {
-            const int64_t o = rows[k], e = ents[k];
-            for (int64_t j = 0; j < n[k]; ++j) {
-                cp[o + j + 1] = e + colptr[k][j + 1];
-                for (int64_t q = colptr[k][j]; q < colptr[k][j + 1]; ++q)
-                    ri[e + q] = (int32_t)(rowind[k][q] + o);
-                pm[o + j] = (int32_t)(o + (perm && perm[k] ? perm[k][j] : j));
-            }
-        }
-    } catch (const std::bad_alloc&) {
-        return SPC_ERR_OOM;
-    }
-    return analyze_checked(N, cp.data(), ri.data(), pm.data(), opt, &rows, out);
+    return analyze_checked(opt, out, [&](const Options& so, int threads, Symbolic* S) {
+        if (threads == 0)
+            threads = (int)std::min<unsigned>(16, std::max(1u, std::thread::hardware_concurrency()));
+        return analyze_batch(count, n, colptr, rowind, perm, so, threads, S);
+    });
 }
 
 spc_status spc_symbolic_info_get(const spc_symbolic* sym, spc_symbolic_info* info) {

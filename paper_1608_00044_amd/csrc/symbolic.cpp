@@ -10,7 +10,11 @@
 
 #include <algorithm>
 #include <cstring>
+#include <functional>
+#include <new>
 #include <numeric>
+#include <system_error>
+#include <thread>
 
 namespace spc {
 
@@ -456,6 +460,159 @@ int32_t analyze(int64_t n, const int64_t* colptr, const int32_t* rowind, const i
     if ((st = slots(S)) != OK) return st;
     if ((st = pairs(S)) != OK) return st;
     levels(S);
+    return OK;
+}
+
+namespace {
+
+// Where member B of a batch goes in the joined analysis: its first row and
+// column, input entry, supernode, row-list entry, pair, relative index and
+// arena element.
+struct MemberOffsets {
+    int64_t o = 0, e = 0, s = 0, r = 0, p = 0, rel = 0, arena = 0;
+};
+
+// Writes member analysis B into its slices of the joined analysis A (sized
+// beforehand).  Every index of B moves by the matching offset; relative
+// indices and segment bounds are local to a supernode and stay.
+void place_member(Symbolic& A, const Symbolic& B, const MemberOffsets& m) {
+    const auto shift = [](int32_t* dst, const std::vector<int32_t>& src, int64_t by,
+                          bool keep_neg) {
+        for (size_t k = 0; k < src.size(); ++k)
+            dst[k] = keep_neg && src[k] < 0 ? src[k] : (int32_t)(src[k] + by);
+    };
+    shift(A.perm.data() + m.o, B.perm, m.o, false);
+    for (int64_t j = 0; j < B.n; ++j) A.Cp[m.o + j + 1] = m.e + B.Cp[j + 1];
+    shift(A.Ci.data() + m.e, B.Ci, m.o, false);
+    for (int64_t q = 0; q < B.nnz_a; ++q) {
+        A.amap[m.e + q] = m.e + B.amap[q];
+        A.slot[m.e + q] = m.arena + B.slot[q];
+    }
+    shift(A.parent.data() + m.o, B.parent, m.o, true);
+    std::copy(B.colcount.begin(), B.colcount.end(), A.colcount.begin() + m.o);
+    shift(A.post.data() + m.o, B.post, m.o, false);
+    shift(A.col_owner.data() + m.o, B.col_owner, m.s, false);
+    for (int64_t s = 0; s < B.nsup; ++s) {
+        A.sn_ptr[m.s + s + 1] = (int32_t)(m.o + B.sn_ptr[s + 1]);
+        A.rowptr[m.s + s + 1] = m.r + B.rowptr[s + 1];
+        A.pair_ptr[m.s + s + 1] = m.p + B.pair_ptr[s + 1];
+        A.off[m.s + s] = m.arena + B.off[s];
+    }
+    shift(A.sn_parent.data() + m.s, B.sn_parent, m.s, true);
+    std::copy(B.ld.begin(), B.ld.end(), A.ld.begin() + m.s);
+    std::copy(B.level.begin(), B.level.end(), A.level.begin() + m.s);
+    shift(A.rows.data() + m.r, B.rows, m.o, false);
+    for (size_t k = 0; k < B.pairs.size(); ++k) {
+        Pair p = B.pairs[k];
+        p.src += (int32_t)m.s;
+        p.tgt += (int32_t)m.s;
+        p.rel_off += m.rel;
+        A.pairs[m.p + k] = p;
+    }
+    std::copy(B.rel.begin(), B.rel.end(), A.rel.begin() + m.rel);
+}
+
+// Runs fn(k) for k in [0, count) on up to nt threads (member k on thread
+// k mod nt); where a thread cannot be started its members run on the caller.
+template <class Fn>
+void for_members(int32_t count, int nt, Fn fn) {
+    auto work = [&](int t) {
+        for (int32_t k = t; k < count; k += nt) fn(k);
+    };
+    std::vector<std::thread> pool;
+    int started = 1;
+    try {
+        for (; started < nt; ++started) pool.emplace_back(work, started);
+    } catch (const std::system_error&) {
+    }
+    for (int t = started; t < nt; ++t) work(t);
+    work(0);
+    for (auto& th : pool) th.join();
+}
+
+}  // namespace
+
+int32_t analyze_batch(int32_t count, const int64_t* n, const int64_t* const* colptr,
+                      const int32_t* const* rowind, const int32_t* const* perm,
+                      const Options& opt, int threads, Symbolic* out) {
+    if (!out || count < 0) return ERR_ARG;
+    std::vector<Symbolic> part((size_t)count);
+    std::vector<int32_t> st((size_t)count, OK);
+    const int nt = std::max(1, std::min<int>(threads, count));
+    for_members(count, nt, [&](int32_t k) {
+        try {
+            st[k] = analyze(n[k], colptr[k], rowind[k], perm ? perm[k] : nullptr, opt, &part[k]);
+        } catch (const std::bad_alloc&) {
+            st[k] = ERR_OOM;
+        }
+    });
+    for (int32_t k = 0; k < count; ++k)
+        if (st[k] != OK) return st[k];
+    Symbolic& A = *out;
+    A = Symbolic();
+    A.opt = opt;
+    std::vector<MemberOffsets> at((size_t)count + 1);
+    int32_t nl = 0;
+    A.batch_ptr.assign(1, 0);
+    for (int32_t k = 0; k < count; ++k) {
+        const Symbolic& B = part[k];
+        MemberOffsets m = at[k];
+        m.o += B.n;
+        m.e += B.nnz_a;
+        m.s += B.nsup;
+        m.r += (int64_t)B.rows.size();
+        m.p += (int64_t)B.pairs.size();
+        m.rel += (int64_t)B.rel.size();
+        m.arena += B.arena;
+        at[k + 1] = m;
+        A.batch_ptr.push_back(m.o);
+        A.nnz_l += B.nnz_l;
+        A.flops += B.flops;
+        A.nnz_stored += B.nnz_stored;
+        A.flops_stored += B.flops_stored;
+        A.max_w = std::max(A.max_w, B.max_w);
+        A.max_r = std::max(A.max_r, B.max_r);
+        nl = std::max<int32_t>(nl, (int32_t)B.level_ptr.size() - 1);
+    }
+    const MemberOffsets& T = at[count];
+    A.n = T.o;
+    A.nnz_a = T.e;
+    A.nsup = T.s;
+    A.arena = T.arena;
+    const size_t N = (size_t)T.o, E = (size_t)T.e, NS = (size_t)T.s;
+    // the joined arrays are sized side by side: their first touch (zero fill
+    // and page faults) costs more than the copy that follows
+    const std::function<void()> sizing[] = {
+        [&] { A.perm.resize(N); }, [&] { A.Cp.assign(N + 1, 0); }, [&] { A.Ci.resize(E); },
+        [&] { A.amap.resize(E); }, [&] { A.slot.resize(E); }, [&] { A.parent.resize(N); },
+        [&] { A.colcount.resize(N); }, [&] { A.post.resize(N); },
+        [&] { A.col_owner.resize(N); }, [&] { A.sn_ptr.assign(NS + 1, 0); },
+        [&] { A.rowptr.assign(NS + 1, 0); }, [&] { A.pair_ptr.assign(NS + 1, 0); },
+        [&] { A.off.resize(NS); }, [&] { A.sn_parent.resize(NS); }, [&] { A.ld.resize(NS); },
+        [&] { A.level.resize(NS); }, [&] { A.rows.resize((size_t)T.r); },
+        [&] { A.pairs.resize((size_t)T.p); }, [&] { A.rel.resize((size_t)T.rel); }};
+    const int32_t nsizing = (int32_t)(sizeof(sizing) / sizeof(sizing[0]));
+    std::vector<int32_t> oom((size_t)nsizing, 0);
+    for_members(nsizing, std::min<int>(nt, nsizing), [&](int32_t k) {
+        try {
+            sizing[k]();
+        } catch (const std::bad_alloc&) {
+            oom[k] = 1;
+        }
+    });
+    if (std::find(oom.begin(), oom.end(), 1) != oom.end()) return ERR_OOM;
+    for_members(count, nt, [&](int32_t k) {
+        place_member(A, part[k], at[k]);
+        part[k] = Symbolic();
+    });
+    // level sets: level l of the whole holds every member's level l, members
+    // in order, each member's supernodes already increasing
+    A.level_ptr.assign((size_t)nl + 1, 0);
+    for (int32_t lv : A.level) A.level_ptr[lv + 1]++;
+    for (int32_t l = 0; l < nl; ++l) A.level_ptr[l + 1] += A.level_ptr[l];
+    A.level_sn.resize(NS);
+    std::vector<int32_t> fill(A.level_ptr.begin(), A.level_ptr.end() - 1);
+    for (size_t s = 0; s < NS; ++s) A.level_sn[fill[A.level[s]]++] = (int32_t)s;
     return OK;
 }
 

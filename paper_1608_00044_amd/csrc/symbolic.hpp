@@ -93,4 +93,13 @@ int32_t validate_input(int64_t n, const int64_t* colptr, const int32_t* rowind,
 int32_t analyze(int64_t n, const int64_t* colptr, const int32_t* rowind, const int32_t* perm,
                 const Options& opt, Symbolic* out);
 
+// Batched analysis of `count` independent matrices: each analysed alone, up
+// to `threads` host threads at a time, then joined into the analysis of their
+// block-diagonal direct sum (matrix k at rows and columns [o_k, o_k + n[k])),
+// identical, field by field, to analysing that matrix whole, with
+// batch_ptr = {o_0, ..., o_count}.  Inputs must have passed validate_input.
+int32_t analyze_batch(int32_t count, const int64_t* n, const int64_t* const* colptr,
+                      const int32_t* const* rowind, const int32_t* const* perm,
+                      const Options& opt, int threads, Symbolic* out);
+
 }  // namespace spc

@@ -1,6 +1,7 @@
 """Host logic of the HIP library, on the CPU: the C ABI loads and exports every
 declared symbol, argument checks, and the symbolic analysis matches the
 oracle's bit for bit."""
+import dataclasses
 import os
 import re
 
@@ -249,6 +250,43 @@ def test_batch_analysis_is_the_union_of_single_analyses():
         off += p.n
         s_at += ns1
     assert s_at == inf["nsup"] and inf["flops"] == flops
+
+
+def _whole_analysis_fields(sym):
+    inf = sym.info()
+    inf.pop("nbatch")
+    out = {"info": inf}
+    out["parent"], out["cc"], out["sn"], out["snpar"] = sym.export()
+    out["rowptr"], out["rows"] = sym.rows()
+    for k, v in sym.pairs().items():
+        out["pair_" + k] = v
+    out["tasks"], out["cnt0"] = sym.tasks(8)
+    return out
+
+
+def test_batch_analysis_equals_the_block_diagonal_analysis():
+    """The batched analysis (members analysed alone on several threads, then
+    joined) gives exactly what the analysis of the block-diagonal matrix gives
+    whole, on every export, for any thread count (empty members included)."""
+    probs = inputs.make_batch(count=9, side_lo=3, side_hi=19)
+    probs.insert(2, inputs.random_spd_pattern(60, 0.08, seed=5))
+    probs.insert(4, inputs.tridiag(1))
+    mats = [(p.n, p.colptr, p.rowind, p.perm) for p in probs]
+    mats.insert(6, (0, np.zeros(1, dtype=np.int64), np.zeros(0, dtype=np.int32), None))
+    whole = inputs.block_diagonal([dataclasses.replace(p, rhs=None) for p in probs])
+    for ratio, cap in ((0.0, 150), (0.2, 7)):
+        ref = spchol.analyze(whole.n, whole.colptr, whole.rowind, whole.perm, sn_cap=cap,
+                             amalg_ratio=ratio, sched=2)
+        want = _whole_analysis_fields(ref)
+        for threads in (1, 3, 0):
+            bs = spchol.analyze_batch(mats, sn_cap=cap, amalg_ratio=ratio, sched=2,
+                                      threads=threads)
+            assert bs.info()["nbatch"] == len(mats)
+            got = _whole_analysis_fields(bs)
+            assert got["info"] == want["info"]
+            for k in want:
+                if k != "info":
+                    assert np.array_equal(got[k], want[k]), (k, ratio, threads)
 
 
 def test_batch_rejects_bad_member():
