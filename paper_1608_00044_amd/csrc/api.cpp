@@ -143,8 +143,10 @@ spc_status spc_analyze_batch(int32_t count, const int64_t* n, const int64_t* con
         rows += n[k];
     }
     return analyze_checked(opt, out, [&](const Options& so, int threads, Symbolic* S) {
-        if (threads == 0)
-            threads = (int)std::min<unsigned>(16, std::max(1u, std::thread::hardware_concurrency()));
+        if (threads == 0) {
+            const unsigned hw = std::thread::hardware_concurrency();
+            threads = (int)std::min<unsigned>(16, std::max(1u, hw));
+        }
         return analyze_batch(count, n, colptr, rowind, perm, so, threads, S);
     });
 }
