@@ -236,25 +236,31 @@ def mixed_precision(name, steps, warmup, tol=1e-10):
     return out
 
 
-def batched(count, steps, precision, tol=1e-10):
-    """Batch of independent 2D Laplacians (BATCH_RECIPE): one batched analysis,
-    then timed steps of factorization + one-RHS solve (FP64) or factorization
-    + refinement to tol (FP32)."""
+def batched(count, steps, precision, tol=1e-10, tune_options=True):
+    """Batch of independent 2D Laplacians (BATCH_RECIPE): the analysis options
+    tuned on this batch (amalgamation ratio, cap), one batched analysis, then
+    timed steps of factorization + one-RHS solve (FP64) or factorization +
+    refinement to tol (FP32)."""
     import torch
 
-    from paper_1608_00044_amd import inputs, spchol
+    from paper_1608_00044_amd import inputs, spchol, tune
 
     t0 = time.perf_counter()
     probs = inputs.make_batch(count=count)
     gen_s = time.perf_counter() - t0
     vals_h, rhs_h = inputs.stack_batch(probs)
-    t0 = time.perf_counter()
-    sym = spchol.analyze_batch([(p.n, p.colptr, p.rowind, p.perm) for p in probs], sn_cap=150,
-                               amalg_ratio=0.0, precision=precision)
-    an_ms = (time.perf_counter() - t0) * 1e3
-    inf = sym.info()
+    mats = [(p.n, p.colptr, p.rowind, p.perm) for p in probs]
     vals = torch.from_numpy(vals_h).to("cuda:0")
     b = torch.from_numpy(np.ascontiguousarray(rhs_h)).to("cuda:0")
+    opts, table = dict(amalg_ratio=0.0, sn_cap=150), None
+    if tune_options:
+        t0 = time.perf_counter()
+        opts, table = tune.tune_batch(mats, vals, b, precision)
+        log("batch tuning (%.1f s): %s" % (time.perf_counter() - t0, opts))
+    t0 = time.perf_counter()
+    sym = spchol.analyze_batch(mats, precision=precision, **opts)
+    an_ms = (time.perf_counter() - t0) * 1e3
+    inf = sym.info()
     num = spchol.factor(sym, vals)
     if num.status() != 0:
         raise RuntimeError("batched factor status %d" % num.status())
@@ -289,7 +295,12 @@ def batched(count, steps, precision, tol=1e-10):
            "factor_gflops": inf["flops"] / (fm * 1e-3) / 1e9, "solve_ms": sm,
            "matrices_per_s": count / ((fm + sm) * 1e-3),
            "backward_error_first50": worst,
-           "launches": "level-set launches over all matrices at once"}
+           "launches": "level-set launches over all matrices at once",
+           "options": opts}
+    if table is not None:
+        out["tuning"] = [{"amalg_ratio": t["options"]["amalg_ratio"],
+                          "sn_cap": t["options"]["sn_cap"], "ms": t["ms"], "nsup": t["nsup"],
+                          "levels": t["levels"]} for t in table]
     if precision == 1:
         out["refine_iters"] = float(np.mean(iters))
     log("batch %s: factor %.2f ms (%.1f GFLOP/s), solve %.2f ms, %.0f matrices/s" %
@@ -395,6 +406,9 @@ def main():
     ap.add_argument("--mixed-steps", type=int, default=3)
     ap.add_argument("--batch", type=int, default=2000,
                     help="matrices of the batched workload (0 to skip)")
+    ap.add_argument("--no-batch-tune", action="store_true",
+                    help="batched workload with the default options (no amalgamation) "
+                         "instead of the tuned ones")
     ap.add_argument("--serve-requests", type=int, default=1000,
                     help="requests of the serving stream (0 to skip)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -557,7 +571,9 @@ def main():
     if args.mixed_workload:
         out["mixed_precision"] = mixed_precision(args.mixed_workload, args.mixed_steps, 1)
     if args.batch:
-        out["batched"] = [batched(args.batch, 3, 0), batched(args.batch, 3, 1)]
+        tb = not args.no_batch_tune
+        out["batched"] = [batched(args.batch, 3, 0, tune_options=tb),
+                          batched(args.batch, 3, 1, tune_options=tb)]
     if args.serve_requests:
         out["serving"] = serving(args.serve_requests)
     if not args.no_cpu_baseline:

@@ -1,0 +1,113 @@
+"""Autotuner for batched factorization.
+
+A batch of many small matrices is latency bound: one factorization is one
+launch per kernel class per level of the batch's elimination forest, and
+its cost follows the number of levels and of supernodes more than the flop
+count.  The relaxed-amalgamation ratio (explicit zeros traded for fewer,
+wider supernodes and fewer levels) and the supernode cap move both, and the
+best setting depends on the matrices' size and sparsity.  The tuner times
+each candidate option set on the GPU, one factorization plus one solve (FP64)
+or one refined solve (FP32 factor), all through the library's own entry
+points, and keeps the fastest.  Choices are cached in a JSON file keyed by a
+size class of the batch (precision, count, mean order and mean entries per
+column, each rounded to a coarse class), so later batches of the same class
+reuse them without timing again.
+
+Every candidate computes the same factorization of the same matrices; only
+the supernode partition (and so the explicit zeros stored) differs.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+CANDIDATES = tuple(dict(amalg_ratio=r, sn_cap=150) for r in (0.0, 0.05, 0.1, 0.2, 0.3, 0.5)) \
+    + (dict(amalg_ratio=0.3, sn_cap=64),)
+
+
+def size_class(mats, precision: int) -> str:
+    """Cache key of a batch: precision, count (power of two), mean order
+    (power of two) and mean stored lower entries per column (halves)."""
+    count = len(mats)
+    n = sum(int(m[0]) for m in mats)
+    nnz = sum(int(m[1][int(m[0])]) for m in mats if int(m[0]) > 0)
+    pow2 = (lambda v: 0 if v < 1 else 1 << int(round(math.log2(v))))
+    deg = round(2.0 * nnz / n) / 2.0 if n else 0.0
+    return "p%d-count%d-n%d-deg%g" % (precision, pow2(count), pow2(n / max(count, 1)), deg)
+
+
+def measure(mats, values, rhs, precision, opts, steps=2, tol=1e-10):
+    """Mean ms of factorization + solve (FP64) or factorization + refined
+    solve to `tol` (FP32) on the current GPU, after one untimed step that
+    builds the plan and captures the graphs.  `values` and `rhs` are device
+    tensors (rhs one column per matrix, stacked)."""
+    import torch
+
+    from . import spchol
+
+    sym = spchol.analyze_batch(mats, precision=precision, **opts)
+    inf = sym.info()
+    num = spchol.factor(sym, values)
+    try:
+        if num.status() != 0:
+            raise spchol.SpcError(num.status(), "spc_factor")
+        x = None
+        ms = []
+        for k in range(steps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            num.refactor(values)
+            if precision == 0:
+                x = num.solve(rhs, x=x)
+            else:
+                x, _, _ = num.solve_refine(rhs, x=x, tol=tol, max_iter=20)
+            torch.cuda.synchronize()
+            if k > 0:
+                ms.append((time.perf_counter() - t0) * 1e3)
+        return {"ms": sum(ms) / len(ms), "nsup": inf["nsup"], "levels": inf["nlevels"],
+                "flops_stored": inf["flops_stored"]}
+    finally:
+        num.free()
+        sym.free()
+
+
+def _load(path):
+    if not path or not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        data = json.load(f)
+    return data if isinstance(data, dict) else {}
+
+
+def _store(path, data):
+    d = os.path.dirname(os.path.abspath(path))
+    os.makedirs(d, exist_ok=True)
+    tmp = "%s.tmp%d" % (path, os.getpid())
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def tune_batch(mats, values, rhs, precision=0, candidates=CANDIDATES, cache_path=None,
+               steps=2, timer=measure):
+    """Options (a dict for spchol.analyze_batch) that minimise factorization +
+    solve time for this batch, and the table of what each candidate measured.
+    A cached choice for the batch's size class is returned without timing
+    (table None); otherwise every candidate is timed with `timer` and, when
+    `cache_path` is given, the winner is stored there."""
+    key = size_class(mats, precision)
+    cached = _load(cache_path).get(key)
+    if cached is not None:
+        return dict(cached["options"]), None
+    table = []
+    for opts in candidates:
+        r = timer(mats, values, rhs, precision, dict(opts), steps=steps)
+        table.append(dict(options=dict(opts), **r))
+    best = min(table, key=lambda t: t["ms"])
+    if cache_path:
+        data = _load(cache_path)
+        data[key] = {"options": best["options"], "ms": best["ms"], "table": table}
+        _store(cache_path, data)
+    return dict(best["options"]), table

@@ -88,3 +88,44 @@ def test_batch_fp32_refined_per_matrix(sched):
         np.testing.assert_allclose(berr[k, 0], eta[0], rtol=0.05, atol=1e-14)
         off += p.n
     say("batch fp32 refine iters", iters, "max eta", berr.max())
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_tuned_batch_options(precision, tmp_path):
+    """The autotuner times its candidates through the library on the GPU; the
+    options it returns (and caches) factor the batch to the same bars."""
+    from paper_1608_00044_amd import tune
+
+    torch = torch_dev()
+    probs = inputs.make_batch(count=40, seed=91 + precision, side_lo=6, side_hi=48)
+    mats = [(p.n, p.colptr, p.rowind, p.perm) for p in probs]
+    vals, rhs = inputs.stack_batch(probs)
+    v = torch.from_numpy(vals).to("cuda:0")
+    b = torch.from_numpy(np.ascontiguousarray(rhs)).to("cuda:0")
+    cands = (dict(amalg_ratio=0.0, sn_cap=150), dict(amalg_ratio=0.3, sn_cap=150),
+             dict(amalg_ratio=0.3, sn_cap=16))
+    path = str(tmp_path / "tune.json")
+    opts, table = tune.tune_batch(mats, v, b, precision, cands, path, steps=1)
+    say("tuning", [(t["options"], round(t["ms"], 3), t["nsup"], t["levels"]) for t in table])
+    assert opts in [dict(c) for c in cands] and len(table) == 3
+    assert all(t["ms"] > 0 for t in table)
+    assert table[1]["nsup"] < table[0]["nsup"]  # amalgamation merged supernodes
+    assert tune.tune_batch(mats, v, b, precision, cands, path)[0] == opts
+    sym, num, _ = _factor_batch(probs, precision=precision, cap=opts["sn_cap"],
+                                ratio=opts["amalg_ratio"])
+    assert num.status() == 0
+    if precision == 0:
+        x = num.solve(b).cpu().numpy()
+        bar = 1e-14
+    else:
+        x, _, _ = num.solve_refine(b, tol=1e-10, max_iter=20)
+        x = x.cpu().numpy()
+        bar = 1e-10
+    off = 0
+    for p in probs:
+        eta = oracle.backward_error(p.n, p.colptr, p.rowind, p.values, p.rhs,
+                                    x[off:off + p.n].reshape(-1, 1))
+        assert eta.max() <= bar
+        off += p.n
+    num.free()
+    sym.free()
