@@ -544,6 +544,8 @@ int32_t analyze_batch(int32_t count, const int64_t* n, const int64_t* const* col
             st[k] = analyze(n[k], colptr[k], rowind[k], perm ? perm[k] : nullptr, opt, &part[k]);
         } catch (const std::bad_alloc&) {
             st[k] = ERR_OOM;
+        } catch (...) {  // nothing may leave a worker thread
+            st[k] = ERR_ARG;
         }
     });
     for (int32_t k = 0; k < count; ++k)
@@ -596,7 +598,7 @@ int32_t analyze_batch(int32_t count, const int64_t* n, const int64_t* const* col
     for_members(nsizing, std::min<int>(nt, nsizing), [&](int32_t k) {
         try {
             sizing[k]();
-        } catch (const std::bad_alloc&) {
+        } catch (...) {  // bad_alloc or length_error: either way the join cannot be held
             oom[k] = 1;
         }
     });
