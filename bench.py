@@ -252,7 +252,7 @@ def batched(count, steps, precision, tol=1e-10, tune_options=True):
     mats = [(p.n, p.colptr, p.rowind, p.perm) for p in probs]
     vals = torch.from_numpy(vals_h).to("cuda:0")
     b = torch.from_numpy(np.ascontiguousarray(rhs_h)).to("cuda:0")
-    opts, table = dict(amalg_ratio=0.0, sn_cap=150), None
+    opts, table = dict(tune.BASE), None
     if tune_options:
         t0 = time.perf_counter()
         opts, table = tune.tune_batch(mats, vals, b, precision)
@@ -298,9 +298,8 @@ def batched(count, steps, precision, tol=1e-10, tune_options=True):
            "launches": "level-set launches over all matrices at once",
            "options": opts}
     if table is not None:
-        out["tuning"] = [{"amalg_ratio": t["options"]["amalg_ratio"],
-                          "sn_cap": t["options"]["sn_cap"], "ms": t["ms"], "nsup": t["nsup"],
-                          "levels": t["levels"]} for t in table]
+        out["tuning"] = [dict(t["options"], stage=t["stage"], ms=t["ms"], nsup=t["nsup"],
+                              levels=t["levels"]) for t in table]
     if precision == 1:
         out["refine_iters"] = float(np.mean(iters))
     log("batch %s: factor %.2f ms (%.1f GFLOP/s), solve %.2f ms, %.0f matrices/s" %

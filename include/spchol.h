@@ -84,6 +84,12 @@ typedef struct spc_options {
     int32_t threads;          /* host threads of spc_analyze_batch (matrices are
                                  analysed side by side); 0 = default: the host's
                                  hardware threads, at most 16                     */
+    int32_t small_w;          /* level-set schedules: supernodes of at most small_w
+                                 columns and small_r rows below the diagonal block
+                                 are factored and solved by a lane group each, the
+                                 others by workgroup kernels on 64 x 64 tiles.
+                                 small_w 1..16, or -1 for none; 0 = default (16) */
+    int32_t small_r;          /* 1..64; 0 = default (64)                           */
 } spc_options;
 
 typedef struct spc_symbolic spc_symbolic;
@@ -108,7 +114,8 @@ typedef struct spc_symbolic_info {
 } spc_symbolic_info;
 
 /* Fills *opt with the defaults (sn_cap 150, sched 0, no amalgamation, no budget,
- * default spin limit, no debug flags). */
+ * default spin limit, no debug flags, default threads and small-supernode
+ * limits). */
 void spc_default_options(spc_options* opt);
 
 /* Symbolic analysis on the host (no device work).  colptr/rowind/perm are

@@ -67,6 +67,8 @@ spc_status analyze_checked(const spc_options* opt, spc_symbolic** out, Run run) 
     if (o.mem_budget_bytes < 0) return SPC_ERR_ARG;
     if (o.precision != 0 && o.precision != 1) return SPC_ERR_ARG;
     if (o.threads < 0) return SPC_ERR_ARG;
+    if (o.small_w < -1 || o.small_w > kSmallW || o.small_r < 0 || o.small_r > kSmallR)
+        return SPC_ERR_ARG;
     spc_symbolic* h = new (std::nothrow) spc_symbolic();
     if (!h) return SPC_ERR_OOM;
     Options so;
@@ -76,6 +78,8 @@ spc_status analyze_checked(const spc_options* opt, spc_symbolic** out, Run run) 
     so.spin_limit = o.spin_limit;
     so.debug_flags = o.debug_flags;
     so.precision = o.precision;
+    so.small_w = o.small_w == 0 ? kSmallW : (o.small_w < 0 ? 0 : o.small_w);
+    so.small_r = o.small_r == 0 ? kSmallR : o.small_r;
     int32_t st;
     try {
         st = run(so, o.threads, &h->S);
@@ -106,6 +110,8 @@ void spc_default_options(spc_options* opt) {
     opt->debug_flags = 0;
     opt->precision = 0;
     opt->threads = 0;
+    opt->small_w = 0;
+    opt->small_r = 0;
 }
 
 const char* spc_status_string(spc_status st) {

@@ -20,12 +20,14 @@ constexpr int kMaxWidth = 150;
 // Column panel of the blocked diagonal factorization; the inverse of every
 // kPanel x kPanel diagonal block is kept for the panel and triangular solves.
 constexpr int kPanel = 16;
-// Small supernodes (at most kSmallW columns and kSmallR rows below the
-// diagonal block) are factored and solved by one wavefront each.
+// Small supernodes (at most small_w columns and small_r rows below the
+// diagonal block, analysis options bounded by kSmallW and kSmallR) are
+// factored and solved by a group of lanes each; the level-set schedules use
+// these kernels, the task queue does not.
 constexpr int kSmallW = 16;
 constexpr int kSmallR = 64;
 inline bool is_small(const Symbolic& S, int64_t s) {
-    return S.width(s) <= kSmallW && S.nbelow(s) <= kSmallR;
+    return S.width(s) <= S.opt.small_w && S.nbelow(s) <= S.opt.small_r;
 }
 // Per-supernode region of the factor's side array (dinv), for w columns:
 //   the inverses of the kPanel-column diagonal blocks, compact: every full

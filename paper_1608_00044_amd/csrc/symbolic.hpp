@@ -22,6 +22,8 @@ struct Options {
     int32_t debug_flags = 0;  // bit 0: withhold one dependency (exercises the watchdog)
     int64_t spin_limit = 0;   // bounded waits of the task-queue schedule; 0 = default
     int32_t precision = 0;    // 0: FP64 factor; 1: FP32 factor with FP64 refinement
+    int32_t small_w = 16;     // supernodes of at most small_w columns and small_r rows
+    int32_t small_r = 64;     // below run on the lane-group kernels (small_w 0: none)
 };
 
 // One (source, target) update pair: source supernode s sends its update block

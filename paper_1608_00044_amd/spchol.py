@@ -44,7 +44,8 @@ EXPORTS = ("spc_default_options", "spc_analyze", "spc_symbolic_info_get", "spc_s
 class spc_options(C.Structure):
     _fields_ = [("sn_cap", C.c_int32), ("sched", C.c_int32), ("amalg_ratio", C.c_double),
                 ("mem_budget_bytes", C.c_int64), ("spin_limit", C.c_int64),
-                ("debug_flags", C.c_int32), ("precision", C.c_int32), ("threads", C.c_int32)]
+                ("debug_flags", C.c_int32), ("precision", C.c_int32), ("threads", C.c_int32),
+                ("small_w", C.c_int32), ("small_r", C.c_int32)]
 
 
 class spc_symbolic_info(C.Structure):
@@ -195,7 +196,7 @@ def _stream_ptr(stream):
 # ---------------------------------------------------------------------------
 
 def _options(sn_cap=150, amalg_ratio=0.0, sched=0, mem_budget_bytes=0, spin_limit=0,
-             debug_flags=0, precision=0, threads=0):
+             debug_flags=0, precision=0, threads=0, small_w=0, small_r=0):
     opt = spc_options()
     lib().spc_default_options(C.byref(opt))
     opt.sn_cap = int(sn_cap)
@@ -206,6 +207,8 @@ def _options(sn_cap=150, amalg_ratio=0.0, sched=0, mem_budget_bytes=0, spin_limi
     opt.debug_flags = int(debug_flags)
     opt.precision = int(precision)
     opt.threads = int(threads)
+    opt.small_w = int(small_w)
+    opt.small_r = int(small_r)
     return opt
 
 

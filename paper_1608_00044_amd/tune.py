@@ -3,18 +3,25 @@
 A batch of many small matrices is latency bound: one factorization is one
 launch per kernel class per level of the batch's elimination forest, and
 its cost follows the number of levels and of supernodes more than the flop
-count.  The relaxed-amalgamation ratio (explicit zeros traded for fewer,
-wider supernodes and fewer levels) and the supernode cap move both, and the
-best setting depends on the matrices' size and sparsity.  The tuner times
-each candidate option set on the GPU, one factorization plus one solve (FP64)
-or one refined solve (FP32 factor), all through the library's own entry
-points, and keeps the fastest.  Choices are cached in a JSON file keyed by a
+count.  Three choices move it, and the best setting depends on the
+matrices' size and sparsity:
+- the relaxed-amalgamation ratio (explicit zeros traded for fewer, wider
+  supernodes and fewer levels);
+- the supernode cap;
+- which supernodes run on the lane-group kernels (16, 32 or 64 lanes per
+  supernode, several supernodes per wave) and which on the workgroup
+  kernels over 64 x 64 tiles (the small_w / small_r limits).
+The tuner searches them one stage at a time (each stage starting from the
+best options so far), timing every option set on the GPU through the
+library's own entry points: one factorization plus one solve (FP64) or one
+refined solve (FP32 factor).  Choices are cached in a JSON file keyed by a
 size class of the batch (precision, count, mean order and mean entries per
 column, each rounded to a coarse class), so later batches of the same class
 reuse them without timing again.
 
-Every candidate computes the same factorization of the same matrices; only
-the supernode partition (and so the explicit zeros stored) differs.
+Every option set computes the same factorization of the same matrices; only
+the supernode partition (and so the explicit zeros stored) and the kernels
+that run each supernode differ.
 """
 from __future__ import annotations
 
@@ -23,8 +30,13 @@ import math
 import os
 import time
 
-CANDIDATES = tuple(dict(amalg_ratio=r, sn_cap=150) for r in (0.0, 0.05, 0.1, 0.2, 0.3, 0.5)) \
-    + (dict(amalg_ratio=0.3, sn_cap=64),)
+BASE = dict(amalg_ratio=0.0, sn_cap=150, small_w=16, small_r=64)
+STAGES = (
+    tuple(dict(amalg_ratio=r) for r in (0.0, 0.05, 0.1, 0.2, 0.3, 0.5)),
+    tuple(dict(sn_cap=c) for c in (150, 64)),
+    tuple(dict(small_w=w, small_r=r)
+          for w, r in ((16, 64), (16, 32), (8, 64), (4, 16), (-1, 64))),
+)
 
 
 def size_class(mats, precision: int) -> str:
@@ -90,24 +102,32 @@ def _store(path, data):
     os.replace(tmp, path)
 
 
-def tune_batch(mats, values, rhs, precision=0, candidates=CANDIDATES, cache_path=None,
-               steps=2, timer=measure):
+def tune_batch(mats, values, rhs, precision=0, stages=STAGES, cache_path=None, steps=2,
+               timer=measure, base=BASE):
     """Options (a dict for spchol.analyze_batch) that minimise factorization +
-    solve time for this batch, and the table of what each candidate measured.
-    A cached choice for the batch's size class is returned without timing
-    (table None); otherwise every candidate is timed with `timer` and, when
+    solve time for this batch, and the table of what each timed option set
+    measured.  A cached choice for the batch's size class is returned without
+    timing (table None).  Otherwise each stage's candidates (partial option
+    dicts) are applied in turn to the best options so far and timed with
+    `timer` (an option set already timed is not timed again); when
     `cache_path` is given, the winner is stored there."""
     key = size_class(mats, precision)
     cached = _load(cache_path).get(key)
     if cached is not None:
         return dict(cached["options"]), None
-    table = []
-    for opts in candidates:
-        r = timer(mats, values, rhs, precision, dict(opts), steps=steps)
-        table.append(dict(options=dict(opts), **r))
-    best = min(table, key=lambda t: t["ms"])
+    best = dict(base)
+    seen, table = {}, []
+    for k, stage in enumerate(stages):
+        for upd in stage:
+            opts = dict(best, **upd)
+            sig = tuple(sorted(opts.items()))
+            if sig not in seen:
+                r = timer(mats, values, rhs, precision, dict(opts), steps=steps)
+                seen[sig] = r["ms"]
+                table.append(dict(options=opts, stage=k, **r))
+        best = dict(min(table, key=lambda t: t["ms"])["options"])
     if cache_path:
         data = _load(cache_path)
-        data[key] = {"options": best["options"], "ms": best["ms"], "table": table}
+        data[key] = {"options": best, "ms": seen[tuple(sorted(best.items()))], "table": table}
         _store(cache_path, data)
-    return dict(best["options"]), table
+    return best, table

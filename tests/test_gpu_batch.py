@@ -26,10 +26,10 @@ def _batch(count, seed, lo=6, hi=40):
     return probs
 
 
-def _factor_batch(probs, sched=0, precision=0, cap=150, ratio=0.1):
+def _factor_batch(probs, sched=0, precision=0, cap=150, ratio=0.1, **extra):
     torch = torch_dev()
     sym = spchol.analyze_batch([(p.n, p.colptr, p.rowind, p.perm) for p in probs], sn_cap=cap,
-                               amalg_ratio=ratio, sched=sched, precision=precision)
+                               amalg_ratio=ratio, sched=sched, precision=precision, **extra)
     vals, rhs = inputs.stack_batch(probs)
     num = spchol.factor(sym, torch.from_numpy(vals).to("cuda:0"))
     return sym, num, rhs
@@ -52,6 +52,29 @@ def test_batch_fp64_factor_and_solve(sched):
         eta = oracle.backward_error(p.n, p.colptr, p.rowind, p.values, p.rhs, xk)
         assert eta.max() <= 1e-14
         off += p.n
+
+
+@pytest.mark.parametrize("small", [(-1, 0), (4, 16), (16, 32)])
+def test_batch_small_supernode_limits(small):
+    """Every split of the supernodes between the lane-group kernels and the
+    tile kernels (none small, narrow limits, the default width) factors the
+    batch to the same bars."""
+    torch = torch_dev()
+    probs = _batch(10, 211 + small[0])
+    sym, num, rhs = _factor_batch(probs, small_w=small[0], small_r=small[1])
+    assert num.status() == 0
+    big = inputs.block_diagonal(probs)
+    worst, rho, _ = compare_factor(big, num, 150, 0.1, "batch small %s" % (small,))
+    say("batch small", small, "worst/tol", worst, "residual", rho)
+    assert worst <= 1.0 and rho <= 1e-12
+    x = num.solve(torch.from_numpy(rhs).to("cuda:0")).cpu().numpy().reshape(-1, 1)
+    off = 0
+    for p in probs:
+        eta = oracle.backward_error(p.n, p.colptr, p.rowind, p.values, p.rhs, x[off:off + p.n])
+        assert eta.max() <= 1e-14
+        off += p.n
+    num.free()
+    sym.free()
 
 
 def test_batch_member_matches_single_factorization():
@@ -102,17 +125,20 @@ def test_tuned_batch_options(precision, tmp_path):
     vals, rhs = inputs.stack_batch(probs)
     v = torch.from_numpy(vals).to("cuda:0")
     b = torch.from_numpy(np.ascontiguousarray(rhs)).to("cuda:0")
-    cands = (dict(amalg_ratio=0.0, sn_cap=150), dict(amalg_ratio=0.3, sn_cap=150),
-             dict(amalg_ratio=0.3, sn_cap=16))
+    stages = ((dict(amalg_ratio=0.0), dict(amalg_ratio=0.3)),
+              (dict(sn_cap=150), dict(sn_cap=16)),
+              (dict(small_w=16, small_r=64), dict(small_w=4, small_r=16),
+               dict(small_w=-1, small_r=64)))
     path = str(tmp_path / "tune.json")
-    opts, table = tune.tune_batch(mats, v, b, precision, cands, path, steps=1)
+    opts, table = tune.tune_batch(mats, v, b, precision, stages, path, steps=1)
     say("tuning", [(t["options"], round(t["ms"], 3), t["nsup"], t["levels"]) for t in table])
-    assert opts in [dict(c) for c in cands] and len(table) == 3
-    assert all(t["ms"] > 0 for t in table)
+    assert len(table) == 5 and all(t["ms"] > 0 for t in table)
     assert table[1]["nsup"] < table[0]["nsup"]  # amalgamation merged supernodes
-    assert tune.tune_batch(mats, v, b, precision, cands, path)[0] == opts
+    assert opts == min(table, key=lambda t: t["ms"])["options"]
+    assert tune.tune_batch(mats, v, b, precision, stages, path)[0] == opts
     sym, num, _ = _factor_batch(probs, precision=precision, cap=opts["sn_cap"],
-                                ratio=opts["amalg_ratio"])
+                                ratio=opts["amalg_ratio"], small_w=opts["small_w"],
+                                small_r=opts["small_r"])
     assert num.status() == 0
     if precision == 0:
         x = num.solve(b).cpu().numpy()

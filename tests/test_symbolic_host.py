@@ -47,10 +47,13 @@ def test_analyze_rejects_bad_arguments():
     assert e.value.status == spchol.SPC_ERR_ARG
     for kw in (dict(sn_cap=0), dict(sn_cap=151), dict(amalg_ratio=-0.1), dict(sched=3), dict(sched=-1),
                dict(mem_budget_bytes=-1), dict(spin_limit=-1), dict(precision=2),
-               dict(precision=-1)):
+               dict(precision=-1), dict(threads=-1), dict(small_w=17), dict(small_w=-2),
+               dict(small_r=65), dict(small_r=-1)):
         with pytest.raises(spchol.SpcError) as e:
             spchol.analyze(2, cp, ri, **kw)
         assert e.value.status == spchol.SPC_ERR_ARG
+    for kw in (dict(small_w=-1), dict(small_w=1, small_r=1), dict(small_w=16, small_r=64)):
+        spchol.analyze(2, cp, ri, **kw).free()
 
 
 def _compare_with_oracle(p, cap=150, ratio=0.0):

@@ -1,6 +1,6 @@
 """The batched-factorization autotuner's host logic, with a stand-in timer
-(no GPU): size classes, the choice of the fastest candidate and the JSON
-cache."""
+(no GPU): size classes, the staged search, the choice of the fastest option
+set and the JSON cache."""
 import json
 
 from paper_1608_00044_amd import inputs, tune
@@ -11,11 +11,10 @@ def _mats(count=5, lo=6, hi=14):
             for p in inputs.make_batch(count=count, side_lo=lo, side_hi=hi)]
 
 
-def _fake_timer(costs, calls):
+def _fake_timer(cost, calls):
     def timer(mats, values, rhs, precision, opts, steps=2):
-        calls.append((precision, opts["amalg_ratio"], opts["sn_cap"]))
-        return {"ms": costs[(opts["amalg_ratio"], opts["sn_cap"])], "nsup": 1, "levels": 1,
-                "flops_stored": 0.0}
+        calls.append((precision, dict(opts)))
+        return {"ms": cost(opts), "nsup": 1, "levels": 1, "flops_stored": 0.0}
     return timer
 
 
@@ -30,35 +29,55 @@ def test_size_class_separates_precision_count_size_and_density():
     assert tune.size_class([], 0) == "p0-count0-n0-deg0"
 
 
-def test_tuner_picks_the_fastest_and_caches_it(tmp_path):
+STAGES = (
+    (dict(amalg_ratio=0.0), dict(amalg_ratio=0.2)),
+    (dict(sn_cap=150), dict(sn_cap=64)),
+)
+BASE = dict(amalg_ratio=0.0, sn_cap=150)
+
+
+def _cost(o):
+    return {(0.0, 150): 3.0, (0.2, 150): 1.5, (0.2, 64): 2.0, (0.0, 64): 0.5}[
+        (o["amalg_ratio"], o["sn_cap"])]
+
+
+def test_staged_search_and_cache(tmp_path):
     mats = _mats()
-    cands = (dict(amalg_ratio=0.0, sn_cap=150), dict(amalg_ratio=0.2, sn_cap=150),
-             dict(amalg_ratio=0.2, sn_cap=64))
-    costs = {(0.0, 150): 3.0, (0.2, 150): 1.5, (0.2, 64): 2.0}
     calls = []
     path = str(tmp_path / "sub" / "tune.json")
-    best, table = tune.tune_batch(mats, None, None, 1, cands, path, timer=_fake_timer(costs, calls))
+    best, table = tune.tune_batch(mats, None, None, 1, STAGES, path,
+                                  timer=_fake_timer(_cost, calls), base=BASE)
+    # stage 0 picks ratio 0.2; stage 1 starts there (the global optimum
+    # (0.0, 64) is never visited: the search is coordinate-wise)
     assert best == {"amalg_ratio": 0.2, "sn_cap": 150}
     assert [t["ms"] for t in table] == [3.0, 1.5, 2.0]
-    assert calls == [(1, 0.0, 150), (1, 0.2, 150), (1, 0.2, 64)]
+    assert [t["stage"] for t in table] == [0, 0, 1]
+    # (0.2, 150) is the incumbent of stage 1: timed once only
+    assert [c[1] for c in calls] == [dict(amalg_ratio=0.0, sn_cap=150),
+                                     dict(amalg_ratio=0.2, sn_cap=150),
+                                     dict(amalg_ratio=0.2, sn_cap=64)]
+    assert all(c[0] == 1 for c in calls)
     data = json.load(open(path))
-    assert list(data) == [tune.size_class(mats, 1)]
+    assert list(data) == [tune.size_class(mats, 1)] and data[tune.size_class(mats, 1)]["ms"] == 1.5
     # a second batch of the same class reuses the choice without timing
     calls.clear()
-    again, table2 = tune.tune_batch(mats, None, None, 1, cands, path,
-                                    timer=_fake_timer(costs, calls))
+    again, table2 = tune.tune_batch(mats, None, None, 1, STAGES, path,
+                                    timer=_fake_timer(_cost, calls), base=BASE)
     assert again == best and table2 is None and calls == []
     # another precision is another class: timed and added beside the first
-    tune.tune_batch(mats, None, None, 0, cands, path, timer=_fake_timer(costs, calls))
+    tune.tune_batch(mats, None, None, 0, STAGES, path, timer=_fake_timer(_cost, calls),
+                    base=BASE)
     assert len(calls) == 3 and len(json.load(open(path))) == 2
 
 
-def test_tuner_without_cache_always_times():
+def test_default_stages_are_valid_options():
     calls = []
-    costs = {(r, c): 1.0 + r for r, c in [(o["amalg_ratio"], o["sn_cap"])
-                                           for o in tune.CANDIDATES]}
-    best, table = tune.tune_batch(_mats(), None, None, 0, timer=_fake_timer(costs, calls))
-    assert best == {"amalg_ratio": 0.0, "sn_cap": 150}
-    assert len(table) == len(tune.CANDIDATES) == len(calls)
-    for o in tune.CANDIDATES:
+    best, table = tune.tune_batch(_mats(), None, None, 0,
+                                  timer=_fake_timer(lambda o: 1.0 + o["amalg_ratio"], calls))
+    assert best == tune.BASE
+    assert len(table) == len(calls) == len({tuple(sorted(c[1].items())) for c in calls})
+    for _, o in calls:
+        assert set(o) == set(tune.BASE)
         assert 0.0 <= o["amalg_ratio"] <= 1.0 and 1 <= o["sn_cap"] <= 150
+        assert o["small_w"] == -1 or 1 <= o["small_w"] <= 16
+        assert 1 <= o["small_r"] <= 64
