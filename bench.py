@@ -413,11 +413,11 @@ def main():
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB (a dispatch of known traffic "
                          "for scaling hardware byte counters)")
-    ap.add_argument("--cpu-batch-sample", type=int, default=1000,
+    ap.add_argument("--cpu-batch-sample", type=int, default=2000,
                     help="matrices of the batched workload the oracle runs on a process "
                          "pool (0 to skip)")
     ap.add_argument("--cpu-sample", default=None,
-                    help="grid of the bounded oracle sample (default: 40^3 for 3D workloads, "
+                    help="grid of the bounded oracle sample (default: 44^3 for 3D workloads, "
                          "the full grid for 2D ones)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -580,7 +580,7 @@ def main():
             dims = tuple(int(v) for v in args.cpu_sample.split(","))
         else:
             full = inputs.WORKLOADS[name]["dims"]
-            dims = (40, 40, 40) if len(full) == 3 else full
+            dims = (44, 44, 44) if len(full) == 3 else full
         log("cpu baseline on", dims)
         out["cpu_baseline"] = cpu_baseline(name, dims)
         if args.batch and args.cpu_batch_sample:
