@@ -236,7 +236,7 @@ def mixed_precision(name, steps, warmup, tol=1e-10):
     return out
 
 
-def batched(count, steps, precision, tol=1e-10, tune_options=True):
+def batched(count, steps, precision, tol=1e-10, tune_options=True, options=None):
     """Batch of independent 2D Laplacians (BATCH_RECIPE): the analysis options
     tuned on this batch (amalgamation ratio, cap), one batched analysis, then
     timed steps of factorization + one-RHS solve (FP64) or factorization +
@@ -252,7 +252,7 @@ def batched(count, steps, precision, tol=1e-10, tune_options=True):
     mats = [(p.n, p.colptr, p.rowind, p.perm) for p in probs]
     vals = torch.from_numpy(vals_h).to("cuda:0")
     b = torch.from_numpy(np.ascontiguousarray(rhs_h)).to("cuda:0")
-    opts, table = dict(tune.BASE), None
+    opts, table = dict(tune.BASE, **(options or {})), None
     if tune_options:
         t0 = time.perf_counter()
         opts, table = tune.tune_batch(mats, vals, b, precision)
@@ -405,6 +405,9 @@ def main():
     ap.add_argument("--mixed-steps", type=int, default=3)
     ap.add_argument("--batch", type=int, default=2000,
                     help="matrices of the batched workload (0 to skip)")
+    ap.add_argument("--batch-options", default=None,
+                    help="JSON dict of analysis options for the batched workload "
+                         "(e.g. '{\"amalg_ratio\": 0.2}'), used as given, no tuning")
     ap.add_argument("--no-batch-tune", action="store_true",
                     help="batched workload with the default options (no amalgamation) "
                          "instead of the tuned ones")
@@ -570,9 +573,10 @@ def main():
     if args.mixed_workload:
         out["mixed_precision"] = mixed_precision(args.mixed_workload, args.mixed_steps, 1)
     if args.batch:
-        tb = not args.no_batch_tune
-        out["batched"] = [batched(args.batch, 3, 0, tune_options=tb),
-                          batched(args.batch, 3, 1, tune_options=tb)]
+        tb = not args.no_batch_tune and not args.batch_options
+        fixed = json.loads(args.batch_options) if args.batch_options else None
+        out["batched"] = [batched(args.batch, 3, 0, tune_options=tb, options=fixed),
+                          batched(args.batch, 3, 1, tune_options=tb, options=fixed)]
     if args.serve_requests:
         out["serving"] = serving(args.serve_requests)
     if not args.no_cpu_baseline:
