@@ -30,6 +30,8 @@ import math
 import os
 import time
 
+from .spchol import SpcError
+
 BASE = dict(amalg_ratio=0.0, sn_cap=150, small_w=16, small_r=64)
 STAGES = (
     tuple(dict(amalg_ratio=r) for r in (0.0, 0.05, 0.1, 0.2, 0.3, 0.5)),
@@ -109,8 +111,9 @@ def tune_batch(mats, values, rhs, precision=0, stages=STAGES, cache_path=None, s
     measured.  A cached choice for the batch's size class is returned without
     timing (table None).  Otherwise each stage's candidates (partial option
     dicts) are applied in turn to the best options so far and timed with
-    `timer` (an option set already timed is not timed again); when
-    `cache_path` is given, the winner is stored there."""
+    `timer` (an option set already timed is not timed again; one that
+    fails with a library error is recorded with ms = inf and never chosen);
+    when `cache_path` is given, the winner is stored there."""
     key = size_class(mats, precision)
     cached = _load(cache_path).get(key)
     if cached is not None:
@@ -122,10 +125,16 @@ def tune_batch(mats, values, rhs, precision=0, stages=STAGES, cache_path=None, s
             opts = dict(best, **upd)
             sig = tuple(sorted(opts.items()))
             if sig not in seen:
-                r = timer(mats, values, rhs, precision, dict(opts), steps=steps)
+                try:
+                    r = timer(mats, values, rhs, precision, dict(opts), steps=steps)
+                except SpcError as e:  # e.g. refinement that does not converge
+                    r = {"ms": math.inf, "error": e.status}
                 seen[sig] = r["ms"]
                 table.append(dict(options=opts, stage=k, **r))
-        best = dict(min(table, key=lambda t: t["ms"])["options"])
+        done = [t for t in table if math.isfinite(t["ms"])]
+        if not done:
+            raise RuntimeError("no candidate option set completed: %s" % table)
+        best = dict(min(done, key=lambda t: t["ms"])["options"])
     if cache_path:
         data = _load(cache_path)
         data[key] = {"options": best, "ms": seen[tuple(sorted(best.items()))], "table": table}

@@ -81,3 +81,27 @@ def test_default_stages_are_valid_options():
         assert 0.0 <= o["amalg_ratio"] <= 1.0 and 1 <= o["sn_cap"] <= 150
         assert o["small_w"] == -1 or 1 <= o["small_w"] <= 16
         assert 1 <= o["small_r"] <= 64
+
+
+def test_failing_candidates_are_skipped():
+    import math
+
+    import pytest
+
+    from paper_1608_00044_amd.spchol import SPC_ERR_NOT_CONVERGED, SpcError
+
+    def timer(mats, values, rhs, precision, opts, steps=2):
+        if opts["amalg_ratio"] == 0.2:
+            raise SpcError(SPC_ERR_NOT_CONVERGED, "spc_solve_refine")
+        return {"ms": 2.0 + opts["amalg_ratio"], "nsup": 1, "levels": 1, "flops_stored": 0.0}
+
+    best, table = tune.tune_batch(_mats(), None, None, 1, STAGES, timer=timer, base=BASE)
+    assert best == {"amalg_ratio": 0.0, "sn_cap": 150}
+    bad = [t for t in table if t["options"]["amalg_ratio"] == 0.2]
+    assert bad and all(math.isinf(t["ms"]) and t["error"] == SPC_ERR_NOT_CONVERGED for t in bad)
+
+    def always(mats, values, rhs, precision, opts, steps=2):
+        raise SpcError(SPC_ERR_NOT_CONVERGED, "spc_solve_refine")
+
+    with pytest.raises(RuntimeError):
+        tune.tune_batch(_mats(), None, None, 1, STAGES, timer=always, base=BASE)
