@@ -126,12 +126,14 @@ __device__ __forceinline__ void rsqrt_sqrt(float d, float& rs, float& sq) {
 // columns j0 .. j0 + jb - 1 over every row from j0 to w - 1 of the packed
 // lower triangle T (entry (i, j) at cst(j) + i).  Lane l holds rows
 // j0 + l + 64 q (q < NQ, with NQ chunks covering the w - j0 rows).  For each
-// column c the pivot comes from the lane that holds row c (v_readlane), the
-// column is scaled by 1/sqrt(pivot), lanes 0-15 put its diagonal-block part
-// L(j0 .. j0 + 15, c) in the LDS array colbuf, and every lane reads those
-// values back (same address, one broadcast read per pair) to update the
-// panel's later columns.  Entries above the diagonal hold garbage in
-// registers and are never stored or broadcast.  1/L(c, c) goes to rdiag[c].
+// column c the pivot comes from the lane that holds row c (v_readlane) and the
+// column is scaled by 1/sqrt(pivot).  Columns go in pairs (c, c + 1): column
+// c + 1 is updated by column c with L(c + 1, c) read from its lane, then lanes
+// 0-15 put both columns' diagonal-block parts L(j0 .. j0 + 15, c .. c + 1) in
+// the LDS array colbuf, and every lane reads those values back (same address,
+// one broadcast read per pair) to update the panel's later columns.  Entries
+// above the diagonal hold garbage in registers and are never stored or
+// broadcast.  1/L(c, c) goes to rdiag[c].
 // Without kCheck the smallest column with a pivot that is not positive is
 // recorded (global column + 1) with atomicMin on *status; with kCheck (FP32
 // pass) a pivot at most kPivotTau times its starting diagonal entry d0[c]
@@ -155,29 +157,53 @@ __device__ __forceinline__ void panel_columns_q(C* __restrict__ T, C* __restrict
     const C piv0 = kCheck ? kPivotTau * d0[lane < jb ? j0 + lane : 0] : C(0);
     C rsv = C(0);   // lane k keeps 1/L(j0 + k, j0 + k)
     int bad = kPanel;  // first failing column of the panel
+    // column k: pivot, square root, scaling (lane k keeps L(k, k))
+    auto factor_column = [&](int k) {
+        const C d = lane_value(x[0][k], k);
+        const bool fail = kCheck ? !(d > lane_value(piv0, k)) : !(d > C(0));
+        bad = (fail && bad == kPanel) ? k : bad;
+        C rs, l;
+        rsqrt_sqrt(d, rs, l);
+        rsv = lane == k ? rs : rsv;
+        x[0][k] = lane == k ? l : x[0][k] * rs;
 #pragma unroll
-    for (int k = 0; k < kPanel; ++k) {
+        for (int q = 1; q < NQ; ++q) x[q][k] *= rs;
+    };
+    // Two columns per step: column k + 1 takes column k's term through a
+    // register broadcast of L(k + 1, k), then both columns go through colbuf
+    // once for the later columns.  Every product and its order are those of
+    // the column-by-column form (column k's term first).
+#pragma unroll
+    for (int k = 0; k < kPanel; k += 2) {
+        const bool has1 = kFull || k + 1 < jb;
         if (kFull || k < jb) {
-            const C d = lane_value(x[0][k], k);
-            const bool fail = kCheck ? !(d > lane_value(piv0, k)) : !(d > C(0));
-            bad = (fail && bad == kPanel) ? k : bad;
-            C rs, l;
-            rsqrt_sqrt(d, rs, l);
-            rsv = lane == k ? rs : rsv;
-            x[0][k] = lane == k ? l : x[0][k] * rs;
+            factor_column(k);
+            if (has1) {
+                const C a = lane_value(x[0][k], k + 1);
 #pragma unroll
-            for (int q = 1; q < NQ; ++q) x[q][k] *= rs;
-            if (k + 1 < kPanel && (kFull || k + 1 < jb)) {
-                if (lane < kPanel) colbuf[k * kPanel + lane] = x[0][k];
+                for (int q = 0; q < NQ; ++q) x[q][k + 1] -= x[q][k] * a;
+                factor_column(k + 1);
+            }
+            if (k + 2 < kPanel && (kFull || k + 2 < jb)) {
+                if (lane < kPanel) {
+                    colbuf[k * kPanel + lane] = x[0][k];
+                    colbuf[(k + 1) * kPanel + lane] = x[0][k + 1];
+                }
                 __builtin_amdgcn_wave_barrier();
-                C ljc[kPanel];
+                C l0[kPanel], l1[kPanel];
 #pragma unroll
-                for (int j = k + 1; j < kPanel; ++j) ljc[j] = colbuf[k * kPanel + j];
+                for (int j = k + 2; j < kPanel; ++j) {
+                    l0[j] = colbuf[k * kPanel + j];
+                    l1[j] = colbuf[(k + 1) * kPanel + j];
+                }
 #pragma unroll
-                for (int j = k + 1; j < kPanel; ++j) {
+                for (int j = k + 2; j < kPanel; ++j) {
                     if (kFull || j < jb) {
 #pragma unroll
-                        for (int q = 0; q < NQ; ++q) x[q][j] -= x[q][k] * ljc[j];
+                        for (int q = 0; q < NQ; ++q) {
+                            x[q][j] -= x[q][k] * l0[j];
+                            x[q][j] -= x[q][k + 1] * l1[j];
+                        }
                     }
                 }
             }
@@ -855,7 +881,8 @@ __global__ __launch_bounds__(kSchedThreads) void k_sched(
         __threadfence();  // release: this task's results before its signal
         __syncthreads();
         if (tk.kind == kTaskF) {
-            if (tid == 0) __hip_atomic_store(doneF + tk.s, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (tid == 0)
+                __hip_atomic_store(doneF + tk.s, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else if (tk.kind == kTaskT) {
             if (tid == 0)
                 __hip_atomic_store(doneT + rb_base[tk.s] + tk.a, 1, __ATOMIC_RELEASE,
