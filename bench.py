@@ -30,6 +30,7 @@ if ROOT not in sys.path:
 
 METRIC = "Cholesky factor GFLOP/s FP64 vs FP32+IR @1e-10 bwd err; p50/p99 solve latency"
 FP64_MFMA_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBPS = 8000.0
 HBM_PEAK_GBS = 8000.0
 
 WORKLOAD_TEXT = {
@@ -56,6 +57,22 @@ def update_flops(sym) -> float:
     w = np.diff(sn).astype(np.float64)
     r = np.diff(rp).astype(np.float64) - w
     return float(np.sum(w * r * (r + 1.0)))
+
+
+def hbm_bytes(sym) -> dict:
+    """Algorithmic HBM bytes of the memory-bound phases, FP64:
+    - one single-RHS solve: the stored factor read forward and backward plus
+      the 4-byte row index of every row below a diagonal block, both ways:
+      2 (8 nnz_stored + 4 sum_s r_s);
+    - the update scatter of one factorization: a 16-byte read-modify-write of
+      the target for every entry of the lower triangle of L21 L21^T:
+      16 sum_s r_s (r_s + 1) / 2."""
+    _, _, sn, _ = sym.export()
+    rp, _ = sym.rows()
+    w = np.diff(sn).astype(np.float64)
+    r = np.diff(rp).astype(np.float64) - w
+    return {"solve": 2.0 * (8.0 * sym.info()["nnz_stored"] + 4.0 * float(r.sum())),
+            "scatter": 16.0 * float(np.sum(r * (r + 1.0) / 2.0))}
 
 
 def backward_error(p, x, b):
@@ -546,6 +563,19 @@ def main():
                 "algorithmic_flops_per_launch": kflops / max(k_launch, 1),
                 "avg_launch_ms": k_ms / max(k_launch, 1), "launches_per_factor": k_launch}
 
+    hb = hbm_bytes(sym)
+    p50 = float(np.percentile(lat, 50))
+    hbm = {"peak_GBps": HBM_PEAK_GBPS,
+           "solve": {"algorithmic_bytes": hb["solve"], "ms": p50,
+                     "GBps": hb["solve"] / (p50 * 1e-3) / 1e9,
+                     "frac": hb["solve"] / (p50 * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                     "note": "p50 single-RHS solve; latency bound (one launch pair per level)"},
+           "scatter": {"algorithmic_bytes": hb["scatter"], "ms": kern["update"] / args.steps,
+                       "GBps": hb["scatter"] / (kern["update"] / args.steps * 1e-3) / 1e9
+                       if kern["update"] > 0 else 0.0,
+                       "note": "scatter bytes over the whole update kernel time (fused with "
+                               "the products): a lower bound on the scatter's own rate"}}
+    hbm["scatter"]["frac"] = hbm["scatter"]["GBps"] / HBM_PEAK_GBPS
     out = {
         "metric": METRIC, "value": gflops, "unit": "GFLOP/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
@@ -567,6 +597,7 @@ def main():
         "kernel_ms_per_factor": {c: kern[c] / args.steps for c in kern},
         "kernel_launches_per_factor": {c: launches[c] / args.steps for c in launches},
         "roofline": roofline,
+        "hbm_phases": hbm,
     }
     num.free()
     sym.free()

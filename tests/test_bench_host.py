@@ -57,3 +57,23 @@ def test_measured_traffic_follows_the_source():
         t = bench.measured_traffic("k_update", "lap3d_7pt_64")
         # present only while the summary's source hash matches the kernel file
         assert t is None or t > 0
+
+
+def test_hbm_bytes_from_the_structure():
+    from paper_1608_00044_amd import spchol
+
+    p = inputs.make_workload("lap2d_5pt_64")
+    sym = spchol.analyze(p.n, p.colptr, p.rowind, p.perm, sn_cap=150, amalg_ratio=0.1)
+    hb = bench.hbm_bytes(sym)
+    _, _, sn, _ = sym.export()
+    rp, _ = sym.rows()
+    solve = scatter = 0
+    for s in range(len(sn) - 1):
+        w = int(sn[s + 1] - sn[s])
+        r = int(rp[s + 1] - rp[s]) - w
+        stored = sum(w - c + r for c in range(w))  # column c stores w - c + r rows
+        solve += 2 * (8 * stored + 4 * r)
+        scatter += 16 * r * (r + 1) // 2
+    assert hb["solve"] == solve and hb["scatter"] == scatter
+    assert stored > 0
+    sym.free()
