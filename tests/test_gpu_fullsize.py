@@ -1,7 +1,8 @@
 """GPU checks at the benchmark's full size, in the launch configuration the
 benchmark times (level-by-level schedule replayed from a captured graph):
-the 64^3 7-point Laplacian (n = 262144) in FP64, and the 27-point 48^3
-problem through the FP32 factor and FP64 refinement.
+the 64^3 7-point Laplacian (n = 262144) in FP64, the 27-point 48^3
+problem through the FP32 factor and FP64 refinement, and the batch of 2000
+2D Laplacians in both precisions at the tuned amalgamation ratios.
 
 The oracle cannot factor these in seconds, so the checks are properties that
 hold at any size, computed on the host from the library's outputs:
@@ -83,5 +84,45 @@ def test_elast27_48_fp32_refined_full_size():
     say("refinement steps", iters, "eta", eta.max(), "library estimate", berr.max())
     assert eta.max() <= 1e-10
     np.testing.assert_allclose(berr, eta, rtol=0.05, atol=1e-14)
+    num.free()
+    sym.free()
+
+
+@pytest.mark.parametrize("precision, ratio", [(0, 0.2), (1, 0.3)])
+def test_batch2000_full_size(precision, ratio):
+    """The batched workload at full size (2000 2D Laplacians, sides 16..128)
+    in the options the benchmark's tuner picks: the backward error of every
+    40th matrix, by the oracle's definition, <= 1e-14 (FP64) or <= 1e-10
+    (FP32 factor + refinement, which also reports it per matrix)."""
+    torch = torch_dev()
+    probs = inputs.make_batch(count=2000)
+    mats = [(p.n, p.colptr, p.rowind, p.perm) for p in probs]
+    sym = spchol.analyze_batch(mats, sn_cap=150, amalg_ratio=ratio, precision=precision)
+    say("batch n", sym.info()["n"], "nsup", sym.info()["nsup"], "levels", sym.info()["nlevels"])
+    vals_h, rhs_h = inputs.stack_batch(probs)
+    vals = torch.from_numpy(vals_h).to("cuda:0")
+    b = torch.from_numpy(np.ascontiguousarray(rhs_h)).to("cuda:0")
+    num = spchol.factor(sym, vals)
+    assert num.status() == 0
+    num.refactor(vals)
+    assert num.status() == 0
+    if precision == 0:
+        x = num.solve(b).cpu().numpy().ravel()
+        bar = 1e-14
+    else:
+        xt, iters, berr = num.solve_refine(b, tol=1e-10, max_iter=20)
+        x = xt.cpu().numpy().ravel()
+        bar = 1e-10
+        say("refinement steps", iters, "worst library estimate", berr.max())
+        assert berr.max() <= 1e-10
+    off, worst = 0, 0.0
+    for k, p in enumerate(probs):
+        if k % 40 == 0:
+            eta = oracle.backward_error(p.n, p.colptr, p.rowind, p.values, p.rhs,
+                                        x[off:off + p.n].reshape(-1, 1))
+            worst = max(worst, float(eta.max()))
+        off += p.n
+    say("sampled backward error", worst)
+    assert worst <= bar
     num.free()
     sym.free()
