@@ -1,7 +1,8 @@
 """CPU oracle for the supernodal Cholesky path -- TEST INFRASTRUCTURE ONLY.
 
-Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
-``bench.py`` may import this package.  It wraps ``oracle.c`` (plain C, one
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline legs of
+``bench.py`` (``cpu_baseline``; ``cpu_batch_baseline``, whose pool workers run
+this package) may import this package.  It wraps ``oracle.c`` (plain C, one
 core, IEEE binary64, built with ``-O2 -ffp-contract=off``) through ctypes and
 shares no code with the HIP library.
 

@@ -1,8 +1,9 @@
 /*
  * CPU oracle for the supernodal sparse Cholesky path -- TEST INFRASTRUCTURE.
  *
- * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
- * may load this file's library.  It shares no code with the HIP library: its
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline legs
+ * (one matrix on one core; the batched matrices on a process pool) may load
+ * this file's library.  It shares no code with the HIP library: its
  * symbolic analysis follows the plain definitions, its numeric factorization
  * is a scalar left-looking column Cholesky, and everything runs on one core in
  * IEEE binary64 (build with -O2 -ffp-contract=off).
