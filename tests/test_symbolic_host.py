@@ -300,3 +300,44 @@ def test_batch_rejects_bad_member():
     assert e.value.status == spchol.SPC_ERR_PATTERN
     empty = spchol.analyze_batch([])
     assert empty.info()["n"] == 0 and empty.info()["nbatch"] == 0
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_batch_analysis_random_mixes(seed):
+    """Random mixes of members (random sparse SPD patterns, grids, dense
+    blocks, 1x1 and empty matrices) at random options and thread counts: the
+    batched analysis equals the block-diagonal matrix's, on every export."""
+    rng = np.random.default_rng(900 + seed)
+    probs = []
+    for k in range(int(rng.integers(3, 14))):
+        kind = int(rng.integers(0, 4))
+        if kind == 0:
+            probs.append(inputs.random_spd_pattern(int(rng.integers(1, 60)),
+                                                   float(rng.uniform(0.02, 0.3)),
+                                                   seed=int(rng.integers(1 << 30))))
+        elif kind == 1:
+            probs.extend(inputs.make_batch(count=1, seed=int(rng.integers(1 << 20)), side_lo=2,
+                                           side_hi=12))
+        elif kind == 2:
+            probs.append(inputs.dense_spd(int(rng.integers(1, 30)), seed=int(rng.integers(99))))
+        else:
+            probs.append(inputs.tridiag(int(rng.integers(1, 40))))
+    mats = [(p.n, p.colptr, p.rowind, p.perm) for p in probs]
+    if rng.random() < 0.5:
+        mats.insert(int(rng.integers(0, len(mats) + 1)),
+                    (0, np.zeros(1, dtype=np.int64), np.zeros(0, dtype=np.int32), None))
+    whole = inputs.block_diagonal([dataclasses.replace(p, rhs=None) for p in probs])
+    cap = int(rng.choice([1, 5, 16, 150]))
+    ratio = float(rng.choice([0.0, 0.1, 0.4]))
+    ref = spchol.analyze(whole.n, whole.colptr, whole.rowind, whole.perm, sn_cap=cap,
+                         amalg_ratio=ratio, sched=2)
+    want = _whole_analysis_fields(ref)
+    threads = int(rng.integers(1, 9))
+    bs = spchol.analyze_batch(mats, sn_cap=cap, amalg_ratio=ratio, sched=2, threads=threads)
+    got = _whole_analysis_fields(bs)
+    assert got["info"] == want["info"]
+    for k in want:
+        if k != "info":
+            assert np.array_equal(got[k], want[k]), (k, seed)
+    bs.free()
+    ref.free()
