@@ -73,11 +73,14 @@ typedef struct spc_options {
                                  queue (dependency counters, Section IV)        */
     double amalg_ratio;       /* relaxed amalgamation zero ratio; 0 = off (default) */
     int64_t mem_budget_bytes; /* device bytes a factor may hold; 0 = no limit       */
-    int64_t spin_limit;       /* sched 2: bound on every device wait, in microseconds;
-                                 past it the factorization stops and its status
+    int64_t spin_limit;       /* bound on every device wait (sched 2 and the
+                                 deterministic order), in microseconds; past it
+                                 the factorization stops waiting and its status
                                  reads SPC_ERR_TIMEOUT; 0 = default (ten seconds) */
     int32_t debug_flags;      /* bit 0: withhold one dependency count so that the
-                                 bounded wait fires (testing only); default 0    */
+                                 bounded wait fires (testing only); bit 1: sched 2
+                                 records when every task starts and finishes
+                                 (spc_numeric_task_log); default 0               */
     int32_t precision;        /* 0 = FP64 factor (default); 1 = FP32 factor on FP32
                                  matrix cores with FP32 accumulation, for use with
                                  spc_solve_refine (FP64 iterative refinement)     */
@@ -90,6 +93,20 @@ typedef struct spc_options {
                                  others by workgroup kernels on 64 x 64 tiles.
                                  small_w 1..16, or -1 for none; 0 = default (16) */
     int32_t small_r;          /* 1..64; 0 = default (64)                           */
+    int32_t deterministic;    /* 1 (default): every target supernode receives its
+                                 update contributions in one fixed order -- level
+                                 by level, and inside a level the sources in
+                                 increasing order (the non-decreasing (target,
+                                 source) order of Section III-D) -- so a factor
+                                 has the same bits on every run, alone or beside
+                                 other work.  0: contributions to a target that
+                                 several sources of a level share are atomic adds
+                                 in arrival order (equal to rounding).  With
+                                 sched 1 the lookahead is then off (one stream,
+                                 level by level); sched 2 requires 0 (its queue
+                                 order is dynamic): SPC_ERR_ARG otherwise.      */
+    int32_t workers;          /* sched 2: persistent workgroups taking tasks;
+                                 0 = as many as fit on the device at once        */
 } spc_options;
 
 typedef struct spc_symbolic spc_symbolic;
@@ -111,11 +128,14 @@ typedef struct spc_symbolic_info {
     int32_t max_width;     /* widest supernode                                      */
     int32_t max_below;     /* most rows below a diagonal block                      */
     int64_t nbatch;        /* independent matrices (1 unless spc_analyze_batch)     */
+    int64_t solve_bytes_per_rhs; /* device work bytes a solve holds per right-hand side
+                                    (solution vector, forward contributions of every
+                                    below-diagonal row, backward partial sums)     */
 } spc_symbolic_info;
 
 /* Fills *opt with the defaults (sn_cap 150, sched 0, no amalgamation, no budget,
  * default spin limit, no debug flags, default threads and small-supernode
- * limits). */
+ * limits, deterministic order, default workers). */
 void spc_default_options(spc_options* opt);
 
 /* Symbolic analysis on the host (no device work).  colptr/rowind/perm are
@@ -223,10 +243,17 @@ spc_status spc_factor_export(spc_numeric* num, int64_t* Sp, int32_t* Si, double*
  * taken at factorization time, the normwise backward error
  * eta_c = ||r_c||_inf / (||A||_inf ||x_c||_inf + ||b_c||_inf) of every column,
  * and, while some eta_c > tol, solves L L^T d = r / ||r|| in the factor's
- * precision and adds ||r|| d to x in FP64.  b_dev, x_dev: column-major device
- * arrays (ldb, ldx >= n) of doubles that must not overlap.  Returns SPC_OK
- * once every column meets tol, SPC_ERR_NOT_CONVERGED after max_iter
- * corrections (x holds the last iterate), or the factor's status.  *iters
+ * precision and adds ||r|| d to x in FP64.  Two steps in a row in which the
+ * worst eta does not halve count as a stall: on an FP32 factor the
+ * corrections then continue with an FP64 factor of the same matrix (made
+ * from the copy of A on first need, kept until the next factorization, about
+ * twice the FP32 factor's bytes; counted in spc_numeric_info's
+ * refine_fallbacks); on an FP64 factor the refinement stops.  b_dev, x_dev:
+ * column-major device arrays (ldb, ldx >= n) of doubles that must not
+ * overlap.  Returns SPC_OK once every column meets tol,
+ * SPC_ERR_NOT_CONVERGED after max_iter corrections (FP32 and FP64 ones
+ * together) or a stall of the FP64 corrections (x holds the last iterate),
+ * the FP64 fallback factor's status, or the factor's status.  *iters
  * (may be NULL) receives the number of corrections; berr (host, may be NULL)
  * the final eta: nrhs entries, or for a batch analysis nrhs x nbatch entries
  * (berr[c * nbatch + k]: matrix k, column c), each matrix's norms taken over
@@ -244,6 +271,7 @@ typedef struct spc_numeric_info {
     int32_t sched;
     int64_t factor_bytes;  /* device bytes held by the factor (estimate) */
     int64_t fp64_blocks;
+    int64_t refine_fallbacks; /* spc_solve_refine calls that switched to an FP64 factor */
 } spc_numeric_info;
 
 spc_status spc_numeric_info_get(spc_numeric* num, spc_numeric_info* out);
@@ -266,6 +294,18 @@ typedef struct spc_kernel_times {
 spc_status spc_numeric_set_timing(spc_numeric* num, int32_t enable);
 spc_status spc_numeric_get_timing(spc_numeric* num, spc_kernel_times* out);
 
+/* Execution log of the device task queue (sched 2, analysed with debug_flags
+ * bit 1): *ntasks tasks in ticket order (tasks: 4 int32 each, kind, s, a, b,
+ * as spc_symbolic_export_tasks) and, per task, two stamps of one device
+ * clock: stamps[2q] when task q's inputs were complete (its dependency waits
+ * over, Section IV), stamps[2q + 1] when its results were written, before
+ * its successors were signalled.  A correct run has every stamp of a task
+ * above the finishing stamp of each task it depends on.  tasks and stamps
+ * may be NULL (query the count first).  Synchronizes.  SPC_ERR_ARG without a
+ * log. */
+spc_status spc_numeric_task_log(spc_numeric* num, int64_t* ntasks, int32_t* tasks,
+                                int32_t* stamps);
+
 /* Releases the factor's device memory (synchronizing its stream). NULL is accepted. */
 void spc_numeric_free(spc_numeric* num);
 
@@ -287,7 +327,9 @@ const char* spc_status_string(spc_status st);
  * meanwhile are admitted in arrival order as slots and memory free up.  A
  * worker thread schedules; submit and wait are thread safe.  The caller's
  * device buffers (values, b, x) must stay valid until the request's wait
- * returns.  This extends the paper's factor/solve split (Section II-A) to a
+ * returns.  A request's device work is ordered after everything enqueued on
+ * its `stream` before spc_server_submit (an event recorded there at
+ * submission), so values, b and x may still be being written on that stream.  This extends the paper's factor/solve split (Section II-A) to a
  * stream of requests; the paper itself serves none.
  * ------------------------------------------------------------------------ */
 typedef struct spc_server spc_server;
@@ -310,6 +352,8 @@ typedef struct spc_request {
     int64_t ldb;
     double* x;              /* device, column-major n x nrhs, leading dimension ldx  */
     int64_t ldx;
+    void* stream;           /* hipStream_t that produced values / b and last used x
+                               (NULL = the default stream)                           */
 } spc_request;
 
 typedef struct spc_request_result {
@@ -321,6 +365,9 @@ typedef struct spc_request_result {
     double latency_ms;      /* submit to completion of its device work               */
 } spc_request_result;
 
+/* bytes_in_use and peak_bytes count the resident factors with their work
+ * vectors, plus each pattern's device plan from its first factor on (plans
+ * stay until the symbolic handle is freed, so eviction does not return them). */
 typedef struct spc_server_stats {
     int64_t submitted, completed, rejected, evictions;
     int64_t bytes_in_use, peak_bytes, budget_bytes;
@@ -329,7 +376,8 @@ typedef struct spc_server_stats {
 
 void spc_server_default_options(spc_server_options* opt);
 spc_status spc_server_create(const spc_server_options* opt, spc_server** out);
-/* Registers a symbolic handle (kept referenced until spc_server_destroy). */
+/* Registers a symbolic handle.  The server holds a reference to it until
+ * spc_server_destroy: spc_symbolic_free returns SPC_ERR_BUSY meanwhile. */
 spc_status spc_server_add_pattern(spc_server* srv, spc_symbolic* sym, int32_t* pattern);
 /* Queues a request; *ticket identifies it.  SPC_ERR_ARG on bad sizes. */
 spc_status spc_server_submit(spc_server* srv, const spc_request* req, int64_t* ticket);

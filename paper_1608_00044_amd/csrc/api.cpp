@@ -19,26 +19,34 @@ using namespace spc;
 
 namespace {
 
-size_t real_size(const Symbolic& S) { return S.opt.precision == 1 ? sizeof(float) : sizeof(double); }
+size_t real_size(int32_t prec) { return prec == 1 ? sizeof(float) : sizeof(double); }
 
 // Device bytes of one numeric factor: supernode blocks and diagonal-block
 // inverses in the factor's type, the FP64 copy of A kept for refinement
 // (full CSR: 8-byte value, 4-byte column and 8-byte source index per entry,
 // plus row pointers), task-queue counters, status words.
-int64_t factor_bytes(const Symbolic& S) {
+int64_t factor_bytes(const spc_symbolic* sym, int32_t prec) {
+    const Symbolic& S = sym->S;
     const int64_t nnzf = 2 * S.nnz_a;  // bound: diagonal entries appear once
-    int64_t b = (int64_t)((S.arena + inverse_blocks_elems(S)) * real_size(S));
+    int64_t b = (int64_t)((S.arena + inverse_blocks_elems(S)) * real_size(prec));
     b += nnzf * 20 + (S.n + 1) * 8;
     if (S.opt.sched == 2) b += 4 * (3 * S.nsup + 4);
+    if (S.opt.deterministic)
+        b += 4 * (S.nsup + (int64_t)S.level_ptr.size()) + sym->det_scratch * real_size(prec);
     return b + 512;
 }
 
 // Frees whatever the numeric object holds (any member may still be null).
 void release_numeric(spc_numeric* num) {
+    if (num->fb) spc_numeric_free(num->fb);
+    (void)hipFree(num->fb_values);
     (void)hipFree(num->arena);
     (void)hipFree(num->status_dev);
     (void)hipFree(num->dinv);
     (void)hipFree(num->sched_state);
+    (void)hipFree(num->det_state);
+    (void)hipFree(num->det_scratch);
+    (void)hipFree(num->task_log);
     drop_solve_graphs(num);
     if (num->factor_exec) (void)hipGraphExecDestroy(num->factor_exec);
     if (num->factor_graph) (void)hipGraphDestroy(num->factor_graph);
@@ -69,6 +77,9 @@ spc_status analyze_checked(const spc_options* opt, spc_symbolic** out, Run run) 
     if (o.threads < 0) return SPC_ERR_ARG;
     if (o.small_w < -1 || o.small_w > kSmallW || o.small_r < 0 || o.small_r > kSmallR)
         return SPC_ERR_ARG;
+    if (o.deterministic != 0 && o.deterministic != 1) return SPC_ERR_ARG;
+    if (o.deterministic && o.sched == 2) return SPC_ERR_ARG;  // the queue's order is dynamic
+    if (o.workers < 0) return SPC_ERR_ARG;
     spc_symbolic* h = new (std::nothrow) spc_symbolic();
     if (!h) return SPC_ERR_OOM;
     Options so;
@@ -80,10 +91,12 @@ spc_status analyze_checked(const spc_options* opt, spc_symbolic** out, Run run) 
     so.precision = o.precision;
     so.small_w = o.small_w == 0 ? kSmallW : (o.small_w < 0 ? 0 : o.small_w);
     so.small_r = o.small_r == 0 ? kSmallR : o.small_r;
+    so.deterministic = o.deterministic;
+    so.workers = o.workers;
     int32_t st;
     try {
         st = run(so, o.threads, &h->S);
-        if (st == OK) h->plan_bytes_estimate = plan_bytes(h->S);
+        if (st == OK) h->plan_bytes_estimate = plan_bytes(h->S, &h->det_scratch);
     } catch (const std::bad_alloc&) {
         st = SPC_ERR_OOM;
     }
@@ -112,6 +125,8 @@ void spc_default_options(spc_options* opt) {
     opt->threads = 0;
     opt->small_w = 0;
     opt->small_r = 0;
+    opt->deterministic = 1;
+    opt->workers = 0;
 }
 
 const char* spc_status_string(spc_status st) {
@@ -169,13 +184,14 @@ spc_status spc_symbolic_info_get(const spc_symbolic* sym, spc_symbolic_info* inf
     info->nlevels = (int64_t)S.level_ptr.size() - 1;
     info->npairs = (int64_t)S.pairs.size();
     info->nrel = (int64_t)S.rel.size();
-    info->factor_bytes = factor_bytes(S);
+    info->factor_bytes = factor_bytes(sym, S.opt.precision);
     info->plan_bytes = (int64_t)sym->plan_bytes_estimate;
     info->flops = S.flops;
     info->flops_stored = S.flops_stored;
     info->max_width = S.max_w;
     info->max_below = S.max_r;
     info->nbatch = (int64_t)S.batch_ptr.size() - 1;
+    info->solve_bytes_per_rhs = solve_work_elems_per_rhs(S) * (int64_t)real_size(S.opt.precision);
     return SPC_OK;
 }
 
@@ -242,11 +258,13 @@ spc_status spc_symbolic_free(spc_symbolic* sym) {
     return SPC_OK;
 }
 
-static spc_status alloc_numeric(spc_symbolic* sym, spc_numeric** out) {
+// A numeric object of sym whose factor has type prec (0 FP64, 1 FP32).
+static spc_status alloc_numeric(spc_symbolic* sym, int32_t prec, spc_numeric** out) {
     int32_t st = configure_kernels();
     if (st != OK) return st;
     const Symbolic& S = sym->S;
-    if (sym->budget > 0 && factor_bytes(S) + (int64_t)sym->plan_bytes_estimate > sym->budget)
+    if (sym->budget > 0 &&
+        factor_bytes(sym, prec) + (int64_t)sym->plan_bytes_estimate > sym->budget)
         return SPC_ERR_OOM;
     DevicePlan* plan = nullptr;
     st = get_plan(sym, &plan);
@@ -256,9 +274,11 @@ static spc_status alloc_numeric(spc_symbolic* sym, spc_numeric** out) {
     num->sym = sym;
     num->plan = plan;
     num->device = plan->device;
-    num->prec = S.opt.precision;
-    num->sched = S.opt.sched;
-    const size_t rs = real_size(S);
+    num->prec = prec;
+    // the lookahead's second stream reorders contributions: the deterministic
+    // order runs level by level on one stream
+    num->sched = (S.opt.sched == 1 && S.opt.deterministic) ? 0 : S.opt.sched;
+    const size_t rs = real_size(prec);
     bool ok = hipMalloc(&num->arena, rs * (size_t)(S.arena > 0 ? S.arena : 1)) == hipSuccess &&
               hipMalloc(&num->status_dev, 256) == hipSuccess &&
               hipMalloc(&num->dinv, rs * (size_t)(plan->inv_elems > 0 ? plan->inv_elems : 1)) ==
@@ -267,6 +287,25 @@ static spc_status alloc_numeric(spc_symbolic* sym, spc_numeric** out) {
         const size_t ints = 2 * (size_t)S.nsup + (size_t)plan->nrowblk + 4;
         ok = hipMalloc(&num->sched_state, ints * sizeof(int32_t)) == hipSuccess;
         num->spin_limit = S.opt.spin_limit > 0 ? S.opt.spin_limit : (int64_t)10000000;
+        if (ok && (S.opt.debug_flags & 2))
+            ok = hipMalloc(&num->task_log, 2 * sizeof(int32_t) *
+                                               (size_t)std::max<int64_t>(plan->ntasks, 1)) ==
+                 hipSuccess;
+    }
+    if (ok && S.opt.deterministic) {
+        // ticks of the wall clock in the wait bound (spin_limit microseconds,
+        // default ten seconds): a wait that exceeds it ends as SPC_ERR_TIMEOUT
+        int clock_khz = 0;
+        if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, plan->device) !=
+                hipSuccess ||
+            clock_khz <= 0)
+            clock_khz = 100000;
+        const int64_t us = S.opt.spin_limit > 0 ? S.opt.spin_limit : (int64_t)10000000;
+        num->det_wait_ticks = (uint64_t)us * (uint64_t)clock_khz / 1000;
+        const size_t ints = (size_t)S.nsup + S.level_ptr.size();
+        ok = hipMalloc(&num->det_state, ints * sizeof(int32_t)) == hipSuccess &&
+             hipMalloc(&num->det_scratch, rs * (size_t)std::max<int64_t>(plan->det_scratch, 1)) ==
+                 hipSuccess;
     }
     if (!ok) {
         release_numeric(num);
@@ -301,7 +340,7 @@ spc_status spc_factor(const spc_symbolic* csym, const double* values_dev, void* 
     spc_symbolic* sym = const_cast<spc_symbolic*>(csym);
     if (sym->S.nnz_a > 0 && !values_dev) return SPC_ERR_ARG;
     spc_numeric* num = nullptr;
-    spc_status st = alloc_numeric(sym, &num);
+    spc_status st = alloc_numeric(sym, sym->S.opt.precision, &num);
     if (st != SPC_OK) return st;
     st = factor_and_keep(num, values_dev, (hipStream_t)stream);
     if (st != SPC_OK) {
@@ -338,6 +377,15 @@ spc_status spc_numeric_status(spc_numeric* num) {
             hipSuccess)
             return SPC_ERR_HIP;
         if (err) num->host_status = SPC_ERR_TIMEOUT;
+    }
+    if (num->det_state) {  // an ordered wait that ran past its bound
+        const Symbolic& S = num->sym->S;
+        int32_t late = 0;
+        const size_t at = (size_t)S.nsup + S.level_ptr.size() - 1;
+        if (hipMemcpy(&late, num->det_state + at, sizeof(int32_t), hipMemcpyDeviceToHost) !=
+            hipSuccess)
+            return SPC_ERR_HIP;
+        if (late) num->host_status = SPC_ERR_TIMEOUT;
     }
     num->status_known = true;
     return num->host_status;
@@ -378,7 +426,8 @@ spc_status spc_numeric_info_get(spc_numeric* num, spc_numeric_info* out) {
     std::memset(out, 0, sizeof(*out));
     out->precision = num->prec;
     out->sched = num->sched;
-    out->factor_bytes = factor_bytes(num->sym->S);
+    out->factor_bytes = factor_bytes(num->sym, num->prec);
+    out->refine_fallbacks = num->refine_fallbacks;
     if (num->factored) {
         if (hipStreamSynchronize(num->stream) != hipSuccess) return SPC_ERR_HIP;
         int32_t v[2] = {0, 0};
@@ -429,6 +478,29 @@ spc_status spc_factor_export(spc_numeric* num, int64_t* Sp, int32_t* Si, double*
             for (int32_t c = 0; c < w; ++c)
                 for (int32_t i = c; i < m; ++i) Sx[q++] = B[i + (int64_t)c * ld];
         }
+    }
+    return SPC_OK;
+}
+
+spc_status spc_numeric_task_log(spc_numeric* num, int64_t* ntasks, int32_t* tasks,
+                                int32_t* stamps) {
+    if (!num || !ntasks) return SPC_ERR_ARG;
+    if (!num->task_log) return SPC_ERR_ARG;
+    const std::vector<Task>& T = num->plan->host_tasks;
+    *ntasks = (int64_t)T.size();
+    if (tasks)
+        for (size_t i = 0; i < T.size(); ++i) {
+            tasks[4 * i] = T[i].kind;
+            tasks[4 * i + 1] = T[i].s;
+            tasks[4 * i + 2] = T[i].a;
+            tasks[4 * i + 3] = T[i].b;
+        }
+    if (stamps) {
+        if (!num->factored) return SPC_ERR_NOT_FACTORED;
+        if (hipStreamSynchronize(num->stream) != hipSuccess) return SPC_ERR_HIP;
+        if (!T.empty() && hipMemcpy(stamps, num->task_log, 2 * sizeof(int32_t) * T.size(),
+                                    hipMemcpyDeviceToHost) != hipSuccess)
+            return SPC_ERR_HIP;
     }
     return SPC_OK;
 }
@@ -485,6 +557,11 @@ void spc_numeric_free(spc_numeric* num) {
 
 namespace spc {
 // Numeric object of sym without a factorization (the request server's pool).
-int32_t numeric_create(spc_symbolic* sym, spc_numeric** out) { return alloc_numeric(sym, out); }
-int64_t numeric_bytes(const Symbolic& S) { return factor_bytes(S); }
+int32_t numeric_create(spc_symbolic* sym, spc_numeric** out) {
+    return alloc_numeric(sym, sym->S.opt.precision, out);
+}
+int32_t numeric_create_prec(spc_symbolic* sym, int32_t prec, spc_numeric** out) {
+    return alloc_numeric(sym, prec, out);
+}
+int64_t numeric_bytes(const spc_symbolic* sym) { return factor_bytes(sym, sym->S.opt.precision); }
 }  // namespace spc

@@ -640,10 +640,21 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
 // Update tile by one workgroup of 4 waves.  If coltgt is given (an LDS array
 // of kTile entries), it receives each column's target supernode (-1 past the
 // panel), in non-decreasing order.
+// With cnt (the deterministic order): before its scatter the tile waits, for
+// every target of a shared pair among its columns, until cnt[target] reaches
+// pair_thr of the pair (every tile of the level's earlier sources into that
+// target has been added), adds its entries (atomic adds, now in a fixed
+// order per entry), waits for them to complete and adds one to cnt[target].
+// Every wait is bounded (deadline in wall-clock ticks): past it the tile sets
+// *late and goes on, and the factorization's status reads SPC_ERR_TIMEOUT.
 template <class R>
 __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
                                             const uint8_t* __restrict__ pair_excl,
-                                            R* __restrict__ arena, int* coltgt) {
+                                            R* __restrict__ arena, int* coltgt,
+                                            const int32_t* __restrict__ pair_thr = nullptr,
+                                            int32_t* __restrict__ cnt = nullptr,
+                                            uint64_t deadline = 0,
+                                            int32_t* __restrict__ late = nullptr) {
     typedef typename Mx<R>::acc Acc;
     __shared__ R lds[2 * 2 * kChunk * kLdsStride > kTile * kCtPad
                               ? 2 * 2 * kChunk * kLdsStride
@@ -651,6 +662,7 @@ __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
     __shared__ int64_t colbase[kTile];
     __shared__ int64_t relbase[kTile];
     __shared__ int colexcl[kTile];
+    __shared__ int colpair[kTile];
     const int s = tile.s;
     const int w = a.sn_w[s], ld = a.sn_ld[s];
     const int64_t rp = a.rowptr[s];
@@ -691,7 +703,7 @@ __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
     // whose chain of dependent loads then hides under them
     fetch(0);
     int64_t my_colbase = 0, my_relbase = 0;
-    int my_excl = 0;
+    int my_excl = 0, my_pair = -1, my_tgt = -1, my_thr = 0;
     if (tid < kTile) {
         const int gc = c0 + tid;
         if (coltgt) coltgt[tid] = -1;
@@ -703,6 +715,9 @@ __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
             my_colbase = a.sn_off[t] + (int64_t)(a.rows[at] - a.sn_first[t]) * a.sn_ld[t];
             my_relbase = a.pair_rel[p] - a.pair_seg[p];
             my_excl = pair_excl ? pair_excl[p] : 0;
+            my_pair = p;
+            my_tgt = t;
+            if (cnt) my_thr = pair_thr[p];
         }
     }
     Acc acc[2][2];
@@ -732,6 +747,7 @@ __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
             colbase[tid] = my_colbase;
             relbase[tid] = my_relbase;
             colexcl[tid] = my_excl;
+            colpair[tid] = my_pair;
         }
         if (ch + 1 < nchunk) stash(buf ^ 1);
         __syncthreads();
@@ -744,6 +760,26 @@ __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
                 const int c = wc * 32 + n * 16 + lr;
                 Ct[c * kCtPad + i] = acc[m][n][q];
             }
+    // deterministic order: the first column of each shared pair waits for the
+    // target's earlier contributions (the lowest unfinished tile of the
+    // launch never waits: tiles take tickets in list order, and a tile only
+    // waits on tiles of earlier sources)
+    int my_sig = -1;
+    if (cnt && tid < kTile && my_pair >= 0 && !my_excl &&
+        (tid == 0 || colpair[tid - 1] != my_pair)) {
+        my_sig = my_tgt;
+        while (__hip_atomic_load(cnt + my_tgt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+               my_thr) {
+            // past the deadline, or once any wait of the run has gone past
+            // its own, stop waiting (the status reports the timeout)
+            if (wall_clock64() > deadline ||
+                __hip_atomic_load(late, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                __hip_atomic_store(late, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
     __syncthreads();
     // thread -> row i = tid & 63 of the tile, columns c = tid / 64 + 4 u
     // (u < 16); every relative index is loaded before the first update is
@@ -773,6 +809,14 @@ __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
         if (colexcl[c]) arena[dst[u]] = old[u] - v;
         else unsafeAtomicAdd(arena + dst[u], -v);
     }
+    if (cnt) {
+        // every add of the workgroup is complete (performed where device-scope
+        // atomics to that address are ordered) before the target's count moves
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (my_sig >= 0)
+            __hip_atomic_fetch_add(cnt + my_sig, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 template <class R>
@@ -780,6 +824,28 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
                                                 KArgs a, const uint8_t* __restrict__ pair_excl,
                                                 R* __restrict__ arena) {
     update_task<R>(tiles[xcd_tile(blockIdx.x, ntiles)], a, pair_excl, arena, nullptr);
+}
+
+// Deterministic order: every workgroup takes the next tile of the list (the
+// level's tiles, sources in increasing order) by an atomic ticket, so that a
+// tile's waits point only at tiles that workgroups already hold.
+template <class R>
+__global__ __launch_bounds__(256) void k_update_ord(const UpdTile* __restrict__ tiles, KArgs a,
+                                                    const uint8_t* __restrict__ pair_excl,
+                                                    const int32_t* __restrict__ pair_thr,
+                                                    int32_t* __restrict__ cnt,
+                                                    int32_t* __restrict__ ticket,
+                                                    int32_t* __restrict__ late,
+                                                    uint64_t wait_ticks, R* __restrict__ arena) {
+    __shared__ int32_t sh_tile;
+    __shared__ uint64_t sh_deadline;
+    if (threadIdx.x == 0) {
+        sh_tile = atomicAdd(ticket, 1);
+        sh_deadline = wall_clock64() + wait_ticks;
+    }
+    __syncthreads();
+    update_task<R>(tiles[sh_tile], a, pair_excl, arena, nullptr, pair_thr, cnt, sh_deadline,
+                   late);
 }
 
 // ---------------------------------------------------------------------------
@@ -802,7 +868,10 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
 // the error, and every worker exits at its next poll.
 //
 // State layout (int32): cntF[nsup], doneF[nsup], doneT[nrowblk], ctrl[4]
-// with ctrl = {ticket, abort, error, unused}.
+// with ctrl = {ticket, abort, error, clock}.  With a log (two int32 per
+// task), a task's entry gets a stamp of the clock when its inputs are done
+// and another when its results are written, before its successors are
+// signalled.
 
 __global__ void k_sched_reset(const int32_t* __restrict__ cnt0, int32_t* __restrict__ state,
                               int64_t nsup, int64_t total) {
@@ -837,7 +906,8 @@ template <class R>
 __global__ __launch_bounds__(kSchedThreads) void k_sched(
     const Task* __restrict__ tasks, int64_t ntasks, const int32_t* __restrict__ rb_base, KArgs a,
     R* __restrict__ arena, R* __restrict__ dinv, int32_t* __restrict__ status,
-    int32_t* __restrict__ state, int64_t nsup, int64_t nrowblk, uint64_t wait_ticks) {
+    int32_t* __restrict__ state, int64_t nsup, int64_t nrowblk, uint64_t wait_ticks,
+    int32_t* __restrict__ log) {
     extern __shared__ double T[];
     __shared__ int32_t sh_ticket;
     __shared__ int coltgt[kTile];
@@ -863,6 +933,7 @@ __global__ __launch_bounds__(kSchedThreads) void k_sched(
                          (tk.a == tk.b || wait_eq(doneT + rb + tk.b, 1, ctrl, deadline));
                 }
                 if (!ok) t = -1;
+                else if (log) log[2 * (int64_t)t] = atomicAdd(ctrl + 3, 1);
             }
             sh_ticket = t;
         }
@@ -880,6 +951,7 @@ __global__ __launch_bounds__(kSchedThreads) void k_sched(
         }
         __threadfence();  // release: this task's results before its signal
         __syncthreads();
+        if (log && tid == 0) log[2 * (int64_t)t + 1] = atomicAdd(ctrl + 3, 1);
         if (tk.kind == kTaskF) {
             if (tid == 0)
                 __hip_atomic_store(doneF + tk.s, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -956,6 +1028,10 @@ void launch_ft(spc_numeric* num, const DevicePlan* P, const Symbolic& S, const K
         ev = mark_begin(num, st);
         launch_small_factor(num, a, P->level_sn + n0 + nbig, n1 - n0 - nbig, P->small_maxw[l],
                             P->small_maxr[l], P->small_maxm[l], st);
+        // deterministic order: the shared targets take the small sources'
+        // blocks from the scratch, one wave per target, sources in order
+        if (num->det_state && P->app_ptr[l + 1] > P->app_ptr[l])
+            launch_small_apply(num, P->app_ptr[l], P->app_ptr[l + 1], st);
         mark_end(num, st, 5, ev);
     }
     const int64_t rb0 = P->rowblk_ptr[l], rb1 = P->rowblk_ptr[l + 1];
@@ -969,12 +1045,23 @@ void launch_ft(spc_numeric* num, const DevicePlan* P, const Symbolic& S, const K
 
 template <class R>
 void launch_update(spc_numeric* num, const DevicePlan* P, const KArgs& a, int64_t u0, int64_t u1,
-                   bool exclusive_ok, hipStream_t st) {
+                   bool exclusive_ok, hipStream_t st, int32_t level = -1) {
     if (u1 <= u0) return;
     const int ev = mark_begin(num, st);
-    hipLaunchKernelGGL(k_update<R>, dim3((unsigned)(u1 - u0)), dim3(256), 0, st, P->tiles + u0,
-                       u1 - u0, a, exclusive_ok ? (const uint8_t*)P->pair_excl : nullptr,
-                       (R*)num->arena);
+    if (num->det_state && level >= 0 && P->level_ordered[level]) {
+        const Symbolic& S = num->sym->S;
+        const int64_t nsup = S.nsup, nl = (int64_t)S.level_ptr.size() - 1;
+        hipLaunchKernelGGL(k_update_ord<R>, dim3((unsigned)(u1 - u0)), dim3(256), 0, st,
+                           P->tiles + u0, a, (const uint8_t*)P->pair_excl,
+                           (const int32_t*)P->pair_thr, num->det_state,
+                           num->det_state + nsup + level, num->det_state + nsup + nl,
+                           num->det_wait_ticks, (R*)num->arena);
+    } else {
+        hipLaunchKernelGGL(k_update<R>, dim3((unsigned)(u1 - u0)), dim3(256), 0, st,
+                           P->tiles + u0, u1 - u0, a,
+                           exclusive_ok ? (const uint8_t*)P->pair_excl : nullptr,
+                           (R*)num->arena);
+    }
     mark_end(num, st, 3, ev);
 }
 
@@ -1007,6 +1094,11 @@ int32_t run_factor_t(spc_numeric* num, const double* values, hipStream_t st) {
     if (S.nnz_a > 0)
         hipLaunchKernelGGL(k_load<R>, dim3(grid_for(S.nnz_a, 256)), dim3(256), 0, st, values,
                            P->slot, arena, S.nnz_a);
+    if (num->det_state) {  // scatter counts and tile tickets start from zero
+        const int64_t ints = S.nsup + (int64_t)S.level_ptr.size();
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(ints, 256)), dim3(256), 0, st,
+                           num->det_state, ints, (int32_t)0);
+    }
     mark_end(num, st, 0, ev);
     const int32_t nl = (int32_t)S.level_ptr.size() - 1;
     if (num->sched == 2) {
@@ -1021,15 +1113,16 @@ int32_t run_factor_t(spc_numeric* num, const double* values, hipStream_t st) {
             HIP_TRY(hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev));
             HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sched<R>,
                                                                 kSchedThreads, lds_tri));
-            const int64_t workers =
+            int64_t workers =
                 std::min<int64_t>(P->ntasks, (int64_t)std::max(1, ncu) * std::max(1, per_cu));
+            if (S.opt.workers > 0) workers = std::min<int64_t>(workers, S.opt.workers);
             const uint64_t ticks =
                 (uint64_t)num->spin_limit * (uint64_t)std::max(1, clock_khz) / 1000;
             ev = mark_begin(num, st);
             hipLaunchKernelGGL(k_sched<R>, dim3((unsigned)workers), dim3(kSchedThreads), lds_tri,
                                st, (const Task*)P->tasks, P->ntasks, (const int32_t*)P->rb_base,
                                a, arena, (R*)num->dinv, num->status_dev, num->sched_state,
-                               S.nsup, P->nrowblk, ticks);
+                               S.nsup, P->nrowblk, ticks, num->task_log);
             mark_end(num, st, 4, ev);
         }
     } else {
@@ -1039,7 +1132,7 @@ int32_t run_factor_t(spc_numeric* num, const double* values, hipStream_t st) {
             if (num->sched == 0 || nl < 2) {
                 for (int32_t l = 0; l < nl; ++l) {
                     launch_ft<R>(num, P, S, a, l, m);
-                    launch_update<R>(num, P, a, P->tile_ptr[l], P->tile_ptr[l + 1], true, m);
+                    launch_update<R>(num, P, a, P->tile_ptr[l], P->tile_ptr[l + 1], true, m, l);
                 }
                 return OK;
             }
@@ -1101,6 +1194,7 @@ int32_t run_factor_t(spc_numeric* num, const double* values, hipStream_t st) {
 int32_t run_factor(spc_numeric* num, const double* values, hipStream_t st) {
     num->stream = st;
     num->factored = false;
+    num->fb_current = false;  // an FP64 fallback factor belongs to the previous values
     num->status_known = false;
     num->marks.clear();
     num->next_event = 0;

@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "../../include/spchol.h"
 #include "runtime.hpp"
 
 namespace spc {
@@ -257,18 +258,58 @@ __global__ void k_scatter_add(const R* __restrict__ y, const int32_t* __restrict
     }
 }
 
+// One correction with factor f (num itself, or its FP64 fallback factor),
+// the batch segments and norms of num.
 template <class R>
-void correction(spc_numeric* num, int32_t nrhs, const double* r, const double* scale,
-                const double* rn, double* x, int64_t ldx, hipStream_t st, int32_t* rc) {
+void correction(spc_numeric* num, spc_numeric* f, int32_t nrhs, const double* r,
+                const double* scale, const double* rn, double* x, int64_t ldx, hipStream_t st,
+                int32_t* rc) {
     const int64_t n = num->sym->S.n;
-    const int32_t* perm = num->plan->perm;
+    const int32_t* perm = f->plan->perm;
     const int g = grid_of(n * nrhs);
     hipLaunchKernelGGL(k_gather_scaled<R>, dim3(g), dim3(256), 0, st, r, perm,
-                       (const int32_t*)num->a_seg, num->nseg, scale, (R*)num->work, n, nrhs);
-    *rc = run_sweeps(num, nrhs, st);
+                       (const int32_t*)num->a_seg, num->nseg, scale, (R*)f->work, n, nrhs);
+    *rc = run_sweeps(f, nrhs, st);
     if (*rc != OK) return;
-    hipLaunchKernelGGL(k_scatter_add<R>, dim3(g), dim3(256), 0, st, (const R*)num->work, perm,
+    hipLaunchKernelGGL(k_scatter_add<R>, dim3(g), dim3(256), 0, st, (const R*)f->work, perm,
                        (const int32_t*)num->a_seg, num->nseg, rn, x, ldx, n, nrhs);
+}
+
+// A's values in the caller's order, from the refinement copy (every input
+// entry appears once or, off the diagonal, twice with the same value).
+__global__ void k_values_from_csr(const double* __restrict__ val, const int64_t* __restrict__ src,
+                                  double* __restrict__ out, int64_t nnzf) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnzf;
+         e += (int64_t)gridDim.x * blockDim.x)
+        out[src[e]] = val[e];
+}
+
+// The FP64 factor of num's matrix for stalled refinement: allocated on first
+// use, factored from the refinement copy of A once per factorization of num.
+int32_t fallback_factor(spc_numeric* num, int32_t nrhs, hipStream_t st) {
+    if (!num->fb) {
+        int32_t rc = numeric_create_prec(num->sym, 0, &num->fb);
+        if (rc != OK) return rc;
+        const int64_t nnz = num->sym->S.nnz_a;
+        if (hipMalloc(&num->fb_values, sizeof(double) * (size_t)std::max<int64_t>(nnz, 1)) !=
+            hipSuccess)
+            return ERR_OOM;
+        num->fb_current = false;
+    }
+    int32_t rc = ensure_solve_work(num->fb, nrhs);
+    if (rc != OK) return rc;
+    if (!num->fb_current) {
+        if (num->a_nnz > 0)
+            hipLaunchKernelGGL(k_values_from_csr, dim3(grid_of(num->a_nnz)), dim3(256), 0, st,
+                               (const double*)num->a_val, (const int64_t*)num->a_src,
+                               num->fb_values, num->a_nnz);
+        rc = run_factor(num->fb, num->fb_values, st);
+        if (rc != OK) return rc;
+        rc = spc_numeric_status(num->fb);
+        if (rc != OK) return rc;
+        num->fb_current = true;
+    }
+    return OK;
 }
 
 }  // namespace
@@ -405,6 +446,12 @@ int32_t run_refine(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb,
     double* scale = eta + ne;
     const int32_t* seg = num->a_seg;
     const dim3 grid_rows(row_blocks(n), nrhs);
+    // stall: consecutive steps whose worst eta did not halve; two of them on
+    // an FP32 factor switch the corrections to the FP64 factor, on an FP64
+    // factor they end the refinement
+    int stall = 0;
+    double prev_worst = 0.0;
+    bool on_fb = false;
     hipLaunchKernelGGL(k_zero_cols, dim3(grid_of(n * nrhs)), dim3(256), 0, st, x, ldx, n, nrhs);
     hipLaunchKernelGGL(k_fill_f64, dim3(grid_of(ne)), dim3(256), 0, st, bn, ne, 0.0);
     hipLaunchKernelGGL(k_colmax, grid_rows, dim3(256), 0, st, b, ldb, n, seg, ns, bn);
@@ -426,18 +473,32 @@ int32_t run_refine(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb,
                                st));
         HIP_TRY(hipStreamSynchronize(st));
         bool done = true;
+        double worst = 0.0;
         for (int64_t e = 0; e < ne; ++e) {
             const double v = num->ir_host[e];
             if (berr) berr[e] = v;
             if (!(v <= tol)) done = false;
+            worst = (v > worst || v != v) ? v : worst;
         }
         if (iters) *iters = it;
         if (done) return OK;
         if (it >= max_iter) return ERR_NOT_CONVERGED;
-        if (num->prec == 1)
-            correction<float>(num, nrhs, r, scale, rn, x, ldx, st, &rc);
+        if (it > 0) stall = (worst > 0.5 * prev_worst || worst != worst) ? stall + 1 : 0;
+        prev_worst = worst;
+        if (stall >= 2) {
+            if (num->prec != 1 || on_fb) return ERR_NOT_CONVERGED;
+            rc = fallback_factor(num, nrhs, st);
+            if (rc != OK) return rc;
+            on_fb = true;
+            stall = 0;
+            num->refine_fallbacks++;
+        }
+        if (on_fb)
+            correction<double>(num, num->fb, nrhs, r, scale, rn, x, ldx, st, &rc);
+        else if (num->prec == 1)
+            correction<float>(num, num, nrhs, r, scale, rn, x, ldx, st, &rc);
         else
-            correction<double>(num, nrhs, r, scale, rn, x, ldx, st, &rc);
+            correction<double>(num, num, nrhs, r, scale, rn, x, ldx, st, &rc);
         if (rc != OK) return rc;
         HIP_TRY(hipGetLastError());
     }

@@ -107,10 +107,32 @@ struct DevicePlan {
     // device task-queue schedule (only when analyzed with sched 2)
     Task* tasks = nullptr;
     int64_t ntasks = 0;
+    std::vector<Task> host_tasks;  // the task order, kept for the execution log
     int32_t* cnt0 = nullptr;     // per supernode: update tiles that scatter into it
     int32_t* rb_base = nullptr;  // per supernode: index of its first panel row block
     int64_t nrowblk = 0;
     int32_t max_w = 0;
+    // deterministic scatter order (analysis option deterministic = 1)
+    int32_t* pair_src = nullptr;  // source supernode of each pair
+    int32_t* pair_end = nullptr;  // seg_end of each pair
+    int32_t* pair_thr = nullptr;  // large sources, shared target: the target's count of
+                                  // finished (tile, target) scatters to wait for
+    int64_t* small_scr = nullptr; // small sources: offset of the update block in the
+                                  // level's scratch (-1: every target exclusive)
+    int32_t* app_t = nullptr;     // apply items: target supernode of item k
+    int64_t* app_p0 = nullptr;    // pairs of item k: app_pairs[app_p0[k] .. app_p0[k + 1])
+    int32_t* app_pairs = nullptr; // small-source pairs in source order
+    // solves: forward contributions are kept per entry of `rows` (the below-
+    // diagonal rows of every supernode) and pulled by the target's rows
+    int64_t* rc_ptr = nullptr;    // n + 1: contributions to row j at rc_slot[rc_ptr[j] ..]
+    int32_t* rc_slot = nullptr;   // positions in rows, sources in increasing order
+    int64_t* pb_off = nullptr;    // per supernode: its backward partial sums (row block b,
+                                  // column k at pb_off + b w + k; large supernodes)
+    int64_t nslots = 0;           // entries of rows
+    int64_t pb_total = 0;
+    std::vector<uint8_t> level_ordered;  // the level's tiles wait on shared targets
+    std::vector<int64_t> app_ptr;        // per level: its apply items
+    int64_t det_scratch = 0;             // elements of the per-level update scratch
     // host-side launch bookkeeping per level; inside each level of level_sn
     // the large supernodes come first, then the small ones
     std::vector<int32_t> level_nbig;
@@ -120,6 +142,28 @@ struct DevicePlan {
     std::vector<int32_t> small_maxw, small_maxr, small_maxm;  // widest / tallest (below, all) small
                                                               // supernode of the level
 };
+
+// Contribution slots of the forward solve and the partial sums of the
+// backward solve, with the plan's lists that address them.
+template <class R>
+struct SolveBufs {
+    R* cb;                    // nslots x nrhs: (L21 y_s)[i] at the slot of row i of s
+    R* pb;                    // pb_total x nrhs: backward partial sums
+    int64_t nslots, pb_total;
+    const int64_t* rc_ptr;    // row j pulls cb at rc_slot[rc_ptr[j] .. rc_ptr[j + 1])
+    const int32_t* rc_slot;
+    const int64_t* pb_off;
+};
+
+// y[j] minus every contribution to row j, in increasing source order.
+template <class R>
+__device__ inline R pulled(const R* __restrict__ yc, const R* __restrict__ cbc,
+                                    const SolveBufs<R>& sb, int64_t j) {
+    R v = yc[j];
+    const int64_t q1 = sb.rc_ptr[j + 1];
+    for (int64_t q = sb.rc_ptr[j]; q < q1; ++q) v -= cbc[sb.rc_slot[q]];
+    return v;
+}
 
 // Pointer bundle passed by value to kernels.
 struct KArgs {
@@ -145,6 +189,7 @@ struct spc_symbolic {
     std::mutex mu;
     std::vector<spc::DevicePlan*> plans;  // one per device that used it
     size_t plan_bytes_estimate = 0;
+    int64_t det_scratch = 0;  // elements of a factor's update scratch (deterministic order)
     int64_t budget = 0;  // mem_budget_bytes of the options (0 = none)
 };
 
@@ -162,6 +207,11 @@ struct spc_numeric {
     std::vector<hipEvent_t> sync_ev; // per-level ordering events between the two streams
     hipStream_t capture = nullptr;  // stream the solve sweeps are captured on
     int32_t* sched_state = nullptr; // task-queue counters: cntF, doneF, doneT, ticket/abort/err
+    int32_t* det_state = nullptr;   // deterministic order: finished (tile, target) scatters per
+                                    // supernode, one tile ticket per level, a late-wait flag
+    uint64_t det_wait_ticks = 0;    // bound of an ordered wait, wall-clock ticks
+    void* det_scratch = nullptr;    // small sources' update blocks of one level (factor type)
+    int32_t* task_log = nullptr;    // sched 2 with debug bit 1: start and finish stamps per task
     int64_t spin_limit = 0;
     struct SolveGraph { int32_t nrhs; hipGraph_t graph; hipGraphExec_t exec; };
     std::vector<SolveGraph> solve_graphs;
@@ -186,6 +236,13 @@ struct spc_numeric {
     double* ir_work = nullptr;      // residuals n x ir_cols, then 4 x ir_cols norms/scales
     int64_t ir_cols = 0;
     double* ir_host = nullptr;      // pinned: backward errors of the current iterate
+    // FP64 factor of the same matrix for refinement that stalls on an FP32
+    // factor: made on first need from the refinement copy of A, reused until
+    // the next factorization of this object
+    spc_numeric* fb = nullptr;
+    double* fb_values = nullptr;    // A's values in the caller's order (nnz_a)
+    bool fb_current = false;
+    int64_t refine_fallbacks = 0;   // refinement solves that switched to fb
     // optional per-launch event timing (class, start, stop)
     bool timing = false;
     std::vector<hipEvent_t> events;
@@ -196,7 +253,9 @@ struct spc_numeric {
 
 namespace spc {
 
-size_t plan_bytes(const Symbolic& S);
+// Device bytes of the plan; *det_scratch (may be null) receives the elements
+// of the per-level update scratch of the deterministic order.
+size_t plan_bytes(const Symbolic& S, int64_t* det_scratch);
 int32_t build_task_order(const Symbolic& S, int workers, std::vector<Task>& order,
                          std::vector<int32_t>& cnt0, std::vector<int32_t>& rb_base);
 int64_t inverse_blocks_elems(const Symbolic& S);
@@ -214,13 +273,22 @@ int32_t run_refine(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb,
                    int32_t* iters, double* berr);
 // Gathers the caller's values into the refinement copy of A (FP64).
 int32_t load_refine_matrix(spc_numeric* num, const double* values, hipStream_t stream);
+int32_t numeric_create_prec(spc_symbolic* sym, int32_t prec, spc_numeric** out);
 void free_refine(spc_numeric* num);
 void drop_solve_graphs(spc_numeric* num);
 // Small-supernode kernels (one wave per supernode of list[0 .. count)).
 void launch_small_factor(spc_numeric* num, const KArgs& a, const int32_t* list, int count,
                          int maxw, int maxr, int maxm, hipStream_t st);
+// Deterministic order: apply items [i0, i1) of the plan (one wave per shared
+// target adds the level's small sources' blocks from the scratch in order).
+void launch_small_apply(spc_numeric* num, int64_t i0, int64_t i1, hipStream_t st);
+// y: the solve vector; cb: the forward contribution slots (factor type).
 void launch_small_solve(spc_numeric* num, const KArgs& a, const int32_t* list, int count,
-                        int maxw, int maxm, void* y, int64_t n, int nrhs, bool forward,
+                        int maxw, int maxm, void* y, void* cb, int64_t n, int nrhs, bool forward,
                         hipStream_t st);
+// Elements of the solve work (y, contribution slots, backward partial sums)
+// for nrhs right-hand sides.
+int64_t solve_work_elems(const spc_numeric* num, int32_t nrhs);
+int64_t solve_work_elems_per_rhs(const Symbolic& S);
 
 }  // namespace spc

@@ -32,7 +32,7 @@
 
 namespace spc {
 int32_t numeric_create(spc_symbolic* sym, spc_numeric** out);
-int64_t numeric_bytes(const Symbolic& S);
+int64_t numeric_bytes(const spc_symbolic* sym);
 }  // namespace spc
 
 using namespace spc;
@@ -55,6 +55,9 @@ struct Fact {
 struct Pattern {
     spc_symbolic* sym = nullptr;
     int64_t bytes = 0;           // predicted device bytes of one factor with its work
+    int64_t plan_bytes = 0;      // the symbolic handle's device plan, made with the first
+                                 // factor and kept until the handle is freed
+    bool plan_charged = false;   // plan_bytes counted in the server's bytes
     Fact* current = nullptr;
     std::vector<Fact*> pool;
 };
@@ -69,6 +72,7 @@ struct Req {
     bool done = false;                   // retired: the waiter may read it
     std::atomic<bool> dev_done{false};   // set by the stream's host function
     struct spc_server* srv = nullptr;
+    hipEvent_t ready = nullptr;          // recorded on the caller's stream at submission
 };
 
 }  // namespace
@@ -101,9 +105,12 @@ namespace {
 // one poll interval).
 void on_done(void* p) {
     Req* q = (Req*)p;
+    // once dev_done is set the scheduler may retire the request and a waiter
+    // may free it: take the server pointer first and touch q no more after
+    spc_server* srv = q->srv;
     q->t_done = Clock::now();
     q->dev_done.store(true, std::memory_order_release);
-    q->srv->cv.notify_all();
+    srv->cv.notify_all();
 }
 
 void destroy_fact(spc_server* s, Fact* f) {
@@ -158,6 +165,10 @@ int32_t new_fact(spc_server* s, int32_t pat, Fact** out) {
         return st;
     }
     s->bytes += f->bytes;
+    if (!p.plan_charged) {
+        s->bytes += p.plan_bytes;
+        p.plan_charged = true;
+    }
     p.pool.push_back(f);
     *out = f;
     return OK;
@@ -169,7 +180,9 @@ int32_t launch(Req* q) {
     spc_numeric* num = f->num;
     const spc_request& r = q->r;
     int32_t st = OK;
-    if (r.kind == 0) {
+    // the caller's work on values, b and x (up to submission) comes first
+    if (q->ready && hipStreamWaitEvent(f->st, q->ready, 0) != hipSuccess) st = ERR_HIP;
+    if (st == OK && r.kind == 0) {
         st = run_factor(num, r.values, f->st);
         if (st == OK &&
             hipMemcpyAsync(f->hstatus, num->status_dev, sizeof(int32_t), hipMemcpyDeviceToHost,
@@ -212,7 +225,8 @@ void admit(spc_server* s, std::vector<Req*>& go) {
             for (Fact* g : p.pool)
                 if (g->refs == 0 && !g->current) f = g;
             if (!f) {
-                if (p.bytes > s->opt.mem_budget_bytes) {
+                const int64_t need = p.bytes + (p.plan_charged ? 0 : p.plan_bytes);
+                if (p.bytes + p.plan_bytes > s->opt.mem_budget_bytes) {
                     q->status = ERR_OOM;
                     q->t_done = Clock::now();
                     s->finished.push_back(q);
@@ -220,7 +234,7 @@ void admit(spc_server* s, std::vector<Req*>& go) {
                     it = s->queue.erase(it);
                     continue;
                 }
-                if (!make_room(s, p.bytes) || new_fact(s, q->r.pattern, &f) != OK) {
+                if (!make_room(s, need) || new_fact(s, q->r.pattern, &f) != OK) {
                     if (s->inflight == 0) {  // nothing will free memory: give up on it
                         q->status = ERR_OOM;
                         q->t_done = Clock::now();
@@ -260,6 +274,10 @@ void retire(spc_server* s) {
         }
     }
     for (Req* q : s->finished) {
+        if (q->ready) {  // its wait is behind it on the stream (or never enqueued)
+            (void)hipEventDestroy(q->ready);
+            q->ready = nullptr;
+        }
         if (q->f) {
             Fact* f = q->f;
             if (q->r.kind == 0) {
@@ -376,7 +394,14 @@ spc_status spc_server_add_pattern(spc_server* s, spc_symbolic* sym, int32_t* pat
     p.sym = sym;
     const Symbolic& S = sym->S;
     const size_t elem = S.opt.precision == 1 ? sizeof(float) : sizeof(double);
-    p.bytes = numeric_bytes(S) + (int64_t)(2 * elem * (size_t)S.n * (size_t)s->opt.max_nrhs);
+    p.bytes = numeric_bytes(sym) +
+              (int64_t)elem * solve_work_elems_per_rhs(S) * (int64_t)s->opt.max_nrhs;
+    p.plan_bytes = (int64_t)sym->plan_bytes_estimate;
+    {
+        // the server keeps the handle referenced until spc_server_destroy
+        std::lock_guard<std::mutex> sl(sym->mu);
+        sym->refs++;
+    }
     s->patterns.push_back(p);
     *pattern = (int32_t)s->patterns.size() - 1;
     return SPC_OK;
@@ -394,6 +419,15 @@ spc_status spc_server_submit(spc_server* s, const spc_request* r, int64_t* ticke
     if (r->nrhs > 0 && n > 0 && (!r->b || !r->x || r->ldb < n || r->ldx < n)) return SPC_ERR_ARG;
     std::unique_ptr<Req> q(new (std::nothrow) Req());
     if (!q) return SPC_ERR_OOM;
+    // order the request after the caller's stream work up to this call
+    if (hipEventCreateWithFlags(&q->ready, hipEventDisableTiming) != hipSuccess) {
+        q->ready = nullptr;
+        return SPC_ERR_HIP;
+    }
+    if (hipEventRecord(q->ready, (hipStream_t)r->stream) != hipSuccess) {
+        (void)hipEventDestroy(q->ready);
+        return SPC_ERR_HIP;
+    }
     q->ticket = s->next_ticket++;
     q->r = *r;
     q->srv = s;
@@ -441,8 +475,11 @@ spc_status spc_server_destroy(spc_server* s) {
         s->cv.notify_all();
     }
     if (s->worker.joinable()) s->worker.join();
-    for (Pattern& p : s->patterns)
+    for (Pattern& p : s->patterns) {
         for (Fact* f : p.pool) destroy_fact(s, f);
+        std::lock_guard<std::mutex> sl(p.sym->mu);
+        p.sym->refs--;
+    }
     delete s;
     return SPC_OK;
 }

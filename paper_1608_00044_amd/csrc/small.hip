@@ -62,11 +62,23 @@ __device__ __forceinline__ float wave_sum(float v) {
 // times its starting diagonal entry makes the function return true before
 // anything is written to global memory, so that the caller can run it again
 // in FP64.
+// Deterministic order (det.scratch set): a column whose pair is exclusive
+// (no other source of the level updates its target) is added to the target
+// directly; the other columns go to the supernode's block in the level's
+// scratch (column c, row i >= c of the r x r lower triangle at
+// c (2r - c + 1) / 2 + i - c), which the apply kernel adds in source order.
+template <class S>
+struct SmallDet {
+    const uint8_t* excl;
+    const int64_t* scr_off;
+    S* scratch;
+};
+
 template <class S, class C, bool kCheck, int G, int LDG>
 __device__ bool small_body(int s, const KArgs& a, S* __restrict__ arena, S* __restrict__ dinv,
                            int32_t* __restrict__ status, C* __restrict__ blk,
                            int64_t* __restrict__ colbase, int64_t* __restrict__ relbase,
-                           int gl) {
+                           int gl, const SmallDet<S>& det) {
     const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
     const int64_t rp = a.rowptr[s];
     const int m = (int)(a.rowptr[s + 1] - rp), r = m - w;
@@ -95,7 +107,9 @@ __device__ bool small_body(int s, const KArgs& a, S* __restrict__ arena, S* __re
         const int64_t at = rp + w + gl;
         const int p = a.rowpair[at];
         const int t = a.pair_tgt[p];
-        colbase[gl] = a.sn_off[t] + (int64_t)(a.rows[at] - a.sn_first[t]) * a.sn_ld[t];
+        const int64_t cb = a.sn_off[t] + (int64_t)(a.rows[at] - a.sn_first[t]) * a.sn_ld[t];
+        // deterministic order: a shared target's column is marked by ~cb (< 0)
+        colbase[gl] = (det.scratch && !det.excl[p]) ? ~cb : cb;
         relbase[gl] = a.pair_rel[p] - a.pair_seg[p];
     }
     __builtin_amdgcn_wave_barrier();
@@ -163,7 +177,16 @@ __device__ bool small_body(int s, const KArgs& a, S* __restrict__ arena, S* __re
 #pragma unroll
                     for (int k = 0; k < kSmallW; ++k)
                         if (k < w) v += li[k] * blk[k * LDG + w + c];
-                    unsafeAtomicAdd(arena + colbase[c] + rv[u], (S)(-v));
+                    const int64_t cb = colbase[c];
+                    if (!det.scratch) {
+                        unsafeAtomicAdd(arena + cb + rv[u], (S)(-v));
+                    } else if (cb >= 0) {  // the only source of the level for this target
+                        S* q = arena + cb + rv[u];
+                        *q = *q + (S)(-v);
+                    } else {
+                        const int64_t at = (int64_t)c * (2 * r - c + 1) / 2 + (gl - c);
+                        det.scratch[det.scr_off[s] + at] = (S)(-v);
+                    }
                 }
             }
         }
@@ -174,17 +197,19 @@ __device__ bool small_body(int s, const KArgs& a, S* __restrict__ arena, S* __re
 template <int G, int LDG>
 __device__ __forceinline__ void small_factor(int s, const KArgs& a, double* arena, double* dinv,
                                              int32_t* status, int32_t*, double* lds,
-                                             int64_t* cb, int64_t* rb, int gl) {
-    small_body<double, double, false, G, LDG>(s, a, arena, dinv, status, lds, cb, rb, gl);
+                                             int64_t* cb, int64_t* rb, int gl,
+                                             const SmallDet<double>& det) {
+    small_body<double, double, false, G, LDG>(s, a, arena, dinv, status, lds, cb, rb, gl, det);
 }
 template <int G, int LDG>
 __device__ __forceinline__ void small_factor(int s, const KArgs& a, float* arena, float* dinv,
                                              int32_t* status, int32_t* fallbacks, double* lds,
-                                             int64_t* cb, int64_t* rb, int gl) {
+                                             int64_t* cb, int64_t* rb, int gl,
+                                             const SmallDet<float>& det) {
     if (small_body<float, float, true, G, LDG>(s, a, arena, dinv, status, (float*)lds, cb, rb,
-                                               gl)) {
+                                               gl, det)) {
         __builtin_amdgcn_wave_barrier();
-        small_body<float, double, false, G, LDG>(s, a, arena, dinv, status, lds, cb, rb, gl);
+        small_body<float, double, false, G, LDG>(s, a, arena, dinv, status, lds, cb, rb, gl, det);
         if (gl == 0) atomicAdd(fallbacks, 1);
     }
 }
@@ -199,7 +224,7 @@ template <class R, int G, int LDG>
 __global__ __launch_bounds__(256) void k_small(const int32_t* __restrict__ list, int count,
                                                KArgs a, R* __restrict__ arena,
                                                R* __restrict__ dinv, int32_t* __restrict__ status,
-                                               int maxw, int maxr) {
+                                               int maxw, int maxr, SmallDet<R> det) {
     extern __shared__ double sm_small[];
     constexpr int kGroups = 4 * (64 / G);  // groups per workgroup
     const int lane = threadIdx.x & 63;
@@ -208,7 +233,46 @@ __global__ __launch_bounds__(256) void k_small(const int32_t* __restrict__ list,
     int64_t* cb = (int64_t*)(sm_small + (size_t)kGroups * LDG * maxw) + (size_t)grp * 2 * maxr;
     const int idx = blockIdx.x * kGroups + grp;
     if (idx >= count) return;
-    small_factor<G, LDG>(list[idx], a, arena, dinv, status, status + 1, blk, cb, cb + maxr, gl);
+    small_factor<G, LDG>(list[idx], a, arena, dinv, status, status + 1, blk, cb, cb + maxr, gl,
+                         det);
+}
+
+// Deterministic order: one wave per apply item (a target that several small
+// sources of the level share) adds those sources' blocks from the scratch,
+// pair by pair in increasing source order; the adds of one pair complete
+// before the next pair's start, so every target entry receives its
+// contributions in that order.
+template <class R>
+__global__ __launch_bounds__(256) void k_small_apply(const int32_t* __restrict__ app_t,
+                                                     const int64_t* __restrict__ app_p0,
+                                                     const int32_t* __restrict__ app_pairs,
+                                                     const int32_t* __restrict__ pair_src,
+                                                     const int32_t* __restrict__ pair_end,
+                                                     const int64_t* __restrict__ scr_off,
+                                                     const R* __restrict__ scratch, KArgs a,
+                                                     R* __restrict__ arena, int64_t count) {
+    const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (k >= count) return;
+    const int t = app_t[k];
+    const int64_t toff = a.sn_off[t];
+    const int tfirst = a.sn_first[t], tld = a.sn_ld[t];
+    for (int64_t q = app_p0[k]; q < app_p0[k + 1]; ++q) {
+        const int p = app_pairs[q];
+        const int s = pair_src[p];
+        const int w = a.sn_w[s];
+        const int64_t rp = a.rowptr[s];
+        const int r = (int)(a.rowptr[s + 1] - rp) - w;
+        const int b = a.pair_seg[p], e = pair_end[p];
+        const int64_t relb = a.pair_rel[p] - b;
+        const R* __restrict__ blk = scratch + scr_off[s];
+        for (int c = b; c < e; ++c) {
+            const int64_t cb = toff + (int64_t)(a.rows[rp + w + c] - tfirst) * tld;
+            const int64_t pk = (int64_t)c * (2 * r - c + 1) / 2 - c;
+            for (int i = c + lane; i < r; i += 64) unsafeAtomicAdd(arena + cb + a.rel[relb + i], blk[pk + i]);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+    }
 }
 
 template <int G, int LDG>
@@ -228,12 +292,14 @@ __device__ __forceinline__ T group_sum(T v) {
 
 // Forward solve of one small supernode per G lanes, every right-hand side
 // (WB: a bound on the level's small widths, so registers follow the level):
-//   y_s = inv(L11) y_s;  y[rows below] -= L21 y_s  (atomic: siblings share ancestors)
+//   y_s = inv(L11) (y_s - contributions pulled in source order);
+//   (L21 y_s)[i] into the contribution slot of each row i below.
 template <class R, int WB, int G>
 __global__ __launch_bounds__(256) void k_small_fwd(const int32_t* __restrict__ list, int count,
                                                    KArgs a, const R* __restrict__ arena,
                                                    const R* __restrict__ dinv,
-                                                   R* __restrict__ y, int64_t n, int nrhs) {
+                                                   R* __restrict__ y, int64_t n, int nrhs,
+                                                   SolveBufs<R> sb) {
     const int lane = threadIdx.x & 63, gl = lane % G;
     const int idx = blockIdx.x * (256 / G) + (int)threadIdx.x / G;
     if (idx >= count) return;
@@ -252,7 +318,8 @@ __global__ __launch_bounds__(256) void k_small_fwd(const int32_t* __restrict__ l
     const int32_t row = gl < r ? a.rows[rp + w + gl] : 0;
     for (int c = 0; c < nrhs; ++c) {
         R* __restrict__ yc = y + (int64_t)c * n;
-        const R b = gl < w ? yc[first + gl] : R(0);
+        R* __restrict__ cbc = sb.cb + (int64_t)c * sb.nslots;
+        const R b = gl < w ? pulled(yc, cbc, sb, first + gl) : R(0);
         R ys = R(0);
 #pragma unroll
         for (int k = 0; k < WB; ++k) ys += iv[k] * __shfl(b, k, G);
@@ -260,7 +327,7 @@ __global__ __launch_bounds__(256) void k_small_fwd(const int32_t* __restrict__ l
         R acc = R(0);
 #pragma unroll
         for (int k = 0; k < WB; ++k) acc += li[k] * __shfl(ys, k, G);
-        if (gl < r) unsafeAtomicAdd(yc + row, -acc);
+        if (gl < r) cbc[rp + w + gl] = acc;
     }
 }
 
@@ -313,11 +380,14 @@ void launch_small_factor(spc_numeric* num, const KArgs& a, const int32_t* list, 
     if (count <= 0) return;
     maxw = std::max(1, std::min(maxw, kSmallW));
     maxr = std::max(1, std::min(maxr, kSmallR));
+    const DevicePlan* P = num->plan;
     auto go = [&](auto kern, size_t lds, int per_block, auto* arena) {
         using T = std::remove_pointer_t<decltype(arena)>;
         const unsigned g = (unsigned)std::max(1, (count + per_block - 1) / per_block);
+        SmallDet<T> det{nullptr, nullptr, nullptr};
+        if (num->det_state) det = SmallDet<T>{P->pair_excl, P->small_scr, (T*)num->det_scratch};
         hipLaunchKernelGGL(kern, dim3(g), dim3(256), lds, st, list, count, a, arena,
-                           (T*)num->dinv, num->status_dev, maxw, maxr);
+                           (T*)num->dinv, num->status_dev, maxw, maxr, det);
     };
     // several supernodes per wave when every one of the level has few rows
     if (num->prec == 1) {
@@ -333,16 +403,37 @@ void launch_small_factor(spc_numeric* num, const KArgs& a, const int32_t* list, 
     }
 }
 
+void launch_small_apply(spc_numeric* num, int64_t i0, int64_t i1, hipStream_t st) {
+    const DevicePlan* P = num->plan;
+    const KArgs a = kargs(P);
+    const int64_t count = i1 - i0;
+    if (count <= 0) return;
+    const dim3 g((unsigned)((count + 3) / 4)), b(256);
+    if (num->prec == 1)
+        hipLaunchKernelGGL(k_small_apply<float>, g, b, 0, st, P->app_t + i0, P->app_p0 + i0,
+                           (const int32_t*)P->app_pairs, (const int32_t*)P->pair_src,
+                           (const int32_t*)P->pair_end, (const int64_t*)P->small_scr,
+                           (const float*)num->det_scratch, a, (float*)num->arena, count);
+    else
+        hipLaunchKernelGGL(k_small_apply<double>, g, b, 0, st, P->app_t + i0, P->app_p0 + i0,
+                           (const int32_t*)P->app_pairs, (const int32_t*)P->pair_src,
+                           (const int32_t*)P->pair_end, (const int64_t*)P->small_scr,
+                           (const double*)num->det_scratch, a, (double*)num->arena, count);
+}
+
 void launch_small_solve(spc_numeric* num, const KArgs& a, const int32_t* list, int count,
-                        int maxw, int maxm, void* y, int64_t n, int nrhs, bool forward,
+                        int maxw, int maxm, void* y, void* cb, int64_t n, int nrhs, bool forward,
                         hipStream_t st) {
     if (count <= 0) return;
+    const DevicePlan* P = num->plan;
     auto go = [&](auto kf, auto kb, int per_block, auto* yt) {
         using T = std::remove_pointer_t<decltype(yt)>;
         const dim3 g((unsigned)std::max(1, (count + per_block - 1) / per_block)), b(256);
+        const SolveBufs<T> sb{(T*)cb, nullptr, P->nslots, P->pb_total, P->rc_ptr, P->rc_slot,
+                              P->pb_off};
         if (forward)
             hipLaunchKernelGGL(kf, g, b, 0, st, list, count, a, (const T*)num->arena,
-                               (const T*)num->dinv, yt, n, nrhs);
+                               (const T*)num->dinv, yt, n, nrhs, sb);
         else
             hipLaunchKernelGGL(kb, g, b, 0, st, list, count, a, (const T*)num->arena,
                                (const T*)num->dinv, yt, n, nrhs);

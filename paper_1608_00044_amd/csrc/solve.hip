@@ -3,17 +3,22 @@
 // elimination tree from the leaves, then z = L^{-T} y from the root back, and
 // x = P^T z.  Both sweeps go level by level; within a level every supernode
 // is independent.  Each level is two launches:
-//   forward:  k_fwd_diag  -- y_s = L11^{-1} y_s, one workgroup per supernode, by
-//                            16-column panels using the inverted 16 x 16
-//                            diagonal blocks the factorization kept;
-//             k_fwd_gemv  -- y[rows below] -= L21 y_s for every 64-row block
-//                            of every panel (atomic adds: sibling supernodes
-//                            share ancestor rows);
-//   backward: k_bwd_gemv  -- t_s += L21^T y[rows below], per 64-row block,
-//                            one thread per column;
-// Several right-hand sides go through every kernel in groups of eight, so the
-// factor is read once per group.
-//             k_bwd_diag  -- y_s = L11^{-T} (y_s - t_s), panels in reverse.
+//   forward:  k_fwd_diag  -- y_s = L11^{-1} (y_s - the contributions of the
+//                            descendants to rows of s), one workgroup per
+//                            supernode, by 16-column panels using the inverted
+//                            16 x 16 diagonal blocks the factorization kept;
+//             k_fwd_gemv  -- (L21 y_s)[i] for every row i of every 64-row
+//                            block of the panel, stored in the contribution
+//                            slot of that row of s (its place in the row
+//                            lists), which the target's diagonal solve pulls
+//                            in increasing source order;
+//   backward: k_bwd_gemv  -- partial sums of L21^T y[rows below], one per
+//                            64-row block and column (one thread per column);
+//             k_bwd_diag  -- y_s = L11^{-T} (y_s - t_s), t_s the sum of the
+//                            partial sums in row-block order, panels in reverse.
+// No update is an atomic add: every sum has one fixed order, so a solve has
+// the same bits on every run.  Several right-hand sides go through every
+// kernel in groups of eight, so the factor is read once per group.
 // The level sweeps are captured once per right-hand-side count into a HIP
 // graph and replayed, so a solve costs three launches on the host.  The
 // kernels are templates on the factor's real type R: an FP32 factor is
@@ -141,10 +146,10 @@ __device__ __forceinline__ void stage_rows(R* __restrict__ Pl, const R* __restri
     }
 }
 
-// Diagonal block, forward: y_s = L11^{-1} y_s.  The workgroup stages L11
-// (packed lower triangle) and the 16 x 16 diagonal-block inverses in LDS;
-// then each wave solves its own right-hand sides with no workgroup barrier,
-// right-looking by panels:
+// Diagonal block, forward: y_s = L11^{-1} (y_s minus the pulled contributions).
+// The workgroup stages L11 (packed lower triangle) and the 16 x 16
+// diagonal-block inverses in LDS; then each wave pulls and solves its own
+// right-hand sides with no workgroup barrier, right-looking by panels:
 //   y_p = inv(D_p) y_p                      (lane (j, part): four products,
 //                                             the parts meet by cross-lane adds)
 //   y[k] -= L[k, p] y_p for every k below   (one row per lane, the sixteen
@@ -154,7 +159,7 @@ __global__ __launch_bounds__(kDiagThreads) void k_fwd_diag(const int32_t* __rest
                                                            KArgs a,
                                                   const R* __restrict__ arena,
                                                   const R* __restrict__ dinv, R* __restrict__ y,
-                                                  int64_t n, int nrhs) {
+                                                  int64_t n, int nrhs, SolveBufs<R> sb) {
     extern __shared__ double sm_raw[];
     R* sm = (R*)sm_raw;
     __shared__ R ys[kDiagThreads / 64][kMaxWidth + kPanel];
@@ -172,12 +177,13 @@ __global__ __launch_bounds__(kDiagThreads) void k_fwd_diag(const int32_t* __rest
     R* yw = ys[wave];
     for (int c = wave; c < nrhs; c += kDiagThreads / 64) {
         R* __restrict__ yc = y + (int64_t)c * n;
+        const R* __restrict__ cbc = sb.cb + (int64_t)c * sb.nslots;
         {
-            R v[(kMaxWidth + 63) / 64];  // all of the wave's loads in flight at once
+            R v[(kMaxWidth + 63) / 64];
 #pragma unroll
             for (int u = 0; u < (kMaxWidth + 63) / 64; ++u) {
                 const int k = lane + 64 * u;
-                v[u] = k < w ? yc[first + k] : R(0);
+                v[u] = k < w ? pulled(yc, cbc, sb, first + k) : R(0);
             }
 #pragma unroll
             for (int u = 0; u < (kMaxWidth + 63) / 64; ++u)
@@ -219,13 +225,14 @@ __global__ __launch_bounds__(kDiagThreads) void k_fwd_diag(const int32_t* __rest
     }
 }
 
-// Below the diagonal block, forward: y[rows(i)] -= sum_k L21[i][k] y_s[k] for
+// Below the diagonal block, forward: sum_k L21[i][k] y_s[k] for the rows i of
 // one 64-row block: the block is staged in LDS, thread (row, wave) sums every
-// 4th column, the four waves meet in LDS, one atomic per row and column.
+// 4th column, the four waves meet in LDS, one store per row and column into
+// the row's contribution slot.
 template <class R, int NR>
 __global__ __launch_bounds__(256) void k_fwd_gemv(const RowBlock* __restrict__ work, KArgs a,
                                                   const R* __restrict__ arena, R* __restrict__ y,
-                                                  int64_t n, int nrhs) {
+                                                  int64_t n, int nrhs, SolveBufs<R> sb) {
     extern __shared__ double sm_raw[];
     R* Pl = (R*)sm_raw;
     __shared__ R ys[kMaxWidth][NR];
@@ -282,25 +289,24 @@ __global__ __launch_bounds__(256) void k_fwd_gemv(const RowBlock* __restrict__ w
         for (int c = 0; c < NR; ++c) red[wave][c][lane] = acc[c];
         __syncthreads();
         if (tid < m) {
-            const int32_t row = below[i0 + tid];
+            const int64_t slot = rp + w + i0 + tid;
             for (int c = 0; c < nc; ++c)
-                unsafeAtomicAdd(y + (int64_t)(c0 + c) * n + row,
-                                -((red[0][c][tid] + red[1][c][tid]) +
-                                  (red[2][c][tid] + red[3][c][tid])));
+                sb.cb[(int64_t)(c0 + c) * sb.nslots + slot] =
+                    (red[0][c][tid] + red[1][c][tid]) + (red[2][c][tid] + red[3][c][tid]);
         }
         __syncthreads();
     }
 }
 
-// Below the diagonal block, backward: t_s[k] += sum_i L21[i][k] y[rows(i)]
-// over one 64-row block staged in LDS: thread k walks column k (its own
-// padded LDS column) for NR right-hand sides at a time and adds one partial
-// sum per column and right-hand side.
+// Below the diagonal block, backward: sum_i L21[i][k] y[rows(i)] over one
+// 64-row block staged in LDS: thread k walks column k (its own padded LDS
+// column) for NR right-hand sides at a time and stores one partial sum per
+// column and right-hand side (the block's place in pb).
 template <class R, int NR>
 __global__ __launch_bounds__(256) void k_bwd_gemv(const RowBlock* __restrict__ work, KArgs a,
                                                   const R* __restrict__ arena,
-                                                  const R* __restrict__ y, R* __restrict__ tacc,
-                                                  int64_t n, int nrhs) {
+                                                  const R* __restrict__ y, int64_t n, int nrhs,
+                                                  SolveBufs<R> sb) {
     extern __shared__ double sm_raw[];
     R* Pl = (R*)sm_raw;
     __shared__ R xr[kTile][NR];
@@ -343,8 +349,9 @@ __global__ __launch_bounds__(256) void k_bwd_gemv(const RowBlock* __restrict__ w
                         acc[c][1] += pv[u + 1] * xv[u + 1][c];
                     }
             }
+            const int64_t at = sb.pb_off[s] + (int64_t)wb.rb * w + k;
             for (int c = 0; c < nc; ++c)
-                unsafeAtomicAdd(tacc + (int64_t)(c0 + c) * n + first + k, acc[c][0] + acc[c][1]);
+                sb.pb[(int64_t)(c0 + c) * sb.pb_total + at] = acc[c][0] + acc[c][1];
         }
         __syncthreads();
     }
@@ -359,8 +366,7 @@ __global__ __launch_bounds__(kDiagThreads) void k_bwd_diag(const int32_t* __rest
                                                            KArgs a,
                                                   const R* __restrict__ arena,
                                                   const R* __restrict__ dinv, R* __restrict__ y,
-                                                  const R* __restrict__ tacc, int64_t n,
-                                                  int nrhs) {
+                                                  int64_t n, int nrhs, SolveBufs<R> sb) {
     extern __shared__ double sm_raw[];
     R* sm = (R*)sm_raw;
     __shared__ R ys[kDiagThreads / 64][kMaxWidth + kPanel];
@@ -376,16 +382,20 @@ __global__ __launch_bounds__(kDiagThreads) void k_bwd_diag(const int32_t* __rest
     stage_block<R>(T, I, inv, w, tid);
     __syncthreads();
     R* yw = ys[wave];
+    const int nb = ((int)(a.rowptr[s + 1] - a.rowptr[s]) - w + kTile - 1) / kTile;
     for (int c = wave; c < nrhs; c += kDiagThreads / 64) {
         R* __restrict__ yc = y + (int64_t)c * n;
-        const R* __restrict__ tc = tacc + (int64_t)c * n;
+        const R* __restrict__ pc = sb.pb + (int64_t)c * sb.pb_total + sb.pb_off[s];
         {
             R v[(kMaxWidth + 63) / 64], t[(kMaxWidth + 63) / 64];
 #pragma unroll
             for (int u = 0; u < (kMaxWidth + 63) / 64; ++u) {
                 const int k = lane + 64 * u;
                 v[u] = k < w ? yc[first + k] : R(0);
-                t[u] = k < w ? tc[first + k] : R(0);
+                R acc = R(0);  // the row blocks' partial sums in block order
+                if (k < w)
+                    for (int b = 0; b < nb; ++b) acc += pc[(int64_t)b * w + k];
+                t[u] = acc;
             }
 #pragma unroll
             for (int u = 0; u < (kMaxWidth + 63) / 64; ++u)
@@ -461,16 +471,17 @@ namespace {
 // enqueued on stream st.  Gather and scatter stay outside: they touch the
 // caller's b and x, which change from call to call.
 template <class R, int NR>
-void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* y, R* tacc, hipStream_t st) {
+void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* work, hipStream_t st) {
     const Symbolic& S = num->sym->S;
     const DevicePlan* P = num->plan;
     const int64_t n = S.n;
     const KArgs a = kargs(P);
     const R* arena = (const R*)num->arena;
     const R* dinv = (const R*)num->dinv;
-    const int64_t total = n * nrhs;
-    const int g = (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 4096));
-    hipLaunchKernelGGL(k_zero<R>, dim3(g), dim3(256), 0, st, tacc, total);
+    R* y = work;
+    R* cb = y + n * nrhs;
+    const SolveBufs<R> sb{cb, cb + P->nslots * nrhs, P->nslots, P->pb_total,
+                          P->rc_ptr, P->rc_slot, P->pb_off};
     const int32_t nl = (int32_t)S.level_ptr.size() - 1;
     for (int32_t l = 0; l < nl; ++l) {
         const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1], nbig = P->level_nbig[l];
@@ -478,13 +489,13 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* y, R* tacc, hipStream_t s
         const size_t lds_rows = (size_t)P->level_maxw[l] * kPs * sizeof(R);
         if (nbig > 0)
             hipLaunchKernelGGL(k_fwd_diag<R>, dim3(nbig), dim3(kDiagThreads), lds, st,
-                               P->level_sn + n0, a, arena, dinv, y, n, nrhs);
+                               P->level_sn + n0, a, arena, dinv, y, n, nrhs, sb);
         launch_small_solve(num, a, P->level_sn + n0 + nbig, n1 - n0 - nbig, P->small_maxw[l],
-                           P->small_maxm[l], y, n, nrhs, true, st);
+                           P->small_maxm[l], y, cb, n, nrhs, true, st);
         const int64_t rb0 = P->rowblk_ptr[l], rb1 = P->rowblk_ptr[l + 1];
         if (rb1 > rb0)
             hipLaunchKernelGGL((k_fwd_gemv<R, NR>), dim3((unsigned)(rb1 - rb0)), dim3(256),
-                               lds_rows, st, P->rowblk + rb0, a, arena, y, n, nrhs);
+                               lds_rows, st, P->rowblk + rb0, a, arena, y, n, nrhs, sb);
     }
     for (int32_t l = nl - 1; l >= 0; --l) {
         const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1], nbig = P->level_nbig[l];
@@ -492,13 +503,13 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* y, R* tacc, hipStream_t s
         if (rb1 > rb0)
             hipLaunchKernelGGL((k_bwd_gemv<R, NR>), dim3((unsigned)(rb1 - rb0)), dim3(256),
                                (size_t)P->level_maxw[l] * kPs * sizeof(R), st, P->rowblk + rb0, a,
-                               arena, (const R*)y, tacc, n, nrhs);
+                               arena, (const R*)y, n, nrhs, sb);
         if (nbig > 0)
             hipLaunchKernelGGL(k_bwd_diag<R>, dim3(nbig), dim3(kDiagThreads),
                                diag_lds(P->level_maxw[l], sizeof(R)), st, P->level_sn + n0, a,
-                               arena, dinv, y, (const R*)tacc, n, nrhs);
+                               arena, dinv, y, n, nrhs, sb);
         launch_small_solve(num, a, P->level_sn + n0 + nbig, n1 - n0 - nbig, P->small_maxw[l],
-                           P->small_maxm[l], y, n, nrhs, false, st);
+                           P->small_maxm[l], y, cb, n, nrhs, false, st);
     }
 }
 
@@ -514,9 +525,22 @@ void drop_solve_graphs(spc_numeric* num) {
     num->solve_graphs.clear();
 }
 
-// Work vectors y and t (n x nrhs each, factor type) for nrhs right-hand sides.
+int64_t solve_work_elems(const spc_numeric* num, int32_t nrhs) {
+    const DevicePlan* P = num->plan;
+    return (num->sym->S.n + P->nslots + P->pb_total) * (int64_t)nrhs;
+}
+
+int64_t solve_work_elems_per_rhs(const Symbolic& S) {
+    int64_t pb = 0;
+    for (int64_t s = 0; s < S.nsup; ++s)
+        if (!is_small(S, s)) pb += (int64_t)((S.nbelow(s) + kTile - 1) / kTile) * S.width(s);
+    return S.n + (int64_t)S.rows.size() + pb;
+}
+
+// Solve work for nrhs right-hand sides (factor type): the vector y (n x nrhs),
+// the forward contribution slots (nslots x nrhs) and the backward partial
+// sums (pb_total x nrhs).
 int32_t ensure_solve_work(spc_numeric* num, int32_t nrhs) {
-    const int64_t n = num->sym->S.n;
     if (num->work_cols >= nrhs) return OK;
     if (num->work) {
         HIP_TRY(hipDeviceSynchronize());
@@ -525,15 +549,14 @@ int32_t ensure_solve_work(spc_numeric* num, int32_t nrhs) {
         num->work = nullptr;
         num->work_cols = 0;
     }
-    if (hipMalloc(&num->work, 2 * elem_size(num) * (size_t)n * nrhs) != hipSuccess)
-        return ERR_OOM;
+    const int64_t elems = std::max<int64_t>(solve_work_elems(num, nrhs), 1);
+    if (hipMalloc(&num->work, elem_size(num) * (size_t)elems) != hipSuccess) return ERR_OOM;
     num->work_cols = nrhs;
     return OK;
 }
 
 // Replays (capturing on first use) the sweeps for nrhs columns on stream st.
 int32_t run_sweeps(spc_numeric* num, int32_t nrhs, hipStream_t st) {
-    const int64_t n = num->sym->S.n;
     spc_numeric::SolveGraph* sg = nullptr;
     for (auto& e : num->solve_graphs)
         if (e.nrhs == nrhs) sg = &e;
@@ -542,15 +565,14 @@ int32_t run_sweeps(spc_numeric* num, int32_t nrhs, hipStream_t st) {
         spc_numeric::SolveGraph e;
         e.nrhs = nrhs;
         HIP_TRY(hipStreamBeginCapture(num->capture, hipStreamCaptureModeThreadLocal));
-        const size_t half = (size_t)n * nrhs;
         if (num->prec == 1) {
             float* y = (float*)num->work;
-            if (nrhs == 1) enqueue_sweeps<float, 1>(num, nrhs, y, y + half, num->capture);
-            else enqueue_sweeps<float, kRhs>(num, nrhs, y, y + half, num->capture);
+            if (nrhs == 1) enqueue_sweeps<float, 1>(num, nrhs, y, num->capture);
+            else enqueue_sweeps<float, kRhs>(num, nrhs, y, num->capture);
         } else {
             double* y = (double*)num->work;
-            if (nrhs == 1) enqueue_sweeps<double, 1>(num, nrhs, y, y + half, num->capture);
-            else enqueue_sweeps<double, kRhs>(num, nrhs, y, y + half, num->capture);
+            if (nrhs == 1) enqueue_sweeps<double, 1>(num, nrhs, y, num->capture);
+            else enqueue_sweeps<double, kRhs>(num, nrhs, y, num->capture);
         }
         const hipError_t ce = hipStreamEndCapture(num->capture, &e.graph);
         if (ce != hipSuccess || !e.graph) return ERR_HIP;

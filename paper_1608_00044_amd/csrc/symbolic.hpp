@@ -24,6 +24,8 @@ struct Options {
     int32_t precision = 0;    // 0: FP64 factor; 1: FP32 factor with FP64 refinement
     int32_t small_w = 16;     // supernodes of at most small_w columns and small_r rows
     int32_t small_r = 64;     // below run on the lane-group kernels (small_w 0: none)
+    int32_t deterministic = 1; // fixed order of the contributions to every target
+    int32_t workers = 0;      // sched 2: persistent workgroups (0 = full occupancy)
 };
 
 // One (source, target) update pair: source supernode s sends its update block

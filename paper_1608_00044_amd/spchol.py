@@ -38,14 +38,15 @@ EXPORTS = ("spc_default_options", "spc_analyze", "spc_symbolic_info_get", "spc_s
            "spc_numeric_get_timing", "spc_solve_refine", "spc_numeric_info_get",
            "spc_analyze_batch", "spc_server_default_options", "spc_server_create",
            "spc_server_add_pattern", "spc_server_submit", "spc_server_wait",
-           "spc_server_stats_get", "spc_server_destroy")
+           "spc_server_stats_get", "spc_server_destroy", "spc_numeric_task_log")
 
 
 class spc_options(C.Structure):
     _fields_ = [("sn_cap", C.c_int32), ("sched", C.c_int32), ("amalg_ratio", C.c_double),
                 ("mem_budget_bytes", C.c_int64), ("spin_limit", C.c_int64),
                 ("debug_flags", C.c_int32), ("precision", C.c_int32), ("threads", C.c_int32),
-                ("small_w", C.c_int32), ("small_r", C.c_int32)]
+                ("small_w", C.c_int32), ("small_r", C.c_int32), ("deterministic", C.c_int32),
+                ("workers", C.c_int32)]
 
 
 class spc_symbolic_info(C.Structure):
@@ -53,12 +54,13 @@ class spc_symbolic_info(C.Structure):
                 ("nnz_stored", C.c_int64), ("nsup", C.c_int64), ("nlevels", C.c_int64),
                 ("npairs", C.c_int64), ("nrel", C.c_int64), ("factor_bytes", C.c_int64),
                 ("plan_bytes", C.c_int64), ("flops", C.c_double), ("flops_stored", C.c_double),
-                ("max_width", C.c_int32), ("max_below", C.c_int32), ("nbatch", C.c_int64)]
+                ("max_width", C.c_int32), ("max_below", C.c_int32), ("nbatch", C.c_int64),
+                ("solve_bytes_per_rhs", C.c_int64)]
 
 
 class spc_numeric_info(C.Structure):
     _fields_ = [("precision", C.c_int32), ("sched", C.c_int32), ("factor_bytes", C.c_int64),
-                ("fp64_blocks", C.c_int64)]
+                ("fp64_blocks", C.c_int64), ("refine_fallbacks", C.c_int64)]
 
 
 class spc_server_options(C.Structure):
@@ -69,7 +71,8 @@ class spc_server_options(C.Structure):
 class spc_request(C.Structure):
     _fields_ = [("pattern", C.c_int32), ("kind", C.c_int32), ("nrhs", C.c_int32),
                 ("reserved", C.c_int32), ("values", C.c_void_p), ("b", C.c_void_p),
-                ("ldb", C.c_int64), ("x", C.c_void_p), ("ldx", C.c_int64)]
+                ("ldb", C.c_int64), ("x", C.c_void_p), ("ldx", C.c_int64),
+                ("stream", C.c_void_p)]
 
 
 class spc_request_result(C.Structure):
@@ -149,6 +152,8 @@ def lib():
         L.spc_solve_refine.argtypes = [vp, C.c_int32, vp, C.c_int64, vp, C.c_int64, C.c_double,
                                        C.c_int32, vp, C.POINTER(C.c_int32), vp]
         L.spc_solve_refine.restype = C.c_int32
+        L.spc_numeric_task_log.argtypes = [vp, C.POINTER(C.c_int64), vp, vp]
+        L.spc_numeric_task_log.restype = C.c_int32
         L.spc_numeric_info_get.argtypes = [vp, C.POINTER(spc_numeric_info)]
         L.spc_numeric_info_get.restype = C.c_int32
         L.spc_server_default_options.argtypes = [C.POINTER(spc_server_options)]
@@ -196,7 +201,10 @@ def _stream_ptr(stream):
 # ---------------------------------------------------------------------------
 
 def _options(sn_cap=150, amalg_ratio=0.0, sched=0, mem_budget_bytes=0, spin_limit=0,
-             debug_flags=0, precision=0, threads=0, small_w=0, small_r=0):
+             debug_flags=0, precision=0, threads=0, small_w=0, small_r=0, deterministic=None,
+             workers=0):
+    """spc_options; deterministic=None takes the library's default (1), except
+    with sched 2, which needs 0."""
     opt = spc_options()
     lib().spc_default_options(C.byref(opt))
     opt.sn_cap = int(sn_cap)
@@ -209,6 +217,11 @@ def _options(sn_cap=150, amalg_ratio=0.0, sched=0, mem_budget_bytes=0, spin_limi
     opt.threads = int(threads)
     opt.small_w = int(small_w)
     opt.small_r = int(small_r)
+    if deterministic is not None:
+        opt.deterministic = int(deterministic)
+    elif int(sched) == 2:
+        opt.deterministic = 0
+    opt.workers = int(workers)
     return opt
 
 
@@ -446,6 +459,19 @@ class Numeric:
         out["total_ms"] = t.total_ms
         return out
 
+    def task_log(self):
+        """spc_numeric_task_log: (tasks[ntasks, 4], stamps[ntasks, 2])."""
+        nt = C.c_int64(0)
+        st = lib().spc_numeric_task_log(self.handle, C.byref(nt), None, None)
+        if st != SPC_OK:
+            raise SpcError(st, "spc_numeric_task_log")
+        tk = np.zeros(max(4 * nt.value, 4), dtype=np.int32)
+        sp = np.zeros(max(2 * nt.value, 2), dtype=np.int32)
+        st = lib().spc_numeric_task_log(self.handle, C.byref(nt), _ptr(tk), _ptr(sp))
+        if st != SPC_OK:
+            raise SpcError(st, "spc_numeric_task_log")
+        return tk[: 4 * nt.value].reshape(-1, 4), sp[: 2 * nt.value].reshape(-1, 2)
+
     def export(self):
         """Host copy (Sp, Si, Sx) of L in the stored supernodal column structure."""
         nnz = self.sym.info()["nnz_stored"]
@@ -474,6 +500,25 @@ class Numeric:
 # request server
 # ---------------------------------------------------------------------------
 
+def request_operands(n, nnz_a, values, b, x):
+    """Checks a server request's device operands: float64 tensors on the GPU,
+    b and x column-major (n, k), values contiguous with nnz_a entries.
+    Returns (values, B, X) with B and X as (n, k) views."""
+    if values is not None:
+        values = _dev_f64(values, "values").contiguous()
+        if values.numel() != nnz_a:
+            raise ValueError("values has %d entries, expected %d" % (values.numel(), nnz_a))
+    B = _dev_f64(b, "b").reshape(n, -1)
+    X = _dev_f64(x, "x").reshape(n, -1)
+    if B.shape[1] != X.shape[1]:
+        raise ValueError("b and x have different column counts")
+    k = B.shape[1]
+    for t, nm in ((B, "b"), (X, "x")):
+        if t.stride(0) != 1 or (k > 1 and t.stride(1) < n):
+            raise ValueError("%s must be column-major (n, k)" % nm)
+    return values, B, X
+
+
 class Server:
     """spc_server_*: continuous batching of factor+solve / solve-only requests."""
 
@@ -499,28 +544,28 @@ class Server:
         self._patterns.append(sym)
         return int(pid.value)
 
-    def submit(self, pattern, b, x, values=None, kind=None) -> int:
+    def submit(self, pattern, b, x, values=None, kind=None, stream=None) -> int:
         """b, x: column-major (n, k) float64 device tensors (x written);
-        values given: factor then solve (kind 0), else solve only (kind 1)."""
+        values given: factor then solve (kind 0), else solve only (kind 1).
+        The request runs after the work enqueued on `stream` (torch's current
+        stream by default) up to this call."""
+        sym = self._patterns[pattern]
+        values, B, X = request_operands(sym.n, sym.info()["nnz_a"], values, b, x)
         r = spc_request()
         r.pattern = int(pattern)
         r.kind = int((0 if values is not None else 1) if kind is None else kind)
-        n = self._patterns[pattern].n
-        B = b.reshape(n, -1)
-        X = x.reshape(n, -1)
+        n = sym.n
         k = B.shape[1]
-        for t, nm in ((B, "b"), (X, "x")):
-            if t.stride(0) != 1 or (k > 1 and t.stride(1) < n):
-                raise ValueError("%s must be column-major (n, k)" % nm)
         r.nrhs = k
         r.values = None if values is None else values.data_ptr()
         r.b, r.ldb = B.data_ptr(), max(B.stride(1) if k > 1 else n, n)
         r.x, r.ldx = X.data_ptr(), max(X.stride(1) if k > 1 else n, n)
+        r.stream = _stream_ptr(stream)
         t = C.c_int64(0)
         st = lib().spc_server_submit(self.handle, C.byref(r), C.byref(t))
         if st != SPC_OK:
             raise SpcError(st, "spc_server_submit")
-        self._keep[int(t.value)] = (values, b, x)
+        self._keep[int(t.value)] = (values, B, X, b, x)
         return int(t.value)
 
     def wait(self, ticket) -> dict:

@@ -23,11 +23,12 @@ def torch_dev():
     return torch
 
 
-def gpu_factor(p, cap=150, ratio=0.0, sched=0):
-    """Analyze + factor on cuda:0; returns (sym, num, values_tensor)."""
+def gpu_factor(p, cap=150, ratio=0.0, sched=0, deterministic=None, **opts):
+    """Analyze + factor on cuda:0; returns (sym, num, values_tensor).
+    deterministic=None: the library's default order (sched 2: atomic)."""
     torch = torch_dev()
     sym = spchol.analyze(p.n, p.colptr, p.rowind, p.perm, sn_cap=cap, amalg_ratio=ratio,
-                         sched=sched)
+                         sched=sched, deterministic=deterministic, **opts)
     vals = torch.from_numpy(np.ascontiguousarray(p.values)).to("cuda:0")
     num = spchol.factor(sym, vals)
     return sym, num, vals

@@ -104,3 +104,17 @@ def csc_to_dense_lower(n, Lp, Li, Lx):
         for p in range(Lp[j], Lp[j + 1]):
             L[Li[p], j] = Lx[p]
     return L
+
+
+def refusal_case(y):
+    """Pattern for the refused-then-accepted amalgamation case (22 columns):
+    columns 2..21 a dense block (supernode pp, 20 columns, nothing below);
+    column 1 (supernode p) with rows {1} + S1, |S1| = 11, min S1 = 2, so
+    colcount 12 and parent 2; column 0 (supernode c) with rows {0, 1} plus
+    y - 2 rows of S1, so colcount y and parent 1."""
+    n = 22
+    S1 = [2, 3, 5, 7, 8, 10, 12, 14, 16, 18, 21]
+    S0 = [1] + S1[: y - 2]
+    ent = [(i, i) for i in range(n)] + [(r, 0) for r in S0] + [(r, 1) for r in S1]
+    ent += [(i, j) for j in range(2, n) for i in range(j + 1, n)]
+    return spd_values_for_pattern(n, ent, seed=y)

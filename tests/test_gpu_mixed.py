@@ -201,3 +201,33 @@ def test_refine_right_hand_side_groups(k):
     # both meet eta <= 1e-10, so they agree to within cond(A) times twice that
     bound = max(1e-12, 4 * _cond_bound(p) * 2e-10)
     assert np.abs(x[:, k - 1] - xl).max() / np.abs(xl).max() <= bound
+
+
+def test_refinement_stall_switches_to_fp64_factor():
+    """A 2D Laplacian with a 1e-8 shift has cond(A) near 8e8, so FP32
+    corrections (u32 cond(A) ~ 50) cannot converge: after two steps in which
+    the worst eta does not halve, the corrections continue with an FP64
+    factor of the same matrix and reach 1e-10 (checked by the oracle's
+    definition); a refactorization makes the FP64 factor again.  A
+    well-conditioned problem never needs it."""
+    torch = torch_dev()
+    p = inputs.make_grid_problem("lap", (48, 48), 71, sigma=None, shift=1e-8, nrhs=2)
+    sym, num = _fp32_factor(p, 150, 0.0)
+    assert num.status() == 0
+    b = torch.from_numpy(np.ascontiguousarray(p.rhs)).to("cuda:0")
+    x, iters, berr = num.solve_refine(b, tol=1e-10, max_iter=30)
+    eta = oracle.backward_error(p.n, p.colptr, p.rowind, p.values, p.rhs,
+                                x.cpu().numpy().reshape(p.n, -1))
+    say("stalled refinement: iters", iters, "eta", eta.max(), "info", num.info())
+    assert eta.max() <= 1e-10 and berr.max() <= 1e-10
+    assert num.info()["refine_fallbacks"] == 1
+    num.refactor(torch.from_numpy(p.values).to("cuda:0"))
+    x2, _, _ = num.solve_refine(b, tol=1e-10, max_iter=30)
+    assert num.info()["refine_fallbacks"] == 2
+    eta2 = oracle.backward_error(p.n, p.colptr, p.rowind, p.values, p.rhs,
+                                 x2.cpu().numpy().reshape(p.n, -1))
+    assert eta2.max() <= 1e-10
+    q = inputs.make_grid_problem("27pt3", (6, 6, 6), 43, shift=1e-3, nrhs=1)
+    sym2, num2 = _fp32_factor(q, 150, 0.1)
+    num2.solve_refine(torch.from_numpy(np.ascontiguousarray(q.rhs)).to("cuda:0"), tol=1e-10)
+    assert num2.info()["refine_fallbacks"] == 0

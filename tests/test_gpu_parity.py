@@ -76,18 +76,22 @@ CASES = ["dense1", "dense2", "dense5", "dense63", "dense64", "dense65", "dense15
          "elast27_6"]
 
 
-SCHED_CASES = ([(c, 0) for c in CASES] + [(c, 1) for c in ("dense300", "fig1", "random3",
-                                                           "lap2d_64", "lap3d_20_cap32",
-                                                           "lap3d_24", "elast27_6")]
-               + [(c, 2) for c in CASES])
+SUBSET = ("dense300", "fig1", "random3", "lap2d_64", "lap3d_20_cap32", "lap3d_24", "elast27_6")
+
+# (case, schedule, order): every case in the default deterministic order
+# (sched 0) and on the task queue (sched 2, atomic order); a subset in the
+# atomic order level by level and with the lookahead (sched 1)
+SCHED_CASES = ([(c, 0, 1) for c in CASES] + [(c, 0, 0) for c in SUBSET]
+               + [(c, 1, 0) for c in SUBSET] + [(c, 2, 0) for c in CASES])
 
 
-@pytest.mark.parametrize("name,sched", SCHED_CASES)
-def test_factor_and_solve_parity(name, sched):
+@pytest.mark.parametrize("name,sched,det", SCHED_CASES)
+def test_factor_and_solve_parity(name, sched, det):
     torch = torch_dev()
     p, cap, ratio = _case(name)
-    say("case", name, "sched", sched, "n", p.n, "nnz", p.nnz, "cap", cap, "ratio", ratio)
-    sym, num, _ = gpu_factor(p, cap, ratio, sched)
+    say("case", name, "sched", sched, "deterministic", det, "n", p.n, "nnz", p.nnz, "cap", cap,
+        "ratio", ratio)
+    sym, num, _ = gpu_factor(p, cap, ratio, sched, deterministic=det)
     assert num.status() == 0
     worst, rho, (osym, Lx, got) = compare_factor(p, num, cap, ratio, name)
     say("  worst/tol", worst, "residual", rho)
@@ -233,11 +237,11 @@ def test_refactor_and_multi_rhs():
     tol = 4 * _cond_bound(p2) * 1e-15
     np.testing.assert_allclose(x, xo, rtol=0, atol=tol * np.abs(xo).max())
     assert oracle.backward_error(p2.n, p2.colptr, p2.rowind, p2.values, p2.rhs, x).max() <= 1e-14
-    # in-place solve (x aliases b); atomic accumulation order may change the
-    # last bits, so compare to rounding level
+    # in-place solve (x aliases b): the solve's sums have one fixed order, so
+    # the same bits
     bb = b.t().contiguous().t()
     num.solve(bb, x=bb)
-    np.testing.assert_allclose(bb.cpu().numpy(), x, rtol=0, atol=1e-12 * np.abs(x).max())
+    assert np.array_equal(bb.cpu().numpy(), x)
 
 
 def test_empty_matrix():
@@ -271,7 +275,7 @@ def test_memory_budget_rejects_large_factor():
 def test_solve_graph_replays_match():
     """The solve sweeps replay from a captured graph: repeated solves, with
     other right-hand sides and a refactorization between them, all give the
-    oracle's answer (to rounding: atomic accumulation order may vary)."""
+    oracle's answer, and (deterministic order) the same bits every time."""
     torch = torch_dev()
     p = inputs.make_grid_problem("lap", (14, 14, 14), 31, sigma=1.0, shift=1e-3, nrhs=3)
     sym, num, vals = gpu_factor(p, 150, 0.1)
@@ -280,12 +284,16 @@ def test_solve_graph_replays_match():
     b = torch.from_numpy(np.ascontiguousarray(p.rhs)).to("cuda:0")
     scale = np.abs(xo).max()
     other = torch.randn(p.n, dtype=torch.float64, device="cuda:0")
+    first = None
     for rep in range(5):
         x = num.solve(b).cpu().numpy()
         np.testing.assert_allclose(x, xo, rtol=0, atol=1e-9 * scale)
         num.solve(other)                       # a different graph (nrhs = 1)
         x1 = num.solve(b[:, 1]).cpu().numpy()  # and a one-column replay
         np.testing.assert_allclose(x1, xo[:, 1], rtol=0, atol=1e-9 * scale)
+        if first is None:
+            first = (x, x1)
+        assert np.array_equal(x, first[0]) and np.array_equal(x1, first[1])
         if rep == 2:
             num.refactor(vals)                 # same values: same factor
             assert num.status() == 0
@@ -311,25 +319,33 @@ def test_solve_right_hand_side_groups(k):
         np.testing.assert_allclose(x[:, c], xc, rtol=0, atol=1e-12 * np.abs(xc).max())
 
 
-@pytest.mark.parametrize("sched", [0, 1])
-def test_factor_graph_replays_match_direct_launches(sched):
+@pytest.mark.parametrize("sched,det", [(0, 1), (0, 0), (1, 0)])
+def test_factor_graph_replays_match_direct_launches(sched, det):
     """The level-set factorization (sched 1: with the lookahead's second
     stream joined into the capture) is captured into a graph on the first
     factorization and replayed after; every replay (with eager work between)
-    and a directly launched factorization (per-launch timing on) agree to
-    rounding, and the last replay meets the parity bars."""
+    and a directly launched factorization (per-launch timing on) agree, bit
+    for bit in the deterministic order and to rounding in the atomic one, and
+    the last replay meets the parity bars."""
     torch = torch_dev()
     p = inputs.make_grid_problem("lap", (16, 16, 16), 71, sigma=1.0, shift=1e-3, nrhs=0)
-    sym, num, vals = gpu_factor(p, 150, 0.1, sched)
+    sym, num, vals = gpu_factor(p, 150, 0.1, sched, deterministic=det)
     L1 = num.export()[2]
     scale = np.abs(L1).max()
+
+    def same(L):
+        if det:
+            assert np.array_equal(L, L1)
+        else:
+            np.testing.assert_allclose(L, L1, rtol=0, atol=1e-13 * scale)
+
     for _ in range(3):
         torch.ones(1000, device="cuda:0").sum().item()  # eager work between replays
         num.refactor(vals)
-        np.testing.assert_allclose(num.export()[2], L1, rtol=0, atol=1e-13 * scale)
+        same(num.export()[2])
     num.set_timing(True)
     num.refactor(vals)
-    np.testing.assert_allclose(num.export()[2], L1, rtol=0, atol=1e-13 * scale)
+    same(num.export()[2])
     assert num.timing()["update"]["launches"] > 0
     num.set_timing(False)
     num.refactor(vals)

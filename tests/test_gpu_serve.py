@@ -2,9 +2,9 @@
 solve-only requests over resident patterns.
 
 Bars: every result of a mix run with overlapping requests (several on the
-device at once) equals the same request run alone, within 1e-12 of the
-solution's size (atomic accumulation order may change the last bits), and is
-backward stable against the oracle's definition (<= 1e-14); admission keeps
+device at once) equals the same request run alone bit for bit (the
+deterministic order of every sum in factor and solve), and is backward
+stable against the oracle's definition (<= 1e-14); admission keeps
 the resident bytes within the budget, evicting idle factors; a request whose
 pattern cannot fit, a solve-only request with no factor, and a failed pivot
 are reported per request."""
@@ -75,7 +75,7 @@ def test_mix_matches_alone_and_overlaps():
     for (k, kind, nr), (ra, xa), (rm, xm), B in zip(reqs, alone, mix, Bs):
         p = probs[k]
         assert ra["status"] == 0 and rm["status"] == 0
-        np.testing.assert_allclose(xm, xa, rtol=0, atol=1e-12 * np.abs(xa).max())
+        assert np.array_equal(xm, xa)
         eta = oracle.backward_error(p.n, p.colptr, p.rowind, p.values, B, xm)
         assert eta.max() <= 1e-14
         lat.append(rm["latency_ms"])
@@ -85,8 +85,12 @@ def test_mix_matches_alone_and_overlaps():
 def test_admission_within_budget_evicts_idle_factors():
     torch = torch_dev()
     probs, syms = _patterns()
-    per = [s.info()["factor_bytes"] + 2 * 8 * s.n * 4 for s in syms]
-    budget = max(per) + min(per) // 2
+    # a factor with its work vectors for 4 columns; every pattern's device plan
+    # is charged once, with its first factor, and stays until the handle is
+    # freed: the budget holds every plan and one and a half factors
+    per = [s.info()["factor_bytes"] + 4 * s.info()["solve_bytes_per_rhs"] for s in syms]
+    plans = sum(s.info()["plan_bytes"] for s in syms)
+    budget = plans + max(per) + min(per) // 2
     reqs = [(k % len(probs), 0, 4) for k in range(3 * len(probs))]
     out, Bs, st = _run(dict(max_inflight=4, max_nrhs=4, mem_budget_bytes=budget), probs, syms,
                        reqs, sequential=False)
@@ -125,9 +129,15 @@ def test_solve_only_statuses_and_failed_factor_keeps_previous():
     assert srv.wait(srv.submit(pid, b, x2, values=bad))["status"] == 45
     x3 = torch.zeros_like(b)
     assert srv.wait(srv.submit(pid, b, x3))["status"] == 0  # the good factor is still current
+    with pytest.raises(spchol.SpcError) as busy:  # the server holds the pattern
+        sym.free()
+    assert busy.value.status == spchol.SPC_ERR_BUSY
     eta = oracle.backward_error(n, p.colptr, p.rowind, p.values, np.ones((n, 1)), x3.cpu().numpy())
     assert eta.max() <= 1e-14
     with pytest.raises(spchol.SpcError):
         srv.submit(pid, torch.ones((3, n), dtype=torch.float64, device="cuda:0").t(),
                    torch.zeros((3, n), dtype=torch.float64, device="cuda:0").t())  # nrhs > 2
+    with pytest.raises(ValueError):  # values of the wrong length
+        srv.submit(pid, b, x, values=good[:-1])
     srv.destroy()
+    sym.free()  # released by the server

@@ -7,7 +7,7 @@ import pytest
 import oracle
 from paper_1608_00044_amd import inputs
 from tests.helpers import (alg1_dense, csc_to_dense_lower, elimination_game, load_fig1,
-                           spd_values_for_pattern)
+                           refusal_case, spd_values_for_pattern)
 
 
 # ---------------------------------------------------------------------------
@@ -369,3 +369,53 @@ def test_amalgamation_hand_worked():
         [0, 1, 2, 3, 4, 5, 8]
     # cap 2 forbids the merge whatever the ratio
     assert oracle.amalgamate(n, sym.parent, sym.colcount, sn0, 2, 0.9).tolist() == sn0.tolist()
+
+
+@pytest.mark.parametrize("y,expect", [(8, [0, 22]), (5, [0, 1, 22]), (11, [0, 22])])
+def test_amalgamation_refused_then_accepted(y, expect):
+    """Hand-worked at ratio 0.1 (a merged column j stores
+    last(parent) - j + 1 + r_parent rows; z and T summed over the merged
+    supernode, the parent's own z carried along):
+    pass 1, c into p: stored(0) = 2 + 11 = 13 against colcount y, so
+    z = 13 - y, T = 13 + 12 = 25, bar 2.5: for y <= 10 c is refused.
+    Later in pass 1, p into pp: stored(1) = 21, z = 21 - 12 = 9,
+    T = 210 + 21 = 231, bar 23.1: merged.
+    Pass 2, c into the grown parent: stored(0) = 22, z = 9 + (22 - y),
+    T = 231 + 22 = 253, bar 25.3: y = 8 gives 23 (merged: one supernode of
+    22 columns); y = 5 gives 26 (refused, although c's own zeros, 17, are
+    under the bar: the parent's zeros count too).  Without repeated passes
+    y = 8 would stay apart.
+    y = 11: pass 1 merges c into p (z = 2, T = 25), then {0, 1} into pp with
+    both columns recounted against pp: z = (22 - 11) + (21 - 12) = 20,
+    T = 210 + 22 + 21 = 253: one supernode."""
+    p = refusal_case(y)
+    sym, _ = _sym_of(p)
+    assert sym.parent[0] == 1 and sym.parent[1] == 2
+    assert sym.colcount[0] == y and sym.colcount[1] == 12 and sym.colcount[2] == 20
+    sn0 = oracle.supernodes(p.n, sym.parent, sym.colcount, 150)
+    assert sn0.tolist() == [0, 1, 2, 22]
+    assert oracle.amalgamate(p.n, sym.parent, sym.colcount, sn0, 150, 0.1).tolist() == expect
+
+
+def test_residual_probe_against_dense_and_exact():
+    """The 8-probe estimate ||(L L^T - C) Z||_F / ||C Z||_F, written out densely
+    with numpy for the same probes, equals the oracle's; its square has
+    expectation rho^2 (E ||E z||^2 = ||E||_F^2 for Gaussian z), so eight probes
+    land within a factor of 3 of the exact rho; a planted error in L raises it."""
+    p = inputs.make_grid_problem("lap", (12, 12), seed=3, sigma=1.0, shift=1e-3)
+    sym, C = _sym_of(p)
+    st, Lx = oracle.factor(p.n, *C, sym)
+    assert st == 0
+    Lp_ = Lx * (1 + 1e-7 * np.random.default_rng(1).standard_normal(Lx.size))
+    z = np.random.default_rng(0).standard_normal((p.n, 8))
+    L = csc_to_dense_lower(p.n, sym.Lp, sym.Li, Lp_)
+    Cd = inputs.dense_from_lower_csc(p.n, *C)
+    dense = np.linalg.norm((L @ L.T - Cd) @ z) / np.linalg.norm(Cd @ z)
+    est = oracle.residual_probe(p.n, *C, sym, Lp_, z)
+    np.testing.assert_allclose(est, dense, rtol=1e-6)
+    rho = oracle.residual_exact(p.n, *C, sym, Lp_)
+    assert rho / 3 <= est <= 3 * rho
+    Lbad = Lx.copy()
+    Lbad[len(Lbad) // 2] += 1e-6
+    assert oracle.residual_probe(p.n, *C, sym, Lbad, z) > 1e-9
+    assert oracle.residual_probe(p.n, *C, sym, Lx, z) <= 1e-12

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 from paper_1608_00044_amd import inputs, spchol
-from tests.helpers import load_fig1, spd_values_for_pattern
+from tests.helpers import load_fig1, refusal_case, spd_values_for_pattern
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -341,3 +341,49 @@ def test_batch_analysis_random_mixes(seed):
             assert np.array_equal(got[k], want[k]), (k, seed)
     bs.free()
     ref.free()
+
+
+@pytest.mark.parametrize("y,expect", [(8, [0, 22]), (5, [0, 1, 22]), (11, [0, 1, 2, 22])])
+def test_library_amalgamation_refused_then_accepted(y, expect):
+    """The library's partition on the hand-worked refusal cases (worked out in
+    the oracle pin of the same name): ratio 0.1 merges y = 8 after a refusal
+    in the first pass, refuses y = 5 on the parent's accumulated zeros; ratio
+    0 leaves the three supernodes alone."""
+    p = refusal_case(y)
+    ratio = 0.0 if y == 11 else 0.1
+    sym = spchol.analyze(p.n, p.colptr, p.rowind, None, sn_cap=150, amalg_ratio=ratio)
+    assert sym.export()[2].tolist() == expect
+
+
+def _paper_dag(sym):
+    """Task graph in the paper's notation (Section III-A) from the library's
+    exported update pairs: F_s -> U_st -> A_t -> F_t for every pair (s, t)."""
+    pr = sym.pairs()
+    edges = set()
+    for s, t in zip(pr["src"].tolist(), pr["tgt"].tolist()):
+        edges |= {(("F", s), ("U", s, t)), (("U", s, t), ("A", t)), (("A", t), ("F", t))}
+    return edges
+
+
+@pytest.mark.parametrize("workers", [1, 2, 256])
+def test_fig2_task_graph(workers):
+    """Fig. 2 of the paper: supernodes j < i < h where j updates i and h and
+    i updates h.  Its edges are F_jj -> U_ji -> A_ii -> F_ii -> U_ih, and
+    U_jh, U_ih -> A_hh (-> F_hh), with F_jj -> U_jh.  A dense 3 x 3 matrix with
+    a one-column cap gives exactly that: j = 0, i = 1, h = 2.  The device task
+    list must hold F, T (panel) and U (tile, with its scatter: U and A fused)
+    tasks in an order that respects those edges, with F_hh's counter waiting
+    for two update tiles and F_ii's for one."""
+    p = inputs.dense_spd(3, seed=1, nrhs=0)
+    sym = spchol.analyze(p.n, p.colptr, p.rowind, None, sn_cap=1, sched=2)
+    j, i, h = 0, 1, 2
+    fig2 = {(("F", j), ("U", j, i)), (("U", j, i), ("A", i)), (("A", i), ("F", i)),
+            (("F", i), ("U", i, h)), (("U", j, h), ("A", h)), (("U", i, h), ("A", h)),
+            (("F", j), ("U", j, h)), (("A", h), ("F", h))}
+    assert _paper_dag(sym) == fig2
+    tk, cnt0 = sym.tasks(workers)
+    assert cnt0.tolist() == [0, 1, 2]
+    order = [tuple(t) for t in tk.tolist()]
+    # F(s) = (0, s, 0, 0); T(s, 0) = (1, s, 0, 0); U(s, 0, 0) = (2, s, 0, 0)
+    assert order == [(0, j, 0, 0), (1, j, 0, 0), (2, j, 0, 0), (0, i, 0, 0), (1, i, 0, 0),
+                     (2, i, 0, 0), (0, h, 0, 0)]
