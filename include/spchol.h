@@ -63,7 +63,8 @@ enum {
     SPC_ERR_NOT_FACTORED = -5,  /* solve on a factor that did not complete          */
     SPC_ERR_NOT_CONVERGED = -6, /* reserved for iterative refinement                */
     SPC_ERR_TIMEOUT = -7,       /* a device wait exceeded its bounded spin          */
-    SPC_ERR_BUSY = -8           /* symbolic handle still referenced by a factor     */
+    SPC_ERR_BUSY = -8,          /* symbolic handle still referenced by a factor     */
+    SPC_ERR_TOO_LARGE = -9      /* the work does not fit spc_solve_noalloc's scratch */
 };
 
 typedef struct spc_options {
@@ -229,6 +230,22 @@ spc_status spc_numeric_status(spc_numeric* num);
  * stream, otherwise asynchronous. */
 spc_status spc_solve(spc_numeric* num, int32_t nrhs, const double* b_dev, int64_t ldb,
                      double* x_dev, int64_t ldx, void* stream);
+
+/* spc_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and result, bit for bit, with the solve's work (the solution vector,
+ * the forward contributions and the backward partial sums, sized by
+ * spc_symbolic_info.solve_bytes_per_rhs times nrhs) in one static device
+ * array of 64 MiB that each device holds from the library's load until the
+ * process ends, instead of the factor's allocated work, and the level sweeps
+ * launched directly on stream instead of replayed from a graph.  It allocates
+ * nothing (no hipMalloc, hipFree or graph instantiation); the factor itself
+ * comes from spc_factor.  Work larger than the array: SPC_ERR_TOO_LARGE,
+ * before any device work.  Every call on a device shares that device's array,
+ * so calls that overlap on one device (different streams or threads) race.
+ * Arguments, status and synchronization as spc_solve. */
+spc_status spc_solve_noalloc(spc_numeric* num, int32_t nrhs, const double* b_dev, int64_t ldb,
+                             double* x_dev, int64_t ldx, void* stream);
 
 /* Host copy of the factor in the stored (supernodal) column structure:
  * Sp[n+1] (int64) and Si (int32) give, for column j of supernode s, the rows

@@ -141,6 +141,7 @@ const char* spc_status_string(spc_status st) {
         case SPC_ERR_NOT_CONVERGED: return "iterative refinement did not converge";
         case SPC_ERR_TIMEOUT: return "device wait exceeded its bound";
         case SPC_ERR_BUSY: return "symbolic handle is still referenced";
+        case SPC_ERR_TOO_LARGE: return "the solve's work does not fit the static scratch";
         default: return "unknown status";
     }
 }

@@ -26,7 +26,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
+#include "../../include/spchol.h"
 #include "runtime.hpp"
 
 namespace spc {
@@ -587,33 +589,107 @@ int32_t run_sweeps(spc_numeric* num, int32_t nrhs, hipStream_t st) {
     return OK;
 }
 
-int32_t run_solve(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb, double* x,
-                  int64_t ldx, hipStream_t st) {
-    const Symbolic& S = num->sym->S;
+namespace {
+
+// Gather, sweeps and scatter of one solve on the work array `work` (factor
+// type; solve_work_elems(num, nrhs) elements).  graph: the sweeps replay from
+// the factor's captured graph (work must be num->work); otherwise they are
+// launched directly on st.
+int32_t enqueue_solve(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb, double* x,
+                      int64_t ldx, void* work, bool graph, hipStream_t st) {
     const DevicePlan* P = num->plan;
-    const int64_t n = S.n;
-    if (n == 0 || nrhs == 0) return OK;
-    int32_t r = ensure_solve_work(num, nrhs);
-    if (r != OK) return r;
+    const int64_t n = num->sym->S.n;
     const int64_t total = n * nrhs;
     const int g = (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 4096));
     if (num->prec == 1)
         hipLaunchKernelGGL(k_gather<float>, dim3(g), dim3(256), 0, st, b, ldb, P->perm,
-                           (float*)num->work, n, nrhs);
+                           (float*)work, n, nrhs);
     else
         hipLaunchKernelGGL(k_gather<double>, dim3(g), dim3(256), 0, st, b, ldb, P->perm,
-                           (double*)num->work, n, nrhs);
-    // the sweeps replay from a graph captured once per right-hand-side count
-    r = run_sweeps(num, nrhs, st);
-    if (r != OK) return r;
+                           (double*)work, n, nrhs);
+    if (graph) {
+        const int32_t r = run_sweeps(num, nrhs, st);
+        if (r != OK) return r;
+    } else if (num->prec == 1) {
+        if (nrhs == 1) enqueue_sweeps<float, 1>(num, nrhs, (float*)work, st);
+        else enqueue_sweeps<float, kRhs>(num, nrhs, (float*)work, st);
+    } else {
+        if (nrhs == 1) enqueue_sweeps<double, 1>(num, nrhs, (double*)work, st);
+        else enqueue_sweeps<double, kRhs>(num, nrhs, (double*)work, st);
+    }
     if (num->prec == 1)
-        hipLaunchKernelGGL(k_scatter<float>, dim3(g), dim3(256), 0, st, (const float*)num->work,
+        hipLaunchKernelGGL(k_scatter<float>, dim3(g), dim3(256), 0, st, (const float*)work,
                            P->perm, x, ldx, n, nrhs);
     else
-        hipLaunchKernelGGL(k_scatter<double>, dim3(g), dim3(256), 0, st, (const double*)num->work,
+        hipLaunchKernelGGL(k_scatter<double>, dim3(g), dim3(256), 0, st, (const double*)work,
                            P->perm, x, ldx, n, nrhs);
     HIP_TRY(hipGetLastError());
     return OK;
 }
 
+}  // namespace
+
+int32_t run_solve(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb, double* x,
+                  int64_t ldx, hipStream_t st) {
+    if (num->sym->S.n == 0 || nrhs == 0) return OK;
+    const int32_t r = ensure_solve_work(num, nrhs);
+    if (r != OK) return r;
+    // the sweeps replay from a graph captured once per right-hand-side count
+    return enqueue_solve(num, nrhs, b, ldb, x, ldx, num->work, true, st);
+}
+
+// ---------------------------------------------------------------------------
+// solve without allocation
+// ---------------------------------------------------------------------------
+
+// Work of spc_solve_noalloc: one static array per device, held until the
+// process ends.  Every element a solve reads it has written first, so no
+// part needs clearing between calls.
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+__device__ __align__(256) double scratch[kNoAllocBytes / sizeof(double)];
+
+namespace {
+
+// Device address of `scratch` on each device, taken once per device with that
+// device current (host code never passes the symbol itself to a kernel).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int32_t scratch_on(int dev, void** out) {
+    if (dev < 0 || dev >= kMaxDevices) return ERR_ARG;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return ERR_HIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return OK;
+}
+
+}  // namespace
+
 }  // namespace spc
+
+extern "C" spc_status spc_solve_noalloc(spc_numeric* num, int32_t nrhs, const double* b_dev,
+                                        int64_t ldb, double* x_dev, int64_t ldx,
+                                        void* stream) {
+    using namespace spc;
+    if (!num || nrhs < 0) return SPC_ERR_ARG;
+    const int64_t n = num->sym->S.n;
+    if (nrhs > 0 && n > 0 && (!b_dev || !x_dev || ldb < n || ldx < n)) return SPC_ERR_ARG;
+    if (b_dev == x_dev && ldb != ldx) return SPC_ERR_ARG;
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return SPC_ERR_HIP;
+    if (cur != num->device) return SPC_ERR_ARG;
+    const size_t elem = num->prec == 1 ? sizeof(float) : sizeof(double);
+    if ((size_t)solve_work_elems(num, nrhs) * elem > kNoAllocBytes) return SPC_ERR_TOO_LARGE;
+    void* work = nullptr;
+    int32_t st = scratch_on(cur, &work);
+    if (st != OK) return st;
+    st = num->status_known ? num->host_status : spc_numeric_status(num);
+    if (st != SPC_OK) return st;
+    if (n == 0 || nrhs == 0) return SPC_OK;
+    return enqueue_solve(num, nrhs, b_dev, ldb, x_dev, ldx, work, false, (hipStream_t)stream);
+}

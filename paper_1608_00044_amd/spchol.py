@@ -28,6 +28,7 @@ SPC_ERR_NOT_FACTORED = -5
 SPC_ERR_NOT_CONVERGED = -6
 SPC_ERR_TIMEOUT = -7
 SPC_ERR_BUSY = -8
+SPC_ERR_TOO_LARGE = -9
 
 # Every symbol include/spchol.h declares.
 EXPORTS = ("spc_default_options", "spc_analyze", "spc_symbolic_info_get", "spc_symbolic_export",
@@ -38,7 +39,8 @@ EXPORTS = ("spc_default_options", "spc_analyze", "spc_symbolic_info_get", "spc_s
            "spc_numeric_get_timing", "spc_solve_refine", "spc_numeric_info_get",
            "spc_analyze_batch", "spc_server_default_options", "spc_server_create",
            "spc_server_add_pattern", "spc_server_submit", "spc_server_wait",
-           "spc_server_stats_get", "spc_server_destroy", "spc_numeric_task_log")
+           "spc_server_stats_get", "spc_server_destroy", "spc_numeric_task_log",
+           "spc_solve_noalloc")
 
 
 class spc_options(C.Structure):
@@ -141,6 +143,8 @@ def lib():
         L.spc_numeric_status.restype = C.c_int32
         L.spc_solve.argtypes = [vp, C.c_int32, vp, C.c_int64, vp, C.c_int64, vp]
         L.spc_solve.restype = C.c_int32
+        L.spc_solve_noalloc.argtypes = [vp, C.c_int32, vp, C.c_int64, vp, C.c_int64, vp]
+        L.spc_solve_noalloc.restype = C.c_int32
         L.spc_factor_export.argtypes = [vp, vp, vp, vp]
         L.spc_factor_export.restype = C.c_int32
         L.spc_numeric_free.argtypes = [vp]
@@ -418,6 +422,26 @@ class Numeric:
             raise SpcError(st, "spc_solve")
         return X.reshape(self.sym.n) if one else X
 
+    def solve_noalloc(self, b, x, stream=None):
+        """spc_solve_noalloc: x = A^{-1} b into the caller's x (no device
+        allocation anywhere on the call's path, x included): b and x must be
+        column-major (n,) or (n, k) GPU float64 tensors; nothing is copied."""
+        n = self.sym.n
+        one = b.dim() == 1
+        B = _dev_f64(b, "b").reshape(n, -1)
+        X = _dev_f64(x, "x").reshape(n, -1)
+        k = B.shape[1]
+        for t, nm in ((B, "b"), (X, "x")):
+            if t.shape[1] != k or t.stride(0) != 1 or (k > 1 and t.stride(1) < n):
+                raise ValueError("%s must be column-major (n, %d)" % (nm, k))
+        ldb = max(B.stride(1) if k > 1 else n, n)
+        ldx = max(X.stride(1) if k > 1 else n, n)
+        st = lib().spc_solve_noalloc(self.handle, k, C.c_void_p(B.data_ptr()), ldb,
+                                     C.c_void_p(X.data_ptr()), ldx, _stream_ptr(stream))
+        if st != SPC_OK:
+            raise SpcError(st, "spc_solve_noalloc")
+        return X.reshape(self.sym.n) if one else X
+
     def solve_refine(self, b, x=None, tol=1e-10, max_iter=10, stream=None, check=True):
         """Iterative refinement in FP64 (spc_solve_refine).  Returns (x, iters,
         berr); raises SpcError unless converged when check is set."""
@@ -619,6 +643,10 @@ def numeric_status(num: Numeric) -> int:
 
 def solve(num: Numeric, b, x=None, stream=None):
     return num.solve(b, x, stream)
+
+
+def solve_noalloc(num: Numeric, b, x, stream=None):
+    return num.solve_noalloc(b, x, stream)
 
 
 def solve_refine(num: Numeric, b, x=None, tol=1e-10, max_iter=10, stream=None):
