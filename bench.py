@@ -416,6 +416,8 @@ def main():
     ap.add_argument("--solves", type=int, default=200)
     ap.add_argument("--sched", type=int, default=0, choices=(0, 1, 2),
                     help="0 level sets, 1 with lookahead, 2 device task queue")
+    ap.add_argument("--deterministic", type=int, default=1, choices=(0, 1),
+                    help="1: fixed contribution order (the library default); 0: atomic order")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mixed-workload", default="elast27_48",
                     help="workload of the FP64 vs FP32+refinement comparison ('' to skip)")
@@ -467,7 +469,8 @@ def main():
 
     t0 = time.perf_counter()
     sym = spchol.analyze(p.n, p.colptr, p.rowind, p.perm, sn_cap=150, amalg_ratio=amalg,
-                         sched=args.sched)
+                         sched=args.sched,
+                         deterministic=args.deterministic if args.sched != 2 else 0)
     analyze_ms = (time.perf_counter() - t0) * 1e3
     info = sym.info()
     F = info["flops"]

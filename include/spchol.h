@@ -74,9 +74,8 @@ typedef struct spc_options {
                                  queue (dependency counters, Section IV)        */
     double amalg_ratio;       /* relaxed amalgamation zero ratio; 0 = off (default) */
     int64_t mem_budget_bytes; /* device bytes a factor may hold; 0 = no limit       */
-    int64_t spin_limit;       /* bound on every device wait (sched 2 and the
-                                 deterministic order), in microseconds; past it
-                                 the factorization stops waiting and its status
+    int64_t spin_limit;       /* sched 2: bound on every device wait, in microseconds;
+                                 past it the factorization stops and its status
                                  reads SPC_ERR_TIMEOUT; 0 = default (ten seconds) */
     int32_t debug_flags;      /* bit 0: withhold one dependency count so that the
                                  bounded wait fires (testing only); bit 1: sched 2

@@ -31,8 +31,7 @@ int64_t factor_bytes(const spc_symbolic* sym, int32_t prec) {
     int64_t b = (int64_t)((S.arena + inverse_blocks_elems(S)) * real_size(prec));
     b += nnzf * 20 + (S.n + 1) * 8;
     if (S.opt.sched == 2) b += 4 * (3 * S.nsup + 4);
-    if (S.opt.deterministic)
-        b += 4 * (S.nsup + (int64_t)S.level_ptr.size()) + sym->det_scratch * real_size(prec);
+    if (S.opt.deterministic) b += sym->det_scratch * real_size(prec);
     return b + 512;
 }
 
@@ -44,7 +43,6 @@ void release_numeric(spc_numeric* num) {
     (void)hipFree(num->status_dev);
     (void)hipFree(num->dinv);
     (void)hipFree(num->sched_state);
-    (void)hipFree(num->det_state);
     (void)hipFree(num->det_scratch);
     (void)hipFree(num->task_log);
     drop_solve_graphs(num);
@@ -293,20 +291,10 @@ static spc_status alloc_numeric(spc_symbolic* sym, int32_t prec, spc_numeric** o
                                                (size_t)std::max<int64_t>(plan->ntasks, 1)) ==
                  hipSuccess;
     }
-    if (ok && S.opt.deterministic) {
-        // ticks of the wall clock in the wait bound (spin_limit microseconds,
-        // default ten seconds): a wait that exceeds it ends as SPC_ERR_TIMEOUT
-        int clock_khz = 0;
-        if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, plan->device) !=
-                hipSuccess ||
-            clock_khz <= 0)
-            clock_khz = 100000;
-        const int64_t us = S.opt.spin_limit > 0 ? S.opt.spin_limit : (int64_t)10000000;
-        num->det_wait_ticks = (uint64_t)us * (uint64_t)clock_khz / 1000;
-        const size_t ints = (size_t)S.nsup + S.level_ptr.size();
-        ok = hipMalloc(&num->det_state, ints * sizeof(int32_t)) == hipSuccess &&
-             hipMalloc(&num->det_scratch, rs * (size_t)std::max<int64_t>(plan->det_scratch, 1)) ==
-                 hipSuccess;
+    if (ok && S.opt.deterministic && num->sched != 2) {
+        num->det = true;
+        ok = hipMalloc(&num->det_scratch, rs * (size_t)std::max<int64_t>(plan->det_scratch, 1)) ==
+             hipSuccess;
     }
     if (!ok) {
         release_numeric(num);
@@ -378,15 +366,6 @@ spc_status spc_numeric_status(spc_numeric* num) {
             hipSuccess)
             return SPC_ERR_HIP;
         if (err) num->host_status = SPC_ERR_TIMEOUT;
-    }
-    if (num->det_state) {  // an ordered wait that ran past its bound
-        const Symbolic& S = num->sym->S;
-        int32_t late = 0;
-        const size_t at = (size_t)S.nsup + S.level_ptr.size() - 1;
-        if (hipMemcpy(&late, num->det_state + at, sizeof(int32_t), hipMemcpyDeviceToHost) !=
-            hipSuccess)
-            return SPC_ERR_HIP;
-        if (late) num->host_status = SPC_ERR_TIMEOUT;
     }
     num->status_known = true;
     return num->host_status;

@@ -637,24 +637,24 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
 // row: target block + rel[i] + (row(c) - first(t)) * ld(t), with a plain
 // read-modify-write when the pair's target has no other source in this
 // level and an atomic add otherwise.
+// Forms of a launch's scatter: kAtomic (shared targets by atomic adds), and
+// those of the deterministic order: kRound (every target of the launch has one
+// writer) and kScratch (shared pairs go to the scratch for the apply pass).
+enum { kAtomic = 0, kRound = 1, kScratch = 2 };
+
 // Update tile by one workgroup of 4 waves.  If coltgt is given (an LDS array
 // of kTile entries), it receives each column's target supernode (-1 past the
-// panel), in non-decreasing order.
-// With cnt (the deterministic order): before its scatter the tile waits, for
-// every target of a shared pair among its columns, until cnt[target] reaches
-// pair_thr of the pair (every tile of the level's earlier sources into that
-// target has been added), adds its entries (atomic adds, now in a fixed
-// order per entry), waits for them to complete and adds one to cnt[target].
-// Every wait is bounded (deadline in wall-clock ticks): past it the tile sets
-// *late and goes on, and the factorization's status reads SPC_ERR_TIMEOUT.
-template <class R>
+// panel), in non-decreasing order.  Entries of a pair whose target no other
+// source of the level touches (pair_excl) are plain read-modify-writes; the
+// others atomic adds (kAtomic), plain read-modify-writes (kRound), or stores
+// of the negated entry to the source's packed block in the scratch at
+// scr_off[s] (kScratch; column c, row i >= c at c (2r - c + 1) / 2 + i - c).
+template <class R, int kMode = kAtomic>
 __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
                                             const uint8_t* __restrict__ pair_excl,
                                             R* __restrict__ arena, int* coltgt,
-                                            const int32_t* __restrict__ pair_thr = nullptr,
-                                            int32_t* __restrict__ cnt = nullptr,
-                                            uint64_t deadline = 0,
-                                            int32_t* __restrict__ late = nullptr) {
+                                            const int64_t* __restrict__ scr_off = nullptr,
+                                            R* __restrict__ scratch = nullptr) {
     typedef typename Mx<R>::acc Acc;
     __shared__ R lds[2 * 2 * kChunk * kLdsStride > kTile * kCtPad
                               ? 2 * 2 * kChunk * kLdsStride
@@ -662,7 +662,6 @@ __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
     __shared__ int64_t colbase[kTile];
     __shared__ int64_t relbase[kTile];
     __shared__ int colexcl[kTile];
-    __shared__ int colpair[kTile];
     const int s = tile.s;
     const int w = a.sn_w[s], ld = a.sn_ld[s];
     const int64_t rp = a.rowptr[s];
@@ -702,8 +701,11 @@ __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
     // the first chunk's loads go out before the column -> target lookups,
     // whose chain of dependent loads then hides under them
     fetch(0);
+    // per column: the target's column base and relative-index base, and its
+    // form: 1 plain, 0 atomic, 2 scratch (colbase then holds the column's
+    // base in the scratch block, row gi at colbase + gi)
     int64_t my_colbase = 0, my_relbase = 0;
-    int my_excl = 0, my_pair = -1, my_tgt = -1, my_thr = 0;
+    int my_excl = kMode == kRound ? 1 : 0;
     if (tid < kTile) {
         const int gc = c0 + tid;
         if (coltgt) coltgt[tid] = -1;
@@ -714,10 +716,11 @@ __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
             if (coltgt) coltgt[tid] = t;
             my_colbase = a.sn_off[t] + (int64_t)(a.rows[at] - a.sn_first[t]) * a.sn_ld[t];
             my_relbase = a.pair_rel[p] - a.pair_seg[p];
-            my_excl = pair_excl ? pair_excl[p] : 0;
-            my_pair = p;
-            my_tgt = t;
-            if (cnt) my_thr = pair_thr[p];
+            if (kMode != kRound) my_excl = pair_excl ? pair_excl[p] : 0;
+            if (kMode == kScratch && !my_excl) {
+                my_excl = 2;
+                my_colbase = scr_off[s] + (int64_t)gc * (2 * r - gc + 1) / 2 - gc;
+            }
         }
     }
     Acc acc[2][2];
@@ -747,7 +750,6 @@ __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
             colbase[tid] = my_colbase;
             relbase[tid] = my_relbase;
             colexcl[tid] = my_excl;
-            colpair[tid] = my_pair;
         }
         if (ch + 1 < nchunk) stash(buf ^ 1);
         __syncthreads();
@@ -760,26 +762,6 @@ __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
                 const int c = wc * 32 + n * 16 + lr;
                 Ct[c * kCtPad + i] = acc[m][n][q];
             }
-    // deterministic order: the first column of each shared pair waits for the
-    // target's earlier contributions (the lowest unfinished tile of the
-    // launch never waits: tiles take tickets in list order, and a tile only
-    // waits on tiles of earlier sources)
-    int my_sig = -1;
-    if (cnt && tid < kTile && my_pair >= 0 && !my_excl &&
-        (tid == 0 || colpair[tid - 1] != my_pair)) {
-        my_sig = my_tgt;
-        while (__hip_atomic_load(cnt + my_tgt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-               my_thr) {
-            // past the deadline, or once any wait of the run has gone past
-            // its own, stop waiting (the status reports the timeout)
-            if (wall_clock64() > deadline ||
-                __hip_atomic_load(late, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                __hip_atomic_store(late, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(2);
-        }
-    }
     __syncthreads();
     // thread -> row i = tid & 63 of the tile, columns c = tid / 64 + 4 u
     // (u < 16); every relative index is loaded before the first update is
@@ -793,59 +775,34 @@ __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
     for (int u = 0; u < kPer; ++u) {
         const int c = (tid >> 6) + 4 * u, gc = c0 + c;
         ok[u] = gi < r && gc < r && gi >= gc;
-        dst[u] = ok[u] ? colbase[c] + a.rel[relbase[c] + gi] : 0;
+        if (kMode == kScratch && colexcl[c] == 2) dst[u] = colbase[c] + gi;
+        else dst[u] = ok[u] ? colbase[c] + a.rel[relbase[c] + gi] : 0;
     }
     R old[kPer];
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const int c = (tid >> 6) + 4 * u;
-        old[u] = (ok[u] && colexcl[c]) ? arena[dst[u]] : R(0);
+        old[u] = (ok[u] && colexcl[c] == 1) ? arena[dst[u]] : R(0);
     }
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         if (!ok[u]) continue;
         const int c = (tid >> 6) + 4 * u;
         const R v = Ct[c * kCtPad + i];
-        if (colexcl[c]) arena[dst[u]] = old[u] - v;
+        if (colexcl[c] == 1) arena[dst[u]] = old[u] - v;
+        else if (kMode == kScratch && colexcl[c] == 2) scratch[dst[u]] = -v;
         else unsafeAtomicAdd(arena + dst[u], -v);
     }
-    if (cnt) {
-        // every add of the workgroup is complete (performed where device-scope
-        // atomics to that address are ordered) before the target's count moves
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        if (my_sig >= 0)
-            __hip_atomic_fetch_add(cnt + my_sig, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
 }
 
-template <class R>
+template <class R, int kMode>
 __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tiles, int64_t ntiles,
                                                 KArgs a, const uint8_t* __restrict__ pair_excl,
-                                                R* __restrict__ arena) {
-    update_task<R>(tiles[xcd_tile(blockIdx.x, ntiles)], a, pair_excl, arena, nullptr);
-}
-
-// Deterministic order: every workgroup takes the next tile of the list (the
-// level's tiles, sources in increasing order) by an atomic ticket, so that a
-// tile's waits point only at tiles that workgroups already hold.
-template <class R>
-__global__ __launch_bounds__(256) void k_update_ord(const UpdTile* __restrict__ tiles, KArgs a,
-                                                    const uint8_t* __restrict__ pair_excl,
-                                                    const int32_t* __restrict__ pair_thr,
-                                                    int32_t* __restrict__ cnt,
-                                                    int32_t* __restrict__ ticket,
-                                                    int32_t* __restrict__ late,
-                                                    uint64_t wait_ticks, R* __restrict__ arena) {
-    __shared__ int32_t sh_tile;
-    __shared__ uint64_t sh_deadline;
-    if (threadIdx.x == 0) {
-        sh_tile = atomicAdd(ticket, 1);
-        sh_deadline = wall_clock64() + wait_ticks;
-    }
-    __syncthreads();
-    update_task<R>(tiles[sh_tile], a, pair_excl, arena, nullptr, pair_thr, cnt, sh_deadline,
-                   late);
+                                                R* __restrict__ arena,
+                                                const int64_t* __restrict__ scr_off,
+                                                R* __restrict__ scratch) {
+    update_task<R, kMode>(tiles[xcd_tile(blockIdx.x, ntiles)], a, pair_excl, arena, nullptr,
+                          scr_off, scratch);
 }
 
 // ---------------------------------------------------------------------------
@@ -1030,8 +987,6 @@ void launch_ft(spc_numeric* num, const DevicePlan* P, const Symbolic& S, const K
                             P->small_maxr[l], P->small_maxm[l], st);
         // deterministic order: the shared targets take the small sources'
         // blocks from the scratch, one wave per target, sources in order
-        if (num->det_state && P->app_ptr[l + 1] > P->app_ptr[l])
-            launch_small_apply(num, P->app_ptr[l], P->app_ptr[l + 1], st);
         mark_end(num, st, 5, ev);
     }
     const int64_t rb0 = P->rowblk_ptr[l], rb1 = P->rowblk_ptr[l + 1];
@@ -1043,25 +998,41 @@ void launch_ft(spc_numeric* num, const DevicePlan* P, const Symbolic& S, const K
     }
 }
 
+// Update tiles [u0, u1).  exclusive_ok: plain read-modify-writes for the
+// pairs whose target no other source of the level touches, atomic adds for
+// the rest.  Deterministic order (level >= 0): the level's large sources in
+// rounds (one launch each, all plain) or in the apply form (shared pairs to
+// the scratch), then the level's apply pass (small sources, and large ones
+// in the apply form).
 template <class R>
 void launch_update(spc_numeric* num, const DevicePlan* P, const KArgs& a, int64_t u0, int64_t u1,
                    bool exclusive_ok, hipStream_t st, int32_t level = -1) {
+    if (num->det && level >= 0) {
+        const std::vector<int64_t>& rp = P->round_ptr[level];
+        const bool apply = P->level_apply[level];
+        for (size_t r = 0; r + 1 < rp.size(); ++r) {
+            if (rp[r + 1] <= rp[r]) continue;
+            const int ev = mark_begin(num, st);
+            auto kern = apply ? k_update<R, kScratch> : k_update<R, kRound>;
+            hipLaunchKernelGGL(kern, dim3((unsigned)(rp[r + 1] - rp[r])), dim3(256), 0, st,
+                               P->tiles + rp[r], rp[r + 1] - rp[r], a,
+                               (const uint8_t*)P->pair_excl, (R*)num->arena,
+                               (const int64_t*)P->scr_off, (R*)num->det_scratch);
+            mark_end(num, st, 3, ev);
+        }
+        if (P->app_ptr[level + 1] > P->app_ptr[level]) {
+            const int ev = mark_begin(num, st);
+            launch_small_apply(num, P->app_ptr[level], P->app_ptr[level + 1], st);
+            mark_end(num, st, 5, ev);
+        }
+        return;
+    }
     if (u1 <= u0) return;
     const int ev = mark_begin(num, st);
-    if (num->det_state && level >= 0 && P->level_ordered[level]) {
-        const Symbolic& S = num->sym->S;
-        const int64_t nsup = S.nsup, nl = (int64_t)S.level_ptr.size() - 1;
-        hipLaunchKernelGGL(k_update_ord<R>, dim3((unsigned)(u1 - u0)), dim3(256), 0, st,
-                           P->tiles + u0, a, (const uint8_t*)P->pair_excl,
-                           (const int32_t*)P->pair_thr, num->det_state,
-                           num->det_state + nsup + level, num->det_state + nsup + nl,
-                           num->det_wait_ticks, (R*)num->arena);
-    } else {
-        hipLaunchKernelGGL(k_update<R>, dim3((unsigned)(u1 - u0)), dim3(256), 0, st,
-                           P->tiles + u0, u1 - u0, a,
-                           exclusive_ok ? (const uint8_t*)P->pair_excl : nullptr,
-                           (R*)num->arena);
-    }
+    hipLaunchKernelGGL((k_update<R, kAtomic>), dim3((unsigned)(u1 - u0)), dim3(256), 0, st,
+                       P->tiles + u0, u1 - u0, a,
+                       exclusive_ok ? (const uint8_t*)P->pair_excl : nullptr, (R*)num->arena,
+                       (const int64_t*)nullptr, (R*)nullptr);
     mark_end(num, st, 3, ev);
 }
 
@@ -1094,11 +1065,6 @@ int32_t run_factor_t(spc_numeric* num, const double* values, hipStream_t st) {
     if (S.nnz_a > 0)
         hipLaunchKernelGGL(k_load<R>, dim3(grid_for(S.nnz_a, 256)), dim3(256), 0, st, values,
                            P->slot, arena, S.nnz_a);
-    if (num->det_state) {  // scatter counts and tile tickets start from zero
-        const int64_t ints = S.nsup + (int64_t)S.level_ptr.size();
-        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(ints, 256)), dim3(256), 0, st,
-                           num->det_state, ints, (int32_t)0);
-    }
     mark_end(num, st, 0, ev);
     const int32_t nl = (int32_t)S.level_ptr.size() - 1;
     if (num->sched == 2) {

@@ -26,8 +26,8 @@ struct Layout {
 struct PlanOffsets {
     size_t sn_first, sn_w, sn_ld, sn_off, inv_off, rowptr, rows, rowpair, slot, perm, pair_tgt,
         pair_seg, pair_rel, pair_excl, rel, level_sn, rowblk, tiles, tasks, cnt0, rb_base;
-    size_t pair_src, pair_end, pair_thr, small_scr, app_t, app_p0, app_pairs;
-    size_t rc_ptr, rc_slot, pb_off;
+    size_t pair_src, pair_end, scr_off, app_t, app_rb, app_p0, app_ent;
+    size_t slot_shared, red_row, red_ptr, red_slot, colblk;
     size_t total;
 };
 
@@ -57,20 +57,33 @@ std::vector<uint8_t> exclusive_pairs(const Symbolic& S) {
 
 // Fixed contribution order for targets shared inside a level (the paper's
 // aggregation of updates, Section III-B, in the order of non-decreasing
-// (target, source) of Section III-D): within a level the small sources'
-// contributions to a shared target come first, in increasing source order,
-// added by one wave per target from a scratch copy of each source's update
-// block; then the large sources' tiles, in increasing source order, each
-// tile waiting until the target has received every tile of the sources
-// before its own (a count of finished (tile, target) scatters, cumulative
-// over the levels: pair_thr).
+// (target, source) of Section III-D).  A pair whose target no other source
+// of the level touches adds its entries directly.  The other ("shared")
+// contributions of a level take one of two forms:
+//   apply: the sources write them to a per-level scratch (each source's
+//          lower r x r update block, packed by columns) and one wave per
+//          (shared target, block of 64 of its rows) adds them, pair by pair
+//          in increasing source order, one lane per target row (so every
+//          target entry is added by one lane, in program order) (always for
+//          the small supernodes' lane-group kernel);
+//   rounds: the large sources are coloured first-fit (round(s) = the first
+//          round none of the level's earlier sources sharing a target with s
+//          took), each round is one launch in which every target has one
+//          writer (plain read-modify-writes), and a target meets its sources
+//          round by round.
+// A level's large sources take the cheaper form by a cost estimate: a round
+// launch about 25 us; the scratch 16 bytes per entry at 4 TB/s plus about
+// 2 us per pair of its longest per-target chain; and the scratch at most
+// 2^25 entries.
 struct DetData {
-    std::vector<int32_t> pair_src, pair_end, pair_thr, app_t, app_pairs;
-    std::vector<int64_t> small_scr, app_p0;
-    std::vector<uint8_t> level_ordered;
+    std::vector<int32_t> pair_src, pair_end, app_t, app_rb;
+    std::vector<AppEnt> app_ent;
+    std::vector<int64_t> scr_off, app_p0;   // scr_off: per supernode, -1 = none
+    std::vector<int32_t> round;             // per supernode (large sources)
+    std::vector<int32_t> level_rounds;      // rounds of every level (apply form: 1)
+    std::vector<uint8_t> level_apply;       // large sources in the apply form
     std::vector<int64_t> app_ptr;
     int64_t scratch = 0;
-    bool overflow = false;  // a count past the 32-bit thresholds
 };
 
 DetData build_det(const Symbolic& S, const std::vector<uint8_t>& ex) {
@@ -79,63 +92,106 @@ DetData build_det(const Symbolic& S, const std::vector<uint8_t>& ex) {
     const int32_t nl = (int32_t)S.level_ptr.size() - 1;
     d.pair_src.resize(np);
     d.pair_end.resize(np);
-    d.pair_thr.assign(np, 0);
     for (size_t p = 0; p < np; ++p) {
         d.pair_src[p] = S.pairs[p].src;
         d.pair_end[p] = S.pairs[p].seg_end;
     }
-    d.small_scr.assign((size_t)S.nsup, -1);
-    d.level_ordered.assign((size_t)nl, 0);
+    d.scr_off.assign((size_t)S.nsup, -1);
+    d.round.assign((size_t)S.nsup, 0);
+    d.level_rounds.assign((size_t)nl, 1);
+    d.level_apply.assign((size_t)nl, 0);
     d.app_ptr.assign((size_t)nl + 1, 0);
     d.app_p0.push_back(0);
-    std::vector<int64_t> acc((size_t)S.nsup, 0);  // finished (tile, target) scatters so far
-    std::vector<std::vector<int32_t>> lists((size_t)S.nsup);
+    std::vector<std::vector<int32_t>> lists((size_t)S.nsup), used((size_t)S.nsup);
     std::vector<int32_t> touched;
+    std::vector<uint8_t> busy;
+    std::vector<std::vector<AppEnt>> blocks;
+    auto has_shared = [&](int32_t s) {
+        for (int64_t p = S.pair_ptr[s]; p < S.pair_ptr[s + 1]; ++p)
+            if (!ex[p]) return true;
+        return false;
+    };
     for (int32_t l = 0; l < nl; ++l) {
+        // first-fit rounds of the large sources, and the apply form's size
+        int32_t rounds = 1, longest = 0;
+        int64_t big_scr = 0;
+        touched.clear();
+        for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
+            const int32_t s = S.level_sn[q];
+            if (is_small(S, s) || !has_shared(s)) continue;
+            busy.assign((size_t)rounds + 1, 0);
+            for (int64_t p = S.pair_ptr[s]; p < S.pair_ptr[s + 1]; ++p)
+                if (!ex[p])
+                    for (int32_t u : used[S.pairs[p].tgt]) busy[u] = 1;
+            int32_t rs = 0;
+            while (busy[rs]) ++rs;
+            for (int64_t p = S.pair_ptr[s]; p < S.pair_ptr[s + 1]; ++p) {
+                if (ex[p]) continue;
+                const int32_t t = S.pairs[p].tgt;
+                if (used[t].empty()) touched.push_back(t);
+                used[t].push_back(rs);
+                longest = std::max(longest, (int32_t)used[t].size());
+            }
+            d.round[s] = rs;
+            rounds = std::max(rounds, rs + 1);
+            const int64_t r = S.nbelow(s);
+            big_scr += r * (r + 1) / 2;
+        }
+        for (int32_t t : touched) used[t].clear();
+        const double round_us = 25.0 * (rounds - 1);
+        const double apply_us = 16.0 * (double)big_scr / 4e6 + 2.0 * longest;
+        const bool apply = rounds > 1 && big_scr <= ((int64_t)1 << 25) && apply_us < round_us;
+        d.level_apply[l] = apply;
+        d.level_rounds[l] = apply ? 1 : rounds;
+        // scratch blocks and apply lists: the small sources, and the large
+        // ones in the apply form, in increasing source order
         int64_t scr = 0;
         touched.clear();
         for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
             const int32_t s = S.level_sn[q];
-            if (!is_small(S, s)) continue;
-            bool shared = false;
+            const bool small = is_small(S, s);
+            if (!small && apply) d.round[s] = 0;
+            if ((!small && !apply) || !has_shared(s)) continue;
             for (int64_t p = S.pair_ptr[s]; p < S.pair_ptr[s + 1]; ++p) {
                 if (ex[p]) continue;
-                shared = true;
                 const int32_t t = S.pairs[p].tgt;
                 if (lists[t].empty()) touched.push_back(t);
                 lists[t].push_back((int32_t)p);
             }
-            if (shared) {
-                const int64_t r = S.nbelow(s);
-                d.small_scr[s] = scr;
-                scr += r * (r + 1) / 2;
-            }
+            const int64_t r = S.nbelow(s);
+            d.scr_off[s] = scr;
+            scr += r * (r + 1) / 2;
         }
         d.scratch = std::max(d.scratch, scr);
         std::sort(touched.begin(), touched.end());
         for (int32_t t : touched) {
-            d.app_t.push_back(t);
-            for (int32_t p : lists[t]) d.app_pairs.push_back(p);
-            d.app_p0.push_back((int64_t)d.app_pairs.size());
+            // split every pair's rows by the 64-row block of the target row they
+            // land in (relative indices increase with the row), then one item
+            // per block with its (pair, rows) entries in source order
+            const int32_t nblk = (S.nrows(t) + kTile - 1) / kTile;
+            blocks.assign((size_t)nblk, {});
+            for (int32_t p : lists[t]) {
+                const Pair& pr = S.pairs[p];
+                const int32_t r = S.nbelow(pr.src);
+                int32_t i = pr.seg_begin;
+                while (i < r) {
+                    const int32_t blk = S.rel[pr.rel_off + (i - pr.seg_begin)] / kTile;
+                    int32_t e = i + 1;
+                    while (e < r && S.rel[pr.rel_off + (e - pr.seg_begin)] / kTile == blk) ++e;
+                    blocks[blk].push_back(AppEnt{p, i, e, 0});
+                    i = e;
+                }
+            }
+            for (int32_t blk = 0; blk < nblk; ++blk) {
+                if (blocks[blk].empty()) continue;
+                d.app_t.push_back(t);
+                d.app_rb.push_back(blk);
+                for (const AppEnt& en : blocks[blk]) d.app_ent.push_back(en);
+                d.app_p0.push_back((int64_t)d.app_ent.size());
+            }
             lists[t].clear();
         }
         d.app_ptr[l + 1] = (int64_t)d.app_t.size();
-        for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
-            const int32_t s = S.level_sn[q];
-            if (is_small(S, s)) continue;
-            const int32_t r = S.nbelow(s), nb = (r + kTile - 1) / kTile;
-            for (int64_t p = S.pair_ptr[s]; p < S.pair_ptr[s + 1]; ++p) {
-                if (ex[p]) continue;
-                const Pair& pr = S.pairs[p];
-                d.level_ordered[l] = 1;
-                d.overflow |= acc[pr.tgt] > INT32_MAX - (int64_t)nb * (nb + 1);
-                d.pair_thr[p] = (int32_t)acc[pr.tgt];
-                int64_t tiles = 0;  // tiles (i, j), i >= j, whose column block j meets the pair
-                for (int32_t bj = pr.seg_begin / kTile; bj <= (pr.seg_end - 1) / kTile; ++bj)
-                    tiles += nb - bj;
-                acc[pr.tgt] += tiles;
-            }
-        }
     }
     return d;
 }
@@ -181,13 +237,94 @@ PlanOffsets plan_layout(const Symbolic& S, const std::vector<int64_t>& rb_ptr,
     o.level_sn = L.add<int32_t>(S.level_sn.size());
     o.rowblk = L.add<RowBlock>((size_t)rb_ptr.back());
     o.tiles = L.add<UpdTile>((size_t)tl_ptr.back());
-    o.rc_ptr = L.add<int64_t>((size_t)S.n + 1);
-    o.rc_slot = L.add<int32_t>(S.rows.size() - (size_t)S.n);  // every below-diagonal row
-    o.pb_off = L.add<int64_t>(ns);
+    o.slot_shared = L.add<uint8_t>(S.rows.size());
+    o.red_row = o.red_ptr = o.red_slot = 0;  // sized by solve_layout
+    o.colblk = 0;
     o.tasks = o.cnt0 = o.rb_base = 0;
-    o.pair_src = o.pair_end = o.pair_thr = o.small_scr = o.app_t = o.app_p0 = o.app_pairs = 0;
+    o.pair_src = o.pair_end = o.scr_off = o.app_t = o.app_rb = o.app_p0 = o.app_ent = 0;
     o.total = L.total;
     return o;
+}
+
+// Forward solve: every below-diagonal row of a source has a contribution
+// slot (its place in rows).  A row that only one source of a level touches
+// is updated by that source directly; a row that several share ("shared"
+// slots) is reduced after the level, sources in increasing order, by one
+// thread per row.  Backward solve: the large supernodes' column groups.
+struct SolveData {
+    std::vector<uint8_t> shared;       // per slot
+    std::vector<int32_t> red_row;      // reduce items: target row
+    std::vector<int64_t> red_ptr;      // its slots red_slot[red_ptr[k] .. red_ptr[k + 1])
+    std::vector<int32_t> red_slot;
+    std::vector<int64_t> red_level_ptr;  // per level: its items
+    std::vector<RowBlock> colblk;      // (s, column group) of the large supernodes
+    std::vector<int64_t> colblk_ptr;   // per level
+};
+
+SolveData build_solve(const Symbolic& S) {
+    SolveData d;
+    const int32_t nl = (int32_t)S.level_ptr.size() - 1;
+    d.shared.assign(S.rows.size(), 0);
+    d.red_level_ptr.assign((size_t)nl + 1, 0);
+    d.colblk_ptr.assign((size_t)nl + 1, 0);
+    d.red_ptr.push_back(0);
+    std::vector<int32_t> cnt((size_t)S.n, 0), stamp((size_t)S.n, -1);
+    std::vector<int32_t> rows_touched;
+    for (int32_t l = 0; l < nl; ++l) {
+        rows_touched.clear();
+        for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
+            const int32_t s = S.level_sn[q];
+            for (int64_t k = S.rowptr[s] + S.width(s); k < S.rowptr[s + 1]; ++k) {
+                const int32_t row = S.rows[k];
+                if (stamp[row] != l) { stamp[row] = l; cnt[row] = 0; rows_touched.push_back(row); }
+                cnt[row]++;
+            }
+        }
+        std::sort(rows_touched.begin(), rows_touched.end());
+        // the level's shared rows become reduce items (cnt turns into the
+        // negated item index + 1); their slots, sources in increasing order
+        const int64_t items0 = (int64_t)d.red_row.size();
+        for (int32_t row : rows_touched)
+            if (cnt[row] > 1) {
+                d.red_row.push_back(row);
+                cnt[row] = -(int32_t)(d.red_row.size() - items0);
+            }
+        const int64_t nitems = (int64_t)d.red_row.size() - items0;
+        std::vector<std::vector<int32_t>> sl((size_t)nitems);
+        for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
+            const int32_t s = S.level_sn[q];
+            for (int64_t k = S.rowptr[s] + S.width(s); k < S.rowptr[s + 1]; ++k) {
+                const int32_t row = S.rows[k];
+                if (cnt[row] < 0) {
+                    d.shared[k] = 1;
+                    sl[(size_t)(-cnt[row] - 1)].push_back((int32_t)k);
+                }
+            }
+        }
+        for (auto& v : sl) {
+            for (int32_t k : v) d.red_slot.push_back(k);
+            d.red_ptr.push_back((int64_t)d.red_slot.size());
+        }
+        d.red_level_ptr[l + 1] = (int64_t)d.red_row.size();
+        for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
+            const int32_t s = S.level_sn[q];
+            if (is_small(S, s) || S.nbelow(s) == 0) continue;
+            const int32_t ng = (S.width(s) + kColGroup - 1) / kColGroup;
+            for (int32_t g = 0; g < ng; ++g) d.colblk.push_back(RowBlock{s, g});
+        }
+        d.colblk_ptr[l + 1] = (int64_t)d.colblk.size();
+    }
+    return d;
+}
+
+void solve_layout(PlanOffsets& o, const SolveData& d) {
+    Layout L;
+    L.total = o.total;
+    o.red_row = L.add<int32_t>(d.red_row.size());
+    o.red_ptr = L.add<int64_t>(d.red_ptr.size());
+    o.red_slot = L.add<int32_t>(d.red_slot.size());
+    o.colblk = L.add<RowBlock>(d.colblk.size());
+    o.total = L.total;
 }
 
 void det_layout(PlanOffsets& o, const DetData& d) {
@@ -195,11 +332,11 @@ void det_layout(PlanOffsets& o, const DetData& d) {
     L.total = o.total;
     o.pair_src = L.add<int32_t>(d.pair_src.size());
     o.pair_end = L.add<int32_t>(d.pair_end.size());
-    o.pair_thr = L.add<int32_t>(d.pair_thr.size());
-    o.small_scr = L.add<int64_t>(d.small_scr.size());
+    o.scr_off = L.add<int64_t>(d.scr_off.size());
     o.app_t = L.add<int32_t>(d.app_t.size());
     o.app_p0 = L.add<int64_t>(d.app_p0.size());
-    o.app_pairs = L.add<int32_t>(d.app_pairs.size());
+    o.app_rb = L.add<int32_t>(d.app_rb.size());
+    o.app_ent = L.add<AppEnt>(d.app_ent.size());
     o.total = L.total;
 }
 
@@ -215,6 +352,7 @@ size_t plan_bytes(const Symbolic& S, int64_t* det_scratch) {
     std::vector<int64_t> a, b;
     count_work(S, a, b);
     PlanOffsets o = plan_layout(S, a, b);
+    solve_layout(o, build_solve(S));
     if (det_scratch) *det_scratch = 0;
     if (S.opt.deterministic) {
         const DetData d = build_det(S, exclusive_pairs(S));
@@ -237,14 +375,15 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
     P->device = dev;
     count_work(S, P->rowblk_ptr, P->tile_ptr);
     PlanOffsets o = plan_layout(S, P->rowblk_ptr, P->tile_ptr);
+    const SolveData sd = build_solve(S);
+    solve_layout(o, sd);
     const std::vector<uint8_t> ex = exclusive_pairs(S);
     DetData det;
     if (S.opt.deterministic) {
         det = build_det(S, ex);
-        if (det.overflow) { delete P; return ERR_ARG; }
         det_layout(o, det);
-        P->level_ordered = det.level_ordered;
         P->app_ptr = det.app_ptr;
+        P->level_apply = det.level_apply;
         P->det_scratch = det.scratch;
     }
     // task-queue schedule: task order, dependency counts, row-block bases
@@ -317,11 +456,11 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
     if (S.opt.deterministic) {
         put(o.pair_src, det.pair_src.data(), det.pair_src.size() * 4);
         put(o.pair_end, det.pair_end.data(), det.pair_end.size() * 4);
-        put(o.pair_thr, det.pair_thr.data(), det.pair_thr.size() * 4);
-        put(o.small_scr, det.small_scr.data(), det.small_scr.size() * 8);
+        put(o.scr_off, det.scr_off.data(), det.scr_off.size() * 8);
         put(o.app_t, det.app_t.data(), det.app_t.size() * 4);
         put(o.app_p0, det.app_p0.data(), det.app_p0.size() * 8);
-        put(o.app_pairs, det.app_pairs.data(), det.app_pairs.size() * 4);
+        put(o.app_rb, det.app_rb.data(), det.app_rb.size() * 4);
+        put(o.app_ent, det.app_ent.data(), det.app_ent.size() * sizeof(AppEnt));
     }
     put(o.rel, S.rel.data(), S.rel.size() * 4);
     {
@@ -358,7 +497,34 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
         size_t a = 0, b = 0;
         std::vector<UpdTile> bulk;
         std::vector<uint8_t> colcrit;
+        if (S.opt.deterministic) P->round_ptr.assign((size_t)nl, {});
         for (int32_t l = 0; l < nl; ++l) {
+            if (S.opt.deterministic) {
+                // rounds one after another, sources in increasing order in each
+                const int32_t R = std::max(1, det.level_rounds[l]);
+                std::vector<int64_t>& rp = P->round_ptr[l];
+                rp.assign((size_t)R + 1, (int64_t)b);
+                for (int32_t rr = 0; rr < R; ++rr) {
+                    for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
+                        const int32_t s = S.level_sn[q];
+                        if (is_small(S, s) || det.round[s] != rr) continue;
+                        const int32_t nb = (S.nbelow(s) + kTile - 1) / kTile;
+                        for (int32_t i = 0; i < nb; ++i)
+                            for (int32_t j = 0; j <= i; ++j)
+                                tl[b++] = UpdTile{s, (int16_t)i, (int16_t)j};
+                    }
+                    rp[rr + 1] = (int64_t)b;
+                }
+                for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
+                    const int32_t s = S.level_sn[q];
+                    if (is_small(S, s)) continue;
+                    P->level_maxw[l] = std::max(P->level_maxw[l], S.width(s));
+                    const int32_t nb = (S.nbelow(s) + kTile - 1) / kTile;
+                    for (int32_t i = 0; i < nb; ++i) rb[a++] = RowBlock{s, i};
+                }
+                P->tile_crit[l] = (int64_t)b - P->tile_ptr[l];
+                continue;
+            }
             // tiles of this level whose columns reach a supernode of level l + 1
             // (needed before that level can be factored) come first, the
             // rest ("bulk") after them
@@ -375,12 +541,10 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
                     if (S.level[S.pairs[pp].tgt] == l + 1)
                         for (int32_t c = S.pairs[pp].seg_begin; c < S.pairs[pp].seg_end; ++c)
                             colcrit[c / kTile] = 1;
-                // deterministic order: every source's tiles together, sources
-                // in increasing order (a tile waits only on earlier tiles)
                 for (int32_t i = 0; i < nb; ++i)
                     for (int32_t j = 0; j <= i; ++j) {
                         const UpdTile t{s, (int16_t)i, (int16_t)j};
-                        if (colcrit[j] || S.opt.deterministic) tl[b++] = t;
+                        if (colcrit[j]) tl[b++] = t;
                         else bulk.push_back(t);
                     }
             }
@@ -391,31 +555,14 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
         put(o.tiles, tl.data(), tl.size() * sizeof(UpdTile));
     }
     {
-        // forward-solve contributions: one slot per below-diagonal row of every
-        // supernode (its position in rows); row j pulls the slots that hold
-        // row j, sources in increasing order
-        std::vector<int64_t> rcp((size_t)S.n + 1, 0);
-        for (int64_t s = 0; s < S.nsup; ++s)
-            for (int64_t q = S.rowptr[s] + S.width(s); q < S.rowptr[s + 1]; ++q)
-                rcp[(size_t)S.rows[q] + 1]++;
-        for (int64_t j = 0; j < S.n; ++j) rcp[j + 1] += rcp[j];
-        std::vector<int32_t> rcs((size_t)std::max<int64_t>(rcp[S.n], 1));
-        std::vector<int64_t> at(rcp.begin(), rcp.end() - 1);
-        for (int64_t s = 0; s < S.nsup; ++s)
-            for (int64_t q = S.rowptr[s] + S.width(s); q < S.rowptr[s + 1]; ++q)
-                rcs[at[S.rows[q]]++] = (int32_t)q;
-        put(o.rc_ptr, rcp.data(), rcp.size() * 8);
-        put(o.rc_slot, rcs.data(), (size_t)rcp[S.n] * 4);
-        // backward partial sums of the large supernodes' row blocks
-        std::vector<int64_t> pbo((size_t)S.nsup, 0);
-        int64_t tot = 0;
-        for (int64_t s = 0; s < S.nsup; ++s) {
-            pbo[s] = tot;
-            if (!is_small(S, s)) tot += (int64_t)((S.nbelow(s) + kTile - 1) / kTile) * S.width(s);
-        }
-        put(o.pb_off, pbo.data(), pbo.size() * 8);
+        put(o.slot_shared, sd.shared.data(), sd.shared.size());
+        put(o.red_row, sd.red_row.data(), sd.red_row.size() * 4);
+        put(o.red_ptr, sd.red_ptr.data(), sd.red_ptr.size() * 8);
+        put(o.red_slot, sd.red_slot.data(), sd.red_slot.size() * 4);
+        put(o.colblk, sd.colblk.data(), sd.colblk.size() * sizeof(RowBlock));
         P->nslots = (int64_t)S.rows.size();
-        P->pb_total = tot;
+        P->red_level_ptr = sd.red_level_ptr;
+        P->colblk_ptr = sd.colblk_ptr;
     }
     if (!tasks.empty()) put(o.tasks, tasks.data(), tasks.size() * sizeof(Task));
     if (!cnt0.empty()) put(o.cnt0, cnt0.data(), cnt0.size() * 4);
@@ -449,17 +596,19 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
     P->level_sn = (int32_t*)(base + o.level_sn);
     P->rowblk = (RowBlock*)(base + o.rowblk);
     P->tiles = (UpdTile*)(base + o.tiles);
-    P->rc_ptr = (int64_t*)(base + o.rc_ptr);
-    P->rc_slot = (int32_t*)(base + o.rc_slot);
-    P->pb_off = (int64_t*)(base + o.pb_off);
+    P->slot_shared = (uint8_t*)(base + o.slot_shared);
+    P->red_row = (int32_t*)(base + o.red_row);
+    P->red_ptr = (int64_t*)(base + o.red_ptr);
+    P->red_slot = (int32_t*)(base + o.red_slot);
+    P->colblk = (RowBlock*)(base + o.colblk);
     if (S.opt.deterministic) {
         P->pair_src = (int32_t*)(base + o.pair_src);
         P->pair_end = (int32_t*)(base + o.pair_end);
-        P->pair_thr = (int32_t*)(base + o.pair_thr);
-        P->small_scr = (int64_t*)(base + o.small_scr);
+        P->scr_off = (int64_t*)(base + o.scr_off);
         P->app_t = (int32_t*)(base + o.app_t);
         P->app_p0 = (int64_t*)(base + o.app_p0);
-        P->app_pairs = (int32_t*)(base + o.app_pairs);
+        P->app_rb = (int32_t*)(base + o.app_rb);
+        P->app_ent = (AppEnt*)(base + o.app_ent);
     }
     if (S.opt.sched == 2) {
         P->tasks = (Task*)(base + o.tasks);

@@ -79,6 +79,9 @@ struct Task { int32_t s; int16_t a, b; int32_t kind; };
 struct UpdTile { int32_t s; int16_t bi, bj; };
 // One panel row block of source supernode s.
 struct RowBlock { int32_t s; int32_t rb; };
+// Deterministic order, apply pass: rows [ilo, ihi) of pair p's source that
+// land in one 64-row block of the target.
+struct AppEnt { int32_t p, ilo, ihi, pad; };
 
 // Device copy of the symbolic analysis, shared by every factor of it on one device.
 struct DevicePlan {
@@ -115,22 +118,24 @@ struct DevicePlan {
     // deterministic scatter order (analysis option deterministic = 1)
     int32_t* pair_src = nullptr;  // source supernode of each pair
     int32_t* pair_end = nullptr;  // seg_end of each pair
-    int32_t* pair_thr = nullptr;  // large sources, shared target: the target's count of
-                                  // finished (tile, target) scatters to wait for
-    int64_t* small_scr = nullptr; // small sources: offset of the update block in the
-                                  // level's scratch (-1: every target exclusive)
+    int64_t* scr_off = nullptr;   // sources in the apply form: offset of the update block
+                                  // in the level's scratch (-1: none)
     int32_t* app_t = nullptr;     // apply items: target supernode of item k
-    int64_t* app_p0 = nullptr;    // pairs of item k: app_pairs[app_p0[k] .. app_p0[k + 1])
-    int32_t* app_pairs = nullptr; // small-source pairs in source order
-    // solves: forward contributions are kept per entry of `rows` (the below-
-    // diagonal rows of every supernode) and pulled by the target's rows
-    int64_t* rc_ptr = nullptr;    // n + 1: contributions to row j at rc_slot[rc_ptr[j] ..]
-    int32_t* rc_slot = nullptr;   // positions in rows, sources in increasing order
-    int64_t* pb_off = nullptr;    // per supernode: its backward partial sums (row block b,
-                                  // column k at pb_off + b w + k; large supernodes)
-    int64_t nslots = 0;           // entries of rows
-    int64_t pb_total = 0;
-    std::vector<uint8_t> level_ordered;  // the level's tiles wait on shared targets
+    int32_t* app_rb = nullptr;    // and the 64-row block of the target it covers
+    int64_t* app_p0 = nullptr;    // entries of item k: app_ent[app_p0[k] .. app_p0[k + 1])
+    AppEnt* app_ent = nullptr;    // in increasing source order
+    // solves: a contribution slot per entry of `rows` (each source's rows
+    // below its diagonal block); rows several sources of a level share are
+    // reduced after the level, sources in increasing order
+    uint8_t* slot_shared = nullptr;  // per slot: its row is shared inside the level
+    int32_t* red_row = nullptr;      // reduce items: row
+    int64_t* red_ptr = nullptr;      // slots of item k: red_slot[red_ptr[k] .. red_ptr[k + 1])
+    int32_t* red_slot = nullptr;
+    RowBlock* colblk = nullptr;      // backward column groups (s, g) of the large supernodes
+    int64_t nslots = 0;              // entries of rows
+    std::vector<int64_t> red_level_ptr, colblk_ptr;  // per level
+    std::vector<std::vector<int64_t>> round_ptr;  // per level: tile ranges of its rounds
+    std::vector<uint8_t> level_apply;    // per level: large sources in the apply form
     std::vector<int64_t> app_ptr;        // per level: its apply items
     int64_t det_scratch = 0;             // elements of the per-level update scratch
     // host-side launch bookkeeping per level; inside each level of level_sn
@@ -143,27 +148,18 @@ struct DevicePlan {
                                                               // supernode of the level
 };
 
-// Contribution slots of the forward solve and the partial sums of the
-// backward solve, with the plan's lists that address them.
+// Columns of the backward solve's column groups.
+constexpr int kColGroup = 8;
+
+// Forward contribution slots: (L21 y_s)[i] of a row that several sources of
+// the level share goes to cb (nslots x nrhs) at the row's slot; the others
+// are subtracted from y directly.
 template <class R>
 struct SolveBufs {
-    R* cb;                    // nslots x nrhs: (L21 y_s)[i] at the slot of row i of s
-    R* pb;                    // pb_total x nrhs: backward partial sums
-    int64_t nslots, pb_total;
-    const int64_t* rc_ptr;    // row j pulls cb at rc_slot[rc_ptr[j] .. rc_ptr[j + 1])
-    const int32_t* rc_slot;
-    const int64_t* pb_off;
+    R* cb;
+    int64_t nslots;
+    const uint8_t* shared;
 };
-
-// y[j] minus every contribution to row j, in increasing source order.
-template <class R>
-__device__ inline R pulled(const R* __restrict__ yc, const R* __restrict__ cbc,
-                                    const SolveBufs<R>& sb, int64_t j) {
-    R v = yc[j];
-    const int64_t q1 = sb.rc_ptr[j + 1];
-    for (int64_t q = sb.rc_ptr[j]; q < q1; ++q) v -= cbc[sb.rc_slot[q]];
-    return v;
-}
 
 // Pointer bundle passed by value to kernels.
 struct KArgs {
@@ -207,9 +203,7 @@ struct spc_numeric {
     std::vector<hipEvent_t> sync_ev; // per-level ordering events between the two streams
     hipStream_t capture = nullptr;  // stream the solve sweeps are captured on
     int32_t* sched_state = nullptr; // task-queue counters: cntF, doneF, doneT, ticket/abort/err
-    int32_t* det_state = nullptr;   // deterministic order: finished (tile, target) scatters per
-                                    // supernode, one tile ticket per level, a late-wait flag
-    uint64_t det_wait_ticks = 0;    // bound of an ordered wait, wall-clock ticks
+    bool det = false;               // deterministic contribution order
     void* det_scratch = nullptr;    // small sources' update blocks of one level (factor type)
     int32_t* task_log = nullptr;    // sched 2 with debug bit 1: start and finish stamps per task
     int64_t spin_limit = 0;

@@ -237,28 +237,35 @@ __global__ __launch_bounds__(256) void k_small(const int32_t* __restrict__ list,
                          det);
 }
 
-// Deterministic order: one wave per apply item (a target that several small
-// sources of the level share) adds those sources' blocks from the scratch,
-// pair by pair in increasing source order; the adds of one pair complete
-// before the next pair's start, so every target entry receives its
-// contributions in that order.
+// Deterministic order, apply pass: one wave per item (a shared target t and
+// a block of 64 of its rows, rho0 .. rho0 + 63).  Lane L owns target row
+// rho0 + L: for every entry of the item, sources in increasing order, it
+// adds the scratch values of the source row landing on its target row, one
+// column after another; so each target entry is updated by one lane, in
+// program order (plain read-modify-writes, no atomics).
 template <class R>
-__global__ __launch_bounds__(256) void k_small_apply(const int32_t* __restrict__ app_t,
-                                                     const int64_t* __restrict__ app_p0,
-                                                     const int32_t* __restrict__ app_pairs,
-                                                     const int32_t* __restrict__ pair_src,
-                                                     const int32_t* __restrict__ pair_end,
-                                                     const int64_t* __restrict__ scr_off,
-                                                     const R* __restrict__ scratch, KArgs a,
-                                                     R* __restrict__ arena, int64_t count) {
-    const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (k >= count) return;
-    const int t = app_t[k];
-    const int64_t toff = a.sn_off[t];
+__global__ __launch_bounds__(256) void k_apply(const int32_t* __restrict__ app_t,
+                                               const int32_t* __restrict__ app_rb,
+                                               const int64_t* __restrict__ app_p0,
+                                               const AppEnt* __restrict__ ent,
+                                               const int32_t* __restrict__ pair_src,
+                                               const int32_t* __restrict__ pair_end,
+                                               const int64_t* __restrict__ scr_off,
+                                               const R* __restrict__ scratch, KArgs a,
+                                               R* __restrict__ arena, int64_t count) {
+    __shared__ int own_s[4][kTile];
+    __shared__ int64_t cb_s[4][kMaxWidth];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t k = (int64_t)blockIdx.x * 4 + wave;
+    if (k >= count) return;  // no workgroup barrier below
+    int* own = own_s[wave];
+    int64_t* cbs = cb_s[wave];
+    const int t = app_t[k], rho0 = app_rb[k] * kTile;
+    const int64_t toff = a.sn_off[t] + rho0 + lane;
     const int tfirst = a.sn_first[t], tld = a.sn_ld[t];
     for (int64_t q = app_p0[k]; q < app_p0[k + 1]; ++q) {
-        const int p = app_pairs[q];
+        const AppEnt en = ent[q];
+        const int p = en.p;
         const int s = pair_src[p];
         const int w = a.sn_w[s];
         const int64_t rp = a.rowptr[s];
@@ -266,12 +273,29 @@ __global__ __launch_bounds__(256) void k_small_apply(const int32_t* __restrict__
         const int b = a.pair_seg[p], e = pair_end[p];
         const int64_t relb = a.pair_rel[p] - b;
         const R* __restrict__ blk = scratch + scr_off[s];
-        for (int c = b; c < e; ++c) {
-            const int64_t cb = toff + (int64_t)(a.rows[rp + w + c] - tfirst) * tld;
-            const int64_t pk = (int64_t)c * (2 * r - c + 1) / 2 - c;
-            for (int i = c + lane; i < r; i += 64) unsafeAtomicAdd(arena + cb + a.rel[relb + i], blk[pk + i]);
+        own[lane] = -1;
+        __builtin_amdgcn_wave_barrier();
+        for (int i = en.ilo + lane; i < en.ihi; i += 64) own[a.rel[relb + i] - rho0] = i;
+        for (int c = b + lane; c < e; c += 64)
+            cbs[c - b] = (int64_t)(a.rows[rp + w + c] - tfirst) * tld;
+        __builtin_amdgcn_wave_barrier();
+        const int i = own[lane];
+        if (i >= 0) {
+            const int c1 = min(e, i + 1);
+            for (int c0 = b; c0 < c1; c0 += 8) {  // eight columns' loads in flight
+                R v[8], old[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int c = c0 + u;
+                    v[u] = c < c1 ? blk[(int64_t)c * (2 * r - c + 1) / 2 + (i - c)] : R(0);
+                    old[u] = c < c1 ? arena[toff + cbs[c - b]] : R(0);
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (c0 + u < c1) arena[toff + cbs[c0 + u - b]] = old[u] + v[u];
+            }
         }
-        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -292,8 +316,9 @@ __device__ __forceinline__ T group_sum(T v) {
 
 // Forward solve of one small supernode per G lanes, every right-hand side
 // (WB: a bound on the level's small widths, so registers follow the level):
-//   y_s = inv(L11) (y_s - contributions pulled in source order);
-//   (L21 y_s)[i] into the contribution slot of each row i below.
+//   y_s = inv(L11) y_s;  y[rows below] -= L21 y_s, in place for a row that no
+//   other source of the level updates, else into the row's contribution slot
+//   (reduced after the level in source order).
 template <class R, int WB, int G>
 __global__ __launch_bounds__(256) void k_small_fwd(const int32_t* __restrict__ list, int count,
                                                    KArgs a, const R* __restrict__ arena,
@@ -316,10 +341,11 @@ __global__ __launch_bounds__(256) void k_small_fwd(const int32_t* __restrict__ l
         iv[k] = (gl < w && k < w) ? inv[gl * w + k] : R(0);
     }
     const int32_t row = gl < r ? a.rows[rp + w + gl] : 0;
+    const bool shared = gl < r && sb.shared[rp + w + gl];
     for (int c = 0; c < nrhs; ++c) {
         R* __restrict__ yc = y + (int64_t)c * n;
         R* __restrict__ cbc = sb.cb + (int64_t)c * sb.nslots;
-        const R b = gl < w ? pulled(yc, cbc, sb, first + gl) : R(0);
+        const R b = gl < w ? yc[first + gl] : R(0);
         R ys = R(0);
 #pragma unroll
         for (int k = 0; k < WB; ++k) ys += iv[k] * __shfl(b, k, G);
@@ -327,7 +353,10 @@ __global__ __launch_bounds__(256) void k_small_fwd(const int32_t* __restrict__ l
         R acc = R(0);
 #pragma unroll
         for (int k = 0; k < WB; ++k) acc += li[k] * __shfl(ys, k, G);
-        if (gl < r) cbc[rp + w + gl] = acc;
+        if (gl < r) {
+            if (shared) cbc[rp + w + gl] = acc;
+            else yc[row] -= acc;
+        }
     }
 }
 
@@ -385,7 +414,7 @@ void launch_small_factor(spc_numeric* num, const KArgs& a, const int32_t* list, 
         using T = std::remove_pointer_t<decltype(arena)>;
         const unsigned g = (unsigned)std::max(1, (count + per_block - 1) / per_block);
         SmallDet<T> det{nullptr, nullptr, nullptr};
-        if (num->det_state) det = SmallDet<T>{P->pair_excl, P->small_scr, (T*)num->det_scratch};
+        if (num->det) det = SmallDet<T>{P->pair_excl, P->scr_off, (T*)num->det_scratch};
         hipLaunchKernelGGL(kern, dim3(g), dim3(256), lds, st, list, count, a, arena,
                            (T*)num->dinv, num->status_dev, maxw, maxr, det);
     };
@@ -410,14 +439,14 @@ void launch_small_apply(spc_numeric* num, int64_t i0, int64_t i1, hipStream_t st
     if (count <= 0) return;
     const dim3 g((unsigned)((count + 3) / 4)), b(256);
     if (num->prec == 1)
-        hipLaunchKernelGGL(k_small_apply<float>, g, b, 0, st, P->app_t + i0, P->app_p0 + i0,
-                           (const int32_t*)P->app_pairs, (const int32_t*)P->pair_src,
-                           (const int32_t*)P->pair_end, (const int64_t*)P->small_scr,
+        hipLaunchKernelGGL(k_apply<float>, g, b, 0, st, P->app_t + i0, P->app_rb + i0,
+                           P->app_p0 + i0, (const AppEnt*)P->app_ent, (const int32_t*)P->pair_src,
+                           (const int32_t*)P->pair_end, (const int64_t*)P->scr_off,
                            (const float*)num->det_scratch, a, (float*)num->arena, count);
     else
-        hipLaunchKernelGGL(k_small_apply<double>, g, b, 0, st, P->app_t + i0, P->app_p0 + i0,
-                           (const int32_t*)P->app_pairs, (const int32_t*)P->pair_src,
-                           (const int32_t*)P->pair_end, (const int64_t*)P->small_scr,
+        hipLaunchKernelGGL(k_apply<double>, g, b, 0, st, P->app_t + i0, P->app_rb + i0,
+                           P->app_p0 + i0, (const AppEnt*)P->app_ent, (const int32_t*)P->pair_src,
+                           (const int32_t*)P->pair_end, (const int64_t*)P->scr_off,
                            (const double*)num->det_scratch, a, (double*)num->arena, count);
 }
 
@@ -429,8 +458,7 @@ void launch_small_solve(spc_numeric* num, const KArgs& a, const int32_t* list, i
     auto go = [&](auto kf, auto kb, int per_block, auto* yt) {
         using T = std::remove_pointer_t<decltype(yt)>;
         const dim3 g((unsigned)std::max(1, (count + per_block - 1) / per_block)), b(256);
-        const SolveBufs<T> sb{(T*)cb, nullptr, P->nslots, P->pb_total, P->rc_ptr, P->rc_slot,
-                              P->pb_off};
+        const SolveBufs<T> sb{(T*)cb, P->nslots, P->slot_shared};
         if (forward)
             hipLaunchKernelGGL(kf, g, b, 0, st, list, count, a, (const T*)num->arena,
                                (const T*)num->dinv, yt, n, nrhs, sb);

@@ -2,20 +2,20 @@
 // arXiv:1608.00044): y = L^{-1} P b by a forward sweep over the supernodal
 // elimination tree from the leaves, then z = L^{-T} y from the root back, and
 // x = P^T z.  Both sweeps go level by level; within a level every supernode
-// is independent.  Each level is two launches:
-//   forward:  k_fwd_diag  -- y_s = L11^{-1} (y_s - the contributions of the
-//                            descendants to rows of s), one workgroup per
-//                            supernode, by 16-column panels using the inverted
-//                            16 x 16 diagonal blocks the factorization kept;
-//             k_fwd_gemv  -- (L21 y_s)[i] for every row i of every 64-row
-//                            block of the panel, stored in the contribution
-//                            slot of that row of s (its place in the row
-//                            lists), which the target's diagonal solve pulls
-//                            in increasing source order;
-//   backward: k_bwd_gemv  -- partial sums of L21^T y[rows below], one per
-//                            64-row block and column (one thread per column);
-//             k_bwd_diag  -- y_s = L11^{-T} (y_s - t_s), t_s the sum of the
-//                            partial sums in row-block order, panels in reverse.
+// is independent.  Per level:
+//   forward:  k_fwd_diag   -- y_s = L11^{-1} y_s, one workgroup per supernode,
+//                             by 16-column panels using the inverted 16 x 16
+//                             diagonal blocks the factorization kept;
+//             k_fwd_gemv   -- y[rows below] -= L21 y_s for every 64-row block
+//                             of the panel; a row that another source of the
+//                             level also updates gets its value in a
+//                             contribution slot instead,
+//             k_fwd_reduce -- which one thread per such row subtracts, sources
+//                             in increasing order;
+//   backward: k_bwd_cols   -- t_s = L21^T y[rows below], one workgroup per group
+//                             of kColGroup columns over every row, summed in a
+//                             fixed tree;
+//             k_bwd_diag   -- y_s = L11^{-T} (y_s - t_s), panels in reverse.
 // No update is an atomic add: every sum has one fixed order, so a solve has
 // the same bits on every run.  Several right-hand sides go through every
 // kernel in groups of eight, so the factor is read once per group.
@@ -148,10 +148,10 @@ __device__ __forceinline__ void stage_rows(R* __restrict__ Pl, const R* __restri
     }
 }
 
-// Diagonal block, forward: y_s = L11^{-1} (y_s minus the pulled contributions).
-// The workgroup stages L11 (packed lower triangle) and the 16 x 16
-// diagonal-block inverses in LDS; then each wave pulls and solves its own
-// right-hand sides with no workgroup barrier, right-looking by panels:
+// Diagonal block, forward: y_s = L11^{-1} y_s.  The workgroup stages L11
+// (packed lower triangle) and the 16 x 16 diagonal-block inverses in LDS;
+// then each wave solves its own right-hand sides with no workgroup barrier,
+// right-looking by panels:
 //   y_p = inv(D_p) y_p                      (lane (j, part): four products,
 //                                             the parts meet by cross-lane adds)
 //   y[k] -= L[k, p] y_p for every k below   (one row per lane, the sixteen
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kDiagThreads) void k_fwd_diag(const int32_t* __rest
                                                            KArgs a,
                                                   const R* __restrict__ arena,
                                                   const R* __restrict__ dinv, R* __restrict__ y,
-                                                  int64_t n, int nrhs, SolveBufs<R> sb) {
+                                                  int64_t n, int nrhs) {
     extern __shared__ double sm_raw[];
     R* sm = (R*)sm_raw;
     __shared__ R ys[kDiagThreads / 64][kMaxWidth + kPanel];
@@ -179,13 +179,12 @@ __global__ __launch_bounds__(kDiagThreads) void k_fwd_diag(const int32_t* __rest
     R* yw = ys[wave];
     for (int c = wave; c < nrhs; c += kDiagThreads / 64) {
         R* __restrict__ yc = y + (int64_t)c * n;
-        const R* __restrict__ cbc = sb.cb + (int64_t)c * sb.nslots;
         {
-            R v[(kMaxWidth + 63) / 64];
+            R v[(kMaxWidth + 63) / 64];  // all of the wave's loads in flight at once
 #pragma unroll
             for (int u = 0; u < (kMaxWidth + 63) / 64; ++u) {
                 const int k = lane + 64 * u;
-                v[u] = k < w ? pulled(yc, cbc, sb, first + k) : R(0);
+                v[u] = k < w ? yc[first + k] : R(0);
             }
 #pragma unroll
             for (int u = 0; u < (kMaxWidth + 63) / 64; ++u)
@@ -227,10 +226,11 @@ __global__ __launch_bounds__(kDiagThreads) void k_fwd_diag(const int32_t* __rest
     }
 }
 
-// Below the diagonal block, forward: sum_k L21[i][k] y_s[k] for the rows i of
+// Below the diagonal block, forward: y[rows(i)] -= sum_k L21[i][k] y_s[k] for
 // one 64-row block: the block is staged in LDS, thread (row, wave) sums every
-// 4th column, the four waves meet in LDS, one store per row and column into
-// the row's contribution slot.
+// 4th column, the four waves meet in LDS; a row no other source of the level
+// updates is updated in place (its only writer), a shared row's sum goes to
+// its contribution slot for k_fwd_reduce.
 template <class R, int NR>
 __global__ __launch_bounds__(256) void k_fwd_gemv(const RowBlock* __restrict__ work, KArgs a,
                                                   const R* __restrict__ arena, R* __restrict__ y,
@@ -292,68 +292,103 @@ __global__ __launch_bounds__(256) void k_fwd_gemv(const RowBlock* __restrict__ w
         __syncthreads();
         if (tid < m) {
             const int64_t slot = rp + w + i0 + tid;
-            for (int c = 0; c < nc; ++c)
-                sb.cb[(int64_t)(c0 + c) * sb.nslots + slot] =
-                    (red[0][c][tid] + red[1][c][tid]) + (red[2][c][tid] + red[3][c][tid]);
+            const int32_t row = below[i0 + tid];
+            const bool sh = sb.shared[slot];
+            for (int c = 0; c < nc; ++c) {
+                const R v = (red[0][c][tid] + red[1][c][tid]) + (red[2][c][tid] + red[3][c][tid]);
+                if (sh) sb.cb[(int64_t)(c0 + c) * sb.nslots + slot] = v;
+                else y[(int64_t)(c0 + c) * n + row] -= v;
+            }
         }
         __syncthreads();
     }
 }
 
-// Below the diagonal block, backward: sum_i L21[i][k] y[rows(i)] over one
-// 64-row block staged in LDS: thread k walks column k (its own padded LDS
-// column) for NR right-hand sides at a time and stores one partial sum per
-// column and right-hand side (the block's place in pb).
+// Shared rows of a level, forward: y[row] -= the row's contribution slots,
+// sources in increasing order, one thread per row and right-hand side; each
+// thread issues its slots' loads eight at a time.
+template <class R>
+__global__ __launch_bounds__(256) void k_fwd_reduce(const int32_t* __restrict__ red_row,
+                                                    const int64_t* __restrict__ red_ptr,
+                                                    const int32_t* __restrict__ red_slot,
+                                                    int64_t count, R* __restrict__ y, int64_t n,
+                                                    int nrhs, SolveBufs<R> sb) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count * nrhs) return;
+    const int64_t k = e % count, c = e / count;
+    const R* __restrict__ cbc = sb.cb + c * sb.nslots;
+    R* __restrict__ yc = y + c * n;
+    const int64_t q0 = red_ptr[k], q1 = red_ptr[k + 1];
+    R v = yc[red_row[k]];
+    for (int64_t q = q0; q < q1; q += 8) {
+        R t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = q + u < q1 ? cbc[red_slot[q + u]] : R(0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (q + u < q1) v -= t[u];
+    }
+    yc[red_row[k]] = v;
+}
+
+// Below the diagonal block, backward: t_s[k] = sum_i L21[i][k] y[rows(i)] for
+// the kColGroup columns k of group g of supernode s, over every row i below
+// the diagonal block: thread tid takes rows tid, tid + 256, ... (coalesced down
+// each column of the column-major panel), then the 256 partial sums of every
+// (column, right-hand side) meet in a fixed tree: across each wave by
+// butterfly shuffles, then the four waves in order.  One workgroup writes
+// each t_s[k] (no atomics).  NR right-hand sides at a time.
 template <class R, int NR>
-__global__ __launch_bounds__(256) void k_bwd_gemv(const RowBlock* __restrict__ work, KArgs a,
+__global__ __launch_bounds__(256) void k_bwd_cols(const RowBlock* __restrict__ work, KArgs a,
                                                   const R* __restrict__ arena,
-                                                  const R* __restrict__ y, int64_t n, int nrhs,
-                                                  SolveBufs<R> sb) {
-    extern __shared__ double sm_raw[];
-    R* Pl = (R*)sm_raw;
-    __shared__ R xr[kTile][NR];
+                                                  const R* __restrict__ y, R* __restrict__ tacc,
+                                                  int64_t n, int nrhs) {
+    constexpr int G = kColGroup;
+    __shared__ R part[4][G * NR];
     const RowBlock wb = work[blockIdx.x];
-    const int s = wb.s;
+    const int s = wb.s, g = wb.rb;
     const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
     const int64_t rp = a.rowptr[s];
     const int r = (int)(a.rowptr[s + 1] - rp) - w;
-    const R* __restrict__ P = arena + a.sn_off[s] + w;
+    const int k0 = g * G, kc = min(G, w - k0);
+    const R* __restrict__ P = arena + a.sn_off[s] + w + (int64_t)k0 * ld;
     const int32_t* __restrict__ below = a.rows + rp + w;
-    const int tid = threadIdx.x;
-    const int i0 = wb.rb * kTile, m = min(kTile, r - i0);
-    stage_rows<R>(Pl, P, ld, i0, m, w, tid);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     for (int c0 = 0; c0 < nrhs; c0 += NR) {
         const int nc = min(NR, nrhs - c0);
-        for (int e = tid; e < NR * kTile; e += 256) {
-            const int c = e / kTile, ii = e - c * kTile;
-            xr[ii][c] = (c < nc && ii < m) ? y[(int64_t)(c0 + c) * n + below[i0 + ii]] : R(0);
+        R acc[G][NR];
+#pragma unroll
+        for (int k = 0; k < G; ++k)
+#pragma unroll
+            for (int c = 0; c < NR; ++c) acc[k][c] = R(0);
+        for (int i = tid; i < r; i += 256) {
+            const int32_t row = below[i];
+            R yv[NR], pv[G];
+#pragma unroll
+            for (int c = 0; c < NR; ++c)
+                yv[c] = c < nc ? y[(int64_t)(c0 + c) * n + row] : R(0);
+#pragma unroll
+            for (int k = 0; k < G; ++k) pv[k] = k < kc ? P[i + (int64_t)k * ld] : R(0);
+#pragma unroll
+            for (int k = 0; k < G; ++k)
+#pragma unroll
+                for (int c = 0; c < NR; ++c) acc[k][c] += pv[k] * yv[c];
         }
-        __syncthreads();
-        for (int k = tid; k < w; k += 256) {
-            const R* __restrict__ col = Pl + k * kPs;
-            R acc[NR][2];
 #pragma unroll
-            for (int c = 0; c < NR; ++c) acc[c][0] = acc[c][1] = R(0);
-            // eight rows per step, every load first (rows past m are zero in LDS)
-            for (int ib = 0; ib < m; ib += 8) {
-                R pv[8], xv[8][NR];
+        for (int k = 0; k < G; ++k)
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    pv[u] = col[ib + u];
+            for (int c = 0; c < NR; ++c) {
+                R v = acc[k][c];
 #pragma unroll
-                    for (int c = 0; c < NR; ++c) xv[u][c] = xr[ib + u][c];
-                }
-#pragma unroll
-                for (int u = 0; u < 8; u += 2)
-#pragma unroll
-                    for (int c = 0; c < NR; ++c) {
-                        acc[c][0] += pv[u] * xv[u][c];
-                        acc[c][1] += pv[u + 1] * xv[u + 1][c];
-                    }
+                for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+                if (lane == 0) part[wave][k * NR + c] = v;
             }
-            const int64_t at = sb.pb_off[s] + (int64_t)wb.rb * w + k;
-            for (int c = 0; c < nc; ++c)
-                sb.pb[(int64_t)(c0 + c) * sb.pb_total + at] = acc[c][0] + acc[c][1];
+        __syncthreads();
+        if (tid < G * NR) {
+            const int k = tid / NR, c = tid % NR;
+            if (k < kc && c < nc)
+                tacc[(int64_t)(c0 + c) * n + first + k0 + k] =
+                    (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
         }
         __syncthreads();
     }
@@ -368,7 +403,8 @@ __global__ __launch_bounds__(kDiagThreads) void k_bwd_diag(const int32_t* __rest
                                                            KArgs a,
                                                   const R* __restrict__ arena,
                                                   const R* __restrict__ dinv, R* __restrict__ y,
-                                                  int64_t n, int nrhs, SolveBufs<R> sb) {
+                                                  const R* __restrict__ tacc, int64_t n,
+                                                  int nrhs) {
     extern __shared__ double sm_raw[];
     R* sm = (R*)sm_raw;
     __shared__ R ys[kDiagThreads / 64][kMaxWidth + kPanel];
@@ -384,20 +420,17 @@ __global__ __launch_bounds__(kDiagThreads) void k_bwd_diag(const int32_t* __rest
     stage_block<R>(T, I, inv, w, tid);
     __syncthreads();
     R* yw = ys[wave];
-    const int nb = ((int)(a.rowptr[s + 1] - a.rowptr[s]) - w + kTile - 1) / kTile;
+    const bool below = a.rowptr[s + 1] - a.rowptr[s] > w;  // t_s exists (rows below)
     for (int c = wave; c < nrhs; c += kDiagThreads / 64) {
         R* __restrict__ yc = y + (int64_t)c * n;
-        const R* __restrict__ pc = sb.pb + (int64_t)c * sb.pb_total + sb.pb_off[s];
+        const R* __restrict__ tc = tacc + (int64_t)c * n;
         {
             R v[(kMaxWidth + 63) / 64], t[(kMaxWidth + 63) / 64];
 #pragma unroll
             for (int u = 0; u < (kMaxWidth + 63) / 64; ++u) {
                 const int k = lane + 64 * u;
                 v[u] = k < w ? yc[first + k] : R(0);
-                R acc = R(0);  // the row blocks' partial sums in block order
-                if (k < w)
-                    for (int b = 0; b < nb; ++b) acc += pc[(int64_t)b * w + k];
-                t[u] = acc;
+                t[u] = (k < w && below) ? tc[first + k] : R(0);
             }
 #pragma unroll
             for (int u = 0; u < (kMaxWidth + 63) / 64; ++u)
@@ -455,12 +488,9 @@ int32_t configure_solve_kernels() {
         if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, mx) != hipSuccess)
             return ERR_HIP;
     const int mg = (int)(kMaxWidth * kPs * sizeof(double));
-    const void* gemv[] = {(const void*)k_fwd_gemv<double, 1>, (const void*)k_bwd_gemv<double, 1>,
-                          (const void*)k_fwd_gemv<float, 1>, (const void*)k_bwd_gemv<float, 1>,
+    const void* gemv[] = {(const void*)k_fwd_gemv<double, 1>, (const void*)k_fwd_gemv<float, 1>,
                           (const void*)k_fwd_gemv<double, kRhs>,
-                          (const void*)k_bwd_gemv<double, kRhs>,
-                          (const void*)k_fwd_gemv<float, kRhs>,
-                          (const void*)k_bwd_gemv<float, kRhs>};
+                          (const void*)k_fwd_gemv<float, kRhs>};
     for (const void* f : gemv)
         if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, mg) != hipSuccess)
             return ERR_HIP;
@@ -469,9 +499,10 @@ int32_t configure_solve_kernels() {
 
 namespace {
 
-// The level sweeps of one solve on the internal work vectors (y, t), as
-// enqueued on stream st.  Gather and scatter stay outside: they touch the
-// caller's b and x, which change from call to call.
+// The level sweeps of one solve on the work array (y, then the contribution
+// slots, then t, factor type), as enqueued on stream st.  Gather and scatter
+// stay outside: they touch the caller's b and x, which change from call to
+// call.
 template <class R, int NR>
 void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* work, hipStream_t st) {
     const Symbolic& S = num->sym->S;
@@ -482,8 +513,8 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* work, hipStream_t st) {
     const R* dinv = (const R*)num->dinv;
     R* y = work;
     R* cb = y + n * nrhs;
-    const SolveBufs<R> sb{cb, cb + P->nslots * nrhs, P->nslots, P->pb_total,
-                          P->rc_ptr, P->rc_slot, P->pb_off};
+    R* tacc = cb + P->nslots * nrhs;
+    const SolveBufs<R> sb{cb, P->nslots, P->slot_shared};
     const int32_t nl = (int32_t)S.level_ptr.size() - 1;
     for (int32_t l = 0; l < nl; ++l) {
         const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1], nbig = P->level_nbig[l];
@@ -491,25 +522,31 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* work, hipStream_t st) {
         const size_t lds_rows = (size_t)P->level_maxw[l] * kPs * sizeof(R);
         if (nbig > 0)
             hipLaunchKernelGGL(k_fwd_diag<R>, dim3(nbig), dim3(kDiagThreads), lds, st,
-                               P->level_sn + n0, a, arena, dinv, y, n, nrhs, sb);
+                               P->level_sn + n0, a, arena, dinv, y, n, nrhs);
         launch_small_solve(num, a, P->level_sn + n0 + nbig, n1 - n0 - nbig, P->small_maxw[l],
                            P->small_maxm[l], y, cb, n, nrhs, true, st);
         const int64_t rb0 = P->rowblk_ptr[l], rb1 = P->rowblk_ptr[l + 1];
         if (rb1 > rb0)
             hipLaunchKernelGGL((k_fwd_gemv<R, NR>), dim3((unsigned)(rb1 - rb0)), dim3(256),
                                lds_rows, st, P->rowblk + rb0, a, arena, y, n, nrhs, sb);
+        const int64_t i0 = P->red_level_ptr[l], i1 = P->red_level_ptr[l + 1];
+        if (i1 > i0) {
+            const int64_t work_items = (i1 - i0) * nrhs;
+            hipLaunchKernelGGL(k_fwd_reduce<R>, dim3((unsigned)((work_items + 255) / 256)),
+                               dim3(256), 0, st, P->red_row + i0, P->red_ptr + i0,
+                               (const int32_t*)P->red_slot, i1 - i0, y, n, nrhs, sb);
+        }
     }
     for (int32_t l = nl - 1; l >= 0; --l) {
         const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1], nbig = P->level_nbig[l];
-        const int64_t rb0 = P->rowblk_ptr[l], rb1 = P->rowblk_ptr[l + 1];
-        if (rb1 > rb0)
-            hipLaunchKernelGGL((k_bwd_gemv<R, NR>), dim3((unsigned)(rb1 - rb0)), dim3(256),
-                               (size_t)P->level_maxw[l] * kPs * sizeof(R), st, P->rowblk + rb0, a,
-                               arena, (const R*)y, n, nrhs, sb);
+        const int64_t g0 = P->colblk_ptr[l], g1 = P->colblk_ptr[l + 1];
+        if (g1 > g0)
+            hipLaunchKernelGGL((k_bwd_cols<R, NR>), dim3((unsigned)(g1 - g0)), dim3(256), 0, st,
+                               P->colblk + g0, a, arena, (const R*)y, tacc, n, nrhs);
         if (nbig > 0)
             hipLaunchKernelGGL(k_bwd_diag<R>, dim3(nbig), dim3(kDiagThreads),
                                diag_lds(P->level_maxw[l], sizeof(R)), st, P->level_sn + n0, a,
-                               arena, dinv, y, n, nrhs, sb);
+                               arena, dinv, y, (const R*)tacc, n, nrhs);
         launch_small_solve(num, a, P->level_sn + n0 + nbig, n1 - n0 - nbig, P->small_maxw[l],
                            P->small_maxm[l], y, cb, n, nrhs, false, st);
     }
@@ -528,20 +565,15 @@ void drop_solve_graphs(spc_numeric* num) {
 }
 
 int64_t solve_work_elems(const spc_numeric* num, int32_t nrhs) {
-    const DevicePlan* P = num->plan;
-    return (num->sym->S.n + P->nslots + P->pb_total) * (int64_t)nrhs;
+    return solve_work_elems_per_rhs(num->sym->S) * (int64_t)nrhs;
 }
 
 int64_t solve_work_elems_per_rhs(const Symbolic& S) {
-    int64_t pb = 0;
-    for (int64_t s = 0; s < S.nsup; ++s)
-        if (!is_small(S, s)) pb += (int64_t)((S.nbelow(s) + kTile - 1) / kTile) * S.width(s);
-    return S.n + (int64_t)S.rows.size() + pb;
+    return 2 * S.n + (int64_t)S.rows.size();
 }
 
 // Solve work for nrhs right-hand sides (factor type): the vector y (n x nrhs),
-// the forward contribution slots (nslots x nrhs) and the backward partial
-// sums (pb_total x nrhs).
+// the forward contribution slots (nslots x nrhs) and t (n x nrhs).
 int32_t ensure_solve_work(spc_numeric* num, int32_t nrhs) {
     if (num->work_cols >= nrhs) return OK;
     if (num->work) {
