@@ -27,7 +27,7 @@ struct PlanOffsets {
     size_t sn_first, sn_w, sn_ld, sn_off, inv_off, rowptr, rows, rowpair, slot, perm, pair_tgt,
         pair_seg, pair_rel, pair_excl, rel, level_sn, rowblk, tiles, tasks, cnt0, rb_base;
     size_t pair_src, pair_end, scr_off, app_t, app_rb, app_p0, app_ent;
-    size_t slot_shared, red_row, red_ptr, red_slot, colblk;
+    size_t slot_shared, red_row, red_ptr, red_slot, colblk, pb_off;
     size_t total;
 };
 
@@ -240,6 +240,7 @@ PlanOffsets plan_layout(const Symbolic& S, const std::vector<int64_t>& rb_ptr,
     o.slot_shared = L.add<uint8_t>(S.rows.size());
     o.red_row = o.red_ptr = o.red_slot = 0;  // sized by solve_layout
     o.colblk = 0;
+    o.pb_off = L.add<int64_t>(ns);
     o.tasks = o.cnt0 = o.rb_base = 0;
     o.pair_src = o.pair_end = o.scr_off = o.app_t = o.app_rb = o.app_p0 = o.app_ent = 0;
     o.total = L.total;
@@ -257,8 +258,10 @@ struct SolveData {
     std::vector<int64_t> red_ptr;      // its slots red_slot[red_ptr[k] .. red_ptr[k + 1])
     std::vector<int32_t> red_slot;
     std::vector<int64_t> red_level_ptr;  // per level: its items
-    std::vector<RowBlock> colblk;      // (s, column group) of the large supernodes
+    std::vector<ColBlk> colblk;        // (s, column group, row chunk) of the large supernodes
     std::vector<int64_t> colblk_ptr;   // per level
+    std::vector<int64_t> pb_off;       // per supernode
+    int64_t pb_total = 0;
 };
 
 SolveData build_solve(const Symbolic& S) {
@@ -268,6 +271,7 @@ SolveData build_solve(const Symbolic& S) {
     d.red_level_ptr.assign((size_t)nl + 1, 0);
     d.colblk_ptr.assign((size_t)nl + 1, 0);
     d.red_ptr.push_back(0);
+    d.pb_off.assign((size_t)S.nsup, 0);
     std::vector<int32_t> cnt((size_t)S.n, 0), stamp((size_t)S.n, -1);
     std::vector<int32_t> rows_touched;
     for (int32_t l = 0; l < nl; ++l) {
@@ -310,7 +314,12 @@ SolveData build_solve(const Symbolic& S) {
             const int32_t s = S.level_sn[q];
             if (is_small(S, s) || S.nbelow(s) == 0) continue;
             const int32_t ng = (S.width(s) + kColGroup - 1) / kColGroup;
-            for (int32_t g = 0; g < ng; ++g) d.colblk.push_back(RowBlock{s, g});
+            const int32_t nh = (S.nbelow(s) + kRowChunk - 1) / kRowChunk;
+            for (int32_t h = 0; h < nh; ++h)
+                for (int32_t g = 0; g < ng; ++g)
+                    d.colblk.push_back(ColBlk{s, (int16_t)g, (int16_t)h});
+            d.pb_off[s] = d.pb_total;
+            d.pb_total += (int64_t)nh * S.width(s);
         }
         d.colblk_ptr[l + 1] = (int64_t)d.colblk.size();
     }
@@ -323,7 +332,7 @@ void solve_layout(PlanOffsets& o, const SolveData& d) {
     o.red_row = L.add<int32_t>(d.red_row.size());
     o.red_ptr = L.add<int64_t>(d.red_ptr.size());
     o.red_slot = L.add<int32_t>(d.red_slot.size());
-    o.colblk = L.add<RowBlock>(d.colblk.size());
+    o.colblk = L.add<ColBlk>(d.colblk.size());
     o.total = L.total;
 }
 
@@ -559,8 +568,10 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
         put(o.red_row, sd.red_row.data(), sd.red_row.size() * 4);
         put(o.red_ptr, sd.red_ptr.data(), sd.red_ptr.size() * 8);
         put(o.red_slot, sd.red_slot.data(), sd.red_slot.size() * 4);
-        put(o.colblk, sd.colblk.data(), sd.colblk.size() * sizeof(RowBlock));
+        put(o.colblk, sd.colblk.data(), sd.colblk.size() * sizeof(ColBlk));
+        put(o.pb_off, sd.pb_off.data(), sd.pb_off.size() * 8);
         P->nslots = (int64_t)S.rows.size();
+        P->pb_total = sd.pb_total;
         P->red_level_ptr = sd.red_level_ptr;
         P->colblk_ptr = sd.colblk_ptr;
     }
@@ -600,7 +611,8 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
     P->red_row = (int32_t*)(base + o.red_row);
     P->red_ptr = (int64_t*)(base + o.red_ptr);
     P->red_slot = (int32_t*)(base + o.red_slot);
-    P->colblk = (RowBlock*)(base + o.colblk);
+    P->colblk = (ColBlk*)(base + o.colblk);
+    P->pb_off = (int64_t*)(base + o.pb_off);
     if (S.opt.deterministic) {
         P->pair_src = (int32_t*)(base + o.pair_src);
         P->pair_end = (int32_t*)(base + o.pair_end);

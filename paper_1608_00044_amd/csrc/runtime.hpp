@@ -79,6 +79,11 @@ struct Task { int32_t s; int16_t a, b; int32_t kind; };
 struct UpdTile { int32_t s; int16_t bi, bj; };
 // One panel row block of source supernode s.
 struct RowBlock { int32_t s; int32_t rb; };
+// Backward solve: a workgroup takes kColGroup columns of one chunk of
+// kRowChunk rows below the diagonal block.
+constexpr int kColGroup = 8;
+constexpr int kRowChunk = 512;
+struct ColBlk { int32_t s; int16_t g, h; };  // column group g, row chunk h of supernode s
 // Deterministic order, apply pass: rows [ilo, ihi) of pair p's source that
 // land in one 64-row block of the target.
 struct AppEnt { int32_t p, ilo, ihi, pad; };
@@ -131,8 +136,11 @@ struct DevicePlan {
     int32_t* red_row = nullptr;      // reduce items: row
     int64_t* red_ptr = nullptr;      // slots of item k: red_slot[red_ptr[k] .. red_ptr[k + 1])
     int32_t* red_slot = nullptr;
-    RowBlock* colblk = nullptr;      // backward column groups (s, g) of the large supernodes
+    ColBlk* colblk = nullptr;        // backward (column group, row chunk) blocks
+    int64_t* pb_off = nullptr;       // per supernode: its partial sums (chunk h, column k at
+                                     // pb_off + h w + k) in the backward work
     int64_t nslots = 0;              // entries of rows
+    int64_t pb_total = 0;
     std::vector<int64_t> red_level_ptr, colblk_ptr;  // per level
     std::vector<std::vector<int64_t>> round_ptr;  // per level: tile ranges of its rounds
     std::vector<uint8_t> level_apply;    // per level: large sources in the apply form
@@ -148,8 +156,6 @@ struct DevicePlan {
                                                               // supernode of the level
 };
 
-// Columns of the backward solve's column groups.
-constexpr int kColGroup = 8;
 
 // Forward contribution slots: (L21 y_s)[i] of a row that several sources of
 // the level share goes to cb (nslots x nrhs) at the row's slot; the others

@@ -12,10 +12,11 @@
 //                             contribution slot instead,
 //             k_fwd_reduce -- which one thread per such row subtracts, sources
 //                             in increasing order;
-//   backward: k_bwd_cols   -- t_s = L21^T y[rows below], one workgroup per group
-//                             of kColGroup columns over every row, summed in a
-//                             fixed tree;
-//             k_bwd_diag   -- y_s = L11^{-T} (y_s - t_s), panels in reverse.
+//   backward: k_bwd_cols   -- partial sums of L21^T y[rows below], one
+//                             workgroup per group of kColGroup columns and
+//                             chunk of kRowChunk rows, summed in a fixed tree;
+//             k_bwd_diag   -- y_s = L11^{-T} (y_s - t_s), t_s the chunks'
+//                             partial sums in chunk order, panels in reverse.
 // No update is an atomic add: every sum has one fixed order, so a solve has
 // the same bits on every run.  Several right-hand sides go through every
 // kernel in groups of eight, so the factor is read once per group.
@@ -248,9 +249,18 @@ __global__ __launch_bounds__(256) void k_fwd_gemv(const RowBlock* __restrict__ w
     const int32_t* __restrict__ below = a.rows + rp + w;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int i0 = wb.rb * kTile, m = min(kTile, r - i0);
+    // the output row, its form and (in place) its current values are loaded
+    // early so that their latency hides under the staging and the products
+    const int64_t slot = rp + w + i0 + tid;
+    const int32_t row = tid < m ? below[i0 + tid] : 0;
+    const bool sh = tid < m && sb.shared[slot];
     stage_rows<R>(Pl, P, ld, i0, m, w, tid);
     for (int c0 = 0; c0 < nrhs; c0 += NR) {
         const int nc = min(NR, nrhs - c0);
+        R yold[NR];
+#pragma unroll
+        for (int c = 0; c < NR; ++c)
+            yold[c] = (tid < m && !sh && c < nc) ? y[(int64_t)(c0 + c) * n + row] : R(0);
         {
             constexpr int kPer = (NR * kMaxWidth + 255) / 256;
             const float invw = 1.0f / (float)w;
@@ -291,13 +301,12 @@ __global__ __launch_bounds__(256) void k_fwd_gemv(const RowBlock* __restrict__ w
         for (int c = 0; c < NR; ++c) red[wave][c][lane] = acc[c];
         __syncthreads();
         if (tid < m) {
-            const int64_t slot = rp + w + i0 + tid;
-            const int32_t row = below[i0 + tid];
-            const bool sh = sb.shared[slot];
-            for (int c = 0; c < nc; ++c) {
+#pragma unroll
+            for (int c = 0; c < NR; ++c) {
+                if (c >= nc) break;
                 const R v = (red[0][c][tid] + red[1][c][tid]) + (red[2][c][tid] + red[3][c][tid]);
                 if (sh) sb.cb[(int64_t)(c0 + c) * sb.nslots + slot] = v;
-                else y[(int64_t)(c0 + c) * n + row] -= v;
+                else y[(int64_t)(c0 + c) * n + row] = yold[c] - v;
             }
         }
         __syncthreads();
@@ -331,28 +340,31 @@ __global__ __launch_bounds__(256) void k_fwd_reduce(const int32_t* __restrict__ 
     yc[red_row[k]] = v;
 }
 
-// Below the diagonal block, backward: t_s[k] = sum_i L21[i][k] y[rows(i)] for
-// the kColGroup columns k of group g of supernode s, over every row i below
-// the diagonal block: thread tid takes rows tid, tid + 256, ... (coalesced down
-// each column of the column-major panel), then the 256 partial sums of every
+// Below the diagonal block, backward: sum_i L21[i][k] y[rows(i)] for the
+// kColGroup columns k of group g of supernode s, over the rows i of chunk h:
+// thread tid takes rows tid, tid + 256, ... of the chunk (coalesced down each
+// column of the column-major panel), then the 256 partial sums of every
 // (column, right-hand side) meet in a fixed tree: across each wave by
-// butterfly shuffles, then the four waves in order.  One workgroup writes
-// each t_s[k] (no atomics).  NR right-hand sides at a time.
+// butterfly shuffles, then the four waves in order, into the chunk's partial
+// sum (pb, one writer per entry, no atomics).  NR right-hand sides at a time.
 template <class R, int NR>
-__global__ __launch_bounds__(256) void k_bwd_cols(const RowBlock* __restrict__ work, KArgs a,
+__global__ __launch_bounds__(256) void k_bwd_cols(const ColBlk* __restrict__ work, KArgs a,
                                                   const R* __restrict__ arena,
-                                                  const R* __restrict__ y, R* __restrict__ tacc,
-                                                  int64_t n, int nrhs) {
+                                                  const R* __restrict__ y, R* __restrict__ pb,
+                                                  const int64_t* __restrict__ pb_off,
+                                                  int64_t pb_total, int64_t n, int nrhs) {
     constexpr int G = kColGroup;
     __shared__ R part[4][G * NR];
-    const RowBlock wb = work[blockIdx.x];
-    const int s = wb.s, g = wb.rb;
-    const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
+    const ColBlk wb = work[blockIdx.x];
+    const int s = wb.s, g = wb.g, h = wb.h;
+    const int w = a.sn_w[s], ld = a.sn_ld[s];
     const int64_t rp = a.rowptr[s];
-    const int r = (int)(a.rowptr[s + 1] - rp) - w;
     const int k0 = g * G, kc = min(G, w - k0);
-    const R* __restrict__ P = arena + a.sn_off[s] + w + (int64_t)k0 * ld;
-    const int32_t* __restrict__ below = a.rows + rp + w;
+    const int rb0 = h * kRowChunk;
+    const int r = min((int)(a.rowptr[s + 1] - rp) - w - rb0, kRowChunk);  // rows of the chunk
+    const R* __restrict__ P = arena + a.sn_off[s] + w + rb0 + (int64_t)k0 * ld;
+    const int32_t* __restrict__ below = a.rows + rp + w + rb0;
+    R* __restrict__ out = pb + pb_off[s] + (int64_t)h * w + k0;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     for (int c0 = 0; c0 < nrhs; c0 += NR) {
         const int nc = min(NR, nrhs - c0);
@@ -361,18 +373,27 @@ __global__ __launch_bounds__(256) void k_bwd_cols(const RowBlock* __restrict__ w
         for (int k = 0; k < G; ++k)
 #pragma unroll
             for (int c = 0; c < NR; ++c) acc[k][c] = R(0);
-        for (int i = tid; i < r; i += 256) {
-            const int32_t row = below[i];
-            R yv[NR], pv[G];
+        // kU rows per step with every load of the step issued first
+        constexpr int kU = NR == 1 ? 4 : 1;
+        for (int i0 = tid; i0 < r; i0 += 256 * kU) {
+            R yv[kU][NR], pv[kU][G];
 #pragma unroll
-            for (int c = 0; c < NR; ++c)
-                yv[c] = c < nc ? y[(int64_t)(c0 + c) * n + row] : R(0);
+            for (int u = 0; u < kU; ++u) {
+                const int i = i0 + 256 * u;
+                const int32_t row = i < r ? below[i] : 0;
 #pragma unroll
-            for (int k = 0; k < G; ++k) pv[k] = k < kc ? P[i + (int64_t)k * ld] : R(0);
+                for (int c = 0; c < NR; ++c)
+                    yv[u][c] = (i < r && c < nc) ? y[(int64_t)(c0 + c) * n + row] : R(0);
 #pragma unroll
-            for (int k = 0; k < G; ++k)
+                for (int k = 0; k < G; ++k)
+                    pv[u][k] = (i < r && k < kc) ? P[i + (int64_t)k * ld] : R(0);
+            }
 #pragma unroll
-                for (int c = 0; c < NR; ++c) acc[k][c] += pv[k] * yv[c];
+            for (int u = 0; u < kU; ++u)
+#pragma unroll
+                for (int k = 0; k < G; ++k)
+#pragma unroll
+                    for (int c = 0; c < NR; ++c) acc[k][c] += pv[u][k] * yv[u][c];
         }
 #pragma unroll
         for (int k = 0; k < G; ++k)
@@ -387,7 +408,7 @@ __global__ __launch_bounds__(256) void k_bwd_cols(const RowBlock* __restrict__ w
         if (tid < G * NR) {
             const int k = tid / NR, c = tid % NR;
             if (k < kc && c < nc)
-                tacc[(int64_t)(c0 + c) * n + first + k0 + k] =
+                out[(int64_t)(c0 + c) * pb_total + k] =
                     (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
         }
         __syncthreads();
@@ -403,8 +424,9 @@ __global__ __launch_bounds__(kDiagThreads) void k_bwd_diag(const int32_t* __rest
                                                            KArgs a,
                                                   const R* __restrict__ arena,
                                                   const R* __restrict__ dinv, R* __restrict__ y,
-                                                  const R* __restrict__ tacc, int64_t n,
-                                                  int nrhs) {
+                                                  const R* __restrict__ pb,
+                                                  const int64_t* __restrict__ pb_off,
+                                                  int64_t pb_total, int64_t n, int nrhs) {
     extern __shared__ double sm_raw[];
     R* sm = (R*)sm_raw;
     __shared__ R ys[kDiagThreads / 64][kMaxWidth + kPanel];
@@ -420,17 +442,28 @@ __global__ __launch_bounds__(kDiagThreads) void k_bwd_diag(const int32_t* __rest
     stage_block<R>(T, I, inv, w, tid);
     __syncthreads();
     R* yw = ys[wave];
-    const bool below = a.rowptr[s + 1] - a.rowptr[s] > w;  // t_s exists (rows below)
+    const int r = (int)(a.rowptr[s + 1] - a.rowptr[s]) - w;
+    const int nh = (r + kRowChunk - 1) / kRowChunk;  // row chunks with partial sums
     for (int c = wave; c < nrhs; c += kDiagThreads / 64) {
         R* __restrict__ yc = y + (int64_t)c * n;
-        const R* __restrict__ tc = tacc + (int64_t)c * n;
+        const R* __restrict__ pc = pb + (int64_t)c * pb_total + pb_off[s];
         {
             R v[(kMaxWidth + 63) / 64], t[(kMaxWidth + 63) / 64];
 #pragma unroll
             for (int u = 0; u < (kMaxWidth + 63) / 64; ++u) {
                 const int k = lane + 64 * u;
                 v[u] = k < w ? yc[first + k] : R(0);
-                t[u] = (k < w && below) ? tc[first + k] : R(0);
+                R acc = R(0);  // the chunks' partial sums in chunk order, 4 loads at a time
+                for (int h0 = 0; h0 < nh; h0 += 4) {
+                    R pv[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        pv[q] = (k < w && h0 + q < nh) ? pc[(int64_t)(h0 + q) * w + k] : R(0);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (h0 + q < nh) acc += pv[q];
+                }
+                t[u] = acc;
             }
 #pragma unroll
             for (int u = 0; u < (kMaxWidth + 63) / 64; ++u)
@@ -513,7 +546,7 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* work, hipStream_t st) {
     const R* dinv = (const R*)num->dinv;
     R* y = work;
     R* cb = y + n * nrhs;
-    R* tacc = cb + P->nslots * nrhs;
+    R* pb = cb + P->nslots * nrhs;
     const SolveBufs<R> sb{cb, P->nslots, P->slot_shared};
     const int32_t nl = (int32_t)S.level_ptr.size() - 1;
     for (int32_t l = 0; l < nl; ++l) {
@@ -542,11 +575,13 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* work, hipStream_t st) {
         const int64_t g0 = P->colblk_ptr[l], g1 = P->colblk_ptr[l + 1];
         if (g1 > g0)
             hipLaunchKernelGGL((k_bwd_cols<R, NR>), dim3((unsigned)(g1 - g0)), dim3(256), 0, st,
-                               P->colblk + g0, a, arena, (const R*)y, tacc, n, nrhs);
+                               P->colblk + g0, a, arena, (const R*)y, pb,
+                               (const int64_t*)P->pb_off, P->pb_total, n, nrhs);
         if (nbig > 0)
             hipLaunchKernelGGL(k_bwd_diag<R>, dim3(nbig), dim3(kDiagThreads),
                                diag_lds(P->level_maxw[l], sizeof(R)), st, P->level_sn + n0, a,
-                               arena, dinv, y, (const R*)tacc, n, nrhs);
+                               arena, dinv, y, (const R*)pb, (const int64_t*)P->pb_off,
+                               P->pb_total, n, nrhs);
         launch_small_solve(num, a, P->level_sn + n0 + nbig, n1 - n0 - nbig, P->small_maxw[l],
                            P->small_maxm[l], y, cb, n, nrhs, false, st);
     }
@@ -569,11 +604,16 @@ int64_t solve_work_elems(const spc_numeric* num, int32_t nrhs) {
 }
 
 int64_t solve_work_elems_per_rhs(const Symbolic& S) {
-    return 2 * S.n + (int64_t)S.rows.size();
+    int64_t pb = 0;
+    for (int64_t s = 0; s < S.nsup; ++s)
+        if (!is_small(S, s) && S.nbelow(s) > 0)
+            pb += (int64_t)((S.nbelow(s) + kRowChunk - 1) / kRowChunk) * S.width(s);
+    return S.n + (int64_t)S.rows.size() + pb;
 }
 
 // Solve work for nrhs right-hand sides (factor type): the vector y (n x nrhs),
-// the forward contribution slots (nslots x nrhs) and t (n x nrhs).
+// the forward contribution slots (nslots x nrhs) and the backward partial
+// sums (pb_total x nrhs).
 int32_t ensure_solve_work(spc_numeric* num, int32_t nrhs) {
     if (num->work_cols >= nrhs) return OK;
     if (num->work) {
