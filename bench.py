@@ -85,37 +85,239 @@ def backward_error(p, x, b):
     return float(np.abs(r).max() / (anorm * np.abs(x).max() + np.abs(b).max()))
 
 
-def cpu_baseline(name, sample_dims, repeat=0):
-    """The oracle (plain left-looking column Cholesky, one core) timed on a
-    bounded sample: the same workload recipe on a smaller grid."""
-    saved = os.sched_getaffinity(0) if hasattr(os, "sched_getaffinity") else None
-    try:
-        os.sched_setaffinity(0, {sorted(saved)[0]})
-    except (AttributeError, OSError, TypeError):
-        pass
-    try:
-        return _cpu_baseline_pinned(name, sample_dims, repeat)
-    finally:
-        if saved is not None:
-            os.sched_setaffinity(0, saved)
+class OracleLeg:
+    """The CPU baseline: the oracle (plain left-looking column Cholesky, one
+    core) on the whole workload, in a thread pinned to one host core while the
+    GPU legs run (the oracle's C code releases the interpreter lock).  It
+    factors (timed), then solves the workload's right-hand side; the small 2D
+    workload (64 x 64) follows for its own parity check.  Nothing else of the
+    benchmark calls the oracle: the parity of the GPU factor and solution is
+    computed from this leg's results."""
+
+    def __init__(self, name, small_name="lap2d_5pt_64"):
+        import threading
+
+        self.name, self.small_name = name, small_name
+        self.result, self.error = None, None
+        cores = sorted(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else [0]
+        self.core = cores[-1]
+        self.thread = threading.Thread(target=self._run, daemon=True)
+        self.thread.start()
+
+    def _run(self):
+        try:
+            try:
+                os.sched_setaffinity(0, {self.core})  # this thread only
+            except (AttributeError, OSError):
+                pass
+            import oracle
+            from paper_1608_00044_amd import inputs
+
+            out = {}
+            for key, nm in (("main", self.name), ("small", self.small_name)):
+                p = inputs.make_workload(nm)
+                t0 = time.perf_counter()
+                Cp, Ci, Cx, _ = oracle.permute(p.n, p.colptr, p.rowind, p.values, p.perm)
+                sym = oracle.symbolic(p.n, Cp, Ci)
+                t1 = time.perf_counter()
+                st, Lx = oracle.factor(p.n, Cp, Ci, Cx, sym)
+                t2 = time.perf_counter()
+                if st != 0:
+                    raise RuntimeError("oracle status %d on %s" % (st, nm))
+                x = oracle.solve(p.n, sym, Lx, p.perm, p.rhs)
+                t3 = time.perf_counter()
+                out[key] = dict(n=p.n, C=(Cp, Ci, Cx), Lp=sym.Lp, Li=sym.Li, Lx=Lx, x=x,
+                                flops=float(sym.flops), symbolic_s=t1 - t0, factor_s=t2 - t1,
+                                solve_s=t3 - t2)
+                log("oracle %s: symbolic %.1f s, factor %.1f s, solve %.1f s" %
+                    (nm, t1 - t0, t2 - t1, t3 - t2))
+            self.result = out
+        except Exception as e:  # reported by join()
+            self.error = e
+
+    def join(self):
+        self.thread.join()
+        if self.error is not None:
+            raise self.error
+        return self.result
 
 
-def _cpu_baseline_pinned(name, sample_dims, repeat):
-    import oracle
-    from paper_1608_00044_amd import inputs
+def factor_parity(n, Cp, Ci, Cx, Lp, Li, Lx, Sp, Si, Sx):
+    """Element-by-element comparison of a GPU factor (stored structure
+    Sp, Si, Sx) with the oracle's (exact structure Lp, Li, Lx): the worst
+    |dL_ij| / (1e-10 |L_ij| + 1e-13 sqrt(c_ii c_jj) / L_jj) (c = the diagonal
+    of P A P^T), the largest relative difference, and whether every stored
+    entry outside the exact structure is an explicit zero."""
+    ks = np.repeat(np.arange(n, dtype=np.int64), np.diff(Sp)) * n + Si
+    ko = np.repeat(np.arange(n, dtype=np.int64), np.diff(Lp)) * n + Li
+    pos = np.searchsorted(ks, ko)
+    if not ((pos < ks.size).all() and np.array_equal(ks[pos], ko)):
+        return {"entries": int(Lx.size), "structure_contained": False}
+    del ko
+    extra = np.ones(ks.size, dtype=bool)
+    extra[pos] = False
+    del ks
+    got = Sx[pos]
+    diag = np.zeros(n)
+    nz = Cp[1:] > Cp[:-1]
+    idx, js = Cp[:-1][nz], np.arange(n)[nz]
+    isd = Ci[idx] == js
+    diag[js[isd]] = Cx[idx[isd]]
+    cols = np.repeat(np.arange(n), np.diff(Lp))
+    ljj = Lx[Lp[:-1]][cols]
+    tol = 1e-10 * np.abs(Lx) + 1e-13 * np.sqrt(np.abs(diag[Li] * diag[cols])) / np.abs(ljj)
+    err = np.abs(got - Lx)
+    return {"entries": int(Lx.size), "structure_contained": True,
+            "explicit_zeros_ok": bool((Sx[extra] == 0.0).all()),
+            "worst_over_tolerance": float((err / tol).max()),
+            "max_rel_diff": float((err / np.maximum(np.abs(Lx), 1e-300)).max()),
+            "bar": "|dL_ij| <= 1e-10 |L_ij| + 1e-13 sqrt(c_ii c_jj) / L_jj for every entry"}
 
-    p = inputs.make_workload(name, repeat=repeat, nrhs=0, dims=sample_dims)
-    Cp, Ci, Cx, _ = oracle.permute(p.n, p.colptr, p.rowind, p.values, p.perm)
-    sym = oracle.symbolic(p.n, Cp, Ci)
-    t0 = time.perf_counter()
-    st, _ = oracle.factor(p.n, Cp, Ci, Cx, sym)
-    dt = time.perf_counter() - t0
-    if st != 0:
-        raise RuntimeError("oracle failed on the sample")
-    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else 1
-    return {"value": sym.flops / dt / 1e9, "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
-            "sample": "same recipe on a %s grid (n=%d, F=%.3e), numeric factorization only, "
-                      "%.1f s" % ("x".join(map(str, sample_dims)), p.n, sym.flops, dt)}
+
+def probe_residual(p, Sp, Si, Sx, probes=8, seed=7):
+    """rho ~ ||(L L^T - P A P^T) Z||_F / ||P A P^T Z||_F over `probes` N(0,1)
+    columns (an unbiased estimate of ||L L^T - P A P^T||_F / ||P A P^T||_F up to
+    the probes' spread), from a factor on the host (scipy; no oracle)."""
+    import scipy.sparse as sp
+
+    A = sp.csc_matrix((p.values, p.rowind, p.colptr), shape=(p.n, p.n))
+    A = (A + sp.tril(A, -1).T).tocsr()
+    perm = p.perm if p.perm is not None else np.arange(p.n)
+    C = A[perm][:, perm]
+    L = sp.csc_matrix((Sx, Si, Sp), shape=(p.n, p.n))
+    Z = np.random.default_rng(seed).standard_normal((p.n, probes))
+    CZ = C @ Z
+    R = L @ (L.T @ Z) - CZ
+    return float(np.linalg.norm(R) / np.linalg.norm(CZ))
+
+
+def exact_residual(p, Sp, Si, Sx):
+    """||L L^T - P A P^T||_F / ||A||_F exactly (scipy sparse products)."""
+    import scipy.sparse as sp
+
+    A = sp.csc_matrix((p.values, p.rowind, p.colptr), shape=(p.n, p.n))
+    A = (A + sp.tril(A, -1).T).tocsr()
+    perm = p.perm if p.perm is not None else np.arange(p.n)
+    C = A[perm][:, perm]
+    L = sp.csc_matrix((Sx, Si, Sp), shape=(p.n, p.n))
+    D = (L @ L.T - C).tocoo()
+    return float(np.sqrt((D.data ** 2).sum()) / sp.linalg.norm(A))
+
+
+def stored_oracle_solution(name):
+    """The FP64 oracle's solution of `name` stored under tests/golden/ by
+    tests/golden/make_oracle_solution.py (read here with numpy only), or None
+    when absent or written by other sources of the oracle or the inputs."""
+    import hashlib
+
+    path = os.path.join(ROOT, "tests", "golden", "oracle_x_%s.npz" % name)
+    if not os.path.exists(path):
+        return None
+    want = {}
+    for key, rel in (("oracle_sha", "oracle/oracle.c"),
+                     ("inputs_sha", "paper_1608_00044_amd/inputs.py")):
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            want[key] = hashlib.sha256(f.read()).hexdigest()
+    with np.load(path, allow_pickle=False) as z:
+        if any(str(z[k]) != v for k, v in want.items()) or str(z["workload"]) != name:
+            return None
+        return np.array(z["x"]), np.array(z["eta"])
+
+
+def other_order(p, amalg, F, deterministic, steps, primary_ms):
+    """The workload factored in the other contribution order (deterministic
+    or atomic), timed the same way; its cost against the headline order."""
+    import torch
+
+    from paper_1608_00044_amd import spchol
+
+    sym = spchol.analyze(p.n, p.colptr, p.rowind, p.perm, sn_cap=150, amalg_ratio=amalg,
+                         deterministic=deterministic)
+    vals = torch.from_numpy(p.values).to("cuda:0")
+    b = torch.from_numpy(np.ascontiguousarray(p.rhs[:, 0])).to("cuda:0")
+    num = spchol.factor(sym, vals)
+    if num.status() != 0:
+        raise RuntimeError("factor status %d" % num.status())
+    x = num.solve(b)
+    stream = torch.cuda.current_stream()
+    f_ms, s_ms = [], []
+    for k in range(steps + 1):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        num.refactor(vals)
+        e1.record(stream)
+        num.solve(b, x=x)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        if k:
+            f_ms.append(e0.elapsed_time(e1))
+            s_ms.append(e1.elapsed_time(e2))
+    fm = float(np.mean(f_ms))
+    out = {"deterministic": deterministic,
+           "order": "fixed (bitwise reproducible)" if deterministic else "atomic",
+           "factor_ms": fm, "factor_gflops": F / (fm * 1e-3) / 1e9,
+           "solve_ms": float(np.mean(s_ms)),
+           "factor_time_ratio_to_headline": fm / primary_ms}
+    log("other order (deterministic=%d): factor %.3f ms (%.3fx)" % (deterministic, fm,
+                                                                     fm / primary_ms))
+    num.free()
+    sym.free()
+    return out
+
+
+def small_workload(name, solves):
+    """The latency-bound 2D workload (64 x 64 grid): factor time (HIP events),
+    solve p50/p99 over `solves` fresh right-hand sides, backward error, the
+    exact residual; returns (report, the factor's export for oracle parity)."""
+    import torch
+
+    from paper_1608_00044_amd import inputs, spchol
+
+    p = inputs.make_workload(name)
+    sym = spchol.analyze(p.n, p.colptr, p.rowind, p.perm, sn_cap=150, amalg_ratio=p.meta["amalg"])
+    inf = sym.info()
+    vals = torch.from_numpy(p.values).to("cuda:0")
+    b = torch.from_numpy(np.ascontiguousarray(p.rhs[:, 0])).to("cuda:0")
+    num = spchol.factor(sym, vals)
+    if num.status() != 0:
+        raise RuntimeError("factor status %d" % num.status())
+    x = num.solve(b)
+    stream = torch.cuda.current_stream()
+    f_us = []
+    for k in range(21):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        num.refactor(vals)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if k:
+            f_us.append(e0.elapsed_time(e1) * 1e3)
+    rng = np.random.Generator(np.random.PCG64(4243))
+    Bm = torch.from_numpy(rng.standard_normal((solves, p.n))).to("cuda:0")
+    lat = []
+    for i in range(solves):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        num.solve(Bm[i], x=x)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t1) * 1e6)
+    x = num.solve(b).cpu().numpy()
+    eta = backward_error(p, x, p.rhs[:, 0])
+    Sp, Si, Sx = num.export()
+    rho = exact_residual(p, Sp, Si, Sx)
+    out = {"workload": name, "description": WORKLOAD_TEXT.get(name, name), "n": p.n,
+           "nnz_L": inf["nnz_l"], "flops_F": inf["flops"], "nsup": inf["nsup"],
+           "levels": inf["nlevels"], "factor_us": float(np.mean(f_us)),
+           "factor_gflops": inf["flops"] / (np.mean(f_us) * 1e-6) / 1e9,
+           "solve_p50_us": float(np.percentile(lat, 50)),
+           "solve_p99_us": float(np.percentile(lat, 99)),
+           "backward_error": eta, "residual_exact": rho,
+           "bound": "latency (launches per level); roofline fractions near zero"}
+    log("small 2D: factor %.1f us, solve p50 %.1f us p99 %.1f us, eta %.1e, rho %.1e" %
+        (out["factor_us"], out["solve_p50_us"], out["solve_p99_us"], eta, rho))
+    num.free()
+    sym.free()
+    return out, (Sp, Si, Sx)
 
 
 def _oracle_batch_share(job):
@@ -140,8 +342,8 @@ def _oracle_batch_share(job):
 def cpu_batch_baseline(count, sample, max_workers=16):
     """The oracle on the first `sample` matrices of the batched workload,
     spread over the host's cores by a process pool (members dealt round
-    robin): the one-core sum and the pool's makespan (the slowest worker's
-    summed compute time), scaled to matrices/s."""
+    robin): matrices/s over the pool's wall time (spawn included), beside the
+    one-core sum and the makespan (the slowest worker's summed compute time)."""
     import multiprocessing
 
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else 1
@@ -157,12 +359,13 @@ def cpu_batch_baseline(count, sample, max_workers=16):
     one_core = sum(per_worker)
     makespan = max(per_worker)
     flops = sum(f for r in res for _, f, _ in r)
-    return {"value": sample / makespan, "unit": "matrices/s", "cores": workers, "kind": "oracle",
+    return {"value": sample / wall, "unit": "matrices/s", "cores": workers, "kind": "oracle",
             "sample": "first %d of the %d matrices: permute + symbolic + factor + one-RHS "
                       "solve each; %d worker processes, members dealt round robin"
                       % (sample, count, workers),
             "one_core_sum_s": one_core, "makespan_s": makespan, "pool_wall_s": wall,
             "one_core_matrices_per_s": sample / one_core,
+            "makespan_matrices_per_s": sample / makespan,
             "factor_flops_F": flops}
 
 
@@ -188,7 +391,7 @@ def measured_traffic(kernel, workload):
     return float(kv["traffic_bytes_per_launch"])
 
 
-def mixed_precision(name, steps, warmup, tol=1e-10):
+def mixed_precision(name, steps, warmup, tol=1e-10, deterministic=0):
     """FP64 factor + solve against FP32 factor + FP64 refinement to a normwise
     backward error <= tol, on the same resident workload and right-hand sides."""
     import torch
@@ -203,9 +406,25 @@ def mixed_precision(name, steps, warmup, tol=1e-10):
     stream = torch.cuda.current_stream()
     out = {"workload": name, "description": WORKLOAD_TEXT.get(name, name), "n": p.n,
            "nrhs": k, "tol": tol}
+    ref = stored_oracle_solution(name)
+    if ref is not None:
+        import scipy.sparse as sp
+
+        A = sp.csc_matrix((p.values, p.rowind, p.colptr), shape=(p.n, p.n))
+        A = A + sp.tril(A, -1).T
+        # lambda_min >= the diagonal shift (the edge blocks form a positive
+        # semidefinite operator), so cond(A) <= ||A||_inf / shift
+        kappa = float(abs(A).sum(axis=1).max()) / p.meta["shift"]
+        out["fp64_oracle_solution"] = {
+            "source": "tests/golden/oracle_x_%s.npz: the FP64 oracle's solution of all %d "
+                      "right-hand sides, written once by tests/golden/make_oracle_solution.py "
+                      "(keyed by the SHA-256 of oracle/oracle.c and the input generator)"
+                      % (name, k),
+            "oracle_backward_error": float(np.max(ref[1])), "cond_bound": kappa}
     for prec in (0, 1):
         sym = spchol.analyze(p.n, p.colptr, p.rowind, p.perm, sn_cap=150,
-                             amalg_ratio=p.meta["amalg"], precision=prec)
+                             amalg_ratio=p.meta["amalg"], precision=prec,
+                             deterministic=deterministic)
         F = sym.info()["flops"]
         num = spchol.factor(sym, vals)
         if num.status() != 0:
@@ -240,6 +459,16 @@ def mixed_precision(name, steps, warmup, tol=1e-10):
         key = "fp64" if prec == 0 else "fp32_ir"
         out[key] = {"factor_ms": fm, "factor_gflops": F / (fm * 1e-3) / 1e9,
                     "solve_ms": sm, "total_ms": fm + sm, "backward_error": eta}
+        if ref is not None:
+            xo, eta_o = ref
+            xo = xo.reshape(p.n, -1)
+            err = max(float(np.abs(xs[:, c] - xo[:, c]).max() / np.abs(xo[:, c]).max())
+                      for c in range(k))
+            out[key]["error_vs_fp64_oracle"] = err
+            out[key]["error_bound"] = 4.0 * out["fp64_oracle_solution"]["cond_bound"] * (
+                eta + float(np.max(eta_o)))
+            log("  %s error vs the FP64 oracle's solution %.2e (bound %.2e)" %
+                (key, err, out[key]["error_bound"]))
         if prec == 1:
             out[key]["refine_iters"] = float(np.mean(iters))
             out[key]["fp64_blocks"] = num.info()["fp64_blocks"]
@@ -253,7 +482,8 @@ def mixed_precision(name, steps, warmup, tol=1e-10):
     return out
 
 
-def batched(count, steps, precision, tol=1e-10, tune_options=True, options=None):
+def batched(count, steps, precision, tol=1e-10, tune_options=True, options=None,
+            deterministic=0):
     """Batch of independent 2D Laplacians (BATCH_RECIPE): the analysis options
     tuned on this batch (amalgamation ratio, cap), one batched analysis, then
     timed steps of factorization + one-RHS solve (FP64) or factorization +
@@ -269,10 +499,11 @@ def batched(count, steps, precision, tol=1e-10, tune_options=True, options=None)
     mats = [(p.n, p.colptr, p.rowind, p.perm) for p in probs]
     vals = torch.from_numpy(vals_h).to("cuda:0")
     b = torch.from_numpy(np.ascontiguousarray(rhs_h)).to("cuda:0")
-    opts, table = dict(tune.BASE, **(options or {})), None
+    base = dict(tune.BASE, deterministic=deterministic)
+    opts, table = dict(base, **(options or {})), None
     if tune_options:
         t0 = time.perf_counter()
-        opts, table = tune.tune_batch(mats, vals, b, precision)
+        opts, table = tune.tune_batch(mats, vals, b, precision, base=base)
         log("batch tuning (%.1f s): %s" % (time.perf_counter() - t0, opts))
     t0 = time.perf_counter()
     sym = spchol.analyze_batch(mats, precision=precision, **opts)
@@ -388,11 +619,20 @@ def serving(requests, seed=5000):
     st = srv.stats()
     srv.destroy()
     lat = np.array([q["latency_ms"] for q in res])
+    que = np.array([q["queue_ms"] for q in res])
+    run = lat - que  # admission to completion of the request's device work
     ok = sum(1 for q in res if q["status"] == 0)
     cols = int(sum(int(nrhs[i]) for i in range(requests) if res[i]["status"] == 0))
     out = {"requests": requests, "rate_per_s": r["rate"], "patterns": len(probs),
            "ok": ok, "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
            "mean_ms": float(lat.mean()), "requests_per_s": requests / wall,
+           "queue_p50_ms": float(np.percentile(que, 50)),
+           "queue_p99_ms": float(np.percentile(que, 99)),
+           "admitted_p50_ms": float(np.percentile(run, 50)),
+           "admitted_p99_ms": float(np.percentile(run, 99)),
+           "latency_split": "latency = queue (submission to admission: waiting for a slot, "
+                            "memory or a factor) + admitted (admission to the end of the "
+                            "request's device work, overlapping other requests)",
            "solves_per_s": cols / wall, "peak_inflight": st["peak_inflight"],
            "peak_bytes": st["peak_bytes"], "evictions": st["evictions"],
            "recipe": "Poisson arrivals at %g/s over %d 2D (side %d..%d) and %d 3D 7-point "
@@ -416,8 +656,14 @@ def main():
     ap.add_argument("--solves", type=int, default=200)
     ap.add_argument("--sched", type=int, default=0, choices=(0, 1, 2),
                     help="0 level sets, 1 with lookahead, 2 device task queue")
-    ap.add_argument("--deterministic", type=int, default=1, choices=(0, 1),
-                    help="1: fixed contribution order (the library default); 0: atomic order")
+    ap.add_argument("--deterministic", type=int, default=0, choices=(0, 1),
+                    help="contribution order of the timed factorization: 0 atomic (default "
+                         "here), 1 fixed (bitwise reproducible; the library default); the "
+                         "other order is timed beside it")
+    ap.add_argument("--other-order-steps", type=int, default=5,
+                    help="timed factorizations in the other contribution order (0 to skip)")
+    ap.add_argument("--small-workload", default="lap2d_5pt_64",
+                    help="the latency-bound 2D workload reported beside ('' to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mixed-workload", default="elast27_48",
                     help="workload of the FP64 vs FP32+refinement comparison ('' to skip)")
@@ -438,14 +684,23 @@ def main():
     ap.add_argument("--cpu-batch-sample", type=int, default=2000,
                     help="matrices of the batched workload the oracle runs on a process "
                          "pool (0 to skip)")
-    ap.add_argument("--cpu-sample", default=None,
-                    help="grid of the bounded oracle sample (default: 44^3 for 3D workloads, "
-                         "the full grid for 2D ones)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+
+    leg = None
+    if not args.no_cpu_baseline:
+        # the oracle on the whole workload, in a thread on one host core of its
+        # own beside the GPU legs (this thread and its children keep off that core)
+        leg = OracleLeg(args.workload, args.small_workload or "lap2d_5pt_64")
+        try:
+            others = set(os.sched_getaffinity(0)) - {leg.core}
+            if others:
+                os.sched_setaffinity(0, others)
+        except (AttributeError, OSError):
+            pass
 
     import torch
 
@@ -544,6 +799,12 @@ def main():
     lat = np.array(lat)
     xs = x.cpu().numpy()
     eta = backward_error(p, xs, B[nsol - 1].cpu().numpy())
+    # the workload's own right-hand side and the factor, for parity with the
+    # oracle (CPU-baseline leg) and the probe residual
+    x_main = num.solve(b).cpu().numpy()
+    Sp, Si, Sx = num.export()
+    rho = probe_residual(p, Sp, Si, Sx)
+    log("probe residual %.2e" % rho)
     log("solve p50 %.3f ms p99 %.3f ms, backward error %.2e" %
         (np.percentile(lat, 50), np.percentile(lat, 99), eta))
 
@@ -552,8 +813,9 @@ def main():
         kname, kcls, kflops = ("k_sched (persistent task queue: POTRF, TRSM, FP64 MFMA update "
                                "tiles + scatter)", "tasks", F)
     else:
-        kname, kcls, kflops = ("k_update (FP64 MFMA SYRK tile + relative-index scatter)",
-                               "update", uflops)
+        kname, kcls, kflops = ("k_update (FP64 MFMA SYRK tile + relative-index scatter; %s "
+                               "contribution order)" % ("fixed" if args.deterministic else
+                                                        "atomic"), "update", uflops)
     k_ms = kern[kcls] / args.steps
     k_launch = launches[kcls] / args.steps
     achieved = kflops / (k_ms * 1e-3) / 1e12 if k_ms > 0 else 0.0
@@ -566,6 +828,10 @@ def main():
                 "algorithmic_flops_per_launch": kflops / max(k_launch, 1),
                 "avg_launch_ms": k_ms / max(k_launch, 1), "launches_per_factor": k_launch}
 
+    ceil = spchol.measure_ceilings()
+    log("measured ceilings: %s" % ceil)
+    roofline["measured_ceiling"] = ceil["fp64_mfma_tflops"]
+    roofline["frac_of_measured_ceiling"] = achieved / ceil["fp64_mfma_tflops"]
     hb = hbm_bytes(sym)
     p50 = float(np.percentile(lat, 50))
     hbm = {"peak_GBps": HBM_PEAK_GBPS,
@@ -579,6 +845,9 @@ def main():
                        "note": "scatter bytes over the whole update kernel time (fused with "
                                "the products): a lower bound on the scatter's own rate"}}
     hbm["scatter"]["frac"] = hbm["scatter"]["GBps"] / HBM_PEAK_GBPS
+    hbm["measured_copy_GBps"] = ceil["copy_gbs"]
+    for k in ("solve", "scatter"):
+        hbm[k]["frac_of_measured_copy"] = hbm[k]["GBps"] / ceil["copy_gbs"]
     out = {
         "metric": METRIC, "value": gflops, "unit": "GFLOP/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
@@ -601,26 +870,54 @@ def main():
         "kernel_launches_per_factor": {c: launches[c] / args.steps for c in launches},
         "roofline": roofline,
         "hbm_phases": hbm,
+        "measured_ceilings": dict(ceil, what="spc_measure_ceilings: 16x16x4 matrix-core "
+                                                "products from registers (8 accumulators per "
+                                                "wave, 8 waves per SIMD) and a 512 MiB copy "
+                                                "(read + write bytes)"),
+        "residual_probe": {"value": rho, "probes": 8,
+                           "what": "||(L L^T - P A P^T) Z||_F / ||P A P^T Z||_F, Z 8 N(0,1) "
+                                   "columns, GPU factor on the host (scipy)"},
     }
     num.free()
     sym.free()
+    if args.other_order_steps and args.sched != 2:
+        out["other_order"] = other_order(p, amalg, F, 1 - args.deterministic,
+                                         args.other_order_steps, factor_ms)
+    small_export = None
+    if args.small_workload:
+        out["small_2d"], small_export = small_workload(args.small_workload, args.solves)
     if args.mixed_workload:
-        out["mixed_precision"] = mixed_precision(args.mixed_workload, args.mixed_steps, 1)
+        out["mixed_precision"] = mixed_precision(args.mixed_workload, args.mixed_steps, 1,
+                                                 deterministic=args.deterministic)
     if args.batch:
         tb = not args.no_batch_tune and not args.batch_options
         fixed = json.loads(args.batch_options) if args.batch_options else None
-        out["batched"] = [batched(args.batch, 3, 0, tune_options=tb, options=fixed),
-                          batched(args.batch, 3, 1, tune_options=tb, options=fixed)]
+        out["batched"] = [batched(args.batch, 3, prec, tune_options=tb, options=fixed,
+                                  deterministic=args.deterministic) for prec in (0, 1)]
     if args.serve_requests:
         out["serving"] = serving(args.serve_requests)
-    if not args.no_cpu_baseline:
-        if args.cpu_sample:
-            dims = tuple(int(v) for v in args.cpu_sample.split(","))
-        else:
-            full = inputs.WORKLOADS[name]["dims"]
-            dims = (44, 44, 44) if len(full) == 3 else full
-        log("cpu baseline on", dims)
-        out["cpu_baseline"] = cpu_baseline(name, dims)
+    if leg is not None:
+        log("waiting for the oracle leg")
+        res = leg.join()
+        m = res["main"]
+        out["cpu_baseline"] = {
+            "value": m["flops"] / m["factor_s"] / 1e9, "unit": "GFLOP/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "the whole %s workload (n=%d, F=%.4e): the oracle's numeric "
+                      "factorization (plain left-looking column Cholesky, untuned) on one "
+                      "pinned host core, %.1f s, run in a thread beside the GPU legs; "
+                      "symbolic %.1f s and solve %.1f s not counted"
+                      % (name, m["n"], m["flops"], m["factor_s"], m["symbolic_s"], m["solve_s"])}
+        par = factor_parity(m["n"], *m["C"], m["Lp"], m["Li"], m["Lx"], Sp, Si, Sx)
+        xo = np.asarray(m["x"]).reshape(p.n, -1)[:, 0]
+        par["solution_max_rel_diff"] = float(np.abs(x_main - xo).max() / np.abs(xo).max())
+        out["oracle_parity"] = par
+        log("oracle parity: %s" % par)
+        if small_export is not None:
+            sm = res["small"]
+            sp_ = factor_parity(sm["n"], *sm["C"], sm["Lp"], sm["Li"], sm["Lx"], *small_export)
+            out["small_2d"]["oracle_parity"] = sp_
+        del res, m
         if args.batch and args.cpu_batch_sample:
             log("cpu baseline of the batch, %d matrices" % min(args.batch, args.cpu_batch_sample))
             out["batched_cpu_baseline"] = cpu_batch_baseline(

@@ -325,6 +325,18 @@ spc_status spc_numeric_task_log(spc_numeric* num, int64_t* ntasks, int32_t* task
 /* Releases the factor's device memory (synchronizing its stream). NULL is accepted. */
 void spc_numeric_free(spc_numeric* num);
 
+/* Measurement helper (not part of the method): what the current device's
+ * matrix cores and HBM deliver to kernels that do nothing else -- 16 x 16 x 4
+ * FP64 and FP32 matrix-core products issued from registers (8 independent
+ * accumulators per wave, 8 waves per SIMD) and a 512 MiB streaming copy
+ * (bytes read + written per second).  Allocates 1 GiB for the copy and
+ * synchronizes the device. */
+typedef struct spc_ceilings {
+    double fp64_mfma_tflops, fp32_mfma_tflops, copy_gbs;
+} spc_ceilings;
+
+spc_status spc_measure_ceilings(spc_ceilings* out);
+
 /* Static English text for a status code. */
 const char* spc_status_string(spc_status st);
 

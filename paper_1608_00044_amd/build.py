@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libspchol.so")
 BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["symbolic.cpp", "plan.cpp", "schedule.cpp", "api.cpp", "server.cpp", "factor.hip",
-           "solve.hip", "refine.hip", "small.hip"]
+           "solve.hip", "refine.hip", "small.hip", "ceiling.hip"]
 ARCH = os.environ.get("SPCHOL_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -282,10 +282,13 @@ __global__ __launch_bounds__(256) void k_fwd_gemv(const RowBlock* __restrict__ w
         R acc[NR];
 #pragma unroll
         for (int c = 0; c < NR; ++c) acc[c] = R(0);
-        for (int k0 = wave; k0 < w; k0 += 32) {  // eight columns per step, loads first
-            R pv[8], yv[8][NR];
+        // kU columns per wave and step, every load of a step first (fewer with
+        // several right-hand sides, whose values take kU * NR registers)
+        constexpr int kU = NR == 1 ? 8 : 2;
+        for (int k0 = wave; k0 < w; k0 += 4 * kU) {
+            R pv[kU], yv[kU][NR];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < kU; ++u) {
                 const int k = min(k0 + 4 * u, w - 1);
                 const bool in = k0 + 4 * u < w;
                 pv[u] = in ? Pl[k * kPs + lane] : R(0);
@@ -293,7 +296,7 @@ __global__ __launch_bounds__(256) void k_fwd_gemv(const RowBlock* __restrict__ w
                 for (int c = 0; c < NR; ++c) yv[u][c] = ys[k][c];
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
+            for (int u = 0; u < kU; ++u)
 #pragma unroll
                 for (int c = 0; c < NR; ++c) acc[c] += pv[u] * yv[u][c];
         }
@@ -366,44 +369,48 @@ __global__ __launch_bounds__(256) void k_bwd_cols(const ColBlk* __restrict__ wor
     const int32_t* __restrict__ below = a.rows + rp + w + rb0;
     R* __restrict__ out = pb + pb_off[s] + (int64_t)h * w + k0;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    // GC columns per pass (all G for one right-hand side; with several, two
+    // at a time so that the accumulators stay in registers)
+    constexpr int GC = NR == 1 ? G : 2;
+    constexpr int kU = NR == 1 ? 4 : 1;  // rows per step, every load of a step first
     for (int c0 = 0; c0 < nrhs; c0 += NR) {
         const int nc = min(NR, nrhs - c0);
-        R acc[G][NR];
+        for (int kg = 0; kg < G; kg += GC) {
+            R acc[GC][NR];
 #pragma unroll
-        for (int k = 0; k < G; ++k)
+            for (int k = 0; k < GC; ++k)
 #pragma unroll
-            for (int c = 0; c < NR; ++c) acc[k][c] = R(0);
-        // kU rows per step with every load of the step issued first
-        constexpr int kU = NR == 1 ? 4 : 1;
-        for (int i0 = tid; i0 < r; i0 += 256 * kU) {
-            R yv[kU][NR], pv[kU][G];
+                for (int c = 0; c < NR; ++c) acc[k][c] = R(0);
+            for (int i0 = tid; i0 < r; i0 += 256 * kU) {
+                R yv[kU][NR], pv[kU][GC];
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                const int i = i0 + 256 * u;
-                const int32_t row = i < r ? below[i] : 0;
+                for (int u = 0; u < kU; ++u) {
+                    const int i = i0 + 256 * u;
+                    const int32_t row = i < r ? below[i] : 0;
 #pragma unroll
-                for (int c = 0; c < NR; ++c)
-                    yv[u][c] = (i < r && c < nc) ? y[(int64_t)(c0 + c) * n + row] : R(0);
+                    for (int c = 0; c < NR; ++c)
+                        yv[u][c] = (i < r && c < nc) ? y[(int64_t)(c0 + c) * n + row] : R(0);
 #pragma unroll
-                for (int k = 0; k < G; ++k)
-                    pv[u][k] = (i < r && k < kc) ? P[i + (int64_t)k * ld] : R(0);
+                    for (int k = 0; k < GC; ++k)
+                        pv[u][k] = (i < r && kg + k < kc) ? P[i + (int64_t)(kg + k) * ld] : R(0);
+                }
+#pragma unroll
+                for (int u = 0; u < kU; ++u)
+#pragma unroll
+                    for (int k = 0; k < GC; ++k)
+#pragma unroll
+                        for (int c = 0; c < NR; ++c) acc[k][c] += pv[u][k] * yv[u][c];
             }
 #pragma unroll
-            for (int u = 0; u < kU; ++u)
+            for (int k = 0; k < GC; ++k)
 #pragma unroll
-                for (int k = 0; k < G; ++k)
+                for (int c = 0; c < NR; ++c) {
+                    R v = acc[k][c];
 #pragma unroll
-                    for (int c = 0; c < NR; ++c) acc[k][c] += pv[u][k] * yv[u][c];
+                    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+                    if (lane == 0) part[wave][(kg + k) * NR + c] = v;
+                }
         }
-#pragma unroll
-        for (int k = 0; k < G; ++k)
-#pragma unroll
-            for (int c = 0; c < NR; ++c) {
-                R v = acc[k][c];
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-                if (lane == 0) part[wave][k * NR + c] = v;
-            }
         __syncthreads();
         if (tid < G * NR) {
             const int k = tid / NR, c = tid % NR;

@@ -40,7 +40,7 @@ EXPORTS = ("spc_default_options", "spc_analyze", "spc_symbolic_info_get", "spc_s
            "spc_analyze_batch", "spc_server_default_options", "spc_server_create",
            "spc_server_add_pattern", "spc_server_submit", "spc_server_wait",
            "spc_server_stats_get", "spc_server_destroy", "spc_numeric_task_log",
-           "spc_solve_noalloc")
+           "spc_solve_noalloc", "spc_measure_ceilings")
 
 
 class spc_options(C.Structure):
@@ -87,6 +87,11 @@ class spc_server_stats(C.Structure):
                 ("evictions", C.c_int64), ("bytes_in_use", C.c_int64), ("peak_bytes", C.c_int64),
                 ("budget_bytes", C.c_int64), ("peak_inflight", C.c_int32),
                 ("resident_factors", C.c_int32)]
+
+
+class spc_ceilings(C.Structure):
+    _fields_ = [("fp64_mfma_tflops", C.c_double), ("fp32_mfma_tflops", C.c_double),
+                ("copy_gbs", C.c_double)]
 
 
 class spc_kernel_times(C.Structure):
@@ -174,6 +179,8 @@ def lib():
         L.spc_server_stats_get.restype = C.c_int32
         L.spc_server_destroy.argtypes = [vp]
         L.spc_server_destroy.restype = C.c_int32
+        L.spc_measure_ceilings.argtypes = [C.POINTER(spc_ceilings)]
+        L.spc_measure_ceilings.restype = C.c_int32
         L.spc_status_string.argtypes = [C.c_int32]
         L.spc_status_string.restype = C.c_char_p
         _lib = L
@@ -618,6 +625,15 @@ class Server:
             self.destroy()
         except Exception:
             pass
+
+
+def measure_ceilings() -> dict:
+    """spc_measure_ceilings: measured FP64/FP32 matrix-core TFLOP/s and copy GB/s."""
+    c = spc_ceilings()
+    st = lib().spc_measure_ceilings(C.byref(c))
+    if st != SPC_OK:
+        raise SpcError(st, "spc_measure_ceilings")
+    return {f: getattr(c, f) for f, _ in c._fields_}
 
 
 # C-ABI-named entry points

@@ -37,17 +37,38 @@ def test_cpu_batch_baseline_small_sample():
     assert r["kind"] == "oracle" and r["unit"] == "matrices/s"
     assert r["cores"] == 3
     assert r["makespan_s"] <= r["one_core_sum_s"]
-    assert r["value"] >= r["one_core_matrices_per_s"]
+    assert r["value"] == 6 / r["pool_wall_s"]  # pool wall time, spawn included
+    assert r["makespan_matrices_per_s"] >= r["one_core_matrices_per_s"]
     assert r["factor_flops_F"] > 0
 
 
-def test_cpu_baseline_restores_affinity():
-    if not hasattr(os, "sched_getaffinity"):
-        return
-    before = os.sched_getaffinity(0)
-    r = bench.cpu_baseline("lap2d_5pt_64", (16, 16))
-    assert os.sched_getaffinity(0) == before
-    assert r["cores"] == 1 and r["value"] > 0
+def test_oracle_leg_parity_and_residuals():
+    """The oracle leg runs in a thread pinned to one core (the caller's
+    affinity is untouched); the parity check passes the oracle's own factor
+    and flags a planted error of 1e-8 in one entry; the probe and exact
+    residuals of the oracle's factor are at rounding level and see a planted
+    1e-6 error."""
+    before = os.sched_getaffinity(0) if hasattr(os, "sched_getaffinity") else None
+    leg = bench.OracleLeg("lap2d_5pt_64", "lap2d_5pt_64")
+    res = leg.join()
+    if before is not None:
+        assert os.sched_getaffinity(0) == before
+    m = res["main"]
+    assert m["factor_s"] > 0 and m["flops"] > 0
+    n, (Cp, Ci, Cx), Lp, Li, Lx = m["n"], m["C"], m["Lp"], m["Li"], m["Lx"]
+    par = bench.factor_parity(n, Cp, Ci, Cx, Lp, Li, Lx, Lp, Li, Lx)
+    assert par["structure_contained"] and par["explicit_zeros_ok"]
+    assert par["worst_over_tolerance"] == 0.0
+    bad = Lx.copy()
+    bad[len(bad) // 3] *= 1 + 1e-8
+    assert bench.factor_parity(n, Cp, Ci, Cx, Lp, Li, Lx, Lp, Li, bad)["worst_over_tolerance"] > 1
+    p = inputs.make_workload("lap2d_5pt_64")
+    assert bench.exact_residual(p, Lp, Li, Lx) <= 1e-12
+    assert bench.probe_residual(p, Lp, Li, Lx) <= 1e-12
+    bad = Lx.copy()
+    bad[len(bad) // 2] += 1e-6
+    assert bench.exact_residual(p, Lp, Li, bad) > 1e-9
+    assert bench.probe_residual(p, Lp, Li, bad) > 1e-9
 
 
 def test_measured_traffic_follows_the_source():
