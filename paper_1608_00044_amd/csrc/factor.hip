@@ -418,28 +418,22 @@ __device__ __forceinline__ bool potrf_task(int s, const KArgs& a, S* __restrict_
     }
     if (kCheck && unstable) return true;  // uniform: read after the last barrier
     panel_inverses<C, S>(T, rdiag, inv_g, cst, w, npanel, wave, lane);
-    // L11 back to the block, and its packed copy for the solves after the
-    // inverses, by the same folded index, many stores per thread in flight
-    S* __restrict__ pk = inv_g + inverse_elems(w);
+    // L11 back to the block by the same folded index, many stores per thread
+    // in flight
     for (int e0 = tid; e0 < nrect; e0 += kPerT * kPotrfThreads) {
         C v[kPerT];
-        int at[kPerT], gj[kPerT];
+        int gj[kPerT];
         bool ok[kPerT];
 #pragma unroll
         for (int u = 0; u < kPerT; ++u) {
             int i, j;
             ok[u] = fold(e0 + u * kPotrfThreads, i, j);
-            at[u] = ok[u] ? cst(j) + i : dummy;
             gj[u] = i + j * ld;
-            v[u] = T[at[u]];
+            v[u] = T[ok[u] ? cst(j) + i : dummy];
         }
 #pragma unroll
-        for (int u = 0; u < kPerT; ++u) {
-            if (ok[u]) {
-                base[gj[u]] = (S)v[u];
-                pk[at[u]] = (S)v[u];
-            }
-        }
+        for (int u = 0; u < kPerT; ++u)
+            if (ok[u]) base[gj[u]] = (S)v[u];
     }
     return false;
 }
@@ -470,6 +464,107 @@ __global__ __launch_bounds__(kPotrfThreads) void k_potrf(const int32_t* __restri
                                                          int32_t* __restrict__ status) {
     extern __shared__ double T[];
     diag_factor(level_sn[blockIdx.x], a, arena, dinv, status, status + 1, T);
+}
+
+// ---------------------------------------------------------------------------
+// inverse of L11 for the solves
+// ---------------------------------------------------------------------------
+
+// L11^{-1} of every large supernode (list), packed lower triangle by columns
+// after the supernode's panel inverses in dinv, so that each solve applies
+// the diagonal block as one triangular matrix-vector product instead of a
+// chain of w dependent steps.  One workgroup per supernode, computing in
+// FP64 whatever the storage type S: L11 (from the factor) and the panel
+// inverses D_i^{-1} go to LDS; wave p forms block column p of X = L11^{-1}
+// by block forward substitution on the matrix cores,
+//   X_pp = D_p^{-1},  X_ip = D_i^{-1} (-sum_{p <= k < i} L_ik X_kp),
+// right-looking: after X_ip is formed, B_j -= L_ji X_ip for every j > i,
+// with the running right-hand sides B_j in accumulator registers.  The FP64
+// accumulator layout of a 16 x 16 block is the B-operand layout of the next
+// product, so X_ip feeds the updates without a trip through LDS.
+constexpr int kLinvThreads = 64 * ((kMaxWidth + kPanel - 1) / kPanel);
+
+template <class S>
+__global__ __launch_bounds__(kLinvThreads) void k_linv(const int32_t* __restrict__ list, KArgs a,
+                                                       const S* __restrict__ arena,
+                                                       S* __restrict__ dinv) {
+    constexpr int NP = (kMaxWidth + kPanel - 1) / kPanel;
+    extern __shared__ double sm_linv[];
+    const int s = list[blockIdx.x];
+    const int w = a.sn_w[s], ld = a.sn_ld[s];
+    const int np = (w + kPanel - 1) / kPanel;
+    const S* __restrict__ base = arena + a.sn_off[s];
+    const S* __restrict__ inv_g = dinv + a.inv_off[s];
+    S* __restrict__ out = dinv + a.inv_off[s] + inverse_elems(w);
+    const int ntri = w * (w + 1) / 2;
+    double* T = sm_linv;               // packed L11, then a zero slot for masked reads
+    double* D = sm_linv + ntri + 1;    // panel inverses, 16 x 16 each, zero padded
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    auto cst = [w](int j) { return (j * (2 * w - j - 1)) >> 1; };
+    {
+        constexpr int kU = 8;
+        for (int e0 = tid; e0 < ntri; e0 += kU * kLinvThreads) {
+            double v[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int e = e0 + u * kLinvThreads;
+                int i = 0, j = 0;
+                if (e < ntri) tri_entry(e, w, i, j);
+                v[u] = e < ntri ? (double)base[i + (int64_t)j * ld] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+                if (e0 + u * kLinvThreads < ntri) T[e0 + u * kLinvThreads] = v[u];
+        }
+        if (tid == 0) T[ntri] = 0.0;
+        for (int e = tid; e < np * kPanel * kPanel; e += kLinvThreads) {
+            const int p = e >> 8, m = (e >> 4) & 15, k = e & 15;
+            const int jb = min(kPanel, w - p * kPanel);
+            D[e] = (m < jb && k < jb) ? (double)inv_g[p * kPanel * kPanel + m * jb + k] : 0.0;
+        }
+    }
+    __syncthreads();
+    const int p = wave;
+    if (p >= np) return;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int c = p * kPanel + lr;  // this lane's column of X
+    v4d B[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) B[j][q] = (j == p && 4 * q + lk == lr) ? 1.0 : 0.0;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        if (i < p || i >= np) continue;
+        // X_ip = D_i^{-1} B_i
+        v4d X = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+            X = __builtin_amdgcn_mfma_f64_16x16x4f64(D[i * 256 + lr * kPanel + 4 * kk + lk],
+                                                    B[i][kk], X, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = i * kPanel + 4 * q + lk;
+            if (r < w && r >= c) out[cst(c) + r] = (S)X[q];
+        }
+        // B_j -= L_ji X_ip for the block rows below
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            if (j <= i || j >= np) continue;
+            const int row = j * kPanel + lr;
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int col = i * kPanel + 4 * kk + lk;
+                const double l = -T[(row < w && col < w) ? cst(col) + row : ntri];
+                B[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(l, X[kk], B[j], 0, 0, 0);
+            }
+        }
+    }
+}
+
+size_t linv_lds(int wmax) {
+    const int np = (wmax + kPanel - 1) / kPanel;
+    return ((size_t)wmax * (wmax + 1) / 2 + 1 + (size_t)np * kPanel * kPanel) * sizeof(double);
 }
 
 // ---------------------------------------------------------------------------
@@ -1047,6 +1142,18 @@ void launch_update(spc_numeric* num, const DevicePlan* P, const KArgs& a, int64_
 // per-launch timing, sched 0 and 1 are captured into a graph on the first
 // factorization and replayed after.  sched 2: one persistent launch of the
 // task queue.
+// The inverses of every large diagonal block, once the factorization is done
+// (nothing in it reads them; the solves do).
+template <class R>
+void launch_linv(spc_numeric* num, const DevicePlan* P, const KArgs& a, hipStream_t st) {
+    if (P->nbig == 0) return;
+    const int ev = mark_begin(num, st);
+    hipLaunchKernelGGL(k_linv<R>, dim3((unsigned)P->nbig), dim3(kLinvThreads),
+                       linv_lds(P->big_maxw), st, (const int32_t*)P->big_sn, a,
+                       (const R*)num->arena, (R*)num->dinv);
+    mark_end(num, st, 1, ev);
+}
+
 template <class R>
 int32_t run_factor_t(spc_numeric* num, const double* values, hipStream_t st) {
     const Symbolic& S = num->sym->S;
@@ -1091,6 +1198,7 @@ int32_t run_factor_t(spc_numeric* num, const double* values, hipStream_t st) {
                                S.nsup, P->nrowblk, ticks, num->task_log);
             mark_end(num, st, 4, ev);
         }
+        launch_linv<R>(num, P, a, st);
     } else {
         // sched 0 (or fewer than two levels): one stream m, level by level.
         // sched 1: the lookahead on m and the bulk stream.
@@ -1100,6 +1208,7 @@ int32_t run_factor_t(spc_numeric* num, const double* values, hipStream_t st) {
                     launch_ft<R>(num, P, S, a, l, m);
                     launch_update<R>(num, P, a, P->tile_ptr[l], P->tile_ptr[l + 1], true, m, l);
                 }
+                launch_linv<R>(num, P, a, m);
                 return OK;
             }
             hipStream_t sb = num->bulk;
@@ -1126,6 +1235,7 @@ int32_t run_factor_t(spc_numeric* num, const double* values, hipStream_t st) {
                 HIP_TRY(hipEventRecord(E[2 + 2 * l], sb));
             }
             HIP_TRY(hipStreamWaitEvent(m, E[2 + 2 * (nl - 1)], 0));
+            launch_linv<R>(num, P, a, m);
             return OK;
         };
         if (num->timing) return enqueue(st);  // per-launch events: launch directly
@@ -1186,6 +1296,11 @@ int32_t configure_kernels() {
     for (const void* f : big)
         if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max) !=
             hipSuccess)
+            result = ERR_HIP;
+    const void* linv[] = {(const void*)k_linv<double>, (const void*)k_linv<float>};
+    for (const void* f : linv)
+        if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)linv_lds(kMaxWidth)) != hipSuccess)
             result = ERR_HIP;
     return result;
 }

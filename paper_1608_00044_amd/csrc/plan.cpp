@@ -25,9 +25,10 @@ struct Layout {
 
 struct PlanOffsets {
     size_t sn_first, sn_w, sn_ld, sn_off, inv_off, rowptr, rows, rowpair, slot, perm, pair_tgt,
-        pair_seg, pair_rel, pair_excl, rel, level_sn, rowblk, tiles, tasks, cnt0, rb_base;
+        pair_seg, pair_rel, pair_excl, rel, level_sn, big_sn, rowblk, tiles, tasks, cnt0,
+        rb_base;
     size_t pair_src, pair_end, scr_off, app_t, app_rb, app_p0, app_ent;
-    size_t slot_shared, red_row, red_ptr, red_slot, colblk, pb_off;
+    size_t slot_shared, red_row, red_ptr, red_slot, colblk, fwdblk, pb_off;
     size_t total;
 };
 
@@ -235,11 +236,12 @@ PlanOffsets plan_layout(const Symbolic& S, const std::vector<int64_t>& rb_ptr,
     o.pair_excl = L.add<uint8_t>(S.pairs.size());
     o.rel = L.add<int32_t>(S.rel.size());
     o.level_sn = L.add<int32_t>(S.level_sn.size());
+    o.big_sn = L.add<int32_t>(S.level_sn.size());
     o.rowblk = L.add<RowBlock>((size_t)rb_ptr.back());
     o.tiles = L.add<UpdTile>((size_t)tl_ptr.back());
     o.slot_shared = L.add<uint8_t>(S.rows.size());
     o.red_row = o.red_ptr = o.red_slot = 0;  // sized by solve_layout
-    o.colblk = 0;
+    o.colblk = o.fwdblk = 0;
     o.pb_off = L.add<int64_t>(ns);
     o.tasks = o.cnt0 = o.rb_base = 0;
     o.pair_src = o.pair_end = o.scr_off = o.app_t = o.app_rb = o.app_p0 = o.app_ent = 0;
@@ -260,6 +262,8 @@ struct SolveData {
     std::vector<int64_t> red_level_ptr;  // per level: its items
     std::vector<ColBlk> colblk;        // (s, column group, row chunk) of the large supernodes
     std::vector<int64_t> colblk_ptr;   // per level
+    std::vector<RowBlock> fwdblk;      // (s, 64-row block) of the large supernodes
+    std::vector<int64_t> fwdblk_ptr;   // per level
     std::vector<int64_t> pb_off;       // per supernode
     int64_t pb_total = 0;
 };
@@ -270,6 +274,7 @@ SolveData build_solve(const Symbolic& S) {
     d.shared.assign(S.rows.size(), 0);
     d.red_level_ptr.assign((size_t)nl + 1, 0);
     d.colblk_ptr.assign((size_t)nl + 1, 0);
+    d.fwdblk_ptr.assign((size_t)nl + 1, 0);
     d.red_ptr.push_back(0);
     d.pb_off.assign((size_t)S.nsup, 0);
     std::vector<int32_t> cnt((size_t)S.n, 0), stamp((size_t)S.n, -1);
@@ -310,9 +315,14 @@ SolveData build_solve(const Symbolic& S) {
             d.red_ptr.push_back((int64_t)d.red_slot.size());
         }
         d.red_level_ptr[l + 1] = (int64_t)d.red_row.size();
+        // every large supernode gets at least one forward workgroup: its
+        // diagonal block is solved there even with no rows below
         for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
             const int32_t s = S.level_sn[q];
-            if (is_small(S, s) || S.nbelow(s) == 0) continue;
+            if (is_small(S, s)) continue;
+            const int32_t nb = std::max<int32_t>(1, (S.nbelow(s) + kTile - 1) / kTile);
+            for (int32_t rb = 0; rb < nb; ++rb) d.fwdblk.push_back(RowBlock{s, rb});
+            if (S.nbelow(s) == 0) continue;
             const int32_t ng = (S.width(s) + kColGroup - 1) / kColGroup;
             const int32_t nh = (S.nbelow(s) + kRowChunk - 1) / kRowChunk;
             for (int32_t h = 0; h < nh; ++h)
@@ -322,6 +332,7 @@ SolveData build_solve(const Symbolic& S) {
             d.pb_total += (int64_t)nh * S.width(s);
         }
         d.colblk_ptr[l + 1] = (int64_t)d.colblk.size();
+        d.fwdblk_ptr[l + 1] = (int64_t)d.fwdblk.size();
     }
     return d;
 }
@@ -333,6 +344,7 @@ void solve_layout(PlanOffsets& o, const SolveData& d) {
     o.red_ptr = L.add<int64_t>(d.red_ptr.size());
     o.red_slot = L.add<int32_t>(d.red_slot.size());
     o.colblk = L.add<ColBlk>(d.colblk.size());
+    o.fwdblk = L.add<RowBlock>(d.fwdblk.size());
     o.total = L.total;
 }
 
@@ -496,6 +508,14 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
                 if (is_small(S, S.level_sn[q])) ls.push_back(S.level_sn[q]);
         }
         put(o.level_sn, ls.data(), ls.size() * 4);
+        std::vector<int32_t> big;
+        for (int32_t l = 0; l < nl; ++l)
+            for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l] + P->level_nbig[l]; ++q) {
+                big.push_back(ls[q]);
+                P->big_maxw = std::max<int32_t>(P->big_maxw, S.width(ls[q]));
+            }
+        P->nbig = (int64_t)big.size();
+        if (!big.empty()) put(o.big_sn, big.data(), big.size() * 4);
     }
     {
         const int32_t nl = (int32_t)S.level_ptr.size() - 1;
@@ -569,11 +589,13 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
         put(o.red_ptr, sd.red_ptr.data(), sd.red_ptr.size() * 8);
         put(o.red_slot, sd.red_slot.data(), sd.red_slot.size() * 4);
         put(o.colblk, sd.colblk.data(), sd.colblk.size() * sizeof(ColBlk));
+        put(o.fwdblk, sd.fwdblk.data(), sd.fwdblk.size() * sizeof(RowBlock));
         put(o.pb_off, sd.pb_off.data(), sd.pb_off.size() * 8);
         P->nslots = (int64_t)S.rows.size();
         P->pb_total = sd.pb_total;
         P->red_level_ptr = sd.red_level_ptr;
         P->colblk_ptr = sd.colblk_ptr;
+        P->fwdblk_ptr = sd.fwdblk_ptr;
     }
     if (!tasks.empty()) put(o.tasks, tasks.data(), tasks.size() * sizeof(Task));
     if (!cnt0.empty()) put(o.cnt0, cnt0.data(), cnt0.size() * 4);
@@ -605,6 +627,7 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
     P->pair_excl = (uint8_t*)(base + o.pair_excl);
     P->rel = (int32_t*)(base + o.rel);
     P->level_sn = (int32_t*)(base + o.level_sn);
+    P->big_sn = (int32_t*)(base + o.big_sn);
     P->rowblk = (RowBlock*)(base + o.rowblk);
     P->tiles = (UpdTile*)(base + o.tiles);
     P->slot_shared = (uint8_t*)(base + o.slot_shared);
@@ -612,6 +635,7 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
     P->red_ptr = (int64_t*)(base + o.red_ptr);
     P->red_slot = (int32_t*)(base + o.red_slot);
     P->colblk = (ColBlk*)(base + o.colblk);
+    P->fwdblk = (RowBlock*)(base + o.fwdblk);
     P->pb_off = (int64_t*)(base + o.pb_off);
     if (S.opt.deterministic) {
         P->pair_src = (int32_t*)(base + o.pair_src);

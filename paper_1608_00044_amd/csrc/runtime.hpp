@@ -33,8 +33,10 @@ inline bool is_small(const Symbolic& S, int64_t s) {
 //   the inverses of the kPanel-column diagonal blocks, compact: every full
 //   panel as kPanel x kPanel, the last partial one (jb < kPanel columns) as
 //   jb x jb, each row major;
-//   then a packed copy of L11 (lower triangle, column major: entry (i, j) at
-//   j (2w - j - 1) / 2 + i), which the solves load in one contiguous sweep.
+//   then, for a large supernode, L11^{-1} as a packed lower triangle by
+//   columns (entry (i, j) at j (2w - j - 1) / 2 + i), which the solves apply
+//   as one triangular matrix-vector product (a small supernode's solves use
+//   the compact inverse, its only panel).
 __host__ __device__ inline int64_t inverse_elems(int32_t w) {
     const int64_t full = w / kPanel, rem = w % kPanel;
     return full * kPanel * kPanel + rem * rem;
@@ -110,6 +112,9 @@ struct DevicePlan {
     uint8_t* pair_excl = nullptr; // 1 if no other source of the level shares the target
     int32_t* rel = nullptr;
     int32_t* level_sn = nullptr;
+    int32_t* big_sn = nullptr;   // every large supernode, level by level
+    int64_t nbig = 0;
+    int32_t big_maxw = 0;        // widest large supernode
     RowBlock* rowblk = nullptr;
     UpdTile* tiles = nullptr;
     // device task-queue schedule (only when analyzed with sched 2)
@@ -137,11 +142,12 @@ struct DevicePlan {
     int64_t* red_ptr = nullptr;      // slots of item k: red_slot[red_ptr[k] .. red_ptr[k + 1])
     int32_t* red_slot = nullptr;
     ColBlk* colblk = nullptr;        // backward (column group, row chunk) blocks
+    RowBlock* fwdblk = nullptr;      // forward (supernode, 64-row block) blocks
     int64_t* pb_off = nullptr;       // per supernode: its partial sums (chunk h, column k at
                                      // pb_off + h w + k) in the backward work
     int64_t nslots = 0;              // entries of rows
     int64_t pb_total = 0;
-    std::vector<int64_t> red_level_ptr, colblk_ptr;  // per level
+    std::vector<int64_t> red_level_ptr, colblk_ptr, fwdblk_ptr;  // per level
     std::vector<std::vector<int64_t>> round_ptr;  // per level: tile ranges of its rounds
     std::vector<uint8_t> level_apply;    // per level: large sources in the apply form
     std::vector<int64_t> app_ptr;        // per level: its apply items

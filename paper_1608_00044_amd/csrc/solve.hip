@@ -2,21 +2,23 @@
 // arXiv:1608.00044): y = L^{-1} P b by a forward sweep over the supernodal
 // elimination tree from the leaves, then z = L^{-T} y from the root back, and
 // x = P^T z.  Both sweeps go level by level; within a level every supernode
-// is independent.  Per level:
-//   forward:  k_fwd_diag   -- y_s = L11^{-1} y_s, one workgroup per supernode,
-//                             by 16-column panels using the inverted 16 x 16
-//                             diagonal blocks the factorization kept;
-//             k_fwd_gemv   -- y[rows below] -= L21 y_s for every 64-row block
-//                             of the panel; a row that another source of the
-//                             level also updates gets its value in a
-//                             contribution slot instead,
+// is independent.  A large supernode's diagonal block is applied as one
+// product with L11^{-1}, which the factorization forms, so no kernel walks
+// the w columns of a block one after another.  Per level:
+//   forward:  k_fwd_level  -- per 64-row block of a supernode's rows below:
+//                             z_s = L11^{-1} y_s (every block of s forms the
+//                             same z_s), then y[rows below] -= L21 z_s; a row
+//                             that another source of the level also updates
+//                             gets its value in a contribution slot instead,
 //             k_fwd_reduce -- which one thread per such row subtracts, sources
 //                             in increasing order;
 //   backward: k_bwd_cols   -- partial sums of L21^T y[rows below], one
 //                             workgroup per group of kColGroup columns and
 //                             chunk of kRowChunk rows, summed in a fixed tree;
-//             k_bwd_diag   -- y_s = L11^{-T} (y_s - t_s), t_s the chunks'
-//                             partial sums in chunk order, panels in reverse.
+//             k_bwd_diag   -- x_s = L11^{-T} (z_s - t_s), t_s the chunks'
+//                             partial sums in chunk order, on the matrix
+//                             cores.
+// Small supernodes (a group of lanes each) go through k_small_fwd/bwd.
 // No update is an atomic add: every sum has one fixed order, so a solve has
 // the same bits on every run.  Several right-hand sides go through every
 // kernel in groups of eight, so the factor is read once per group.
@@ -80,239 +82,197 @@ __device__ __forceinline__ float lane_bcast(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
-// Threads of the diagonal-block solve kernels: eight waves, each solving its
-// own right-hand sides after the workgroup has staged the block.
-constexpr int kDiagThreads = 512;
-constexpr int kDiagRegionMax = (kMaxWidth / kPanel) * kPanel * kPanel +
-                               (kMaxWidth % kPanel) * (kMaxWidth % kPanel) +
-                               kMaxWidth * (kMaxWidth + 1) / 2;
-
-// Stages the supernode's region of dinv (compact diagonal-block inverses,
-// then the packed L11) into LDS in one sweep with every load in flight: T gets
-// the packed lower triangle (entry (i, j) at cst(j) + i), I every panel's
-// inverse as a zero-padded 16 x 16 row-major block.
-template <class R>
-__device__ __forceinline__ void stage_block(R* __restrict__ T, R* __restrict__ I,
-                                            const R* __restrict__ region, int w, int tid) {
-    constexpr int kPer = (kDiagRegionMax + kDiagThreads - 1) / kDiagThreads;
-    const int ninv = (int)inverse_elems(w);
-    const int total = ninv + w * (w + 1) / 2;
-    const int plast = w / kPanel, jbl = w % kPanel;  // trailing partial panel, if any
-    R v[kPer];
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int e = tid + u * kDiagThreads;
-        v[u] = e < total ? region[e] : R(0);
-    }
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int e = tid + u * kDiagThreads;
-        if (e >= total) continue;
-        if (e >= ninv) {
-            T[e - ninv] = v[u];
-        } else {
-            const int p = e >> 8, q = e & 255;
-            if (p < plast) I[e] = v[u];  // full panel: already 16 x 16
-            else I[p * kPanel * kPanel + (q / jbl) * kPanel + q % jbl] = v[u];
-        }
-    }
-    if (jbl) {  // zero padding of the partial panel
-        for (int e = tid; e < kPanel * kPanel; e += kDiagThreads)
-            if ((e >> 4) >= jbl || (e & 15) >= jbl) I[plast * kPanel * kPanel + e] = R(0);
-    }
-}
-
-// Right-hand sides go through the row-block kernels NR at a time (NR = 1,
-// or kRhs for several): the block of L21 is read once per group and every
+// Right-hand sides go through the level kernels NR at a time (NR = 1, or
+// kRhs for several): the factor's blocks are read once per group and every
 // thread keeps NR partial sums.
 constexpr int kRhs = 8;
-constexpr int kPs = kTile + 1;  // padded LDS column stride of a staged 64-row block of L21
 
-// Stages rows [i0, i0 + 64) of the w columns of a panel block into LDS,
-// column by column (Pl[k * kPs + i]), zero past the m valid rows; sixteen
-// independent loads per thread in flight.
-template <class R>
-__device__ __forceinline__ void stage_rows(R* __restrict__ Pl, const R* __restrict__ P, int ld,
-                                           int i0, int m, int w, int tid) {
-    constexpr int kPer = (kTile * kMaxWidth + 255) / 256;
-    const int total = kTile * w;
-    R v[kPer];
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int e = tid + u * 256, k = e >> 6, i = e & 63;
-        v[u] = (e < total && i < m) ? P[i0 + i + (int64_t)k * ld] : R(0);
+// Matrix-core step 16 x 16 x 4 in the solve's arithmetic.  Operands: lane l
+// holds A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator register q of
+// lane l holds D[row(q, l / 16)][l % 16], row = 4q + l/16 (FP64) or
+// 4 (l/16) + q (FP32).
+template <class R> struct SMx;
+template <> struct SMx<double> {
+    typedef double acc __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc mfma(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int e = tid + u * 256;
-        if (e < total) Pl[(e >> 6) * kPs + (e & 63)] = v[u];
+    static __device__ __forceinline__ int row(int q, int lk) { return 4 * q + lk; }
+};
+template <> struct SMx<float> {
+    typedef float acc __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc mfma(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
-}
+    static __device__ __forceinline__ int row(int q, int lk) { return 4 * lk + q; }
+};
 
-// Diagonal block, forward: y_s = L11^{-1} y_s.  The workgroup stages L11
-// (packed lower triangle) and the 16 x 16 diagonal-block inverses in LDS;
-// then each wave solves its own right-hand sides with no workgroup barrier,
-// right-looking by panels:
-//   y_p = inv(D_p) y_p                      (lane (j, part): four products,
-//                                             the parts meet by cross-lane adds)
-//   y[k] -= L[k, p] y_p for every k below   (one row per lane, the sixteen
-//                                             y_p values broadcast in registers)
-template <class R>
-__global__ __launch_bounds__(kDiagThreads) void k_fwd_diag(const int32_t* __restrict__ level_sn,
-                                                           KArgs a,
-                                                  const R* __restrict__ arena,
-                                                  const R* __restrict__ dinv, R* __restrict__ y,
-                                                  int64_t n, int nrhs) {
-    extern __shared__ double sm_raw[];
-    R* sm = (R*)sm_raw;
-    __shared__ R ys[kDiagThreads / 64][kMaxWidth + kPanel];
-    const int s = level_sn[blockIdx.x];
-    const int w = a.sn_w[s], first = a.sn_first[s];
-    const R* __restrict__ inv = dinv + a.inv_off[s];  // inverses, then packed L11
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int j = lane & 15, part = lane >> 4;
-    const int npanel = (w + kPanel - 1) / kPanel;
-    auto cst = [w](int q) { return (q * (2 * w - q - 1)) >> 1; };
-    R* T = sm;
-    R* I = sm + w * (w + 1) / 2;
-    stage_block<R>(T, I, inv, w, tid);
-    __syncthreads();
-    R* yw = ys[wave];
-    for (int c = wave; c < nrhs; c += kDiagThreads / 64) {
-        R* __restrict__ yc = y + (int64_t)c * n;
-        {
-            R v[(kMaxWidth + 63) / 64];  // all of the wave's loads in flight at once
-#pragma unroll
-            for (int u = 0; u < (kMaxWidth + 63) / 64; ++u) {
-                const int k = lane + 64 * u;
-                v[u] = k < w ? yc[first + k] : R(0);
-            }
-#pragma unroll
-            for (int u = 0; u < (kMaxWidth + 63) / 64; ++u)
-                if (lane + 64 * u < w) yw[lane + 64 * u] = v[u];
-        }
-        __builtin_amdgcn_wave_barrier();
-        for (int p = 0; p < npanel; ++p) {
-            const int j0 = p * kPanel, jb = min(kPanel, w - j0);
-            R o = R(0);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int k = 4 * part + q;
-                o += I[p * kPanel * kPanel + j * kPanel + k] * (k < jb ? yw[j0 + k] : R(0));
-            }
-            o += __shfl_xor(o, 16, 64);
-            o += __shfl_xor(o, 32, 64);
-            R yp[kPanel];
-#pragma unroll
-            for (int q = 0; q < kPanel; ++q) yp[q] = lane_bcast(o, q);
-            __builtin_amdgcn_wave_barrier();
-            if (part == 0 && j < jb) yw[j0 + j] = o;
-            for (int k = j0 + kPanel + lane; k < w; k += 64) {
-                // every load of the row first, then two accumulation chains
-                R tv[kPanel];
-#pragma unroll
-                for (int q = 0; q < kPanel; ++q) tv[q] = T[cst(j0 + q) + k];
-                R acc0 = R(0), acc1 = R(0);
-#pragma unroll
-                for (int q = 0; q < kPanel; q += 2) {
-                    acc0 += tv[q] * yp[q];
-                    acc1 += tv[q + 1] * yp[q + 1];
-                }
-                yw[k] -= acc0 + acc1;
-            }
-            __builtin_amdgcn_wave_barrier();
-        }
-        for (int k = lane; k < w; k += 64) yc[first + k] = yw[k];
-        __builtin_amdgcn_wave_barrier();
-    }
-}
-
-// Below the diagonal block, forward: y[rows(i)] -= sum_k L21[i][k] y_s[k] for
-// one 64-row block: the block is staged in LDS, thread (row, wave) sums every
-// 4th column, the four waves meet in LDS; a row no other source of the level
-// updates is updated in place (its only writer), a shared row's sum goes to
-// its contribution slot for k_fwd_reduce.
+// Forward, one level, large supernodes: one workgroup per 64-row block of a
+// supernode's rows below its diagonal block (one block when there are none):
+//   z_s = L11^{-1} y_s          as one product with the inverse the
+//                               factorization formed (packed by columns
+//                               after the panel inverses): lane = row,
+//                               wave = every 4th column, the four waves'
+//                               partial sums meet in LDS in wave order;
+//                               every workgroup of s forms the same z_s, the
+//                               first writes it to zb (y_s itself stays: the
+//                               others still read it);
+//   y[rows(i)] -= L21[i] z_s    the block's 64 rows (loaded before z_s is
+//                               formed, so that their latency overlaps it),
+//                               lane = row, wave = every 4th column, waves
+//                               meet in LDS; a row no other source of the
+//                               level updates is updated in place (its only
+//                               writer), a shared row's sum goes to its
+//                               contribution slot for k_fwd_reduce.
 template <class R, int NR>
-__global__ __launch_bounds__(256) void k_fwd_gemv(const RowBlock* __restrict__ work, KArgs a,
-                                                  const R* __restrict__ arena, R* __restrict__ y,
-                                                  int64_t n, int nrhs, SolveBufs<R> sb) {
-    extern __shared__ double sm_raw[];
-    R* Pl = (R*)sm_raw;
+__global__ __launch_bounds__(256) void k_fwd_level(const RowBlock* __restrict__ work, KArgs a,
+                                                   const R* __restrict__ arena,
+                                                   const R* __restrict__ dinv,
+                                                   R* __restrict__ y, R* __restrict__ zb,
+                                                   int64_t n, int nrhs, SolveBufs<R> sb) {
+    static_assert(kMaxWidth <= 192, "three 64-row chunks of the diagonal block");
+    constexpr int KW = (kMaxWidth + 3) / 4;  // columns per wave
+    constexpr int kB = 8;                    // inverse loads in flight per batch
     __shared__ R ys[kMaxWidth][NR];
-    __shared__ R red[4][NR][64];
+    __shared__ R red[4][NR][kMaxWidth];
     const RowBlock wb = work[blockIdx.x];
     const int s = wb.s;
     const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
     const int64_t rp = a.rowptr[s];
     const int r = (int)(a.rowptr[s + 1] - rp) - w;
     const R* __restrict__ P = arena + a.sn_off[s] + w;
+    const R* __restrict__ Li = dinv + a.inv_off[s] + inverse_elems(w);
     const int32_t* __restrict__ below = a.rows + rp + w;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int i0 = wb.rb * kTile, m = min(kTile, r - i0);
-    // the output row, its form and (in place) its current values are loaded
-    // early so that their latency hides under the staging and the products
+    const int i0 = wb.rb * kTile, m = max(0, min(kTile, r - i0));
+    auto cst = [w](int q) { return (q * (2 * w - q - 1)) >> 1; };
+    R lv[KW];
+#pragma unroll
+    for (int u = 0; u < KW; ++u) {
+        const int k = wave + 4 * u;
+        lv[u] = (lane < m && k < w) ? P[i0 + lane + (int64_t)k * ld] : R(0);
+    }
     const int64_t slot = rp + w + i0 + tid;
     const int32_t row = tid < m ? below[i0 + tid] : 0;
     const bool sh = tid < m && sb.shared[slot];
-    stage_rows<R>(Pl, P, ld, i0, m, w, tid);
     for (int c0 = 0; c0 < nrhs; c0 += NR) {
         const int nc = min(NR, nrhs - c0);
         R yold[NR];
 #pragma unroll
         for (int c = 0; c < NR; ++c)
             yold[c] = (tid < m && !sh && c < nc) ? y[(int64_t)(c0 + c) * n + row] : R(0);
-        {
-            constexpr int kPer = (NR * kMaxWidth + 255) / 256;
-            const float invw = 1.0f / (float)w;
-            R v[kPer];
-            int kk[kPer];
-#pragma unroll
-            for (int u = 0; u < kPer; ++u) {
-                const int e = tid + 256 * u;
-                int c, k;
-                divmod_small(e, w, invw, c, k);
-                kk[u] = (e < NR * w) ? k * NR + c : -1;
-                v[u] = (e < NR * w && c < nc) ? y[(int64_t)(c0 + c) * n + first + k] : R(0);
-            }
-#pragma unroll
-            for (int u = 0; u < kPer; ++u)
-                if (kk[u] >= 0) (&ys[0][0])[kk[u]] = v[u];
+        for (int e = tid; e < w * NR; e += 256) {
+            const int k = e / NR, c = e % NR;
+            ys[k][c] = c < nc ? y[(int64_t)(c0 + c) * n + first + k] : R(0);
         }
         __syncthreads();
-        R acc[NR];
 #pragma unroll
-        for (int c = 0; c < NR; ++c) acc[c] = R(0);
-        // kU columns per wave and step, every load of a step first (fewer with
-        // several right-hand sides, whose values take kU * NR registers)
-        constexpr int kU = NR == 1 ? 8 : 2;
-        for (int k0 = wave; k0 < w; k0 += 4 * kU) {
-            R pv[kU], yv[kU][NR];
+        for (int q = 0; q < 3; ++q) {
+            if (64 * q >= w) break;
+            const int i = 64 * q + lane;
+            const int kend = min(w, 64 * q + 64);
+            R acc[NR];
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                const int k = min(k0 + 4 * u, w - 1);
-                const bool in = k0 + 4 * u < w;
-                pv[u] = in ? Pl[k * kPs + lane] : R(0);
+            for (int c = 0; c < NR; ++c) acc[c] = R(0);
+            for (int k0 = wave; k0 < kend; k0 += 4 * kB) {
+                R lx[kB];
 #pragma unroll
-                for (int c = 0; c < NR; ++c) yv[u][c] = ys[k][c];
+                for (int u = 0; u < kB; ++u) {
+                    const int k = k0 + 4 * u;
+                    lx[u] = (k < kend && k <= i && i < w) ? Li[cst(k) + i] : R(0);
+                }
+#pragma unroll
+                for (int u = 0; u < kB; ++u) {
+                    const int k = k0 + 4 * u;
+                    if (k < kend) {
+#pragma unroll
+                        for (int c = 0; c < NR; ++c) acc[c] += lx[u] * ys[k][c];
+                    }
+                }
             }
+            if (i < w) {
 #pragma unroll
-            for (int u = 0; u < kU; ++u)
-#pragma unroll
-                for (int c = 0; c < NR; ++c) acc[c] += pv[u] * yv[u][c];
-        }
-#pragma unroll
-        for (int c = 0; c < NR; ++c) red[wave][c][lane] = acc[c];
-        __syncthreads();
-        if (tid < m) {
-#pragma unroll
-            for (int c = 0; c < NR; ++c) {
-                if (c >= nc) break;
-                const R v = (red[0][c][tid] + red[1][c][tid]) + (red[2][c][tid] + red[3][c][tid]);
-                if (sh) sb.cb[(int64_t)(c0 + c) * sb.nslots + slot] = v;
-                else y[(int64_t)(c0 + c) * n + row] = yold[c] - v;
+                for (int c = 0; c < NR; ++c) red[wave][c][i] = acc[c];
             }
         }
         __syncthreads();
+        for (int e = tid; e < w * NR; e += 256) {
+            const int k = e / NR, c = e % NR;
+            ys[k][c] = (red[0][c][k] + red[1][c][k]) + (red[2][c][k] + red[3][c][k]);
+        }
+        __syncthreads();
+        if (wb.rb == 0) {
+            for (int e = tid; e < w * NR; e += 256) {
+                const int k = e / NR, c = e % NR;
+                if (c < nc) zb[(int64_t)(c0 + c) * n + first + k] = ys[k][c];
+            }
+        }
+        if (m > 0) {
+            R acc[NR];
+#pragma unroll
+            for (int c = 0; c < NR; ++c) acc[c] = R(0);
+#pragma unroll
+            for (int u = 0; u < KW; ++u) {
+                const int k = wave + 4 * u;
+                if (k < w) {
+#pragma unroll
+                    for (int c = 0; c < NR; ++c) acc[c] += lv[u] * ys[k][c];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < NR; ++c) red[wave][c][lane] = acc[c];
+            __syncthreads();
+            if (tid < m) {
+#pragma unroll
+                for (int c = 0; c < NR; ++c) {
+                    if (c >= nc) break;
+                    const R v = (red[0][c][tid] + red[1][c][tid]) +
+                                (red[2][c][tid] + red[3][c][tid]);
+                    if (sh) sb.cb[(int64_t)(c0 + c) * sb.nslots + slot] = v;
+                    else y[(int64_t)(c0 + c) * n + row] = yold[c] - v;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// x^T = u^T L11^{-1} on the matrix cores: x[k][c] = sum_{i >= k}
+// L11^{-1}[i][k] u[i][c], with u^T as the A operand (right-hand sides as its
+// 16 rows, zero past NR) and 16-column blocks of the packed inverse (Li, by
+// columns) as B.  Column block j goes to wave (j / 4 even ? j % 4 : 3 - j % 4)
+// counted from the last block, which spreads the blocks' falling cost over
+// the four waves; each wave issues eight operand loads before their products.
+template <class R, int NR>
+__device__ __forceinline__ void inv_upper(const R* __restrict__ Li, int w,
+                                          const R (*__restrict__ us)[NR], R* __restrict__ y,
+                                          int64_t n, int first, int c0, int nc, int wave,
+                                          int lane) {
+    const int lr = lane & 15, lk = lane >> 4;
+    const int np = (w + 15) / 16;
+    auto cst = [w](int q) { return (q * (2 * w - q - 1)) >> 1; };
+    for (int j = 0; j < np; ++j) {
+        const int jr = np - 1 - j;
+        if ((((jr >> 2) & 1) ? 3 - (jr & 3) : (jr & 3)) != wave) continue;
+        const int col = 16 * j + lr;
+        typename SMx<R>::acc acc = {R(0), R(0), R(0), R(0)};
+        for (int i0 = 16 * j; i0 < w; i0 += 32) {
+            R av[8], bv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = i0 + 4 * u + lk;
+                av[u] = (i < w && lr < NR) ? us[i < w ? i : 0][lr < NR ? lr : 0] : R(0);
+                bv[u] = (i < w && col < w && i >= col) ? Li[cst(col) + i] : R(0);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (i0 + 4 * u < w) acc = SMx<R>::mfma(av[u], bv[u], acc);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = SMx<R>::row(q, lk);
+            if (c < nc && col < w) y[(int64_t)(c0 + c) * n + first + col] = acc[q];
+        }
     }
 }
 
@@ -343,13 +303,13 @@ __global__ __launch_bounds__(256) void k_fwd_reduce(const int32_t* __restrict__ 
     yc[red_row[k]] = v;
 }
 
-// Below the diagonal block, backward: sum_i L21[i][k] y[rows(i)] for the
+// Backward, below the diagonal block: sum_i L21[i][k] y[rows(i)] for the
 // kColGroup columns k of group g of supernode s, over the rows i of chunk h:
-// thread tid takes rows tid, tid + 256, ... of the chunk (coalesced down each
-// column of the column-major panel), then the 256 partial sums of every
-// (column, right-hand side) meet in a fixed tree: across each wave by
-// butterfly shuffles, then the four waves in order, into the chunk's partial
-// sum (pb, one writer per entry, no atomics).  NR right-hand sides at a time.
+// thread tid takes rows tid, tid + 256, ... (coalesced down each column of
+// the column-major panel), then the 256 partial sums of every (column,
+// right-hand side) meet in a fixed tree: across each wave by butterfly
+// shuffles, then the four waves in order, into the chunk's partial sum (pb,
+// one writer per entry, no atomics).  NR right-hand sides at a time.
 template <class R, int NR>
 __global__ __launch_bounds__(256) void k_bwd_cols(const ColBlk* __restrict__ work, KArgs a,
                                                   const R* __restrict__ arena,
@@ -422,127 +382,49 @@ __global__ __launch_bounds__(256) void k_bwd_cols(const ColBlk* __restrict__ wor
     }
 }
 
-// Diagonal block, backward: y_s = L11^{-T} (y_s - t_s), right-looking from
-// the last panel:
-//   y_p = inv(D_p)^T y_p;   y[k] -= L[p, k]^T y_p for every k left of the panel,
-// one wave per right-hand side as in k_fwd_diag.
-template <class R>
-__global__ __launch_bounds__(kDiagThreads) void k_bwd_diag(const int32_t* __restrict__ level_sn,
-                                                           KArgs a,
-                                                  const R* __restrict__ arena,
-                                                  const R* __restrict__ dinv, R* __restrict__ y,
+// Backward, diagonal block, one workgroup per large supernode of the level:
+// t_s = the chunks' partial sums in chunk order, then
+// x_s = L11^{-T} (z_s - t_s) (inv_upper) into y, which now holds the solution
+// of every supernode done so far.
+template <class R, int NR>
+__global__ __launch_bounds__(256) void k_bwd_diag(const int32_t* __restrict__ level_sn, KArgs a,
+                                                  const R* __restrict__ dinv,
+                                                  R* __restrict__ y, const R* __restrict__ zb,
                                                   const R* __restrict__ pb,
                                                   const int64_t* __restrict__ pb_off,
                                                   int64_t pb_total, int64_t n, int nrhs) {
-    extern __shared__ double sm_raw[];
-    R* sm = (R*)sm_raw;
-    __shared__ R ys[kDiagThreads / 64][kMaxWidth + kPanel];
+    __shared__ R us[kMaxWidth][NR];
     const int s = level_sn[blockIdx.x];
     const int w = a.sn_w[s], first = a.sn_first[s];
-    const R* __restrict__ inv = dinv + a.inv_off[s];  // inverses, then packed L11
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int j = lane & 15, part = lane >> 4;
-    const int npanel = (w + kPanel - 1) / kPanel;
-    auto cst = [w](int q) { return (q * (2 * w - q - 1)) >> 1; };
-    R* T = sm;
-    R* I = sm + w * (w + 1) / 2;
-    stage_block<R>(T, I, inv, w, tid);
-    __syncthreads();
-    R* yw = ys[wave];
     const int r = (int)(a.rowptr[s + 1] - a.rowptr[s]) - w;
-    const int nh = (r + kRowChunk - 1) / kRowChunk;  // row chunks with partial sums
-    for (int c = wave; c < nrhs; c += kDiagThreads / 64) {
-        R* __restrict__ yc = y + (int64_t)c * n;
-        const R* __restrict__ pc = pb + (int64_t)c * pb_total + pb_off[s];
-        {
-            R v[(kMaxWidth + 63) / 64], t[(kMaxWidth + 63) / 64];
-#pragma unroll
-            for (int u = 0; u < (kMaxWidth + 63) / 64; ++u) {
-                const int k = lane + 64 * u;
-                v[u] = k < w ? yc[first + k] : R(0);
-                R acc = R(0);  // the chunks' partial sums in chunk order, 4 loads at a time
-                for (int h0 = 0; h0 < nh; h0 += 4) {
-                    R pv[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        pv[q] = (k < w && h0 + q < nh) ? pc[(int64_t)(h0 + q) * w + k] : R(0);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (h0 + q < nh) acc += pv[q];
-                }
-                t[u] = acc;
-            }
-#pragma unroll
-            for (int u = 0; u < (kMaxWidth + 63) / 64; ++u)
-                if (lane + 64 * u < w) yw[lane + 64 * u] = v[u] - t[u];
+    const int nh = r > 0 ? (r + kRowChunk - 1) / kRowChunk : 0;
+    const R* __restrict__ Li = dinv + a.inv_off[s] + inverse_elems(w);
+    const R* __restrict__ ps = pb + (r > 0 ? pb_off[s] : 0);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (int c0 = 0; c0 < nrhs; c0 += NR) {
+        const int nc = min(NR, nrhs - c0);
+        for (int e = tid; e < w * NR; e += 256) {
+            const int k = e / NR, c = e % NR;
+            R t = R(0);
+            if (c < nc)
+                for (int hh = 0; hh < nh; ++hh)
+                    t += ps[(int64_t)(c0 + c) * pb_total + (int64_t)hh * w + k];
+            us[k][c] = c < nc ? zb[(int64_t)(c0 + c) * n + first + k] - t : R(0);
         }
-        __builtin_amdgcn_wave_barrier();
-        for (int p = npanel - 1; p >= 0; --p) {
-            const int j0 = p * kPanel, jb = min(kPanel, w - j0);
-            R o = R(0);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int k = 4 * part + q;
-                o += I[p * kPanel * kPanel + k * kPanel + j] * (k < jb ? yw[j0 + k] : R(0));
-            }
-            o += __shfl_xor(o, 16, 64);
-            o += __shfl_xor(o, 32, 64);
-            R yp[kPanel];
-#pragma unroll
-            for (int q = 0; q < kPanel; ++q) yp[q] = lane_bcast(o, q);  // zero past jb
-            __builtin_amdgcn_wave_barrier();
-            if (part == 0 && j < jb) yw[j0 + j] = o;
-            for (int k = lane; k < j0; k += 64) {
-                // row j0 + q of column k (past the last row, any entry of the
-                // column: it meets yp[q] = 0)
-                const int ck = cst(k) + j0;
-                R tv[kPanel];
-#pragma unroll
-                for (int q = 0; q < kPanel; ++q) tv[q] = T[q < jb ? ck + q : ck];
-                R acc0 = R(0), acc1 = R(0);
-#pragma unroll
-                for (int q = 0; q < kPanel; q += 2) {
-                    acc0 += tv[q] * yp[q];
-                    acc1 += tv[q + 1] * yp[q + 1];
-                }
-                yw[k] -= acc0 + acc1;
-            }
-            __builtin_amdgcn_wave_barrier();
-        }
-        for (int k = lane; k < w; k += 64) yc[first + k] = yw[k];
-        __builtin_amdgcn_wave_barrier();
+        __syncthreads();
+        inv_upper<R, NR>(Li, w, us, y, n, first, c0, nc, wave, lane);
+        __syncthreads();
     }
 }
 
-// Dynamic LDS of the diagonal-block kernels: packed triangle + inverse blocks.
-static size_t diag_lds(int wmax, size_t elem) {
-    const int np = (wmax + kPanel - 1) / kPanel;
-    return ((size_t)wmax * (wmax + 1) / 2 + (size_t)np * kPanel * kPanel) * elem;
-}
-
-int32_t configure_solve_kernels() {
-    const int mx = (int)diag_lds(kMaxWidth, sizeof(double));
-    const void* diag[] = {(const void*)k_fwd_diag<double>, (const void*)k_bwd_diag<double>,
-                          (const void*)k_fwd_diag<float>, (const void*)k_bwd_diag<float>};
-    for (const void* f : diag)
-        if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, mx) != hipSuccess)
-            return ERR_HIP;
-    const int mg = (int)(kMaxWidth * kPs * sizeof(double));
-    const void* gemv[] = {(const void*)k_fwd_gemv<double, 1>, (const void*)k_fwd_gemv<float, 1>,
-                          (const void*)k_fwd_gemv<double, kRhs>,
-                          (const void*)k_fwd_gemv<float, kRhs>};
-    for (const void* f : gemv)
-        if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, mg) != hipSuccess)
-            return ERR_HIP;
-    return OK;
-}
+int32_t configure_solve_kernels() { return OK; }
 
 namespace {
 
-// The level sweeps of one solve on the work array (y, then the contribution
-// slots, then t, factor type), as enqueued on stream st.  Gather and scatter
-// stay outside: they touch the caller's b and x, which change from call to
-// call.
+// The level sweeps of one solve on the work array (factor type): y, then z
+// (the forward result of the large supernodes), the contribution slots and
+// the backward partial sums, each nrhs columns; as enqueued on stream st.  Gather and scatter stay outside: they
+// touch the caller's b and x, which change from call to call.
 template <class R, int NR>
 void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* work, hipStream_t st) {
     const Symbolic& S = num->sym->S;
@@ -552,23 +434,19 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* work, hipStream_t st) {
     const R* arena = (const R*)num->arena;
     const R* dinv = (const R*)num->dinv;
     R* y = work;
-    R* cb = y + n * nrhs;
+    R* zb = y + n * nrhs;
+    R* cb = zb + n * nrhs;
     R* pb = cb + P->nslots * nrhs;
     const SolveBufs<R> sb{cb, P->nslots, P->slot_shared};
     const int32_t nl = (int32_t)S.level_ptr.size() - 1;
     for (int32_t l = 0; l < nl; ++l) {
         const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1], nbig = P->level_nbig[l];
-        const size_t lds = diag_lds(P->level_maxw[l], sizeof(R));
-        const size_t lds_rows = (size_t)P->level_maxw[l] * kPs * sizeof(R);
-        if (nbig > 0)
-            hipLaunchKernelGGL(k_fwd_diag<R>, dim3(nbig), dim3(kDiagThreads), lds, st,
-                               P->level_sn + n0, a, arena, dinv, y, n, nrhs);
         launch_small_solve(num, a, P->level_sn + n0 + nbig, n1 - n0 - nbig, P->small_maxw[l],
                            P->small_maxm[l], y, cb, n, nrhs, true, st);
-        const int64_t rb0 = P->rowblk_ptr[l], rb1 = P->rowblk_ptr[l + 1];
-        if (rb1 > rb0)
-            hipLaunchKernelGGL((k_fwd_gemv<R, NR>), dim3((unsigned)(rb1 - rb0)), dim3(256),
-                               lds_rows, st, P->rowblk + rb0, a, arena, y, n, nrhs, sb);
+        const int64_t f0 = P->fwdblk_ptr[l], f1 = P->fwdblk_ptr[l + 1];
+        if (f1 > f0)
+            hipLaunchKernelGGL((k_fwd_level<R, NR>), dim3((unsigned)(f1 - f0)), dim3(256), 0, st,
+                               P->fwdblk + f0, a, arena, dinv, y, zb, n, nrhs, sb);
         const int64_t i0 = P->red_level_ptr[l], i1 = P->red_level_ptr[l + 1];
         if (i1 > i0) {
             const int64_t work_items = (i1 - i0) * nrhs;
@@ -585,10 +463,9 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* work, hipStream_t st) {
                                P->colblk + g0, a, arena, (const R*)y, pb,
                                (const int64_t*)P->pb_off, P->pb_total, n, nrhs);
         if (nbig > 0)
-            hipLaunchKernelGGL(k_bwd_diag<R>, dim3(nbig), dim3(kDiagThreads),
-                               diag_lds(P->level_maxw[l], sizeof(R)), st, P->level_sn + n0, a,
-                               arena, dinv, y, (const R*)pb, (const int64_t*)P->pb_off,
-                               P->pb_total, n, nrhs);
+            hipLaunchKernelGGL((k_bwd_diag<R, NR>), dim3((unsigned)nbig), dim3(256), 0, st,
+                               P->level_sn + n0, a, dinv, y, (const R*)zb, (const R*)pb,
+                               (const int64_t*)P->pb_off, P->pb_total, n, nrhs);
         launch_small_solve(num, a, P->level_sn + n0 + nbig, n1 - n0 - nbig, P->small_maxw[l],
                            P->small_maxm[l], y, cb, n, nrhs, false, st);
     }
@@ -615,12 +492,12 @@ int64_t solve_work_elems_per_rhs(const Symbolic& S) {
     for (int64_t s = 0; s < S.nsup; ++s)
         if (!is_small(S, s) && S.nbelow(s) > 0)
             pb += (int64_t)((S.nbelow(s) + kRowChunk - 1) / kRowChunk) * S.width(s);
-    return S.n + (int64_t)S.rows.size() + pb;
+    return 2 * S.n + (int64_t)S.rows.size() + pb;  // y, z, slots, partial sums
 }
 
-// Solve work for nrhs right-hand sides (factor type): the vector y (n x nrhs),
-// the forward contribution slots (nslots x nrhs) and the backward partial
-// sums (pb_total x nrhs).
+// Solve work for nrhs right-hand sides (factor type): the vectors y and z
+// (n x nrhs each), the forward contribution slots (nslots x nrhs), the
+// backward partial sums (pb_total x nrhs).
 int32_t ensure_solve_work(spc_numeric* num, int32_t nrhs) {
     if (num->work_cols >= nrhs) return OK;
     if (num->work) {
