@@ -107,6 +107,17 @@ typedef struct spc_options {
                                  order is dynamic): SPC_ERR_ARG otherwise.      */
     int32_t workers;          /* sched 2: persistent workgroups taking tasks;
                                  0 = as many as fit on the device at once        */
+    int32_t solve_tail;       /* 1: with deterministic = 0, the solves' top
+                                 levels of the supernodal elimination tree
+                                 (levels above the last one with more than 128
+                                 supernodes or any small one) run as one
+                                 persistent launch of dependent tasks, the
+                                 counters of Section IV applied to the two
+                                 solves (forward updates by atomic adds);
+                                 0 (default): every level as its own launches,
+                                 which measures faster on MI355X (a task's
+                                 signal costs a device-scope memory round trip,
+                                 about as much as a launch)                     */
 } spc_options;
 
 typedef struct spc_symbolic spc_symbolic;
@@ -130,7 +141,11 @@ typedef struct spc_symbolic_info {
     int64_t nbatch;        /* independent matrices (1 unless spc_analyze_batch)     */
     int64_t solve_bytes_per_rhs; /* device work bytes a solve holds per right-hand side
                                     (solution vector, forward contributions of every
-                                    below-diagonal row, backward partial sums)     */
+                                    below-diagonal row, backward partial sums), plus
+                                    16 (tail_supernodes + 1) bytes once per solve  */
+    int32_t tail_levels;   /* top levels whose solves run in the persistent launch
+                              (spc_options.solve_tail; 0 = none)                  */
+    int32_t tail_supernodes; /* supernodes on those levels                         */
 } spc_symbolic_info;
 
 /* Fills *opt with the defaults (sn_cap 150, sched 0, no amalgamation, no budget,
@@ -234,7 +249,8 @@ spc_status spc_solve(spc_numeric* num, int32_t nrhs, const double* b_dev, int64_
  * graph capture, serving loops, harnesses that forbid hipMalloc): the same
  * kernels and result, bit for bit, with the solve's work (the solution vector,
  * the forward contributions and the backward partial sums, sized by
- * spc_symbolic_info.solve_bytes_per_rhs times nrhs) in one static device
+ * spc_symbolic_info.solve_bytes_per_rhs times nrhs, plus the persistent
+ * launch's counters) in one static device
  * array of 64 MiB that each device holds from the library's load until the
  * process ends, instead of the factor's allocated work, and the level sweeps
  * launched directly on stream instead of replayed from a graph.  It allocates

@@ -78,6 +78,7 @@ spc_status analyze_checked(const spc_options* opt, spc_symbolic** out, Run run) 
     if (o.deterministic != 0 && o.deterministic != 1) return SPC_ERR_ARG;
     if (o.deterministic && o.sched == 2) return SPC_ERR_ARG;  // the queue's order is dynamic
     if (o.workers < 0) return SPC_ERR_ARG;
+    if (o.solve_tail != 0 && o.solve_tail != 1) return SPC_ERR_ARG;
     spc_symbolic* h = new (std::nothrow) spc_symbolic();
     if (!h) return SPC_ERR_OOM;
     Options so;
@@ -91,6 +92,7 @@ spc_status analyze_checked(const spc_options* opt, spc_symbolic** out, Run run) 
     so.small_r = o.small_r == 0 ? kSmallR : o.small_r;
     so.deterministic = o.deterministic;
     so.workers = o.workers;
+    so.solve_tail = o.solve_tail;
     int32_t st;
     try {
         st = run(so, o.threads, &h->S);
@@ -125,6 +127,7 @@ void spc_default_options(spc_options* opt) {
     opt->small_r = 0;
     opt->deterministic = 1;
     opt->workers = 0;
+    opt->solve_tail = 0;
 }
 
 const char* spc_status_string(spc_status st) {
@@ -191,6 +194,9 @@ spc_status spc_symbolic_info_get(const spc_symbolic* sym, spc_symbolic_info* inf
     info->max_below = S.max_r;
     info->nbatch = (int64_t)S.batch_ptr.size() - 1;
     info->solve_bytes_per_rhs = solve_work_elems_per_rhs(S) * (int64_t)real_size(S.opt.precision);
+    const int32_t nl = (int32_t)S.level_ptr.size() - 1, l0 = tail_start(S);
+    info->tail_levels = nl > l0 ? nl - l0 : 0;
+    info->tail_supernodes = nl > l0 ? S.level_ptr[nl] - S.level_ptr[l0] : 0;
     return SPC_OK;
 }
 

@@ -471,7 +471,8 @@ __global__ __launch_bounds__(kPotrfThreads) void k_potrf(const int32_t* __restri
 // ---------------------------------------------------------------------------
 
 // L11^{-1} of every large supernode (list), packed lower triangle by columns
-// after the supernode's panel inverses in dinv, so that each solve applies
+// after the supernode's panel inverses in dinv, and its transpose packed
+// upper by columns after it, so that each solve applies
 // the diagonal block as one triangular matrix-vector product instead of a
 // chain of w dependent steps.  One workgroup per supernode, computing in
 // FP64 whatever the storage type S: L11 (from the factor) and the panel
@@ -496,6 +497,7 @@ __global__ __launch_bounds__(kLinvThreads) void k_linv(const int32_t* __restrict
     const S* __restrict__ base = arena + a.sn_off[s];
     const S* __restrict__ inv_g = dinv + a.inv_off[s];
     S* __restrict__ out = dinv + a.inv_off[s] + inverse_elems(w);
+    S* __restrict__ outT = out + (w * (w + 1) / 2);  // L11^{-T}, packed upper by columns
     const int ntri = w * (w + 1) / 2;
     double* T = sm_linv;               // packed L11, then a zero slot for masked reads
     double* D = sm_linv + ntri + 1;    // panel inverses, 16 x 16 each, zero padded
@@ -545,7 +547,10 @@ __global__ __launch_bounds__(kLinvThreads) void k_linv(const int32_t* __restrict
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int r = i * kPanel + 4 * q + lk;
-            if (r < w && r >= c) out[cst(c) + r] = (S)X[q];
+            if (r < w && r >= c) {
+                out[cst(c) + r] = (S)X[q];
+                outT[((r * (r + 1)) >> 1) + c] = (S)X[q];
+            }
         }
         // B_j -= L_ji X_ip for the block rows below
 #pragma unroll

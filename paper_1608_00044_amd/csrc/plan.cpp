@@ -29,6 +29,7 @@ struct PlanOffsets {
         rb_base;
     size_t pair_src, pair_end, scr_off, app_t, app_rb, app_p0, app_ent;
     size_t slot_shared, red_row, red_ptr, red_slot, colblk, fwdblk, pb_off;
+    size_t tail_tasks, tail_segs;
     size_t total;
 };
 
@@ -241,7 +242,7 @@ PlanOffsets plan_layout(const Symbolic& S, const std::vector<int64_t>& rb_ptr,
     o.tiles = L.add<UpdTile>((size_t)tl_ptr.back());
     o.slot_shared = L.add<uint8_t>(S.rows.size());
     o.red_row = o.red_ptr = o.red_slot = 0;  // sized by solve_layout
-    o.colblk = o.fwdblk = 0;
+    o.colblk = o.fwdblk = o.tail_tasks = o.tail_segs = 0;
     o.pb_off = L.add<int64_t>(ns);
     o.tasks = o.cnt0 = o.rb_base = 0;
     o.pair_src = o.pair_end = o.scr_off = o.app_t = o.app_rb = o.app_p0 = o.app_ent = 0;
@@ -266,7 +267,85 @@ struct SolveData {
     std::vector<int64_t> fwdblk_ptr;   // per level
     std::vector<int64_t> pb_off;       // per supernode
     int64_t pb_total = 0;
+    int32_t tail_l0 = 0, ntail = 0;
+    std::vector<TailTask> tail;        // the tail's tasks in ticket order
+    std::vector<TailSeg> segs;
 };
+
+// The tail's tasks (levels [l0, levels) of the supernodal etree, every
+// supernode there large), in a topological ticket order: per level from the
+// leaves, the F tasks, then the R blocks; then per level from the root, the
+// C blocks, then the B tasks.  A forward row block's rows are split into
+// segments by target; a target receives its rows' updates source after
+// source in that ticket order, so each segment's rank is the number of the
+// target's rows that earlier blocks update.  A backward row block lists the
+// supernodes its rows belong to (it waits for each one's solution).
+void build_tail(const Symbolic& S, int32_t l0, SolveData& d) {
+    const int32_t nl = (int32_t)S.level_ptr.size() - 1;
+    d.tail_l0 = l0;
+    if (l0 >= nl) return;
+    std::vector<int32_t> tix((size_t)S.nsup, -1);
+    int32_t nt = 0;
+    for (int32_t q = S.level_ptr[l0]; q < S.level_ptr[nl]; ++q) tix[S.level_sn[q]] = nt++;
+    d.ntail = nt;
+    std::vector<int32_t> need((size_t)nt, 0), acc((size_t)nt, 0);
+    for (int32_t q = S.level_ptr[l0]; q < S.level_ptr[nl]; ++q) {
+        const int32_t s = S.level_sn[q];
+        for (int64_t k = S.rowptr[s] + S.width(s); k < S.rowptr[s + 1]; ++k)
+            need[tix[S.col_owner[S.rows[k]]]]++;
+    }
+    auto blocks = [&](int32_t s) { return (S.nbelow(s) + kTile - 1) / kTile; };
+    for (int32_t l = l0; l < nl; ++l) {
+        for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
+            const int32_t s = S.level_sn[q];
+            d.tail.push_back(TailTask{s, tix[s], kTailF, 0, need[tix[s]], 0});
+        }
+        for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
+            const int32_t s = S.level_sn[q];
+            const int32_t r = S.nbelow(s);
+            for (int32_t rb = 0; rb < blocks(s); ++rb) {
+                const int64_t base = S.rowptr[s] + S.width(s) + (int64_t)rb * kTile;
+                const int32_t m = std::min(kTile, r - rb * kTile);
+                const int32_t g0 = (int32_t)d.segs.size();
+                for (int32_t i = 0; i < m;) {
+                    const int32_t t = S.col_owner[S.rows[base + i]];
+                    int32_t j = i + 1;
+                    while (j < m && S.col_owner[S.rows[base + j]] == t) ++j;
+                    const int32_t u = tix[t];
+                    d.segs.push_back(TailSeg{u, i, j, acc[u]});
+                    acc[u] += j - i;
+                    i = j;
+                }
+                d.tail.push_back(
+                    TailTask{s, tix[s], kTailR, (int16_t)rb, g0, (int32_t)d.segs.size()});
+            }
+        }
+    }
+    for (int32_t l = nl - 1; l >= l0; --l) {
+        for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
+            const int32_t s = S.level_sn[q];
+            const int32_t r = S.nbelow(s);
+            for (int32_t rb = 0; rb < blocks(s); ++rb) {
+                const int64_t base = S.rowptr[s] + S.width(s) + (int64_t)rb * kTile;
+                const int32_t m = std::min(kTile, r - rb * kTile);
+                const int32_t g0 = (int32_t)d.segs.size();
+                for (int32_t i = 0; i < m;) {
+                    const int32_t t = S.col_owner[S.rows[base + i]];
+                    int32_t j = i + 1;
+                    while (j < m && S.col_owner[S.rows[base + j]] == t) ++j;
+                    d.segs.push_back(TailSeg{tix[t], i, j, 0});
+                    i = j;
+                }
+                d.tail.push_back(
+                    TailTask{s, tix[s], kTailC, (int16_t)rb, g0, (int32_t)d.segs.size()});
+            }
+        }
+        for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
+            const int32_t s = S.level_sn[q];
+            d.tail.push_back(TailTask{s, tix[s], kTailB, 0, blocks(s), 0});
+        }
+    }
+}
 
 SolveData build_solve(const Symbolic& S) {
     SolveData d;
@@ -279,7 +358,20 @@ SolveData build_solve(const Symbolic& S) {
     d.pb_off.assign((size_t)S.nsup, 0);
     std::vector<int32_t> cnt((size_t)S.n, 0), stamp((size_t)S.n, -1);
     std::vector<int32_t> rows_touched;
+    const int32_t l0 = tail_start(S);
     for (int32_t l = 0; l < nl; ++l) {
+        if (l >= l0) {
+            // the tail: no level kernels; 64-row partial sums for its C blocks
+            d.red_level_ptr[l + 1] = d.red_level_ptr[l];
+            d.colblk_ptr[l + 1] = (int64_t)d.colblk.size();
+            d.fwdblk_ptr[l + 1] = (int64_t)d.fwdblk.size();
+            for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
+                const int32_t s = S.level_sn[q];
+                d.pb_off[s] = d.pb_total;
+                d.pb_total += (int64_t)((S.nbelow(s) + kTile - 1) / kTile) * S.width(s);
+            }
+            continue;
+        }
         rows_touched.clear();
         for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
             const int32_t s = S.level_sn[q];
@@ -334,6 +426,7 @@ SolveData build_solve(const Symbolic& S) {
         d.colblk_ptr[l + 1] = (int64_t)d.colblk.size();
         d.fwdblk_ptr[l + 1] = (int64_t)d.fwdblk.size();
     }
+    build_tail(S, l0, d);
     return d;
 }
 
@@ -345,6 +438,8 @@ void solve_layout(PlanOffsets& o, const SolveData& d) {
     o.red_slot = L.add<int32_t>(d.red_slot.size());
     o.colblk = L.add<ColBlk>(d.colblk.size());
     o.fwdblk = L.add<RowBlock>(d.fwdblk.size());
+    o.tail_tasks = L.add<TailTask>(d.tail.size());
+    o.tail_segs = L.add<TailSeg>(d.segs.size());
     o.total = L.total;
 }
 
@@ -362,6 +457,40 @@ void det_layout(PlanOffsets& o, const DetData& d) {
 }
 
 }  // namespace
+
+int32_t tail_start(const Symbolic& S) {
+    const int32_t nl = (int32_t)S.level_ptr.size() - 1;
+    // the tail's forward updates are atomic adds: only in the atomic order
+    if (S.opt.solve_tail != 1 || S.opt.deterministic || nl < 2) return std::max(nl, 0);
+    int32_t l = nl;
+    while (l > 0) {
+        const int32_t q0 = S.level_ptr[l - 1], q1 = S.level_ptr[l];
+        if (q1 - q0 > kTailMaxLevelSn) break;
+        bool small = false;
+        for (int32_t q = q0; q < q1 && !small; ++q) small = is_small(S, S.level_sn[q]);
+        if (small) break;
+        --l;
+    }
+    return nl - l >= 2 ? l : nl;  // a tail of one level saves nothing
+}
+
+int64_t solve_pb_elems(const Symbolic& S) {
+    const int32_t l0 = tail_start(S);
+    int64_t pb = 0;
+    for (int64_t s = 0; s < S.nsup; ++s) {
+        const int32_t r = S.nbelow(s);
+        if (S.level[s] >= l0) pb += (int64_t)((r + kTile - 1) / kTile) * S.width(s);
+        else if (!is_small(S, s) && r > 0) pb += (int64_t)((r + kRowChunk - 1) / kRowChunk) * S.width(s);
+    }
+    return pb;
+}
+
+int64_t tail_state_words(const Symbolic& S) {
+    const int32_t nl = (int32_t)S.level_ptr.size() - 1;
+    const int32_t l0 = tail_start(S);
+    if (l0 >= nl) return 0;
+    return 4 * (int64_t)(S.level_ptr[nl] - S.level_ptr[l0]) + 4;
+}
 
 int64_t inverse_blocks_elems(const Symbolic& S) {
     int64_t t = 0;
@@ -596,6 +725,14 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
         P->red_level_ptr = sd.red_level_ptr;
         P->colblk_ptr = sd.colblk_ptr;
         P->fwdblk_ptr = sd.fwdblk_ptr;
+        put(o.tail_tasks, sd.tail.data(), sd.tail.size() * sizeof(TailTask));
+        put(o.tail_segs, sd.segs.data(), sd.segs.size() * sizeof(TailSeg));
+        P->tail_l0 = sd.tail_l0;
+        P->ntail = sd.ntail;
+        P->ntail_tasks = (int64_t)sd.tail.size();
+        while (P->ntail_fwd < P->ntail_tasks &&
+               (sd.tail[P->ntail_fwd].kind == kTailF || sd.tail[P->ntail_fwd].kind == kTailR))
+            ++P->ntail_fwd;
     }
     if (!tasks.empty()) put(o.tasks, tasks.data(), tasks.size() * sizeof(Task));
     if (!cnt0.empty()) put(o.cnt0, cnt0.data(), cnt0.size() * 4);
@@ -637,6 +774,8 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
     P->colblk = (ColBlk*)(base + o.colblk);
     P->fwdblk = (RowBlock*)(base + o.fwdblk);
     P->pb_off = (int64_t*)(base + o.pb_off);
+    P->tail_tasks = (TailTask*)(base + o.tail_tasks);
+    P->tail_segs = (TailSeg*)(base + o.tail_segs);
     if (S.opt.deterministic) {
         P->pair_src = (int32_t*)(base + o.pair_src);
         P->pair_end = (int32_t*)(base + o.pair_end);

@@ -36,13 +36,16 @@ inline bool is_small(const Symbolic& S, int64_t s) {
 //   then, for a large supernode, L11^{-1} as a packed lower triangle by
 //   columns (entry (i, j) at j (2w - j - 1) / 2 + i), which the solves apply
 //   as one triangular matrix-vector product (a small supernode's solves use
-//   the compact inverse, its only panel).
+//   the compact inverse, its only panel);
+//   then L11^{-T} as a packed upper triangle by columns (entry (i, j), i <= j,
+//   at j (j + 1) / 2 + i): the backward solve's product with consecutive
+//   rows in consecutive addresses.
 __host__ __device__ inline int64_t inverse_elems(int32_t w) {
     const int64_t full = w / kPanel, rem = w % kPanel;
     return full * kPanel * kPanel + rem * rem;
 }
 __host__ __device__ inline int64_t diag_region_elems(int32_t w) {
-    return inverse_elems(w) + (int64_t)w * (w + 1) / 2;
+    return inverse_elems(w) + (int64_t)w * (w + 1);
 }
 // Row i and column j of entry e of a packed lower triangle of order w stored
 // by columns (column j starts at j (2w - j - 1) / 2 + j): j from the root of
@@ -89,6 +92,21 @@ struct ColBlk { int32_t s; int16_t g, h; };  // column group g, row chunk h of s
 // Deterministic order, apply pass: rows [ilo, ihi) of pair p's source that
 // land in one 64-row block of the target.
 struct AppEnt { int32_t p, ilo, ihi, pad; };
+// Solves of the top levels of the supernodal elimination tree (the tail: the
+// levels above the last one with more than kTailMaxLevelSn supernodes or a
+// small one) run as one persistent launch of tasks in a fixed topological
+// order (solve.hip, k_tail).  u is the supernode's index among the tail's.
+enum : int16_t { kTailF = 0, kTailR = 1, kTailC = 2, kTailB = 3 };
+struct TailTask {
+    int32_t s, u;
+    int16_t kind, rb;  // task kind, 64-row block of the supernode's rows below
+    int32_t a, b;      // F: rows the tail's sources update; R, C: its segments [a, b);
+                       // B: its row blocks
+};
+// Rows [lo, hi) of an R block that land in tail supernode u (rank: rows of u
+// that earlier sources update), or of a C block that belong to u (rank 0).
+struct TailSeg { int32_t u, lo, hi, rank; };
+constexpr int kTailMaxLevelSn = 128;
 
 // Device copy of the symbolic analysis, shared by every factor of it on one device.
 struct DevicePlan {
@@ -148,6 +166,13 @@ struct DevicePlan {
     int64_t nslots = 0;              // entries of rows
     int64_t pb_total = 0;
     std::vector<int64_t> red_level_ptr, colblk_ptr, fwdblk_ptr;  // per level
+    // the tail's solve tasks: levels [tail_l0, levels) (none: tail_l0 = levels)
+    int32_t tail_l0 = 0;
+    int32_t ntail = 0;               // supernodes in the tail
+    TailTask* tail_tasks = nullptr;
+    int64_t ntail_tasks = 0;
+    int64_t ntail_fwd = 0;           // forward tasks come first
+    TailSeg* tail_segs = nullptr;
     std::vector<std::vector<int64_t>> round_ptr;  // per level: tile ranges of its rounds
     std::vector<uint8_t> level_apply;    // per level: large sources in the apply form
     std::vector<int64_t> app_ptr;        // per level: its apply items
@@ -296,5 +321,13 @@ void launch_small_solve(spc_numeric* num, const KArgs& a, const int32_t* list, i
 // for nrhs right-hand sides.
 int64_t solve_work_elems(const spc_numeric* num, int32_t nrhs);
 int64_t solve_work_elems_per_rhs(const Symbolic& S);
+// First level of the solves' tail (levels when there is none).
+int32_t tail_start(const Symbolic& S);
+// Backward partial sums per right-hand side: kRowChunk-row chunks of the
+// large supernodes below the tail, kTile-row blocks of the tail's.
+int64_t solve_pb_elems(const Symbolic& S);
+// int32 words of the tail's task state (four counters per supernode, the
+// ticket and the abort and error words), at the end of the solve work.
+int64_t tail_state_words(const Symbolic& S);
 
 }  // namespace spc

@@ -395,7 +395,8 @@ spc_status spc_server_add_pattern(spc_server* s, spc_symbolic* sym, int32_t* pat
     const Symbolic& S = sym->S;
     const size_t elem = S.opt.precision == 1 ? sizeof(float) : sizeof(double);
     p.bytes = numeric_bytes(sym) +
-              (int64_t)elem * solve_work_elems_per_rhs(S) * (int64_t)s->opt.max_nrhs;
+              (int64_t)elem * solve_work_elems_per_rhs(S) * (int64_t)s->opt.max_nrhs +
+              4 * tail_state_words(S);
     p.plan_bytes = (int64_t)sym->plan_bytes_estimate;
     {
         // the server keeps the handle referenced until spc_server_destroy

@@ -87,33 +87,147 @@ __device__ __forceinline__ float lane_bcast(float v, int lane) {
 // thread keeps NR partial sums.
 constexpr int kRhs = 8;
 
-// Matrix-core step 16 x 16 x 4 in the solve's arithmetic.  Operands: lane l
-// holds A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator register q of
-// lane l holds D[row(q, l / 16)][l % 16], row = 4q + l/16 (FP64) or
-// 4 (l/16) + q (FP32).
-template <class R> struct SMx;
-template <> struct SMx<double> {
-    typedef double acc __attribute__((ext_vector_type(4)));
-    static __device__ __forceinline__ acc mfma(double a, double b, acc c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+// Row i's partial sums over this wave's columns k = wave + 4u of a packed
+// triangle already in registers (m[u] = entry (i, k), zero outside the
+// triangle), into red[wave][.][i].
+template <class R, int NR, int KW>
+__device__ __forceinline__ void tri_rows(const R (&m)[KW], const R (*__restrict__ ys)[NR],
+                                         R (*__restrict__ red)[NR][kMaxWidth], int w, int i,
+                                         int wave) {
+    R acc[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) acc[c] = R(0);
+#pragma unroll
+    for (int u = 0; u < KW; ++u) {
+        const int k = wave + 4 * u;
+        if (k < w) {
+#pragma unroll
+            for (int c = 0; c < NR; ++c) acc[c] += m[u] * ys[k][c];
+        }
     }
-    static __device__ __forceinline__ int row(int q, int lk) { return 4 * q + lk; }
-};
-template <> struct SMx<float> {
-    typedef float acc __attribute__((ext_vector_type(4)));
-    static __device__ __forceinline__ acc mfma(float a, float b, acc c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    if (i < w) {
+#pragma unroll
+        for (int c = 0; c < NR; ++c) red[wave][c][i] = acc[c];
     }
-    static __device__ __forceinline__ int row(int q, int lk) { return 4 * lk + q; }
-};
+}
+
+// Products with a diagonal block's inverse, one matrix-vector product per
+// right-hand side: lane = row of a 64-row chunk, wave = every 4th column
+// k = wave + 4u, the waves' partial sums into red[wave][c][i].  kUpper =
+// false: z = L11^{-1} v with L11^{-1} packed lower by columns (entry (i, k) at
+// k (2w - k - 1) / 2 + i); kUpper = true: x = L11^{-T} v with L11^{-T} packed
+// upper by columns (entry (i, k) at k (k + 1) / 2 + i): both read
+// consecutive rows at consecutive addresses.  tri_first loads, early, the
+// chunk with the most columns (the last rows for the lower triangle, the
+// first for the upper) into registers; tri_rest forms every chunk's sums,
+// the other chunks' entries loaded 16 at a time.
+constexpr int kTriKW = (kMaxWidth + 3) / 4;
+
+template <bool kUpper>
+__device__ __forceinline__ int tri_first_chunk(int w) { return kUpper ? 0 : (w - 1) >> 6; }
+template <bool kUpper>
+__device__ __forceinline__ bool tri_in(int w, int i, int k) {
+    return kUpper ? (k >= i && k < w) : (k <= i && i < w);
+}
+template <bool kUpper>
+__device__ __forceinline__ int tri_at(int w, int i, int k) {
+    return kUpper ? ((k * (k + 1)) >> 1) + i : ((k * (2 * w - k - 1)) >> 1) + i;
+}
+
+template <class R, bool kUpper>
+__device__ __forceinline__ void tri_first(const R* __restrict__ M, int w, int wave, int lane,
+                                          R (&m)[kTriKW]) {
+    const int i = 64 * tri_first_chunk<kUpper>(w) + lane;
+#pragma unroll
+    for (int u = 0; u < kTriKW; ++u) {
+        const int k = wave + 4 * u;
+        m[u] = tri_in<kUpper>(w, i, k) ? M[tri_at<kUpper>(w, i, k)] : R(0);
+    }
+}
+
+template <class R, int NR, bool kUpper>
+__device__ __forceinline__ void tri_rest(const R* __restrict__ M, int w, const R (&m)[kTriKW],
+                                         const R (*__restrict__ ys)[NR],
+                                         R (*__restrict__ red)[NR][kMaxWidth], int wave, int lane) {
+    const int qa = tri_first_chunk<kUpper>(w), nq = (w + 63) >> 6;
+    tri_rows<R, NR, kTriKW>(m, ys, red, w, 64 * qa + lane, wave);
+    for (int q = 0; q < nq; ++q) {
+        if (q == qa) continue;
+        const int i = 64 * q + lane;
+        // the columns that meet rows [64q, 64q + 64)
+        const int u_lo = kUpper ? 16 * q : 0;
+        const int u_hi = kUpper ? kTriKW : min(kTriKW, 16 * (q + 1));
+        R acc[NR];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) acc[c] = R(0);
+        for (int u0 = u_lo; u0 < u_hi; u0 += 16) {
+            R lb[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int k = wave + 4 * (u0 + u);
+                lb[u] = (u0 + u < kTriKW && tri_in<kUpper>(w, i, k)) ? M[tri_at<kUpper>(w, i, k)]
+                                                                     : R(0);
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int k = wave + 4 * (u0 + u);
+                if (u0 + u < kTriKW && k < w) {
+#pragma unroll
+                    for (int c = 0; c < NR; ++c) acc[c] += lb[u] * ys[k][c];
+                }
+            }
+        }
+        if (i < w) {
+#pragma unroll
+            for (int c = 0; c < NR; ++c) red[wave][c][i] = acc[c];
+        }
+    }
+}
+
+// The same lower product as tri_first + tri_rest with no early registers:
+// each wave's columns eight loads at a time (FP64 with eight right-hand
+// sides, where the early chunk would cost occupancy).
+template <class R, int NR>
+__device__ __forceinline__ void tri_lower_batched(const R* __restrict__ M, int w,
+                                                  const R (*__restrict__ ys)[NR],
+                                                  R (*__restrict__ red)[NR][kMaxWidth], int wave,
+                                                  int lane) {
+    constexpr int kB = 8;
+    for (int q = 0; q < 3; ++q) {
+        if (64 * q >= w) break;
+        const int i = 64 * q + lane;
+        const int kend = min(w, 64 * q + 64);
+        R acc[NR];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) acc[c] = R(0);
+        for (int k0 = wave; k0 < kend; k0 += 4 * kB) {
+            R lx[kB];
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                const int k = k0 + 4 * u;
+                lx[u] = (k < kend && tri_in<false>(w, i, k)) ? M[tri_at<false>(w, i, k)] : R(0);
+            }
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                if (k0 + 4 * u < kend) {
+#pragma unroll
+                    for (int c = 0; c < NR; ++c) acc[c] += lx[u] * ys[k0 + 4 * u][c];
+                }
+            }
+        }
+        if (i < w) {
+#pragma unroll
+            for (int c = 0; c < NR; ++c) red[wave][c][i] = acc[c];
+        }
+    }
+}
 
 // Forward, one level, large supernodes: one workgroup per 64-row block of a
 // supernode's rows below its diagonal block (one block when there are none):
 //   z_s = L11^{-1} y_s          as one product with the inverse the
-//                               factorization formed (packed by columns
-//                               after the panel inverses): lane = row,
-//                               wave = every 4th column, the four waves'
-//                               partial sums meet in LDS in wave order;
+//                               factorization formed (tri_first / tri_rest;
+//                               its largest chunk loaded with the block's
+//                               rows, before y_s);
 //                               every workgroup of s forms the same z_s, the
 //                               first writes it to zb (y_s itself stays: the
 //                               others still read it);
@@ -131,8 +245,7 @@ __global__ __launch_bounds__(256) void k_fwd_level(const RowBlock* __restrict__ 
                                                    R* __restrict__ y, R* __restrict__ zb,
                                                    int64_t n, int nrhs, SolveBufs<R> sb) {
     static_assert(kMaxWidth <= 192, "three 64-row chunks of the diagonal block");
-    constexpr int KW = (kMaxWidth + 3) / 4;  // columns per wave
-    constexpr int kB = 8;                    // inverse loads in flight per batch
+    constexpr int KW = kTriKW;  // columns per wave
     __shared__ R ys[kMaxWidth][NR];
     __shared__ R red[4][NR][kMaxWidth];
     const RowBlock wb = work[blockIdx.x];
@@ -145,7 +258,10 @@ __global__ __launch_bounds__(256) void k_fwd_level(const RowBlock* __restrict__ 
     const int32_t* __restrict__ below = a.rows + rp + w;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int i0 = wb.rb * kTile, m = max(0, min(kTile, r - i0));
-    auto cst = [w](int q) { return (q * (2 * w - q - 1)) >> 1; };
+    // FP64 with several right-hand sides: no early inverse chunk (occupancy)
+    constexpr bool kEarly = NR == 1 || sizeof(R) == 4;
+    R la[KW];
+    if (kEarly) tri_first<R, false>(Li, w, wave, lane, la);
     R lv[KW];
 #pragma unroll
     for (int u = 0; u < KW; ++u) {
@@ -166,35 +282,8 @@ __global__ __launch_bounds__(256) void k_fwd_level(const RowBlock* __restrict__ 
             ys[k][c] = c < nc ? y[(int64_t)(c0 + c) * n + first + k] : R(0);
         }
         __syncthreads();
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            if (64 * q >= w) break;
-            const int i = 64 * q + lane;
-            const int kend = min(w, 64 * q + 64);
-            R acc[NR];
-#pragma unroll
-            for (int c = 0; c < NR; ++c) acc[c] = R(0);
-            for (int k0 = wave; k0 < kend; k0 += 4 * kB) {
-                R lx[kB];
-#pragma unroll
-                for (int u = 0; u < kB; ++u) {
-                    const int k = k0 + 4 * u;
-                    lx[u] = (k < kend && k <= i && i < w) ? Li[cst(k) + i] : R(0);
-                }
-#pragma unroll
-                for (int u = 0; u < kB; ++u) {
-                    const int k = k0 + 4 * u;
-                    if (k < kend) {
-#pragma unroll
-                        for (int c = 0; c < NR; ++c) acc[c] += lx[u] * ys[k][c];
-                    }
-                }
-            }
-            if (i < w) {
-#pragma unroll
-                for (int c = 0; c < NR; ++c) red[wave][c][i] = acc[c];
-            }
-        }
+        if (kEarly) tri_rest<R, NR, false>(Li, w, la, ys, red, wave, lane);
+        else tri_lower_batched<R, NR>(Li, w, ys, red, wave, lane);
         __syncthreads();
         for (int e = tid; e < w * NR; e += 256) {
             const int k = e / NR, c = e % NR;
@@ -236,6 +325,26 @@ __global__ __launch_bounds__(256) void k_fwd_level(const RowBlock* __restrict__ 
         __syncthreads();
     }
 }
+
+// Matrix-core step 16 x 16 x 4 in the solve's arithmetic.  Operands: lane l
+// holds A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator register q of
+// lane l holds D[row(q, l / 16)][l % 16], row = 4q + l/16 (FP64) or
+// 4 (l/16) + q (FP32).
+template <class R> struct SMx;
+template <> struct SMx<double> {
+    typedef double acc __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc mfma(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int q, int lk) { return 4 * q + lk; }
+};
+template <> struct SMx<float> {
+    typedef float acc __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc mfma(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int q, int lk) { return 4 * lk + q; }
+};
 
 // x^T = u^T L11^{-1} on the matrix cores: x[k][c] = sum_{i >= k}
 // L11^{-1}[i][k] u[i][c], with u^T as the A operand (right-hand sides as its
@@ -384,8 +493,9 @@ __global__ __launch_bounds__(256) void k_bwd_cols(const ColBlk* __restrict__ wor
 
 // Backward, diagonal block, one workgroup per large supernode of the level:
 // t_s = the chunks' partial sums in chunk order, then
-// x_s = L11^{-T} (z_s - t_s) (inv_upper) into y, which now holds the solution
-// of every supernode done so far.
+// x_s = L11^{-T} (z_s - t_s) into y, which now holds the solution of every
+// supernode done so far: one right-hand side by tri_first / tri_rest with the
+// packed L11^{-T}, eight on the matrix cores (inv_upper).
 template <class R, int NR>
 __global__ __launch_bounds__(256) void k_bwd_diag(const int32_t* __restrict__ level_sn, KArgs a,
                                                   const R* __restrict__ dinv,
@@ -394,25 +504,341 @@ __global__ __launch_bounds__(256) void k_bwd_diag(const int32_t* __restrict__ le
                                                   const int64_t* __restrict__ pb_off,
                                                   int64_t pb_total, int64_t n, int nrhs) {
     __shared__ R us[kMaxWidth][NR];
+    __shared__ R red[4][NR][kMaxWidth];
     const int s = level_sn[blockIdx.x];
     const int w = a.sn_w[s], first = a.sn_first[s];
     const int r = (int)(a.rowptr[s + 1] - a.rowptr[s]) - w;
     const int nh = r > 0 ? (r + kRowChunk - 1) / kRowChunk : 0;
-    const R* __restrict__ Li = dinv + a.inv_off[s] + inverse_elems(w);
+    const R* __restrict__ Lt = dinv + a.inv_off[s] + inverse_elems(w) + w * (w + 1) / 2;
     const R* __restrict__ ps = pb + (r > 0 ? pb_off[s] : 0);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    R la[kTriKW];
+    if (NR == 1) tri_first<R, true>(Lt, w, wave, lane, la);
     for (int c0 = 0; c0 < nrhs; c0 += NR) {
         const int nc = min(NR, nrhs - c0);
         for (int e = tid; e < w * NR; e += 256) {
             const int k = e / NR, c = e % NR;
             R t = R(0);
-            if (c < nc)
-                for (int hh = 0; hh < nh; ++hh)
-                    t += ps[(int64_t)(c0 + c) * pb_total + (int64_t)hh * w + k];
+            if (c < nc) {
+                const R* __restrict__ pk = ps + (int64_t)(c0 + c) * pb_total + k;
+                for (int h0 = 0; h0 < nh; h0 += 8) {
+                    R v[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) v[j] = h0 + j < nh ? pk[(int64_t)(h0 + j) * w] : R(0);
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) t += v[j];
+                }
+            }
             us[k][c] = c < nc ? zb[(int64_t)(c0 + c) * n + first + k] - t : R(0);
         }
         __syncthreads();
-        inv_upper<R, NR>(Li, w, us, y, n, first, c0, nc, wave, lane);
+        if (NR == 1) {
+            tri_rest<R, NR, true>(Lt, w, la, us, red, wave, lane);
+            __syncthreads();
+            for (int e = tid; e < w * NR; e += 256) {
+                const int k = e / NR, c = e % NR;
+                if (c < nc)
+                    y[(int64_t)(c0 + c) * n + first + k] =
+                        (red[0][c][k] + red[1][c][k]) + (red[2][c][k] + red[3][c][k]);
+            }
+        } else {
+            // eight right-hand sides fill half of the matrix-core operand
+            inv_upper<R, NR>(Lt - w * (w + 1) / 2, w, us, y, n, first, c0, nc, wave, lane);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the tail of the elimination tree: both sweeps in one persistent launch
+// ---------------------------------------------------------------------------
+//
+// The top levels of a nested-dissection tree hold few supernodes each (the
+// 64^3 problem: 73 of its 82 levels hold at most 103, the last 29 one each),
+// and each level costs a few dependent launches whatever its work.  Those
+// levels run instead as tasks of one launch: workgroups take tasks in a
+// fixed topological order by an atomic ticket and wait on dependency
+// counters before running them, the counters of the paper's task queue
+// (Section IV) applied to the two solves:
+//   F(t)     forward, diagonal block: waits until every row of t has its
+//            updates from the tail's sources (turn[t] == rows updated), then
+//            z_t = L11^{-1} y_t in place, sets ready[t];
+//   R(s, b)  forward, 64-row block b below source s: its part of L21 is loaded
+//            before the wait on ready[s], then y[rows] -= L21[b] z_s by atomic
+//            adds, and each target's count (turn) grows by the block's rows
+//            in it;
+//   C(s, b)  backward, 64-row block b below s: its part of L21 is loaded
+//            before it waits for the solution of every supernode its rows
+//            belong to; writes the block's partial sums of L21^T x[rows] (one
+//            writer per entry) and counts itself in cntB[s];
+//   B(s)     backward, diagonal block: waits for ready[s] and all its C
+//            blocks, then
+//            x_s = L11^{-T} (z_s - the partial sums in block order) in place,
+//            sets done[s].
+// The forward updates of a row from several sources land in arrival order
+// (the atomic contribution order: equal to rounding from run to run; the
+// deterministic order sweeps these levels one by one instead).  A worker takes its next ticket only after its task is done, and a
+// task waits only on tasks of smaller tickets, so the lowest unfinished
+// ticket can always run: no deadlock for any number of resident workers.
+// Every wait is bounded: past the deadline the worker sets the error and
+// abort words, and every worker leaves at its next wait.
+//
+// State (int32, zeroed before each launch): turn, ready, cntB, done (one per
+// tail supernode), then ticket, abort, error.
+
+// Data that one task writes and another reads in the same launch (y, z, x,
+// the partial sums) is stored and loaded at device scope, coherent across the
+// eight XCDs' L2 caches without a cache writeback or invalidation: a signal
+// follows its task's stores once they are complete (s_waitcnt, then the
+// workgroup barrier), and a waiter loads the data only after it has seen the
+// signal.  Acquire/release fences would write back or invalidate a whole L2
+// on every task, which costs more than the solve's work.
+template <class T>
+__device__ __forceinline__ T ld_dev(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ void st_dev(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bounded wait of one thread until *p == want (device-scope polls).
+__device__ __forceinline__ bool tail_wait(const int32_t* p, int32_t want, int32_t* ctrl,
+                                          uint64_t deadline) {
+    for (;;) {
+        if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == want) return true;
+        if (__hip_atomic_load(ctrl + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+        if (wall_clock64() > deadline) {
+            __hip_atomic_store(ctrl + 2, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(ctrl + 1, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+__global__ void k_tail_reset(int32_t* __restrict__ state, int64_t words) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+         i += (int64_t)gridDim.x * blockDim.x)
+        state[i] = 0;
+}
+
+template <class R, int NR>
+__global__ __launch_bounds__(256, 2) void k_tail(const TailTask* __restrict__ tasks, int64_t ntasks,
+                                              const TailSeg* __restrict__ segs, KArgs a,
+                                              const R* __restrict__ arena,
+                                              const R* __restrict__ dinv, R* __restrict__ y,
+                                              R* __restrict__ pb,
+                                              const int64_t* __restrict__ pb_off,
+                                              int64_t pb_total, int64_t n, int nrhs,
+                                              int32_t* __restrict__ state, int32_t ntail,
+                                              uint64_t wait_ticks) {
+    static_assert(kMaxWidth <= 192, "three 64-lane column sets");
+    constexpr int KW = kTriKW;  // columns per wave
+    __shared__ R ys[kMaxWidth][NR];
+    __shared__ R red[4][NR][kMaxWidth];
+    __shared__ int32_t sh_ticket, sh_ok;
+    int32_t* turn = state;
+    int32_t* ready = turn + ntail;
+    int32_t* cntB = ready + ntail;
+    int32_t* done = cntB + ntail;
+    int32_t* ctrl = done + ntail;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (;;) {
+        if (tid == 0) sh_ticket = atomicAdd(ctrl, 1);
+        __syncthreads();
+        const int32_t t = sh_ticket;
+        if (t >= ntasks) break;
+        const TailTask tk = tasks[t];
+        const int s = tk.s;
+        const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
+        const int64_t rp = a.rowptr[s];
+        const int r = (int)(a.rowptr[s + 1] - rp) - w;
+        const R* __restrict__ P = arena + a.sn_off[s] + w;  // rows below the diagonal block
+        const R* __restrict__ Li = dinv + a.inv_off[s] + inverse_elems(w);
+        const int32_t* __restrict__ below = a.rows + rp + w;
+        const uint64_t deadline = wall_clock64() + wait_ticks;
+        if (tk.kind == kTailR) {
+            const int i0 = tk.rb * kTile, m = min(kTile, r - i0);
+            R lv[KW];
+#pragma unroll
+            for (int u = 0; u < KW; ++u) {
+                const int k = wave + 4 * u;
+                lv[u] = (lane < m && k < w) ? P[i0 + lane + (int64_t)k * ld] : R(0);
+            }
+            const int32_t row = lane < m ? below[i0 + lane] : 0;
+            if (tid == 0) sh_ok = tail_wait(ready + tk.u, 1, ctrl, deadline);
+            __syncthreads();
+            if (!sh_ok) break;
+            for (int c0 = 0; c0 < nrhs; c0 += NR) {
+                const int nc = min(NR, nrhs - c0);
+                for (int e = tid; e < w * NR; e += 256) {
+                    const int k = e / NR, c = e % NR;
+                    ys[k][c] = c < nc ? ld_dev(y + (int64_t)(c0 + c) * n + first + k) : R(0);
+                }
+                __syncthreads();
+                R acc[NR];
+#pragma unroll
+                for (int c = 0; c < NR; ++c) acc[c] = R(0);
+#pragma unroll
+                for (int u = 0; u < KW; ++u) {
+                    const int k = wave + 4 * u;
+                    if (k < w) {
+#pragma unroll
+                        for (int c = 0; c < NR; ++c) acc[c] += lv[u] * ys[k][c];
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < NR; ++c) red[wave][c][lane] = acc[c];
+                __syncthreads();
+                if (tid < m) {
+#pragma unroll
+                    for (int c = 0; c < NR; ++c) {
+                        if (c >= nc) break;
+                        const R v = (red[0][c][tid] + red[1][c][tid]) +
+                                    (red[2][c][tid] + red[3][c][tid]);
+                        unsafeAtomicAdd(y + (int64_t)(c0 + c) * n + row, -v);
+                    }
+                }
+                __syncthreads();
+            }
+            __builtin_amdgcn_s_waitcnt(0);  // this thread's stores and adds are done
+            __syncthreads();
+            if (tid == 0)
+                for (int32_t q = tk.a; q < tk.b; ++q)
+                    __hip_atomic_fetch_add(turn + segs[q].u, segs[q].hi - segs[q].lo,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (tk.kind == kTailF) {
+            // z = L11^{-1} y_s (tri_first before the wait, tri_rest after)
+            R la[KW];
+            tri_first<R, false>(Li, w, wave, lane, la);
+            if (tid == 0) sh_ok = tk.a == 0 || tail_wait(turn + tk.u, tk.a, ctrl, deadline);
+            __syncthreads();
+            if (!sh_ok) break;
+            for (int c0 = 0; c0 < nrhs; c0 += NR) {
+                const int nc = min(NR, nrhs - c0);
+                for (int e = tid; e < w * NR; e += 256) {
+                    const int k = e / NR, c = e % NR;
+                    ys[k][c] = c < nc ? ld_dev(y + (int64_t)(c0 + c) * n + first + k) : R(0);
+                }
+                __syncthreads();
+                tri_rest<R, NR, false>(Li, w, la, ys, red, wave, lane);
+                __syncthreads();
+                for (int e = tid; e < w * NR; e += 256) {
+                    const int k = e / NR, c = e % NR;
+                    if (c < nc)
+                        st_dev(y + (int64_t)(c0 + c) * n + first + k,
+                               (red[0][c][k] + red[1][c][k]) + (red[2][c][k] + red[3][c][k]));
+                }
+                __syncthreads();
+            }
+            __builtin_amdgcn_s_waitcnt(0);  // this thread's stores and adds are done
+            __syncthreads();
+            if (tid == 0)
+                __hip_atomic_store(ready + tk.u, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (tk.kind == kTailC) {
+            // lane = column (three 64-column sets), wave = 16 rows of the block
+            const int i0 = tk.rb * kTile, m = min(kTile, r - i0);
+            R pv[3][16];
+#pragma unroll
+            for (int cs = 0; cs < 3; ++cs) {
+                const int k = lane + 64 * cs;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const int i = 16 * wave + j;
+                    pv[cs][j] = (i < m && k < w) ? P[i0 + i + (int64_t)k * ld] : R(0);
+                }
+            }
+            if (tid == 0) {
+                bool g = true;
+                for (int32_t q = tk.a; q < tk.b && g; ++q)
+                    g = tail_wait(done + segs[q].u, 1, ctrl, deadline);
+                sh_ok = g;
+            }
+            __syncthreads();
+            if (!sh_ok) break;
+            R* __restrict__ out = pb + pb_off[s] + (int64_t)tk.rb * w;
+            for (int c0 = 0; c0 < nrhs; c0 += NR) {
+                const int nc = min(NR, nrhs - c0);
+                for (int e = tid; e < kTile * NR; e += 256) {
+                    const int i = e / NR, c = e % NR;
+                    ys[i][c] = (i < m && c < nc) ? ld_dev(y + (int64_t)(c0 + c) * n + below[i0 + i])
+                                                 : R(0);
+                }
+                __syncthreads();
+#pragma unroll
+                for (int cs = 0; cs < 3; ++cs) {
+                    R acc[NR];
+#pragma unroll
+                    for (int c = 0; c < NR; ++c) acc[c] = R(0);
+#pragma unroll
+                    for (int j = 0; j < 16; ++j)
+#pragma unroll
+                        for (int c = 0; c < NR; ++c) acc[c] += pv[cs][j] * ys[16 * wave + j][c];
+                    if (lane + 64 * cs < w) {
+#pragma unroll
+                        for (int c = 0; c < NR; ++c) red[wave][c][lane + 64 * cs] = acc[c];
+                    }
+                }
+                __syncthreads();
+                for (int e = tid; e < w * NR; e += 256) {
+                    const int k = e / NR, c = e % NR;
+                    if (c < nc)
+                        st_dev(out + (int64_t)(c0 + c) * pb_total + k,
+                               (red[0][c][k] + red[1][c][k]) + (red[2][c][k] + red[3][c][k]));
+                }
+                __syncthreads();
+            }
+            __builtin_amdgcn_s_waitcnt(0);  // this thread's stores and adds are done
+            __syncthreads();
+            if (tid == 0)
+                __hip_atomic_fetch_add(cntB + tk.u, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {  // kTailB
+            // x = L11^{-T} (z_s - t_s) (tri_first before the wait, tri_rest after)
+            const R* __restrict__ Lt = Li + w * (w + 1) / 2;
+            R la[KW];
+            tri_first<R, true>(Lt, w, wave, lane, la);
+            // z_s written (a root has no C block to order it), then its C blocks
+            if (tid == 0)
+                sh_ok = tail_wait(ready + tk.u, 1, ctrl, deadline) &&
+                        (tk.a == 0 || tail_wait(cntB + tk.u, tk.a, ctrl, deadline));
+            __syncthreads();
+            if (!sh_ok) break;
+            const R* __restrict__ ps = pb + pb_off[s];
+            for (int c0 = 0; c0 < nrhs; c0 += NR) {
+                const int nc = min(NR, nrhs - c0);
+                for (int e = tid; e < w * NR; e += 256) {
+                    const int k = e / NR, c = e % NR;
+                    R tsum = R(0);
+                    if (c < nc) {
+                        const R* __restrict__ pk = ps + (int64_t)(c0 + c) * pb_total + k;
+                        for (int h0 = 0; h0 < tk.a; h0 += 8) {
+                            R v[8];
+#pragma unroll
+                            for (int j = 0; j < 8; ++j)
+                                v[j] = h0 + j < tk.a ? ld_dev(pk + (int64_t)(h0 + j) * w) : R(0);
+#pragma unroll
+                            for (int j = 0; j < 8; ++j) tsum += v[j];
+                        }
+                    }
+                    ys[k][c] = c < nc ? ld_dev(y + (int64_t)(c0 + c) * n + first + k) - tsum : R(0);
+                }
+                __syncthreads();
+                tri_rest<R, NR, true>(Lt, w, la, ys, red, wave, lane);
+                __syncthreads();
+                for (int e = tid; e < w * NR; e += 256) {
+                    const int k = e / NR, c = e % NR;
+                    if (c < nc)
+                        st_dev(y + (int64_t)(c0 + c) * n + first + k,
+                               (red[0][c][k] + red[1][c][k]) + (red[2][c][k] + red[3][c][k]));
+                }
+                __syncthreads();
+            }
+            __builtin_amdgcn_s_waitcnt(0);  // this thread's stores and adds are done
+            __syncthreads();
+            if (tid == 0)
+                __hip_atomic_store(done + tk.u, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         __syncthreads();
     }
 }
@@ -438,7 +864,7 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* work, hipStream_t st) {
     R* cb = zb + n * nrhs;
     R* pb = cb + P->nslots * nrhs;
     const SolveBufs<R> sb{cb, P->nslots, P->slot_shared};
-    const int32_t nl = (int32_t)S.level_ptr.size() - 1;
+    const int32_t nl = P->tail_l0;  // levels below the tail go level by level
     for (int32_t l = 0; l < nl; ++l) {
         const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1], nbig = P->level_nbig[l];
         launch_small_solve(num, a, P->level_sn + n0 + nbig, n1 - n0 - nbig, P->small_maxw[l],
@@ -454,6 +880,27 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* work, hipStream_t st) {
                                dim3(256), 0, st, P->red_row + i0, P->red_ptr + i0,
                                (const int32_t*)P->red_slot, i1 - i0, y, n, nrhs, sb);
         }
+    }
+    if (P->ntail_tasks > 0) {
+        int32_t* state = (int32_t*)(pb + P->pb_total * nrhs);
+        const int64_t words = 4 * (int64_t)P->ntail + 4;
+        hipLaunchKernelGGL(k_tail_reset, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, st,
+                           state, words);
+        int per_cu = 0, ncu = 0, dev = 0, clock_khz = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tail<R, NR>, 256, 0);
+        const int64_t workers = std::min<int64_t>(
+            P->ntail_tasks, (int64_t)std::max(1, ncu) * std::max(1, per_cu));
+        const int64_t lim = S.opt.spin_limit > 0 ? S.opt.spin_limit : (int64_t)10000000;
+        const uint64_t ticks = (uint64_t)lim *
+                               (uint64_t)std::max(1, clock_khz) / 1000;
+        hipLaunchKernelGGL((k_tail<R, NR>), dim3((unsigned)workers), dim3(256), 0, st,
+                           (const TailTask*)P->tail_tasks, P->ntail_tasks,
+                           (const TailSeg*)P->tail_segs, a, arena, dinv, y, pb,
+                           (const int64_t*)P->pb_off, P->pb_total, n, nrhs, state, P->ntail,
+                           ticks);
     }
     for (int32_t l = nl - 1; l >= 0; --l) {
         const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1], nbig = P->level_nbig[l];
@@ -483,16 +930,18 @@ void drop_solve_graphs(spc_numeric* num) {
     num->solve_graphs.clear();
 }
 
+// y, z, contribution slots and partial sums per right-hand side, then the
+// tail's task state (int32 words, rounded up to whole elements of 4 bytes or
+// more).
 int64_t solve_work_elems(const spc_numeric* num, int32_t nrhs) {
-    return solve_work_elems_per_rhs(num->sym->S) * (int64_t)nrhs;
+    const Symbolic& S = num->sym->S;
+    const int64_t words = tail_state_words(S);
+    const int64_t esz = num->prec == 1 ? 4 : 8;
+    return solve_work_elems_per_rhs(S) * (int64_t)nrhs + (words * 4 + esz - 1) / esz;
 }
 
 int64_t solve_work_elems_per_rhs(const Symbolic& S) {
-    int64_t pb = 0;
-    for (int64_t s = 0; s < S.nsup; ++s)
-        if (!is_small(S, s) && S.nbelow(s) > 0)
-            pb += (int64_t)((S.nbelow(s) + kRowChunk - 1) / kRowChunk) * S.width(s);
-    return 2 * S.n + (int64_t)S.rows.size() + pb;  // y, z, slots, partial sums
+    return 2 * S.n + (int64_t)S.rows.size() + solve_pb_elems(S);  // y, z, slots, partial sums
 }
 
 // Solve work for nrhs right-hand sides (factor type): the vectors y and z

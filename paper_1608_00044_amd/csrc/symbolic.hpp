@@ -26,6 +26,7 @@ struct Options {
     int32_t small_r = 64;     // below run on the lane-group kernels (small_w 0: none)
     int32_t deterministic = 1; // fixed order of the contributions to every target
     int32_t workers = 0;      // sched 2: persistent workgroups (0 = full occupancy)
+    int32_t solve_tail = 0;   // 1: the solves' top levels in one persistent launch; 0: off
 };
 
 // One (source, target) update pair: source supernode s sends its update block

@@ -387,3 +387,38 @@ def test_fig2_task_graph(workers):
     # F(s) = (0, s, 0, 0); T(s, 0) = (1, s, 0, 0); U(s, 0, 0) = (2, s, 0, 0)
     assert order == [(0, j, 0, 0), (1, j, 0, 0), (2, j, 0, 0), (0, i, 0, 0), (1, i, 0, 0),
                      (2, i, 0, 0), (0, h, 0, 0)]
+
+
+def test_solve_tail_levels():
+    """The solves' persistent launch covers the top levels of the supernodal
+    elimination tree: only when asked for (solve_tail=1) and in the atomic
+    order; every level it covers holds at most 128 supernodes and no small
+    one, and the level below it does not (or there is none)."""
+    p = inputs.make_grid_problem("lap", (16, 16, 16), 3, sigma=1.0, shift=1e-6, nrhs=1)
+    kw = dict(sn_cap=16, amalg_ratio=0.0, small_w=-1)
+    assert spchol.analyze(p.n, p.colptr, p.rowind, p.perm, **kw).info()["tail_levels"] == 0
+    assert spchol.analyze(p.n, p.colptr, p.rowind, p.perm, solve_tail=1,
+                          **kw).info()["tail_levels"] == 0  # deterministic order
+    with pytest.raises(spchol.SpcError):
+        spchol.analyze(p.n, p.colptr, p.rowind, p.perm, solve_tail=2, **kw)
+    for kw2 in (kw, dict(sn_cap=150, amalg_ratio=0.1)):
+        sym = spchol.analyze(p.n, p.colptr, p.rowind, p.perm, solve_tail=1, deterministic=0,
+                             **kw2)
+        info = sym.info()
+        _, _, sp, spar = sym.export()
+        rp, _ = sym.rows()
+        w, r = np.diff(sp), np.diff(rp) - np.diff(sp)
+        small = (w <= (16 if kw2.get("small_w", 0) == 0 else 0)) & (r <= 64)
+        lev = np.zeros(len(spar), dtype=np.int64)
+        for s in range(len(spar)):
+            if spar[s] >= 0:
+                lev[spar[s]] = max(lev[spar[s]], lev[s] + 1)
+        nl = int(lev.max()) + 1
+        assert info["nlevels"] == nl
+        l0 = nl - info["tail_levels"]
+        ok = [np.sum(lev == l) <= 128 and not small[lev == l].any() for l in range(nl)]
+        if info["tail_levels"]:
+            assert all(ok[l0:]) and (l0 == 0 or not ok[l0 - 1])
+            assert info["tail_supernodes"] == int(np.sum(lev >= l0))
+        else:
+            assert nl - (np.argmin(ok[::-1]) if not all(ok) else nl) < 2
