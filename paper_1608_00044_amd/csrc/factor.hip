@@ -937,14 +937,12 @@ __global__ void k_sched_reset(const int32_t* __restrict__ cnt0, int32_t* __restr
         state[i] = i < nsup ? cnt0[i] : 0;
 }
 
-__device__ __forceinline__ int32_t load_acquire(const int32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Bounded wait of one thread until *p == want.  Returns false on abort.
+// Bounded wait of one thread until *p == want.  Returns false on abort.  The
+// polls are relaxed (an acquiring load invalidates the caches on every poll);
+// the caller acquires once, after the last wait.
 __device__ bool wait_eq(const int32_t* p, int32_t want, int32_t* ctrl, uint64_t deadline) {
     for (;;) {
-        if (load_acquire(p) == want) return true;
+        if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == want) return true;
         if (__hip_atomic_load(ctrl + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
         if (wall_clock64() > deadline) {
             __hip_atomic_store(ctrl + 2, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -991,13 +989,16 @@ __global__ __launch_bounds__(kSchedThreads) void k_sched(
                 }
                 if (!ok) t = -1;
                 else if (log) log[2 * (int64_t)t] = atomicAdd(ctrl + 3, 1);
+                // acquire, once per task: the L1 of this CU and the lines of
+                // this XCD's L2 that other XCDs may have written are invalidated
+                // before any wave of the workgroup reads the task's inputs
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             sh_ticket = t;
         }
         __syncthreads();
         const int32_t t = sh_ticket;
         if (t < 0 || t >= ntasks) break;
-        __threadfence();  // acquire for every wave: inputs written by other workers
         const Task tk = tasks[t];
         if (tk.kind == kTaskF) {
             diag_factor(tk.s, a, arena, dinv, status, status + 1, T);
@@ -1006,20 +1007,24 @@ __global__ __launch_bounds__(kSchedThreads) void k_sched(
         } else {
             update_task<R>(UpdTile{tk.s, tk.a, tk.b}, a, nullptr, arena, coltgt);
         }
-        __threadfence();  // release: this task's results before its signal
+        // release, once per task: every wave's stores and adds have reached
+        // this XCD's L2 (s_waitcnt, then the barrier); one write-back of that
+        // L2 then makes them visible to every XCD before the signal
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
+        if (tid == 0) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         if (log && tid == 0) log[2 * (int64_t)t + 1] = atomicAdd(ctrl + 3, 1);
         if (tk.kind == kTaskF) {
             if (tid == 0)
-                __hip_atomic_store(doneF + tk.s, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(doneF + tk.s, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else if (tk.kind == kTaskT) {
             if (tid == 0)
-                __hip_atomic_store(doneT + rb_base[tk.s] + tk.a, 1, __ATOMIC_RELEASE,
+                __hip_atomic_store(doneT + rb_base[tk.s] + tk.a, 1, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
         } else if (tid < kTile) {
             const int tg = coltgt[tid];
             if (tg >= 0 && (tid == 0 || coltgt[tid - 1] != tg))
-                __hip_atomic_fetch_add(cntF + tg, -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(cntF + tg, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();
     }
