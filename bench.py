@@ -482,8 +482,12 @@ def mixed_precision(name, steps, warmup, tol=1e-10, deterministic=0):
     return out
 
 
+TUNE_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1608_00044_amd",
+                          "tuned_batch.json")
+
+
 def batched(count, steps, precision, tol=1e-10, tune_options=True, options=None,
-            deterministic=0):
+            deterministic=0, launch_form_sample=200, retune=False, cache=TUNE_CACHE):
     """Batch of independent 2D Laplacians (BATCH_RECIPE): the analysis options
     tuned on this batch (amalgamation ratio, cap), one batched analysis, then
     timed steps of factorization + one-RHS solve (FP64) or factorization +
@@ -500,11 +504,16 @@ def batched(count, steps, precision, tol=1e-10, tune_options=True, options=None,
     vals = torch.from_numpy(vals_h).to("cuda:0")
     b = torch.from_numpy(np.ascontiguousarray(rhs_h)).to("cuda:0")
     base = dict(tune.BASE, deterministic=deterministic)
-    opts, table = dict(base, **(options or {})), None
+    opts, table, tuned = dict(base, **(options or {})), None, None
     if tune_options:
         t0 = time.perf_counter()
-        opts, table = tune.tune_batch(mats, vals, b, precision, base=base)
-        log("batch tuning (%.1f s): %s" % (time.perf_counter() - t0, opts))
+        opts, table = tune.tune_batch(mats, vals, b, precision, base=base,
+                                      cache_path=cache, retune=retune)
+        tuned = "timed in this run" if table is not None else \
+            "cached choice of an earlier timed run (%s)" % os.path.basename(cache)
+        if table is None:
+            table = tune.cached_table(mats, precision, cache)
+        log("batch tuning (%.1f s, %s): %s" % (time.perf_counter() - t0, tuned, opts))
     t0 = time.perf_counter()
     sym = spchol.analyze_batch(mats, precision=precision, **opts)
     an_ms = (time.perf_counter() - t0) * 1e3
@@ -546,15 +555,59 @@ def batched(count, steps, precision, tol=1e-10, tune_options=True, options=None,
            "launches": "level-set launches over all matrices at once",
            "options": opts}
     if table is not None:
-        out["tuning"] = [dict(t["options"], stage=t["stage"], ms=t["ms"], nsup=t["nsup"],
-                              levels=t["levels"]) for t in table]
+        out["tuning"] = [dict(t["options"], stage=t["stage"], ms=t["ms"], nsup=t.get("nsup"),
+                              levels=t.get("levels")) for t in table]
+        out["tuning_source"] = tuned
     if precision == 1:
         out["refine_iters"] = float(np.mean(iters))
     log("batch %s: factor %.2f ms (%.1f GFLOP/s), solve %.2f ms, %.0f matrices/s" %
         (out["precision"], fm, out["factor_gflops"], sm, out["matrices_per_s"]))
     num.free()
     sym.free()
+    if precision == 0 and launch_form_sample > 0:
+        out["launch_forms"] = launch_forms(mats[:launch_form_sample],
+                                           vals[:sum(int(m[1][int(m[0])]) for m in
+                                                     mats[:launch_form_sample])],
+                                           opts, steps)
     return out
+
+
+def launch_forms(mats, vals, opts, steps):
+    """The batch's factorization in its two launch forms on the same members
+    and options: level-set launches over all matrices at once (sched 0, the
+    lane-group kernels for small supernodes) against one persistent
+    task-queue launch (sched 2, Section IV's counters; every supernode a
+    workgroup task, atomic contribution order)."""
+    import torch
+
+    from paper_1608_00044_amd import spchol
+
+    res = {"matrices": len(mats)}
+    for name, extra in (("level_sets", dict(sched=0, deterministic=0)),
+                        ("task_queue", dict(sched=2, deterministic=0))):
+        t0 = time.perf_counter()
+        sym = spchol.analyze_batch(mats, **dict(opts, **extra))
+        num = spchol.factor(sym, vals)
+        torch.cuda.synchronize()
+        prep = time.perf_counter() - t0
+        if num.status() != 0:
+            raise RuntimeError("%s factor status %d" % (name, num.status()))
+        ms = []
+        for _ in range(max(1, steps)):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            num.refactor(vals)
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        res[name + "_factor_ms"] = float(np.mean(ms))
+        res[name + "_setup_s"] = prep
+        num.free()
+        sym.free()
+    res["winner"] = min(("level_sets", "task_queue"), key=lambda k: res[k + "_factor_ms"])
+    log("batch launch forms on %d matrices: level sets %.2f ms, task queue %.2f ms" %
+        (len(mats), res["level_sets_factor_ms"], res["task_queue_factor_ms"]))
+    return res
 
 
 SERVE_RECIPE = dict(rate=200.0, patterns_2d=16, patterns_3d=16, side2d=(32, 256),
@@ -673,6 +726,12 @@ def main():
     ap.add_argument("--batch-options", default=None,
                     help="JSON dict of analysis options for the batched workload "
                          "(e.g. '{\"amalg_ratio\": 0.2}'), used as given, no tuning")
+    ap.add_argument("--retune", action="store_true",
+                    help="time the batch autotuner's candidates again and store the "
+                         "choices in paper_1608_00044_amd/tuned_batch.json (default: "
+                         "use the stored choice of the batch's size class, if any)")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE,
+                    help="the autotuner's JSON cache of choices per size class")
     ap.add_argument("--no-batch-tune", action="store_true",
                     help="batched workload with the default options (no amalgamation) "
                          "instead of the tuned ones")
@@ -893,7 +952,9 @@ def main():
         tb = not args.no_batch_tune and not args.batch_options
         fixed = json.loads(args.batch_options) if args.batch_options else None
         out["batched"] = [batched(args.batch, 3, prec, tune_options=tb, options=fixed,
-                                  deterministic=args.deterministic) for prec in (0, 1)]
+                                  deterministic=args.deterministic, retune=args.retune,
+                                  cache=args.tune_cache)
+                          for prec in (0, 1)]
     if args.serve_requests:
         out["serving"] = serving(args.serve_requests)
     if leg is not None:

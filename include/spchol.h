@@ -118,6 +118,12 @@ typedef struct spc_options {
                                  which measures faster on MI355X (a task's
                                  signal costs a device-scope memory round trip,
                                  about as much as a launch)                     */
+    int32_t upd_chunk;        /* update tiles (Section III-A, U and A tasks):
+                                 columns of the source panel staged through LDS
+                                 per step, 8, 16 or 32; 0 = default (16).  A
+                                 tile shape the batch autotuner searches; every
+                                 value computes the same products in the same
+                                 order                                          */
 } spc_options;
 
 typedef struct spc_symbolic spc_symbolic;

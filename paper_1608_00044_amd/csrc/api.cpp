@@ -79,6 +79,8 @@ spc_status analyze_checked(const spc_options* opt, spc_symbolic** out, Run run) 
     if (o.deterministic && o.sched == 2) return SPC_ERR_ARG;  // the queue's order is dynamic
     if (o.workers < 0) return SPC_ERR_ARG;
     if (o.solve_tail != 0 && o.solve_tail != 1) return SPC_ERR_ARG;
+    if (o.upd_chunk != 0 && o.upd_chunk != 8 && o.upd_chunk != 16 && o.upd_chunk != 32)
+        return SPC_ERR_ARG;
     spc_symbolic* h = new (std::nothrow) spc_symbolic();
     if (!h) return SPC_ERR_OOM;
     Options so;
@@ -93,6 +95,7 @@ spc_status analyze_checked(const spc_options* opt, spc_symbolic** out, Run run) 
     so.deterministic = o.deterministic;
     so.workers = o.workers;
     so.solve_tail = o.solve_tail;
+    so.upd_chunk = o.upd_chunk == 0 ? 16 : o.upd_chunk;
     int32_t st;
     try {
         st = run(so, o.threads, &h->S);
@@ -128,6 +131,7 @@ void spc_default_options(spc_options* opt) {
     opt->deterministic = 1;
     opt->workers = 0;
     opt->solve_tail = 0;
+    opt->upd_chunk = 0;
 }
 
 const char* spc_status_string(spc_status st) {

@@ -713,7 +713,9 @@ static_assert(kMaxWidth <= 10 * kPanel, "k_trsm instantiates at most 10 panels")
 // U + A: update tiles on FP64 MFMA with relative-index scatter
 // ---------------------------------------------------------------------------
 
-constexpr int kChunk = 16;             // K columns staged per step
+// K columns staged per step: 16 by default; 8 or 32 by the analysis option
+// upd_chunk (one of the tile shapes the batch autotuner searches).
+constexpr int kChunkDefault = 16;
 constexpr int kLdsStride = kTile + 2;  // padded row count of a staged K column
 constexpr int kCtPad = kTile + 1;
 
@@ -749,7 +751,7 @@ enum { kAtomic = 0, kRound = 1, kScratch = 2 };
 // others atomic adds (kAtomic), plain read-modify-writes (kRound), or stores
 // of the negated entry to the source's packed block in the scratch at
 // scr_off[s] (kScratch; column c, row i >= c at c (2r - c + 1) / 2 + i - c).
-template <class R, int kMode = kAtomic>
+template <class R, int kMode = kAtomic, int kChunk = kChunkDefault>
 __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
                                             const uint8_t* __restrict__ pair_excl,
                                             R* __restrict__ arena, int* coltgt,
@@ -895,14 +897,21 @@ __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
     }
 }
 
-template <class R, int kMode>
+template <class R, int kMode, int kChunk>
 __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tiles, int64_t ntiles,
                                                 KArgs a, const uint8_t* __restrict__ pair_excl,
                                                 R* __restrict__ arena,
                                                 const int64_t* __restrict__ scr_off,
                                                 R* __restrict__ scratch) {
-    update_task<R, kMode>(tiles[xcd_tile(blockIdx.x, ntiles)], a, pair_excl, arena, nullptr,
-                          scr_off, scratch);
+    update_task<R, kMode, kChunk>(tiles[xcd_tile(blockIdx.x, ntiles)], a, pair_excl, arena,
+                                  nullptr, scr_off, scratch);
+}
+
+// The k_update instance of a scatter form and K chunk.
+template <class R, int kMode>
+auto update_kernel(int chunk) {
+    return chunk == 8 ? k_update<R, kMode, 8>
+                      : (chunk == 32 ? k_update<R, kMode, 32> : k_update<R, kMode, 16>);
 }
 
 // ---------------------------------------------------------------------------
@@ -1118,7 +1127,8 @@ void launch_update(spc_numeric* num, const DevicePlan* P, const KArgs& a, int64_
         for (size_t r = 0; r + 1 < rp.size(); ++r) {
             if (rp[r + 1] <= rp[r]) continue;
             const int ev = mark_begin(num, st);
-            auto kern = apply ? k_update<R, kScratch> : k_update<R, kRound>;
+            const int ch = num->sym->S.opt.upd_chunk;
+            auto kern = apply ? update_kernel<R, kScratch>(ch) : update_kernel<R, kRound>(ch);
             hipLaunchKernelGGL(kern, dim3((unsigned)(rp[r + 1] - rp[r])), dim3(256), 0, st,
                                P->tiles + rp[r], rp[r + 1] - rp[r], a,
                                (const uint8_t*)P->pair_excl, (R*)num->arena,
@@ -1134,7 +1144,8 @@ void launch_update(spc_numeric* num, const DevicePlan* P, const KArgs& a, int64_
     }
     if (u1 <= u0) return;
     const int ev = mark_begin(num, st);
-    hipLaunchKernelGGL((k_update<R, kAtomic>), dim3((unsigned)(u1 - u0)), dim3(256), 0, st,
+    auto kern = update_kernel<R, kAtomic>(num->sym->S.opt.upd_chunk);
+    hipLaunchKernelGGL(kern, dim3((unsigned)(u1 - u0)), dim3(256), 0, st,
                        P->tiles + u0, u1 - u0, a,
                        exclusive_ok ? (const uint8_t*)P->pair_excl : nullptr, (R*)num->arena,
                        (const int64_t*)nullptr, (R*)nullptr);

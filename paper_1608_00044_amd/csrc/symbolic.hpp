@@ -27,6 +27,7 @@ struct Options {
     int32_t deterministic = 1; // fixed order of the contributions to every target
     int32_t workers = 0;      // sched 2: persistent workgroups (0 = full occupancy)
     int32_t solve_tail = 0;   // 1: the solves' top levels in one persistent launch; 0: off
+    int32_t upd_chunk = 16;   // K columns the update tiles stage per step: 8, 16 or 32
 };
 
 // One (source, target) update pair: source supernode s sends its update block

@@ -48,7 +48,7 @@ class spc_options(C.Structure):
                 ("mem_budget_bytes", C.c_int64), ("spin_limit", C.c_int64),
                 ("debug_flags", C.c_int32), ("precision", C.c_int32), ("threads", C.c_int32),
                 ("small_w", C.c_int32), ("small_r", C.c_int32), ("deterministic", C.c_int32),
-                ("workers", C.c_int32), ("solve_tail", C.c_int32)]
+                ("workers", C.c_int32), ("solve_tail", C.c_int32), ("upd_chunk", C.c_int32)]
 
 
 class spc_symbolic_info(C.Structure):
@@ -214,7 +214,7 @@ def _stream_ptr(stream):
 
 def _options(sn_cap=150, amalg_ratio=0.0, sched=0, mem_budget_bytes=0, spin_limit=0,
              debug_flags=0, precision=0, threads=0, small_w=0, small_r=0, deterministic=None,
-             workers=0, solve_tail=0):
+             workers=0, solve_tail=0, upd_chunk=0):
     """spc_options; deterministic=None takes the library's default (1), except
     with sched 2, which needs 0."""
     opt = spc_options()
@@ -235,6 +235,7 @@ def _options(sn_cap=150, amalg_ratio=0.0, sched=0, mem_budget_bytes=0, spin_limi
         opt.deterministic = 0
     opt.workers = int(workers)
     opt.solve_tail = int(solve_tail)
+    opt.upd_chunk = int(upd_chunk)
     return opt
 
 

@@ -10,7 +10,10 @@ matrices' size and sparsity:
 - the supernode cap;
 - which supernodes run on the lane-group kernels (16, 32 or 64 lanes per
   supernode, several supernodes per wave) and which on the workgroup
-  kernels over 64 x 64 tiles (the small_w / small_r limits).
+  kernels over 64 x 64 tiles (the small_w / small_r limits);
+- the update tiles' shape: the columns of the source panel staged through
+  LDS per step (8, 16 or 32: fewer steps against less LDS, and so more
+  tiles resident per CU).
 The tuner searches them one stage at a time (each stage starting from the
 best options so far), timing every option set on the GPU through the
 library's own entry points: one factorization plus one solve (FP64) or one
@@ -32,12 +35,13 @@ import time
 
 from .spchol import SpcError
 
-BASE = dict(amalg_ratio=0.0, sn_cap=150, small_w=16, small_r=64)
+BASE = dict(amalg_ratio=0.0, sn_cap=150, small_w=16, small_r=64, upd_chunk=16)
 STAGES = (
     tuple(dict(amalg_ratio=r) for r in (0.0, 0.05, 0.1, 0.2, 0.3, 0.5)),
     tuple(dict(sn_cap=c) for c in (150, 64)),
     tuple(dict(small_w=w, small_r=r)
           for w, r in ((16, 64), (16, 32), (8, 64), (4, 16), (-1, 64))),
+    tuple(dict(upd_chunk=c) for c in (16, 8, 32)),
 )
 
 
@@ -104,19 +108,25 @@ def _store(path, data):
     os.replace(tmp, path)
 
 
+def cached_table(mats, precision, cache_path):
+    """The timed table stored with a cached choice (None if there is none)."""
+    got = _load(cache_path).get(size_class(mats, precision))
+    return None if got is None else got.get("table")
+
+
 def tune_batch(mats, values, rhs, precision=0, stages=STAGES, cache_path=None, steps=2,
-               timer=measure, base=BASE):
+               timer=measure, base=BASE, retune=False):
     """Options (a dict for spchol.analyze_batch) that minimise factorization +
     solve time for this batch, and the table of what each timed option set
     measured.  A cached choice for the batch's size class is returned without
-    timing (table None).  Otherwise each stage's candidates (partial option
+    timing (table None) unless `retune`.  Otherwise each stage's candidates (partial option
     dicts) are applied in turn to the best options so far and timed with
     `timer` (an option set already timed is not timed again; one that
     fails with a library error is recorded with ms = inf and never chosen);
     when `cache_path` is given, the winner is stored there."""
     key = size_class(mats, precision)
     cached = _load(cache_path).get(key)
-    if cached is not None:
+    if cached is not None and not retune:
         return dict(cached["options"]), None
     best = dict(base)
     seen, table = {}, []

@@ -351,3 +351,18 @@ def test_factor_graph_replays_match_direct_launches(sched, det):
     num.refactor(vals)
     worst, rho, _ = compare_factor(p, num, 150, 0.1, "graph replay")
     assert worst <= 1.0 and rho <= 1e-12
+
+
+@pytest.mark.parametrize("chunk,precision", [(8, 0), (32, 0), (8, 1), (32, 1)])
+def test_update_chunk_shapes_give_the_same_bits(chunk, precision):
+    """The update tiles' K chunk (a tile shape the batch autotuner searches)
+    changes only how the source panel is staged: the products and their
+    order are the same, so the factor has the same bits."""
+    p = inputs.make_grid_problem("lap", (20, 20, 20), 6, sigma=1.0, shift=1e-6, nrhs=0)
+    say("chunk", chunk, "precision", precision, "n", p.n)
+    sym, num, _ = gpu_factor(p, 150, 0.1, precision=precision)
+    symc, numc, _ = gpu_factor(p, 150, 0.1, precision=precision, upd_chunk=chunk)
+    assert num.status() == 0 and numc.status() == 0
+    assert np.array_equal(numc.export()[2], num.export()[2])
+    for o in (num, numc, sym, symc):
+        o.free()

@@ -3,6 +3,8 @@
 set and the JSON cache."""
 import json
 
+import pytest
+
 from paper_1608_00044_amd import inputs, tune
 
 
@@ -105,3 +107,21 @@ def test_failing_candidates_are_skipped():
 
     with pytest.raises(RuntimeError):
         tune.tune_batch(_mats(), None, None, 1, STAGES, timer=always, base=BASE)
+
+
+def test_default_stages_are_valid_analysis_options():
+    """Every candidate of the library's stages (ratio, cap, lane-group split,
+    update tile K chunk) is an option set the batched analysis accepts."""
+    from paper_1608_00044_amd import inputs, spchol
+
+    chunks = {c["upd_chunk"] for st in tune.STAGES for c in st if "upd_chunk" in c}
+    assert chunks == {8, 16, 32}
+    probs = inputs.make_batch(count=3, side_lo=16, side_hi=20)
+    mats = [(q.n, q.colptr, q.rowind, q.perm) for q in probs]
+    for stage in tune.STAGES:
+        for cand in stage:
+            sym = spchol.analyze_batch(mats, **dict(tune.BASE, **cand))
+            assert sym.info()["nbatch"] == 3
+            sym.free()
+    with pytest.raises(spchol.SpcError):
+        spchol.analyze_batch(mats, **dict(tune.BASE, upd_chunk=12))
