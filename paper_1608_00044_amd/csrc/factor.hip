@@ -1008,6 +1008,7 @@ __global__ __launch_bounds__(kSchedThreads) void k_sched(
         __syncthreads();
         const int32_t t = sh_ticket;
         if (t < 0 || t >= ntasks) break;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every wave, after the barrier
         const Task tk = tasks[t];
         if (tk.kind == kTaskF) {
             diag_factor(tk.s, a, arena, dinv, status, status + 1, T);
@@ -1017,9 +1018,11 @@ __global__ __launch_bounds__(kSchedThreads) void k_sched(
             update_task<R>(UpdTile{tk.s, tk.a, tk.b}, a, nullptr, arena, coltgt);
         }
         // release, once per task: every wave's stores and adds have reached
-        // this XCD's L2 (s_waitcnt, then the barrier); one write-back of that
-        // L2 then makes them visible to every XCD before the signal
-        __builtin_amdgcn_s_waitcnt(0);
+        // this XCD's L2 (a wait for the wave's outstanding memory operations,
+        // which the compiler may not move anything across, then the barrier);
+        // one write-back of that L2 then makes them visible to every XCD
+        // before the signal
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
         if (tid == 0) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         if (log && tid == 0) log[2 * (int64_t)t + 1] = atomicAdd(ctrl + 3, 1);

@@ -168,9 +168,25 @@ __global__ __launch_bounds__(256) void k_colmax(const double* __restrict__ v, in
     sm.flush(out + c * nseg);
 }
 
+// xt[k NR + c] = x[k + (c0 + c) ldx] (zero past nrhs): the NR columns of x
+// interleaved, so that the residual's gather of row k of x is one
+// contiguous read instead of NR reads NR cache lines apart.
+template <int NR>
+__global__ void k_interleave(const double* __restrict__ x, int64_t ldx, double* __restrict__ xt,
+                             int64_t n, int c0, int nrhs) {
+    const int64_t total = n * NR;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = e / NR;
+        const int c = (int)(e % NR);
+        xt[e] = c0 + c < nrhs ? x[k + (int64_t)(c0 + c) * ldx] : 0.0;
+    }
+}
+
 // r_c = b_c - A x_c and ||r_{k,c}||_inf for the columns c0 .. c0 + NR - 1
 // (those below nrhs) in one pass over A: each entry of A is read once and
-// multiplies NR gathered entries of x.
+// multiplies NR gathered entries of x (NR > 1: from the interleaved copy xt,
+// row k at xt + k NR).
 template <int NR>
 __global__ __launch_bounds__(256) void k_resid(const int64_t* __restrict__ ptr,
                                                const int32_t* __restrict__ col,
@@ -192,9 +208,13 @@ __global__ __launch_bounds__(256) void k_resid(const int64_t* __restrict__ ptr,
             for (int64_t q = ptr[i] + j; q < ptr[i + 1]; q += kLpr) {
                 const double v = val[q];
                 const int64_t k = col[q];
+                if (NR == 1) {
+                    acc[0] += v * x[k + (int64_t)c0 * ldx];
+                } else {
+                    const double* __restrict__ xk = x + k * NR;
 #pragma unroll
-                for (int c = 0; c < NR; ++c)
-                    if (c < nc) acc[c] += v * x[k + (int64_t)(c0 + c) * ldx];
+                    for (int c = 0; c < NR; ++c) acc[c] += v * xk[c];
+                }
             }
         }
         const int si = seg_of(seg, i, n);
@@ -430,8 +450,8 @@ int32_t run_refine(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb,
         num->ir_work = nullptr;
         num->ir_host = nullptr;
         num->ir_cols = 0;
-        if (hipMalloc(&num->ir_work, sizeof(double) * ((size_t)n + 5 * (size_t)ns) * nrhs) !=
-            hipSuccess)
+        if (hipMalloc(&num->ir_work, sizeof(double) * (((size_t)n + 5 * (size_t)ns) * nrhs +
+                                                       (size_t)n * kResidCols)) != hipSuccess)
             return ERR_OOM;
         if (hipHostMalloc(&num->ir_host, sizeof(double) * (size_t)ns * nrhs,
                           hipHostMallocDefault) != hipSuccess)
@@ -444,6 +464,7 @@ int32_t run_refine(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb,
     double* rn = xn + ne;
     double* eta = rn + ne;
     double* scale = eta + ne;
+    double* xt = scale + ne;  // n x kResidCols, x's columns interleaved for the residual
     const int32_t* seg = num->a_seg;
     const dim3 grid_rows(row_blocks(n), nrhs);
     // stall: consecutive steps whose worst eta did not halve; two of them on
@@ -458,11 +479,20 @@ int32_t run_refine(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb,
     for (int32_t it = 0;; ++it) {
         hipLaunchKernelGGL(k_fill_f64, dim3(grid_of(2 * ne)), dim3(256), 0, st, xn, 2 * ne, 0.0);
         for (int32_t c0 = 0; c0 < nrhs; c0 += kResidCols) {
-            auto kr = nrhs - c0 == 1 ? k_resid<1> : k_resid<kResidCols>;
-            hipLaunchKernelGGL(kr, dim3(sparse_blocks(n)), dim3(256), 0, st,
-                               (const int64_t*)num->a_ptr, (const int32_t*)num->a_col,
-                               (const double*)num->a_val, b, ldb, (const double*)x, ldx, r, n,
-                               (int)c0, (int)nrhs, seg, ns, rn);
+            if (nrhs - c0 == 1) {
+                hipLaunchKernelGGL(k_resid<1>, dim3(sparse_blocks(n)), dim3(256), 0, st,
+                                   (const int64_t*)num->a_ptr, (const int32_t*)num->a_col,
+                                   (const double*)num->a_val, b, ldb, (const double*)x, ldx, r,
+                                   n, (int)c0, (int)nrhs, seg, ns, rn);
+            } else {
+                hipLaunchKernelGGL(k_interleave<kResidCols>, dim3(grid_of(n * kResidCols)),
+                                   dim3(256), 0, st, (const double*)x, ldx, xt, n, (int)c0,
+                                   (int)nrhs);
+                hipLaunchKernelGGL(k_resid<kResidCols>, dim3(sparse_blocks(n)), dim3(256), 0, st,
+                                   (const int64_t*)num->a_ptr, (const int32_t*)num->a_col,
+                                   (const double*)num->a_val, b, ldb, (const double*)xt,
+                                   (int64_t)kResidCols, r, n, (int)c0, (int)nrhs, seg, ns, rn);
+            }
         }
         hipLaunchKernelGGL(k_colmax, grid_rows, dim3(256), 0, st, (const double*)x, ldx, n, seg,
                            ns, xn);

@@ -491,6 +491,72 @@ __global__ __launch_bounds__(256) void k_bwd_cols(const ColBlk* __restrict__ wor
     }
 }
 
+// k_bwd_cols for several right-hand sides (NR = kRhs = 8): 256 rows of the
+// chunk at a time are staged in LDS, the block's kColGroup columns of L21
+// and the rows' entries of y, every load coalesced and issued at once; then
+// thread (column k, right-hand side c, quarter q) sums its quarter of the
+// staged rows, and the four quarters meet in order.  One workgroup per
+// (supernode, column group, row chunk), as k_bwd_cols, with no shuffles.
+template <class R, int NR>
+__global__ __launch_bounds__(256) void k_bwd_cols_multi(const ColBlk* __restrict__ work,
+                                                        KArgs a, const R* __restrict__ arena,
+                                                        const R* __restrict__ y,
+                                                        R* __restrict__ pb,
+                                                        const int64_t* __restrict__ pb_off,
+                                                        int64_t pb_total, int64_t n, int nrhs) {
+    constexpr int G = kColGroup;
+    static_assert(G * NR * 4 == 256, "one thread per (column, right-hand side, quarter)");
+    constexpr int kRows = 256;
+    __shared__ R Ls[kRows][G + 1];
+    __shared__ R Xs[kRows][NR + 1];
+    __shared__ R part[4][G][NR];
+    const ColBlk wb = work[blockIdx.x];
+    const int s = wb.s, g = wb.g, h = wb.h;
+    const int w = a.sn_w[s], ld = a.sn_ld[s];
+    const int64_t rp = a.rowptr[s];
+    const int k0 = g * G, kc = min(G, w - k0);
+    const int rb0 = h * kRowChunk;
+    const int r = min((int)(a.rowptr[s + 1] - rp) - w - rb0, kRowChunk);  // rows of the chunk
+    const R* __restrict__ P = arena + a.sn_off[s] + w + rb0 + (int64_t)k0 * ld;
+    const int32_t* __restrict__ below = a.rows + rp + w + rb0;
+    R* __restrict__ out = pb + pb_off[s] + (int64_t)h * w + k0;
+    const int tid = threadIdx.x;
+    const int k = tid % G, c = (tid / G) % NR, q = tid / (G * NR);
+    for (int c0 = 0; c0 < nrhs; c0 += NR) {
+        const int nc = min(NR, nrhs - c0);
+        R acc = R(0);
+        for (int i0 = 0; i0 < r; i0 += kRows) {
+            const int i = i0 + tid;
+            const int32_t row = i < r ? below[i] : 0;
+            R lv[G], xv[NR];
+#pragma unroll
+            for (int kk = 0; kk < G; ++kk)
+                lv[kk] = (i < r && kk < kc) ? P[i + (int64_t)kk * ld] : R(0);
+#pragma unroll
+            for (int cc = 0; cc < NR; ++cc)
+                xv[cc] = (i < r && cc < nc) ? y[(int64_t)(c0 + cc) * n + row] : R(0);
+#pragma unroll
+            for (int kk = 0; kk < G; ++kk) Ls[tid][kk] = lv[kk];
+#pragma unroll
+            for (int cc = 0; cc < NR; ++cc) Xs[tid][cc] = xv[cc];
+            __syncthreads();
+            const int j0 = q * (kRows / 4);
+#pragma unroll 8
+            for (int j = j0; j < j0 + kRows / 4; ++j) acc += Ls[j][k] * Xs[j][c];
+            __syncthreads();
+        }
+        part[q][k][c] = acc;
+        __syncthreads();
+        if (tid < G * NR) {
+            const int kk = tid % G, cc = tid / G;
+            if (kk < kc && cc < nc)
+                out[(int64_t)(c0 + cc) * pb_total + kk] =
+                    (part[0][kk][cc] + part[1][kk][cc]) + (part[2][kk][cc] + part[3][kk][cc]);
+        }
+        __syncthreads();
+    }
+}
+
 // Backward, diagonal block, one workgroup per large supernode of the level:
 // t_s = the chunks' partial sums in chunk order, then
 // x_s = L11^{-T} (z_s - t_s) into y, which now holds the solution of every
@@ -589,9 +655,10 @@ __global__ __launch_bounds__(256) void k_bwd_diag(const int32_t* __restrict__ le
 // Data that one task writes and another reads in the same launch (y, z, x,
 // the partial sums) is stored and loaded at device scope, coherent across the
 // eight XCDs' L2 caches without a cache writeback or invalidation: a signal
-// follows its task's stores once they are complete (s_waitcnt, then the
-// workgroup barrier), and a waiter loads the data only after it has seen the
-// signal.  Acquire/release fences would write back or invalidate a whole L2
+// follows its task's stores once they are complete (a wait for each wave's
+// outstanding memory operations that the compiler cannot reorder around, then
+// the workgroup barrier), and a waiter loads the data only after it has seen
+// the signal.  Acquire/release fences would write back or invalidate a whole L2
 // on every task, which costs more than the solve's work.
 template <class T>
 __device__ __forceinline__ T ld_dev(const T* p) {
@@ -702,7 +769,7 @@ __global__ __launch_bounds__(256, 2) void k_tail(const TailTask* __restrict__ ta
                 }
                 __syncthreads();
             }
-            __builtin_amdgcn_s_waitcnt(0);  // this thread's stores and adds are done
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this thread's stores and adds done
             __syncthreads();
             if (tid == 0)
                 for (int32_t q = tk.a; q < tk.b; ++q)
@@ -732,7 +799,7 @@ __global__ __launch_bounds__(256, 2) void k_tail(const TailTask* __restrict__ ta
                 }
                 __syncthreads();
             }
-            __builtin_amdgcn_s_waitcnt(0);  // this thread's stores and adds are done
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this thread's stores and adds done
             __syncthreads();
             if (tid == 0)
                 __hip_atomic_store(ready + tk.u, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -789,7 +856,7 @@ __global__ __launch_bounds__(256, 2) void k_tail(const TailTask* __restrict__ ta
                 }
                 __syncthreads();
             }
-            __builtin_amdgcn_s_waitcnt(0);  // this thread's stores and adds are done
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this thread's stores and adds done
             __syncthreads();
             if (tid == 0)
                 __hip_atomic_fetch_add(cntB + tk.u, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -834,7 +901,7 @@ __global__ __launch_bounds__(256, 2) void k_tail(const TailTask* __restrict__ ta
                 }
                 __syncthreads();
             }
-            __builtin_amdgcn_s_waitcnt(0);  // this thread's stores and adds are done
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this thread's stores and adds done
             __syncthreads();
             if (tid == 0)
                 __hip_atomic_store(done + tk.u, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -905,10 +972,16 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* work, hipStream_t st) {
     for (int32_t l = nl - 1; l >= 0; --l) {
         const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1], nbig = P->level_nbig[l];
         const int64_t g0 = P->colblk_ptr[l], g1 = P->colblk_ptr[l + 1];
-        if (g1 > g0)
-            hipLaunchKernelGGL((k_bwd_cols<R, NR>), dim3((unsigned)(g1 - g0)), dim3(256), 0, st,
-                               P->colblk + g0, a, arena, (const R*)y, pb,
-                               (const int64_t*)P->pb_off, P->pb_total, n, nrhs);
+        if (g1 > g0) {
+            if constexpr (NR == 1)
+                hipLaunchKernelGGL((k_bwd_cols<R, NR>), dim3((unsigned)(g1 - g0)), dim3(256), 0,
+                                   st, P->colblk + g0, a, arena, (const R*)y, pb,
+                                   (const int64_t*)P->pb_off, P->pb_total, n, nrhs);
+            else
+                hipLaunchKernelGGL((k_bwd_cols_multi<R, NR>), dim3((unsigned)(g1 - g0)),
+                                   dim3(256), 0, st, P->colblk + g0, a, arena, (const R*)y, pb,
+                                   (const int64_t*)P->pb_off, P->pb_total, n, nrhs);
+        }
         if (nbig > 0)
             hipLaunchKernelGGL((k_bwd_diag<R, NR>), dim3((unsigned)nbig), dim3(256), 0, st,
                                P->level_sn + n0, a, dinv, y, (const R*)zb, (const R*)pb,
