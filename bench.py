@@ -615,9 +615,10 @@ SERVE_RECIPE = dict(rate=200.0, patterns_2d=16, patterns_3d=16, side2d=(32, 256)
                     value_sets=2)
 
 
-def serving(requests, seed=5000):
+def serving(requests, seed=5000, deterministic=0):
     """Poisson request stream over 32 resident patterns through the request
-    server; reports latency percentiles and throughput."""
+    server; reports latency percentiles and throughput (patterns analysed in
+    the given contribution order)."""
     import torch
 
     from paper_1608_00044_amd import inputs, spchol
@@ -635,8 +636,8 @@ def serving(requests, seed=5000):
         vals.append([torch.from_numpy(p.values).to("cuda:0") for p in sets])
     torch.zeros(1, device="cuda:0")
     srv = spchol.Server(max_inflight=16, max_nrhs=max(r["nrhs"]))
-    syms = [spchol.analyze(p.n, p.colptr, p.rowind, p.perm, sn_cap=150, amalg_ratio=0.1)
-            for p in probs]
+    syms = [spchol.analyze(p.n, p.colptr, p.rowind, p.perm, sn_cap=150, amalg_ratio=0.1,
+                           deterministic=deterministic) for p in probs]
     pids = [srv.add_pattern(s) for s in syms]
     # requests: pattern, kind, nrhs, arrival time
     gaps = rng.exponential(1.0 / r["rate"], size=requests)
@@ -673,6 +674,14 @@ def serving(requests, seed=5000):
     srv.destroy()
     lat = np.array([q["latency_ms"] for q in res])
     que = np.array([q["queue_ms"] for q in res])
+    # each pattern's first request also makes its first factor (allocation
+    # and the capture of its launch graphs)
+    first = np.zeros(requests, dtype=bool)
+    seen_p = set()
+    for i in range(requests):
+        if pat[i] not in seen_p:
+            first[i] = True
+            seen_p.add(pat[i])
     run = lat - que  # admission to completion of the request's device work
     ok = sum(1 for q in res if q["status"] == 0)
     cols = int(sum(int(nrhs[i]) for i in range(requests) if res[i]["status"] == 0))
@@ -683,9 +692,14 @@ def serving(requests, seed=5000):
            "queue_p99_ms": float(np.percentile(que, 99)),
            "admitted_p50_ms": float(np.percentile(run, 50)),
            "admitted_p99_ms": float(np.percentile(run, 99)),
+           "warm_p50_ms": float(np.percentile(lat[~first], 50)),
+           "warm_p99_ms": float(np.percentile(lat[~first], 99)),
+           "first_request_p50_ms": float(np.percentile(lat[first], 50)),
+           "first_request_max_ms": float(lat[first].max()),
            "latency_split": "latency = queue (submission to admission: waiting for a slot, "
                             "memory or a factor) + admitted (admission to the end of the "
                             "request's device work, overlapping other requests)",
+           "order": "fixed (bitwise reproducible)" if deterministic else "atomic",
            "solves_per_s": cols / wall, "peak_inflight": st["peak_inflight"],
            "peak_bytes": st["peak_bytes"], "evictions": st["evictions"],
            "recipe": "Poisson arrivals at %g/s over %d 2D (side %d..%d) and %d 3D 7-point "
@@ -694,8 +708,10 @@ def serving(requests, seed=5000):
                          r["rate"], r["patterns_2d"], r["side2d"][0], r["side2d"][1],
                          r["patterns_3d"], r["side3d"][0], r["side3d"][1], r["sigma"],
                          int(100 * r["solve_only"]), list(r["nrhs"]))}
-    log("serve: p50 %.2f ms p99 %.2f ms, %.1f req/s, %.0f solves/s, peak inflight %d" %
-        (out["p50_ms"], out["p99_ms"], out["requests_per_s"], out["solves_per_s"],
+    log("serve: p50 %.2f ms p99 %.2f ms (warm %.2f / %.2f, first requests p50 %.2f ms), "
+        "%.1f req/s, %.0f solves/s, peak inflight %d" %
+        (out["p50_ms"], out["p99_ms"], out["warm_p50_ms"], out["warm_p99_ms"],
+         out["first_request_p50_ms"], out["requests_per_s"], out["solves_per_s"],
          out["peak_inflight"]))
     return out
 
@@ -956,7 +972,7 @@ def main():
                                   cache=args.tune_cache)
                           for prec in (0, 1)]
     if args.serve_requests:
-        out["serving"] = serving(args.serve_requests)
+        out["serving"] = serving(args.serve_requests, deterministic=args.deterministic)
     if leg is not None:
         log("waiting for the oracle leg")
         res = leg.join()

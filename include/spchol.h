@@ -426,8 +426,10 @@ typedef struct spc_server_stats {
 
 void spc_server_default_options(spc_server_options* opt);
 spc_status spc_server_create(const spc_server_options* opt, spc_server** out);
-/* Registers a symbolic handle.  The server holds a reference to it until
- * spc_server_destroy: spc_symbolic_free returns SPC_ERR_BUSY meanwhile. */
+/* Registers a symbolic handle and makes its device plan on the server's
+ * device now (SPC_ERR_OOM if it does not fit), so that the pattern's first
+ * request does not build it.  The server holds a reference to the handle
+ * until spc_server_destroy: spc_symbolic_free returns SPC_ERR_BUSY meanwhile. */
 spc_status spc_server_add_pattern(spc_server* srv, spc_symbolic* sym, int32_t* pattern);
 /* Queues a request; *ticket identifies it.  SPC_ERR_ARG on bad sizes. */
 spc_status spc_server_submit(spc_server* srv, const spc_request* req, int64_t* ticket);

@@ -399,6 +399,17 @@ spc_status spc_server_add_pattern(spc_server* s, spc_symbolic* sym, int32_t* pat
               4 * tail_state_words(S);
     p.plan_bytes = (int64_t)sym->plan_bytes_estimate;
     {
+        // the pattern's device plan is made now, on the server's device, so
+        // that its first request does not wait for it
+        int cur = 0;
+        if (hipGetDevice(&cur) != hipSuccess || hipSetDevice(s->device) != hipSuccess)
+            return SPC_ERR_HIP;
+        DevicePlan* plan = nullptr;
+        const int32_t st = get_plan(sym, &plan);
+        (void)hipSetDevice(cur);
+        if (st != OK) return st;
+    }
+    {
         // the server keeps the handle referenced until spc_server_destroy
         std::lock_guard<std::mutex> sl(sym->mu);
         sym->refs++;
