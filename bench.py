@@ -224,6 +224,56 @@ def stored_oracle_solution(name):
         return np.array(z["x"]), np.array(z["eta"])
 
 
+def oracle_factor_parity(name, p, Sp, Si, Sx):
+    """Worst |dL_ij| / (1e-10 |L_ij| + 1e-13 sqrt(c_ii c_jj) / |L_jj|) of the GPU
+    factor over the FP64 oracle's factor entries stored under tests/golden/ by
+    tests/golden/make_oracle_factor_sample.py (every stride-th entry of the
+    exact structure; read here with numpy only), with C = P A P^T; None when
+    the sample is absent or written by other sources of the oracle or the
+    inputs."""
+    import hashlib
+
+    path = os.path.join(ROOT, "tests", "golden", "oracle_L_sample_%s.npz" % name)
+    if not os.path.exists(path):
+        return None
+    want = {}
+    for key, rel in (("oracle_sha", "oracle/oracle.c"),
+                     ("inputs_sha", "paper_1608_00044_amd/inputs.py")):
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            want[key] = hashlib.sha256(f.read()).hexdigest()
+    with np.load(path, allow_pickle=False) as z:
+        if any(str(z[k]) != v for k, v in want.items()) or str(z["workload"]) != name:
+            return None
+        rows, cols, ref, ljj = (np.array(z[k]) for k in ("rows", "cols", "vals", "ljj"))
+        stride, nnz_l = int(z["stride"]), int(z["nnz_l"])
+    n = p.n
+    colA = np.repeat(np.arange(n), np.diff(p.colptr))
+    isd = p.rowind == colA
+    diagA = np.zeros(n)
+    diagA[colA[isd]] = p.values[isd]
+    perm = p.perm if p.perm is not None else np.arange(n)
+    c = diagA[perm]
+    # binary search of each sampled row in its column (rows increase within
+    # a stored column)
+    lo, end = Sp[cols].astype(np.int64), Sp[cols + 1].astype(np.int64)
+    hi = end.copy()
+    while (lo < hi).any():
+        act = lo < hi
+        mid = (lo + hi) // 2
+        go = Si[np.minimum(mid, Si.size - 1)] < rows
+        lo = np.where(act & go, mid + 1, lo)
+        hi = np.where(act & ~go, mid, hi)
+    if (lo >= end).any() or (Si[np.minimum(lo, Si.size - 1)] != rows).any():
+        return {"worst": float("inf"), "what": "oracle entry outside the stored structure"}
+    pos = lo
+    bar = 1e-10 * np.abs(ref) + 1e-13 * np.sqrt(np.abs(c[rows] * c[cols])) / np.abs(ljj)
+    worst = float((np.abs(Sx[pos] - ref) / bar).max())
+    return {"worst": worst, "entries": int(ref.size), "of": nnz_l, "stride": stride,
+            "what": "max |L_gpu - L_oracle| / (1e-10 |L| + 1e-13 sqrt(c_ii c_jj) / |L_jj|) "
+                    "over every %d-th entry of the oracle's exact factor "
+                    "(tests/golden/oracle_L_sample_%s.npz); <= 1 passes" % (stride, name)}
+
+
 def other_order(p, amalg, F, deterministic, steps, primary_ms):
     """The workload factored in the other contribution order (deterministic
     or atomic), timed the same way; its cost against the headline order."""
@@ -880,6 +930,10 @@ def main():
     Sp, Si, Sx = num.export()
     rho = probe_residual(p, Sp, Si, Sx)
     log("probe residual %.2e" % rho)
+    lpar = oracle_factor_parity(name, p, Sp, Si, Sx)
+    if lpar is not None:
+        log("factor vs stored oracle entries: worst %.3g of the bar over %d entries" %
+            (lpar["worst"], lpar.get("entries", 0)))
     log("solve p50 %.3f ms p99 %.3f ms, backward error %.2e" %
         (np.percentile(lat, 50), np.percentile(lat, 99), eta))
 
@@ -949,6 +1003,7 @@ def main():
                                                 "products from registers (8 accumulators per "
                                                 "wave, 8 waves per SIMD) and a 512 MiB copy "
                                                 "(read + write bytes)"),
+        "oracle_sample_parity": lpar,
         "residual_probe": {"value": rho, "probes": 8,
                            "what": "||(L L^T - P A P^T) Z||_F / ||P A P^T Z||_F, Z 8 N(0,1) "
                                    "columns, GPU factor on the host (scipy)"},
