@@ -323,18 +323,20 @@ __device__ __forceinline__ void trailing_block(C* __restrict__ T, Cst cst, int d
 //      panel (16 x 16 blocks, K = 16 on the matrix cores);
 //   2. wave 0 factors the next panel column by column in registers
 //      (panel_columns: its diagonal block and every row below it at once),
-//      while waves 1-3 update the rest of the trailing triangle;
+//      while waves 1-3 update the rest of the trailing triangle and then
+//      write the current panel's columns back to the block;
 // so the chain from panel to panel is one block update and one register
-// column factorization.  The inverses of the 16 x 16 diagonal blocks (for the
-// panel and triangular solves) are formed at the end by all four waves.  The
-// block is loaded and written back by packed index with many accesses per
-// thread in flight; the packed copy goes after the inverses in dinv.
+// column factorization, and only the last panel is written after it.  The
+// inverses of the 16 x 16 diagonal blocks (for the panel and triangular
+// solves) are formed at the end by all four waves.  The block is loaded by
+// packed index with many loads per thread in flight.
 // Storage type S, compute type C.  Without kCheck a pivot that is not
 // positive records its global column with atomicMin on *status (the smallest
-// failing column wins).  With kCheck (FP32 pass) nothing is recorded: if any
-// pivot is not above kPivotTau times its starting diagonal entry the block is
-// left unwritten in global memory and the function returns true, so that the
-// caller can factor it again in FP64.
+// failing column wins).  With kCheck (FP32 pass) nothing is recorded and
+// nothing is written before the end: if any pivot is not above kPivotTau
+// times its starting diagonal entry the block is left unwritten in global
+// memory and the function returns true, so that the caller can factor it
+// again in FP64; otherwise the block goes back by packed index at the end.
 template <class S, class C, bool kCheck>
 __device__ __forceinline__ bool potrf_task(int s, const KArgs& a, S* __restrict__ arena,
                                            S* __restrict__ dinv, int32_t* __restrict__ status,
@@ -389,6 +391,26 @@ __device__ __forceinline__ bool potrf_task(int s, const KArgs& a, S* __restrict_
     }
     __syncthreads();
     const int npanel = (w + kPanel - 1) / kPanel;
+    // panel q's columns (rows q * 16 .. w - 1) back to the block, round robin
+    // over waves wv0 .. 3
+    auto emit = [&](int q, int wv0) {
+        const int j0 = q * kPanel, jb = min(kPanel, w - j0);
+        for (int k = wave - wv0; k < jb; k += nwave - wv0) {
+            const int j = j0 + k, cj = cst(j);
+            S* __restrict__ col = base + (int64_t)j * ld;
+            C v[3];
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                const int i = j + lane + 64 * u;
+                v[u] = T[i < w ? cj + i : dummy];
+            }
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                const int i = j + lane + 64 * u;
+                if (i < w) col[i] = (S)v[u];
+            }
+        }
+    };
     if (wave == 0)
         panel_columns<C, kCheck>(T, rdiag, colbuf, cst, w, 0, min(kPanel, w), lane, first,
                                  status, d0, &unstable);
@@ -413,10 +435,16 @@ __device__ __forceinline__ bool potrf_task(int s, const KArgs& a, S* __restrict_
                 const int bj = b - bi * (bi - 1) / 2 + 1;
                 trailing_block<C>(T, cst, dummy, w, j0, t0, bi, bj, lr, lk);
             }
+            if (!kCheck) emit(p, 1);
         }
         __syncthreads();
     }
-    if (kCheck && unstable) return true;  // uniform: read after the last barrier
+    if (!kCheck) {
+        emit(npanel - 1, 0);
+        panel_inverses<C, S>(T, rdiag, inv_g, cst, w, npanel, wave, lane);
+        return false;
+    }
+    if (unstable) return true;  // uniform: read after the last barrier
     panel_inverses<C, S>(T, rdiag, inv_g, cst, w, npanel, wave, lane);
     // L11 back to the block by the same folded index, many stores per thread
     // in flight
