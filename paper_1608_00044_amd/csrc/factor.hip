@@ -355,39 +355,44 @@ __device__ __forceinline__ bool potrf_task(int s, const KArgs& a, S* __restrict_
     const int dummy = w * (w + 1) / 2;  // masked accesses land here
     if (kCheck && tid == 0) unstable = 0;
     // The lower triangle folded into a (w + 1) x ceil(w / 2) rectangle:
-    // rectangle column p holds column p (rows p .. w - 1) followed by column
-    // w - 1 - p (rows w - 1 - p .. w - 1), so a flat index maps to its entry
-    // with one division; for odd w the middle column is taken once.  Loaded in
-    // two rounds with every load of a round in flight.
-    const int hw = (w + 1) >> 1, w1 = w + 1, nrect = w1 * hw;
-    const float inv_w1 = 1.0f / (float)w1;
-    auto fold = [&](int e, int& i, int& j) {  // false past the end or for a duplicate
-        int pcol, q;
-        divmod_small(e, w1, inv_w1, pcol, q);
-        const bool first = q < w - pcol;
-        j = first ? pcol : w - 1 - pcol;
-        i = first ? pcol + q : j + q - (w - pcol);
-        return e < nrect && (first || j != pcol);
-    };
-    constexpr int kPerT = ((kMaxWidth + 1) * ((kMaxWidth + 1) / 2) + 2 * kPotrfThreads - 1) /
-                          (2 * kPotrfThreads);
-    for (int e0 = tid; e0 < nrect; e0 += kPerT * kPotrfThreads) {
-        C v[kPerT];
-        int at[kPerT];
-        int dg[kCheck ? kPerT : 1];  // diagonal entries keep their column for d0
+    // rectangle column pc holds column pc (rows pc .. w - 1) followed by
+    // column w - 1 - pc (rows w - 1 - pc .. w - 1); for odd w the middle
+    // column is taken once.  Wave v loads rectangle columns v, v + 4, ...,
+    // lane l their entries l, l + 64 and l + 128, in rounds of kRound
+    // rectangle columns with every load of a round in flight.
+    const int hw = (w + 1) >> 1, w1 = w + 1;
+    constexpr int kRect = ((kMaxWidth + 1) / 2 + nwave - 1) / nwave;  // per wave
+    constexpr int kRound = (kRect + 1) / 2;
+    for (int t0 = 0; t0 * nwave < hw; t0 += kRound) {
+        C v[kRound][3];
+        int at[kRound][3];
 #pragma unroll
-        for (int u = 0; u < kPerT; ++u) {
-            int i, j;
-            const bool ok = fold(e0 + u * kPotrfThreads, i, j);
-            v[u] = ok ? (C)base[i + (int64_t)j * ld] : C(0);
-            at[u] = ok ? cst(j) + i : dummy;
-            if (kCheck) dg[kCheck ? u : 0] = (ok && i == j) ? j : -1;
+        for (int t = 0; t < kRound; ++t) {
+            const int pc = wave + nwave * (t0 + t), pj = w - 1 - pc;
+            const S* __restrict__ c0 = base + (int64_t)pc * ld;
+            const S* __restrict__ c1 = base + (int64_t)pj * ld;
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                const int q = lane + 64 * u;
+                const bool first = q < w - pc;
+                const int j = first ? pc : pj, i = first ? pc + q : pj + q - (w - pc);
+                const bool ok = pc < hw && q < w1 && (first || pj != pc);
+                v[t][u] = ok ? (C)(first ? c0 : c1)[i] : C(0);
+                at[t][u] = ok ? cst(j) + i : dummy;
+            }
         }
 #pragma unroll
-        for (int u = 0; u < kPerT; ++u) {
-            T[at[u]] = v[u];
-            if (kCheck && dg[kCheck ? u : 0] >= 0) d0[dg[kCheck ? u : 0]] = v[u];
-        }
+        for (int t = 0; t < kRound; ++t)
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                T[at[t][u]] = v[t][u];
+                if (kCheck) {
+                    const int pc = wave + nwave * (t0 + t), q = lane + 64 * u;
+                    // the diagonal entries: q = 0 of column pc and q = w - pc of w - 1 - pc
+                    if (pc < hw && q == 0) d0[pc] = v[t][u];
+                    if (pc < hw && q == w - pc && w - 1 - pc != pc) d0[w - 1 - pc] = v[t][u];
+                }
+            }
     }
     __syncthreads();
     const int npanel = (w + kPanel - 1) / kPanel;
@@ -446,22 +451,28 @@ __device__ __forceinline__ bool potrf_task(int s, const KArgs& a, S* __restrict_
     }
     if (unstable) return true;  // uniform: read after the last barrier
     panel_inverses<C, S>(T, rdiag, inv_g, cst, w, npanel, wave, lane);
-    // L11 back to the block by the same folded index, many stores per thread
-    // in flight
-    for (int e0 = tid; e0 < nrect; e0 += kPerT * kPotrfThreads) {
-        C v[kPerT];
-        int gj[kPerT];
-        bool ok[kPerT];
+    // L11 back to the block by the same rectangle columns as the load
 #pragma unroll
-        for (int u = 0; u < kPerT; ++u) {
-            int i, j;
-            ok[u] = fold(e0 + u * kPotrfThreads, i, j);
-            gj[u] = i + j * ld;
-            v[u] = T[ok[u] ? cst(j) + i : dummy];
+    for (int t = 0; t < kRect; ++t) {
+        const int pc = wave + nwave * t, pj = w - 1 - pc;
+        S* __restrict__ c0 = base + (int64_t)pc * ld;
+        S* __restrict__ c1 = base + (int64_t)pj * ld;
+        C v[3];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            const int q = lane + 64 * u;
+            const bool first = q < w - pc;
+            const int j = first ? pc : pj, i = first ? pc + q : pj + q - (w - pc);
+            const bool ok = pc < hw && q < w1 && (first || pj != pc);
+            v[u] = T[ok ? cst(j) + i : dummy];
         }
 #pragma unroll
-        for (int u = 0; u < kPerT; ++u)
-            if (ok[u]) base[gj[u]] = (S)v[u];
+        for (int u = 0; u < 3; ++u) {
+            const int q = lane + 64 * u;
+            const bool first = q < w - pc;
+            const bool ok = pc < hw && q < w1 && (first || pj != pc);
+            if (ok) (first ? c0 : c1)[first ? pc + q : pj + q - (w - pc)] = (S)v[u];
+        }
     }
     return false;
 }
