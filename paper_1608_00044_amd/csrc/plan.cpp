@@ -28,7 +28,7 @@ struct PlanOffsets {
         pair_seg, pair_rel, pair_excl, rel, level_sn, big_sn, rowblk, tiles, tasks, cnt0,
         rb_base;
     size_t pair_src, pair_end, scr_off, app_t, app_rb, app_p0, app_ent;
-    size_t slot_shared, red_row, red_ptr, red_slot, colblk, fwdblk, pb_off;
+    size_t slot_shared, red_row, red_ptr, red_slot, colblk, fwdblk, sspart, pb_off;
     size_t tail_tasks, tail_segs;
     size_t total;
 };
@@ -242,7 +242,7 @@ PlanOffsets plan_layout(const Symbolic& S, const std::vector<int64_t>& rb_ptr,
     o.tiles = L.add<UpdTile>((size_t)tl_ptr.back());
     o.slot_shared = L.add<uint8_t>(S.rows.size());
     o.red_row = o.red_ptr = o.red_slot = 0;  // sized by solve_layout
-    o.colblk = o.fwdblk = o.tail_tasks = o.tail_segs = 0;
+    o.colblk = o.fwdblk = o.sspart = o.tail_tasks = o.tail_segs = 0;
     o.pb_off = L.add<int64_t>(ns);
     o.tasks = o.cnt0 = o.rb_base = 0;
     o.pair_src = o.pair_end = o.scr_off = o.app_t = o.app_rb = o.app_p0 = o.app_ent = 0;
@@ -265,6 +265,8 @@ struct SolveData {
     std::vector<int64_t> colblk_ptr;   // per level
     std::vector<RowBlock> fwdblk;      // (s, 64-row block) of the large supernodes
     std::vector<int64_t> fwdblk_ptr;   // per level
+    std::vector<RowBlock> sspart;      // (s, 16-row part of the diagonal block), large ones
+    std::vector<int64_t> sspart_ptr;   // per level
     std::vector<int64_t> pb_off;       // per supernode
     int64_t pb_total = 0;
     int32_t tail_l0 = 0, ntail = 0;
@@ -354,6 +356,7 @@ SolveData build_solve(const Symbolic& S) {
     d.red_level_ptr.assign((size_t)nl + 1, 0);
     d.colblk_ptr.assign((size_t)nl + 1, 0);
     d.fwdblk_ptr.assign((size_t)nl + 1, 0);
+    d.sspart_ptr.assign((size_t)nl + 1, 0);
     d.red_ptr.push_back(0);
     d.pb_off.assign((size_t)S.nsup, 0);
     std::vector<int32_t> cnt((size_t)S.n, 0), stamp((size_t)S.n, -1);
@@ -365,6 +368,7 @@ SolveData build_solve(const Symbolic& S) {
             d.red_level_ptr[l + 1] = d.red_level_ptr[l];
             d.colblk_ptr[l + 1] = (int64_t)d.colblk.size();
             d.fwdblk_ptr[l + 1] = (int64_t)d.fwdblk.size();
+            d.sspart_ptr[l + 1] = (int64_t)d.sspart.size();
             for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
                 const int32_t s = S.level_sn[q];
                 d.pb_off[s] = d.pb_total;
@@ -414,6 +418,8 @@ SolveData build_solve(const Symbolic& S) {
             if (is_small(S, s)) continue;
             const int32_t nb = std::max<int32_t>(1, (S.nbelow(s) + kTile - 1) / kTile);
             for (int32_t rb = 0; rb < nb; ++rb) d.fwdblk.push_back(RowBlock{s, rb});
+            for (int32_t pt = 0; pt * kPartRows < S.width(s); ++pt)
+                d.sspart.push_back(RowBlock{s, pt});
             if (S.nbelow(s) == 0) continue;
             const int32_t ng = (S.width(s) + kColGroup - 1) / kColGroup;
             const int32_t nh = (S.nbelow(s) + kRowChunk - 1) / kRowChunk;
@@ -425,6 +431,7 @@ SolveData build_solve(const Symbolic& S) {
         }
         d.colblk_ptr[l + 1] = (int64_t)d.colblk.size();
         d.fwdblk_ptr[l + 1] = (int64_t)d.fwdblk.size();
+        d.sspart_ptr[l + 1] = (int64_t)d.sspart.size();
     }
     build_tail(S, l0, d);
     return d;
@@ -438,6 +445,7 @@ void solve_layout(PlanOffsets& o, const SolveData& d) {
     o.red_slot = L.add<int32_t>(d.red_slot.size());
     o.colblk = L.add<ColBlk>(d.colblk.size());
     o.fwdblk = L.add<RowBlock>(d.fwdblk.size());
+    o.sspart = L.add<RowBlock>(d.sspart.size());
     o.tail_tasks = L.add<TailTask>(d.tail.size());
     o.tail_segs = L.add<TailSeg>(d.segs.size());
     o.total = L.total;
@@ -491,6 +499,8 @@ int64_t tail_state_words(const Symbolic& S) {
     if (l0 >= nl) return 0;
     return 4 * (int64_t)(S.level_ptr[nl] - S.level_ptr[l0]) + 4;
 }
+
+int64_t split_state_words(const Symbolic& S) { return 2 * S.nsup + 2; }
 
 int64_t inverse_blocks_elems(const Symbolic& S) {
     int64_t t = 0;
@@ -719,12 +729,14 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
         put(o.red_slot, sd.red_slot.data(), sd.red_slot.size() * 4);
         put(o.colblk, sd.colblk.data(), sd.colblk.size() * sizeof(ColBlk));
         put(o.fwdblk, sd.fwdblk.data(), sd.fwdblk.size() * sizeof(RowBlock));
+        put(o.sspart, sd.sspart.data(), sd.sspart.size() * sizeof(RowBlock));
         put(o.pb_off, sd.pb_off.data(), sd.pb_off.size() * 8);
         P->nslots = (int64_t)S.rows.size();
         P->pb_total = sd.pb_total;
         P->red_level_ptr = sd.red_level_ptr;
         P->colblk_ptr = sd.colblk_ptr;
         P->fwdblk_ptr = sd.fwdblk_ptr;
+        P->sspart_ptr = sd.sspart_ptr;
         put(o.tail_tasks, sd.tail.data(), sd.tail.size() * sizeof(TailTask));
         put(o.tail_segs, sd.segs.data(), sd.segs.size() * sizeof(TailSeg));
         P->tail_l0 = sd.tail_l0;
@@ -773,6 +785,7 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
     P->red_slot = (int32_t*)(base + o.red_slot);
     P->colblk = (ColBlk*)(base + o.colblk);
     P->fwdblk = (RowBlock*)(base + o.fwdblk);
+    P->sspart = (RowBlock*)(base + o.sspart);
     P->pb_off = (int64_t*)(base + o.pb_off);
     P->tail_tasks = (TailTask*)(base + o.tail_tasks);
     P->tail_segs = (TailSeg*)(base + o.tail_segs);

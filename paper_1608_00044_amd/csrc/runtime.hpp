@@ -88,6 +88,9 @@ struct RowBlock { int32_t s; int32_t rb; };
 // kRowChunk rows below the diagonal block.
 constexpr int kColGroup = 8;
 constexpr int kRowChunk = 512;
+// Single-right-hand-side level solves: a large supernode's diagonal block is
+// applied by parts of kPartRows rows, one workgroup each.
+constexpr int kPartRows = 16;
 struct ColBlk { int32_t s; int16_t g, h; };  // column group g, row chunk h of supernode s
 // Deterministic order, apply pass: rows [ilo, ihi) of pair p's source that
 // land in one 64-row block of the target.
@@ -161,11 +164,13 @@ struct DevicePlan {
     int32_t* red_slot = nullptr;
     ColBlk* colblk = nullptr;        // backward (column group, row chunk) blocks
     RowBlock* fwdblk = nullptr;      // forward (supernode, 64-row block) blocks
+    RowBlock* sspart = nullptr;      // (supernode, 16-row part of its diagonal block)
     int64_t* pb_off = nullptr;       // per supernode: its partial sums (chunk h, column k at
                                      // pb_off + h w + k) in the backward work
     int64_t nslots = 0;              // entries of rows
     int64_t pb_total = 0;
     std::vector<int64_t> red_level_ptr, colblk_ptr, fwdblk_ptr;  // per level
+    std::vector<int64_t> sspart_ptr;  // per level
     // the tail's solve tasks: levels [tail_l0, levels) (none: tail_l0 = levels)
     int32_t tail_l0 = 0;
     int32_t ntail = 0;               // supernodes in the tail
@@ -329,5 +334,8 @@ int64_t solve_pb_elems(const Symbolic& S);
 // int32 words of the tail's task state (four counters per supernode, the
 // ticket and the abort and error words), at the end of the solve work.
 int64_t tail_state_words(const Symbolic& S);
+// int32 words of the single-right-hand-side level launches' counts (forward
+// and backward per supernode, the abort and error words), after the tail's.
+int64_t split_state_words(const Symbolic& S);
 
 }  // namespace spc

@@ -396,7 +396,7 @@ spc_status spc_server_add_pattern(spc_server* s, spc_symbolic* sym, int32_t* pat
     const size_t elem = S.opt.precision == 1 ? sizeof(float) : sizeof(double);
     p.bytes = numeric_bytes(sym) +
               (int64_t)elem * solve_work_elems_per_rhs(S) * (int64_t)s->opt.max_nrhs +
-              4 * tail_state_words(S);
+              4 * (tail_state_words(S) + split_state_words(S));
     p.plan_bytes = (int64_t)sym->plan_bytes_estimate;
     {
         // the pattern's device plan is made now, on the server's device, so

@@ -910,6 +910,226 @@ __global__ __launch_bounds__(256, 2) void k_tail(const TailTask* __restrict__ ta
     }
 }
 
+// ---------------------------------------------------------------------------
+// one right-hand side: each level's sweep in one launch, the diagonal block
+// split over workgroups
+// ---------------------------------------------------------------------------
+//
+// A large supernode's diagonal block costs a level kernel most of its time:
+// its inverse (up to 11k entries) read by one workgroup.  With one
+// right-hand side each level runs instead as one launch whose workgroups
+// split that product by parts of kPartRows rows, one workgroup per part,
+// and exchange the parts through device-scope stores and a per-supernode
+// count (zeroed before each solve; bounded waits as the tail's):
+//   forward:  parts   z_s[part] = (L11^{-1} y_s)[part] to zb, then count;
+//             blocks  (the 64-row blocks below, which load their part of L21
+//                     first) wait for every part of s, then
+//                     y[rows] -= L21 z_s as k_fwd_level;
+//   backward: blocks  the partial sums of L21^T x[rows below] as k_bwd_cols,
+//                     stored at device scope, then count;
+//             parts   (which load their rows of L11^{-1} first) wait for
+//                     every block of s, then
+//                     x_s[part] = (L11^{-T} (z_s - t_s))[part] into y.
+// Every waiting workgroup comes after all the workgroups it waits for in
+// the launch, and those wait on nothing, so the waits end whatever the
+// number of resident workgroups.  A part's product: 16 threads per row,
+// each over every 16th column, then a butterfly over the 16; one fixed
+// order, so a solve has the same bits on every run.  A wait that passes its
+// bound sets the abort and error words and leaves NaN in its outputs.
+
+__device__ __forceinline__ bool split_wait(const int32_t* p, int32_t want, int32_t* ctrl,
+                                           uint64_t deadline) {
+    return tail_wait(p, want, ctrl, deadline);
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_fwd_split(const RowBlock* __restrict__ parts,
+                                                   int32_t nparts,
+                                                   const RowBlock* __restrict__ work, KArgs a,
+                                                   const R* __restrict__ arena,
+                                                   const R* __restrict__ dinv,
+                                                   R* __restrict__ y, R* __restrict__ zb,
+                                                   int64_t n, SolveBufs<R> sb,
+                                                   int32_t* __restrict__ cnt,
+                                                   int32_t* __restrict__ ctrl, uint64_t ticks) {
+    constexpr int KW = kTriKW;  // columns per wave
+    constexpr int kPer = (kMaxWidth + 15) / 16;  // a part thread's columns
+    __shared__ R ys[kMaxWidth];
+    __shared__ R red[4][kTile];
+    __shared__ int ok_sh;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    if ((int)blockIdx.x < nparts) {
+        const RowBlock pt = parts[blockIdx.x];
+        const int s = pt.s, w = a.sn_w[s], first = a.sn_first[s];
+        // L11^{-T}, packed upper by columns: row i of L11^{-1} is contiguous
+        const R* __restrict__ LT = dinv + a.inv_off[s] + inverse_elems(w) + w * (w + 1) / 2;
+        const int i = pt.rb * kPartRows + (tid >> 4), j = tid & 15;
+        R lv[kPer], yv[kPer];
+#pragma unroll
+        for (int t = 0; t < kPer; ++t) {
+            const int k = j + 16 * t;
+            const bool in = i < w && k <= i;
+            lv[t] = in ? LT[(i * (i + 1) >> 1) + k] : R(0);
+            yv[t] = in ? y[first + k] : R(0);
+        }
+        R acc = R(0);
+#pragma unroll
+        for (int t = 0; t < kPer; ++t) acc += lv[t] * yv[t];
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if (j == 0 && i < w) st_dev(zb + first + i, acc);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (tid == 0) __hip_atomic_fetch_add(cnt + s, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+    const RowBlock wb = work[blockIdx.x - nparts];
+    const int s = wb.s;
+    const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
+    const int64_t rp = a.rowptr[s];
+    const int r = (int)(a.rowptr[s + 1] - rp) - w;
+    const int i0 = wb.rb * kTile, m = max(0, min(kTile, r - i0));
+    if (m == 0) return;  // a supernode with no rows below: its parts did the work
+    const R* __restrict__ P = arena + a.sn_off[s] + w;
+    const int32_t* __restrict__ below = a.rows + rp + w;
+    R lv[KW];
+#pragma unroll
+    for (int u = 0; u < KW; ++u) {
+        const int k = wave + 4 * u;
+        lv[u] = (lane < m && k < w) ? P[i0 + lane + (int64_t)k * ld] : R(0);
+    }
+    const int64_t slot = rp + w + i0 + tid;
+    const int32_t row = tid < m ? below[i0 + tid] : 0;
+    const bool sh = tid < m && sb.shared[slot];
+    const R yold = (tid < m && !sh) ? y[row] : R(0);
+    if (tid == 0)
+        ok_sh = split_wait(cnt + s, (w + kPartRows - 1) / kPartRows, ctrl,
+                           wall_clock64() + ticks);
+    __syncthreads();
+    const bool ok = ok_sh;
+    for (int k = tid; k < w; k += 256) ys[k] = ok ? ld_dev(zb + first + k) : R(NAN);
+    __syncthreads();
+    R acc = R(0);
+#pragma unroll
+    for (int u = 0; u < KW; ++u) {
+        const int k = wave + 4 * u;
+        if (k < w) acc += lv[u] * ys[k];
+    }
+    red[wave][lane] = acc;
+    __syncthreads();
+    if (tid < m) {
+        const R v = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+        if (sh) sb.cb[slot] = v;
+        else y[row] = yold - v;
+    }
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_bwd_split(const ColBlk* __restrict__ work,
+                                                   int32_t nblk,
+                                                   const RowBlock* __restrict__ parts, KArgs a,
+                                                   const R* __restrict__ arena,
+                                                   const R* __restrict__ dinv,
+                                                   R* __restrict__ y, const R* __restrict__ zb,
+                                                   R* __restrict__ pb,
+                                                   const int64_t* __restrict__ pb_off,
+                                                   int64_t pb_total, int64_t n,
+                                                   int32_t* __restrict__ cnt,
+                                                   int32_t* __restrict__ ctrl, uint64_t ticks) {
+    constexpr int G = kColGroup;
+    constexpr int kPer = (kMaxWidth + 15) / 16;
+    __shared__ R part[4][G];
+    __shared__ R us[kMaxWidth];
+    __shared__ int ok_sh;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    if ((int)blockIdx.x < nblk) {
+        // partial sums of L21^T y[rows] for the block's columns and rows, as k_bwd_cols
+        const ColBlk wb = work[blockIdx.x];
+        const int s = wb.s, g = wb.g, h = wb.h;
+        const int w = a.sn_w[s], ld = a.sn_ld[s];
+        const int64_t rp = a.rowptr[s];
+        const int k0 = g * G, kc = min(G, w - k0);
+        const int rb0 = h * kRowChunk;
+        const int r = min((int)(a.rowptr[s + 1] - rp) - w - rb0, kRowChunk);
+        const R* __restrict__ P = arena + a.sn_off[s] + w + rb0 + (int64_t)k0 * ld;
+        const int32_t* __restrict__ below = a.rows + rp + w + rb0;
+        R* __restrict__ out = pb + pb_off[s] + (int64_t)h * w + k0;
+        R acc[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) acc[k] = R(0);
+        for (int i0 = tid; i0 < r; i0 += 256 * 4) {
+            R yv[4], pv[4][G];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + 256 * u;
+                const int32_t row = i < r ? below[i] : 0;
+                yv[u] = i < r ? y[row] : R(0);
+#pragma unroll
+                for (int k = 0; k < G; ++k) pv[u][k] = (i < r && k < kc) ? P[i + (int64_t)k * ld] : R(0);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int k = 0; k < G; ++k) acc[k] += pv[u][k] * yv[u];
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            R v = acc[k];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0) part[wave][k] = v;
+        }
+        __syncthreads();
+        if (tid < kc) st_dev(out + tid, (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]));
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (tid == 0) __hip_atomic_fetch_add(cnt + s, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+    const RowBlock pt = parts[blockIdx.x - nblk];
+    const int s = pt.s, w = a.sn_w[s], first = a.sn_first[s];
+    const int r = (int)(a.rowptr[s + 1] - a.rowptr[s]) - w;
+    const int nh = r > 0 ? (r + kRowChunk - 1) / kRowChunk : 0;
+    const int nblk_s = nh * ((w + G - 1) / G);
+    // L11^{-1}, packed lower by columns: column i (rows i .. w - 1) is contiguous
+    const R* __restrict__ Li = dinv + a.inv_off[s] + inverse_elems(w);
+    const int p0 = pt.rb * kPartRows;
+    const int i = p0 + (tid >> 4), j = tid & 15;
+    R lv[kPer];
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+        const int k = i + j + 16 * t;
+        lv[t] = (i < w && k < w) ? Li[((i * (2 * w - i - 1)) >> 1) + k] : R(0);
+    }
+    if (tid == 0) ok_sh = nblk_s == 0 || split_wait(cnt + s, nblk_s, ctrl, wall_clock64() + ticks);
+    __syncthreads();
+    const bool ok = ok_sh;
+    // u = z_s - t_s for the columns from the part's first row on, the chunks'
+    // partial sums in chunk order
+    for (int k = p0 + tid; k < w; k += 256) {
+        R t = R(0);
+        const R* __restrict__ pk = pb + (r > 0 ? pb_off[s] : 0) + k;
+        for (int h0 = 0; h0 < nh; h0 += 8) {
+            R v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = h0 + q < nh ? ld_dev(pk + (int64_t)(h0 + q) * w) : R(0);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) t += v[q];
+        }
+        us[k] = ok ? zb[first + k] - t : R(NAN);
+    }
+    __syncthreads();
+    R acc = R(0);
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+        const int k = i + j + 16 * t;
+        if (i < w && k < w) acc += lv[t] * us[k];
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (j == 0 && i < w) y[first + i] = acc;
+}
+
 int32_t configure_solve_kernels() { return OK; }
 
 namespace {
@@ -932,12 +1152,34 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* work, hipStream_t st) {
     R* pb = cb + P->nslots * nrhs;
     const SolveBufs<R> sb{cb, P->nslots, P->slot_shared};
     const int32_t nl = P->tail_l0;  // levels below the tail go level by level
+    // one right-hand side: the split level launches and their counts
+    // (forward, backward, then the abort and error words), zeroed here
+    int32_t* cnt = (int32_t*)(pb + P->pb_total * nrhs) + tail_state_words(S);
+    const int64_t cwords = split_state_words(S);
+    uint64_t split_ticks = 0;
+    if (NR == 1 && nl > 0) {
+        hipLaunchKernelGGL(k_tail_reset, dim3((unsigned)((cwords + 255) / 256)), dim3(256), 0,
+                           st, cnt, cwords);
+        int dev = 0, clock_khz = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev);
+        const int64_t lim = S.opt.spin_limit > 0 ? S.opt.spin_limit : (int64_t)10000000;
+        split_ticks = (uint64_t)lim * (uint64_t)std::max(1, clock_khz) / 1000;
+    }
+    int32_t* cnt_f = cnt;
+    int32_t* cnt_b = cnt + S.nsup;
+    int32_t* ctrl = cnt + 2 * S.nsup;
     for (int32_t l = 0; l < nl; ++l) {
         const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1], nbig = P->level_nbig[l];
         launch_small_solve(num, a, P->level_sn + n0 + nbig, n1 - n0 - nbig, P->small_maxw[l],
                            P->small_maxm[l], y, cb, n, nrhs, true, st);
         const int64_t f0 = P->fwdblk_ptr[l], f1 = P->fwdblk_ptr[l + 1];
-        if (f1 > f0)
+        const int64_t p0 = P->sspart_ptr[l], p1 = P->sspart_ptr[l + 1];
+        if (NR == 1 && p1 > p0)
+            hipLaunchKernelGGL(k_fwd_split<R>, dim3((unsigned)((p1 - p0) + (f1 - f0))), dim3(256),
+                               0, st, P->sspart + p0, (int32_t)(p1 - p0), P->fwdblk + f0, a,
+                               arena, dinv, y, zb, n, sb, cnt_f, ctrl, split_ticks);
+        else if (f1 > f0)
             hipLaunchKernelGGL((k_fwd_level<R, NR>), dim3((unsigned)(f1 - f0)), dim3(256), 0, st,
                                P->fwdblk + f0, a, arena, dinv, y, zb, n, nrhs, sb);
         const int64_t i0 = P->red_level_ptr[l], i1 = P->red_level_ptr[l + 1];
@@ -972,7 +1214,13 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* work, hipStream_t st) {
     for (int32_t l = nl - 1; l >= 0; --l) {
         const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1], nbig = P->level_nbig[l];
         const int64_t g0 = P->colblk_ptr[l], g1 = P->colblk_ptr[l + 1];
-        if (g1 > g0) {
+        const int64_t p0 = P->sspart_ptr[l], p1 = P->sspart_ptr[l + 1];
+        if (NR == 1 && p1 > p0) {
+            hipLaunchKernelGGL(k_bwd_split<R>, dim3((unsigned)((g1 - g0) + (p1 - p0))), dim3(256),
+                               0, st, P->colblk + g0, (int32_t)(g1 - g0), P->sspart + p0, a,
+                               arena, dinv, y, (const R*)zb, pb, (const int64_t*)P->pb_off,
+                               P->pb_total, n, cnt_b, ctrl, split_ticks);
+        } else if (g1 > g0) {
             if constexpr (NR == 1)
                 hipLaunchKernelGGL((k_bwd_cols<R, NR>), dim3((unsigned)(g1 - g0)), dim3(256), 0,
                                    st, P->colblk + g0, a, arena, (const R*)y, pb,
@@ -982,7 +1230,7 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* work, hipStream_t st) {
                                    dim3(256), 0, st, P->colblk + g0, a, arena, (const R*)y, pb,
                                    (const int64_t*)P->pb_off, P->pb_total, n, nrhs);
         }
-        if (nbig > 0)
+        if (nbig > 0 && !(NR == 1 && p1 > p0))
             hipLaunchKernelGGL((k_bwd_diag<R, NR>), dim3((unsigned)nbig), dim3(256), 0, st,
                                P->level_sn + n0, a, dinv, y, (const R*)zb, (const R*)pb,
                                (const int64_t*)P->pb_off, P->pb_total, n, nrhs);
@@ -1008,7 +1256,7 @@ void drop_solve_graphs(spc_numeric* num) {
 // more).
 int64_t solve_work_elems(const spc_numeric* num, int32_t nrhs) {
     const Symbolic& S = num->sym->S;
-    const int64_t words = tail_state_words(S);
+    const int64_t words = tail_state_words(S) + split_state_words(S);
     const int64_t esz = num->prec == 1 ? 4 : 8;
     return solve_work_elems_per_rhs(S) * (int64_t)nrhs + (words * 4 + esz - 1) / esz;
 }
@@ -1121,8 +1369,8 @@ int32_t run_solve(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb, 
 // ---------------------------------------------------------------------------
 
 // Work of spc_solve_noalloc: one static array per device, held until the
-// process ends.  Every element a solve reads it has written first, so no
-// part needs clearing between calls.
+// process ends.  Every element a solve reads it has written first (the
+// sweeps zero their own counts), so no part needs clearing between calls.
 constexpr size_t kNoAllocBytes = size_t(64) << 20;
 __device__ __align__(256) double scratch[kNoAllocBytes / sizeof(double)];
 
