@@ -1130,6 +1130,262 @@ __global__ __launch_bounds__(256) void k_bwd_split(const ColBlk* __restrict__ wo
     if (j == 0 && i < w) y[first + i] = acc;
 }
 
+// The same split launches for NR right-hand sides at a time (groups of NR
+// columns in turn): a part stages y_s (or u) for its group in LDS, each
+// thread keeps NR sums; the 64-row blocks below as k_fwd_level and the
+// column blocks as k_bwd_cols_multi, with device-scope stores and counts.
+template <class R, int NR>
+__global__ __launch_bounds__(256) void k_fwd_split_m(const RowBlock* __restrict__ parts,
+                                                     int32_t nparts,
+                                                     const RowBlock* __restrict__ work, KArgs a,
+                                                     const R* __restrict__ arena,
+                                                     const R* __restrict__ dinv,
+                                                     R* __restrict__ y, R* __restrict__ zb,
+                                                     int64_t n, int nrhs, SolveBufs<R> sb,
+                                                     int32_t* __restrict__ cnt,
+                                                     int32_t* __restrict__ ctrl, uint64_t ticks) {
+    constexpr int KW = kTriKW;
+    constexpr int kPer = (kMaxWidth + 15) / 16;
+    __shared__ R ys[kMaxWidth][NR + 1];
+    __shared__ R red[4][NR][kTile];
+    __shared__ int ok_sh;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    if ((int)blockIdx.x < nparts) {
+        const RowBlock pt = parts[blockIdx.x];
+        const int s = pt.s, w = a.sn_w[s], first = a.sn_first[s];
+        const R* __restrict__ LT = dinv + a.inv_off[s] + inverse_elems(w) + w * (w + 1) / 2;
+        const int i = pt.rb * kPartRows + (tid >> 4), j = tid & 15;
+        R lv[kPer];
+#pragma unroll
+        for (int t = 0; t < kPer; ++t) {
+            const int k = j + 16 * t;
+            lv[t] = (i < w && k <= i) ? LT[(i * (i + 1) >> 1) + k] : R(0);
+        }
+        const int kend = min(w, pt.rb * kPartRows + kPartRows);  // columns the part needs
+        for (int c0 = 0; c0 < nrhs; c0 += NR) {
+            const int nc = min(NR, nrhs - c0);
+            for (int e = tid; e < kend * NR; e += 256) {
+                const int k = e / NR, c = e % NR;
+                ys[k][c] = c < nc ? y[(int64_t)(c0 + c) * n + first + k] : R(0);
+            }
+            __syncthreads();
+            R acc[NR];
+#pragma unroll
+            for (int c = 0; c < NR; ++c) acc[c] = R(0);
+#pragma unroll
+            for (int t = 0; t < kPer; ++t) {
+                const int k = j + 16 * t;
+                if (i < w && k <= i) {
+#pragma unroll
+                    for (int c = 0; c < NR; ++c) acc[c] += lv[t] * ys[k][c];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < NR; ++c) {
+#pragma unroll
+                for (int o = 8; o > 0; o >>= 1) acc[c] += __shfl_xor(acc[c], o, 64);
+                if (j == 0 && i < w && c < nc) st_dev(zb + (int64_t)(c0 + c) * n + first + i, acc[c]);
+            }
+            __syncthreads();
+        }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (tid == 0) __hip_atomic_fetch_add(cnt + s, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+    const RowBlock wb = work[blockIdx.x - nparts];
+    const int s = wb.s;
+    const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
+    const int64_t rp = a.rowptr[s];
+    const int r = (int)(a.rowptr[s + 1] - rp) - w;
+    const int i0 = wb.rb * kTile, m = max(0, min(kTile, r - i0));
+    if (m == 0) return;
+    const R* __restrict__ P = arena + a.sn_off[s] + w;
+    const int32_t* __restrict__ below = a.rows + rp + w;
+    R lv[KW];
+#pragma unroll
+    for (int u = 0; u < KW; ++u) {
+        const int k = wave + 4 * u;
+        lv[u] = (lane < m && k < w) ? P[i0 + lane + (int64_t)k * ld] : R(0);
+    }
+    const int64_t slot = rp + w + i0 + tid;
+    const int32_t row = tid < m ? below[i0 + tid] : 0;
+    const bool sh = tid < m && sb.shared[slot];
+    if (tid == 0)
+        ok_sh = split_wait(cnt + s, (w + kPartRows - 1) / kPartRows, ctrl,
+                           wall_clock64() + ticks);
+    __syncthreads();
+    const bool ok = ok_sh;
+    for (int c0 = 0; c0 < nrhs; c0 += NR) {
+        const int nc = min(NR, nrhs - c0);
+        R yold[NR];
+#pragma unroll
+        for (int c = 0; c < NR; ++c)
+            yold[c] = (tid < m && !sh && c < nc) ? y[(int64_t)(c0 + c) * n + row] : R(0);
+        for (int e = tid; e < w * NR; e += 256) {
+            const int k = e / NR, c = e % NR;
+            ys[k][c] = c < nc ? (ok ? ld_dev(zb + (int64_t)(c0 + c) * n + first + k) : R(NAN))
+                              : R(0);
+        }
+        __syncthreads();
+        R acc[NR];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) acc[c] = R(0);
+#pragma unroll
+        for (int u = 0; u < KW; ++u) {
+            const int k = wave + 4 * u;
+            if (k < w) {
+#pragma unroll
+                for (int c = 0; c < NR; ++c) acc[c] += lv[u] * ys[k][c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NR; ++c) red[wave][c][lane] = acc[c];
+        __syncthreads();
+        if (tid < m) {
+#pragma unroll
+            for (int c = 0; c < NR; ++c) {
+                if (c >= nc) break;
+                const R v = (red[0][c][tid] + red[1][c][tid]) + (red[2][c][tid] + red[3][c][tid]);
+                if (sh) sb.cb[(int64_t)(c0 + c) * sb.nslots + slot] = v;
+                else y[(int64_t)(c0 + c) * n + row] = yold[c] - v;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <class R, int NR>
+__global__ __launch_bounds__(256) void k_bwd_split_m(const ColBlk* __restrict__ work,
+                                                     int32_t nblk,
+                                                     const RowBlock* __restrict__ parts, KArgs a,
+                                                     const R* __restrict__ arena,
+                                                     const R* __restrict__ dinv,
+                                                     R* __restrict__ y, const R* __restrict__ zb,
+                                                     R* __restrict__ pb,
+                                                     const int64_t* __restrict__ pb_off,
+                                                     int64_t pb_total, int64_t n, int nrhs,
+                                                     int32_t* __restrict__ cnt,
+                                                     int32_t* __restrict__ ctrl, uint64_t ticks) {
+    constexpr int G = kColGroup;
+    static_assert(G * NR * 4 == 256, "one thread per (column, right-hand side, quarter)");
+    constexpr int kRows = 256;
+    constexpr int kPer = (kMaxWidth + 15) / 16;
+    __shared__ R Ls[kRows][G + 1];
+    __shared__ R Xs[kRows][NR + 1];
+    __shared__ R part[4][G][NR];
+    __shared__ int ok_sh;
+    const int tid = threadIdx.x;
+    if ((int)blockIdx.x < nblk) {
+        // the column block's partial sums, as k_bwd_cols_multi
+        const ColBlk wb = work[blockIdx.x];
+        const int s = wb.s, g = wb.g, h = wb.h;
+        const int w = a.sn_w[s], ld = a.sn_ld[s];
+        const int64_t rp = a.rowptr[s];
+        const int k0 = g * G, kc = min(G, w - k0);
+        const int rb0 = h * kRowChunk;
+        const int r = min((int)(a.rowptr[s + 1] - rp) - w - rb0, kRowChunk);
+        const R* __restrict__ P = arena + a.sn_off[s] + w + rb0 + (int64_t)k0 * ld;
+        const int32_t* __restrict__ below = a.rows + rp + w + rb0;
+        R* __restrict__ out = pb + pb_off[s] + (int64_t)h * w + k0;
+        const int k = tid % G, c = (tid / G) % NR, q = tid / (G * NR);
+        for (int c0 = 0; c0 < nrhs; c0 += NR) {
+            const int nc = min(NR, nrhs - c0);
+            R acc = R(0);
+            for (int i0 = 0; i0 < r; i0 += kRows) {
+                const int i = i0 + tid;
+                const int32_t row = i < r ? below[i] : 0;
+                R lv[G], xv[NR];
+#pragma unroll
+                for (int kk = 0; kk < G; ++kk)
+                    lv[kk] = (i < r && kk < kc) ? P[i + (int64_t)kk * ld] : R(0);
+#pragma unroll
+                for (int cc = 0; cc < NR; ++cc)
+                    xv[cc] = (i < r && cc < nc) ? y[(int64_t)(c0 + cc) * n + row] : R(0);
+#pragma unroll
+                for (int kk = 0; kk < G; ++kk) Ls[tid][kk] = lv[kk];
+#pragma unroll
+                for (int cc = 0; cc < NR; ++cc) Xs[tid][cc] = xv[cc];
+                __syncthreads();
+                const int j0 = q * (kRows / 4);
+#pragma unroll 8
+                for (int jj = j0; jj < j0 + kRows / 4; ++jj) acc += Ls[jj][k] * Xs[jj][c];
+                __syncthreads();
+            }
+            part[q][k][c] = acc;
+            __syncthreads();
+            if (tid < G * NR) {
+                const int kk = tid % G, cc = tid / G;
+                if (kk < kc && cc < nc)
+                    st_dev(out + (int64_t)(c0 + cc) * pb_total + kk,
+                           (part[0][kk][cc] + part[1][kk][cc]) + (part[2][kk][cc] + part[3][kk][cc]));
+            }
+            __syncthreads();
+        }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (tid == 0) __hip_atomic_fetch_add(cnt + s, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+    R (*us)[NR + 1] = Xs;  // u = z_s - t_s by column, from the part's first row on
+    const RowBlock pt = parts[blockIdx.x - nblk];
+    const int s = pt.s, w = a.sn_w[s], first = a.sn_first[s];
+    const int r = (int)(a.rowptr[s + 1] - a.rowptr[s]) - w;
+    const int nh = r > 0 ? (r + kRowChunk - 1) / kRowChunk : 0;
+    const int nblk_s = nh * ((w + G - 1) / G);
+    const R* __restrict__ Li = dinv + a.inv_off[s] + inverse_elems(w);
+    const int p0 = pt.rb * kPartRows;
+    const int i = p0 + (tid >> 4), j = tid & 15;
+    R lv[kPer];
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+        const int k = i + j + 16 * t;
+        lv[t] = (i < w && k < w) ? Li[((i * (2 * w - i - 1)) >> 1) + k] : R(0);
+    }
+    if (tid == 0) ok_sh = nblk_s == 0 || split_wait(cnt + s, nblk_s, ctrl, wall_clock64() + ticks);
+    __syncthreads();
+    const bool ok = ok_sh;
+    const R* __restrict__ ps = pb + (r > 0 ? pb_off[s] : 0);
+    for (int c0 = 0; c0 < nrhs; c0 += NR) {
+        const int nc = min(NR, nrhs - c0);
+        for (int e = tid; e < (w - p0) * NR; e += 256) {
+            const int k = p0 + e / NR, c = e % NR;
+            R t = R(0);
+            if (c < nc) {
+                const R* __restrict__ pk = ps + (int64_t)(c0 + c) * pb_total + k;
+                for (int h0 = 0; h0 < nh; h0 += 8) {
+                    R v[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        v[q] = h0 + q < nh ? ld_dev(pk + (int64_t)(h0 + q) * w) : R(0);
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) t += v[q];
+                }
+            }
+            us[k - p0][c] = c < nc ? (ok ? zb[(int64_t)(c0 + c) * n + first + k] - t : R(NAN)) : R(0);
+        }
+        __syncthreads();
+        R acc[NR];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) acc[c] = R(0);
+#pragma unroll
+        for (int t = 0; t < kPer; ++t) {
+            const int k = i + j + 16 * t;
+            if (i < w && k < w) {
+#pragma unroll
+                for (int c = 0; c < NR; ++c) acc[c] += lv[t] * us[k - p0][c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1) acc[c] += __shfl_xor(acc[c], o, 64);
+            if (j == 0 && i < w && c < nc) y[(int64_t)(c0 + c) * n + first + i] = acc[c];
+        }
+        __syncthreads();
+    }
+}
+
 int32_t configure_solve_kernels() { return OK; }
 
 namespace {
@@ -1157,7 +1413,7 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* work, hipStream_t st) {
     int32_t* cnt = (int32_t*)(pb + P->pb_total * nrhs) + tail_state_words(S);
     const int64_t cwords = split_state_words(S);
     uint64_t split_ticks = 0;
-    if (NR == 1 && nl > 0) {
+    if (nl > 0) {
         hipLaunchKernelGGL(k_tail_reset, dim3((unsigned)((cwords + 255) / 256)), dim3(256), 0,
                            st, cnt, cwords);
         int dev = 0, clock_khz = 0;
@@ -1175,11 +1431,18 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* work, hipStream_t st) {
                            P->small_maxm[l], y, cb, n, nrhs, true, st);
         const int64_t f0 = P->fwdblk_ptr[l], f1 = P->fwdblk_ptr[l + 1];
         const int64_t p0 = P->sspart_ptr[l], p1 = P->sspart_ptr[l + 1];
-        if (NR == 1 && p1 > p0)
-            hipLaunchKernelGGL(k_fwd_split<R>, dim3((unsigned)((p1 - p0) + (f1 - f0))), dim3(256),
-                               0, st, P->sspart + p0, (int32_t)(p1 - p0), P->fwdblk + f0, a,
-                               arena, dinv, y, zb, n, sb, cnt_f, ctrl, split_ticks);
-        else if (f1 > f0)
+        if (p1 > p0) {
+            if constexpr (NR == 1)
+                hipLaunchKernelGGL(k_fwd_split<R>, dim3((unsigned)((p1 - p0) + (f1 - f0))),
+                                   dim3(256), 0, st, P->sspart + p0, (int32_t)(p1 - p0),
+                                   P->fwdblk + f0, a, arena, dinv, y, zb, n, sb, cnt_f, ctrl,
+                                   split_ticks);
+            else
+                hipLaunchKernelGGL((k_fwd_split_m<R, NR>),
+                                   dim3((unsigned)((p1 - p0) + (f1 - f0))), dim3(256), 0, st,
+                                   P->sspart + p0, (int32_t)(p1 - p0), P->fwdblk + f0, a, arena,
+                                   dinv, y, zb, n, nrhs, sb, cnt_f, ctrl, split_ticks);
+        } else if (f1 > f0)
             hipLaunchKernelGGL((k_fwd_level<R, NR>), dim3((unsigned)(f1 - f0)), dim3(256), 0, st,
                                P->fwdblk + f0, a, arena, dinv, y, zb, n, nrhs, sb);
         const int64_t i0 = P->red_level_ptr[l], i1 = P->red_level_ptr[l + 1];
@@ -1215,11 +1478,19 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* work, hipStream_t st) {
         const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1], nbig = P->level_nbig[l];
         const int64_t g0 = P->colblk_ptr[l], g1 = P->colblk_ptr[l + 1];
         const int64_t p0 = P->sspart_ptr[l], p1 = P->sspart_ptr[l + 1];
-        if (NR == 1 && p1 > p0) {
-            hipLaunchKernelGGL(k_bwd_split<R>, dim3((unsigned)((g1 - g0) + (p1 - p0))), dim3(256),
-                               0, st, P->colblk + g0, (int32_t)(g1 - g0), P->sspart + p0, a,
-                               arena, dinv, y, (const R*)zb, pb, (const int64_t*)P->pb_off,
-                               P->pb_total, n, cnt_b, ctrl, split_ticks);
+        if (p1 > p0) {
+            if constexpr (NR == 1)
+                hipLaunchKernelGGL(k_bwd_split<R>, dim3((unsigned)((g1 - g0) + (p1 - p0))),
+                                   dim3(256), 0, st, P->colblk + g0, (int32_t)(g1 - g0),
+                                   P->sspart + p0, a, arena, dinv, y, (const R*)zb, pb,
+                                   (const int64_t*)P->pb_off, P->pb_total, n, cnt_b, ctrl,
+                                   split_ticks);
+            else
+                hipLaunchKernelGGL((k_bwd_split_m<R, NR>),
+                                   dim3((unsigned)((g1 - g0) + (p1 - p0))), dim3(256), 0, st,
+                                   P->colblk + g0, (int32_t)(g1 - g0), P->sspart + p0, a, arena,
+                                   dinv, y, (const R*)zb, pb, (const int64_t*)P->pb_off,
+                                   P->pb_total, n, nrhs, cnt_b, ctrl, split_ticks);
         } else if (g1 > g0) {
             if constexpr (NR == 1)
                 hipLaunchKernelGGL((k_bwd_cols<R, NR>), dim3((unsigned)(g1 - g0)), dim3(256), 0,
@@ -1230,7 +1501,7 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* work, hipStream_t st) {
                                    dim3(256), 0, st, P->colblk + g0, a, arena, (const R*)y, pb,
                                    (const int64_t*)P->pb_off, P->pb_total, n, nrhs);
         }
-        if (nbig > 0 && !(NR == 1 && p1 > p0))
+        if (nbig > 0 && p1 <= p0)
             hipLaunchKernelGGL((k_bwd_diag<R, NR>), dim3((unsigned)nbig), dim3(256), 0, st,
                                P->level_sn + n0, a, dinv, y, (const R*)zb, (const R*)pb,
                                (const int64_t*)P->pb_off, P->pb_total, n, nrhs);
