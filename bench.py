@@ -967,7 +967,7 @@ def main():
            "solve": {"algorithmic_bytes": hb["solve"], "ms": p50,
                      "GBps": hb["solve"] / (p50 * 1e-3) / 1e9,
                      "frac": hb["solve"] / (p50 * 1e-3) / 1e9 / HBM_PEAK_GBPS,
-                     "note": "p50 single-RHS solve; latency bound (one launch pair per level)"},
+                     "note": "p50 single-RHS solve; latency bound (one launch per level and direction, plus the forward's shared-row reductions)"},
            "scatter": {"algorithmic_bytes": hb["scatter"], "ms": kern["update"] / args.steps,
                        "GBps": hb["scatter"] / (kern["update"] / args.steps * 1e-3) / 1e9
                        if kern["update"] > 0 else 0.0,
