@@ -74,11 +74,14 @@ typedef struct spc_options {
                                  queue (dependency counters, Section IV)        */
     double amalg_ratio;       /* relaxed amalgamation zero ratio; 0 = off (default) */
     int64_t mem_budget_bytes; /* device bytes a factor may hold; 0 = no limit       */
-    int64_t spin_limit;       /* sched 2: bound on every device wait, in microseconds;
-                                 past it the factorization stops and its status
-                                 reads SPC_ERR_TIMEOUT; 0 = default (ten seconds) */
-    int32_t debug_flags;      /* bit 0: withhold one dependency count so that the
-                                 bounded wait fires (testing only); bit 1: sched 2
+    int64_t spin_limit;       /* bound on every device wait, in microseconds: sched 2
+                                 (past it the factorization stops and its status
+                                 reads SPC_ERR_TIMEOUT) and the solves' level
+                                 launches (past it the solution holds NaN); 0 =
+                                 default (ten seconds)                          */
+    int32_t debug_flags;      /* bit 0: withhold one dependency count (sched 2) and
+                                 one count of every solve wait, so that the bounded
+                                 waits fire (testing only); bit 1: sched 2
                                  records when every task starts and finishes
                                  (spc_numeric_task_log); default 0               */
     int32_t precision;        /* 0 = FP64 factor (default); 1 = FP32 factor on FP32
@@ -247,7 +250,9 @@ spc_status spc_numeric_status(spc_numeric* num);
  * device arrays (leading dimensions ldb, ldx >= n) of doubles; x_dev may equal
  * b_dev when ldx == ldb.  Synchronizes on the factor status first: a failed
  * factor returns its status (> 0) and leaves x_dev untouched.  Enqueued on
- * stream, otherwise asynchronous. */
+ * stream, otherwise asynchronous.  The workgroups of a level wait on each
+ * other through device-side counts (bounded by spin_limit); a wait past its
+ * bound leaves NaN in x_dev. */
 spc_status spc_solve(spc_numeric* num, int32_t nrhs, const double* b_dev, int64_t ldb,
                      double* x_dev, int64_t ldx, void* stream);
 

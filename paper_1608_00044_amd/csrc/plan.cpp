@@ -500,7 +500,7 @@ int64_t tail_state_words(const Symbolic& S) {
     return 4 * (int64_t)(S.level_ptr[nl] - S.level_ptr[l0]) + 4;
 }
 
-int64_t split_state_words(const Symbolic& S) { return 2 * S.nsup + 2; }
+int64_t split_state_words(const Symbolic& S) { return 2 * S.nsup + 3; }
 
 int64_t inverse_blocks_elems(const Symbolic& S) {
     int64_t t = 0;

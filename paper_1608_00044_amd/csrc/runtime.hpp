@@ -334,8 +334,9 @@ int64_t solve_pb_elems(const Symbolic& S);
 // int32 words of the tail's task state (four counters per supernode, the
 // ticket and the abort and error words), at the end of the solve work.
 int64_t tail_state_words(const Symbolic& S);
-// int32 words of the single-right-hand-side level launches' counts (forward
-// and backward per supernode, the abort and error words), after the tail's.
+// int32 words of the split level launches' counts (forward and backward per
+// supernode, then three control words: unused, abort, error, as the tail's
+// waits address them), after the tail's.
 int64_t split_state_words(const Symbolic& S);
 
 }  // namespace spc

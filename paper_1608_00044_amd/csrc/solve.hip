@@ -951,7 +951,8 @@ __global__ __launch_bounds__(256) void k_fwd_split(const RowBlock* __restrict__ 
                                                    R* __restrict__ y, R* __restrict__ zb,
                                                    int64_t n, SolveBufs<R> sb,
                                                    int32_t* __restrict__ cnt,
-                                                   int32_t* __restrict__ ctrl, uint64_t ticks) {
+                                                   int32_t* __restrict__ ctrl, uint64_t ticks,
+                                                   int32_t extra) {
     constexpr int KW = kTriKW;  // columns per wave
     constexpr int kPer = (kMaxWidth + 15) / 16;  // a part thread's columns
     __shared__ R ys[kMaxWidth];
@@ -1003,7 +1004,7 @@ __global__ __launch_bounds__(256) void k_fwd_split(const RowBlock* __restrict__ 
     const bool sh = tid < m && sb.shared[slot];
     const R yold = (tid < m && !sh) ? y[row] : R(0);
     if (tid == 0)
-        ok_sh = split_wait(cnt + s, (w + kPartRows - 1) / kPartRows, ctrl,
+        ok_sh = split_wait(cnt + s, (w + kPartRows - 1) / kPartRows + extra, ctrl,
                            wall_clock64() + ticks);
     __syncthreads();
     const bool ok = ok_sh;
@@ -1035,7 +1036,8 @@ __global__ __launch_bounds__(256) void k_bwd_split(const ColBlk* __restrict__ wo
                                                    const int64_t* __restrict__ pb_off,
                                                    int64_t pb_total, int64_t n,
                                                    int32_t* __restrict__ cnt,
-                                                   int32_t* __restrict__ ctrl, uint64_t ticks) {
+                                                   int32_t* __restrict__ ctrl, uint64_t ticks,
+                                                   int32_t extra) {
     constexpr int G = kColGroup;
     constexpr int kPer = (kMaxWidth + 15) / 16;
     __shared__ R part[4][G];
@@ -1101,7 +1103,8 @@ __global__ __launch_bounds__(256) void k_bwd_split(const ColBlk* __restrict__ wo
         const int k = i + j + 16 * t;
         lv[t] = (i < w && k < w) ? Li[((i * (2 * w - i - 1)) >> 1) + k] : R(0);
     }
-    if (tid == 0) ok_sh = nblk_s == 0 || split_wait(cnt + s, nblk_s, ctrl, wall_clock64() + ticks);
+    if (tid == 0)
+        ok_sh = nblk_s == 0 || split_wait(cnt + s, nblk_s + extra, ctrl, wall_clock64() + ticks);
     __syncthreads();
     const bool ok = ok_sh;
     // u = z_s - t_s for the columns from the part's first row on, the chunks'
@@ -1143,7 +1146,8 @@ __global__ __launch_bounds__(256) void k_fwd_split_m(const RowBlock* __restrict_
                                                      R* __restrict__ y, R* __restrict__ zb,
                                                      int64_t n, int nrhs, SolveBufs<R> sb,
                                                      int32_t* __restrict__ cnt,
-                                                     int32_t* __restrict__ ctrl, uint64_t ticks) {
+                                                     int32_t* __restrict__ ctrl, uint64_t ticks,
+                                                     int32_t extra) {
     constexpr int KW = kTriKW;
     constexpr int kPer = (kMaxWidth + 15) / 16;
     __shared__ R ys[kMaxWidth][NR + 1];
@@ -1212,7 +1216,7 @@ __global__ __launch_bounds__(256) void k_fwd_split_m(const RowBlock* __restrict_
     const int32_t row = tid < m ? below[i0 + tid] : 0;
     const bool sh = tid < m && sb.shared[slot];
     if (tid == 0)
-        ok_sh = split_wait(cnt + s, (w + kPartRows - 1) / kPartRows, ctrl,
+        ok_sh = split_wait(cnt + s, (w + kPartRows - 1) / kPartRows + extra, ctrl,
                            wall_clock64() + ticks);
     __syncthreads();
     const bool ok = ok_sh;
@@ -1266,7 +1270,8 @@ __global__ __launch_bounds__(256) void k_bwd_split_m(const ColBlk* __restrict__ 
                                                      const int64_t* __restrict__ pb_off,
                                                      int64_t pb_total, int64_t n, int nrhs,
                                                      int32_t* __restrict__ cnt,
-                                                     int32_t* __restrict__ ctrl, uint64_t ticks) {
+                                                     int32_t* __restrict__ ctrl, uint64_t ticks,
+                                                     int32_t extra) {
     constexpr int G = kColGroup;
     static_assert(G * NR * 4 == 256, "one thread per (column, right-hand side, quarter)");
     constexpr int kRows = 256;
@@ -1342,7 +1347,8 @@ __global__ __launch_bounds__(256) void k_bwd_split_m(const ColBlk* __restrict__ 
         const int k = i + j + 16 * t;
         lv[t] = (i < w && k < w) ? Li[((i * (2 * w - i - 1)) >> 1) + k] : R(0);
     }
-    if (tid == 0) ok_sh = nblk_s == 0 || split_wait(cnt + s, nblk_s, ctrl, wall_clock64() + ticks);
+    if (tid == 0)
+        ok_sh = nblk_s == 0 || split_wait(cnt + s, nblk_s + extra, ctrl, wall_clock64() + ticks);
     __syncthreads();
     const bool ok = ok_sh;
     const R* __restrict__ ps = pb + (r > 0 ? pb_off[s] : 0);
@@ -1408,8 +1414,8 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* work, hipStream_t st) {
     R* pb = cb + P->nslots * nrhs;
     const SolveBufs<R> sb{cb, P->nslots, P->slot_shared};
     const int32_t nl = P->tail_l0;  // levels below the tail go level by level
-    // one right-hand side: the split level launches and their counts
-    // (forward, backward, then the abort and error words), zeroed here
+    // the split level launches' counts (forward, backward, then the control
+    // words: ctrl[1] abort, ctrl[2] error, as tail_wait uses them), zeroed here
     int32_t* cnt = (int32_t*)(pb + P->pb_total * nrhs) + tail_state_words(S);
     const int64_t cwords = split_state_words(S);
     uint64_t split_ticks = 0;
@@ -1425,6 +1431,8 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* work, hipStream_t st) {
     int32_t* cnt_f = cnt;
     int32_t* cnt_b = cnt + S.nsup;
     int32_t* ctrl = cnt + 2 * S.nsup;
+    // debug bit 0 withholds one count from every wait, so that each bound fires
+    const int32_t extra = (S.opt.debug_flags & 1) ? 1 : 0;
     for (int32_t l = 0; l < nl; ++l) {
         const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1], nbig = P->level_nbig[l];
         launch_small_solve(num, a, P->level_sn + n0 + nbig, n1 - n0 - nbig, P->small_maxw[l],
@@ -1436,12 +1444,12 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* work, hipStream_t st) {
                 hipLaunchKernelGGL(k_fwd_split<R>, dim3((unsigned)((p1 - p0) + (f1 - f0))),
                                    dim3(256), 0, st, P->sspart + p0, (int32_t)(p1 - p0),
                                    P->fwdblk + f0, a, arena, dinv, y, zb, n, sb, cnt_f, ctrl,
-                                   split_ticks);
+                                   split_ticks, extra);
             else
                 hipLaunchKernelGGL((k_fwd_split_m<R, NR>),
                                    dim3((unsigned)((p1 - p0) + (f1 - f0))), dim3(256), 0, st,
                                    P->sspart + p0, (int32_t)(p1 - p0), P->fwdblk + f0, a, arena,
-                                   dinv, y, zb, n, nrhs, sb, cnt_f, ctrl, split_ticks);
+                                   dinv, y, zb, n, nrhs, sb, cnt_f, ctrl, split_ticks, extra);
         } else if (f1 > f0)
             hipLaunchKernelGGL((k_fwd_level<R, NR>), dim3((unsigned)(f1 - f0)), dim3(256), 0, st,
                                P->fwdblk + f0, a, arena, dinv, y, zb, n, nrhs, sb);
@@ -1484,13 +1492,13 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* work, hipStream_t st) {
                                    dim3(256), 0, st, P->colblk + g0, (int32_t)(g1 - g0),
                                    P->sspart + p0, a, arena, dinv, y, (const R*)zb, pb,
                                    (const int64_t*)P->pb_off, P->pb_total, n, cnt_b, ctrl,
-                                   split_ticks);
+                                   split_ticks, extra);
             else
                 hipLaunchKernelGGL((k_bwd_split_m<R, NR>),
                                    dim3((unsigned)((g1 - g0) + (p1 - p0))), dim3(256), 0, st,
                                    P->colblk + g0, (int32_t)(g1 - g0), P->sspart + p0, a, arena,
                                    dinv, y, (const R*)zb, pb, (const int64_t*)P->pb_off,
-                                   P->pb_total, n, nrhs, cnt_b, ctrl, split_ticks);
+                                   P->pb_total, n, nrhs, cnt_b, ctrl, split_ticks, extra);
         } else if (g1 > g0) {
             if constexpr (NR == 1)
                 hipLaunchKernelGGL((k_bwd_cols<R, NR>), dim3((unsigned)(g1 - g0)), dim3(256), 0,

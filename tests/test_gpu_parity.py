@@ -211,6 +211,31 @@ def test_task_queue_bounded_wait_reports_timeout():
     assert num2.status() == 0
 
 
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_solve_bounded_wait_leaves_nan(nrhs):
+    """The solves' level launches wait on device-side counts; with one count
+    withheld (debug flag) every wait passes its bound (2 ms), every
+    workgroup still exits, and the solution holds NaN instead of numbers
+    computed from data that never arrived; the device stays usable."""
+    torch = torch_dev()
+    p = inputs.make_grid_problem("lap", (12, 12, 12), 5, sigma=1.0, shift=1e-3, nrhs=nrhs)
+    sym = spchol.analyze(p.n, p.colptr, p.rowind, p.perm, spin_limit=2000, debug_flags=1)
+    vals = torch.from_numpy(p.values).to("cuda:0")
+    num = spchol.factor(sym, vals)
+    assert num.status() == 0  # the level-set factorization has no waits
+    b = torch.from_numpy(np.ascontiguousarray(p.rhs)).to("cuda:0")
+    x = num.solve(b if nrhs > 1 else b[:, 0]).cpu().numpy()
+    say("nrhs", nrhs, "NaN entries", int(np.isnan(x).sum()), "of", x.size)
+    assert np.isnan(x).any()
+    num.free()
+    sym.free()
+    sym2, num2, _ = gpu_factor(p)
+    x2 = num2.solve(b if nrhs > 1 else b[:, 0]).cpu().numpy()
+    eta = oracle.backward_error(p.n, p.colptr, p.rowind, p.values, p.rhs,
+                                x2.reshape(p.n, -1))
+    assert eta.max() <= 1e-14
+
+
 def test_nan_value_reports_status():
     n = 50
     p = inputs.tridiag(n)
