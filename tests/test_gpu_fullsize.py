@@ -178,3 +178,47 @@ def test_lap3d_64_factor_matches_stored_oracle_entries(deterministic):
     assert worst <= 1.0
     num.free()
     sym.free()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_elast27_48_solution_matches_stored_oracle_solution(precision):
+    """The 27-point 48^3 problem's solution (FP64 factor and solve, or FP32
+    factor + FP64 refinement to 1e-10) against the FP64 oracle's solution of
+    the same eight right-hand sides, stored once by
+    tests/golden/make_oracle_solution.py: both are backward stable, so they
+    differ by at most 4 cond(A) (eta_gpu + eta_oracle) in the max norm,
+    cond(A) <= ||A||_inf / shift (the edge blocks form a positive
+    semidefinite operator)."""
+    import scipy.sparse as sp
+
+    from tests.golden.make_oracle_solution import load
+
+    torch = torch_dev()
+    ref = load("elast27_48")
+    assert ref is not None, "oracle solution missing or written by another oracle/input version"
+    xo, meta = ref
+    p = inputs.make_workload("elast27_48")
+    xo = xo.reshape(p.n, -1)
+    sym = spchol.analyze(p.n, p.colptr, p.rowind, p.perm, sn_cap=150,
+                         amalg_ratio=p.meta["amalg"], precision=precision)
+    vals = torch.from_numpy(p.values).to("cuda:0")
+    num = spchol.factor(sym, vals)
+    assert num.status() == 0
+    b = torch.from_numpy(np.ascontiguousarray(p.rhs)).to("cuda:0")
+    if precision == 0:
+        x = num.solve(b).cpu().numpy()
+    else:
+        xt, iters, berr = num.solve_refine(b, tol=1e-10, max_iter=20)
+        x = xt.cpu().numpy()
+    x = x.reshape(p.n, -1)
+    eta = oracle.backward_error(p.n, p.colptr, p.rowind, p.values, p.rhs, x)
+    A = sp.csc_matrix((p.values, p.rowind, p.colptr), shape=(p.n, p.n))
+    A = A + sp.tril(A, -1).T
+    kappa = float(abs(A).sum(axis=1).max()) / p.meta["shift"]
+    for c in range(x.shape[1]):
+        err = np.abs(x[:, c] - xo[:, c]).max() / np.abs(xo[:, c]).max()
+        bound = 4.0 * kappa * (eta[c] + meta["eta"].reshape(-1)[c])
+        say("column", c, "error vs oracle %.2e bound %.2e" % (err, bound))
+        assert err <= bound
+    num.free()
+    sym.free()
