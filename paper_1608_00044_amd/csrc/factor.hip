@@ -223,8 +223,9 @@ __device__ __forceinline__ void panel_columns_q(C* __restrict__ T, C* __restrict
         }
 }
 
-// Panel j0 of width jb: the register factorization sized to its rows.
-template <class C, bool kCheck, class Cst>
+// Panel j0 of width jb: the register factorization sized to its rows (kW:
+// the widest block the instance handles; at most 64 needs one row chunk).
+template <class C, bool kCheck, int kW, class Cst>
 __device__ __forceinline__ void panel_columns(C* __restrict__ T, C* __restrict__ rdiag,
                                               C* __restrict__ colbuf, Cst cst, int w, int j0,
                                               int jb, int lane, int first,
@@ -235,14 +236,14 @@ __device__ __forceinline__ void panel_columns(C* __restrict__ T, C* __restrict__
 #define SPC_PANEL(NQ, FULL)                                                                   \
     panel_columns_q<NQ, FULL, C, kCheck>(T, rdiag, colbuf, cst, w, j0, jb, lane, first, status, \
                                          d0, unstable)
-    if (jb < kPanel)  // the last panel: fewer than 16 rows
+    if (jb < kPanel) {  // the last panel: fewer than 16 rows
         SPC_PANEL(1, false);
-    else if (rows <= 64)
+    } else if (kW <= 64 || rows <= 64) {
         SPC_PANEL(1, true);
-    else if (rows <= 128)
-        SPC_PANEL(2, true);
-    else
-        SPC_PANEL(3, true);
+    } else if constexpr (kW > 64) {
+        if (rows <= 128) SPC_PANEL(2, true);
+        else SPC_PANEL(3, true);
+    }
 #undef SPC_PANEL
 }
 
@@ -337,7 +338,7 @@ __device__ __forceinline__ void trailing_block(C* __restrict__ T, Cst cst, int d
 // times its starting diagonal entry the block is left unwritten in global
 // memory and the function returns true, so that the caller can factor it
 // again in FP64; otherwise the block goes back by packed index at the end.
-template <class S, class C, bool kCheck>
+template <class S, class C, bool kCheck, int kW = kMaxWidth>
 __device__ __forceinline__ bool potrf_task(int s, const KArgs& a, S* __restrict__ arena,
                                            S* __restrict__ dinv, int32_t* __restrict__ status,
                                            C* __restrict__ T) {
@@ -361,7 +362,7 @@ __device__ __forceinline__ bool potrf_task(int s, const KArgs& a, S* __restrict_
     // lane l their entries l, l + 64 and l + 128, in rounds of kRound
     // rectangle columns with every load of a round in flight.
     const int hw = (w + 1) >> 1, w1 = w + 1;
-    constexpr int kRect = ((kMaxWidth + 1) / 2 + nwave - 1) / nwave;  // per wave
+    constexpr int kRect = ((kW + 1) / 2 + nwave - 1) / nwave;  // per wave
     constexpr int kRound = (kRect + 1) / 2;
     for (int t0 = 0; t0 * nwave < hw; t0 += kRound) {
         C v[kRound][3];
@@ -417,7 +418,7 @@ __device__ __forceinline__ bool potrf_task(int s, const KArgs& a, S* __restrict_
         }
     };
     if (wave == 0)
-        panel_columns<C, kCheck>(T, rdiag, colbuf, cst, w, 0, min(kPanel, w), lane, first,
+        panel_columns<C, kCheck, kW>(T, rdiag, colbuf, cst, w, 0, min(kPanel, w), lane, first,
                                  status, d0, &unstable);
     __syncthreads();
     for (int p = 0; p + 1 < npanel; ++p) {
@@ -429,7 +430,7 @@ __device__ __forceinline__ bool potrf_task(int s, const KArgs& a, S* __restrict_
         __syncthreads();
         // 2. wave 0 factors the next panel; waves 1-3 update the other columns
         if (wave == 0) {
-            panel_columns<C, kCheck>(T, rdiag, colbuf, cst, w, t0, min(kPanel, w - t0), lane,
+            panel_columns<C, kCheck, kW>(T, rdiag, colbuf, cst, w, t0, min(kPanel, w - t0), lane,
                                      first, status, d0, &unstable);
         } else {
             const int nblk = nbr * (nbr - 1) / 2;  // blocks (bi, bj), 1 <= bj <= bi
@@ -482,27 +483,33 @@ __device__ __forceinline__ bool potrf_task(int s, const KArgs& a, S* __restrict_
 // ratio below kPivotTau) is factored again from its unchanged FP32 input in
 // FP64 arithmetic and rounded to FP32, and counted in *fallbacks.  T must
 // hold the packed triangle in the compute type of either pass.
+template <int kW = kMaxWidth>
 __device__ __forceinline__ void diag_factor(int s, const KArgs& a, double* arena, double* dinv,
                                             int32_t* status, int32_t* fallbacks, void* T) {
-    potrf_task<double, double, false>(s, a, arena, dinv, status, (double*)T);
+    potrf_task<double, double, false, kW>(s, a, arena, dinv, status, (double*)T);
 }
+template <int kW = kMaxWidth>
 __device__ __forceinline__ void diag_factor(int s, const KArgs& a, float* arena, float* dinv,
                                             int32_t* status, int32_t* fallbacks, void* T) {
-    if (potrf_task<float, float, true>(s, a, arena, dinv, status, (float*)T)) {
+    if (potrf_task<float, float, true, kW>(s, a, arena, dinv, status, (float*)T)) {
         __syncthreads();
-        potrf_task<float, double, false>(s, a, arena, dinv, status, (double*)T);
+        potrf_task<float, double, false, kW>(s, a, arena, dinv, status, (double*)T);
         if (threadIdx.x == 0) atomicAdd(fallbacks, 1);
     }
 }
 
-// Level-set form: one workgroup per supernode of the level.
-template <class R>
+// Level-set form: one workgroup per supernode of the level.  The instance
+// for blocks of at most 64 columns (kNarrow) holds a quarter of the
+// registers of the general one (one row chunk per lane), so that several
+// workgroups share a compute unit on levels of many such blocks.
+constexpr int kNarrow = 64;
+template <class R, int kW>
 __global__ __launch_bounds__(kPotrfThreads) void k_potrf(const int32_t* __restrict__ level_sn,
                                                          KArgs a, R* __restrict__ arena,
                                                          R* __restrict__ dinv,
                                                          int32_t* __restrict__ status) {
     extern __shared__ double T[];
-    diag_factor(level_sn[blockIdx.x], a, arena, dinv, status, status + 1, T);
+    diag_factor<kW>(level_sn[blockIdx.x], a, arena, dinv, status, status + 1, T);
 }
 
 // ---------------------------------------------------------------------------
@@ -711,7 +718,7 @@ __device__ __forceinline__ void trsm_rows(const R* __restrict__ L, int ld,
 // 16-column panels with the inverses of the diagonal blocks from k_potrf.
 constexpr int kTrsmThreads = 256;
 
-template <class R>
+template <class R, int kMaxNP = 10>
 __device__ __forceinline__ void trsm_task(RowBlock wb, const KArgs& a, R* __restrict__ arena,
                                           const R* __restrict__ dinv) {
     __shared__ R trs[kTrsmThreads / 64][16 * 17];
@@ -725,25 +732,34 @@ __device__ __forceinline__ void trsm_task(RowBlock wb, const KArgs& a, R* __rest
     const int row0 = wb.rb * kTile + wave * 16;
     if (row0 >= r) return;  // no barrier follows
     R* tr = trs[wave];
+    // an instance for at most kMaxNP panels compiles (and holds registers
+    // for) no more
     switch ((w + kPanel - 1) / kPanel) {
         case 1: trsm_rows<R, 1>(L, ld, inv, P, w, r, row0, tr, lane); break;
         case 2: trsm_rows<R, 2>(L, ld, inv, P, w, r, row0, tr, lane); break;
         case 3: trsm_rows<R, 3>(L, ld, inv, P, w, r, row0, tr, lane); break;
         case 4: trsm_rows<R, 4>(L, ld, inv, P, w, r, row0, tr, lane); break;
-        case 5: trsm_rows<R, 5>(L, ld, inv, P, w, r, row0, tr, lane); break;
-        case 6: trsm_rows<R, 6>(L, ld, inv, P, w, r, row0, tr, lane); break;
-        case 7: trsm_rows<R, 7>(L, ld, inv, P, w, r, row0, tr, lane); break;
-        case 8: trsm_rows<R, 8>(L, ld, inv, P, w, r, row0, tr, lane); break;
-        case 9: trsm_rows<R, 9>(L, ld, inv, P, w, r, row0, tr, lane); break;
-        default: trsm_rows<R, 10>(L, ld, inv, P, w, r, row0, tr, lane); break;
+        default:
+            if constexpr (kMaxNP > 4) {
+                switch ((w + kPanel - 1) / kPanel) {
+                    case 5: trsm_rows<R, 5>(L, ld, inv, P, w, r, row0, tr, lane); break;
+                    case 6: trsm_rows<R, 6>(L, ld, inv, P, w, r, row0, tr, lane); break;
+                    case 7: trsm_rows<R, 7>(L, ld, inv, P, w, r, row0, tr, lane); break;
+                    case 8: trsm_rows<R, 8>(L, ld, inv, P, w, r, row0, tr, lane); break;
+                    case 9: trsm_rows<R, 9>(L, ld, inv, P, w, r, row0, tr, lane); break;
+                    default: trsm_rows<R, 10>(L, ld, inv, P, w, r, row0, tr, lane); break;
+                }
+            }
+            break;
     }
 }
 
-template <class R>
+// kW: the widest supernode of the launch (kNarrow: four panels at most).
+template <class R, int kW>
 __global__ __launch_bounds__(kTrsmThreads) void k_trsm(const RowBlock* __restrict__ work, KArgs a,
                                                        R* __restrict__ arena,
                                                        const R* __restrict__ dinv) {
-    trsm_task(work[blockIdx.x], a, arena, dinv);
+    trsm_task<R, (kW + kPanel - 1) / kPanel>(work[blockIdx.x], a, arena, dinv);
 }
 
 static_assert(kMaxWidth <= 10 * kPanel, "k_trsm instantiates at most 10 panels");
@@ -1133,7 +1149,8 @@ void launch_ft(spc_numeric* num, const DevicePlan* P, const Symbolic& S, const K
     int ev;
     if (nbig > 0) {
         ev = mark_begin(num, st);
-        hipLaunchKernelGGL(k_potrf<R>, dim3(nbig), dim3(kPotrfThreads), lds_tri, st,
+        auto kern = wmax <= kNarrow ? k_potrf<R, kNarrow> : k_potrf<R, kMaxWidth>;
+        hipLaunchKernelGGL(kern, dim3(nbig), dim3(kPotrfThreads), lds_tri, st,
                            P->level_sn + n0, a, (R*)num->arena, (R*)num->dinv, num->status_dev);
         mark_end(num, st, 1, ev);
     }
@@ -1148,7 +1165,8 @@ void launch_ft(spc_numeric* num, const DevicePlan* P, const Symbolic& S, const K
     const int64_t rb0 = P->rowblk_ptr[l], rb1 = P->rowblk_ptr[l + 1];
     if (rb1 > rb0) {
         ev = mark_begin(num, st);
-        hipLaunchKernelGGL(k_trsm<R>, dim3((unsigned)(rb1 - rb0)), dim3(kTrsmThreads), 0, st,
+        auto kern = wmax <= kNarrow ? k_trsm<R, kNarrow> : k_trsm<R, kMaxWidth>;
+        hipLaunchKernelGGL(kern, dim3((unsigned)(rb1 - rb0)), dim3(kTrsmThreads), 0, st,
                            P->rowblk + rb0, a, (R*)num->arena, (const R*)num->dinv);
         mark_end(num, st, 2, ev);
     }
@@ -1354,7 +1372,10 @@ int32_t configure_kernels() {
     done = 1;
     result = configure_solve_kernels();
     const int lds_max = (int)(((size_t)kMaxWidth * (kMaxWidth + 1) / 2 + 1) * sizeof(double));
-    const void* big[] = {(const void*)k_potrf<double>, (const void*)k_potrf<float>,
+    const void* big[] = {(const void*)k_potrf<double, kMaxWidth>,
+                         (const void*)k_potrf<float, kMaxWidth>,
+                         (const void*)k_potrf<double, kNarrow>,
+                         (const void*)k_potrf<float, kNarrow>,
                          (const void*)k_sched<double>, (const void*)k_sched<float>};
     for (const void* f : big)
         if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max) !=
