@@ -916,11 +916,11 @@ __global__ __launch_bounds__(256, 2) void k_tail(const TailTask* __restrict__ ta
 // ---------------------------------------------------------------------------
 //
 // A large supernode's diagonal block costs a level kernel most of its time:
-// its inverse (up to 11k entries) read by one workgroup.  With one
-// right-hand side each level runs instead as one launch whose workgroups
-// split that product by parts of kPartRows rows, one workgroup per part,
-// and exchange the parts through device-scope stores and a per-supernode
-// count (zeroed before each solve; bounded waits as the tail's):
+// its inverse (up to 11k entries) read by one workgroup.  Each level (below
+// the tail) runs instead as one launch per direction whose workgroups split
+// that product by parts of kPartRows rows, one workgroup per part, and
+// exchange the parts through device-scope stores and a per-supernode count
+// (zeroed before each solve; bounded waits as the tail's):
 //   forward:  parts   z_s[part] = (L11^{-1} y_s)[part] to zb, then count;
 //             blocks  (the 64-row blocks below, which load their part of L21
 //                     first) wait for every part of s, then
@@ -931,8 +931,9 @@ __global__ __launch_bounds__(256, 2) void k_tail(const TailTask* __restrict__ ta
 //                     every block of s, then
 //                     x_s[part] = (L11^{-T} (z_s - t_s))[part] into y.
 // Every waiting workgroup comes after all the workgroups it waits for in
-// the launch, and those wait on nothing, so the waits end whatever the
-// number of resident workgroups.  A part's product: 16 threads per row,
+// the launch (the device dispatches a launch's workgroups in index order),
+// and those wait on nothing, so the waits end whatever the number of
+// resident workgroups.  A part's product: 16 threads per row,
 // each over every 16th column, then a butterfly over the 16; one fixed
 // order, so a solve has the same bits on every run.  A wait that passes its
 // bound sets the abort and error words and leaves NaN in its outputs.
