@@ -81,3 +81,15 @@ def compare_factor(p, num, cap=150, ratio=0.0, label=""):
     worst = float((err / tol).max()) if err.size else 0.0
     rho = oracle.residual_exact(p.n, Cp, Ci, Cx, osym, got)
     return worst, rho, (osym, Lx, got)
+
+
+def eta_agreement_atol(p):
+    """Bound on |eta_lib - eta_oracle| for one solution: both evaluate
+    r = b - A x in FP64, each within gamma_m (|A||x| + |b|) per row (m = the
+    row's entries + 1, Higham's dot-product bound), so the normwise backward
+    errors differ by at most about 2 gamma_m <= 2.1 m u absolutely; twice
+    that, with m the largest row of the full symmetric A."""
+    col = np.repeat(np.arange(p.n), np.diff(p.colptr))
+    off = p.rowind != col
+    m = np.bincount(col, minlength=p.n) + np.bincount(p.rowind[off], minlength=p.n)
+    return 4.2 * (int(m.max()) + 1) * np.finfo(np.float64).eps / 2
