@@ -333,11 +333,10 @@ __device__ __forceinline__ void trailing_block(C* __restrict__ T, Cst cst, int d
 // packed index with many loads per thread in flight.
 // Storage type S, compute type C.  Without kCheck a pivot that is not
 // positive records its global column with atomicMin on *status (the smallest
-// failing column wins).  With kCheck (FP32 pass) nothing is recorded and
-// nothing is written before the end: if any pivot is not above kPivotTau
-// times its starting diagonal entry the block is left unwritten in global
-// memory and the function returns true, so that the caller can factor it
-// again in FP64; otherwise the block goes back by packed index at the end.
+// failing column wins).  With kCheck (FP32 pass) nothing is recorded: if any
+// pivot is not above kPivotTau times its starting diagonal entry the block's
+// input values go back to global memory (from a copy in LDS) and the
+// function returns true, so that the caller can factor it again in FP64.
 template <class S, class C, bool kCheck, int kW = kMaxWidth>
 __device__ __forceinline__ bool potrf_task(int s, const KArgs& a, S* __restrict__ arena,
                                            S* __restrict__ dinv, int32_t* __restrict__ status,
@@ -363,6 +362,10 @@ __device__ __forceinline__ bool potrf_task(int s, const KArgs& a, S* __restrict_
     // rectangle columns with every load of a round in flight.
     const int hw = (w + 1) >> 1, w1 = w + 1;
     constexpr int kRect = ((kW + 1) / 2 + nwave - 1) / nwave;  // per wave
+    // FP32 pass: a copy of the input block after the triangle (the LDS holds
+    // an FP64 triangle, room for two FP32 ones), written back if a pivot
+    // fails the check, so that the FP64 pass starts from the input
+    C* __restrict__ Tb = T + dummy + 1;
     constexpr int kRound = (kRect + 1) / 2;
     for (int t0 = 0; t0 * nwave < hw; t0 += kRound) {
         C v[kRound][3];
@@ -388,6 +391,7 @@ __device__ __forceinline__ bool potrf_task(int s, const KArgs& a, S* __restrict_
             for (int u = 0; u < 3; ++u) {
                 T[at[t][u]] = v[t][u];
                 if (kCheck) {
+                    Tb[at[t][u]] = v[t][u];
                     const int pc = wave + nwave * (t0 + t), q = lane + 64 * u;
                     // the diagonal entries: q = 0 of column pc and q = w - pc of w - 1 - pc
                     if (pc < hw && q == 0) d0[pc] = v[t][u];
@@ -441,18 +445,19 @@ __device__ __forceinline__ bool potrf_task(int s, const KArgs& a, S* __restrict_
                 const int bj = b - bi * (bi - 1) / 2 + 1;
                 trailing_block<C>(T, cst, dummy, w, j0, t0, bi, bj, lr, lk);
             }
-            if (!kCheck) emit(p, 1);
+            emit(p, 1);
         }
         __syncthreads();
     }
-    if (!kCheck) {
-        emit(npanel - 1, 0);
+    emit(npanel - 1, 0);
+    if (!kCheck || !unstable) {  // uniform: read after the last barrier
         panel_inverses<C, S>(T, rdiag, inv_g, cst, w, npanel, wave, lane);
         return false;
     }
-    if (unstable) return true;  // uniform: read after the last barrier
-    panel_inverses<C, S>(T, rdiag, inv_g, cst, w, npanel, wave, lane);
-    // L11 back to the block by the same rectangle columns as the load
+    // a failed check: the input block back by the rectangle columns of the
+    // load, after every emitted store has completed
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
 #pragma unroll
     for (int t = 0; t < kRect; ++t) {
         const int pc = wave + nwave * t, pj = w - 1 - pc;
@@ -465,7 +470,7 @@ __device__ __forceinline__ bool potrf_task(int s, const KArgs& a, S* __restrict_
             const bool first = q < w - pc;
             const int j = first ? pc : pj, i = first ? pc + q : pj + q - (w - pc);
             const bool ok = pc < hw && q < w1 && (first || pj != pc);
-            v[u] = T[ok ? cst(j) + i : dummy];
+            v[u] = Tb[ok ? cst(j) + i : dummy];
         }
 #pragma unroll
         for (int u = 0; u < 3; ++u) {
@@ -475,7 +480,8 @@ __device__ __forceinline__ bool potrf_task(int s, const KArgs& a, S* __restrict_
             if (ok) (first ? c0 : c1)[first ? pc + q : pj + q - (w - pc)] = (S)v[u];
         }
     }
-    return false;
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // before the FP64 pass reloads it
+    return true;
 }
 
 // Diagonal factorization in the factor's precision.  FP64 factors: one FP64
