@@ -812,7 +812,8 @@ enum { kAtomic = 0, kRound = 1, kScratch = 2 };
 // others atomic adds (kAtomic), plain read-modify-writes (kRound), or stores
 // of the negated entry to the source's packed block in the scratch at
 // scr_off[s] (kScratch; column c, row i >= c at c (2r - c + 1) / 2 + i - c).
-template <class R, int kMode = kAtomic, int kChunk = kChunkDefault>
+template <class R, int kMode = kAtomic, int kChunk = kChunkDefault,
+          bool kDma = sizeof(R) == 4 && kChunk == kChunkDefault>
 __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
                                             const uint8_t* __restrict__ pair_excl,
                                             R* __restrict__ arena, int* coltgt,
@@ -861,9 +862,36 @@ __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
             if (!diag) Bs[(buf * kChunk + kq * kPerT + u) * kLdsStride + srow] = rb[u];
         }
     };
+    // kDma (FP32, 16-column chunks): full chunks of full tiles go from global
+    // memory straight to LDS, 4 bytes a lane and a column of 64 rows per
+    // instruction, without the register round trip; wave kq takes columns
+    // kq * kPerT .. as in fetch.  The same bits as the register path.
+    const bool full_rows = i0 + kTile <= r && (diag || c0 + kTile <= r);
+    auto direct = [&](int chunk) { return kDma && full_rows && (chunk + 1) * kChunk <= w; };
+    auto dma = [&](int chunk, int buf) {
+        constexpr int kIns = (int)sizeof(R) / 4;
+#pragma unroll
+        for (int u = 0; u < kPerT; ++u) {
+            const int kc = kq * kPerT + u, k = chunk * kChunk + kc;
+            const char* colA = (const char*)(P + (int64_t)k * ld + i0);
+            const char* colB = (const char*)(P + (int64_t)k * ld + c0);
+#pragma unroll
+            for (int h = 0; h < kIns; ++h) {
+                __builtin_amdgcn_global_load_lds(
+                    (const void*)(colA + (h * 64 + lane) * 4),
+                    (void*)((char*)(As + (buf * kChunk + kc) * kLdsStride) + h * 256), 4, 0, 0);
+                if (!diag)
+                    __builtin_amdgcn_global_load_lds(
+                        (const void*)(colB + (h * 64 + lane) * 4),
+                        (void*)((char*)(Bs + (buf * kChunk + kc) * kLdsStride) + h * 256), 4, 0,
+                        0);
+            }
+        }
+    };
     // the first chunk's loads go out before the column -> target lookups,
     // whose chain of dependent loads then hides under them
-    fetch(0);
+    if (direct(0)) dma(0, 0);
+    else fetch(0);
     // per column: the target's column base and relative-index base, and its
     // form: 1 plain, 0 atomic, 2 scratch (colbase then holds the column's
     // base in the scratch block, row gi at colbase + gi)
@@ -889,12 +917,15 @@ __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
     Acc acc[2][2];
     for (int m = 0; m < 2; ++m)
         for (int n = 0; n < 2; ++n) acc[m][n] = Acc{R(0), R(0), R(0), R(0)};
-    stash(0);
+    if (direct(0)) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the DMA written
+    else stash(0);
     __syncthreads();
     const R* Bsrc = diag ? As : Bs;
     for (int ch = 0; ch < nchunk; ++ch) {
         const int buf = ch & 1;
-        if (ch + 1 < nchunk) fetch(ch + 1);
+        const bool dnext = ch + 1 < nchunk && direct(ch + 1);
+        if (dnext) dma(ch + 1, buf ^ 1);
+        else if (ch + 1 < nchunk) fetch(ch + 1);
         if (!skip) {
 #pragma unroll
             for (int kk = 0; kk < kChunk / 4; ++kk) {
@@ -914,7 +945,8 @@ __device__ __forceinline__ void update_task(UpdTile tile, const KArgs& a,
             relbase[tid] = my_relbase;
             colexcl[tid] = my_excl;
         }
-        if (ch + 1 < nchunk) stash(buf ^ 1);
+        if (dnext) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        else if (ch + 1 < nchunk) stash(buf ^ 1);
         __syncthreads();
     }
     R* Ct = lds;  // the staging buffers are free now
