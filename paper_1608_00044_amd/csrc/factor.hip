@@ -628,19 +628,61 @@ size_t linv_lds(int wmax) {
 // F: panel solve L21 = A21 L11^{-T}
 // ---------------------------------------------------------------------------
 
+constexpr int kTrsmThreads = 256;
+
+// The operands of panel p in the panel solve are rows 16p .. 16p + 15 of L11,
+// columns 0 .. 16p - 1.  The staged form copies them once per workgroup into
+// LDS as slab p: entry (16p + i, k) at slab_base(p) + 16k + i, rows past w
+// clamped to row w - 1 (finite values that only reach output columns past w,
+// which are never stored).
+__host__ __device__ constexpr int slab_base(int p) { return 128 * p * (p - 1); }
+__host__ __device__ constexpr int slab_elems(int np) { return np > 1 ? slab_base(np) : 0; }
+
+// Every wave of the workgroup issues a share of the slab copies: direct
+// global-to-LDS loads of one dword per lane, 256 contiguous LDS bytes (whole
+// 16-row columns of a slab) per instruction, no register round trip.
+template <class R, int NP>
+__device__ __forceinline__ void stage_slabs(const R* __restrict__ L, int ld, int w,
+                                            R* __restrict__ Ls, int wave, int lane) {
+    constexpr int kD = sizeof(R) / 4;   // dwords per entry
+    constexpr int kCols = 4 / kD;       // slab columns per instruction
+    const int e = lane / kD, i = e & 15, kl = e >> 4;
+    const int half = lane % kD;
+#pragma unroll
+    for (int p = 1; p < NP; ++p) {
+        const char* src = (const char*)(L + min(16 * p + i, w - 1)) + 4 * half;
+        for (int g = wave; g < 16 * p / kCols; g += kTrsmThreads / 64) {
+            const int64_t k = g * kCols + kl;
+            __builtin_amdgcn_global_load_lds((const void*)(src + k * ld * (int64_t)sizeof(R)),
+                                             (void*)(Ls + slab_base(p) + g * kCols * 16), 4, 0,
+                                             0);
+        }
+        // at most 20 copies per slab and wave: the count of loads in flight
+        // stays within what the wait counter holds
+        asm volatile("s_waitcnt vmcnt(32)" ::: "memory");
+    }
+}
+
 // Panel solve for the 16 rows [row0, row0 + 16) of a panel, one wave, with
 // NP 16-column panels (w <= 16 NP).  Everything stays in registers:
 //   xo[p][q]  = X[row(q, lk)][16p + lr]  (matrix-core output layout)
 //   xa[p][kk] = X[lr][16p + 4kk + lk]    (matrix-core A-operand layout)
 // Panel p: B = X[:, p] - sum_{p' < p} X[:, p'] L[p, p']^T on
-// the matrix cores with L read straight from the supernode block (the next
-// panel's operands are prefetched into registers while the current panel
-// runs), then X[:, p] = B inv(D_p)^T; a 16 x 16 LDS tile converts between the
-// layouts.
-template <class R, int NP>
+// the matrix cores with L read from the supernode block, or (kStaged) from
+// the workgroup's LDS slabs (the next panel's operands are prefetched into
+// registers while the current panel runs), then X[:, p] = B inv(D_p)^T; a
+// 16 x 16 LDS tile converts between the layouts.  kStaged: every wave of the
+// workgroup calls this (active: its rows start inside the block), copies its
+// share of the slabs, and meets the others at one barrier.  kLean: no
+// prefetch (each panel loads its own operands) and every finished panel goes
+// to memory at once, so that fewer registers are live (FP64: 243 instead of
+// 371, two waves per SIMD instead of one); the products are the same.
+template <class R, int NP, bool kStaged = false, bool kLean = false>
 __device__ __forceinline__ void trsm_rows(const R* __restrict__ L, int ld,
                                           const R* __restrict__ inv, R* __restrict__ P, int w,
-                                          int r, int row0, R* __restrict__ tr, int lane) {
+                                          int r, int row0, R* __restrict__ tr, int lane,
+                                          R* __restrict__ Ls = nullptr, int wave = 0,
+                                          bool active = true) {
     typedef typename Mx<R>::acc Acc;
     const int lr = lane & 15, lk = lane >> 4;
     R xo[NP][4], xa[NP][4];
@@ -656,7 +698,8 @@ __device__ __forceinline__ void trsm_rows(const R* __restrict__ L, int ld,
 #pragma unroll
                 for (int kk = 0; kk < 4; ++kk) {
                     const int k = 16 * pp + 4 * kk + lk;
-                    const R v = L[okc ? col + (int64_t)k * ld : 0];
+                    const R v = kStaged ? Ls[slab_base(p) + 16 * k + lr]
+                                        : L[okc ? col + (int64_t)k * ld : 0];
                     lv[4 * pp + kk] = okc ? v : R(0);
                 }
             }
@@ -679,12 +722,21 @@ __device__ __forceinline__ void trsm_rows(const R* __restrict__ L, int ld,
             const R v = P[ok ? row + (int64_t)col * ld : 0];
             xo[p][q] = ok ? v : R(0);
         }
+    if constexpr (kStaged) {
+        if constexpr (NP > 1) stage_slabs<R, NP>(L, ld, w, Ls, wave, lane);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (!active) return;
+    }
     fetch(0, lv0, iv0);
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
         R* lv = (p & 1) ? lv1 : lv0;
         R* iv = (p & 1) ? iv1 : iv0;
-        if (p + 1 < NP) fetch(p + 1, (p & 1) ? lv0 : lv1, (p & 1) ? iv0 : iv1);
+        if constexpr (kLean) {
+            lv = lv0; iv = iv0;
+            if (p > 0) fetch(p, lv0, iv0);
+        } else if (p + 1 < NP) fetch(p + 1, (p & 1) ? lv0 : lv1, (p & 1) ? iv0 : iv1);
         Acc acc = {xo[p][0], xo[p][1], xo[p][2], xo[p][3]};
 #pragma unroll
         for (int pp = 0; pp < p; ++pp)
@@ -704,29 +756,36 @@ __device__ __forceinline__ void trsm_rows(const R* __restrict__ L, int ld,
         for (int q = 0; q < 4; ++q) {
             xo[p][q] = out[q];
             tr[Mx<R>::row(q, lk) * 17 + lr] = out[q];
+            if constexpr (kLean) {
+                const int row = row0 + Mx<R>::row(q, lk), col = 16 * p + lr;
+                if (row < r && col < w) P[row + (int64_t)col * ld] = out[q];
+            }
         }
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) xa[p][kk] = tr[lr * 17 + 4 * kk + lk];
         __builtin_amdgcn_wave_barrier();
     }
+    if constexpr (!kLean) {
 #pragma unroll
-    for (int p = 0; p < NP; ++p)
+        for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int row = row0 + Mx<R>::row(q, lk), col = 16 * p + lr;
-            if (row < r && col < w) P[row + (int64_t)col * ld] = xo[p][q];
-        }
+            for (int q = 0; q < 4; ++q) {
+                const int row = row0 + Mx<R>::row(q, lk), col = 16 * p + lr;
+                if (row < r && col < w) P[row + (int64_t)col * ld] = xo[p][q];
+            }
+    }
 }
 
-// One workgroup of 4 waves per 64-row block of a panel, 16 rows per wave, no
-// workgroup barrier: L21 = A21 L11^{-T} by blocked forward substitution over
-// 16-column panels with the inverses of the diagonal blocks from k_potrf.
-constexpr int kTrsmThreads = 256;
+// One workgroup of 4 waves per 64-row block of a panel, 16 rows per wave:
+// L21 = A21 L11^{-T} by blocked forward substitution over 16-column panels
+// with the inverses of the diagonal blocks from k_potrf.
 
-template <class R, int kMaxNP = 10>
+// kStaged: the L11 operands come from LDS slabs at Ls (slab_elems of the
+// block's panel count), copied once per workgroup instead of once per wave.
+template <class R, int kMaxNP = 10, bool kStaged = false, bool kLean = false>
 __device__ __forceinline__ void trsm_task(RowBlock wb, const KArgs& a, R* __restrict__ arena,
-                                          const R* __restrict__ dinv) {
+                                          const R* __restrict__ dinv, R* __restrict__ Ls = nullptr) {
     __shared__ R trs[kTrsmThreads / 64][16 * 17];
     const int s = wb.s;
     const int w = a.sn_w[s], ld = a.sn_ld[s];
@@ -736,39 +795,58 @@ __device__ __forceinline__ void trsm_task(RowBlock wb, const KArgs& a, R* __rest
     const R* __restrict__ inv = dinv + a.inv_off[s];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int row0 = wb.rb * kTile + wave * 16;
-    if (row0 >= r) return;  // no barrier follows
+    const bool active = row0 < r;
+    if (!kStaged && !active) return;  // no barrier follows
     R* tr = trs[wave];
+#define SPC_TRSM(NP) \
+    trsm_rows<R, NP, kStaged, kLean>(L, ld, inv, P, w, r, row0, tr, lane, Ls, wave, active)
     // an instance for at most kMaxNP panels compiles (and holds registers
     // for) no more
     switch ((w + kPanel - 1) / kPanel) {
-        case 1: trsm_rows<R, 1>(L, ld, inv, P, w, r, row0, tr, lane); break;
-        case 2: trsm_rows<R, 2>(L, ld, inv, P, w, r, row0, tr, lane); break;
-        case 3: trsm_rows<R, 3>(L, ld, inv, P, w, r, row0, tr, lane); break;
-        case 4: trsm_rows<R, 4>(L, ld, inv, P, w, r, row0, tr, lane); break;
+        case 1: SPC_TRSM(1); break;
+        case 2: SPC_TRSM(2); break;
+        case 3: SPC_TRSM(3); break;
+        case 4: SPC_TRSM(4); break;
         default:
             if constexpr (kMaxNP > 4) {
                 switch ((w + kPanel - 1) / kPanel) {
-                    case 5: trsm_rows<R, 5>(L, ld, inv, P, w, r, row0, tr, lane); break;
-                    case 6: trsm_rows<R, 6>(L, ld, inv, P, w, r, row0, tr, lane); break;
-                    case 7: trsm_rows<R, 7>(L, ld, inv, P, w, r, row0, tr, lane); break;
-                    case 8: trsm_rows<R, 8>(L, ld, inv, P, w, r, row0, tr, lane); break;
-                    case 9: trsm_rows<R, 9>(L, ld, inv, P, w, r, row0, tr, lane); break;
-                    default: trsm_rows<R, 10>(L, ld, inv, P, w, r, row0, tr, lane); break;
+                    case 5: SPC_TRSM(5); break;
+                    case 6: SPC_TRSM(6); break;
+                    case 7: SPC_TRSM(7); break;
+                    case 8: SPC_TRSM(8); break;
+                    case 9: SPC_TRSM(9); break;
+                    default: SPC_TRSM(10); break;
                 }
             }
             break;
     }
+#undef SPC_TRSM
 }
 
-// kW: the widest supernode of the launch (kNarrow: four panels at most).
-template <class R, int kW>
+// kW: the widest supernode of the launch (kNarrow: four panels at most).  The
+// FP32 instance stages its operands in LDS (the launch brings
+// slab_elems(ceil(wmax / 16)) entries of dynamic LDS, at most 45 KiB): it
+// then holds 124 instead of 197 registers and runs three workgroups per
+// compute unit instead of two.  FP64 reads L11 from memory (staged, one
+// workgroup per compute unit either way, it measured slower); its lean form
+// (kLean) serves launches of more blocks than compute units, where a second
+// wave per SIMD hides the loads, and the prefetching form the others, where
+// each block runs alone on its compute unit.
+template <class R>
+constexpr bool trsm_staged() { return sizeof(R) == 4; }
+
+template <class R, int kW, bool kLean = false>
 __global__ __launch_bounds__(kTrsmThreads) void k_trsm(const RowBlock* __restrict__ work, KArgs a,
                                                        R* __restrict__ arena,
                                                        const R* __restrict__ dinv) {
-    trsm_task<R, (kW + kPanel - 1) / kPanel>(work[blockIdx.x], a, arena, dinv);
+    extern __shared__ double Tsl[];
+    trsm_task<R, (kW + kPanel - 1) / kPanel, trsm_staged<R>(), kLean>(
+        work[blockIdx.x], a, arena, dinv, reinterpret_cast<R*>(Tsl));
 }
 
 static_assert(kMaxWidth <= 10 * kPanel, "k_trsm instantiates at most 10 panels");
+static_assert(slab_elems(10) * sizeof(float) <= 65536,
+              "the FP32 panel solve's slabs fit the default dynamic LDS limit");
 
 // ---------------------------------------------------------------------------
 // U + A: update tiles on FP64 MFMA with relative-index scatter
@@ -1204,7 +1282,12 @@ void launch_ft(spc_numeric* num, const DevicePlan* P, const Symbolic& S, const K
     if (rb1 > rb0) {
         ev = mark_begin(num, st);
         auto kern = wmax <= kNarrow ? k_trsm<R, kNarrow> : k_trsm<R, kMaxWidth>;
-        hipLaunchKernelGGL(kern, dim3((unsigned)(rb1 - rb0)), dim3(kTrsmThreads), 0, st,
+        if constexpr (sizeof(R) == 8)
+            if (rb1 - rb0 > P->ncu)
+                kern = wmax <= kNarrow ? k_trsm<R, kNarrow, true> : k_trsm<R, kMaxWidth, true>;
+        const size_t lds_slab =
+            trsm_staged<R>() ? (size_t)slab_elems((wmax + kPanel - 1) / kPanel) * sizeof(R) : 0;
+        hipLaunchKernelGGL(kern, dim3((unsigned)(rb1 - rb0)), dim3(kTrsmThreads), lds_slab, st,
                            P->rowblk + rb0, a, (R*)num->arena, (const R*)num->dinv);
         mark_end(num, st, 2, ev);
     }

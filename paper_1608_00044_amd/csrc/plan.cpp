@@ -549,11 +549,14 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
     // task-queue schedule: task order, dependency counts, row-block bases
     std::vector<Task> tasks;
     std::vector<int32_t> cnt0, rb_base;
-    if (S.opt.sched == 2) {
+    {
         int ncu = 0;
-        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-            ncu = 256;
-        int32_t st = build_task_order(S, ncu, tasks, cnt0, rb_base);
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            ncu > 0)
+            P->ncu = ncu;
+    }
+    if (S.opt.sched == 2) {
+        int32_t st = build_task_order(S, P->ncu, tasks, cnt0, rb_base);
         if (st != OK) { delete P; return st; }
         if ((S.opt.debug_flags & 1) && S.nsup > 0) cnt0[S.nsup - 1] += 1;
         Layout L2;

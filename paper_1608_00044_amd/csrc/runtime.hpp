@@ -114,6 +114,7 @@ constexpr int kTailMaxLevelSn = 128;
 // Device copy of the symbolic analysis, shared by every factor of it on one device.
 struct DevicePlan {
     int device = -1;
+    int32_t ncu = 256;  // compute units of the device
     void* block = nullptr;  // single allocation holding everything below
     size_t bytes = 0;
     int32_t* sn_first = nullptr;
