@@ -239,11 +239,16 @@ spc_status spc_symbolic_free(spc_symbolic* sym);
 spc_status spc_factor(const spc_symbolic* sym, const double* values_dev, void* stream,
                       spc_numeric** out);
 
-/* Factor again with fresh values on the same pattern, reusing num's memory. */
+/* Factor again with fresh values on the same pattern, reusing num's memory:
+ * the symbolic analysis (Section II-B) depends on the pattern alone, so only
+ * the numeric tasks of Section III-A run again.  values_dev, stream, status
+ * and errors as spc_factor. */
 spc_status spc_refactor(spc_numeric* num, const double* values_dev, void* stream);
 
 /* Synchronizes the factor's stream and returns its status: 0, the 1-based
- * failing pivot column (> 0), SPC_ERR_TIMEOUT or SPC_ERR_HIP. */
+ * failing pivot column (> 0: the diagonal entry under the square root of
+ * equation (1)'s column recurrence was not positive, so A is not positive
+ * definite), SPC_ERR_TIMEOUT or SPC_ERR_HIP. */
 spc_status spc_numeric_status(spc_numeric* num);
 
 /* x = A^{-1} b for nrhs right-hand sides: b_dev and x_dev are column-major
@@ -276,7 +281,10 @@ spc_status spc_solve_noalloc(spc_numeric* num, int32_t nrhs, const double* b_dev
 /* Host copy of the factor in the stored (supernodal) column structure:
  * Sp[n+1] (int64) and Si (int32) give, for column j of supernode s, the rows
  * j..last(s) then the rows below the supernode's diagonal block; Sx holds the
- * values.  Entries outside the exact structure of L are explicit zeros.
+ * values.  Entries outside the exact structure of L are explicit zeros: the
+ * stored structure is that of the amalgamated supernodes (Section II-B), a
+ * superset of the exact structure; L itself is the unique factor of
+ * equation (1).
  * Synchronizes.  Any output may be NULL; sizes are n+1 and nnz_stored. */
 spc_status spc_factor_export(spc_numeric* num, int64_t* Sp, int32_t* Si, double* Sx);
 
