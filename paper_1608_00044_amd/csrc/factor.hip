@@ -829,9 +829,11 @@ __device__ __forceinline__ void trsm_task(RowBlock wb, const KArgs& a, R* __rest
 // then holds 124 instead of 197 registers and runs three workgroups per
 // compute unit instead of two.  FP64 reads L11 from memory (staged, one
 // workgroup per compute unit either way, it measured slower); its lean form
-// (kLean) serves launches of more blocks than compute units, where a second
-// wave per SIMD hides the loads, and the prefetching form the others, where
-// each block runs alone on its compute unit.
+// (kLean) serves launches of more blocks than compute units with blocks
+// wider than kNarrow, where a second wave per SIMD hides the loads, and the
+// prefetching form the others: there each block runs alone on its compute
+// unit, or (at most four panels) the prefetching form already runs three
+// workgroups per compute unit and measured faster.
 template <class R>
 constexpr bool trsm_staged() { return sizeof(R) == 4; }
 
@@ -1283,8 +1285,7 @@ void launch_ft(spc_numeric* num, const DevicePlan* P, const Symbolic& S, const K
         ev = mark_begin(num, st);
         auto kern = wmax <= kNarrow ? k_trsm<R, kNarrow> : k_trsm<R, kMaxWidth>;
         if constexpr (sizeof(R) == 8)
-            if (rb1 - rb0 > P->ncu)
-                kern = wmax <= kNarrow ? k_trsm<R, kNarrow, true> : k_trsm<R, kMaxWidth, true>;
+            if (wmax > kNarrow && rb1 - rb0 > P->ncu) kern = k_trsm<R, kMaxWidth, true>;
         const size_t lds_slab =
             trsm_staged<R>() ? (size_t)slab_elems((wmax + kPanel - 1) / kPanel) * sizeof(R) : 0;
         hipLaunchKernelGGL(kern, dim3((unsigned)(rb1 - rb0)), dim3(kTrsmThreads), lds_slab, st,

@@ -25,8 +25,8 @@ struct Layout {
 
 struct PlanOffsets {
     size_t sn_first, sn_w, sn_ld, sn_off, inv_off, rowptr, rows, rowpair, slot, perm, pair_tgt,
-        pair_seg, pair_rel, pair_excl, rel, level_sn, big_sn, rowblk, tiles, tasks, cnt0,
-        rb_base;
+        pair_seg, pair_rel, pair_excl, rel, level_sn, small_rec, big_sn, rowblk, tiles, tasks,
+        cnt0, rb_base;
     size_t pair_src, pair_end, scr_off, app_t, app_rb, app_p0, app_ent;
     size_t slot_shared, red_row, red_ptr, red_slot, colblk, fwdblk, sspart, pb_off;
     size_t tail_tasks, tail_segs;
@@ -237,6 +237,7 @@ PlanOffsets plan_layout(const Symbolic& S, const std::vector<int64_t>& rb_ptr,
     o.pair_excl = L.add<uint8_t>(S.pairs.size());
     o.rel = L.add<int32_t>(S.rel.size());
     o.level_sn = L.add<int32_t>(S.level_sn.size());
+    o.small_rec = L.add<SmallRec>(S.level_sn.size());
     o.big_sn = L.add<int32_t>(S.level_sn.size());
     o.rowblk = L.add<RowBlock>((size_t)rb_ptr.back());
     o.tiles = L.add<UpdTile>((size_t)tl_ptr.back());
@@ -650,6 +651,13 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
                 if (is_small(S, S.level_sn[q])) ls.push_back(S.level_sn[q]);
         }
         put(o.level_sn, ls.data(), ls.size() * 4);
+        std::vector<SmallRec> rec(ls.size());
+        for (size_t q = 0; q < ls.size(); ++q) {
+            const int32_t s = ls[q];
+            rec[q] = SmallRec{S.off[s], inv[s], S.rowptr[s], w[s], S.ld[s], first[s],
+                              (int32_t)S.nbelow(s)};
+        }
+        put(o.small_rec, rec.data(), rec.size() * sizeof(SmallRec));
         std::vector<int32_t> big;
         for (int32_t l = 0; l < nl; ++l)
             for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l] + P->level_nbig[l]; ++q) {
@@ -779,6 +787,7 @@ int32_t get_plan(spc_symbolic* sym, DevicePlan** out) {
     P->pair_excl = (uint8_t*)(base + o.pair_excl);
     P->rel = (int32_t*)(base + o.rel);
     P->level_sn = (int32_t*)(base + o.level_sn);
+    P->small_rec = (SmallRec*)(base + o.small_rec);
     P->big_sn = (int32_t*)(base + o.big_sn);
     P->rowblk = (RowBlock*)(base + o.rowblk);
     P->tiles = (UpdTile*)(base + o.tiles);

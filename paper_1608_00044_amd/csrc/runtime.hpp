@@ -84,6 +84,11 @@ struct Task { int32_t s; int16_t a, b; int32_t kind; };
 struct UpdTile { int32_t s; int16_t bi, bj; };
 // One panel row block of source supernode s.
 struct RowBlock { int32_t s; int32_t rb; };
+// One small supernode's solve metadata in one record (the kernels read it
+// with one load instead of a supernode index and then seven lookups):
+// arena offset of its block, offset of its diagonal region in dinv, its
+// first entry in rows, width, leading dimension, first column, rows below.
+struct SmallRec { int64_t off, inv, rp; int32_t w, ld, first, r; };
 // Backward solve: a workgroup takes kColGroup columns of one chunk of
 // kRowChunk rows below the diagonal block.
 constexpr int kColGroup = 8;
@@ -134,6 +139,7 @@ struct DevicePlan {
     uint8_t* pair_excl = nullptr; // 1 if no other source of the level shares the target
     int32_t* rel = nullptr;
     int32_t* level_sn = nullptr;
+    SmallRec* small_rec = nullptr;  // aligned with level_sn
     int32_t* big_sn = nullptr;   // every large supernode, level by level
     int64_t nbig = 0;
     int32_t big_maxw = 0;        // widest large supernode
@@ -320,7 +326,7 @@ void launch_small_factor(spc_numeric* num, const KArgs& a, const int32_t* list, 
 // target adds the level's small sources' blocks from the scratch in order).
 void launch_small_apply(spc_numeric* num, int64_t i0, int64_t i1, hipStream_t st);
 // y: the solve vector; cb: the forward contribution slots (factor type).
-void launch_small_solve(spc_numeric* num, const KArgs& a, const int32_t* list, int count,
+void launch_small_solve(spc_numeric* num, const KArgs& a, const SmallRec* recs, int count,
                         int maxw, int maxm, void* y, void* cb, int64_t n, int nrhs, bool forward,
                         hipStream_t st);
 // Elements of the solve work (y, contribution slots, backward partial sums)

@@ -318,9 +318,10 @@ __device__ __forceinline__ T group_sum(T v) {
 // (WB: a bound on the level's small widths, so registers follow the level):
 //   y_s = inv(L11) y_s;  y[rows below] -= L21 y_s, in place for a row that no
 //   other source of the level updates, else into the row's contribution slot
-//   (reduced after the level in source order).
+//   (reduced after the level in source order).  recs: the level's small
+//   supernodes, one record each.
 template <class R, int WB, int G>
-__global__ __launch_bounds__(256) void k_small_fwd(const int32_t* __restrict__ list, int count,
+__global__ __launch_bounds__(256) void k_small_fwd(const SmallRec* __restrict__ recs, int count,
                                                    KArgs a, const R* __restrict__ arena,
                                                    const R* __restrict__ dinv,
                                                    R* __restrict__ y, int64_t n, int nrhs,
@@ -328,12 +329,11 @@ __global__ __launch_bounds__(256) void k_small_fwd(const int32_t* __restrict__ l
     const int lane = threadIdx.x & 63, gl = lane % G;
     const int idx = blockIdx.x * (256 / G) + (int)threadIdx.x / G;
     if (idx >= count) return;
-    const int s = list[idx];
-    const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
-    const int64_t rp = a.rowptr[s];
-    const int r = (int)(a.rowptr[s + 1] - rp) - w;
-    const R* __restrict__ L = arena + a.sn_off[s];
-    const R* __restrict__ inv = dinv + a.inv_off[s];
+    const SmallRec rec = recs[idx];
+    const int w = rec.w, ld = rec.ld, first = rec.first, r = rec.r;
+    const int64_t rp = rec.rp;
+    const R* __restrict__ L = arena + rec.off;
+    const R* __restrict__ inv = dinv + rec.inv;
     R li[WB], iv[WB];
 #pragma unroll
     for (int k = 0; k < WB; ++k) {
@@ -364,19 +364,18 @@ __global__ __launch_bounds__(256) void k_small_fwd(const int32_t* __restrict__ l
 // (WB as for the forward solve):
 //   t = L21^T y[rows below] (group sums);  y_s = inv(L11)^T (y_s - t)
 template <class R, int WB, int G>
-__global__ __launch_bounds__(256) void k_small_bwd(const int32_t* __restrict__ list, int count,
+__global__ __launch_bounds__(256) void k_small_bwd(const SmallRec* __restrict__ recs, int count,
                                                    KArgs a, const R* __restrict__ arena,
                                                    const R* __restrict__ dinv,
                                                    R* __restrict__ y, int64_t n, int nrhs) {
     const int lane = threadIdx.x & 63, gl = lane % G;
     const int idx = blockIdx.x * (256 / G) + (int)threadIdx.x / G;
     if (idx >= count) return;
-    const int s = list[idx];
-    const int w = a.sn_w[s], ld = a.sn_ld[s], first = a.sn_first[s];
-    const int64_t rp = a.rowptr[s];
-    const int r = (int)(a.rowptr[s + 1] - rp) - w;
-    const R* __restrict__ L = arena + a.sn_off[s];
-    const R* __restrict__ inv = dinv + a.inv_off[s];
+    const SmallRec rec = recs[idx];
+    const int w = rec.w, ld = rec.ld, first = rec.first, r = rec.r;
+    const int64_t rp = rec.rp;
+    const R* __restrict__ L = arena + rec.off;
+    const R* __restrict__ inv = dinv + rec.inv;
     R li[WB], ivt[WB];
 #pragma unroll
     for (int k = 0; k < WB; ++k) {
@@ -450,7 +449,7 @@ void launch_small_apply(spc_numeric* num, int64_t i0, int64_t i1, hipStream_t st
                            (const double*)num->det_scratch, a, (double*)num->arena, count);
 }
 
-void launch_small_solve(spc_numeric* num, const KArgs& a, const int32_t* list, int count,
+void launch_small_solve(spc_numeric* num, const KArgs& a, const SmallRec* recs, int count,
                         int maxw, int maxm, void* y, void* cb, int64_t n, int nrhs, bool forward,
                         hipStream_t st) {
     if (count <= 0) return;
@@ -460,10 +459,10 @@ void launch_small_solve(spc_numeric* num, const KArgs& a, const int32_t* list, i
         const dim3 g((unsigned)std::max(1, (count + per_block - 1) / per_block)), b(256);
         const SolveBufs<T> sb{(T*)cb, P->nslots, P->slot_shared};
         if (forward)
-            hipLaunchKernelGGL(kf, g, b, 0, st, list, count, a, (const T*)num->arena,
+            hipLaunchKernelGGL(kf, g, b, 0, st, recs, count, a, (const T*)num->arena,
                                (const T*)num->dinv, yt, n, nrhs, sb);
         else
-            hipLaunchKernelGGL(kb, g, b, 0, st, list, count, a, (const T*)num->arena,
+            hipLaunchKernelGGL(kb, g, b, 0, st, recs, count, a, (const T*)num->arena,
                                (const T*)num->dinv, yt, n, nrhs);
     };
     // the width bound sizes the registers; lanes per supernode follow the

@@ -1436,7 +1436,7 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* work, hipStream_t st) {
     const int32_t extra = (S.opt.debug_flags & 1) ? 1 : 0;
     for (int32_t l = 0; l < nl; ++l) {
         const int32_t n0 = S.level_ptr[l], n1 = S.level_ptr[l + 1], nbig = P->level_nbig[l];
-        launch_small_solve(num, a, P->level_sn + n0 + nbig, n1 - n0 - nbig, P->small_maxw[l],
+        launch_small_solve(num, a, P->small_rec + n0 + nbig, n1 - n0 - nbig, P->small_maxw[l],
                            P->small_maxm[l], y, cb, n, nrhs, true, st);
         const int64_t f0 = P->fwdblk_ptr[l], f1 = P->fwdblk_ptr[l + 1];
         const int64_t p0 = P->sspart_ptr[l], p1 = P->sspart_ptr[l + 1];
@@ -1514,7 +1514,7 @@ void enqueue_sweeps(spc_numeric* num, int32_t nrhs, R* work, hipStream_t st) {
             hipLaunchKernelGGL((k_bwd_diag<R, NR>), dim3((unsigned)nbig), dim3(256), 0, st,
                                P->level_sn + n0, a, dinv, y, (const R*)zb, (const R*)pb,
                                (const int64_t*)P->pb_off, P->pb_total, n, nrhs);
-        launch_small_solve(num, a, P->level_sn + n0 + nbig, n1 - n0 - nbig, P->small_maxw[l],
+        launch_small_solve(num, a, P->small_rec + n0 + nbig, n1 - n0 - nbig, P->small_maxw[l],
                            P->small_maxm[l], y, cb, n, nrhs, false, st);
     }
 }
