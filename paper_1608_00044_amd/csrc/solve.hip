@@ -1057,33 +1057,74 @@ __global__ __launch_bounds__(256) void k_bwd_split(const ColBlk* __restrict__ wo
         const R* __restrict__ P = arena + a.sn_off[s] + w + rb0 + (int64_t)k0 * ld;
         const int32_t* __restrict__ below = a.rows + rp + w + rb0;
         R* __restrict__ out = pb + pb_off[s] + (int64_t)h * w + k0;
-        R acc[G];
+        if (r <= 128) {
+            // a short chunk: the waves split the columns instead of the rows.
+            // r <= 64: wave q sums columns kQ q .. kQ q + kQ - 1 over every
+            // row (lane = row); else waves 2c and 2c + 1 sum columns
+            // 2 kQ c .. over rows 0-63 and 64-127.  Each column's sum takes
+            // the same products in the same lanes and order as the general
+            // path below, whose other waves add zeros here.
+            constexpr int kQ = G / 4;
+            static_assert(G % 4 == 0, "four waves share a column group");
+            const bool one = r <= 64;
+            const int c0 = one ? wave * kQ : (wave >> 1) * (2 * kQ);
+            const int ncw = one ? kQ : 2 * kQ;
+            const int i = one ? lane : lane + 64 * (wave & 1);
+            const int32_t row = i < r ? below[i] : 0;
+            const R yv = i < r ? y[row] : R(0);
+            R v[2 * kQ];
 #pragma unroll
-        for (int k = 0; k < G; ++k) acc[k] = R(0);
-        for (int i0 = tid; i0 < r; i0 += 256 * 4) {
-            R yv[4], pv[4][G];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int i = i0 + 256 * u;
-                const int32_t row = i < r ? below[i] : 0;
-                yv[u] = i < r ? y[row] : R(0);
-#pragma unroll
-                for (int k = 0; k < G; ++k) pv[u][k] = (i < r && k < kc) ? P[i + (int64_t)k * ld] : R(0);
+            for (int k = 0; k < 2 * kQ; ++k) {
+                const int c = c0 + k;
+                const R pv = (k < ncw && i < r && c < kc) ? P[i + (int64_t)c * ld] : R(0);
+                v[k] = R(0);
+                v[k] += pv * yv;
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int k = 0; k < 2 * kQ; ++k) {
+                if (k < ncw) {
 #pragma unroll
-                for (int k = 0; k < G; ++k) acc[k] += pv[u][k] * yv[u];
+                    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+                    if (lane == 0) part[wave][c0 + k] = v[k];
+                }
+            }
+            __syncthreads();
+            if (tid < kc) {
+                const int c = tid / (2 * kQ);
+                st_dev(out + tid,
+                       one ? part[tid / kQ][tid] : part[2 * c][tid] + part[2 * c + 1][tid]);
+            }
+        } else {
+            R acc[G];
+#pragma unroll
+            for (int k = 0; k < G; ++k) acc[k] = R(0);
+            for (int i0 = tid; i0 < r; i0 += 256 * 4) {
+                R yv[4], pv[4][G];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int i = i0 + 256 * u;
+                    const int32_t row = i < r ? below[i] : 0;
+                    yv[u] = i < r ? y[row] : R(0);
+#pragma unroll
+                    for (int k = 0; k < G; ++k)
+                        pv[u][k] = (i < r && k < kc) ? P[i + (int64_t)k * ld] : R(0);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int k = 0; k < G; ++k) acc[k] += pv[u][k] * yv[u];
+            }
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                R v = acc[k];
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+                if (lane == 0) part[wave][k] = v;
+            }
+            __syncthreads();
+            if (tid < kc)
+                st_dev(out + tid, (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]));
         }
-#pragma unroll
-        for (int k = 0; k < G; ++k) {
-            R v = acc[k];
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-            if (lane == 0) part[wave][k] = v;
-        }
-        __syncthreads();
-        if (tid < kc) st_dev(out + tid, (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]));
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
         if (tid == 0) __hip_atomic_fetch_add(cnt + s, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
