@@ -346,6 +346,10 @@ __global__ __launch_bounds__(256) void k_small_fwd(const SmallRec* __restrict__ 
         R* __restrict__ yc = y + (int64_t)c * n;
         R* __restrict__ cbc = sb.cb + (int64_t)c * sb.nslots;
         const R b = gl < w ? yc[first + gl] : R(0);
+        // a row below that no other source of the level updates has this
+        // supernode as its one writer here, and lies outside its columns:
+        // its old value can be loaded with b, before y_s is stored
+        const R yold = (gl < r && !shared) ? yc[row] : R(0);
         R ys = R(0);
 #pragma unroll
         for (int k = 0; k < WB; ++k) ys += iv[k] * __shfl(b, k, G);
@@ -355,7 +359,7 @@ __global__ __launch_bounds__(256) void k_small_fwd(const SmallRec* __restrict__ 
         for (int k = 0; k < WB; ++k) acc += li[k] * __shfl(ys, k, G);
         if (gl < r) {
             if (shared) cbc[rp + w + gl] = acc;
-            else yc[row] -= acc;
+            else yc[row] = yold - acc;
         }
     }
 }
