@@ -509,11 +509,16 @@ __device__ __forceinline__ void diag_factor(int s, const KArgs& a, float* arena,
 // registers of the general one (one row chunk per lane), so that several
 // workgroups share a compute unit on levels of many such blocks.
 constexpr int kNarrow = 64;
+// The narrow instances are held to three (FP64) or four (FP32) waves per SIMD:
+// a level's many narrow blocks then share each compute unit three or four at
+// a time, at the price of a few spilled registers.
 template <class R, int kW>
-__global__ __launch_bounds__(kPotrfThreads) void k_potrf(const int32_t* __restrict__ level_sn,
-                                                         KArgs a, R* __restrict__ arena,
-                                                         R* __restrict__ dinv,
-                                                         int32_t* __restrict__ status) {
+constexpr int potrf_waves() { return kW > kNarrow ? 1 : (sizeof(R) == 4 ? 4 : 3); }
+
+template <class R, int kW>
+__global__ __launch_bounds__(kPotrfThreads, (potrf_waves<R, kW>())) void k_potrf(
+    const int32_t* __restrict__ level_sn, KArgs a, R* __restrict__ arena, R* __restrict__ dinv,
+    int32_t* __restrict__ status) {
     extern __shared__ double T[];
     diag_factor<kW>(level_sn[blockIdx.x], a, arena, dinv, status, status + 1, T);
 }
