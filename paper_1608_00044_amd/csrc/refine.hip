@@ -120,20 +120,26 @@ __global__ void k_gather_vals(const double* __restrict__ values, const int64_t* 
 // of the group reads entries ptr[i] + j, + kLpr, ... so the group's loads of
 // val and col are contiguous), the partial sums meet by shuffles, and each
 // wave walks kRowGroups groups of 64 / kLpr consecutive rows.
+// The single-column residual of matrices with short rows (at most six
+// entries on average, the 2D stencils) uses groups of kLprShort lanes.
 constexpr int kLpr = 8;
+constexpr int kLprShort = 4;
 constexpr int kRowGroups = 16;
+template <int L = kLpr>
 unsigned sparse_blocks(int64_t n) {
-    const int64_t per_block = 4 * (64 / kLpr) * (int64_t)kRowGroups;
+    const int64_t per_block = 4 * (64 / L) * (int64_t)kRowGroups;
     return (unsigned)std::max<int64_t>(1, (n + per_block - 1) / per_block);
 }
 // Row of this lane's group in step u, and the lane's place in the group.
+template <int L = kLpr>
 __device__ __forceinline__ int64_t sparse_row(int u) {
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    return (wave * kRowGroups + u) * (64 / kLpr) + ((threadIdx.x & 63) / kLpr);
+    return (wave * kRowGroups + u) * (64 / L) + ((threadIdx.x & 63) / L);
 }
+template <int L = kLpr>
 __device__ __forceinline__ double group_sum(double v) {
 #pragma unroll
-    for (int o = 1; o < kLpr; o <<= 1) v += __shfl_xor(v, o, 64);
+    for (int o = 1; o < L; o <<= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
 
@@ -187,7 +193,7 @@ __global__ void k_interleave(const double* __restrict__ x, int64_t ldx, double* 
 // (those below nrhs) in one pass over A: each entry of A is read once and
 // multiplies NR gathered entries of x (NR > 1: from the interleaved copy xt,
 // row k at xt + k NR).
-template <int NR>
+template <int NR, int L = kLpr>
 __global__ __launch_bounds__(256) void k_resid(const int64_t* __restrict__ ptr,
                                                const int32_t* __restrict__ col,
                                                const double* __restrict__ val,
@@ -196,16 +202,16 @@ __global__ __launch_bounds__(256) void k_resid(const int64_t* __restrict__ ptr,
                                                double* __restrict__ r, int64_t n, int c0,
                                                int nrhs, const int32_t* __restrict__ seg,
                                                int64_t nseg, double* __restrict__ rnorm) {
-    const int j = threadIdx.x % kLpr;
+    const int j = threadIdx.x % L;
     const int nc = min(NR, nrhs - c0);
     SegMax sm[NR];
     for (int u = 0; u < kRowGroups; ++u) {
-        const int64_t i = sparse_row(u);
+        const int64_t i = sparse_row<L>(u);
         double acc[NR];
 #pragma unroll
         for (int c = 0; c < NR; ++c) acc[c] = 0.0;
         if (i < n) {
-            for (int64_t q = ptr[i] + j; q < ptr[i + 1]; q += kLpr) {
+            for (int64_t q = ptr[i] + j; q < ptr[i + 1]; q += L) {
                 const double v = val[q];
                 const int64_t k = col[q];
                 if (NR == 1) {
@@ -221,7 +227,7 @@ __global__ __launch_bounds__(256) void k_resid(const int64_t* __restrict__ ptr,
 #pragma unroll
         for (int c = 0; c < NR; ++c) {
             if (c >= nc) break;  // uniform
-            const double s = group_sum(acc[c]);
+            const double s = group_sum<L>(acc[c]);
             double ri = 0.0;
             if (i < n) {
                 ri = b[i + (int64_t)(c0 + c) * ldb] - s;
@@ -480,10 +486,12 @@ int32_t run_refine(spc_numeric* num, int32_t nrhs, const double* b, int64_t ldb,
         hipLaunchKernelGGL(k_fill_f64, dim3(grid_of(2 * ne)), dim3(256), 0, st, xn, 2 * ne, 0.0);
         for (int32_t c0 = 0; c0 < nrhs; c0 += kResidCols) {
             if (nrhs - c0 == 1) {
-                hipLaunchKernelGGL(k_resid<1>, dim3(sparse_blocks(n)), dim3(256), 0, st,
-                                   (const int64_t*)num->a_ptr, (const int32_t*)num->a_col,
-                                   (const double*)num->a_val, b, ldb, (const double*)x, ldx, r,
-                                   n, (int)c0, (int)nrhs, seg, ns, rn);
+                const bool short_rows = num->a_nnz <= 6 * n;
+                auto kern = short_rows ? k_resid<1, kLprShort> : k_resid<1>;
+                const unsigned g = short_rows ? sparse_blocks<kLprShort>(n) : sparse_blocks(n);
+                hipLaunchKernelGGL(kern, dim3(g), dim3(256), 0, st, (const int64_t*)num->a_ptr,
+                                   (const int32_t*)num->a_col, (const double*)num->a_val, b, ldb,
+                                   (const double*)x, ldx, r, n, (int)c0, (int)nrhs, seg, ns, rn);
             } else {
                 hipLaunchKernelGGL(k_interleave<kResidCols>, dim3(grid_of(n * kResidCols)),
                                    dim3(256), 0, st, (const double*)x, ldx, xt, n, (int)c0,
